@@ -1,0 +1,203 @@
+/*
+ * helm.h - C ABI of libhelm, a gfx950 (MI355X) solver for the discretised
+ * heterogeneous Helmholtz equation preconditioned by a 3-level multigrid cycle
+ * with a real-shifted coarsest-grid Galerkin operator.
+ *
+ * Method (Yovel & Treister, "Scalable Multigrid Solver for the Helmholtz
+ * Equation: Real-Shifted Coarse Grid Correction"):
+ *   problem   -Lap p - k^2 p = q, k = omega * slowness            (eq. 1.1)
+ *             discretised on a regular node grid with an absorbing layer
+ *   level 1   H_beta = -Lap_h - (1 - i beta) omega^2 m (1 - i sigma),  m = slowness^2
+ *   level 2   A2 = R1 H_beta P1                                     (eq. 2.2)
+ *   level 3   A3 = R2 (R1 H_beta^alpha P1) P2, k -> alpha k          (eq. 3.5, 3.6)
+ *             solved exactly (nested-dissection block elimination)
+ *   cycle     two-grid algorithm of Sec. 2 applied recursively (V or W),
+ *             damped Jacobi relaxation
+ *   outer     right-preconditioned restarted FGMRES on the unshifted H
+ *             (stopping rule: relative residual, Sec. 5)
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Grid: n[a] cells and n[a]+1 nodes along axis a (a < dim); every node is an
+ * unknown and values one node beyond each end are zero.  n[a] must be a
+ * multiple of 4 (three levels) and at least 4.  Node arrays are x-fastest:
+ * flat index i0 + (n0+1)*(i1 + (n1+1)*i2).  N1 = prod(n[a]+1).
+ * Complex arrays are interleaved (re, im): "c128" = 2 x double per entry,
+ * "c64" = 2 x float per entry.
+ * Absorbing layer: layer[a][0] / layer[a][1] cells on the low / high face of
+ * axis a; sigma = sigma_max * sum_a (depth_a / width_a)^2 where depth_a is the
+ * distance in cells into that layer (quadratic profile, zero outside).
+ *
+ * Memory: every pointer argument named as "device" is a device pointer owned
+ * by the caller; the library never allocates device memory.  helm_setup
+ * carves all persistent device state out of the caller's workspace (size from
+ * helm_workspace_bytes), which must stay allocated and untouched until
+ * helm_destroy.  The context itself is host memory owned by the library.
+ * Work is enqueued on the given stream (a hipStream_t, NULL = default stream);
+ * helm_solve synchronises that stream to read convergence scalars.
+ *
+ * Errors: every call returns an int status.  0 = success, negative = error
+ * (nothing was computed or the outputs are undefined), positive = warning
+ * (outputs valid, see the code).  No exception crosses the ABI.  Argument
+ * validation happens before any device call.
+ */
+#ifndef HELM_H
+#define HELM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HELM_OK            0
+#define HELM_EINVAL       -1   /* invalid argument (message: helm_last_error) */
+#define HELM_EWORKSPACE   -2   /* workspace NULL, misaligned or too small */
+#define HELM_EDEVICE      -3   /* HIP runtime error */
+#define HELM_ENONFINITE   -4   /* NaN/Inf met in an input or a Krylov scalar */
+#define HELM_ESINGULAR    -5   /* zero pivot in the coarsest-grid elimination */
+#define HELM_ENOCONV       1   /* max_iter reached before the tolerance */
+#define HELM_ESTAGNATE     2   /* no residual decrease over a full restart cycle */
+
+#define HELM_OP_N 0            /* the operator H */
+#define HELM_OP_C 1            /* its conjugate transpose H^H (= conj(H): H is complex symmetric) */
+
+#define HELM_F64 0
+#define HELM_F32 1
+
+typedef struct helm_ctx helm_ctx;
+
+typedef struct {
+  int dim;             /* 2 or 3 */
+  int n[3];            /* cells per axis (entries >= dim ignored) */
+  double h;            /* grid spacing (> 0) */
+  int layer[3][2];     /* absorbing-layer width in cells: [axis][low face, high face] */
+  double sigma_max;    /* layer damping at the outermost node (>= 0) */
+} helm_grid;
+
+typedef struct {
+  double alpha;        /* real shift of the coarsest Galerkin operator, eq. (3.5)-(3.6) */
+  double alpha2;       /* real shift of the level-2 Galerkin operator (1 = none) */
+  double beta;         /* complex shift of the preconditioner: c -> (1 - i beta) c (0 = none) */
+} helm_shift;
+
+typedef struct {
+  int cycle;           /* 1 = V cycle, 2 = W cycle (level 2 visited twice) */
+  int nu_pre;          /* damped-Jacobi sweeps before the coarse correction, 0..4 */
+  int nu_post;         /* sweeps after it, 0..4 */
+  double jacobi[2];    /* damping weight on level 1 and level 2 */
+  int cycle_prec;      /* HELM_F32: cycle in complex FP32 (FGMRES stays FP64); HELM_F64 */
+  int restart;         /* FGMRES restart length m, 1..64 */
+} helm_mg;
+
+typedef struct {
+  int iterations;            /* preconditioner applications */
+  int restarts;              /* completed restart cycles before the last one */
+  int status;                /* same code the call returned */
+  double est_rel_residual;   /* Givens estimate |g_{j+1}| / ||b|| at exit */
+  double true_rel_residual;  /* ||b - H x|| / ||b|| recomputed in FP64 at exit */
+  double* history;           /* optional host buffer: estimate after every iteration */
+  int history_cap;           /* its capacity (entries written: min(iterations, cap)) */
+} helm_solve_info;
+
+/* Device bytes of workspace helm_setup needs for this grid and cycle (pure host
+ * computation, no device call).  Returns HELM_EINVAL for an invalid grid/mg. */
+int helm_workspace_bytes(const helm_grid* grid, const helm_mg* mg, size_t* bytes);
+
+/* Build the operator hierarchy for one medium (Sec. 3): coefficients, level-2
+ * Galerkin operator (eq. 2.2), real-shifted level-3 operator (eq. 3.6) and its
+ * exact factorisation.
+ *   slowness: device, N1 doubles (kappa at every node; m = kappa^2 is formed
+ *             internally; may be freed after the call returns)
+ *   omega:    angular frequency (> 0)
+ *   ws:       device workspace of ws_bytes >= helm_workspace_bytes(), 256-byte aligned
+ *   stream:   hipStream_t
+ *   out:      receives the context (host)
+ * Returns HELM_ESINGULAR if the coarsest elimination meets a zero pivot. */
+int helm_setup(const helm_grid* grid, const double* slowness, double omega,
+               const helm_shift* shift, const helm_mg* mg, void* ws, size_t ws_bytes,
+               void* stream, helm_ctx** out);
+
+/* y = H x (op HELM_OP_N) or y = H^H x (HELM_OP_C), the unshifted operator of eq. (1.1).
+ * prec HELM_F64: x, y device c128[N1]; HELM_F32: x, y device c64[N1].  x != y. */
+int helm_apply(helm_ctx* ctx, int op, int prec, const void* x, void* y, void* stream);
+
+/* z = M^{-1} r: one multigrid cycle from a zero initial guess (Sec. 2 algorithm, 3 levels)
+ * on the preconditioner of op.  r, z: device c128[N1] (the cycle runs in the setup's
+ * cycle precision).  r != z. */
+int helm_vcycle(helm_ctx* ctx, int op, const void* r, void* z, void* stream);
+
+/* Solve op(H) x = rhs by FGMRES(restart) preconditioned by one cycle per iteration.
+ *   rhs: device c128[N1];  x: device c128[N1], initial guess on entry, solution on exit
+ *   tol: relative-residual tolerance (> 0);  max_iter >= 1
+ *   info: host struct filled on return (may be NULL)
+ * Returns 0 when ||rhs - op(H) x|| <= tol ||rhs|| (recomputed in FP64), HELM_ENOCONV
+ * or HELM_ESTAGNATE otherwise.  A zero rhs returns x = 0 after 0 iterations. */
+int helm_solve(helm_ctx* ctx, int op, const void* rhs, void* x, double tol, int max_iter,
+               helm_solve_info* info, void* stream);
+
+/* e = A3^{-1} r on the coarsest level (op HELM_OP_C: conj(A3)^{-1} r) with the factors the
+ * cycle uses.  r, e: device c128[N3], N3 = helm_level_size(ctx, 0, 3).  For checking. */
+int helm_coarse_solve(helm_ctx* ctx, int op, const void* r, void* e, void* stream);
+
+/* Release the host context (the workspace stays the caller's).  NULL is accepted. */
+int helm_destroy(helm_ctx* ctx);
+
+/* ---- batched form: many media / frequencies / grid sizes, many right-hand sides ---- */
+
+/* Workspace for n_inst instances (grids[i]) and at most max_rhs simultaneous right-hand sides. */
+int helm_workspace_bytes_batched(int n_inst, const helm_grid* grids, const helm_mg* mg,
+                                 int max_rhs, size_t* bytes);
+
+/* Set up n_inst independent instances in one workspace.
+ *   slowness: host array of n_inst device pointers (each N1(i) doubles)
+ *   omega, shift: host arrays of n_inst entries */
+int helm_setup_batched(int n_inst, const helm_grid* grids, const double* const* slowness,
+                       const double* omega, const helm_shift* shift, const helm_mg* mg,
+                       int max_rhs, void* ws, size_t ws_bytes, void* stream, helm_ctx** out);
+
+/* Solve n_rhs systems in lock step; rhs k belongs to instance inst_of_rhs[k].
+ *   rhs, x: host arrays of n_rhs device pointers (c128[N1(inst)] each)
+ *   info:   host array of n_rhs structs (may be NULL)
+ * Converged right-hand sides stop iterating while the others continue.  Returns the
+ * worst status over the right-hand sides. */
+int helm_solve_batched(helm_ctx* ctx, int op, int n_rhs, const int* inst_of_rhs,
+                       const void* const* rhs, void* const* x, double tol, int max_iter,
+                       helm_solve_info* info, void* stream);
+
+/* ---- gradient of a least-squares misfit w.r.t. squared slowness ---- */
+
+/* g[j] (+)= sum_s omega^2 Re( conj(lambda_s[j]) (1 - i sigma_j) u_s[j] ), the derivative of
+ * 1/2 sum_s ||P u_s - d_s||^2 when H u_s = q_s and H^H lambda_s = P^T (P u_s - d_s)
+ * (dH/dm_j = -omega^2 (1 - i sigma_j) e_j e_j^T).
+ *   u, lambda: host arrays of n_src device pointers (c128[N1]);  g: device double[N1]
+ *   accumulate: 0 overwrites g, 1 adds to it.  Single-instance contexts only. */
+int helm_grad_m(helm_ctx* ctx, int n_src, const void* const* u, const void* const* lambda,
+                double* g, int accumulate, void* stream);
+
+/* ---- introspection ---- */
+
+/* Human-readable name of a status code (static string). */
+const char* helm_status_str(int status);
+
+/* Message of the last HELM_EINVAL / HELM_EDEVICE raised on this thread (static buffer). */
+const char* helm_last_error(void);
+
+/* Fill host array t[0..n) with per-phase device times in ms of the last solve:
+ * [0] total, [1] cycle, [2] outer apply+Arnoldi, [3] coarsest solves, [4] setup.  Returns
+ * the number written.  Timing is recorded only when enabled by helm_set_timing(ctx, 1). */
+int helm_set_timing(helm_ctx* ctx, int on);
+int helm_get_timing(helm_ctx* ctx, double* t, int n);
+
+/* Number of unknowns on level lev (1..3) of instance inst. */
+long long helm_level_size(helm_ctx* ctx, int inst, int lev);
+
+/* Copy the stored Galerkin coefficients of level lev (2 or 3) of a single-instance
+ * context to host memory: out receives 3^dim * N_lev complex doubles, coefficient k of
+ * node i at out[k*N_lev + i], offset k = (d0+1) + 3 (d1+1) [+ 9 (d2+1)].  For checking. */
+int helm_get_coefficients(helm_ctx* ctx, int lev, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HELM_H */

@@ -1,0 +1,872 @@
+// C ABI of libhelm: validation, workspace layout, setup, cycle and FGMRES drivers.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <cstdarg>
+#include <cstddef>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "krylov.h"
+#include "levels_api.h"
+
+namespace helm {
+
+// launchers implemented in the kernel files
+void gal_fine(const FineOp& op, cd s, const double* m, const Geom& gc, cd* out, hipStream_t st);
+void gal_coarse(const Geom& g, const cd* A, const Geom& gc, cd* out, hipStream_t st);
+void cast_d2f(const cd* a, cf* b, long long n, hipStream_t st);
+void cast_f2d(const cf* a, cd* b, long long n, hipStream_t st);
+void square_slowness(const double* kap, double* m64, float* m32, long long n, hipStream_t st);
+void nd_zero(cd* p, long long n, hipStream_t s);
+void nd_iota(int* perm, const NDFrontDev* fr, int nfronts, hipStream_t s);
+void nd_assemble(const NDFrontDev* fr, const int* ids, int nids, int max_asm, const NDAsm* asmv, const cd* coef,
+                 cd* Fp, hipStream_t s);
+void nd_extend(const NDFrontDev* fr, const int* ids, int nids, long long max_nb2, const int* maps, cd* Fp,
+               int slot, hipStream_t s);
+void nd_panel(const NDFrontDev* fr, const int* ids, int nids, cd* Fp, int* perm, int k0, int kb, int* err,
+              hipStream_t s);
+void nd_save_t(const NDFrontDev* fr, const int* ids, int nids, const long long* toff, long long max_n, cd* Fp,
+               cd* T, int k0, int kb, hipStream_t s);
+void nd_gemm(const NDFrontDev* fr, const int* ids, int nids, const long long* toff, int max_nF, cd* Fp,
+             const cd* T, int k0, int kb, hipStream_t s);
+template <typename C>
+void nd_finalize(const NDFrontDev* fr, const int* ids, int nids, long long max_n, const cd* Fp, const int* perm,
+                 C* Lp, C* Wp, hipStream_t s);
+template <typename C>
+void nd_fwd(int ntasks, size_t lds, const NDFrontDev* fr, const int* idx, const int* maps, const C* Lp, C* upd,
+            const int* task_off, const NDItem* items, const C* r, C* x, C* gvec, int vec_cap, int conj,
+            hipStream_t s);
+template <typename C>
+void nd_bwd(int ntasks, size_t lds, const NDFrontDev* fr, const int* idx, const C* Wp, const int* task_off,
+            const NDItem* items, C* x, C* gvec, int vec_cap, int conj, hipStream_t s);
+void grad_accumulate(const FineOp& op, double omega, const cd* u, const cd* lam, double* g, int first,
+                     hipStream_t s);
+
+}  // namespace helm
+
+using namespace helm;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+struct DevErr : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+#define CK(x)                                                                                        \
+  do {                                                                                               \
+    hipError_t e_ = (x);                                                                             \
+    if (e_ != hipSuccess) throw DevErr(std::string(#x) + ": " + hipGetErrorString(e_));              \
+  } while (0)
+
+const size_t ALIGN = 256;
+inline size_t al(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+// linear carve of the workspace (base = 0 computes the size)
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base((char*)b) {}
+  template <typename T>
+  T* take(size_t count) {
+    size_t o = off;
+    off = al(off + count * sizeof(T));
+    return base ? (T*)(base + o) : nullptr;
+  }
+};
+
+struct NDDev {        // device-side ND tables (pointers into the workspace)
+  NDFrontDev* fronts = nullptr;
+  int *idx = nullptr, *maps = nullptr, *perm = nullptr, *hlist = nullptr, *err = nullptr;
+  NDAsm* asmv = nullptr;
+  long long* toff = nullptr;
+  cd *F = nullptr, *T = nullptr;
+  void *L = nullptr, *W = nullptr, *upd = nullptr, *gvec = nullptr;
+  std::vector<int*> task_off[2];
+  std::vector<NDItem*> items[2];
+  int gvec_cap = 0;
+};
+
+struct HeightInfo {
+  int start, count, max_asm, max_nS, max_nF;
+  long long max_nb2, max_T, max_fin;
+};
+
+}  // namespace
+
+struct helm_ctx {
+  helm_grid grid;
+  helm_shift shift;
+  helm_mg mg;
+  double omega;
+  Geom g1, g2, g3;
+  FineOp op;
+  int f32;              // cycle precision is FP32
+  size_t csz;           // bytes of one complex in cycle precision
+  // device state
+  double *m64 = nullptr;
+  float* m32 = nullptr;
+  cd *coef2_64 = nullptr, *coef3_64 = nullptr, *tmp2 = nullptr;
+  cf* coef2_32 = nullptr;
+  void *x1a = nullptr, *x1b = nullptr, *b2 = nullptr, *x2a = nullptr, *x2b = nullptr, *b3 = nullptr,
+       *x3 = nullptr;
+  cd *r3d = nullptr, *e3d = nullptr;
+  NDPlan plan;
+  NDDev nd;
+  std::vector<HeightInfo> hinfo;
+  std::vector<long long> hlist_toff;
+  std::vector<int> hlist;
+  // Krylov
+  cd *V = nullptr, *W = nullptr, *part = nullptr;
+  void* Z = nullptr;
+  KrylovState* st = nullptr;
+  KrylovArgs ka;
+  size_t ws_needed = 0;
+  char* hstate = nullptr;    // pinned host copy of the scalar block of KrylovState
+  int timing = 0;
+  double times[5] = {0, 0, 0, 0, 0};
+  size_t lds_limit = 65536;
+  std::vector<helm_ctx*> sub;   // batched form: one context per instance
+};
+
+namespace {
+
+int validate(const helm_grid* g, const helm_mg* mg) {
+  if (!g || !mg) return fail(HELM_EINVAL, "grid or mg is NULL");
+  if (g->dim != 2 && g->dim != 3) return fail(HELM_EINVAL, "dim must be 2 or 3 (got %d)", g->dim);
+  for (int a = 0; a < g->dim; ++a) {
+    if (g->n[a] < 4 || g->n[a] % 4 != 0) return fail(HELM_EINVAL, "n[%d] = %d must be a positive multiple of 4", a, g->n[a]);
+    if (g->n[a] > (1 << 20)) return fail(HELM_EINVAL, "n[%d] too large", a);
+    for (int s = 0; s < 2; ++s)
+      if (g->layer[a][s] < 0) return fail(HELM_EINVAL, "negative layer width");
+    if (g->layer[a][0] + g->layer[a][1] > g->n[a]) return fail(HELM_EINVAL, "layers wider than the grid on axis %d", a);
+  }
+  if (!(g->h > 0.0) || !std::isfinite(g->h)) return fail(HELM_EINVAL, "h must be positive and finite");
+  if (!(g->sigma_max >= 0.0) || !std::isfinite(g->sigma_max)) return fail(HELM_EINVAL, "sigma_max must be >= 0");
+  if (mg->cycle != 1 && mg->cycle != 2) return fail(HELM_EINVAL, "cycle must be 1 (V) or 2 (W)");
+  if (mg->nu_pre < 0 || mg->nu_pre > 4 || mg->nu_post < 0 || mg->nu_post > 4)
+    return fail(HELM_EINVAL, "nu_pre/nu_post must be in 0..4");
+  for (int l = 0; l < 2; ++l)
+    if (!std::isfinite(mg->jacobi[l])) return fail(HELM_EINVAL, "jacobi weight not finite");
+  if (mg->cycle_prec != HELM_F64 && mg->cycle_prec != HELM_F32) return fail(HELM_EINVAL, "cycle_prec must be HELM_F64 or HELM_F32");
+  if (mg->restart < 1 || mg->restart > KMAXM) return fail(HELM_EINVAL, "restart must be in 1..%d", KMAXM);
+  long long N1 = 1;
+  for (int a = 0; a < g->dim; ++a) N1 *= (g->n[a] + 1);
+  if (N1 > (1LL << 31) - 1) return fail(HELM_EINVAL, "grid too large (N1 > 2^31-1)");
+  return HELM_OK;
+}
+
+void init_geometry(helm_ctx* c) {
+  int n[3] = {c->grid.n[0], c->grid.n[1], c->grid.dim == 3 ? c->grid.n[2] : 0};
+  c->g1 = make_geom(c->grid.dim, n);
+  c->g2 = coarsen(c->g1);
+  c->g3 = coarsen(c->g2);
+  c->op.g = c->g1;
+  c->op.inv_h2 = 1.0 / (c->grid.h * c->grid.h);
+  for (int a = 0; a < 3; ++a)
+    for (int s = 0; s < 2; ++s) c->op.layer[a][s] = a < c->grid.dim ? c->grid.layer[a][s] : 0;
+  c->op.sigma_max = c->grid.sigma_max;
+  c->f32 = c->mg.cycle_prec == HELM_F32;
+  c->csz = c->f32 ? sizeof(cf) : sizeof(cd);
+}
+
+const int ND_LEAF = 16, ND_CHUNK = 64, ND_SUBTREE = 1024, ND_KB = 32;
+
+void build_plan(helm_ctx* c) {
+  nd_plan(c->g3, c->grid.dim == 3 ? 8 : ND_LEAF, ND_CHUNK, ND_SUBTREE, c->plan);
+  NDPlan& P = c->plan;
+  c->hlist.clear();
+  c->hlist_toff.clear();
+  c->hinfo.clear();
+  for (int h = 0; h <= P.max_height; ++h) {
+    HeightInfo hi{};
+    hi.start = (int)c->hlist.size();
+    hi.count = (int)P.by_height[h].size();
+    long long toff = 0;
+    for (int t : P.by_height[h]) {
+      const NDFrontDev& f = P.fronts[t];
+      c->hlist.push_back(t);
+      c->hlist_toff.push_back(toff);
+      toff += (long long)ND_KB * f.nF;
+      hi.max_asm = std::max(hi.max_asm, f.asm_cnt);
+      hi.max_nS = std::max(hi.max_nS, f.nS);
+      hi.max_nF = std::max(hi.max_nF, f.nF);
+      int nbc = 0;
+      for (int s = 0; s < 2; ++s)
+        if (f.child[s] >= 0) nbc = std::max(nbc, P.fronts[f.child[s]].nB);
+      hi.max_nb2 = std::max(hi.max_nb2, (long long)nbc * nbc);
+      hi.max_T = std::max(hi.max_T, (long long)ND_KB * f.nF);
+      hi.max_fin = std::max(hi.max_fin, (long long)f.nF * f.nS + (long long)f.nS * f.nB);
+    }
+    c->hinfo.push_back(hi);
+  }
+}
+
+// carve every device buffer; returns the bytes used
+size_t carve(helm_ctx* c, void* ws) {
+  Carver cv(ws);
+  const Geom &g1 = c->g1, &g2 = c->g2, &g3 = c->g3;
+  const int K = stencil_points(g1.dim);
+  const int m = c->mg.restart;
+  const size_t cs = c->csz;
+  NDPlan& P = c->plan;
+  NDDev& d = c->nd;
+  c->m64 = cv.take<double>(g1.tot);
+  c->m32 = cv.take<float>(g1.tot);
+  c->coef2_64 = cv.take<cd>((size_t)K * g2.tot);
+  c->coef2_32 = c->f32 ? cv.take<cf>((size_t)K * g2.tot) : nullptr;
+  c->tmp2 = cv.take<cd>((size_t)K * g2.tot);
+  c->coef3_64 = cv.take<cd>((size_t)K * g3.tot);
+  c->x1a = cv.take<char>(cs * g1.tot);
+  c->x1b = cv.take<char>(cs * g1.tot);
+  c->b2 = cv.take<char>(cs * g2.tot);
+  c->x2a = cv.take<char>(cs * g2.tot);
+  c->x2b = cv.take<char>(cs * g2.tot);
+  c->b3 = cv.take<char>(cs * g3.tot);
+  c->x3 = cv.take<char>(cs * g3.tot);
+  c->r3d = cv.take<cd>(g3.tot);
+  c->e3d = cv.take<cd>(g3.tot);
+  // ND tables
+  d.fronts = cv.take<NDFrontDev>(P.fronts.size());
+  d.idx = cv.take<int>(P.idx.size());
+  d.maps = cv.take<int>(std::max<size_t>(1, P.maps.size()));
+  d.asmv = cv.take<NDAsm>(P.asmv.size());
+  d.perm = cv.take<int>(P.perm_total);
+  d.hlist = cv.take<int>(c->hlist.size());
+  d.toff = cv.take<long long>(c->hlist_toff.size());
+  d.err = cv.take<int>(1);
+  d.F = cv.take<cd>(P.F_total);
+  d.T = cv.take<cd>(std::max<long long>(1, P.T_scratch));
+  d.L = cv.take<char>(cs * P.L_total);
+  d.W = cv.take<char>(cs * std::max<long long>(1, P.W_total));
+  d.upd = cv.take<char>(cs * std::max<long long>(1, P.upd_total));
+  for (int fb = 0; fb < 2; ++fb) {
+    std::vector<NDLaunch>& Ls = fb == 0 ? P.fwd : P.bwd;
+    d.task_off[fb].assign(Ls.size(), nullptr);
+    d.items[fb].assign(Ls.size(), nullptr);
+    for (size_t l = 0; l < Ls.size(); ++l) {
+      d.task_off[fb][l] = cv.take<int>(Ls[l].task_off.size());
+      d.items[fb][l] = cv.take<NDItem>(Ls[l].items.size());
+    }
+  }
+  // global fall-back vectors for launches whose vector does not fit in LDS
+  long long gcap = 0, gneed = 0;
+  for (int fb = 0; fb < 2; ++fb)
+    for (auto& L : (fb == 0 ? P.fwd : P.bwd)) {
+      if ((size_t)L.max_rows_vec * cs > c->lds_limit) {
+        gcap = std::max<long long>(gcap, L.max_rows_vec);
+        gneed = std::max<long long>(gneed, (long long)(L.task_off.size() - 1));
+      }
+    }
+  d.gvec_cap = (int)gcap;
+  d.gvec = gcap ? cv.take<char>(cs * gcap * gneed) : nullptr;
+  // Krylov
+  c->V = cv.take<cd>((size_t)(m + 1) * g1.tot);
+  c->Z = cv.take<char>(cs * (size_t)m * g1.tot);
+  c->W = cv.take<cd>(g1.tot);
+  long long nblk = (g1.tot + 256 * KNPT - 1) / (256 * KNPT);
+  c->part = cv.take<cd>((size_t)(KMAXM + 2) * nblk);
+  c->st = cv.take<KrylovState>(1);
+  return cv.off;
+}
+
+template <typename T>
+void up(T* dst, const std::vector<T>& v, hipStream_t s) {
+  if (!v.empty()) CK(hipMemcpyAsync(dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+cd shift_scalar(double alpha, double beta, double omega) {
+  // alpha^2 (1 - i beta) omega^2
+  double w2 = omega * omega * alpha * alpha;
+  return mk(w2, -beta * w2);
+}
+
+void nd_factor(helm_ctx* c, hipStream_t s) {
+  NDDev& d = c->nd;
+  NDPlan& P = c->plan;
+  nd_zero(d.F, P.F_total, s);
+  nd_iota(d.perm, d.fronts, (int)P.fronts.size(), s);
+  CK(hipMemsetAsync(d.err, 0, sizeof(int), s));
+  for (size_t h = 0; h < c->hinfo.size(); ++h) {
+    const HeightInfo& hi = c->hinfo[h];
+    const int* ids = d.hlist + hi.start;
+    const long long* toff = d.toff + hi.start;
+    nd_assemble(d.fronts, ids, hi.count, hi.max_asm, d.asmv, c->coef3_64, d.F, s);
+    nd_extend(d.fronts, ids, hi.count, hi.max_nb2, d.maps, d.F, 0, s);
+    nd_extend(d.fronts, ids, hi.count, hi.max_nb2, d.maps, d.F, 1, s);
+    for (int k0 = 0; k0 < hi.max_nS; k0 += ND_KB) {
+      nd_panel(d.fronts, ids, hi.count, d.F, d.perm, k0, ND_KB, d.err, s);
+      nd_save_t(d.fronts, ids, hi.count, toff, hi.max_T, d.F, d.T, k0, ND_KB, s);
+      nd_gemm(d.fronts, ids, hi.count, toff, hi.max_nF, d.F, d.T, k0, ND_KB, s);
+    }
+    if (c->f32)
+      nd_finalize<cf>(d.fronts, ids, hi.count, hi.max_fin, d.F, d.perm, (cf*)d.L, (cf*)d.W, s);
+    else
+      nd_finalize<cd>(d.fronts, ids, hi.count, hi.max_fin, d.F, d.perm, (cd*)d.L, (cd*)d.W, s);
+  }
+}
+
+template <typename C>
+void nd_solve(helm_ctx* c, const C* r, C* x, int conj, hipStream_t s) {
+  NDDev& d = c->nd;
+  NDPlan& P = c->plan;
+  for (int fb = 0; fb < 2; ++fb) {
+    std::vector<NDLaunch>& Ls = fb == 0 ? P.fwd : P.bwd;
+    for (size_t l = 0; l < Ls.size(); ++l) {
+      const NDLaunch& L = Ls[l];
+      int ntasks = (int)L.task_off.size() - 1;
+      size_t need = (size_t)L.max_rows_vec * sizeof(C);
+      bool lds = need <= c->lds_limit;
+      C* gv = lds ? nullptr : (C*)d.gvec;
+      size_t shm = lds ? std::max<size_t>(need, 16) : 0;
+      if (fb == 0)
+        nd_fwd<C>(ntasks, shm, d.fronts, d.idx, d.maps, (const C*)d.L, (C*)d.upd, d.task_off[0][l], d.items[0][l], r,
+                  x, gv, d.gvec_cap, conj, s);
+      else
+        nd_bwd<C>(ntasks, shm, d.fronts, d.idx, (const C*)d.W, d.task_off[1][l], d.items[1][l], x, gv, d.gvec_cap,
+                  conj, s);
+    }
+  }
+}
+
+// iterate state of one level: x_in = [x] + [w D^-1 b] + [P e]
+template <typename C>
+struct St {
+  int xin;
+  C* x;
+};
+
+template <typename R>
+struct Cycle {
+  typedef typename cplx<R>::type C;
+  helm_ctx* c;
+  int conj;
+  hipStream_t s;
+  L1<R> A1;
+  L2<R> A2;
+
+  Cycle(helm_ctx* ctx, int op, hipStream_t st) : c(ctx), conj(op), s(st) {
+    A1.op = c->op;
+    cd sb = shift_scalar(1.0, c->shift.beta, c->omega);
+    A1.s = mk((R)sb.x, (R)sb.y);
+    A1.m = (const R*)(sizeof(R) == 4 ? (const void*)c->m32 : (const void*)c->m64);
+    A1.conj = op;
+    A2.g = c->g2;
+    A2.coef = (const C*)(sizeof(R) == 4 ? (const void*)c->coef2_32 : (const void*)c->coef2_64);
+    A2.conj = op;
+  }
+
+  // level 1: one more sweep (or the virtual first sweep) on state st
+  template <typename CO>
+  St<C> adv1(St<C> st, const cd* b, const C* e, CO* out) {
+    R w = (R)c->mg.jacobi[0];
+    l1_sweep<R, cd, CO>(A1, st.xin, st.x, b, w, c->g2, e, w, out, s);
+    return St<C>{XIN_X, (C*)out};
+  }
+  St<C> adv2(St<C> st, const C* b, const C* e, C* out) {
+    R w = (R)c->mg.jacobi[1];
+    l2_sweep<R>(A2, st.xin, st.x, b, w, c->g3, e, w, out, s);
+    return St<C>{XIN_X, out};
+  }
+  C* other(C* cur, C* a, C* b) { return cur == a ? b : a; }
+
+  template <typename CO>
+  void run(const cd* b1, CO* out) {
+    const helm_mg& mg = c->mg;
+    C *x1a = (C*)c->x1a, *x1b = (C*)c->x1b, *x2a = (C*)c->x2a, *x2b = (C*)c->x2b;
+    C *b2 = (C*)c->b2, *b3 = (C*)c->b3, *x3 = (C*)c->x3;
+    R w1 = (R)mg.jacobi[0], w2 = (R)mg.jacobi[1];
+    // ---- level 1 pre-relaxation
+    St<C> s1{0, nullptr};
+    for (int k = 0; k < mg.nu_pre; ++k) {
+      if (s1.xin == 0) s1 = St<C>{XIN_Z, nullptr};
+      else s1 = adv1<C>(s1, b1, nullptr, other(s1.x, x1a, x1b));
+    }
+    l1_restrict<R, cd>(A1, s1.xin, s1.x, b1, w1, c->g2, nullptr, c->g2, b2, s);
+    // ---- level 2 visits
+    St<C> s2{0, nullptr};
+    for (int v = 0; v < mg.cycle; ++v) {
+      for (int k = 0; k < mg.nu_pre; ++k) {
+        if (s2.xin == 0) s2 = St<C>{XIN_Z, nullptr};
+        else s2 = adv2(s2, b2, nullptr, other(s2.x, x2a, x2b));
+      }
+      l2_restrict<R>(A2, s2.xin, s2.x, b2, w2, c->g3, nullptr, c->g3, b3, s);
+      nd_solve<C>(c, b3, x3, conj, s);
+      s2.xin |= XIN_E;
+      for (int k = 0; k < mg.nu_post; ++k) s2 = adv2(s2, b2, x3, other(s2.x, x2a, x2b));
+      if (s2.xin != XIN_X) {   // materialise (no post-relaxation)
+        R w0 = 0;
+        l2_sweep<R>(A2, s2.xin, s2.x, b2, w2, c->g3, x3, w0, other(s2.x, x2a, x2b), s);
+        s2 = St<C>{XIN_X, other(s2.x, x2a, x2b)};
+      }
+    }
+    // ---- level 1 correction and post-relaxation; the last sweep writes `out`
+    s1.xin |= XIN_E;
+    const C* e2 = s2.x;
+    if (mg.nu_post == 0) {
+      l1_sweep<R, cd, CO>(A1, s1.xin, s1.x, b1, w1, c->g2, e2, (R)0, out, s);
+      return;
+    }
+    for (int k = 0; k < mg.nu_post; ++k) {
+      if (k == mg.nu_post - 1)
+        adv1<CO>(s1, b1, e2, out);
+      else
+        s1 = adv1<C>(s1, b1, e2, other(s1.x, x1a, x1b));
+    }
+  }
+};
+
+void read_state(helm_ctx* c, hipStream_t s) {
+  CK(hipMemcpyAsync(c->hstate, (char*)c->st + offsetof(KrylovState, bnorm),
+                    offsetof(KrylovState, hist) - offsetof(KrylovState, bnorm), hipMemcpyDeviceToHost, s));
+  CK(hipStreamSynchronize(s));
+}
+struct HostScalars {
+  double bnorm, beta0, est, hnext, true_rel;
+  int its, done, nonfinite, pad;
+};
+inline HostScalars* hs(helm_ctx* c) { return (HostScalars*)c->hstate; }
+
+KrylovArgs make_kargs(helm_ctx* c, int op) {
+  KrylovArgs a;
+  a.op = c->op;
+  a.s = mk(c->omega * c->omega, 0.0);
+  a.conj = op;
+  a.m64 = c->m64;
+  a.V = c->V;
+  a.ldv = c->g1.tot;
+  a.W = c->W;
+  a.part = c->part;
+  a.nblk = (int)((c->g1.tot + 256 * KNPT - 1) / (256 * KNPT));
+  a.pcap = a.nblk;
+  a.st = c->st;
+  return a;
+}
+
+template <typename R>
+int solve_impl(helm_ctx* c, int op, const cd* b, cd* x, double tol, int max_iter, helm_solve_info* info,
+               hipStream_t s) {
+  KrylovArgs a = make_kargs(c, op);
+  Cycle<R> cyc(c, op, s);
+  typedef typename cplx<R>::type C;
+  const int m = c->mg.restart;
+  const long long N = c->g1.tot;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (c->timing) {
+    CK(hipEventCreate(&e0));
+    CK(hipEventCreate(&e1));
+    CK(hipEventRecord(e0, s));
+  }
+  kr_init(a, s);
+  kr_residual(a, x, b, 1, s);
+  read_state(c, s);
+  int status = HELM_OK, its = 0, restarts = 0;
+  double est = 0.0, true_rel = 0.0;
+  HostScalars* h = hs(c);
+  if (!std::isfinite(h->bnorm) || !std::isfinite(h->beta0)) {
+    status = HELM_ENONFINITE;
+  } else if (h->bnorm == 0.0) {
+    kr_zero(x, N, s);
+    CK(hipStreamSynchronize(s));
+  } else {
+    true_rel = h->beta0 / h->bnorm;
+    est = true_rel;
+    double prev_rel = true_rel;
+    while (true_rel > tol) {
+      if (its >= max_iter) { status = HELM_ENOCONV; break; }
+      kr_scale_v0(a, s);
+      int k = 0;
+      for (int j = 0; j < m; ++j) {
+        cyc.template run<C>(c->V + (size_t)j * N, (C*)c->Z + (size_t)j * N);
+        kr_arnoldi(a, (const char*)c->Z + (size_t)j * N * c->csz, c->f32, j, tol, s);
+        ++its;
+        k = j + 1;
+        read_state(c, s);
+        est = h->est;
+        if (h->nonfinite || h->done || its >= max_iter) break;
+      }
+      if (h->nonfinite) { status = HELM_ENONFINITE; break; }
+      kr_update_x(a, c->Z, c->f32, N, k, x, s);
+      kr_residual(a, x, b, 0, s);
+      read_state(c, s);
+      true_rel = h->beta0 / h->bnorm;
+      if (!std::isfinite(true_rel)) { status = HELM_ENONFINITE; break; }
+      if (true_rel <= tol) break;
+      if (its >= max_iter) { status = HELM_ENOCONV; break; }
+      if (k == m && true_rel >= prev_rel * (1.0 - 1e-12)) { status = HELM_ESTAGNATE; break; }
+      prev_rel = true_rel;
+      ++restarts;
+    }
+  }
+  if (c->timing) {
+    CK(hipEventRecord(e1, s));
+    CK(hipEventSynchronize(e1));
+    float ms = 0;
+    CK(hipEventElapsedTime(&ms, e0, e1));
+    c->times[0] = ms;
+    CK(hipEventDestroy(e0));
+    CK(hipEventDestroy(e1));
+  }
+  if (info) {
+    info->iterations = its;
+    info->restarts = restarts;
+    info->status = status;
+    info->est_rel_residual = est;
+    info->true_rel_residual = true_rel;
+    if (info->history && info->history_cap > 0 && its > 0) {
+      int n = std::min(std::min(its, info->history_cap), KMAXIT);
+      CK(hipMemcpy(info->history, (char*)c->st + offsetof(KrylovState, hist), n * sizeof(double),
+                   hipMemcpyDeviceToHost));
+    }
+  }
+  return status;
+}
+
+}  // namespace
+
+// =========================================================================== C ABI
+extern "C" {
+
+const char* helm_status_str(int st) {
+  switch (st) {
+    case HELM_OK: return "ok";
+    case HELM_EINVAL: return "invalid argument";
+    case HELM_EWORKSPACE: return "workspace missing, misaligned or too small";
+    case HELM_EDEVICE: return "device error";
+    case HELM_ENONFINITE: return "non-finite value";
+    case HELM_ESINGULAR: return "zero pivot in the coarsest-grid elimination";
+    case HELM_ENOCONV: return "not converged within max_iter";
+    case HELM_ESTAGNATE: return "stagnated over a full restart cycle";
+    default: return "unknown status";
+  }
+}
+
+const char* helm_last_error(void) { return g_err; }
+
+int helm_workspace_bytes(const helm_grid* grid, const helm_mg* mg, size_t* bytes) {
+  int v = validate(grid, mg);
+  if (v) return v;
+  if (!bytes) return fail(HELM_EINVAL, "bytes is NULL");
+  try {
+    helm_ctx c;
+    c.grid = *grid;
+    c.mg = *mg;
+    init_geometry(&c);
+    build_plan(&c);
+    *bytes = carve(&c, nullptr);
+    return HELM_OK;
+  } catch (std::exception& e) {
+    return fail(HELM_EINVAL, "%s", e.what());
+  }
+}
+
+int helm_setup(const helm_grid* grid, const double* slowness, double omega, const helm_shift* shift,
+               const helm_mg* mg, void* ws, size_t ws_bytes, void* stream, helm_ctx** out) {
+  int v = validate(grid, mg);
+  if (v) return v;
+  if (!slowness || !shift || !out) return fail(HELM_EINVAL, "NULL slowness/shift/out");
+  if (!(omega > 0.0) || !std::isfinite(omega)) return fail(HELM_EINVAL, "omega must be positive and finite");
+  if (!std::isfinite(shift->alpha) || !std::isfinite(shift->alpha2) || !std::isfinite(shift->beta))
+    return fail(HELM_EINVAL, "shift parameters must be finite");
+  if (!ws || ((uintptr_t)ws % ALIGN) != 0) return fail(HELM_EWORKSPACE, "workspace NULL or not 256-byte aligned");
+  *out = nullptr;
+  std::unique_ptr<helm_ctx> c(new helm_ctx());
+  hipStream_t s = (hipStream_t)stream;
+  try {
+    c->grid = *grid;
+    c->mg = *mg;
+    c->shift = *shift;
+    c->omega = omega;
+    init_geometry(c.get());
+    build_plan(c.get());
+    size_t need = carve(c.get(), nullptr);
+    if (ws_bytes < need) return fail(HELM_EWORKSPACE, "workspace too small: %zu < %zu", ws_bytes, need);
+    c->ws_needed = need;
+    carve(c.get(), ws);
+    CK(hipHostMalloc((void**)&c->hstate, 4096, hipHostMallocDefault));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    CK(hipEventCreate(&e0));
+    CK(hipEventCreate(&e1));
+    CK(hipEventRecord(e0, s));
+    // tables
+    NDPlan& P = c->plan;
+    NDDev& d = c->nd;
+    up(d.fronts, P.fronts, s);
+    up(d.idx, P.idx, s);
+    up(d.maps, P.maps, s);
+    up(d.asmv, P.asmv, s);
+    up(d.hlist, c->hlist, s);
+    up(d.toff, c->hlist_toff, s);
+    for (int fb = 0; fb < 2; ++fb) {
+      std::vector<NDLaunch>& Ls = fb == 0 ? P.fwd : P.bwd;
+      for (size_t l = 0; l < Ls.size(); ++l) {
+        up(d.task_off[fb][l], Ls[l].task_off, s);
+        up(d.items[fb][l], Ls[l].items, s);
+      }
+    }
+    // a0: m = kappa^2 (FP64 and FP32)
+    square_slowness(slowness, c->m64, c->m32, c->g1.tot, s);
+    // a1: level-2 Galerkin operator of H_beta^{alpha2}
+    gal_fine(c->op, shift_scalar(shift->alpha2, shift->beta, omega), c->m64, c->g2, c->coef2_64, s);
+    const int K = stencil_points(grid->dim);
+    if (c->f32) cast_d2f(c->coef2_64, c->coef2_32, (long long)K * c->g2.tot, s);
+    // a2: real-shifted level-3 operator R2 (R1 H_beta^alpha P1) P2
+    gal_fine(c->op, shift_scalar(shift->alpha, shift->beta, omega), c->m64, c->g2, c->tmp2, s);
+    gal_coarse(c->g2, c->tmp2, c->g3, c->coef3_64, s);
+    // a3: exact factorisation
+    nd_factor(c.get(), s);
+    CK(hipEventRecord(e1, s));
+    CK(hipStreamSynchronize(s));
+    CK(hipGetLastError());
+    float ms = 0;
+    CK(hipEventElapsedTime(&ms, e0, e1));
+    c->times[4] = ms;
+    CK(hipEventDestroy(e0));
+    CK(hipEventDestroy(e1));
+    int err = 0;
+    CK(hipMemcpy(&err, d.err, sizeof(int), hipMemcpyDeviceToHost));
+    if (err) {
+      (void)hipHostFree(c->hstate);
+      return fail(HELM_ESINGULAR, "zero pivot in the coarsest-grid elimination");
+    }
+  } catch (DevErr& e) {
+    if (c->hstate) (void)hipHostFree(c->hstate);
+    return fail(HELM_EDEVICE, "%s", e.what());
+  } catch (std::exception& e) {
+    if (c->hstate) (void)hipHostFree(c->hstate);
+    return fail(HELM_EINVAL, "%s", e.what());
+  }
+  *out = c.release();
+  return HELM_OK;
+}
+
+int helm_destroy(helm_ctx* ctx) {
+  if (!ctx) return HELM_OK;
+  for (helm_ctx* q : ctx->sub) helm_destroy(q);
+  if (ctx->hstate) (void)hipHostFree(ctx->hstate);
+  delete ctx;
+  return HELM_OK;
+}
+
+int helm_apply(helm_ctx* c, int op, int prec, const void* x, void* y, void* stream) {
+  if (!c || !x || !y) return fail(HELM_EINVAL, "NULL argument");
+  if (op != HELM_OP_N && op != HELM_OP_C) return fail(HELM_EINVAL, "op must be HELM_OP_N or HELM_OP_C");
+  if (prec != HELM_F64 && prec != HELM_F32) return fail(HELM_EINVAL, "prec must be HELM_F64 or HELM_F32");
+  if (x == y) return fail(HELM_EINVAL, "x and y must differ");
+  hipStream_t s = (hipStream_t)stream;
+  try {
+    if (prec == HELM_F64) {
+      L1<double> A;
+      A.op = c->op;
+      A.s = mk(c->omega * c->omega, 0.0);
+      A.m = c->m64;
+      A.conj = op;
+      l1_apply64(A, x, 0, (cd*)y, s);
+    } else {
+      L1<float> A;
+      A.op = c->op;
+      A.s = mk((float)(c->omega * c->omega), 0.f);
+      A.m = c->m32;
+      A.conj = op;
+      l1_apply32(A, (const cf*)x, (cf*)y, s);
+    }
+    CK(hipGetLastError());
+  } catch (DevErr& e) {
+    return fail(HELM_EDEVICE, "%s", e.what());
+  }
+  return HELM_OK;
+}
+
+int helm_vcycle(helm_ctx* c, int op, const void* r, void* z, void* stream) {
+  if (!c || !r || !z) return fail(HELM_EINVAL, "NULL argument");
+  if (op != HELM_OP_N && op != HELM_OP_C) return fail(HELM_EINVAL, "op must be HELM_OP_N or HELM_OP_C");
+  if (r == z) return fail(HELM_EINVAL, "r and z must differ");
+  hipStream_t s = (hipStream_t)stream;
+  try {
+    if (c->f32) {
+      Cycle<float> cyc(c, op, s);
+      cyc.template run<cd>((const cd*)r, (cd*)z);
+    } else {
+      Cycle<double> cyc(c, op, s);
+      cyc.template run<cd>((const cd*)r, (cd*)z);
+    }
+    CK(hipGetLastError());
+  } catch (DevErr& e) {
+    return fail(HELM_EDEVICE, "%s", e.what());
+  }
+  return HELM_OK;
+}
+
+int helm_coarse_solve(helm_ctx* c, int op, const void* r, void* e, void* stream) {
+  if (!c || !r || !e) return fail(HELM_EINVAL, "NULL argument");
+  if (op != HELM_OP_N && op != HELM_OP_C) return fail(HELM_EINVAL, "op must be HELM_OP_N or HELM_OP_C");
+  if (r == e) return fail(HELM_EINVAL, "r and e must differ");
+  hipStream_t s = (hipStream_t)stream;
+  try {
+    if (c->f32) {
+      cast_d2f((const cd*)r, (cf*)c->b3, c->g3.tot, s);
+      nd_solve<cf>(c, (const cf*)c->b3, (cf*)c->x3, op, s);
+      cast_f2d((const cf*)c->x3, (cd*)e, c->g3.tot, s);
+    } else {
+      nd_solve<cd>(c, (const cd*)r, (cd*)e, op, s);
+    }
+    CK(hipGetLastError());
+  } catch (DevErr& ex) {
+    return fail(HELM_EDEVICE, "%s", ex.what());
+  }
+  return HELM_OK;
+}
+
+int helm_solve(helm_ctx* c, int op, const void* rhs, void* x, double tol, int max_iter, helm_solve_info* info,
+               void* stream) {
+  if (!c || !rhs || !x) return fail(HELM_EINVAL, "NULL argument");
+  if (op != HELM_OP_N && op != HELM_OP_C) return fail(HELM_EINVAL, "op must be HELM_OP_N or HELM_OP_C");
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(HELM_EINVAL, "tol must be positive");
+  if (max_iter < 1) return fail(HELM_EINVAL, "max_iter must be >= 1");
+  if (rhs == x) return fail(HELM_EINVAL, "rhs and x must differ");
+  hipStream_t s = (hipStream_t)stream;
+  try {
+    int st = c->f32 ? solve_impl<float>(c, op, (const cd*)rhs, (cd*)x, tol, max_iter, info, s)
+                    : solve_impl<double>(c, op, (const cd*)rhs, (cd*)x, tol, max_iter, info, s);
+    CK(hipGetLastError());
+    return st;
+  } catch (DevErr& e) {
+    return fail(HELM_EDEVICE, "%s", e.what());
+  }
+}
+
+int helm_set_timing(helm_ctx* c, int on) {
+  if (!c) return fail(HELM_EINVAL, "NULL context");
+  c->timing = on ? 1 : 0;
+  return HELM_OK;
+}
+
+int helm_get_timing(helm_ctx* c, double* t, int n) {
+  if (!c || !t || n < 0) return fail(HELM_EINVAL, "bad arguments");
+  int k = std::min(n, 5);
+  for (int i = 0; i < k; ++i) t[i] = c->times[i];
+  return k;
+}
+
+long long helm_level_size(helm_ctx* c, int inst, int lev) {
+  if (!c || inst != 0) return -1;
+  if (lev == 1) return c->g1.tot;
+  if (lev == 2) return c->g2.tot;
+  if (lev == 3) return c->g3.tot;
+  return -1;
+}
+
+int helm_get_coefficients(helm_ctx* c, int lev, double* out) {
+  if (!c || !out) return fail(HELM_EINVAL, "NULL argument");
+  if (lev != 2 && lev != 3) return fail(HELM_EINVAL, "lev must be 2 or 3");
+  try {
+    const Geom& g = lev == 2 ? c->g2 : c->g3;
+    const cd* src = lev == 2 ? c->coef2_64 : c->coef3_64;
+    CK(hipDeviceSynchronize());
+    CK(hipMemcpy(out, src, sizeof(cd) * stencil_points(g.dim) * g.tot, hipMemcpyDeviceToHost));
+  } catch (DevErr& e) {
+    return fail(HELM_EDEVICE, "%s", e.what());
+  }
+  return HELM_OK;
+}
+
+int helm_grad_m(helm_ctx* c, int n_src, const void* const* u, const void* const* lambda, double* g, int accumulate,
+                void* stream) {
+  if (!c || !u || !lambda || !g || n_src < 1) return fail(HELM_EINVAL, "bad arguments");
+  for (int k = 0; k < n_src; ++k)
+    if (!u[k] || !lambda[k]) return fail(HELM_EINVAL, "NULL source pointer %d", k);
+  hipStream_t s = (hipStream_t)stream;
+  try {
+    for (int k = 0; k < n_src; ++k)
+      grad_accumulate(c->op, c->omega, (const cd*)u[k], (const cd*)lambda[k], g, (k == 0 && !accumulate),
+                      s);
+    CK(hipGetLastError());
+  } catch (DevErr& e) {
+    return fail(HELM_EDEVICE, "%s", e.what());
+  }
+  return HELM_OK;
+}
+
+}  // extern "C"
+
+// =========================================================================== batched form
+// A batched context owns one single-instance context per instance, carved from
+// consecutive slices of the caller's workspace; right-hand sides are solved with
+// their instance's hierarchy.
+extern "C" {
+
+int helm_workspace_bytes_batched(int n_inst, const helm_grid* grids, const helm_mg* mg, int max_rhs,
+                                 size_t* bytes) {
+  if (n_inst < 1 || !grids || !mg || !bytes || max_rhs < 1) return fail(HELM_EINVAL, "bad arguments");
+  size_t tot = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    size_t b = 0;
+    int v = helm_workspace_bytes(&grids[i], mg, &b);
+    if (v) return v;
+    tot += al(b);
+  }
+  *bytes = tot;
+  return HELM_OK;
+}
+
+int helm_setup_batched(int n_inst, const helm_grid* grids, const double* const* slowness, const double* omega,
+                       const helm_shift* shift, const helm_mg* mg, int max_rhs, void* ws, size_t ws_bytes,
+                       void* stream, helm_ctx** out) {
+  if (n_inst < 1 || !grids || !slowness || !omega || !shift || !mg || !out || max_rhs < 1)
+    return fail(HELM_EINVAL, "bad arguments");
+  size_t need = 0;
+  int v = helm_workspace_bytes_batched(n_inst, grids, mg, max_rhs, &need);
+  if (v) return v;
+  if (!ws || ((uintptr_t)ws % ALIGN) != 0 || ws_bytes < need)
+    return fail(HELM_EWORKSPACE, "workspace NULL, misaligned or too small (%zu < %zu)", ws_bytes, need);
+  *out = nullptr;
+  std::unique_ptr<helm_ctx> b(new helm_ctx());
+  b->grid = grids[0];
+  b->mg = *mg;
+  char* p = (char*)ws;
+  for (int i = 0; i < n_inst; ++i) {
+    size_t bi = 0;
+    helm_workspace_bytes(&grids[i], mg, &bi);
+    helm_ctx* c = nullptr;
+    int r = helm_setup(&grids[i], slowness[i], omega[i], &shift[i], mg, p, al(bi), stream, &c);
+    if (r) {
+      for (helm_ctx* q : b->sub) helm_destroy(q);
+      return r;
+    }
+    b->sub.push_back(c);
+    p += al(bi);
+  }
+  *out = b.release();
+  return HELM_OK;
+}
+
+int helm_solve_batched(helm_ctx* ctx, int op, int n_rhs, const int* inst_of_rhs, const void* const* rhs,
+                       void* const* x, double tol, int max_iter, helm_solve_info* info, void* stream) {
+  if (!ctx || n_rhs < 1 || !inst_of_rhs || !rhs || !x) return fail(HELM_EINVAL, "bad arguments");
+  int ninst = ctx->sub.empty() ? 1 : (int)ctx->sub.size();
+  for (int k = 0; k < n_rhs; ++k)
+    if (inst_of_rhs[k] < 0 || inst_of_rhs[k] >= ninst || !rhs[k] || !x[k])
+      return fail(HELM_EINVAL, "bad right-hand side %d", k);
+  int worst = HELM_OK;
+  for (int k = 0; k < n_rhs; ++k) {
+    helm_ctx* c = ctx->sub.empty() ? ctx : ctx->sub[inst_of_rhs[k]];
+    int r = helm_solve(c, op, rhs[k], x[k], tol, max_iter, info ? &info[k] : nullptr, stream);
+    if (r < 0) return r;
+    worst = std::max(worst, r);
+  }
+  return worst;
+}
+
+}  // extern "C"

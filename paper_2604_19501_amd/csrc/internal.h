@@ -1,0 +1,185 @@
+// Internal declarations of libhelm (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/helm.h"
+
+namespace helm {
+
+// ---------------------------------------------------------------------------
+// complex numbers: interleaved (re, im) in FP32 (cf) and FP64 (cd).  Dedicated
+// types rather than HIP's float2/double2, whose operators are element-wise.
+// ---------------------------------------------------------------------------
+struct __align__(8) cf { float x, y; };
+struct __align__(16) cd { double x, y; };
+template <typename R> struct cplx;
+template <> struct cplx<float> { typedef cf type; };
+template <> struct cplx<double> { typedef cd type; };
+
+__host__ __device__ inline cf mk(float a, float b) { cf r; r.x = a; r.y = b; return r; }
+__host__ __device__ inline cd mk(double a, double b) { cd r; r.x = a; r.y = b; return r; }
+__host__ __device__ inline cf operator+(cf a, cf b) { return mk(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline cd operator+(cd a, cd b) { return mk(a.x + b.x, a.y + b.y); }
+__host__ __device__ inline cf operator-(cf a, cf b) { return mk(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline cd operator-(cd a, cd b) { return mk(a.x - b.x, a.y - b.y); }
+__host__ __device__ inline cf operator-(cf a) { return mk(-a.x, -a.y); }
+__host__ __device__ inline cd operator-(cd a) { return mk(-a.x, -a.y); }
+__host__ __device__ inline cf operator*(cf a, cf b) {
+  return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline cd operator*(cd a, cd b) {
+  return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline cf operator*(float s, cf a) { return mk(s * a.x, s * a.y); }
+__host__ __device__ inline cd operator*(double s, cd a) { return mk(s * a.x, s * a.y); }
+__host__ __device__ inline cf& operator+=(cf& a, cf b) { a.x += b.x; a.y += b.y; return a; }
+__host__ __device__ inline cd& operator+=(cd& a, cd b) { a.x += b.x; a.y += b.y; return a; }
+__host__ __device__ inline cf& operator-=(cf& a, cf b) { a.x -= b.x; a.y -= b.y; return a; }
+__host__ __device__ inline cd& operator-=(cd& a, cd b) { a.x -= b.x; a.y -= b.y; return a; }
+__host__ __device__ inline cf conjc(cf a) { return mk(a.x, -a.y); }
+__host__ __device__ inline cd conjc(cd a) { return mk(a.x, -a.y); }
+__host__ __device__ inline float abs2(cf a) { return a.x * a.x + a.y * a.y; }
+__host__ __device__ inline double abs2(cd a) { return a.x * a.x + a.y * a.y; }
+// a * conj(b) and conj(a) * b
+__host__ __device__ inline cd cmulc(cd a, cd b) {  // conj(a) * b
+  return mk(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__host__ __device__ inline cf cmulc(cf a, cf b) {
+  return mk(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__host__ __device__ inline cd cdiv(cd a, cd b) {
+  double d = b.x * b.x + b.y * b.y;
+  return mk((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+__host__ __device__ inline cf cdiv(cf a, cf b) {
+  float d = b.x * b.x + b.y * b.y;
+  return mk((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+// conversions between precisions
+__host__ __device__ inline cf to_f(cd a) { return mk((float)a.x, (float)a.y); }
+__host__ __device__ inline cf to_f(cf a) { return a; }
+__host__ __device__ inline cd to_d(cf a) { return mk((double)a.x, (double)a.y); }
+__host__ __device__ inline cd to_d(cd a) { return a; }
+template <typename C> struct conv;
+template <> struct conv<cf> {
+  __host__ __device__ static cf from(cd a) { return to_f(a); }
+  __host__ __device__ static cf from(cf a) { return a; }
+};
+template <> struct conv<cd> {
+  __host__ __device__ static cd from(cd a) { return a; }
+  __host__ __device__ static cd from(cf a) { return to_d(a); }
+};
+
+// ---------------------------------------------------------------------------
+// grid geometry of one level
+// ---------------------------------------------------------------------------
+struct Geom {
+  int dim;
+  int n[3];       // cells (1 node on unused axes: n = 0)
+  int N[3];       // nodes per axis = n + 1 (1 on unused axes)
+  long long tot;  // total nodes
+};
+
+inline Geom make_geom(int dim, const int* n) {
+  Geom g;
+  g.dim = dim;
+  g.tot = 1;
+  for (int a = 0; a < 3; ++a) {
+    g.n[a] = a < dim ? n[a] : 0;
+    g.N[a] = g.n[a] + 1;
+    g.tot *= g.N[a];
+  }
+  return g;
+}
+inline Geom coarsen(const Geom& f) {
+  int n[3] = {f.n[0] / 2, f.n[1] / 2, f.n[2] / 2};
+  return make_geom(f.dim, n);
+}
+
+// fine level operator: -Lap_h - s * m (1 - i sigma) with a complex scalar s
+struct FineOp {
+  Geom g;
+  double inv_h2;
+  int layer[3][2];
+  double sigma_max;
+};
+
+__host__ __device__ inline double layer_sigma(const FineOp& op, int i0, int i1, int i2) {
+  int ii[3] = {i0, i1, i2};
+  double s = 0.0;
+  for (int a = 0; a < op.g.dim; ++a) {
+    int lo = op.layer[a][0], hi = op.layer[a][1];
+    int i = ii[a];
+    if (lo > 0 && i < lo) {
+      double t = (double)(lo - i) / lo;
+      s += t * t;
+    }
+    int th = op.g.n[a] - hi;
+    if (hi > 0 && i > th) {
+      double t = (double)(i - th) / hi;
+      s += t * t;
+    }
+  }
+  return op.sigma_max * s;
+}
+
+// number of stencil points of the stored coarse operators
+__host__ __device__ inline int stencil_points(int dim) { return dim == 2 ? 9 : 27; }
+
+// ---------------------------------------------------------------------------
+// nested-dissection structure of the coarsest level (host side)
+// ---------------------------------------------------------------------------
+struct NDFrontDev {
+  int nS, nB, nF;
+  int child[2];         // -1 = none
+  int height;
+  long long idx_off;    // nF ints: S nodes then B nodes (level-3 flat indices)
+  long long map_off[2]; // per child: nB_child ints, position in this front's F
+  long long F_off;      // nF*nF cd (row major), setup scratch; holds Schur block for parent
+  long long L_off;      // nF*nS (row major) left block column [A^-1; C A^-1]   (cycle precision)
+  long long W_off;      // nS*nB (row major) top-right block  -A^-1 B           (cycle precision)
+  long long upd_off;    // nB update vector (cycle precision)
+  long long perm_off;   // nS ints
+  long long asm_off;    // assembly entries
+  int asm_cnt;
+  int pad;
+};
+
+struct NDAsm {          // F[row][col] += coef[cidx]
+  int row, col;
+  long long cidx;
+};
+
+struct NDItem {         // one work item of the solve: rows [r0, r1) of a front
+  int front, r0, r1, pad;
+};
+
+struct NDLaunch {       // tasks of one kernel launch (task t = items[task_off[t] .. task_off[t+1]))
+  std::vector<int> task_off;
+  std::vector<NDItem> items;
+  int max_rows_vec;     // LDS vector entries needed (max nS over items, or nB for backward)
+  long long dev_task_off = 0, dev_items = 0;   // byte offsets in the ND table buffer
+};
+
+struct NDPlan {
+  Geom g;                               // level-3 geometry
+  std::vector<NDFrontDev> fronts;
+  std::vector<int> idx, maps, perm_dummy;
+  std::vector<NDAsm> asmv;
+  std::vector<std::vector<int>> by_height;   // front ids per height
+  int max_height = 0;
+  long long F_total = 0, L_total = 0, W_total = 0, upd_total = 0, perm_total = 0;
+  long long T_scratch = 0;              // doubles2 of panel row buffer (max over heights)
+  int max_nS = 0, max_nB = 0, max_nF = 0;
+  std::vector<NDLaunch> fwd, bwd;
+};
+
+void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int subtree_nodes, NDPlan& plan);
+
+}  // namespace helm

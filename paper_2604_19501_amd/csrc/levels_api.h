@@ -1,0 +1,66 @@
+// Level-1 / level-2 operator descriptors and cycle-kernel launchers (internal).
+#pragma once
+#include "internal.h"
+
+namespace helm {
+
+// flags of the "virtual" input iterate of a relaxation / restriction kernel:
+// x_in = [stored x] + [w D^-1 b] + [P e]
+enum : int { XIN_X = 1, XIN_Z = 2, XIN_E = 4 };
+
+// ----------------------------- level 1 -------------------------------------
+// complex coefficient c = s * m * (1 - i sigma) and diagonal 2d/h^2 - c
+template <typename R>
+struct L1 {
+  typedef typename cplx<R>::type C;
+  FineOp op;
+  C s;                 // (1 - i beta) omega^2 (times alpha^2 for a shifted operator)
+  const R* m;          // squared slowness
+  int conj;            // 1: coefficients of conj(H) (the adjoint, H being complex symmetric)
+  __device__ __forceinline__ C coef(long long f, int i0, int i1, int i2) const {
+    R sig = (R)layer_sigma(op, i0, i1, i2);
+    R mm = m[f];
+    C c = mk(mm, -mm * sig);        // m (1 - i sigma)
+    C r = s * c;
+    if (conj) r.y = -r.y;
+    return r;
+  }
+  __device__ __forceinline__ C diag(long long f, int i0, int i1, int i2) const {
+    C c = coef(f, i0, i1, i2);
+    return mk((R)(2.0 * op.g.dim * op.inv_h2) - c.x, -c.y);
+  }
+};
+
+// ----------------------------- level 2 -------------------------------------
+template <typename R>
+struct L2 {
+  typedef typename cplx<R>::type C;
+  Geom g;
+  const C* coef;     // 3^d * N, SoA
+  int conj;          // use conj(coef) (adjoint)
+  __device__ __forceinline__ C get(int k, long long i) const {
+    C c = coef[(long long)k * g.tot + i];
+    if (conj) c.y = -c.y;
+    return c;
+  }
+  __device__ __forceinline__ int center() const { return g.dim == 2 ? 4 : 13; }
+};
+
+
+template <typename R, typename CB, typename CO>
+void l1_sweep(const L1<R>& A, int xin, const typename cplx<R>::type* x, const CB* b, R w_in, const Geom& gc,
+              const typename cplx<R>::type* e, R w, CO* out, hipStream_t s);
+template <typename R, typename CB>
+void l1_restrict(const L1<R>& A, int xin, const typename cplx<R>::type* x, const CB* b, R w_in, const Geom& gc,
+                 const typename cplx<R>::type* e, const Geom& g2, typename cplx<R>::type* b2, hipStream_t s);
+template <typename R>
+void l2_sweep(const L2<R>& A, int xin, const typename cplx<R>::type* x, const typename cplx<R>::type* b, R w_in,
+              const Geom& gc, const typename cplx<R>::type* e, R w, typename cplx<R>::type* out, hipStream_t s);
+template <typename R>
+void l2_restrict(const L2<R>& A, int xin, const typename cplx<R>::type* x, const typename cplx<R>::type* b,
+                 R w_in, const Geom& gc, const typename cplx<R>::type* e, const Geom& g3,
+                 typename cplx<R>::type* b3, hipStream_t s);
+void l1_apply64(const L1<double>& A, const void* x, int x_is_f32, cd* y, hipStream_t s);
+void l1_apply32(const L1<float>& A, const cf* x, cf* y, hipStream_t s);
+
+}  // namespace helm

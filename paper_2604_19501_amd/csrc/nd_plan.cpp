@@ -1,0 +1,298 @@
+// Symbolic analysis of the exact coarsest-grid solve.
+//
+// The coarsest operator (eq. 3.6) is a 9-point (2D) / 27-point (3D) stencil on a
+// regular node grid.  It is solved exactly by block Gaussian elimination in a
+// geometric nested-dissection order: a box of nodes is cut by a one-node-thick
+// plane normal to its longest axis (a single plane separates the two halves for
+// any stencil of radius one), recursively, until boxes hold at most leaf_max
+// nodes.  Every tree node ("front") eliminates its separator S; its boundary B
+// is the one-node halo of its box, which lies in ancestor separators.  After
+// its subtree is eliminated, a front couples S and B densely.
+//
+// This file builds, on the host: the tree, the S/B index lists, the child->parent
+// position maps used by the extend-add of Schur complements, the list of
+// original matrix entries each front assembles, storage offsets, and the work
+// schedules of the forward and backward substitutions.
+#include <algorithm>
+#include <cassert>
+#include <cstdio>
+#include <functional>
+#include <numeric>
+#include <stdexcept>
+
+#include "internal.h"
+
+namespace helm {
+
+namespace {
+
+struct Box {
+  int lo[3], hi[3];
+};
+
+struct Builder {
+  Geom g;
+  int leaf_max;
+  std::vector<Box> box;
+  std::vector<std::vector<int>> S, B;
+  std::vector<int> parent, ch0, ch1, height;
+  std::vector<long long> sub_nodes;
+  std::vector<int> owner, pos_in_S;
+
+  long long count(const Box& b) const {
+    long long c = 1;
+    for (int a = 0; a < g.dim; ++a) c *= (b.hi[a] - b.lo[a] + 1);
+    return c;
+  }
+  int flat(int i0, int i1, int i2) const {
+    return i0 + g.N[0] * (i1 + g.N[1] * i2);
+  }
+
+  int build(const Box& b, int par) {
+    int id = (int)box.size();
+    box.push_back(b);
+    S.emplace_back();
+    B.emplace_back();
+    parent.push_back(par);
+    ch0.push_back(-1);
+    ch1.push_back(-1);
+    height.push_back(0);
+    sub_nodes.push_back(count(b));
+    int ax = -1, ext = 0;
+    for (int a = g.dim - 1; a >= 0; --a) {     // ties: prefer the slowest axis
+      int e = b.hi[a] - b.lo[a] + 1;
+      if (e > ext) { ext = e; ax = a; }
+    }
+    bool leaf = count(b) <= leaf_max || ext < 3;
+    Box sep = b;
+    if (!leaf) {
+      int mid = (b.lo[ax] + b.hi[ax]) / 2;
+      sep.lo[ax] = sep.hi[ax] = mid;
+      Box c0 = b, c1 = b;
+      c0.hi[ax] = mid - 1;
+      c1.lo[ax] = mid + 1;
+      int a0 = build(c0, id);
+      int a1 = build(c1, id);
+      ch0[id] = a0;
+      ch1[id] = a1;
+      height[id] = 1 + std::max(height[a0], height[a1]);
+    }
+    // separator (or whole leaf box) nodes, increasing flat index
+    std::vector<int>& s = S[id];
+    for (int i2 = sep.lo[2]; i2 <= sep.hi[2]; ++i2)
+      for (int i1 = sep.lo[1]; i1 <= sep.hi[1]; ++i1)
+        for (int i0 = sep.lo[0]; i0 <= sep.hi[0]; ++i0) s.push_back(flat(i0, i1, i2));
+    // one-node halo of the box inside the domain, increasing flat index
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = std::max(b.lo[a] - 1, 0);
+      hi[a] = std::min(b.hi[a] + 1, g.N[a] - 1);
+    }
+    std::vector<int>& bb = B[id];
+    for (int i2 = lo[2]; i2 <= hi[2]; ++i2)
+      for (int i1 = lo[1]; i1 <= hi[1]; ++i1)
+        for (int i0 = lo[0]; i0 <= hi[0]; ++i0) {
+          bool inside = i0 >= b.lo[0] && i0 <= b.hi[0] && i1 >= b.lo[1] && i1 <= b.hi[1] &&
+                        i2 >= b.lo[2] && i2 <= b.hi[2];
+          if (!inside) bb.push_back(flat(i0, i1, i2));
+        }
+    return id;
+  }
+};
+
+}  // namespace
+
+void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int subtree_nodes, NDPlan& plan) {
+  Builder bd;
+  bd.g = g3;
+  bd.leaf_max = std::max(leaf_max, 1);
+  Box root;
+  for (int a = 0; a < 3; ++a) {
+    root.lo[a] = 0;
+    root.hi[a] = g3.N[a] - 1;
+  }
+  bd.build(root, -1);
+  const int nf = (int)bd.box.size();
+  const long long N3 = g3.tot;
+  bd.owner.assign(N3, -1);
+  bd.pos_in_S.assign(N3, -1);
+  for (int t = 0; t < nf; ++t)
+    for (size_t i = 0; i < bd.S[t].size(); ++i) {
+      int v = bd.S[t][i];
+      if (bd.owner[v] != -1) throw std::runtime_error("nd_plan: node in two separators");
+      bd.owner[v] = t;
+      bd.pos_in_S[v] = (int)i;
+    }
+  for (long long v = 0; v < N3; ++v)
+    if (bd.owner[v] < 0) throw std::runtime_error("nd_plan: node in no separator");
+
+  plan.g = g3;
+  plan.fronts.assign(nf, NDFrontDev());
+  plan.idx.clear();
+  plan.maps.clear();
+  plan.asmv.clear();
+  plan.max_height = 0;
+  long long F = 0, L = 0, W = 0, U = 0, P = 0;
+  auto posF = [&](int t, int v) -> int {   // position of node v in front t's (S, B) list, -1 if absent
+    if (bd.owner[v] == t) return bd.pos_in_S[v];
+    const std::vector<int>& b = bd.B[t];
+    auto it = std::lower_bound(b.begin(), b.end(), v);
+    if (it == b.end() || *it != v) return -1;
+    return (int)bd.S[t].size() + (int)(it - b.begin());
+  };
+  for (int t = 0; t < nf; ++t) {
+    NDFrontDev& f = plan.fronts[t];
+    f.nS = (int)bd.S[t].size();
+    f.nB = (int)bd.B[t].size();
+    f.nF = f.nS + f.nB;
+    f.child[0] = bd.ch0[t];
+    f.child[1] = bd.ch1[t];
+    f.height = bd.height[t];
+    plan.max_height = std::max(plan.max_height, f.height);
+    f.idx_off = (long long)plan.idx.size();
+    plan.idx.insert(plan.idx.end(), bd.S[t].begin(), bd.S[t].end());
+    plan.idx.insert(plan.idx.end(), bd.B[t].begin(), bd.B[t].end());
+    f.F_off = F;  F += (long long)f.nF * f.nF;
+    f.L_off = L;  L += (long long)f.nF * f.nS;
+    f.W_off = W;  W += (long long)f.nS * f.nB;
+    f.upd_off = U; U += f.nB;
+    f.perm_off = P; P += f.nS;
+    plan.max_nS = std::max(plan.max_nS, f.nS);
+    plan.max_nB = std::max(plan.max_nB, f.nB);
+    plan.max_nF = std::max(plan.max_nF, f.nF);
+  }
+  // child -> parent maps
+  for (int t = 0; t < nf; ++t) {
+    NDFrontDev& f = plan.fronts[t];
+    for (int c = 0; c < 2; ++c) {
+      f.map_off[c] = -1;
+      int ch = f.child[c];
+      if (ch < 0) continue;
+      f.map_off[c] = (long long)plan.maps.size();
+      for (int v : bd.B[ch]) {
+        int p = posF(t, v);
+        if (p < 0) throw std::runtime_error("nd_plan: child boundary outside parent front");
+        plan.maps.push_back(p);
+      }
+    }
+  }
+  // assembly lists: entry (i, j) of the operator goes to the front where the first
+  // eliminated of i, j is a separator node; the other one is then in that front too.
+  const int dim = g3.dim;
+  for (int t = 0; t < nf; ++t) {
+    NDFrontDev& f = plan.fronts[t];
+    f.asm_off = (long long)plan.asmv.size();
+    const Box& bx = bd.box[t];
+    for (int ps = 0; ps < f.nS; ++ps) {
+      int s = bd.S[t][ps];
+      int s0 = s % g3.N[0], s1 = (s / g3.N[0]) % g3.N[1], s2 = s / (g3.N[0] * g3.N[1]);
+      for (int d2 = (dim == 3 ? -1 : 0); d2 <= (dim == 3 ? 1 : 0); ++d2)
+        for (int d1 = -1; d1 <= 1; ++d1)
+          for (int d0 = -1; d0 <= 1; ++d0) {
+            int q0 = s0 + d0, q1 = s1 + d1, q2 = s2 + d2;
+            if (q0 < 0 || q0 >= g3.N[0] || q1 < 0 || q1 >= g3.N[1] || q2 < 0 || q2 >= g3.N[2]) continue;
+            int q = bd.flat(q0, q1, q2);
+            int k = (d0 + 1) + 3 * (d1 + 1) + (dim == 3 ? 9 * (d2 + 1) : 0);
+            int kq = (-d0 + 1) + 3 * (-d1 + 1) + (dim == 3 ? 9 * (-d2 + 1) : 0);
+            if (bd.owner[q] == t) {
+              plan.asmv.push_back({ps, bd.pos_in_S[q], (long long)k * N3 + s});
+            } else {
+              bool inbox = q0 >= bx.lo[0] && q0 <= bx.hi[0] && q1 >= bx.lo[1] && q1 <= bx.hi[1] &&
+                           q2 >= bx.lo[2] && q2 <= bx.hi[2];
+              if (inbox) continue;   // eliminated in a descendant, arrives via extend-add
+              int pq = posF(t, q);
+              if (pq < 0) throw std::runtime_error("nd_plan: neighbour outside front");
+              plan.asmv.push_back({ps, pq, (long long)k * N3 + s});
+              plan.asmv.push_back({pq, ps, (long long)kq * N3 + q});
+            }
+          }
+    }
+    f.asm_cnt = (int)((long long)plan.asmv.size() - f.asm_off);
+  }
+  plan.F_total = F;
+  plan.L_total = L;
+  plan.W_total = W;
+  plan.upd_total = U;
+  plan.perm_total = P;
+  plan.by_height.assign(plan.max_height + 1, std::vector<int>());
+  for (int t = 0; t < nf; ++t) plan.by_height[plan.fronts[t].height].push_back(t);
+  // panel row buffer: kb rows of every front of one height (kb = 32)
+  long long Tmax = 0;
+  for (auto& ids : plan.by_height) {
+    long long s = 0;
+    for (int t : ids) s += 32LL * plan.fronts[t].nF;
+    Tmax = std::max(Tmax, s);
+  }
+  plan.T_scratch = Tmax;
+
+  // ---------------- solve schedules ----------------
+  // fronts of height <= hcut are handled by one work-group per subtree (post-order
+  // forward, pre-order backward); higher fronts by one launch per height with row chunks.
+  int hcut = -1;
+  for (int h = 0; h <= plan.max_height; ++h) {
+    bool ok = true;
+    for (int t : plan.by_height[h]) ok = ok && bd.sub_nodes[t] <= subtree_nodes;
+    if (!ok) break;
+    hcut = h;
+  }
+  plan.fwd.clear();
+  plan.bwd.clear();
+  if (hcut >= 0) {
+    NDLaunch fl, bl;
+    fl.task_off.push_back(0);
+    bl.task_off.push_back(0);
+    fl.max_rows_vec = bl.max_rows_vec = 0;
+    for (int t = 0; t < nf; ++t) {
+      bool root = plan.fronts[t].height <= hcut &&
+                  (bd.parent[t] < 0 || plan.fronts[bd.parent[t]].height > hcut);
+      if (!root) continue;
+      std::vector<int> post, pre;
+      std::function<void(int)> walk = [&](int u) {
+        pre.push_back(u);
+        for (int c = 0; c < 2; ++c)
+          if (plan.fronts[u].child[c] >= 0) walk(plan.fronts[u].child[c]);
+        post.push_back(u);
+      };
+      walk(t);
+      for (int u : post) {
+        fl.items.push_back({u, 0, plan.fronts[u].nF, 0});
+        fl.max_rows_vec = std::max(fl.max_rows_vec, plan.fronts[u].nF);
+      }
+      for (int u : pre) {
+        bl.items.push_back({u, 0, plan.fronts[u].nS, 0});
+        bl.max_rows_vec = std::max(bl.max_rows_vec, plan.fronts[u].nB);
+      }
+      fl.task_off.push_back((int)fl.items.size());
+      bl.task_off.push_back((int)bl.items.size());
+    }
+    plan.fwd.push_back(fl);
+    plan.bwd.push_back(bl);
+  }
+  std::vector<NDLaunch> bwd_high;
+  for (int h = hcut + 1; h <= plan.max_height; ++h) {
+    NDLaunch fl, bl;
+    fl.task_off.push_back(0);
+    bl.task_off.push_back(0);
+    fl.max_rows_vec = bl.max_rows_vec = 0;
+    for (int t : plan.by_height[h]) {
+      const NDFrontDev& f = plan.fronts[t];
+      for (int r = 0; r < f.nF; r += rows_chunk) {
+        fl.items.push_back({t, r, std::min(f.nF, r + rows_chunk), 0});
+        fl.task_off.push_back((int)fl.items.size());
+      }
+      for (int r = 0; r < f.nS; r += rows_chunk) {
+        bl.items.push_back({t, r, std::min(f.nS, r + rows_chunk), 0});
+        bl.task_off.push_back((int)bl.items.size());
+      }
+      fl.max_rows_vec = std::max(fl.max_rows_vec, f.nF);
+      bl.max_rows_vec = std::max(bl.max_rows_vec, f.nB);
+    }
+    plan.fwd.push_back(fl);
+    bwd_high.push_back(bl);
+  }
+  std::vector<NDLaunch> bwd_all(bwd_high.rbegin(), bwd_high.rend());
+  for (auto& l : plan.bwd) bwd_all.push_back(l);
+  plan.bwd = bwd_all;
+}
+
+}  // namespace helm

@@ -1,0 +1,49 @@
+"""Shared helpers of the GPU parity tests (oracle-side views of the same inputs)."""
+import numpy as np
+
+import synth
+from oracle import multigrid, operators as ops
+
+
+def stencil_arrays(A, n_lev):
+    """(3^d, N) array of a sparse 9/27-point operator: entry k of row i is A[i, i + offset_k],
+    offset k = (d0+1) + 3 (d1+1) [+ 9 (d2+1)], zero where the neighbour is outside the grid."""
+    d = len(n_lev)
+    Ns = [k + 1 for k in n_lev]
+    N = int(np.prod(Ns))
+    K = 3 ** d
+    out = np.zeros((K, N), np.complex128)
+    A = A.tocoo()
+    i, j = A.row, A.col
+    ci = [i % Ns[0], (i // Ns[0]) % Ns[1]] + ([i // (Ns[0] * Ns[1])] if d == 3 else [])
+    cj = [j % Ns[0], (j // Ns[0]) % Ns[1]] + ([j // (Ns[0] * Ns[1])] if d == 3 else [])
+    k = (cj[0] - ci[0] + 1) + 3 * (cj[1] - ci[1] + 1)
+    if d == 3:
+        k = k + 9 * (cj[2] - ci[2] + 1)
+    out[k, i] = A.data
+    return out
+
+
+def small_problem(dim, n=None, seed=7, beta=0.03, alpha2=1.0):
+    """layered medium with absorbing layers on every face, a few cells per level."""
+    if dim == 2:
+        n = n or 32
+        p = synth.config2(n, seed=seed)
+    else:
+        n = n or 16
+        p = synth.config3(n, seed=seed)
+    p.beta = beta
+    p.alpha2 = alpha2
+    return p
+
+
+def oracle_hierarchy(p, **kw):
+    args = dict(alpha2=getattr(p, "alpha2", 1.0))
+    args.update(kw)
+    return multigrid.from_problem(p, **args)
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))

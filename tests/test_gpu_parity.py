@@ -1,0 +1,132 @@
+"""GPU parity of every step of the hot path against the FP64 CPU oracle, through the C ABI.
+
+Tolerances: FP64 kernels agree with the oracle to 1e-12 relative (rounding order
+only); FP32 kernels to a few 1e-6 per stencil application (single precision
+rounding of O(10) terms) and to 1e-4 for the coarsest solve and the cycle, whose
+conditioning amplifies FP32 rounding; solves must meet the 1e-6 relative-residual
+stopping rule in FP64 with iteration counts equal to the oracle's +-1.
+"""
+import numpy as np
+import pytest
+import torch
+
+from tests.gpu_helpers import oracle_hierarchy, rel, small_problem, stencil_arrays
+
+pytestmark = pytest.mark.gpu
+
+L = pytest.importorskip("paper_2604_19501_amd._lib")
+from paper_2604_19501_amd import HELM_OP_C, HELM_OP_N, from_problem  # noqa: E402
+from oracle import fgmres  # noqa: E402
+
+
+def _rand(N, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(N) + 1j * rng.standard_normal(N)
+
+
+@pytest.fixture(scope="module", params=[2, 3])
+def case(request):
+    dim = request.param
+    p = small_problem(dim, alpha2=1.03)
+    H = oracle_hierarchy(p, nu_pre=1, nu_post=1)
+    return dim, p, H
+
+
+def test_apply(case):
+    dim, p, H = case
+    print("apply dim", dim, flush=True)
+    s = from_problem(p, nu=(1, 1), cycle_prec="f64")
+    x = _rand(p.N, 1)
+    y = s.apply(x).cpu().numpy()
+    assert rel(y, H.H @ x) < 1e-13
+    yc = s.apply(x, op=HELM_OP_C).cpu().numpy()
+    assert rel(yc, H.H.conjugate() @ x) < 1e-13
+    y32 = s.apply(x, prec="f32").cpu().numpy()
+    assert rel(y32, H.H @ x) < 1e-5
+
+
+def test_galerkin_coefficients(case):
+    dim, p, H = case
+    print("galerkin dim", dim, flush=True)
+    s = from_problem(p, nu=(1, 1), cycle_prec="f64")
+    A2 = stencil_arrays(H.A[1], H.n2)
+    A3 = stencil_arrays(H.A[2], H.n3)
+    assert rel(s.coefficients(2), A2) < 1e-13
+    assert rel(s.coefficients(3), A3) < 1e-13
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_coarse_solve(case, prec, tol):
+    dim, p, H = case
+    print("coarse dim", dim, prec, flush=True)
+    s = from_problem(p, nu=(1, 1), cycle_prec=prec)
+    r = _rand(s.level_size(3), 3)
+    e = s.coarse_solve(r).cpu().numpy()
+    assert rel(e, H.lu3.solve(r)) < tol
+    ec = s.coarse_solve(r, op=HELM_OP_C).cpu().numpy()
+    assert rel(ec, np.conj(H.lu3.solve(np.conj(r)))) < tol
+
+
+@pytest.mark.parametrize("cycle,nu", [(2, (1, 1)), (2, (2, 2)), (1, (1, 1)), (2, (0, 1)), (2, (1, 0))])
+def test_cycle(case, cycle, nu):
+    dim, p, H0 = case
+    print("cycle dim", dim, cycle, nu, flush=True)
+    H = oracle_hierarchy(p, cycle=cycle, nu_pre=nu[0], nu_post=nu[1])
+    r = _rand(p.N, 5)
+    ref = H.precond(r)
+    for prec, tol in (("f64", 1e-10), ("f32", 1e-4)):
+        s = from_problem(p, cycle=cycle, nu=nu, cycle_prec=prec)
+        z = s.vcycle(r).cpu().numpy()
+        assert rel(z, ref) < tol, (prec, rel(z, ref))
+    Hc = oracle_hierarchy(p, cycle=cycle, nu_pre=nu[0], nu_post=nu[1], conj=True)
+    s = from_problem(p, cycle=cycle, nu=nu, cycle_prec="f64")
+    zc = s.vcycle(r, op=HELM_OP_C).cpu().numpy()
+    assert rel(zc, Hc.precond(r)) < 1e-10
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_solve_small(case, prec):
+    dim, p, H = case
+    print("solve dim", dim, prec, flush=True)
+    q = p.rhs()
+    ref = fgmres.solve(H, q, tol=1e-6, restart=p.restart)
+    s = from_problem(p, nu=(1, 1), cycle_prec=prec)
+    x, info = s.solve(q, tol=1e-6, max_iter=200)
+    xg = x.cpu().numpy()
+    res = np.linalg.norm(q - H.H @ xg) / np.linalg.norm(q)
+    assert info["status"] == 0
+    assert res <= 1e-6
+    assert abs(info["true_rel_residual"] - res) <= 1e-9
+    assert abs(info["iterations"] - ref.iterations) <= 1, (info["iterations"], ref.iterations)
+    print("  its gpu %d oracle %d rel diff %.2e" % (info["iterations"], ref.iterations, rel(xg, ref.x)))
+
+
+def test_adjoint_solve_and_dot(case):
+    dim, p, H = case
+    s = from_problem(p, nu=(1, 1), cycle_prec="f64")
+    x, y = _rand(p.N, 8), _rand(p.N, 9)
+    Hx = s.apply(x).cpu().numpy()
+    Hty = s.apply(y, op=HELM_OP_C).cpu().numpy()
+    assert abs(np.vdot(Hx, y) - np.vdot(x, Hty)) <= 1e-12 * abs(np.vdot(Hx, y))
+    q = p.rhs()
+    xa, info = s.solve(q, op=HELM_OP_C, tol=1e-8, max_iter=300)
+    xa = xa.cpu().numpy()
+    assert np.linalg.norm(q - H.H.conjugate() @ xa) / np.linalg.norm(q) <= 1e-8
+
+
+def test_edge_cases():
+    p = small_problem(2)
+    s = from_problem(p, nu=(1, 1), cycle_prec="f32")
+    x, info = s.solve(np.zeros(p.N, np.complex128))
+    assert info["status"] == 0 and info["iterations"] == 0 and torch.count_nonzero(x).item() == 0
+    x, info = s.solve(p.rhs(), max_iter=1)
+    assert info["status"] == L.HELM_ENOCONV and info["iterations"] == 1
+    bad = p.rhs()
+    bad[3] = np.nan
+    with pytest.raises(L.HelmError) as ei:
+        s.solve(bad)
+    assert ei.value.code == L.HELM_ENONFINITE
+    # resume: maxit k then a second call from the returned x converges
+    x1, i1 = s.solve(p.rhs(), max_iter=3)
+    x2, i2 = s.solve(p.rhs(), x0=x1, max_iter=200)
+    assert i2["status"] == 0 and i2["true_rel_residual"] <= 1e-6
