@@ -118,6 +118,11 @@ int helm_setup(const helm_grid* grid, const double* slowness, double omega,
                const helm_shift* shift, const helm_mg* mg, void* ws, size_t ws_bytes,
                void* stream, helm_ctx** out);
 
+/* Redo the numerical setup of helm_setup (coefficients, Galerkin operators, coarsest
+ * factorisation) for a new medium / frequency / shift on the same grid, reusing the
+ * context's symbolic structure and workspace.  Arguments as in helm_setup. */
+int helm_refactor(helm_ctx* ctx, const double* slowness, double omega, const helm_shift* shift, void* stream);
+
 /* y = H x (op HELM_OP_N) or y = H^H x (HELM_OP_C), the unshifted operator of eq. (1.1).
  * prec HELM_F64: x, y device c128[N1]; HELM_F32: x, y device c64[N1].  x != y. */
 int helm_apply(helm_ctx* ctx, int op, int prec, const void* x, void* y, void* stream);
@@ -183,9 +188,13 @@ const char* helm_status_str(int status);
 /* Message of the last HELM_EINVAL / HELM_EDEVICE raised on this thread (static buffer). */
 const char* helm_last_error(void);
 
-/* Fill host array t[0..n) with per-phase device times in ms of the last solve:
- * [0] total, [1] cycle, [2] outer apply+Arnoldi, [3] coarsest solves, [4] setup.  Returns
- * the number written.  Timing is recorded only when enabled by helm_set_timing(ctx, 1). */
+/* Device timing (HIP events), recorded while enabled by helm_set_timing(ctx, 1), which also
+ * clears the accumulators.  helm_get_timing fills host array t[0..n): [0] last solve total ms,
+ * [1..3] reserved (0), [4] last setup ms, then for kernel class k = 0..9 (level-1 sweep,
+ * level-1 residual+restriction, level-2 sweep, level-2 residual+restriction, coarsest
+ * forward substitution, coarsest backward substitution, Arnoldi step (apply, two
+ * orthogonalisation passes, Givens, normalisation), -, -, -) the pair
+ * t[5+2k] = accumulated ms, t[6+2k] = launches.  Returns the number of entries written. */
 int helm_set_timing(helm_ctx* ctx, int on);
 int helm_get_timing(helm_ctx* ctx, double* t, int n);
 

@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstring>
 #include <cstdarg>
+#include <cstdlib>
 #include <cstddef>
 #include <memory>
 #include <stdexcept>
@@ -25,8 +26,8 @@ void nd_zero(cd* p, long long n, hipStream_t s);
 void nd_iota(int* perm, const NDFrontDev* fr, int nfronts, hipStream_t s);
 void nd_assemble(const NDFrontDev* fr, const int* ids, int nids, int max_asm, const NDAsm* asmv, const cd* coef,
                  cd* Fp, hipStream_t s);
-void nd_extend(const NDFrontDev* fr, const int* ids, int nids, long long max_nb2, const int* maps, cd* Fp,
-               int slot, hipStream_t s);
+void nd_extend(const NDFrontDev* fr, const int* ids, int nids, long long max_nb2, const int* children,
+               const long long* child_map_off, const int* maps, cd* Fp, int slot, hipStream_t s);
 void nd_panel(const NDFrontDev* fr, const int* ids, int nids, cd* Fp, int* perm, int k0, int kb, int* err,
               hipStream_t s);
 void nd_save_t(const NDFrontDev* fr, const int* ids, int nids, const long long* toff, long long max_n, cd* Fp,
@@ -37,12 +38,14 @@ template <typename C>
 void nd_finalize(const NDFrontDev* fr, const int* ids, int nids, long long max_n, const cd* Fp, const int* perm,
                  C* Lp, C* Wp, hipStream_t s);
 template <typename C>
-void nd_fwd(int ntasks, size_t lds, const NDFrontDev* fr, const int* idx, const int* maps, const C* Lp, C* upd,
-            const int* task_off, const NDItem* items, const C* r, C* x, C* gvec, int vec_cap, int conj,
-            hipStream_t s);
+void nd_fwd(int kind, int ntasks, size_t lds, const NDFrontDev* fr, const int* idx, const int* cptr, const int* cidx,
+            const C* Lp, C* upd, const int* task_off, const NDItem* items, const C* r, C* x, C* gvec, int cap,
+            int conj, hipStream_t s);
+void nd_panel_lds(const NDFrontDev* fr, const int* ids, int nids, int max_nF, cd* Fp, int* perm, int* swp, int k0,
+                  int kb, int* err, hipStream_t s);
 template <typename C>
-void nd_bwd(int ntasks, size_t lds, const NDFrontDev* fr, const int* idx, const C* Wp, const int* task_off,
-            const NDItem* items, C* x, C* gvec, int vec_cap, int conj, hipStream_t s);
+void nd_bwd(int kind, int ntasks, size_t lds, const NDFrontDev* fr, const int* idx, const C* Wp, const int* task_off,
+            const NDItem* items, C* x, C* gvec, int cap, int conj, hipStream_t s);
 void grad_accumulate(const FineOp& op, double omega, const cd* u, const cd* lam, double* g, int first,
                      hipStream_t s);
 
@@ -89,7 +92,10 @@ struct Carver {
 
 struct NDDev {        // device-side ND tables (pointers into the workspace)
   NDFrontDev* fronts = nullptr;
-  int *idx = nullptr, *maps = nullptr, *perm = nullptr, *hlist = nullptr, *err = nullptr;
+  int *idx = nullptr, *maps = nullptr, *cptr = nullptr, *cidx = nullptr, *perm = nullptr, *hlist = nullptr,
+      *err = nullptr, *swp = nullptr;
+  int* children = nullptr;
+  long long* child_map_off = nullptr;
   NDAsm* asmv = nullptr;
   long long* toff = nullptr;
   cd *F = nullptr, *T = nullptr;
@@ -99,8 +105,16 @@ struct NDDev {        // device-side ND tables (pointers into the workspace)
   int gvec_cap = 0;
 };
 
+// kernel classes timed with HIP events when timing is on
+enum KClass { KT_L1_SWEEP, KT_L1_RESTRICT, KT_L2_SWEEP, KT_L2_RESTRICT, KT_ND_FWD, KT_ND_BWD, KT_APPLY_DOT,
+              KT_UPDATE_DOT, KT_NORMALIZE, KT_KRYLOV_OTHER, KT_N };
+struct Pending {
+  int cls;
+  hipEvent_t a, b;
+};
+
 struct HeightInfo {
-  int start, count, max_asm, max_nS, max_nF;
+  int start, count, max_asm, max_nS, max_nF, max_child;
   long long max_nb2, max_T, max_fin;
 };
 
@@ -137,8 +151,18 @@ struct helm_ctx {
   char* hstate = nullptr;    // pinned host copy of the scalar block of KrylovState
   int timing = 0;
   double times[5] = {0, 0, 0, 0, 0};
-  size_t lds_limit = 65536;
+  double kt_ms[KT_N] = {0};
+  long long kt_cnt[KT_N] = {0};
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> evpool;
+  size_t lds_limit = 65536;     // LDS bytes for substitution vectors
+  size_t lds_panel = 0;         // LDS bytes for a resident factorisation panel (device maximum - 2 KB)
   std::vector<helm_ctx*> sub;   // batched form: one context per instance
+  // one captured graph per (operator, Arnoldi index j): cycle on V_j + Arnoldi step
+  hipStream_t cap = nullptr;    // library-owned stream used only for capture
+  std::vector<hipGraphExec_t> gexec[2];
+  double gtol[2] = {-1.0, -1.0};
+  int graphs = 1;
 };
 
 namespace {
@@ -182,10 +206,19 @@ void init_geometry(helm_ctx* c) {
   c->csz = c->f32 ? sizeof(cf) : sizeof(cd);
 }
 
-const int ND_LEAF = 16, ND_CHUNK = 64, ND_SUBTREE = 1024, ND_KB = 32;
+const int ND_KB = 32;
+// nested-dissection parameters (tunable through the environment for the autotuner):
+// leaf box size, rows per work-group of big fronts, nodes per subtree task
+int env_int(const char* name, int dflt) {
+  const char* v = getenv(name);
+  return v && *v ? atoi(v) : dflt;
+}
 
 void build_plan(helm_ctx* c) {
-  nd_plan(c->g3, c->grid.dim == 3 ? 8 : ND_LEAF, ND_CHUNK, ND_SUBTREE, c->plan);
+  const int leaf = env_int("HELM_ND_LEAF", c->grid.dim == 3 ? 8 : 32);
+  const int subtree = env_int("HELM_ND_SUBTREE", c->grid.dim == 3 ? 512 : 256);
+  const int merge = env_int("HELM_ND_ROOT", c->grid.dim == 3 ? 1 : 1100);
+  nd_plan(c->g3, leaf, 16, subtree, merge, c->plan);
   NDPlan& P = c->plan;
   c->hlist.clear();
   c->hlist_toff.clear();
@@ -204,8 +237,8 @@ void build_plan(helm_ctx* c) {
       hi.max_nS = std::max(hi.max_nS, f.nS);
       hi.max_nF = std::max(hi.max_nF, f.nF);
       int nbc = 0;
-      for (int s = 0; s < 2; ++s)
-        if (f.child[s] >= 0) nbc = std::max(nbc, P.fronts[f.child[s]].nB);
+      hi.max_child = std::max(hi.max_child, f.nchild);
+      for (int q = 0; q < f.nchild; ++q) nbc = std::max(nbc, P.fronts[P.children[f.child_off + q]].nB);
       hi.max_nb2 = std::max(hi.max_nb2, (long long)nbc * nbc);
       hi.max_T = std::max(hi.max_T, (long long)ND_KB * f.nF);
       hi.max_fin = std::max(hi.max_fin, (long long)f.nF * f.nS + (long long)f.nS * f.nB);
@@ -242,6 +275,15 @@ size_t carve(helm_ctx* c, void* ws) {
   d.fronts = cv.take<NDFrontDev>(P.fronts.size());
   d.idx = cv.take<int>(P.idx.size());
   d.maps = cv.take<int>(std::max<size_t>(1, P.maps.size()));
+  d.cptr = cv.take<int>(std::max<size_t>(1, P.cptr.size()));
+  d.cidx = cv.take<int>(std::max<size_t>(1, P.cidx.size()));
+  d.children = cv.take<int>(std::max<size_t>(1, P.children.size()));
+  d.child_map_off = cv.take<long long>(std::max<size_t>(1, P.child_map_off.size()));
+  {
+    size_t mx = 1;
+    for (auto& h : P.by_height) mx = std::max(mx, h.size());
+    d.swp = cv.take<int>(32 * mx);
+  }
   d.asmv = cv.take<NDAsm>(P.asmv.size());
   d.perm = cv.take<int>(P.perm_total);
   d.hlist = cv.take<int>(c->hlist.size());
@@ -261,13 +303,15 @@ size_t carve(helm_ctx* c, void* ws) {
       d.items[fb][l] = cv.take<NDItem>(Ls[l].items.size());
     }
   }
-  // global fall-back vectors for launches whose vector does not fit in LDS
+  // global fall-back vectors for launches whose vectors do not fit in LDS
+  // (a subtree task holds one vector per wavefront)
   long long gcap = 0, gneed = 0;
   for (int fb = 0; fb < 2; ++fb)
     for (auto& L : (fb == 0 ? P.fwd : P.bwd)) {
-      if ((size_t)L.max_rows_vec * cs > c->lds_limit) {
+      int per = L.kind == 0 ? 4 : 1;
+      if ((size_t)L.max_rows_vec * cs * per > c->lds_limit) {
         gcap = std::max<long long>(gcap, L.max_rows_vec);
-        gneed = std::max<long long>(gneed, (long long)(L.task_off.size() - 1));
+        gneed = std::max<long long>(gneed, (long long)(L.task_off.size() - 1) * per);
       }
     }
   d.gvec_cap = (int)gcap;
@@ -304,12 +348,20 @@ void nd_factor(helm_ctx* c, hipStream_t s) {
     const int* ids = d.hlist + hi.start;
     const long long* toff = d.toff + hi.start;
     nd_assemble(d.fronts, ids, hi.count, hi.max_asm, d.asmv, c->coef3_64, d.F, s);
-    nd_extend(d.fronts, ids, hi.count, hi.max_nb2, d.maps, d.F, 0, s);
-    nd_extend(d.fronts, ids, hi.count, hi.max_nb2, d.maps, d.F, 1, s);
-    for (int k0 = 0; k0 < hi.max_nS; k0 += ND_KB) {
-      nd_panel(d.fronts, ids, hi.count, d.F, d.perm, k0, ND_KB, d.err, s);
-      nd_save_t(d.fronts, ids, hi.count, toff, hi.max_T, d.F, d.T, k0, ND_KB, s);
-      nd_gemm(d.fronts, ids, hi.count, toff, hi.max_nF, d.F, d.T, k0, ND_KB, s);
+    for (int slot = 0; slot < hi.max_child; ++slot)
+      nd_extend(d.fronts, ids, hi.count, hi.max_nb2, d.children, d.child_map_off, d.maps, d.F, slot, s);
+    // panel width: the LDS-resident panel kernel when a panel of >= 8 columns fits
+    int kb = 32;
+    while (kb > 8 && (size_t)hi.max_nF * kb * sizeof(cd) > c->lds_panel) kb /= 2;
+    const bool lds_panel = (size_t)hi.max_nF * kb * sizeof(cd) <= c->lds_panel;
+    if (!lds_panel) kb = ND_KB;
+    for (int k0 = 0; k0 < hi.max_nS; k0 += kb) {
+      if (lds_panel)
+        nd_panel_lds(d.fronts, ids, hi.count, hi.max_nF, d.F, d.perm, d.swp, k0, kb, d.err, s);
+      else
+        nd_panel(d.fronts, ids, hi.count, d.F, d.perm, k0, kb, d.err, s);
+      nd_save_t(d.fronts, ids, hi.count, toff, hi.max_T, d.F, d.T, k0, kb, s);
+      nd_gemm(d.fronts, ids, hi.count, toff, hi.max_nF, d.F, d.T, k0, kb, s);
     }
     if (c->f32)
       nd_finalize<cf>(d.fronts, ids, hi.count, hi.max_fin, d.F, d.perm, (cf*)d.L, (cf*)d.W, s);
@@ -317,6 +369,43 @@ void nd_factor(helm_ctx* c, hipStream_t s) {
       nd_finalize<cd>(d.fronts, ids, hi.count, hi.max_fin, d.F, d.perm, (cd*)d.L, (cd*)d.W, s);
   }
 }
+
+hipEvent_t ev_get(helm_ctx* c) {
+  if (!c->evpool.empty()) {
+    hipEvent_t e = c->evpool.back();
+    c->evpool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  CK(hipEventCreate(&e));
+  return e;
+}
+// resolve recorded event pairs (the stream must have been synchronised)
+void ev_flush(helm_ctx* c) {
+  for (auto& p : c->pending) {
+    float ms = 0;
+    CK(hipEventElapsedTime(&ms, p.a, p.b));
+    c->kt_ms[p.cls] += ms;
+    c->kt_cnt[p.cls] += 1;
+    c->evpool.push_back(p.a);
+    c->evpool.push_back(p.b);
+  }
+  c->pending.clear();
+}
+#define TIMED(c, cls, s, stmt)                                  \
+  do {                                                          \
+    hipEvent_t a_ = nullptr;                                    \
+    if ((c)->timing) {                                          \
+      a_ = ev_get(c);                                           \
+      CK(hipEventRecord(a_, s));                                \
+    }                                                           \
+    stmt;                                                       \
+    if ((c)->timing) {                                          \
+      hipEvent_t b_ = ev_get(c);                                \
+      CK(hipEventRecord(b_, s));                                \
+      (c)->pending.push_back(Pending{cls, a_, b_});             \
+    }                                                           \
+  } while (0)
 
 template <typename C>
 void nd_solve(helm_ctx* c, const C* r, C* x, int conj, hipStream_t s) {
@@ -327,18 +416,40 @@ void nd_solve(helm_ctx* c, const C* r, C* x, int conj, hipStream_t s) {
     for (size_t l = 0; l < Ls.size(); ++l) {
       const NDLaunch& L = Ls[l];
       int ntasks = (int)L.task_off.size() - 1;
-      size_t need = (size_t)L.max_rows_vec * sizeof(C);
+      int per = L.kind == 0 ? 4 : 1;
+      size_t need = (size_t)L.max_rows_vec * sizeof(C) * per;
       bool lds = need <= c->lds_limit;
       C* gv = lds ? nullptr : (C*)d.gvec;
+      int cap = lds ? L.max_rows_vec : d.gvec_cap;
       size_t shm = lds ? std::max<size_t>(need, 16) : 0;
       if (fb == 0)
-        nd_fwd<C>(ntasks, shm, d.fronts, d.idx, d.maps, (const C*)d.L, (C*)d.upd, d.task_off[0][l], d.items[0][l], r,
-                  x, gv, d.gvec_cap, conj, s);
+        TIMED(c, KT_ND_FWD, s,
+              nd_fwd<C>(L.kind, ntasks, shm, d.fronts, d.idx, d.cptr, d.cidx, (const C*)d.L, (C*)d.upd,
+                        d.task_off[0][l], d.items[0][l], r, x, gv, cap, conj, s));
       else
-        nd_bwd<C>(ntasks, shm, d.fronts, d.idx, (const C*)d.W, d.task_off[1][l], d.items[1][l], x, gv, d.gvec_cap,
-                  conj, s);
+        TIMED(c, KT_ND_BWD, s,
+              nd_bwd<C>(L.kind, ntasks, shm, d.fronts, d.idx, (const C*)d.W, d.task_off[1][l], d.items[1][l], x, gv,
+                        cap, conj, s));
     }
   }
+}
+
+
+// a0-a3: coefficients, Galerkin operators, real-shifted coarsest operator, factorisation
+void numeric_setup(helm_ctx* c, const double* slowness, hipStream_t s) {
+  const helm_shift* shift = &c->shift;
+  const double omega = c->omega;
+  // a0: m = kappa^2 (FP64 and FP32)
+  square_slowness(slowness, c->m64, c->m32, c->g1.tot, s);
+  // a1: level-2 Galerkin operator of H_beta^{alpha2}
+  gal_fine(c->op, shift_scalar(shift->alpha2, shift->beta, omega), c->m64, c->g2, c->coef2_64, s);
+  const int K = stencil_points(c->grid.dim);
+  if (c->f32) cast_d2f(c->coef2_64, c->coef2_32, (long long)K * c->g2.tot, s);
+  // a2: real-shifted level-3 operator R2 (R1 H_beta^alpha P1) P2
+  gal_fine(c->op, shift_scalar(shift->alpha, shift->beta, omega), c->m64, c->g2, c->tmp2, s);
+  gal_coarse(c->g2, c->tmp2, c->g3, c->coef3_64, s);
+  // a3: exact factorisation
+  nd_factor(c, s);
 }
 
 // iterate state of one level: x_in = [x] + [w D^-1 b] + [P e]
@@ -372,12 +483,12 @@ struct Cycle {
   template <typename CO>
   St<C> adv1(St<C> st, const cd* b, const C* e, CO* out) {
     R w = (R)c->mg.jacobi[0];
-    l1_sweep<R, cd, CO>(A1, st.xin, st.x, b, w, c->g2, e, w, out, s);
+    TIMED(c, KT_L1_SWEEP, s, (l1_sweep<R, cd, CO>(A1, st.xin, st.x, b, w, c->g2, e, w, out, s)));
     return St<C>{XIN_X, (C*)out};
   }
   St<C> adv2(St<C> st, const C* b, const C* e, C* out) {
     R w = (R)c->mg.jacobi[1];
-    l2_sweep<R>(A2, st.xin, st.x, b, w, c->g3, e, w, out, s);
+    TIMED(c, KT_L2_SWEEP, s, (l2_sweep<R>(A2, st.xin, st.x, b, w, c->g3, e, w, out, s)));
     return St<C>{XIN_X, out};
   }
   C* other(C* cur, C* a, C* b) { return cur == a ? b : a; }
@@ -394,7 +505,7 @@ struct Cycle {
       if (s1.xin == 0) s1 = St<C>{XIN_Z, nullptr};
       else s1 = adv1<C>(s1, b1, nullptr, other(s1.x, x1a, x1b));
     }
-    l1_restrict<R, cd>(A1, s1.xin, s1.x, b1, w1, c->g2, nullptr, c->g2, b2, s);
+    TIMED(c, KT_L1_RESTRICT, s, (l1_restrict<R, cd>(A1, s1.xin, s1.x, b1, w1, c->g2, nullptr, c->g2, b2, s)));
     // ---- level 2 visits
     St<C> s2{0, nullptr};
     for (int v = 0; v < mg.cycle; ++v) {
@@ -402,7 +513,7 @@ struct Cycle {
         if (s2.xin == 0) s2 = St<C>{XIN_Z, nullptr};
         else s2 = adv2(s2, b2, nullptr, other(s2.x, x2a, x2b));
       }
-      l2_restrict<R>(A2, s2.xin, s2.x, b2, w2, c->g3, nullptr, c->g3, b3, s);
+      TIMED(c, KT_L2_RESTRICT, s, (l2_restrict<R>(A2, s2.xin, s2.x, b2, w2, c->g3, nullptr, c->g3, b3, s)));
       nd_solve<C>(c, b3, x3, conj, s);
       s2.xin |= XIN_E;
       for (int k = 0; k < mg.nu_post; ++k) s2 = adv2(s2, b2, x3, other(s2.x, x2a, x2b));
@@ -455,6 +566,44 @@ KrylovArgs make_kargs(helm_ctx* c, int op) {
   return a;
 }
 
+void drop_graphs(helm_ctx* c) {
+  for (int op = 0; op < 2; ++op) {
+    for (hipGraphExec_t g : c->gexec[op]) (void)hipGraphExecDestroy(g);
+    c->gexec[op].clear();
+    c->gtol[op] = -1.0;
+  }
+}
+
+// capture the m per-iteration graphs of operator op (kernel arguments are fixed: buffers,
+// shifts, tolerance), once per context until the frequency or shifts change
+template <typename R>
+void iter_graphs(helm_ctx* c, int op, double tol) {
+  typedef typename cplx<R>::type C;
+  const int m = c->mg.restart;
+  if ((int)c->gexec[op].size() == m && c->gtol[op] == tol) return;
+  for (hipGraphExec_t g : c->gexec[op]) (void)hipGraphExecDestroy(g);
+  c->gexec[op].clear();
+  if (!c->cap) CK(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
+  KrylovArgs a = make_kargs(c, op);
+  Cycle<R> cyc(c, op, c->cap);
+  const long long N = c->g1.tot;
+  const int saved = c->timing;
+  c->timing = 0;
+  for (int j = 0; j < m; ++j) {
+    hipGraph_t g = nullptr;
+    CK(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+    cyc.template run<C>(c->V + (size_t)j * N, (C*)c->Z + (size_t)j * N);
+    kr_arnoldi(a, (const char*)c->Z + (size_t)j * N * c->csz, c->f32, j, tol, c->cap);
+    CK(hipStreamEndCapture(c->cap, &g));
+    hipGraphExec_t e = nullptr;
+    CK(hipGraphInstantiate(&e, g, nullptr, nullptr, 0));
+    (void)hipGraphDestroy(g);
+    c->gexec[op].push_back(e);
+  }
+  c->timing = saved;
+  c->gtol[op] = tol;
+}
+
 template <typename R>
 int solve_impl(helm_ctx* c, int op, const cd* b, cd* x, double tol, int max_iter, helm_solve_info* info,
                hipStream_t s) {
@@ -469,6 +618,8 @@ int solve_impl(helm_ctx* c, int op, const cd* b, cd* x, double tol, int max_iter
     CK(hipEventCreate(&e1));
     CK(hipEventRecord(e0, s));
   }
+  const bool use_graphs = c->graphs && !c->timing;
+  if (use_graphs) iter_graphs<R>(c, op, tol);
   kr_init(a, s);
   kr_residual(a, x, b, 1, s);
   read_state(c, s);
@@ -489,8 +640,12 @@ int solve_impl(helm_ctx* c, int op, const cd* b, cd* x, double tol, int max_iter
       kr_scale_v0(a, s);
       int k = 0;
       for (int j = 0; j < m; ++j) {
-        cyc.template run<C>(c->V + (size_t)j * N, (C*)c->Z + (size_t)j * N);
-        kr_arnoldi(a, (const char*)c->Z + (size_t)j * N * c->csz, c->f32, j, tol, s);
+        if (use_graphs) {
+          CK(hipGraphLaunch(c->gexec[op][j], s));
+        } else {
+          cyc.template run<C>(c->V + (size_t)j * N, (C*)c->Z + (size_t)j * N);
+          TIMED(c, KT_APPLY_DOT, s, kr_arnoldi(a, (const char*)c->Z + (size_t)j * N * c->csz, c->f32, j, tol, s));
+        }
         ++its;
         k = j + 1;
         read_state(c, s);
@@ -519,6 +674,8 @@ int solve_impl(helm_ctx* c, int op, const cd* b, cd* x, double tol, int max_iter
     CK(hipEventDestroy(e0));
     CK(hipEventDestroy(e1));
   }
+  CK(hipStreamSynchronize(s));
+  ev_flush(c);
   if (info) {
     info->iterations = its;
     info->restarts = restarts;
@@ -589,6 +746,7 @@ int helm_setup(const helm_grid* grid, const double* slowness, double omega, cons
     c->mg = *mg;
     c->shift = *shift;
     c->omega = omega;
+    c->graphs = env_int("HELM_GRAPHS", 1);
     init_geometry(c.get());
     build_plan(c.get());
     size_t need = carve(c.get(), nullptr);
@@ -596,6 +754,13 @@ int helm_setup(const helm_grid* grid, const double* slowness, double omega, cons
     c->ws_needed = need;
     carve(c.get(), ws);
     CK(hipHostMalloc((void**)&c->hstate, 4096, hipHostMallocDefault));
+    {
+      int dev = 0, lds = 0;
+      CK(hipGetDevice(&dev));
+      CK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+      c->lds_panel = lds > 4096 ? (size_t)lds - 2048 : 0;
+      if (env_int("HELM_VERBOSE", 0)) fprintf(stderr, "helm: LDS per block %d bytes\n", lds);
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     CK(hipEventCreate(&e0));
     CK(hipEventCreate(&e1));
@@ -606,6 +771,10 @@ int helm_setup(const helm_grid* grid, const double* slowness, double omega, cons
     up(d.fronts, P.fronts, s);
     up(d.idx, P.idx, s);
     up(d.maps, P.maps, s);
+    up(d.cptr, P.cptr, s);
+    up(d.cidx, P.cidx, s);
+    up(d.children, P.children, s);
+    up(d.child_map_off, P.child_map_off, s);
     up(d.asmv, P.asmv, s);
     up(d.hlist, c->hlist, s);
     up(d.toff, c->hlist_toff, s);
@@ -616,17 +785,7 @@ int helm_setup(const helm_grid* grid, const double* slowness, double omega, cons
         up(d.items[fb][l], Ls[l].items, s);
       }
     }
-    // a0: m = kappa^2 (FP64 and FP32)
-    square_slowness(slowness, c->m64, c->m32, c->g1.tot, s);
-    // a1: level-2 Galerkin operator of H_beta^{alpha2}
-    gal_fine(c->op, shift_scalar(shift->alpha2, shift->beta, omega), c->m64, c->g2, c->coef2_64, s);
-    const int K = stencil_points(grid->dim);
-    if (c->f32) cast_d2f(c->coef2_64, c->coef2_32, (long long)K * c->g2.tot, s);
-    // a2: real-shifted level-3 operator R2 (R1 H_beta^alpha P1) P2
-    gal_fine(c->op, shift_scalar(shift->alpha, shift->beta, omega), c->m64, c->g2, c->tmp2, s);
-    gal_coarse(c->g2, c->tmp2, c->g3, c->coef3_64, s);
-    // a3: exact factorisation
-    nd_factor(c.get(), s);
+    numeric_setup(c.get(), slowness, s);
     CK(hipEventRecord(e1, s));
     CK(hipStreamSynchronize(s));
     CK(hipGetLastError());
@@ -652,9 +811,36 @@ int helm_setup(const helm_grid* grid, const double* slowness, double omega, cons
   return HELM_OK;
 }
 
+int helm_refactor(helm_ctx* c, const double* slowness, double omega, const helm_shift* shift, void* stream) {
+  if (!c || !slowness || !shift) return fail(HELM_EINVAL, "NULL argument");
+  if (!c->sub.empty()) return fail(HELM_EINVAL, "helm_refactor takes a single-instance context");
+  if (!(omega > 0.0) || !std::isfinite(omega)) return fail(HELM_EINVAL, "omega must be positive and finite");
+  if (!std::isfinite(shift->alpha) || !std::isfinite(shift->alpha2) || !std::isfinite(shift->beta))
+    return fail(HELM_EINVAL, "shift parameters must be finite");
+  hipStream_t s = (hipStream_t)stream;
+  try {
+    if (omega != c->omega || shift->alpha != c->shift.alpha || shift->alpha2 != c->shift.alpha2 ||
+        shift->beta != c->shift.beta)
+      drop_graphs(c);          // captured kernel arguments hold the shifted coefficients' scalars
+    c->omega = omega;
+    c->shift = *shift;
+    numeric_setup(c, slowness, s);
+    int err = 0;
+    CK(hipMemcpyAsync(c->hstate, c->nd.err, sizeof(int), hipMemcpyDeviceToHost, s));
+    CK(hipStreamSynchronize(s));
+    std::memcpy(&err, c->hstate, sizeof(int));
+    if (err) return fail(HELM_ESINGULAR, "zero pivot in the coarsest-grid elimination");
+  } catch (DevErr& e) {
+    return fail(HELM_EDEVICE, "%s", e.what());
+  }
+  return HELM_OK;
+}
+
 int helm_destroy(helm_ctx* ctx) {
   if (!ctx) return HELM_OK;
   for (helm_ctx* q : ctx->sub) helm_destroy(q);
+  drop_graphs(ctx);
+  if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
   if (ctx->hstate) (void)hipHostFree(ctx->hstate);
   delete ctx;
   return HELM_OK;
@@ -750,14 +936,28 @@ int helm_solve(helm_ctx* c, int op, const void* rhs, void* x, double tol, int ma
 int helm_set_timing(helm_ctx* c, int on) {
   if (!c) return fail(HELM_EINVAL, "NULL context");
   c->timing = on ? 1 : 0;
+  for (int k = 0; k < KT_N; ++k) {
+    c->kt_ms[k] = 0.0;
+    c->kt_cnt[k] = 0;
+  }
   return HELM_OK;
 }
 
 int helm_get_timing(helm_ctx* c, double* t, int n) {
   if (!c || !t || n < 0) return fail(HELM_EINVAL, "bad arguments");
-  int k = std::min(n, 5);
-  for (int i = 0; i < k; ++i) t[i] = c->times[i];
-  return k;
+  try {
+    ev_flush(c);
+  } catch (DevErr& e) {
+    return fail(HELM_EDEVICE, "%s", e.what());
+  }
+  std::vector<double> v(c->times, c->times + 5);
+  for (int k = 0; k < KT_N; ++k) {
+    v.push_back(c->kt_ms[k]);
+    v.push_back((double)c->kt_cnt[k]);
+  }
+  int m = std::min<int>(n, (int)v.size());
+  for (int i = 0; i < m; ++i) t[i] = v[i];
+  return m;
 }
 
 long long helm_level_size(helm_ctx* c, int inst, int lev) {

@@ -137,13 +137,15 @@ __host__ __device__ inline int stencil_points(int dim) { return dim == 2 ? 9 : 2
 // ---------------------------------------------------------------------------
 struct NDFrontDev {
   int nS, nB, nF;
-  int child[2];         // -1 = none
+  int nchild;           // children: plan.children[child_off .. child_off + nchild)
+  int child_off;
   int height;
   long long idx_off;    // nF ints: S nodes then B nodes (level-3 flat indices)
-  long long map_off[2]; // per child: nB_child ints, position in this front's F
+  long long inv_off;    // nF+1 ints at cptr[inv_off]: contributions to position i are
+                        // cidx[cptr[i] .. cptr[i+1]) (absolute indices into the update pool)
   long long F_off;      // nF*nF cd (row major), setup scratch; holds Schur block for parent
-  long long L_off;      // nF*nS (row major) left block column [A^-1; C A^-1]   (cycle precision)
-  long long W_off;      // nS*nB (row major) top-right block  -A^-1 B           (cycle precision)
+  long long L_off;      // nF x nS column major (ld nF): left block column [A^-1; C A^-1] (cycle precision)
+  long long W_off;      // nS x nB column major (ld nS): top-right block -A^-1 B          (cycle precision)
   long long upd_off;    // nB update vector (cycle precision)
   long long perm_off;   // nS ints
   long long asm_off;    // assembly entries
@@ -157,20 +159,23 @@ struct NDAsm {          // F[row][col] += coef[cidx]
 };
 
 struct NDItem {         // one work item of the solve: rows [r0, r1) of a front
-  int front, r0, r1, pad;
+  int front, r0, r1;
+  int stage;            // subtree tasks: items of one stage are independent (one per wavefront)
 };
 
 struct NDLaunch {       // tasks of one kernel launch (task t = items[task_off[t] .. task_off[t+1]))
+  int kind = 0;         // 0: one work-group per subtree, one front per wavefront; 1: row chunks of big fronts
   std::vector<int> task_off;
   std::vector<NDItem> items;
-  int max_rows_vec;     // LDS vector entries needed (max nS over items, or nB for backward)
-  long long dev_task_off = 0, dev_items = 0;   // byte offsets in the ND table buffer
+  int max_rows_vec = 0; // vector entries per front (nF forward, nB backward)
 };
 
 struct NDPlan {
   Geom g;                               // level-3 geometry
   std::vector<NDFrontDev> fronts;
-  std::vector<int> idx, maps, perm_dummy;
+  std::vector<int> idx, maps, cptr, cidx, children;
+  std::vector<long long> child_map_off;   // per entry of `children`: offset of its map
+  int max_children = 0;
   std::vector<NDAsm> asmv;
   std::vector<std::vector<int>> by_height;   // front ids per height
   int max_height = 0;
@@ -180,6 +185,6 @@ struct NDPlan {
   std::vector<NDLaunch> fwd, bwd;
 };
 
-void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int subtree_nodes, NDPlan& plan);
+void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int subtree_nodes, int root_merge, NDPlan& plan);
 
 }  // namespace helm

@@ -39,13 +39,14 @@ __global__ void __launch_bounds__(256) k_nd_assemble(const NDFrontDev* __restric
 }
 
 __global__ void __launch_bounds__(256) k_nd_extend(const NDFrontDev* __restrict__ fr, const int* __restrict__ ids,
+                                                   const int* __restrict__ children,
+                                                   const long long* __restrict__ child_map_off,
                                                    const int* __restrict__ maps, cd* __restrict__ Fp, int slot) {
   const NDFrontDev f = fr[ids[blockIdx.y]];
-  int c = f.child[slot];
-  if (c < 0) return;
-  const NDFrontDev fc = fr[c];
+  if (slot >= f.nchild) return;
+  const NDFrontDev fc = fr[children[f.child_off + slot]];
   long long n2 = (long long)fc.nB * fc.nB;
-  const int* mp = maps + f.map_off[slot];
+  const int* mp = maps + child_map_off[f.child_off + slot];
   cd* F = Fp + f.F_off;
   const cd* Fc = Fp + fc.F_off;
   for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n2; p += (long long)gridDim.x * blockDim.x) {
@@ -129,6 +130,117 @@ __global__ void __launch_bounds__(256) k_nd_panel(const NDFrontDev* __restrict__
         rowk[tid] = -(s_rk[tid] * inv);
     }
     __syncthreads();
+  }
+}
+
+// Panel [k0, k0 + kbb) of every front of one height with the panel block (nF x KB)
+// resident in LDS: one 1024-thread work-group per front; per pivot a block-wide
+// argmax, an LDS row swap and the exchange update of the panel columns.  Row swaps
+// of the columns outside the panel are recorded in swp and applied by
+// k_nd_swap_rest.
+__device__ __forceinline__ void argmax_block1024(double v, int idx, double* sv, int* si, double& bv, int& bi) {
+  for (int o = 32; o > 0; o >>= 1) {
+    double ov = __shfl_xor(v, o, 64);
+    int oi = __shfl_xor(idx, o, 64);
+    if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) { sv[w] = v; si[w] = idx; }
+  __syncthreads();
+  bv = sv[0];
+  bi = si[0];
+  for (int q = 1; q < (int)(blockDim.x >> 6); ++q)
+    if (sv[q] > bv || (sv[q] == bv && si[q] < bi)) { bv = sv[q]; bi = si[q]; }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(1024) k_nd_panel_lds(const NDFrontDev* __restrict__ fr, const int* __restrict__ ids,
+                                                       cd* __restrict__ Fp, int* __restrict__ perm,
+                                                       int* __restrict__ swp, int k0, int KB, int* __restrict__ err) {
+  extern __shared__ char smem[];
+  cd* P = (cd*)smem;                                   // nF x KB
+  __shared__ cd s_rk[32];
+  __shared__ double s_v[16];
+  __shared__ int s_i[16];
+  const NDFrontDev f = fr[ids[blockIdx.x]];
+  if (f.nS <= k0) return;
+  const int kbb = min(KB, f.nS - k0);
+  const int nF = f.nF, tid = threadIdx.x, nt = blockDim.x;
+  cd* F = Fp + f.F_off;
+  int* pm = perm + f.perm_off;
+  int* sw = swp + (long long)blockIdx.x * 32;
+  for (int e = tid; e < nF * kbb; e += nt) {
+    int i = e / kbb, jj = e % kbb;
+    P[i * KB + jj] = F[(long long)i * nF + k0 + jj];
+  }
+  __syncthreads();
+  for (int kk = 0; kk < kbb; ++kk) {
+    const int k = k0 + kk;
+    double best = -1.0;
+    int bi = k;
+    for (int i = k + tid; i < f.nS; i += nt) {
+      double v = abs2(P[i * KB + kk]);
+      if (v > best || (v == best && i < bi)) { best = v; bi = i; }
+    }
+    double pv;
+    int p;
+    argmax_block1024(best, bi, s_v, s_i, pv, p);
+    if (p != k && tid < kbb) {
+      cd t = P[k * KB + tid];
+      P[k * KB + tid] = P[p * KB + tid];
+      P[p * KB + tid] = t;
+    }
+    if (tid == 0) {
+      sw[kk] = p;
+      if (p != k) {
+        int t = pm[k];
+        pm[k] = pm[p];
+        pm[p] = t;
+      }
+      if (!(pv > 0.0)) atomicOr(err, 1);
+    }
+    __syncthreads();
+    if (tid < kbb) s_rk[tid] = P[k * KB + tid];
+    __syncthreads();
+    cd piv = s_rk[kk];
+    if (!(pv > 0.0)) piv = mk(1.0, 0.0);
+    const cd inv = cdiv(mk(1.0, 0.0), piv);
+    for (int i = tid; i < nF; i += nt) {
+      if (i == k) continue;
+      cd* row = P + i * KB;
+      cd ck = row[kk] * inv;
+      for (int jj = 0; jj < kbb; ++jj)
+        if (jj != kk) row[jj] -= ck * s_rk[jj];
+      row[kk] = ck;
+    }
+    if (tid < kbb) P[k * KB + tid] = (tid == kk) ? inv : -(s_rk[tid] * inv);
+    __syncthreads();
+  }
+  for (int e = tid; e < nF * kbb; e += nt) {
+    int i = e / kbb, jj = e % kbb;
+    F[(long long)i * nF + k0 + jj] = P[i * KB + jj];
+  }
+}
+
+// apply the panel's recorded row swaps to the columns outside the panel
+__global__ void __launch_bounds__(256) k_nd_swap_rest(const NDFrontDev* __restrict__ fr, const int* __restrict__ ids,
+                                                      cd* __restrict__ Fp, const int* __restrict__ swp, int k0,
+                                                      int KB) {
+  const NDFrontDev f = fr[ids[blockIdx.y]];
+  if (f.nS <= k0) return;
+  const int kbb = min(KB, f.nS - k0);
+  const int* sw = swp + (long long)blockIdx.y * 32;
+  cd* F = Fp + f.F_off;
+  for (int jj = blockIdx.x * blockDim.x + threadIdx.x; jj < f.nF - kbb; jj += gridDim.x * blockDim.x) {
+    int j = jj < k0 ? jj : jj + kbb;
+    for (int kk = 0; kk < kbb; ++kk) {
+      int p = sw[kk], k = k0 + kk;
+      if (p != k) {
+        cd t = F[(long long)k * f.nF + j];
+        F[(long long)k * f.nF + j] = F[(long long)p * f.nF + j];
+        F[(long long)p * f.nF + j] = t;
+      }
+    }
   }
 }
 
@@ -216,13 +328,13 @@ __global__ void __launch_bounds__(256) k_nd_finalize(const NDFrontDev* __restric
   long long nL = (long long)f.nF * f.nS, nW = (long long)f.nS * f.nB;
   for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < nL + nW;
        p += (long long)gridDim.x * blockDim.x) {
-    if (p < nL) {
+    if (p < nL) {                 // column pm[k] of L (column major, ld nF) <- column k of F
       int i = (int)(p / f.nS), k = (int)(p % f.nS);
-      Lp[f.L_off + (long long)i * f.nS + pm[k]] = conv<C>::from(F[(long long)i * f.nF + k]);
-    } else {
+      Lp[f.L_off + (long long)pm[k] * f.nF + i] = conv<C>::from(F[(long long)i * f.nF + k]);
+    } else {                      // W (column major, ld nS) <- F[0:nS, nS:nF]
       long long q = p - nL;
       int i = (int)(q / f.nB), j = (int)(q % f.nB);
-      Wp[f.W_off + q] = conv<C>::from(F[(long long)i * f.nF + f.nS + j]);
+      Wp[f.W_off + (long long)j * f.nS + i] = conv<C>::from(F[(long long)i * f.nF + f.nS + j]);
     }
   }
 }
@@ -236,89 +348,188 @@ __global__ void k_iota(int* __restrict__ p, const NDFrontDev* __restrict__ fr, i
 
 // ----------------------------------------------------------------- solve ----
 template <typename C>
-__device__ __forceinline__ C cfma_conj(C a, C x, int conj) {   // (conj? conj(a) : a) * x
+__device__ __forceinline__ C cmul_conj(C a, C x, int conj) {   // (conj? conj(a) : a) * x
   if (conj) a.y = -a.y;
   return a * x;
 }
 
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// f_S (and v_B) entry i of front f: right-hand side on S plus the children's updates
+// (contribution list cptr[i] .. cptr[i+1] of absolute indices into the update pool)
 template <typename C>
-__device__ __forceinline__ C wave_sum(C v) {
-  for (int o = 32; o > 0; o >>= 1) {
-    v.x += __shfl_xor(v.x, o, 64);
-    v.y += __shfl_xor(v.y, o, 64);
-  }
+__device__ __forceinline__ C gather_entry(const NDFrontDev& f, const int* __restrict__ cptr,
+                                          const int* __restrict__ cidx, const int* __restrict__ id,
+                                          const C* __restrict__ upd, const C* __restrict__ r, int i) {
+  typedef decltype(r[0].x) R;
+  C v = i < f.nS ? r[id[i]] : mk((R)0, (R)0);
+  const int* cp = cptr + f.inv_off;
+  const int a = cp[i], b = cp[i + 1];
+  for (int q = a; q < b; ++q) v += upd[cidx[q]];
   return v;
 }
 
+// y_i = sum_k M[k*ld + i] v[k] for rows i in [i0, i1) by one wavefront: `lpr` lanes per row
+// (power of two) split k, the row groups walk the rows; loads unrolled for memory-level
+// parallelism; epi(i, y_i) is called by the first lane of each group.
+template <typename C, typename Epi>
+__device__ __forceinline__ void gemv_wave(const C* __restrict__ M, long long ld, int i0, int i1, int K,
+                                          const C* __restrict__ v, int conj, Epi epi) {
+  typedef decltype(v[0].x) R;
+  const int lane = threadIdx.x & 63;
+  const int rows = i1 - i0;
+  int lpr = 1;
+  while (lpr < 64 && rows * lpr * 2 <= 64 && K >= 4 * lpr) lpr *= 2;
+  const int g = lane / lpr, sub = lane % lpr, rpp = 64 / lpr;
+  for (int base = i0; base < i1; base += rpp) {
+    const int i = base + g;
+    C acc = mk((R)0, (R)0);
+    if (i < i1) {
+      const C* col = M + i;
+      int k = sub;
+#pragma unroll 16
+      for (; k < K; k += lpr) acc += cmul_conj(col[(long long)k * ld], v[k], conj);
+    }
+    for (int o = lpr >> 1; o > 0; o >>= 1) {
+      acc.x += __shfl_xor(acc.x, o, 64);
+      acc.y += __shfl_xor(acc.y, o, 64);
+    }
+    if (sub == 0 && i < i1) epi(i, acc);
+  }
+}
+
+// forward substitution, small fronts: one work-group per subtree, one front per wavefront
+// per stage; [g_S; t_B] = L f_S with L column major (ld nF).
 template <typename C>
-__global__ void __launch_bounds__(256) k_nd_fwd(const NDFrontDev* __restrict__ fr, const int* __restrict__ idx,
-                                                const int* __restrict__ maps, const C* __restrict__ Lp,
-                                                C* __restrict__ upd, const int* __restrict__ task_off,
-                                                const NDItem* __restrict__ items, const C* __restrict__ r,
-                                                C* __restrict__ x, C* __restrict__ gvec, int vec_cap, int conj) {
+__global__ void __launch_bounds__(256) k_nd_fwd_small(const NDFrontDev* __restrict__ fr, const int* __restrict__ idx,
+                                                      const int* __restrict__ cptr, const int* __restrict__ cidx,
+                                                      const C* __restrict__ Lp,
+                                                      C* __restrict__ upd, const int* __restrict__ task_off,
+                                                      const NDItem* __restrict__ items, const C* __restrict__ r,
+                                                      C* __restrict__ x, C* __restrict__ gvec, int cap, int conj) {
   extern __shared__ char smem[];
-  C* vec = gvec ? gvec + (long long)blockIdx.x * vec_cap : (C*)smem;
-  typedef decltype(vec[0].x) R;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  for (int it = task_off[blockIdx.x]; it < task_off[blockIdx.x + 1]; ++it) {
-    const NDItem item = items[it];
-    const NDFrontDev f = fr[item.front];
-    const int* id = idx + f.idx_off;
-    for (int i = tid; i < f.nF; i += 256) {
-      vec[i] = i < f.nS ? r[id[i]] : mk((R)0, (R)0);
-    }
-    __syncthreads();
-    for (int s = 0; s < 2; ++s) {
-      int c = f.child[s];
-      if (c < 0) continue;
-      const NDFrontDev fc = fr[c];
-      const int* mp = maps + f.map_off[s];
-      const C* u = upd + fc.upd_off;
-      for (int k = tid; k < fc.nB; k += 256) vec[mp[k]] += u[k];
-      __syncthreads();
-    }
-    const C* L = Lp + f.L_off;
-    for (int i = item.r0 + wv; i < item.r1; i += 4) {
-      const C* row = L + (long long)i * f.nS;
-      C acc = mk((R)0, (R)0);
-      for (int k = lane; k < f.nS; k += 64) acc += cfma_conj(row[k], vec[k], conj);
-      acc = wave_sum(acc);
-      if (lane == 0) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  C* vec = (gvec ? gvec + (long long)blockIdx.x * 4 * cap : (C*)smem) + (long long)wv * cap;
+  const int beg = task_off[blockIdx.x], end = task_off[blockIdx.x + 1];
+  for (int it = beg; it < end;) {
+    const int stage = items[it].stage;
+    int send = it;
+    while (send < end && items[send].stage == stage) ++send;
+    for (int q = it + wv; q < send; q += 4) {
+      const NDFrontDev f = fr[items[q].front];
+      const int* id = idx + f.idx_off;
+      for (int i = lane; i < f.nF; i += 64) vec[i] = gather_entry(f, cptr, cidx, id, upd, r, i);
+      wave_sync();
+      gemv_wave(Lp + f.L_off, f.nF, 0, f.nF, f.nS, vec, conj, [&](int i, C acc) {
         if (i < f.nS)
           x[id[i]] = acc;
         else
           upd[f.upd_off + i - f.nS] = vec[i] - acc;
-      }
+      });
+      wave_sync();
     }
     __syncthreads();
+    it = send;
+  }
+}
+
+// backward substitution, small fronts: x_S = g_S + W x_B (W column major, ld nS)
+template <typename C>
+__global__ void __launch_bounds__(256) k_nd_bwd_small(const NDFrontDev* __restrict__ fr, const int* __restrict__ idx,
+                                                      const C* __restrict__ Wp, const int* __restrict__ task_off,
+                                                      const NDItem* __restrict__ items, C* __restrict__ x,
+                                                      C* __restrict__ gvec, int cap, int conj) {
+  extern __shared__ char smem[];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  C* vec = (gvec ? gvec + (long long)blockIdx.x * 4 * cap : (C*)smem) + (long long)wv * cap;
+  const int beg = task_off[blockIdx.x], end = task_off[blockIdx.x + 1];
+  for (int it = beg; it < end;) {
+    const int stage = items[it].stage;
+    int send = it;
+    while (send < end && items[send].stage == stage) ++send;
+    for (int q = it + wv; q < send; q += 4) {
+      const NDFrontDev f = fr[items[q].front];
+      const int* id = idx + f.idx_off;
+      for (int j = lane; j < f.nB; j += 64) vec[j] = x[id[f.nS + j]];
+      wave_sync();
+      gemv_wave(Wp + f.W_off, f.nS, 0, f.nS, f.nB, vec, conj, [&](int i, C acc) { x[id[i]] = x[id[i]] + acc; });
+      wave_sync();
+    }
+    __syncthreads();
+    it = send;
+  }
+}
+
+// rows [r0, r1) (at most 16) of a big front: 16 row lanes x 16 k-splits per work-group,
+// partial sums reduced through LDS; consecutive threads read consecutive rows of one column.
+template <typename C>
+__device__ __forceinline__ C gemv_block16(const C* __restrict__ M, long long ld, int r0, int r1, int K,
+                                          const C* __restrict__ v, int conj, C* red) {
+  typedef decltype(v[0].x) R;
+  const int row = threadIdx.x & 15, ks = threadIdx.x >> 4;
+  const int i = r0 + row;
+  const int kq = (K + 15) / 16, kb = ks * kq, ke = min(K, kb + kq);
+  C acc = mk((R)0, (R)0);
+  if (i < r1) {
+    const C* col = M + i;
+#pragma unroll 16
+    for (int k = kb; k < ke; ++k) acc += cmul_conj(col[(long long)k * ld], v[k], conj);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  C tot = mk((R)0, (R)0);
+  if (threadIdx.x < 16)
+    for (int q = 0; q < 16; ++q) tot += red[q * 16 + threadIdx.x];
+  return tot;
+}
+
+// forward substitution, big fronts: one work-group per chunk of at most 64 rows
+template <typename C>
+__global__ void __launch_bounds__(256) k_nd_fwd_big(const NDFrontDev* __restrict__ fr, const int* __restrict__ idx,
+                                                    const int* __restrict__ cptr, const int* __restrict__ cidx,
+                                                    const C* __restrict__ Lp,
+                                                    C* __restrict__ upd, const NDItem* __restrict__ items,
+                                                    const C* __restrict__ r, C* __restrict__ x,
+                                                    C* __restrict__ gvec, int cap, int conj) {
+  extern __shared__ char smem[];
+  __shared__ C red[256];
+  C* vec = gvec ? gvec + (long long)blockIdx.x * cap : (C*)smem;
+  const NDItem item = items[blockIdx.x];
+  const NDFrontDev f = fr[item.front];
+  const int* id = idx + f.idx_off;
+  for (int i = threadIdx.x; i < f.nS; i += 256) vec[i] = gather_entry(f, cptr, cidx, id, upd, r, i);
+  for (int i = max(item.r0, f.nS) + threadIdx.x; i < item.r1; i += 256)
+    vec[i] = gather_entry(f, cptr, cidx, id, upd, r, i);
+  __syncthreads();
+  C acc = gemv_block16(Lp + f.L_off, f.nF, item.r0, item.r1, f.nS, vec, conj, red);
+  const int i = item.r0 + threadIdx.x;
+  if (threadIdx.x < 16 && i < item.r1) {
+    if (i < f.nS)
+      x[id[i]] = acc;
+    else
+      upd[f.upd_off + i - f.nS] = vec[i] - acc;
   }
 }
 
 template <typename C>
-__global__ void __launch_bounds__(256) k_nd_bwd(const NDFrontDev* __restrict__ fr, const int* __restrict__ idx,
-                                                const C* __restrict__ Wp, const int* __restrict__ task_off,
-                                                const NDItem* __restrict__ items, C* __restrict__ x,
-                                                C* __restrict__ gvec, int vec_cap, int conj) {
+__global__ void __launch_bounds__(256) k_nd_bwd_big(const NDFrontDev* __restrict__ fr, const int* __restrict__ idx,
+                                                    const C* __restrict__ Wp, const NDItem* __restrict__ items,
+                                                    C* __restrict__ x, C* __restrict__ gvec, int cap, int conj) {
   extern __shared__ char smem[];
-  C* vec = gvec ? gvec + (long long)blockIdx.x * vec_cap : (C*)smem;
-  typedef decltype(vec[0].x) R;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  for (int it = task_off[blockIdx.x]; it < task_off[blockIdx.x + 1]; ++it) {
-    const NDItem item = items[it];
-    const NDFrontDev f = fr[item.front];
-    const int* id = idx + f.idx_off;
-    for (int j = tid; j < f.nB; j += 256) vec[j] = x[id[f.nS + j]];
-    __syncthreads();
-    const C* W = Wp + f.W_off;
-    for (int i = item.r0 + wv; i < item.r1; i += 4) {
-      const C* row = W + (long long)i * f.nB;
-      C acc = mk((R)0, (R)0);
-      for (int k = lane; k < f.nB; k += 64) acc += cfma_conj(row[k], vec[k], conj);
-      acc = wave_sum(acc);
-      if (lane == 0) x[id[i]] = x[id[i]] + acc;
-    }
-    __syncthreads();
-  }
+  __shared__ C red[256];
+  C* vec = gvec ? gvec + (long long)blockIdx.x * cap : (C*)smem;
+  const NDItem item = items[blockIdx.x];
+  const NDFrontDev f = fr[item.front];
+  const int* id = idx + f.idx_off;
+  for (int j = threadIdx.x; j < f.nB; j += 256) vec[j] = x[id[f.nS + j]];
+  __syncthreads();
+  C acc = gemv_block16(Wp + f.W_off, f.nS, item.r0, item.r1, f.nB, vec, conj, red);
+  const int i = item.r0 + threadIdx.x;
+  if (threadIdx.x < 16 && i < item.r1) x[id[i]] = x[id[i]] + acc;
 }
 
 // ------------------------------------------------------------- launchers ----
@@ -333,14 +544,23 @@ void nd_assemble(const NDFrontDev* fr, const int* ids, int nids, int max_asm, co
   unsigned gx = (unsigned)std::min(1024, std::max(1, (max_asm + 255) / 256));
   hipLaunchKernelGGL(k_nd_assemble, dim3(gx, nids), dim3(256), 0, s, fr, ids, asmv, coef, Fp);
 }
-void nd_extend(const NDFrontDev* fr, const int* ids, int nids, long long max_nb2, const int* maps, cd* Fp,
-               int slot, hipStream_t s) {
+void nd_extend(const NDFrontDev* fr, const int* ids, int nids, long long max_nb2, const int* children,
+               const long long* child_map_off, const int* maps, cd* Fp, int slot, hipStream_t s) {
   unsigned gx = (unsigned)std::min<long long>(2048, std::max<long long>(1, (max_nb2 + 255) / 256));
-  hipLaunchKernelGGL(k_nd_extend, dim3(gx, nids), dim3(256), 0, s, fr, ids, maps, Fp, slot);
+  hipLaunchKernelGGL(k_nd_extend, dim3(gx, nids), dim3(256), 0, s, fr, ids, children, child_map_off, maps, Fp, slot);
 }
 void nd_panel(const NDFrontDev* fr, const int* ids, int nids, cd* Fp, int* perm, int k0, int kb, int* err,
               hipStream_t s) {
   hipLaunchKernelGGL(k_nd_panel, dim3(nids), dim3(256), 0, s, fr, ids, Fp, perm, k0, kb, err);
+}
+void nd_panel_lds(const NDFrontDev* fr, const int* ids, int nids, int max_nF, cd* Fp, int* perm, int* swp, int k0,
+                  int kb, int* err, hipStream_t s) {
+  size_t lds = (size_t)max_nF * kb * sizeof(cd);
+  if (lds > 65536) (void)hipFuncSetAttribute((const void*)k_nd_panel_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)lds);
+  hipLaunchKernelGGL(k_nd_panel_lds, dim3(nids), dim3(1024), lds, s, fr, ids, Fp, perm, swp, k0, kb, err);
+  unsigned gx = (unsigned)std::min(64, std::max(1, (max_nF + 255) / 256));
+  hipLaunchKernelGGL(k_nd_swap_rest, dim3(gx, nids), dim3(256), 0, s, fr, ids, Fp, swp, k0, kb);
 }
 void nd_save_t(const NDFrontDev* fr, const int* ids, int nids, const long long* toff, long long max_n,
                cd* Fp, cd* T, int k0, int kb, hipStream_t s) {
@@ -359,30 +579,37 @@ void nd_finalize(const NDFrontDev* fr, const int* ids, int nids, long long max_n
   hipLaunchKernelGGL((k_nd_finalize<C>), dim3(gx, nids), dim3(256), 0, s, fr, ids, Fp, perm, Lp, Wp);
 }
 template <typename C>
-void nd_fwd(int ntasks, size_t lds, const NDFrontDev* fr, const int* idx, const int* maps, const C* Lp, C* upd,
-            const int* task_off, const NDItem* items, const C* r, C* x, C* gvec, int vec_cap, int conj,
-            hipStream_t s) {
-  hipLaunchKernelGGL((k_nd_fwd<C>), dim3(ntasks), dim3(256), lds, s, fr, idx, maps, Lp, upd, task_off, items, r, x,
-                     gvec, vec_cap, conj);
+void nd_fwd(int kind, int ntasks, size_t lds, const NDFrontDev* fr, const int* idx, const int* cptr,
+            const int* cidx, const C* Lp, C* upd, const int* task_off, const NDItem* items, const C* r, C* x,
+            C* gvec, int cap, int conj, hipStream_t s) {
+  if (kind == 0)
+    hipLaunchKernelGGL((k_nd_fwd_small<C>), dim3(ntasks), dim3(256), lds, s, fr, idx, cptr, cidx, Lp, upd, task_off,
+                       items, r, x, gvec, cap, conj);
+  else
+    hipLaunchKernelGGL((k_nd_fwd_big<C>), dim3(ntasks), dim3(256), lds, s, fr, idx, cptr, cidx, Lp, upd, items, r, x,
+                       gvec, cap, conj);
 }
 template <typename C>
-void nd_bwd(int ntasks, size_t lds, const NDFrontDev* fr, const int* idx, const C* Wp, const int* task_off,
-            const NDItem* items, C* x, C* gvec, int vec_cap, int conj, hipStream_t s) {
-  hipLaunchKernelGGL((k_nd_bwd<C>), dim3(ntasks), dim3(256), lds, s, fr, idx, Wp, task_off, items, x, gvec, vec_cap,
-                     conj);
+void nd_bwd(int kind, int ntasks, size_t lds, const NDFrontDev* fr, const int* idx, const C* Wp, const int* task_off,
+            const NDItem* items, C* x, C* gvec, int cap, int conj, hipStream_t s) {
+  if (kind == 0)
+    hipLaunchKernelGGL((k_nd_bwd_small<C>), dim3(ntasks), dim3(256), lds, s, fr, idx, Wp, task_off, items, x, gvec,
+                       cap, conj);
+  else
+    hipLaunchKernelGGL((k_nd_bwd_big<C>), dim3(ntasks), dim3(256), lds, s, fr, idx, Wp, items, x, gvec, cap, conj);
 }
 
 template void nd_finalize<cf>(const NDFrontDev*, const int*, int, long long, const cd*, const int*,
                                   cf*, cf*, hipStream_t);
 template void nd_finalize<cd>(const NDFrontDev*, const int*, int, long long, const cd*, const int*,
                                    cd*, cd*, hipStream_t);
-template void nd_fwd<cf>(int, size_t, const NDFrontDev*, const int*, const int*, const cf*, cf*,
-                             const int*, const NDItem*, const cf*, cf*, cf*, int, int, hipStream_t);
-template void nd_fwd<cd>(int, size_t, const NDFrontDev*, const int*, const int*, const cd*, cd*,
-                              const int*, const NDItem*, const cd*, cd*, cd*, int, int, hipStream_t);
-template void nd_bwd<cf>(int, size_t, const NDFrontDev*, const int*, const cf*, const int*, const NDItem*,
-                             cf*, cf*, int, int, hipStream_t);
-template void nd_bwd<cd>(int, size_t, const NDFrontDev*, const int*, const cd*, const int*,
-                              const NDItem*, cd*, cd*, int, int, hipStream_t);
+template void nd_fwd<cf>(int, int, size_t, const NDFrontDev*, const int*, const int*, const int*, const cf*, cf*,
+                         const int*, const NDItem*, const cf*, cf*, cf*, int, int, hipStream_t);
+template void nd_fwd<cd>(int, int, size_t, const NDFrontDev*, const int*, const int*, const int*, const cd*, cd*,
+                         const int*, const NDItem*, const cd*, cd*, cd*, int, int, hipStream_t);
+template void nd_bwd<cf>(int, int, size_t, const NDFrontDev*, const int*, const cf*, const int*, const NDItem*, cf*,
+                         cf*, int, int, hipStream_t);
+template void nd_bwd<cd>(int, int, size_t, const NDFrontDev*, const int*, const cd*, const int*, const NDItem*, cd*,
+                         cd*, int, int, hipStream_t);
 
 }  // namespace helm

@@ -9,10 +9,14 @@
 // is the one-node halo of its box, which lies in ancestor separators.  After
 // its subtree is eliminated, a front couples S and B densely.
 //
+// The separators of the top levels may be merged into one root front (a
+// supernode): elimination stays exact, the tree gets shallower, and the solve
+// needs fewer dependent steps at the price of a larger dense root block.
+//
 // This file builds, on the host: the tree, the S/B index lists, the child->parent
-// position maps used by the extend-add of Schur complements, the list of
-// original matrix entries each front assembles, storage offsets, and the work
-// schedules of the forward and backward substitutions.
+// position maps used by the extend-add of Schur complements and their inverses,
+// the list of original matrix entries each front assembles, storage offsets, and
+// the work schedules of the forward and backward substitutions.
 #include <algorithm>
 #include <cassert>
 #include <cstdio>
@@ -34,30 +38,23 @@ struct Builder {
   Geom g;
   int leaf_max;
   std::vector<Box> box;
-  std::vector<std::vector<int>> S, B;
-  std::vector<int> parent, ch0, ch1, height;
-  std::vector<long long> sub_nodes;
-  std::vector<int> owner, pos_in_S;
+  std::vector<std::vector<int>> S, B, kids;
+  std::vector<int> parent;
 
   long long count(const Box& b) const {
     long long c = 1;
     for (int a = 0; a < g.dim; ++a) c *= (b.hi[a] - b.lo[a] + 1);
     return c;
   }
-  int flat(int i0, int i1, int i2) const {
-    return i0 + g.N[0] * (i1 + g.N[1] * i2);
-  }
+  int flat(int i0, int i1, int i2) const { return i0 + g.N[0] * (i1 + g.N[1] * i2); }
 
   int build(const Box& b, int par) {
     int id = (int)box.size();
     box.push_back(b);
     S.emplace_back();
     B.emplace_back();
+    kids.emplace_back();
     parent.push_back(par);
-    ch0.push_back(-1);
-    ch1.push_back(-1);
-    height.push_back(0);
-    sub_nodes.push_back(count(b));
     int ax = -1, ext = 0;
     for (int a = g.dim - 1; a >= 0; --a) {     // ties: prefer the slowest axis
       int e = b.hi[a] - b.lo[a] + 1;
@@ -73,28 +70,23 @@ struct Builder {
       c1.lo[ax] = mid + 1;
       int a0 = build(c0, id);
       int a1 = build(c1, id);
-      ch0[id] = a0;
-      ch1[id] = a1;
-      height[id] = 1 + std::max(height[a0], height[a1]);
+      kids[id] = {a0, a1};
     }
-    // separator (or whole leaf box) nodes, increasing flat index
-    std::vector<int>& s = S[id];
     for (int i2 = sep.lo[2]; i2 <= sep.hi[2]; ++i2)
       for (int i1 = sep.lo[1]; i1 <= sep.hi[1]; ++i1)
-        for (int i0 = sep.lo[0]; i0 <= sep.hi[0]; ++i0) s.push_back(flat(i0, i1, i2));
+        for (int i0 = sep.lo[0]; i0 <= sep.hi[0]; ++i0) S[id].push_back(flat(i0, i1, i2));
     // one-node halo of the box inside the domain, increasing flat index
     int lo[3], hi[3];
     for (int a = 0; a < 3; ++a) {
       lo[a] = std::max(b.lo[a] - 1, 0);
       hi[a] = std::min(b.hi[a] + 1, g.N[a] - 1);
     }
-    std::vector<int>& bb = B[id];
     for (int i2 = lo[2]; i2 <= hi[2]; ++i2)
       for (int i1 = lo[1]; i1 <= hi[1]; ++i1)
         for (int i0 = lo[0]; i0 <= hi[0]; ++i0) {
           bool inside = i0 >= b.lo[0] && i0 <= b.hi[0] && i1 >= b.lo[1] && i1 <= b.hi[1] &&
                         i2 >= b.lo[2] && i2 <= b.hi[2];
-          if (!inside) bb.push_back(flat(i0, i1, i2));
+          if (!inside) B[id].push_back(flat(i0, i1, i2));
         }
     return id;
   }
@@ -102,56 +94,98 @@ struct Builder {
 
 }  // namespace
 
-void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int subtree_nodes, NDPlan& plan) {
+void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int subtree_nodes, int root_merge, NDPlan& plan) {
   Builder bd;
   bd.g = g3;
   bd.leaf_max = std::max(leaf_max, 1);
-  Box root;
+  Box rootbox;
   for (int a = 0; a < 3; ++a) {
-    root.lo[a] = 0;
-    root.hi[a] = g3.N[a] - 1;
+    rootbox.lo[a] = 0;
+    rootbox.hi[a] = g3.N[a] - 1;
   }
-  bd.build(root, -1);
-  const int nf = (int)bd.box.size();
-  const long long N3 = g3.tot;
-  bd.owner.assign(N3, -1);
-  bd.pos_in_S.assign(N3, -1);
-  for (int t = 0; t < nf; ++t)
-    for (size_t i = 0; i < bd.S[t].size(); ++i) {
-      int v = bd.S[t][i];
-      if (bd.owner[v] != -1) throw std::runtime_error("nd_plan: node in two separators");
-      bd.owner[v] = t;
-      bd.pos_in_S[v] = (int)i;
+  bd.build(rootbox, -1);
+  const int nraw = (int)bd.box.size();
+  // ---- merge whole levels of separators into the root while its separator stays <= root_merge
+  std::vector<char> alive(nraw, 1);
+  {
+    std::vector<int> frontier = bd.kids[0];
+    while (!frontier.empty()) {
+      size_t add = 0;
+      for (int c : frontier) add += bd.S[c].size();
+      if (bd.S[0].size() + add > (size_t)root_merge) break;
+      std::vector<int> next;
+      for (int c : frontier) {
+        bd.S[0].insert(bd.S[0].end(), bd.S[c].begin(), bd.S[c].end());
+        alive[c] = 0;
+        next.insert(next.end(), bd.kids[c].begin(), bd.kids[c].end());
+      }
+      frontier = next;
     }
+    std::sort(bd.S[0].begin(), bd.S[0].end());
+    bd.kids[0] = frontier;
+    for (int c : frontier) bd.parent[c] = 0;
+  }
+  // ---- renumber the surviving fronts (children keep larger ids than their parent)
+  std::vector<int> nid(nraw, -1), oid;
+  for (int t = 0; t < nraw; ++t)
+    if (alive[t]) {
+      nid[t] = (int)oid.size();
+      oid.push_back(t);
+    }
+  const int nf = (int)oid.size();
+  const long long N3 = g3.tot;
+  std::vector<int> owner(N3, -1), pos_in_S(N3, -1);
+  for (int t = 0; t < nf; ++t) {
+    const std::vector<int>& s = bd.S[oid[t]];
+    for (size_t i = 0; i < s.size(); ++i) {
+      if (owner[s[i]] != -1) throw std::runtime_error("nd_plan: node in two separators");
+      owner[s[i]] = t;
+      pos_in_S[s[i]] = (int)i;
+    }
+  }
   for (long long v = 0; v < N3; ++v)
-    if (bd.owner[v] < 0) throw std::runtime_error("nd_plan: node in no separator");
+    if (owner[v] < 0) throw std::runtime_error("nd_plan: node in no separator");
+  std::vector<std::vector<int>> kids(nf);
+  std::vector<int> par(nf, -1), height(nf, 0);
+  for (int t = 0; t < nf; ++t)
+    for (int c : bd.kids[oid[t]]) {
+      kids[t].push_back(nid[c]);
+      par[nid[c]] = t;
+    }
+  for (int t = nf - 1; t >= 0; --t)
+    for (int c : kids[t]) height[t] = std::max(height[t], height[c] + 1);
 
   plan.g = g3;
   plan.fronts.assign(nf, NDFrontDev());
   plan.idx.clear();
   plan.maps.clear();
   plan.asmv.clear();
+  plan.children.clear();
+  plan.child_map_off.clear();
   plan.max_height = 0;
+  plan.max_children = 0;
+  plan.max_nS = plan.max_nB = plan.max_nF = 0;
   long long F = 0, L = 0, W = 0, U = 0, P = 0;
+  auto Bof = [&](int t) -> const std::vector<int>& { return bd.B[oid[t]]; };
   auto posF = [&](int t, int v) -> int {   // position of node v in front t's (S, B) list, -1 if absent
-    if (bd.owner[v] == t) return bd.pos_in_S[v];
-    const std::vector<int>& b = bd.B[t];
+    if (owner[v] == t) return pos_in_S[v];
+    const std::vector<int>& b = Bof(t);
     auto it = std::lower_bound(b.begin(), b.end(), v);
     if (it == b.end() || *it != v) return -1;
-    return (int)bd.S[t].size() + (int)(it - b.begin());
+    return (int)bd.S[oid[t]].size() + (int)(it - b.begin());
   };
   for (int t = 0; t < nf; ++t) {
     NDFrontDev& f = plan.fronts[t];
-    f.nS = (int)bd.S[t].size();
-    f.nB = (int)bd.B[t].size();
+    f.nS = (int)bd.S[oid[t]].size();
+    f.nB = (int)Bof(t).size();
     f.nF = f.nS + f.nB;
-    f.child[0] = bd.ch0[t];
-    f.child[1] = bd.ch1[t];
-    f.height = bd.height[t];
+    f.nchild = (int)kids[t].size();
+    f.height = height[t];
     plan.max_height = std::max(plan.max_height, f.height);
+    plan.max_children = std::max(plan.max_children, f.nchild);
     f.idx_off = (long long)plan.idx.size();
-    plan.idx.insert(plan.idx.end(), bd.S[t].begin(), bd.S[t].end());
-    plan.idx.insert(plan.idx.end(), bd.B[t].begin(), bd.B[t].end());
+    plan.idx.insert(plan.idx.end(), bd.S[oid[t]].begin(), bd.S[oid[t]].end());
+    plan.idx.insert(plan.idx.end(), Bof(t).begin(), Bof(t).end());
     f.F_off = F;  F += (long long)f.nF * f.nF;
     f.L_off = L;  L += (long long)f.nF * f.nS;
     f.W_off = W;  W += (long long)f.nS * f.nB;
@@ -161,20 +195,39 @@ void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int subtree_nodes, ND
     plan.max_nB = std::max(plan.max_nB, f.nB);
     plan.max_nF = std::max(plan.max_nF, f.nF);
   }
-  // child -> parent maps
+  // child -> parent maps (setup extend-add) and, per parent position, the list of
+  // child-update entries that add into it (solve gather), as CSR over positions
+  plan.cptr.clear();
+  plan.cidx.clear();
   for (int t = 0; t < nf; ++t) {
     NDFrontDev& f = plan.fronts[t];
-    for (int c = 0; c < 2; ++c) {
-      f.map_off[c] = -1;
-      int ch = f.child[c];
-      if (ch < 0) continue;
-      f.map_off[c] = (long long)plan.maps.size();
-      for (int v : bd.B[ch]) {
+    f.child_off = (int)plan.children.size();
+    std::vector<std::vector<int>> contrib(f.nF);
+    for (int c = 0; c < f.nchild; ++c) {
+      int ch = kids[t][c];
+      plan.children.push_back(ch);
+      plan.child_map_off.push_back((long long)plan.maps.size());
+      std::vector<char> seen(f.nF, 0);
+      int k = 0;
+      for (int v : Bof(ch)) {
         int p = posF(t, v);
         if (p < 0) throw std::runtime_error("nd_plan: child boundary outside parent front");
+        if (seen[p]) throw std::runtime_error("nd_plan: map not injective");
+        seen[p] = 1;
         plan.maps.push_back(p);
+        long long a = plan.fronts[ch].upd_off + k++;
+        if (a > 0x7fffffffLL) throw std::runtime_error("nd_plan: update pool too large");
+        contrib[p].push_back((int)a);
       }
     }
+    f.inv_off = (long long)plan.cptr.size();
+    int acc = (int)plan.cidx.size();
+    for (int p = 0; p < f.nF; ++p) {
+      plan.cptr.push_back(acc);
+      plan.cidx.insert(plan.cidx.end(), contrib[p].begin(), contrib[p].end());
+      acc += (int)contrib[p].size();
+    }
+    plan.cptr.push_back(acc);
   }
   // assembly lists: entry (i, j) of the operator goes to the front where the first
   // eliminated of i, j is a separator node; the other one is then in that front too.
@@ -182,9 +235,10 @@ void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int subtree_nodes, ND
   for (int t = 0; t < nf; ++t) {
     NDFrontDev& f = plan.fronts[t];
     f.asm_off = (long long)plan.asmv.size();
-    const Box& bx = bd.box[t];
+    const Box& bx = bd.box[oid[t]];
+    const std::vector<int>& St = bd.S[oid[t]];
     for (int ps = 0; ps < f.nS; ++ps) {
-      int s = bd.S[t][ps];
+      int s = St[ps];
       int s0 = s % g3.N[0], s1 = (s / g3.N[0]) % g3.N[1], s2 = s / (g3.N[0] * g3.N[1]);
       for (int d2 = (dim == 3 ? -1 : 0); d2 <= (dim == 3 ? 1 : 0); ++d2)
         for (int d1 = -1; d1 <= 1; ++d1)
@@ -194,8 +248,8 @@ void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int subtree_nodes, ND
             int q = bd.flat(q0, q1, q2);
             int k = (d0 + 1) + 3 * (d1 + 1) + (dim == 3 ? 9 * (d2 + 1) : 0);
             int kq = (-d0 + 1) + 3 * (-d1 + 1) + (dim == 3 ? 9 * (-d2 + 1) : 0);
-            if (bd.owner[q] == t) {
-              plan.asmv.push_back({ps, bd.pos_in_S[q], (long long)k * N3 + s});
+            if (owner[q] == t) {
+              plan.asmv.push_back({ps, pos_in_S[q], (long long)k * N3 + s});
             } else {
               bool inbox = q0 >= bx.lo[0] && q0 <= bx.hi[0] && q1 >= bx.lo[1] && q1 <= bx.hi[1] &&
                            q2 >= bx.lo[2] && q2 <= bx.hi[2];
@@ -224,14 +278,20 @@ void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int subtree_nodes, ND
     Tmax = std::max(Tmax, s);
   }
   plan.T_scratch = Tmax;
+  std::vector<long long> subn(nf, 0);
+  for (int t = nf - 1; t >= 0; --t) {
+    subn[t] = plan.fronts[t].nS;
+    for (int c : kids[t]) subn[t] += subn[c];
+  }
 
   // ---------------- solve schedules ----------------
-  // fronts of height <= hcut are handled by one work-group per subtree (post-order
-  // forward, pre-order backward); higher fronts by one launch per height with row chunks.
+  // fronts of height <= hcut are handled by one work-group per subtree, stage by
+  // stage (heights ascending forward, descending backward) with one front per
+  // wavefront; higher fronts by one launch per height with chunks of rows_chunk rows.
   int hcut = -1;
   for (int h = 0; h <= plan.max_height; ++h) {
     bool ok = true;
-    for (int t : plan.by_height[h]) ok = ok && bd.sub_nodes[t] <= subtree_nodes;
+    for (int t : plan.by_height[h]) ok = ok && subn[t] <= subtree_nodes && plan.fronts[t].nF <= 1024;
     if (!ok) break;
     hcut = h;
   }
@@ -239,28 +299,29 @@ void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int subtree_nodes, ND
   plan.bwd.clear();
   if (hcut >= 0) {
     NDLaunch fl, bl;
+    fl.kind = bl.kind = 0;
     fl.task_off.push_back(0);
     bl.task_off.push_back(0);
-    fl.max_rows_vec = bl.max_rows_vec = 0;
     for (int t = 0; t < nf; ++t) {
-      bool root = plan.fronts[t].height <= hcut &&
-                  (bd.parent[t] < 0 || plan.fronts[bd.parent[t]].height > hcut);
+      bool root = plan.fronts[t].height <= hcut && (par[t] < 0 || plan.fronts[par[t]].height > hcut);
       if (!root) continue;
-      std::vector<int> post, pre;
+      std::vector<int> sub;
       std::function<void(int)> walk = [&](int u) {
-        pre.push_back(u);
-        for (int c = 0; c < 2; ++c)
-          if (plan.fronts[u].child[c] >= 0) walk(plan.fronts[u].child[c]);
-        post.push_back(u);
+        sub.push_back(u);
+        for (int c : kids[u]) walk(c);
       };
       walk(t);
-      for (int u : post) {
-        fl.items.push_back({u, 0, plan.fronts[u].nF, 0});
-        fl.max_rows_vec = std::max(fl.max_rows_vec, plan.fronts[u].nF);
+      std::stable_sort(sub.begin(), sub.end(),
+                       [&](int a, int b) { return plan.fronts[a].height < plan.fronts[b].height; });
+      for (int u : sub) {
+        const NDFrontDev& f = plan.fronts[u];
+        fl.items.push_back({u, 0, f.nF, f.height});
+        fl.max_rows_vec = std::max(fl.max_rows_vec, f.nF);
       }
-      for (int u : pre) {
-        bl.items.push_back({u, 0, plan.fronts[u].nS, 0});
-        bl.max_rows_vec = std::max(bl.max_rows_vec, plan.fronts[u].nB);
+      for (auto it = sub.rbegin(); it != sub.rend(); ++it) {
+        const NDFrontDev& f = plan.fronts[*it];
+        bl.items.push_back({*it, 0, f.nS, f.height});
+        bl.max_rows_vec = std::max(bl.max_rows_vec, f.nB);
       }
       fl.task_off.push_back((int)fl.items.size());
       bl.task_off.push_back((int)bl.items.size());
@@ -271,24 +332,25 @@ void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int subtree_nodes, ND
   std::vector<NDLaunch> bwd_high;
   for (int h = hcut + 1; h <= plan.max_height; ++h) {
     NDLaunch fl, bl;
+    fl.kind = bl.kind = 1;
     fl.task_off.push_back(0);
     bl.task_off.push_back(0);
-    fl.max_rows_vec = bl.max_rows_vec = 0;
     for (int t : plan.by_height[h]) {
       const NDFrontDev& f = plan.fronts[t];
       for (int r = 0; r < f.nF; r += rows_chunk) {
-        fl.items.push_back({t, r, std::min(f.nF, r + rows_chunk), 0});
+        fl.items.push_back({t, r, std::min(f.nF, r + rows_chunk), h});
         fl.task_off.push_back((int)fl.items.size());
       }
-      for (int r = 0; r < f.nS; r += rows_chunk) {
-        bl.items.push_back({t, r, std::min(f.nS, r + rows_chunk), 0});
-        bl.task_off.push_back((int)bl.items.size());
-      }
+      if (f.nB > 0)          // a front without boundary has nothing to back-substitute
+        for (int r = 0; r < f.nS; r += rows_chunk) {
+          bl.items.push_back({t, r, std::min(f.nS, r + rows_chunk), h});
+          bl.task_off.push_back((int)bl.items.size());
+        }
       fl.max_rows_vec = std::max(fl.max_rows_vec, f.nF);
       bl.max_rows_vec = std::max(bl.max_rows_vec, f.nB);
     }
     plan.fwd.push_back(fl);
-    bwd_high.push_back(bl);
+    if (!bl.items.empty()) bwd_high.push_back(bl);
   }
   std::vector<NDLaunch> bwd_all(bwd_high.rbegin(), bwd_high.rend());
   for (auto& l : plan.bwd) bwd_all.push_back(l);

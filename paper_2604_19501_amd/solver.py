@@ -85,11 +85,33 @@ class Solver:
         kap = _dev_tensor(slowness, torch.float64, self.device)
         if kap.numel() != self.N:
             raise ValueError("slowness has %d entries, grid has %d nodes" % (kap.numel(), self.N))
+        self._kap = kap
         ctx = C.c_void_p()
         L.check(L.lib.helm_setup(C.byref(self.grid), C.c_void_p(kap.data_ptr()), self.omega, C.byref(self.shift),
                                  C.byref(self.mg), C.c_void_p(self._ws_ptr), self.ws_bytes,
                                  C.c_void_p(_stream_ptr(self.device)), C.byref(ctx)), "helm_setup")
         self.ctx = ctx
+
+    def refactor(self, slowness=None, omega=None, alpha=None, alpha2=None, beta=None):
+        """numerical setup again (coefficients, Galerkin operators, coarsest factorisation) for a
+        new medium / frequency / shift on the same grid."""
+        if slowness is not None:
+            self._kap = _dev_tensor(slowness, torch.float64, self.device)
+        if omega is not None:
+            self.omega = float(omega)
+        for name, v in (("alpha", alpha), ("alpha2", alpha2), ("beta", beta)):
+            if v is not None:
+                setattr(self.shift, name, float(v))
+        L.check(L.lib.helm_refactor(self.ctx, C.c_void_p(self._kap.data_ptr()), self.omega, C.byref(self.shift),
+                                    self._s()), "helm_refactor")
+
+    KERNEL_CLASSES = ("l1_sweep", "l1_restrict", "l2_sweep", "l2_restrict", "nd_fwd", "nd_bwd", "arnoldi")
+
+    def kernel_times(self):
+        """{class: (ms, launches)} accumulated since set_timing(True)."""
+        t = (C.c_double * 25)()
+        L.lib.helm_get_timing(self.ctx, t, 25)
+        return {k: (t[5 + 2 * i], int(t[6 + 2 * i])) for i, k in enumerate(self.KERNEL_CLASSES)}
 
     # -- lifetime
     def close(self):

@@ -138,6 +138,7 @@ class Problem:
     beta: float
     sources: List[Tuple[int, ...]]
     G: float
+    alpha2: float = 1.0     # real shift of the level-2 Galerkin operator
     cycle: int = 2          # 1 = V, 2 = W
     nu_pre: int = 2
     nu_post: int = 2
@@ -166,16 +167,25 @@ def config1(n: int = 128) -> Problem:
                    [(n // 2, n // 2)], G)
 
 
+# level-2 real shifts: the same grid-to-grid analysis between levels 1 and 2
+# (e = r_2 / (2 r_1) - 1) for the contract stack; used where both coarse grids are shifted.
+ALPHA2_STAR = {(2, 10.0): 1.0360, (2, 12.0): 1.0255}
+
+CFG2_BETA = 0.1
+
+
 def config2(n: int = 1024, seed: int = 2000) -> Problem:
     """2D layered: 8 layers + noise smoothed over 20 cells, G = 10 at the largest slowness,
-    20-cell layer on all faces, source at the centre, real shift plus complex shift 0.03."""
+    20-cell layer on all faces, source at the centre; real shifts on both coarse grids plus a
+    complex shift of the preconditioner, W(1,1) cycle."""
     dim, G = 2, 10.0
     h = 1.0 / n
     sig = 20.0 * n / 1024.0 if n < 1024 else 20.0
     kap = layered_slowness((n, n), 8, sig, seed)
     L = 20 if n >= 128 else max(2, (20 * n) // 1024 + 2)
     return Problem("cfg2_2d_layered_%d" % n, dim, (n, n), h, kap, omega_for_G(G, h, kap.max()),
-                   ((L, L), (L, L)), SIGMA_MAX, alpha_for(dim, G), 0.03, [(n // 2, n // 2)], G)
+                   ((L, L), (L, L)), SIGMA_MAX, alpha_for(dim, G), CFG2_BETA, [(n // 2, n // 2)], G,
+                   alpha2=ALPHA2_STAR[(2, G)], nu_pre=1, nu_post=1)
 
 
 def config3(n: int = 256, seed: int = 3000) -> Problem:

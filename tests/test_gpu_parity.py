@@ -130,3 +130,21 @@ def test_edge_cases():
     x1, i1 = s.solve(p.rhs(), max_iter=3)
     x2, i2 = s.solve(p.rhs(), x0=x1, max_iter=200)
     assert i2["status"] == 0 and i2["true_rel_residual"] <= 1e-6
+
+
+def test_graph_replays_match_eager(monkeypatch):
+    """the per-iteration hipGraphs, replayed over several solves with eager work and host
+    synchronisation in between, give exactly the eager (uncaptured) result."""
+    p = small_problem(2, n=64, alpha2=1.03)
+    q = p.rhs()
+    monkeypatch.setenv("HELM_GRAPHS", "0")
+    se = from_problem(p, nu=(1, 1), cycle_prec="f32")
+    xe, ie = se.solve(q, tol=1e-6, max_iter=200)
+    monkeypatch.setenv("HELM_GRAPHS", "1")
+    sg = from_problem(p, nu=(1, 1), cycle_prec="f32")
+    for rep in range(3):
+        xg, ig = sg.solve(q, tol=1e-6, max_iter=200)
+        torch.cuda.synchronize()
+        _ = se.apply(xg)                       # eager work between replays
+        assert ig["iterations"] == ie["iterations"]
+        assert torch.equal(xg, xe), rep
