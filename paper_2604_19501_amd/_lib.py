@@ -9,6 +9,12 @@ import ctypes as C
 import os
 import re
 
+# PyTorch supplies device memory and streams and bundles its own HIP runtime
+# (soname libamdhip64.so.7).  Importing it first makes libhelm bind to that same
+# runtime instance; loading the system copy first would leave two HIP/HSA runtimes
+# in the process and the second one finds no device.
+import torch  # noqa: F401
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libhelm.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "helm.h")

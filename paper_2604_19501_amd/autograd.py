@@ -1,0 +1,75 @@
+"""Differentiable least-squares misfit of Helmholtz solves w.r.t. squared slowness.
+
+    loss = helmholtz_misfit(m, solver, sources, receivers, data, tol=1e-10)
+    loss.backward()          # m.grad = dL/dm
+
+For H(m) = -Lap_h - omega^2 m (1 - i sigma) (eq. (1.1) with the absorbing layer),
+sources q_s, receivers given as flat node indices (sampling operator P) and data d_s,
+
+    L(m) = 1/2 sum_s || P u_s - d_s ||^2,   H(m) u_s = q_s.
+
+The backward pass solves the adjoint systems H^H lambda_s = P^T (P u_s - d_s) with the
+same preconditioner on the conjugate-transpose operator (op = HELM_OP_C) and forms
+dL/dm_j = sum_s omega^2 Re(conj(lambda_s[j]) (1 - i sigma_j) u_s[j]) in the library's
+gradient kernel.  Every solve and the gradient run in libhelm; this module only
+orders the calls.
+"""
+from __future__ import annotations
+
+from typing import Sequence
+
+import torch
+
+from . import _lib as L
+from .solver import Solver
+
+
+class _Misfit(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, m, solver: Solver, sources, receivers, data, tol, max_iter):
+        solver.refactor(slowness=torch.sqrt(m.detach()).to(torch.float64))
+        us, res = [], []
+        loss = torch.zeros((), dtype=torch.float64, device=m.device)
+        for s, q in enumerate(sources):
+            u, info = solver.solve(q, tol=tol, max_iter=max_iter)
+            if info["status"] != 0:
+                raise L.HelmError(info["status"], "forward solve %d" % s)
+            r = u[receivers] - data[s]
+            loss = loss + 0.5 * torch.sum(r.real ** 2 + r.imag ** 2)
+            us.append(u)
+            res.append(r)
+        ctx.solver, ctx.us, ctx.res, ctx.receivers = solver, us, res, receivers
+        ctx.tol, ctx.max_iter, ctx.N = tol, max_iter, m.numel()
+        return loss
+
+    @staticmethod
+    def backward(ctx, gout):
+        solver = ctx.solver
+        lams = []
+        for s, r in enumerate(ctx.res):
+            rhs = torch.zeros(ctx.N, dtype=torch.complex128, device=r.device)
+            rhs.index_put_((ctx.receivers,), r, accumulate=True)
+            lam, info = solver.solve(rhs, tol=ctx.tol, max_iter=ctx.max_iter, op=L.HELM_OP_C)
+            if info["status"] != 0:
+                raise L.HelmError(info["status"], "adjoint solve %d" % s)
+            lams.append(lam)
+        g = solver.grad_m(ctx.us, lams)
+        return gout * g, None, None, None, None, None, None
+
+
+def helmholtz_misfit(m: torch.Tensor, solver: Solver, sources: Sequence[torch.Tensor], receivers: torch.Tensor,
+                     data: Sequence[torch.Tensor], tol: float = 1e-10, max_iter: int = 1000) -> torch.Tensor:
+    """L(m) = 1/2 sum_s ||P u_s - d_s||^2 with u_s = H(m)^{-1} q_s; differentiable in m (float64, N1)."""
+    return _Misfit.apply(m, solver, list(sources), receivers, list(data), tol, max_iter)
+
+
+class HelmholtzLoss(torch.nn.Module):
+    """module form of helmholtz_misfit for a fixed solver, source set, receiver set and data."""
+
+    def __init__(self, solver: Solver, sources, receivers, data, tol: float = 1e-10, max_iter: int = 1000):
+        super().__init__()
+        self.solver, self.sources, self.receivers, self.data = solver, list(sources), receivers, list(data)
+        self.tol, self.max_iter = tol, max_iter
+
+    def forward(self, m):
+        return helmholtz_misfit(m, self.solver, self.sources, self.receivers, self.data, self.tol, self.max_iter)

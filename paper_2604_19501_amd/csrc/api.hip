@@ -9,6 +9,7 @@
 #include <memory>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "krylov.h"
@@ -158,6 +159,7 @@ struct helm_ctx {
   size_t lds_limit = 65536;     // LDS bytes for substitution vectors
   size_t lds_panel = 0;         // LDS bytes for a resident factorisation panel (device maximum - 2 KB)
   std::vector<helm_ctx*> sub;   // batched form: one context per instance
+  std::vector<hipStream_t> bstreams;   // batched form: streams of the concurrent instances
   // one captured graph per (operator, Arnoldi index j): cycle on V_j + Arnoldi step
   hipStream_t cap = nullptr;    // library-owned stream used only for capture
   std::vector<hipGraphExec_t> gexec[2];
@@ -841,6 +843,7 @@ int helm_destroy(helm_ctx* ctx) {
   for (helm_ctx* q : ctx->sub) helm_destroy(q);
   drop_graphs(ctx);
   if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
+  for (hipStream_t t : ctx->bstreams) (void)hipStreamDestroy(t);
   if (ctx->hstate) (void)hipHostFree(ctx->hstate);
   delete ctx;
   return HELM_OK;
@@ -1055,16 +1058,59 @@ int helm_setup_batched(int n_inst, const helm_grid* grids, const double* const* 
 int helm_solve_batched(helm_ctx* ctx, int op, int n_rhs, const int* inst_of_rhs, const void* const* rhs,
                        void* const* x, double tol, int max_iter, helm_solve_info* info, void* stream) {
   if (!ctx || n_rhs < 1 || !inst_of_rhs || !rhs || !x) return fail(HELM_EINVAL, "bad arguments");
-  int ninst = ctx->sub.empty() ? 1 : (int)ctx->sub.size();
+  if (op != HELM_OP_N && op != HELM_OP_C) return fail(HELM_EINVAL, "op must be HELM_OP_N or HELM_OP_C");
+  const int ninst = ctx->sub.empty() ? 1 : (int)ctx->sub.size();
   for (int k = 0; k < n_rhs; ++k)
     if (inst_of_rhs[k] < 0 || inst_of_rhs[k] >= ninst || !rhs[k] || !x[k])
       return fail(HELM_EINVAL, "bad right-hand side %d", k);
+  hipStream_t s = (hipStream_t)stream;
+  // instances are independent: they run concurrently on library-owned streams (one host
+  // worker per stream); the right-hand sides of one instance run in order on its stream.
+  const int nst = std::max(1, std::min(env_int("HELM_BATCH_STREAMS", 8), ninst));
+  std::vector<int> status(n_rhs, HELM_OK);
+  std::vector<std::string> errs(nst);
+  try {
+    while ((int)ctx->bstreams.size() < nst) {
+      hipStream_t t;
+      CK(hipStreamCreateWithFlags(&t, hipStreamNonBlocking));
+      ctx->bstreams.push_back(t);
+    }
+    hipEvent_t ready;
+    CK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    CK(hipEventRecord(ready, s));
+    for (int w = 0; w < nst; ++w) CK(hipStreamWaitEvent(ctx->bstreams[w], ready, 0));
+    std::vector<std::thread> pool;
+    for (int w = 0; w < nst; ++w)
+      pool.emplace_back([&, w]() {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        for (int k = 0; k < n_rhs; ++k) {
+          if (inst_of_rhs[k] % nst != w) continue;
+          helm_ctx* c = ctx->sub.empty() ? ctx : ctx->sub[inst_of_rhs[k]];
+          status[k] = helm_solve(c, op, rhs[k], x[k], tol, max_iter, info ? &info[k] : nullptr, ctx->bstreams[w]);
+          if (status[k] < 0) {
+            errs[w] = helm_last_error();
+            return;
+          }
+        }
+      });
+    for (auto& t : pool) t.join();
+    for (int w = 0; w < nst; ++w) {
+      CK(hipEventRecord(ready, ctx->bstreams[w]));
+      CK(hipStreamWaitEvent(s, ready, 0));
+    }
+    CK(hipEventDestroy(ready));
+  } catch (DevErr& e) {
+    return fail(HELM_EDEVICE, "%s", e.what());
+  }
   int worst = HELM_OK;
   for (int k = 0; k < n_rhs; ++k) {
-    helm_ctx* c = ctx->sub.empty() ? ctx : ctx->sub[inst_of_rhs[k]];
-    int r = helm_solve(c, op, rhs[k], x[k], tol, max_iter, info ? &info[k] : nullptr, stream);
-    if (r < 0) return r;
-    worst = std::max(worst, r);
+    if (status[k] < 0) {
+      for (auto& e : errs)
+        if (!e.empty()) return fail(status[k], "%s", e.c_str());
+      return status[k];
+    }
+    worst = std::max(worst, status[k]);
   }
   return worst;
 }
