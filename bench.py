@@ -32,6 +32,25 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_2d_1024_layered.json")
+
+
+def measured_traffic(cls):
+    """HBM bytes per launch of a kernel class from the committed FETCH_SIZE/WRITE_SIZE runs.
+
+    The record stores the SHA-256 of the kernel sources it was taken on; once any of them
+    has changed the counters no longer describe the kernels and None is returned."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    for f, h in rec.get("source_sha256", {}).items():
+        path = os.path.join(ROOT, "paper_2604_19501_amd", "csrc", f)
+        if not os.path.exists(path) or hashlib.sha256(open(path, "rb").read()).hexdigest() != h:
+            return None
+    c = rec.get("classes", {}).get(cls)
+    return None if c is None else c["bytes_per_launch"]
 
 
 def workload(n):
@@ -63,20 +82,33 @@ def timed_steps(s, p, q, steps, warmup, refactor=True):
     return dt, its, info, x
 
 
-def bytes_model(cls, p, its_info):
-    """algorithmic HBM bytes of one launch of a kernel class (fine-node counts N1, N2, N3)."""
+def bytes_model(cls, p, info, iters, restart):
+    """algorithmic HBM bytes of one launch of a kernel class.
+
+    Per-unit figures: fine node N1, level-2 node N2, factor entry / update entry of the
+    coarsest elimination (info from helm_get_info), cb = bytes of a cycle complex."""
     d = p.dim
-    N1 = int(np.prod([k + 1 for k in p.n]))
-    N2 = int(np.prod([k // 2 + 1 for k in p.n]))
+    N1, N2, N3 = info["N1"], info["N2"], info["N3"]
+    cb = info["cycle_complex_bytes"]
     K = 3 ** d
-    if cls == "l1_restrict":      # b (c128) + m (f32) per fine node, r2 (c64) per level-2 node
-        return N1 * (16 + 4) + N2 * 8
-    if cls == "l1_sweep":         # b (c128) + m (f32) + z out (c64) per fine node, e2 (c64) per level-2 node
-        return N1 * (16 + 4 + 8) + N2 * 8
-    if cls == "l2_sweep":         # coefficients (c64 x K) + b2 + x in + x out (c64), e3 (c64) per level-3 node
-        return N2 * (8 * K + 8 * 3)
+    if cls == "l1_restrict":      # b (c128) + m (f32) per fine node, r2 per level-2 node
+        return N1 * (16 + 4) + N2 * cb
+    if cls == "l1_sweep":         # b (c128) + m (f32) + z out per fine node, e2 per level-2 node
+        return N1 * (16 + 4 + cb) + N2 * cb
+    if cls == "l2_sweep":         # coefficients (K) + b2 + x in + x out per level-2 node
+        return N2 * cb * (K + 3)
     if cls == "l2_restrict":      # coefficients + b2 + x per level-2 node
-        return N2 * (8 * K + 8 * 2)
+        return N2 * cb * (K + 2)
+    if cls == "nd_fwd":           # [A^-1; C A^-1] once, right-hand side gather, updates written and read
+        per_solve = (info["L_entries"] * cb + N3 * (cb + 4) + info["upd_entries"] * (2 * cb + 4) + N3 * cb)
+        return per_solve / info["fwd_launches"]
+    if cls == "nd_bwd":           # -A^-1 B once, boundary gather, g read and x written
+        per_solve = info["W_entries"] * cb + info["upd_entries"] * (cb + 4) + 2 * N3 * cb
+        return per_solve / max(1, info["bwd_launches"])
+    if cls == "arnoldi":          # apply (z, m, w) + three passes over V_0..V_j (FP64) + w traffic
+        js = [k % restart for k in range(iters)]
+        jm = sum(js) / max(1, len(js))
+        return N1 * (cb + 8 + 16 + 32 + 16 + 16 + 48 * (jm + 1))
     return None
 
 
@@ -105,6 +137,9 @@ def main():
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--pmc-pass", action="store_true",
+                    help="for hardware-counter runs: a 256 MiB device copy (calibrates FETCH_SIZE/WRITE_SIZE "
+                         "against known bytes) followed by one setup+solve step, no timing output")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the solver has no multi-GPU path (requested --gpus %d)" % args.gpus,
@@ -114,6 +149,17 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     p = workload(args.n)
     q = torch.from_numpy(p.rhs()).cuda()
+    if args.pmc_pass:
+        a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")      # 256 MiB
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        s32 = make_solver(p, "f32")
+        s32.refactor()
+        x, info = s32.solve(q, tol=p.tol, max_iter=2000)
+        torch.cuda.synchronize()
+        print(json.dumps({"pmc_pass": True, "iterations": info["iterations"], "copy_bytes": 2 * a.numel() * 8}))
+        return
     # mixed precision: FP32 cycle, FP64 FGMRES
     s32 = make_solver(p, "f32")
     dt, its, info, x = timed_steps(s32, p, q, args.steps, args.warmup)
@@ -125,6 +171,7 @@ def main():
     torch.cuda.synchronize()
     kt = s32.kernel_times()
     s32.set_timing(False)
+    sinfo = s32.info()
     # true residual recomputed by the library in FP64 on the final iterate
     res = info["true_rel_residual"]
     out = {
@@ -162,18 +209,21 @@ def main():
         out["speedup_mixed_vs_fp64"] = dt64 / dt
         out["speedup_mixed_vs_fp64_solve_only"] = dts64 / dt_solve
         s64.close()
-    # roofline of the dominant kernel class with a bytes model
+    # roofline of the dominant kernel class (by HIP-event time) with its algorithmic bytes
+    gbs = {}
+    for k, (ms, cnt) in kt.items():
+        B = bytes_model(k, p, sinfo, its[-1], p.restart)
+        if B is not None and cnt > 0 and ms > 0:
+            gbs[k] = B / (ms / cnt / 1e3) / 1e9
+    out["kernel_achieved_GBs"] = {k: round(v, 1) for k, v in gbs.items()}
     dom = max(kt.items(), key=lambda kv: kv[1][0])[0]
-    cand = [(k, v) for k, v in kt.items() if bytes_model(k, p, info) is not None and v[1] > 0]
-    rk, rv = max(cand, key=lambda kv: kv[1][0]) if cand else (None, None)
-    if rk is not None:
-        avg_s = rv[0] / rv[1] / 1e3
-        B = bytes_model(rk, p, info)
-        ach = B / avg_s / 1e9
-        out["roofline"] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": rk,
-                           "bytes_per_launch": B, "avg_launch_us": avg_s * 1e6,
-                           "dominant_class_by_time": dom}
+    ms, cnt = kt[dom]
+    B = bytes_model(dom, p, sinfo, its[-1], p.restart)
+    avg_s = ms / cnt / 1e3
+    out["roofline"] = {"bound": "hbm", "achieved": B / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": B / avg_s / 1e9 / HBM_PEAK_GBS, "traffic": measured_traffic(dom), "kernel": dom,
+                       "bytes_per_launch": B, "avg_launch_us": avg_s * 1e6,
+                       "share_of_instrumented_solve": ms / sum(v[0] for v in kt.values())}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, its[-1])
     print(json.dumps(out))

@@ -198,6 +198,15 @@ const char* helm_last_error(void);
 int helm_set_timing(helm_ctx* ctx, int on);
 int helm_get_timing(helm_ctx* ctx, double* t, int n);
 
+/* Sizes of a single-instance context (host integers), for bytes models and checks:
+ * [0] N1, [1] N2, [2] N3 unknowns per level, [3] fronts of the coarsest elimination,
+ * [4] entries of the forward factor blocks sum(nF*nS), [5] entries of the backward blocks
+ * sum(nS*nB), [6] update entries sum(nB), [7] separator entries sum(nS) (= N3),
+ * [8] forward and [9] backward substitution launches per coarsest solve, [10] workspace
+ * bytes, [11] largest front size nF, [12] bytes per complex of the cycle (8 or 16).
+ * Returns the number of entries written (at most n). */
+int helm_get_info(helm_ctx* ctx, long long* out, int n);
+
 /* Number of unknowns on level lev (1..3) of instance inst. */
 long long helm_level_size(helm_ctx* ctx, int inst, int lev);
 

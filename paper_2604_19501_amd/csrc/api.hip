@@ -963,6 +963,23 @@ int helm_get_timing(helm_ctx* c, double* t, int n) {
   return m;
 }
 
+int helm_get_info(helm_ctx* c, long long* out, int n) {
+  if (!c || !out || n < 0) return fail(HELM_EINVAL, "bad arguments");
+  if (!c->sub.empty()) return fail(HELM_EINVAL, "single-instance contexts only");
+  const NDPlan& P = c->plan;
+  long long sB = 0, maxF = 0;
+  for (const NDFrontDev& f : P.fronts) {
+    sB += f.nB;
+    maxF = std::max<long long>(maxF, f.nF);
+  }
+  long long v[13] = {c->g1.tot, c->g2.tot, c->g3.tot, (long long)P.fronts.size(), P.L_total, P.W_total, sB,
+                     c->g3.tot, (long long)P.fwd.size(), (long long)P.bwd.size(), (long long)c->ws_needed, maxF,
+                     (long long)c->csz};
+  int m = std::min(n, 13);
+  for (int i = 0; i < m; ++i) out[i] = v[i];
+  return m;
+}
+
 long long helm_level_size(helm_ctx* c, int inst, int lev) {
   if (!c || inst != 0) return -1;
   if (lev == 1) return c->g1.tot;

@@ -197,6 +197,14 @@ class Solver:
                                   self._s()), "helm_grad_m")
         return g
 
+    INFO_KEYS = ("N1", "N2", "N3", "fronts", "L_entries", "W_entries", "upd_entries", "sep_entries",
+                 "fwd_launches", "bwd_launches", "workspace_bytes", "max_front", "cycle_complex_bytes")
+
+    def info(self) -> dict:
+        v = (C.c_longlong * 13)()
+        L.check(L.lib.helm_get_info(self.ctx, v, 13), "helm_get_info")
+        return {k: int(v[i]) for i, k in enumerate(self.INFO_KEYS)}
+
     def set_timing(self, on: bool = True):
         L.lib.helm_set_timing(self.ctx, 1 if on else 0)
 
