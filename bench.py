@@ -105,10 +105,10 @@ def bytes_model(cls, p, info, iters, restart):
     if cls == "nd_bwd":           # -A^-1 B once, boundary gather, g read and x written
         per_solve = info["W_entries"] * cb + info["upd_entries"] * (cb + 4) + 2 * N3 * cb
         return per_solve / max(1, info["bwd_launches"])
-    if cls == "arnoldi":          # apply (z, m, w) + three passes over V_0..V_j (FP64) + w traffic
+    if cls == "arnoldi":          # two passes, each reading z, m and V_0..V_j; V_{j+1} written
         js = [k % restart for k in range(iters)]
         jm = sum(js) / max(1, len(js))
-        return N1 * (cb + 8 + 16 + 32 + 16 + 16 + 48 * (jm + 1))
+        return N1 * (2 * (cb + 8) + 16 + 32 * (jm + 1))
     return None
 
 

@@ -214,6 +214,38 @@ def alpha_star(kind: str, transfer: str, G: float, lo: float = 1.0, hi: float = 
     return best_a, best_e
 
 
+def level2_stencil(kind: str, transfer: str, kh: float, alpha2: float) -> np.ndarray:
+    """stencil of the level-2 Galerkin operator R1 H^alpha2 P1 (the second shift of Remark 4.1)."""
+    s = fine_stencil(kind, alpha2 * kh)
+    r, p = transfer_1d(transfer, 1)
+    return galerkin_stencil(s, r, p)
+
+
+def eg_level2(kind: str, transfer: str, G: float, alpha2: float, mode: str = "root",
+              r1=None) -> np.ndarray:
+    """grid-1-to-grid-2 analogue of eq. (4.8): e = r_2 / (2 r_1) - 1 over the sampled directions."""
+    dim = 2 if kind in ("p5", "c9") else 3
+    kh = 2.0 * math.pi / G
+    if r1 is None:
+        r1 = _fine_radii(kind, G, mode)
+    s2 = level2_stencil(kind, transfer, kh, alpha2)
+    r2 = np.array([ray_radius(s2, u, mode=mode) for u in directions(dim)])
+    return r2 / (2.0 * r1) - 1.0
+
+
+def alpha2_star(kind: str, transfer: str, G: float, lo: float = 1.0, hi: float = 1.1,
+                step: float = 5e-4, mode: str = "root"):
+    """(alpha2*, max |e|): the level-2 shift minimising the worst grid-1-to-grid-2 error."""
+    r1 = _fine_radii(kind, G, mode)
+    best_a, best_e = None, float("inf")
+    for a in lo + step * np.arange(int(round((hi - lo) / step)) + 1):
+        e = np.abs(eg_level2(kind, transfer, G, a, mode, r1))
+        v = float(np.max(e)) if np.all(np.isfinite(e)) else float("inf")
+        if v < best_e - 1e-15:
+            best_a, best_e = float(round(a, 6)), v
+    return best_a, best_e
+
+
 def ncrit_bounds(G: float, e: float) -> Tuple[float, float]:
     """eq. (4.9): G/(4 e_g) <= n_crit <= G/(2 e_g)."""
     return G / (4.0 * e), G / (2.0 * e)

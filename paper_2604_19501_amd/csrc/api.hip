@@ -144,7 +144,7 @@ struct helm_ctx {
   std::vector<long long> hlist_toff;
   std::vector<int> hlist;
   // Krylov
-  cd *V = nullptr, *W = nullptr, *part = nullptr;
+  cd *V = nullptr, *part = nullptr;
   void* Z = nullptr;
   KrylovState* st = nullptr;
   KrylovArgs ka;
@@ -321,9 +321,8 @@ size_t carve(helm_ctx* c, void* ws) {
   // Krylov
   c->V = cv.take<cd>((size_t)(m + 1) * g1.tot);
   c->Z = cv.take<char>(cs * (size_t)m * g1.tot);
-  c->W = cv.take<cd>(g1.tot);
   long long nblk = (g1.tot + 256 * KNPT - 1) / (256 * KNPT);
-  c->part = cv.take<cd>((size_t)(KMAXM + 2) * nblk);
+  c->part = cv.take<cd>((size_t)(2 * KMAXM + 3) * nblk);
   c->st = cv.take<KrylovState>(1);
   return cv.off;
 }
@@ -560,7 +559,6 @@ KrylovArgs make_kargs(helm_ctx* c, int op) {
   a.m64 = c->m64;
   a.V = c->V;
   a.ldv = c->g1.tot;
-  a.W = c->W;
   a.part = c->part;
   a.nblk = (int)((c->g1.tot + 256 * KNPT - 1) / (256 * KNPT));
   a.pcap = a.nblk;

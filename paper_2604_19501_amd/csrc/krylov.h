@@ -14,11 +14,13 @@ struct KrylovState {
   cd sn[KMAXM];
   cd g[KMAXM + 1];
   cd y[KMAXM];
-  cd h1[KMAXM + 2], h2[KMAXM + 2];
+  cd h1[2 * KMAXM + 3];          // sums of the dot pass: h1, Gram column, ||w||^2
+  cd c[KMAXM + 1];               // Hessenberg column before rotation (h1 + h2)
   cd tmp[2];
   double bnorm, beta0, est, hnext, true_rel;
   int its, done, nonfinite, pad;
   double hist[KMAXIT];
+  cd G[(KMAXM + 1) * (KMAXM + 1)];   // Gram matrix of the stored basis, leading dimension KMAXM + 1
 };
 
 struct KrylovArgs {
@@ -28,7 +30,6 @@ struct KrylovArgs {
   const double* m64;
   cd* V;          // basis, restart + 1 vectors
   long long ldv;
-  cd* W;          // work vector
   cd* part;       // partial sums, value-major: part[i * pcap + block]
   int pcap;
   int nblk;            // blocks of the node kernels = ceil(N / (256 * KNPT))

@@ -1,16 +1,22 @@
 // FP64 kernels of the outer right-preconditioned FGMRES (restarted).
 //
-// Per iteration j (basis V_0..V_j orthonormal, z_j = M^{-1} V_j from the cycle):
-//   k_apply_dot    w = H z_j (FP64), partial sums of h1_i = <V_i, w>
-//   k_fin_sum      h1 = sum of partials (one block per value)
-//   k_update_dot   w' = w - sum_i h1_i V_i, partial sums of h2_i = <V_i, w'> and ||w'||^2
-//   k_fin_sum      h2, ||w'||^2
-//   k_givens       H(:, j) = h1 + h2 (classical Gram-Schmidt with one re-orthogonalisation),
-//                  h_{j+1,j}^2 = ||w'||^2 - ||h2||^2, Givens rotation of the Hessenberg
-//                  column, residual estimate |g_{j+1}| / ||b||, convergence flag
-//   k_normalize    V_{j+1} = (w' - sum_i h2_i V_i) / h_{j+1,j}
-// Reductions are two-stage (per-block partials, then a fixed-order sum), so the
-// results are bitwise reproducible run to run.
+// Per iteration j (basis V_0..V_j, z_j = M^{-1} V_j from the cycle), two passes over
+// the basis:
+//   k_arnoldi_dots    w = H z_j (FP64) and, reading every V_i once, partial sums of
+//                     h1_i = <V_i, w>, the Gram column G_ij = <V_i, V_j> and ||w||^2
+//   k_fin_sum         the sums, in a fixed order
+//   k_givens          classical Gram-Schmidt with one re-orthogonalisation, the second
+//                     projection taken from the Gram matrix instead of a second pass:
+//                       h2 = V^H (w - V h1) = h1 - G h1,   c = h1 + h2 = H(:, j),
+//                       h_{j+1,j}^2 = ||w - V c||^2 = ||w||^2 - 2 Re(c^H h1) + c^H G c;
+//                     then the Givens rotation of the Hessenberg column, the residual
+//                     estimate |g_{j+1}| / ||b|| and the convergence flag
+//   k_arnoldi_update  V_{j+1} = (H z_j - V c) / h_{j+1,j}, recomputing H z_j (16 B per
+//                     node) instead of storing and reloading w (32 B per node)
+// Because G holds the inner products of the stored vectors, any loss of orthogonality
+// of V is corrected in the next column rather than accumulated.  Reductions are
+// two-stage (per-block partials, then a fixed-order sum), so the results are bitwise
+// reproducible run to run.
 #include <cstddef>
 
 #include "krylov.h"
@@ -63,28 +69,52 @@ __device__ __forceinline__ cd apply_h(const KrylovArgs& a, const CX* __restrict_
   return D * to_d(x[f]) - a.op.inv_h2 * nb;
 }
 
-// w = H z (FP64), partials of <V_i, w> for i <= j
+// wave-level partial sums of nv values, then one fixed-order sum over the 4 waves per value
+__device__ __forceinline__ void store_partials(cd (*red)[2 * KMAXM + 3], int nv, cd* part, int pcap) {
+  __syncthreads();
+  for (int t = threadIdx.x; t < nv; t += 256)
+    part[(long long)t * pcap + blockIdx.x] = (red[0][t] + red[1][t]) + (red[2][t] + red[3][t]);
+}
+
+// w = H z_j (FP64); partials of <V_i, w> (values 0..j), <V_i, V_j> (values j+1..2j+1) and
+// ||w||^2 (value 2j+2, real part)
 template <typename CZ>
-__global__ void __launch_bounds__(256) k_apply_dot(KrylovArgs a, const CZ* __restrict__ z, int j) {
-  __shared__ cd lds[4];
+__global__ void __launch_bounds__(256) k_arnoldi_dots(KrylovArgs a, const CZ* __restrict__ z, int j) {
+  __shared__ cd red[4][2 * KMAXM + 3];
   const long long N = a.op.g.tot;
-  cd w[KNPT];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  cd w[KNPT], vj[KNPT];
+  double nw = 0.0;
   for (int q = 0; q < KNPT; ++q) {
     long long f = node_of(q);
     w[q] = mk(0.0, 0.0);
+    vj[q] = mk(0.0, 0.0);
     if (f < N) {
       w[q] = apply_h(a, z, f);
-      a.W[f] = w[q];
+      vj[q] = a.V[(long long)j * a.ldv + f];
+      nw += abs2(w[q]);
     }
   }
   for (int i = 0; i <= j; ++i) {
-    cd v = mk(0.0, 0.0);
+    cd s1 = mk(0.0, 0.0), s2 = mk(0.0, 0.0);
     for (int q = 0; q < KNPT; ++q) {
       long long f = node_of(q);
-      if (f < N) v += cmulc(a.V[(long long)i * a.ldv + f], w[q]);
+      if (f < N) {
+        cd vi = i == j ? vj[q] : a.V[(long long)i * a.ldv + f];
+        s1 += cmulc(vi, w[q]);
+        s2 += cmulc(vi, vj[q]);
+      }
     }
-    block_sum(v, lds, a.part + (long long)i * a.pcap + blockIdx.x);
+    s1 = wsum(s1);
+    s2 = wsum(s2);
+    if (lane == 0) {
+      red[wv][i] = s1;
+      red[wv][j + 1 + i] = s2;
+    }
   }
+  cd t = wsum(mk(nw, 0.0));
+  if (lane == 0) red[wv][2 * j + 2] = t;
+  store_partials(red, 2 * j + 3, a.part, a.pcap);
 }
 
 // r = b - H x (FP64) into V_0; partials of (||r||^2, ||b||^2) in slot 0
@@ -113,37 +143,6 @@ __global__ void __launch_bounds__(256) k_fin_sum(KrylovArgs a, cd* dst) {
   block_sum(v, lds, dst + i);
 }
 
-// w' = w - sum h1_i V_i ; partials of <V_i, w'> (i <= j) and ||w'||^2 (value j+1, .x)
-__global__ void __launch_bounds__(256) k_update_dot(KrylovArgs a, int j) {
-  __shared__ cd lds[4];
-  __shared__ cd sh[KMAXM + 1];
-  if (threadIdx.x <= j) sh[threadIdx.x] = a.st->h1[threadIdx.x];
-  __syncthreads();
-  const long long N = a.op.g.tot;
-  cd w[KNPT];
-  double nw = 0.0;
-  for (int q = 0; q < KNPT; ++q) {
-    long long f = node_of(q);
-    w[q] = mk(0.0, 0.0);
-    if (f < N) {
-      cd t = a.W[f];
-      for (int i = 0; i <= j; ++i) t -= sh[i] * a.V[(long long)i * a.ldv + f];
-      a.W[f] = t;
-      w[q] = t;
-      nw += abs2(t);
-    }
-  }
-  for (int i = 0; i <= j; ++i) {
-    cd v = mk(0.0, 0.0);
-    for (int q = 0; q < KNPT; ++q) {
-      long long f = node_of(q);
-      if (f < N) v += cmulc(a.V[(long long)i * a.ldv + f], w[q]);
-    }
-    block_sum(v, lds, a.part + (long long)i * a.pcap + blockIdx.x);
-  }
-  block_sum(mk(nw, 0.0), lds, a.part + (long long)(j + 1) * a.pcap + blockIdx.x);
-}
-
 __device__ inline void givens(cd a, cd b, double& c, cd& s, cd& r) {
   double na = sqrt(abs2(a)), nb = sqrt(abs2(b));
   if (nb == 0.0) {
@@ -161,61 +160,113 @@ __device__ inline void givens(cd a, cd b, double& c, cd& s, cd& r) {
   r = t * ph;
 }
 
-// finish the Arnoldi column j and the Givens update (one thread)
-__global__ void k_givens(KrylovArgs a, int j, double tol) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// finish the Arnoldi column j and the Givens update (one wavefront); st->h1 holds the
+// sums of k_arnoldi_dots.  Lane i owns row i of the Gram products; the serial part
+// (rotations of the column) runs on lane 0 out of LDS.
+__global__ void __launch_bounds__(64) k_givens(KrylovArgs a, int j, double tol) {
+  __shared__ cd sh1[KMAXM + 1], sg[KMAXM + 1], sc[KMAXM + 1], col[KMAXM + 2], ssn[KMAXM];
+  __shared__ double scs[KMAXM], r1[64], r2[64];
   KrylovState* st = a.st;
-  const int ld = KMAXM + 1;
-  double nw2 = st->h2[j + 1].x;
-  double hh = 0.0;
-  for (int i = 0; i <= j; ++i) {
-    st->H[i + ld * j] = st->h1[i] + st->h2[i];
-    hh += abs2(st->h2[i]);
+  const int t = threadIdx.x, ld = KMAXM + 1;
+  for (int i = t; i <= j; i += 64) {
+    sh1[i] = st->h1[i];
+    sg[i] = st->h1[j + 1 + i];                 // G(i, j) = <V_i, V_j>
   }
-  double n2 = nw2 - hh;
-  double hn = n2 > 0.0 ? sqrt(n2) : 0.0;
-  st->H[j + 1 + ld * j] = mk(hn, 0.0);
-  st->hnext = hn;
-  for (int i = 0; i < j; ++i) {          // previous rotations on column j
-    cd hi = st->H[i + ld * j], hi1 = st->H[i + 1 + ld * j];
-    double c = st->cs[i];
-    cd s = st->sn[i];
-    st->H[i + ld * j] = c * hi + s * hi1;
-    st->H[i + 1 + ld * j] = c * hi1 - conjc(s) * hi;
+  for (int i = t; i < j; i += 64) {
+    scs[i] = st->cs[i];
+    ssn[i] = st->sn[i];
   }
-  double c;
-  cd s, r;
-  givens(st->H[j + ld * j], st->H[j + 1 + ld * j], c, s, r);
-  st->cs[j] = c;
-  st->sn[j] = s;
-  st->H[j + ld * j] = r;
-  st->H[j + 1 + ld * j] = mk(0.0, 0.0);
-  cd gj = st->g[j];
-  st->g[j + 1] = -(conjc(s) * gj);
-  st->g[j] = c * gj;
-  double est = sqrt(abs2(st->g[j + 1])) / st->bnorm;
-  st->est = est;
-  if (st->its < KMAXIT) st->hist[st->its] = est;
-  st->its += 1;
-  bool fin = isfinite(est) && isfinite(hn);
-  if (!fin) st->nonfinite = 1;
-  st->done = (est <= tol || !fin || hn == 0.0) ? 1 : 0;
+  __syncthreads();
+  // G(i, k): k < j from earlier columns, column / row j from this pass
+  auto gik = [&](int i, int k) -> cd {
+    if (k == j) return sg[i];
+    if (i == j) return conjc(sg[k]);
+    return st->G[i + ld * k];
+  };
+  // c = h1 + (h1 - G h1)
+  for (int i = t; i <= j; i += 64) {
+    cd gh = mk(0.0, 0.0);
+    for (int k = 0; k <= j; ++k) gh += gik(i, k) * sh1[k];
+    sc[i] = (sh1[i] + sh1[i]) - gh;
+  }
+  __syncthreads();
+  // Re(c^H h1) and c^H G c, per lane then summed in lane order
+  double p1 = 0.0, p2 = 0.0;
+  for (int i = t; i <= j; i += 64) {
+    cd gc = mk(0.0, 0.0);
+    for (int k = 0; k <= j; ++k) gc += gik(i, k) * sc[k];
+    p1 += sc[i].x * sh1[i].x + sc[i].y * sh1[i].y;
+    p2 += sc[i].x * gc.x + sc[i].y * gc.y;
+  }
+  r1[t] = p1;
+  r2[t] = p2;
+  for (int i = t; i <= j; i += 64) {          // store column / row j of G for later columns
+    st->G[i + ld * j] = sg[i];
+    st->G[j + ld * i] = conjc(sg[i]);
+  }
+  __syncthreads();
+  if (t == 0) {
+    double ch = 0.0, cgc = 0.0;
+    for (int i = 0; i < 64; ++i) {
+      ch += r1[i];
+      cgc += r2[i];
+    }
+    const double nw2 = st->h1[2 * j + 2].x;
+    const double n2 = nw2 - 2.0 * ch + cgc;     // ||w - V c||^2
+    const double hn = n2 > 0.0 ? sqrt(n2) : 0.0;
+    for (int i = 0; i <= j; ++i) col[i] = sc[i];
+    col[j + 1] = mk(hn, 0.0);
+    st->hnext = hn;
+    for (int i = 0; i < j; ++i) {             // previous rotations on column j
+      cd hi = col[i], hi1 = col[i + 1];
+      col[i] = scs[i] * hi + ssn[i] * hi1;
+      col[i + 1] = scs[i] * hi1 - conjc(ssn[i]) * hi;
+    }
+    double c;
+    cd s, r;
+    givens(col[j], col[j + 1], c, s, r);
+    st->cs[j] = c;
+    st->sn[j] = s;
+    col[j] = r;
+    col[j + 1] = mk(0.0, 0.0);
+    cd gj = st->g[j];
+    st->g[j + 1] = -(conjc(s) * gj);
+    st->g[j] = c * gj;
+    double est = sqrt(abs2(st->g[j + 1])) / st->bnorm;
+    st->est = est;
+    if (st->its < KMAXIT) st->hist[st->its] = est;
+    st->its += 1;
+    bool fin = isfinite(est) && isfinite(hn);
+    if (!fin) st->nonfinite = 1;
+    st->done = (est <= tol || !fin || hn == 0.0) ? 1 : 0;
+  }
+  __syncthreads();
+  for (int i = t; i <= j + 1; i += 64) st->H[i + ld * j] = col[i];
+  for (int i = t; i <= j; i += 64) st->c[i] = sc[i];
 }
 
-// V_{j+1} = (w' - sum h2_i V_i) / h_{j+1,j}
-__global__ void __launch_bounds__(256) k_normalize(KrylovArgs a, int j) {
-  __shared__ cd sh[KMAXM + 1];
+// V_{j+1} = (H z_j - sum_i c_i V_i) / h_{j+1,j}
+template <typename CZ>
+__global__ void __launch_bounds__(256) k_arnoldi_update(KrylovArgs a, const CZ* __restrict__ z, int j) {
+  __shared__ cd sc[KMAXM + 1];
   __shared__ double sinv;
-  if (threadIdx.x <= j) sh[threadIdx.x] = a.st->h2[threadIdx.x];
+  if (threadIdx.x <= j) sc[threadIdx.x] = a.st->c[threadIdx.x];
   if (threadIdx.x == 0) sinv = a.st->hnext > 0.0 ? 1.0 / a.st->hnext : 0.0;
   __syncthreads();
   const long long N = a.op.g.tot;
+  cd w[KNPT];
   for (int q = 0; q < KNPT; ++q) {
     long long f = node_of(q);
-    if (f >= N) continue;
-    cd w = a.W[f];
-    for (int i = 0; i <= j; ++i) w -= sh[i] * a.V[(long long)i * a.ldv + f];
-    a.V[(long long)(j + 1) * a.ldv + f] = sinv * w;
+    w[q] = f < N ? apply_h(a, z, f) : mk(0.0, 0.0);
+  }
+  for (int i = 0; i <= j; ++i)
+    for (int q = 0; q < KNPT; ++q) {
+      long long f = node_of(q);
+      if (f < N) w[q] -= sc[i] * a.V[(long long)i * a.ldv + f];
+    }
+  for (int q = 0; q < KNPT; ++q) {
+    long long f = node_of(q);
+    if (f < N) a.V[(long long)(j + 1) * a.ldv + f] = sinv * w[q];
   }
 }
 
@@ -300,14 +351,15 @@ void kr_scale_v0(const KrylovArgs& a, hipStream_t s) {
 void kr_arnoldi(const KrylovArgs& a, const void* z, int z_f32, int j, double tol, hipStream_t s) {
   dim3 g(a.nblk);
   if (z_f32)
-    hipLaunchKernelGGL((k_apply_dot<cf>), g, dim3(256), 0, s, a, (const cf*)z, j);
+    hipLaunchKernelGGL((k_arnoldi_dots<cf>), g, dim3(256), 0, s, a, (const cf*)z, j);
   else
-    hipLaunchKernelGGL((k_apply_dot<cd>), g, dim3(256), 0, s, a, (const cd*)z, j);
-  hipLaunchKernelGGL(k_fin_sum, dim3(j + 1), dim3(256), 0, s, a, st_field(a, offsetof(KrylovState, h1)));
-  hipLaunchKernelGGL(k_update_dot, g, dim3(256), 0, s, a, j);
-  hipLaunchKernelGGL(k_fin_sum, dim3(j + 2), dim3(256), 0, s, a, st_field(a, offsetof(KrylovState, h2)));
-  hipLaunchKernelGGL(k_givens, dim3(1), dim3(1), 0, s, a, j, tol);
-  hipLaunchKernelGGL(k_normalize, g, dim3(256), 0, s, a, j);
+    hipLaunchKernelGGL((k_arnoldi_dots<cd>), g, dim3(256), 0, s, a, (const cd*)z, j);
+  hipLaunchKernelGGL(k_fin_sum, dim3(2 * j + 3), dim3(256), 0, s, a, st_field(a, offsetof(KrylovState, h1)));
+  hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, s, a, j, tol);
+  if (z_f32)
+    hipLaunchKernelGGL((k_arnoldi_update<cf>), g, dim3(256), 0, s, a, (const cf*)z, j);
+  else
+    hipLaunchKernelGGL((k_arnoldi_update<cd>), g, dim3(256), 0, s, a, (const cd*)z, j);
 }
 void kr_update_x(const KrylovArgs& a, const void* Z, int z_f32, long long ldz, int k, cd* x, hipStream_t s) {
   hipLaunchKernelGGL(k_solve_y, dim3(1), dim3(1), 0, s, a, k);

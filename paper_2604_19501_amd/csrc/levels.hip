@@ -27,7 +27,7 @@ __device__ __forceinline__ long long xcd_block(long long nblocks) {
   long long per = (nblocks + 7) / 8;
   long long xcd = b % 8, k = b / 8;
   long long lb = xcd * per + k;
-  return lb;   // may exceed nblocks - 1: caller bounds-checks the node index
+  return lb;   // may exceed nblocks - 1: caller bounds-checks
 }
 
 __device__ __forceinline__ void decode(const Geom& g, long long f, int& i0, int& i1, int& i2) {
@@ -37,136 +37,230 @@ __device__ __forceinline__ void decode(const Geom& g, long long f, int& i0, int&
   i2 = (int)(r / g.N[1]);
 }
 
-// P e at fine node (i0,i1,i2): d-linear interpolation of the coarse vector e
-template <typename C>
-__device__ __forceinline__ C prolong_at(const Geom& gc, const C* __restrict__ e, int i0, int i1, int i2,
-                                        int dim) {
-  int lo[3], hi[3];
-  int ii[3] = {i0, i1, i2};
-  for (int a = 0; a < 3; ++a) {
-    lo[a] = ii[a] >> 1;
-    hi[a] = (ii[a] + 1) >> 1;
+__device__ __forceinline__ bool inside(const Geom& g, int i0, int i1, int i2) {
+  return i0 >= 0 && i0 <= g.n[0] && i1 >= 0 && i1 <= g.n[1] && i2 >= 0 && i2 <= g.n[2];
+}
+__device__ __forceinline__ long long flat(const Geom& g, int i0, int i1, int i2) {
+  return i0 + (long long)g.N[0] * (i1 + (long long)g.N[1] * i2);
+}
+
+// ----------------------------------------------------------------------------
+// Tiled kernels.  A block owns a box of output nodes.  It stages in LDS
+//   * the coarse correction e on the box's coarse footprint (sweeps with XIN_E),
+//   * the virtual input iterate x_in on the box plus a one-node halo,
+//   * for restrictions, the residual b - A x_in on the (2c+1)^d fine footprint,
+// so every x_in and every residual is evaluated once per node (plus the halo)
+// and every global array is read with x-consecutive lanes.  Nodes outside the
+// grid are stored as zero, which is the operator's boundary condition (zero
+// values one node outside); the stored coarse coefficients that point outside
+// are zero as well.
+//
+// Box shapes (threads = 256):
+//   sweeps       2D 32 x 16            3D 32 x 8 x 4
+//   restrictions 2D 16 x 8 coarse      3D 16 x 4 x 4 coarse (8 x 4 x 4 in FP64)
+template <int DIM> struct SBox {
+  static constexpr int x = 32, y = DIM == 2 ? 16 : 8, z = DIM == 2 ? 1 : 4;
+};
+template <int DIM, int CSZ> struct RBox {
+  static constexpr int x = DIM == 2 ? 16 : (CSZ == 8 ? 16 : 8), y = DIM == 2 ? 8 : 4, z = DIM == 2 ? 1 : 4;
+};
+
+// level-1 operator H_s with x from LDS (centre index k, strides sy, sz)
+template <int DIM, typename R>
+struct Op1 {
+  typedef R Real;
+  typedef typename cplx<R>::type C;
+  L1<R> A;
+  __host__ __device__ __forceinline__ const Geom& geom() const { return A.op.g; }
+  __device__ __forceinline__ C diag(long long f, int i0, int i1, int i2) const { return A.diag(f, i0, i1, i2); }
+  __device__ __forceinline__ C ax(const C* xs, int k, int sy, int sz, long long, C D) const {
+    C nb = (xs[k - 1] + xs[k + 1]) + (xs[k - sy] + xs[k + sy]);
+    if (DIM == 3) nb += xs[k - sz] + xs[k + sz];
+    return D * xs[k] - (R)A.op.inv_h2 * nb;
   }
-  C acc = mk((decltype(acc.x))0, (decltype(acc.x))0);
-  typedef decltype(acc.x) R;
-  if (dim == 2) {
-    R w0 = (lo[0] == hi[0]) ? (R)1 : (R)0.5, w1 = (lo[1] == hi[1]) ? (R)1 : (R)0.5;
-    for (int b1 = 0; b1 < (lo[1] == hi[1] ? 1 : 2); ++b1)
-      for (int b0 = 0; b0 < (lo[0] == hi[0] ? 1 : 2); ++b0) {
-        int c0 = b0 ? hi[0] : lo[0], c1 = b1 ? hi[1] : lo[1];
-        acc += (w0 * w1) * e[c0 + (long long)gc.N[0] * c1];
-      }
-  } else {
-    R w0 = (lo[0] == hi[0]) ? (R)1 : (R)0.5, w1 = (lo[1] == hi[1]) ? (R)1 : (R)0.5,
-      w2 = (lo[2] == hi[2]) ? (R)1 : (R)0.5;
-    for (int b2 = 0; b2 < (lo[2] == hi[2] ? 1 : 2); ++b2)
-      for (int b1 = 0; b1 < (lo[1] == hi[1] ? 1 : 2); ++b1)
-        for (int b0 = 0; b0 < (lo[0] == hi[0] ? 1 : 2); ++b0) {
-          int c0 = b0 ? hi[0] : lo[0], c1 = b1 ? hi[1] : lo[1], c2 = b2 ? hi[2] : lo[2];
-          acc += (w0 * w1 * w2) * e[c0 + (long long)gc.N[0] * (c1 + (long long)gc.N[1] * c2)];
+};
+
+// level-2 Galerkin operator (3^d stored coefficients per node)
+template <int DIM, typename R>
+struct Op2 {
+  typedef R Real;
+  typedef typename cplx<R>::type C;
+  L2<R> A;
+  __host__ __device__ __forceinline__ const Geom& geom() const { return A.g; }
+  __device__ __forceinline__ C diag(long long f, int, int, int) const { return A.get(DIM == 2 ? 4 : 13, f); }
+  __device__ __forceinline__ C ax(const C* xs, int k, int sy, int sz, long long f, C D) const {
+    C acc = D * xs[k];
+#pragma unroll
+    for (int d2 = (DIM == 3 ? -1 : 0); d2 <= (DIM == 3 ? 1 : 0); ++d2)
+#pragma unroll
+      for (int d1 = -1; d1 <= 1; ++d1)
+#pragma unroll
+        for (int d0 = -1; d0 <= 1; ++d0) {
+          if (d0 == 0 && d1 == 0 && d2 == 0) continue;
+          const int kk = (d0 + 1) + 3 * (d1 + 1) + (DIM == 3 ? 9 * (d2 + 1) : 0);
+          acc += A.get(kk, f) * xs[k + d0 + sy * d1 + sz * d2];
         }
+    return acc;
   }
-  return acc;
-}
+};
 
-// virtual iterate at a level-1 node
-template <typename R, typename CB, int XIN>
-__device__ __forceinline__ typename cplx<R>::type xin_l1(const L1<R>& A, const typename cplx<R>::type* __restrict__ x,
-                                                        const CB* __restrict__ b, R w, const Geom& gc,
-                                                        const typename cplx<R>::type* __restrict__ e,
-                                                        long long f, int i0, int i1, int i2) {
-  typedef typename cplx<R>::type C;
-  C v = mk((R)0, (R)0);
-  if (XIN & XIN_X) v += x[f];
-  if (XIN & XIN_Z) {
-    C d = A.diag(f, i0, i1, i2);
-    v += w * cdiv(conv<C>::from(b[f]), d);
+// d-linear interpolation of the staged coarse vector at fine node (i0,i1,i2); a
+// coordinate on a coarse node reads the same value twice with weight 1/2 each,
+// which is exact
+template <int DIM, typename C>
+__device__ __forceinline__ C prolong_lds(const C* es, int ex, int ey, int c0, int c1, int c2, int i0, int i1,
+                                         int i2) {
+  typedef decltype(es[0].x) R;
+  const int l0 = (i0 >> 1) - c0, h0 = ((i0 + 1) >> 1) - c0;
+  const int l1 = (i1 >> 1) - c1, h1 = ((i1 + 1) >> 1) - c1;
+  if (DIM == 2) {
+    C v = (es[l0 + ex * l1] + es[h0 + ex * l1]) + (es[l0 + ex * h1] + es[h0 + ex * h1]);
+    return (R)0.25 * v;
+  } else {
+    const int l2 = (i2 >> 1) - c2, h2 = ((i2 + 1) >> 1) - c2;
+    const int pl = ex * ey * l2, ph = ex * ey * h2;
+    C v = ((es[l0 + ex * l1 + pl] + es[h0 + ex * l1 + pl]) + (es[l0 + ex * h1 + pl] + es[h0 + ex * h1 + pl])) +
+          ((es[l0 + ex * l1 + ph] + es[h0 + ex * l1 + ph]) + (es[l0 + ex * h1 + ph] + es[h0 + ex * h1 + ph]));
+    return (R)0.125 * v;
   }
-  if (XIN & XIN_E) v += prolong_at(gc, e, i0, i1, i2, A.op.g.dim);
-  return v;
 }
 
-// (A x_in)(f) and D(f) for the level-1 operator
-template <typename R, typename CB, int XIN>
-__device__ __forceinline__ void apply_l1(const L1<R>& A, const typename cplx<R>::type* __restrict__ x,
-                                         const CB* __restrict__ b, R w, const Geom& gc,
-                                         const typename cplx<R>::type* __restrict__ e, long long f, int i0,
-                                         int i1, int i2, typename cplx<R>::type& Ax,
-                                         typename cplx<R>::type& xc, typename cplx<R>::type& D) {
-  typedef typename cplx<R>::type C;
-  const Geom& g = A.op.g;
-  D = A.diag(f, i0, i1, i2);
-  xc = xin_l1<R, CB, XIN>(A, x, b, w, gc, e, f, i0, i1, i2);
-  C nb = mk((R)0, (R)0);
-  long long s1 = g.N[0], s2 = (long long)g.N[0] * g.N[1];
-  if (i0 > 0) nb += xin_l1<R, CB, XIN>(A, x, b, w, gc, e, f - 1, i0 - 1, i1, i2);
-  if (i0 < g.n[0]) nb += xin_l1<R, CB, XIN>(A, x, b, w, gc, e, f + 1, i0 + 1, i1, i2);
-  if (i1 > 0) nb += xin_l1<R, CB, XIN>(A, x, b, w, gc, e, f - s1, i0, i1 - 1, i2);
-  if (i1 < g.n[1]) nb += xin_l1<R, CB, XIN>(A, x, b, w, gc, e, f + s1, i0, i1 + 1, i2);
-  if (g.dim == 3) {
-    if (i2 > 0) nb += xin_l1<R, CB, XIN>(A, x, b, w, gc, e, f - s2, i0, i1, i2 - 1);
-    if (i2 < g.n[2]) nb += xin_l1<R, CB, XIN>(A, x, b, w, gc, e, f + s2, i0, i1, i2 + 1);
+struct TileGrid {
+  int nt[3];
+  long long ntiles;
+};
+
+__device__ __forceinline__ bool tile_origin(const TileGrid& tg, int bx, int by, int bz, int& o0, int& o1,
+                                           int& o2) {
+  long long t = xcd_block(tg.ntiles);
+  if (t >= tg.ntiles) return false;
+  o0 = (int)(t % tg.nt[0]) * bx;
+  long long q = t / tg.nt[0];
+  o1 = (int)(q % tg.nt[1]) * by;
+  o2 = (int)(q / tg.nt[1]) * bz;
+  return true;
+}
+
+// stage x_in on the box [s0, s0+SX) x [s1, s1+SY) x [s2, s2+SZ)
+template <int DIM, int XIN, class Op, typename C, typename CB, typename R>
+__device__ __forceinline__ void stage_xin(const Op& op, const C* __restrict__ x, const CB* __restrict__ b, R w_in,
+                                          const C* es, int ex, int ey, int c0, int c1, int c2, int s0, int s1,
+                                          int s2, int SX, int SY, int SZ, C* xs) {
+  const Geom& g = op.geom();
+  const int tot = SX * SY * SZ;
+  for (int k = threadIdx.x; k < tot; k += 256) {
+    const int a = k % SX, q = k / SX;
+    const int i0 = s0 + a, i1 = s1 + q % SY, i2 = s2 + q / SY;
+    C v = mk((R)0, (R)0);
+    if (inside(g, i0, i1, i2)) {
+      const long long f = flat(g, i0, i1, i2);
+      if (XIN & XIN_X) v += x[f];
+      if (XIN & XIN_Z) v += w_in * cdiv(conv<C>::from(b[f]), op.diag(f, i0, i1, i2));
+      if (XIN & XIN_E) v += prolong_lds<DIM>(es, ex, ey, c0, c1, c2, i0, i1, i2);
+    }
+    xs[k] = v;
   }
-  R ih = (R)A.op.inv_h2;
-  Ax = D * xc - ih * nb;
 }
 
-// x_out = x_in + w D^{-1}(b - A x_in)   (w = 0: just materialise x_in)
-template <typename R, typename CB, typename CO, int XIN>
-__global__ void __launch_bounds__(256) k_l1_sweep(L1<R> A, const typename cplx<R>::type* __restrict__ x,
-                                                  const CB* __restrict__ b, R w_in, Geom gc,
-                                                  const typename cplx<R>::type* __restrict__ e, R w,
-                                                  CO* __restrict__ out) {
-  typedef typename cplx<R>::type C;
-  const Geom& g = A.op.g;
-  long long nb = (g.tot + 255) / 256;
-  long long f = xcd_block(nb) * 256 + threadIdx.x;
-  if (f >= g.tot) return;
-  int i0, i1, i2;
-  decode(g, f, i0, i1, i2);
-  C Ax, xc, D;
-  apply_l1<R, CB, XIN>(A, x, b, w_in, gc, e, f, i0, i1, i2, Ax, xc, D);
-  C r = conv<C>::from(b[f]) - Ax;
-  C y = xc + w * cdiv(r, D);
-  out[f] = conv<CO>::from(y);
+// x_out = x_in + w D^{-1}(b - A x_in) on one box (w = 0: materialise x_in)
+template <int DIM, class Op, typename CB, typename CO, int XIN>
+__global__ void __launch_bounds__(256) k_sweep(Op op, const typename Op::C* __restrict__ x,
+                                               const CB* __restrict__ b, typename Op::Real w_in, Geom gc,
+                                               const typename Op::C* __restrict__ e,
+                                               typename Op::Real w, CO* __restrict__ out, TileGrid tg) {
+  typedef typename Op::C C;
+  typedef typename Op::Real R;
+  constexpr int TX = SBox<DIM>::x, TY = SBox<DIM>::y, TZ = SBox<DIM>::z;
+  constexpr int SX = TX + 2, SY = TY + 2, SZ = DIM == 3 ? TZ + 2 : 1;
+  constexpr int EX = TX / 2 + 3, EY = TY / 2 + 3, EZ = DIM == 3 ? TZ / 2 + 3 : 1;
+  __shared__ C xs[SX * SY * SZ];
+  __shared__ C es[(XIN & XIN_E) ? EX * EY * EZ : 1];
+  const Geom& g = op.geom();
+  int o0, o1, o2;
+  if (!tile_origin(tg, TX, TY, TZ, o0, o1, o2)) return;
+  const int s0 = o0 - 1, s1 = o1 - 1, s2 = DIM == 3 ? o2 - 1 : 0;
+  const int c0 = s0 >> 1, c1 = s1 >> 1, c2 = s2 >> 1;   // floor: s may be -1
+  if (XIN & XIN_E) {
+    for (int k = threadIdx.x; k < EX * EY * EZ; k += 256) {
+      const int a = k % EX, q = k / EX;
+      const int j0 = c0 + a, j1 = c1 + q % EY, j2 = (DIM == 3 ? c2 : 0) + q / EY;
+      C v = mk((R)0, (R)0);
+      if (inside(gc, j0, j1, j2)) v = e[flat(gc, j0, j1, j2)];
+      es[k] = v;
+    }
+    __syncthreads();
+  }
+  stage_xin<DIM, XIN>(op, x, b, w_in, es, EX, EY, c0, c1, c2, s0, s1, s2, SX, SY, SZ, xs);
+  __syncthreads();
+  for (int k = threadIdx.x; k < TX * TY * TZ; k += 256) {
+    const int a = k % TX, q = k / TX;
+    const int i0 = o0 + a, i1 = o1 + q % TY, i2 = o2 + q / TY;
+    if (!inside(g, i0, i1, i2)) continue;
+    const long long f = flat(g, i0, i1, i2);
+    const int kk = (a + 1) + SX * ((q % TY + 1) + SY * (DIM == 3 ? q / TY + 1 : 0));
+    const C D = op.diag(f, i0, i1, i2);
+    const C r = conv<C>::from(b[f]) - op.ax(xs, kk, SX, SX * SY, f, D);
+    out[f] = conv<CO>::from(xs[kk] + w * cdiv(r, D));
+  }
 }
 
-// b2(I) = sum_f R(I, f) (b - A x_in)(f), full weighting [1 2 1]/4 per axis
-template <typename R, typename CB, int XIN>
-__global__ void __launch_bounds__(256) k_l1_restrict(L1<R> A, const typename cplx<R>::type* __restrict__ x,
-                                                     const CB* __restrict__ b, R w_in, Geom gc,
-                                                     const typename cplx<R>::type* __restrict__ e,
-                                                     Geom g2, typename cplx<R>::type* __restrict__ b2) {
-  typedef typename cplx<R>::type C;
-  const Geom& g = A.op.g;
-  long long nb = (g2.tot + 255) / 256;
-  long long I = xcd_block(nb) * 256 + threadIdx.x;
-  if (I >= g2.tot) return;
-  int I0, I1, I2;
-  decode(g2, I, I0, I1, I2);
-  C acc = mk((R)0, (R)0);
-  int r2 = g.dim == 3 ? 1 : 0;
-  for (int o2 = -r2; o2 <= r2; ++o2) {
-    int f2 = 2 * I2 + o2;
-    if (f2 < 0 || f2 > g.n[2]) continue;
-    R w2 = (g.dim == 3) ? (o2 == 0 ? (R)0.5 : (R)0.25) : (R)1;
-    for (int o1 = -1; o1 <= 1; ++o1) {
-      int f1 = 2 * I1 + o1;
-      if (f1 < 0 || f1 > g.n[1]) continue;
-      R w1 = o1 == 0 ? (R)0.5 : (R)0.25;
-      for (int o0 = -1; o0 <= 1; ++o0) {
-        int f0 = 2 * I0 + o0;
-        if (f0 < 0 || f0 > g.n[0]) continue;
-        R w0 = o0 == 0 ? (R)0.5 : (R)0.25;
-        long long f = f0 + (long long)g.N[0] * (f1 + (long long)g.N[1] * f2);
-        C Ax, xc, D;
-        apply_l1<R, CB, XIN>(A, x, b, w_in, gc, e, f, f0, f1, f2, Ax, xc, D);
-        C r = conv<C>::from(b[f]) - Ax;
-        acc += (w0 * w1 * w2) * r;
+// b_c(I) = sum_f R(I, f) (b - A x_in)(f), full weighting [1 2 1]/4 per axis, one coarse box
+template <int DIM, class Op, typename CB, int XIN>
+__global__ void __launch_bounds__(256) k_restrict(Op op, const typename Op::C* __restrict__ x,
+                                                  const CB* __restrict__ b, typename Op::Real w_in,
+                                                  Geom g2, typename Op::C* __restrict__ b2, TileGrid tg) {
+  typedef typename Op::C C;
+  typedef typename Op::Real R;
+  constexpr int CX = RBox<DIM, sizeof(C)>::x, CY = RBox<DIM, sizeof(C)>::y, CZ = RBox<DIM, sizeof(C)>::z;
+  constexpr int RX = 2 * CX + 1, RY = 2 * CY + 1, RZ = DIM == 3 ? 2 * CZ + 1 : 1;
+  constexpr int SX = RX + 2, SY = RY + 2, SZ = DIM == 3 ? RZ + 2 : 1;
+  __shared__ C xs[XIN ? SX * SY * SZ : 1];
+  __shared__ C rs[RX * RY * RZ];
+  const Geom& g = op.geom();
+  int O0, O1, O2;
+  if (!tile_origin(tg, CX, CY, CZ, O0, O1, O2)) return;
+  const int r0 = 2 * O0 - 1, r1 = 2 * O1 - 1, r2 = DIM == 3 ? 2 * O2 - 1 : 0;
+  if (XIN) {
+    stage_xin<DIM, XIN>(op, x, b, w_in, (const C*)nullptr, 1, 1, 0, 0, 0, r0 - 1, r1 - 1,
+                        DIM == 3 ? r2 - 1 : 0, SX, SY, SZ, xs);
+    __syncthreads();
+  }
+  for (int k = threadIdx.x; k < RX * RY * RZ; k += 256) {
+    const int a = k % RX, q = k / RX;
+    const int i0 = r0 + a, i1 = r1 + q % RY, i2 = r2 + q / RY;
+    C v = mk((R)0, (R)0);
+    if (inside(g, i0, i1, i2)) {
+      const long long f = flat(g, i0, i1, i2);
+      v = conv<C>::from(b[f]);
+      if (XIN) {
+        const int kk = (a + 1) + SX * ((q % RY + 1) + SY * (DIM == 3 ? q / RY + 1 : 0));
+        v -= op.ax(xs, kk, SX, SX * SY, f, op.diag(f, i0, i1, i2));
       }
     }
+    rs[k] = v;
   }
-  b2[I] = acc;
+  __syncthreads();
+  for (int k = threadIdx.x; k < CX * CY * CZ; k += 256) {
+    const int a = k % CX, q = k / CX, bb = q % CY, cc = q / CY;
+    const int I0 = O0 + a, I1 = O1 + bb, I2 = O2 + cc;
+    if (!inside(g2, I0, I1, I2)) continue;
+    C acc = mk((R)0, (R)0);
+#pragma unroll
+    for (int d2 = (DIM == 3 ? -1 : 0); d2 <= (DIM == 3 ? 1 : 0); ++d2) {
+      const R w2 = DIM == 3 ? (d2 == 0 ? (R)0.5 : (R)0.25) : (R)1;
+#pragma unroll
+      for (int d1 = -1; d1 <= 1; ++d1) {
+        const R w1 = d1 == 0 ? (R)0.5 : (R)0.25;
+#pragma unroll
+        for (int d0 = -1; d0 <= 1; ++d0) {
+          const R w0 = d0 == 0 ? (R)0.5 : (R)0.25;
+          const int kk = (2 * a + 1 + d0) + RX * ((2 * bb + 1 + d1) + RY * (DIM == 3 ? 2 * cc + 1 + d2 : 0));
+          acc += (w0 * w1 * w2) * rs[kk];
+        }
+      }
+    }
+    b2[flat(g2, I0, I1, I2)] = acc;
+  }
 }
 
 // y = A x for the outer operator (FP64 arithmetic), x in c64 or c128
@@ -216,102 +310,6 @@ __global__ void __launch_bounds__(256) k_l1_apply32(L1<float> A, const cf* __res
   y[f] = D * x[f] - (float)A.op.inv_h2 * nbs;
 }
 
-template <typename R, int XIN>
-__device__ __forceinline__ typename cplx<R>::type xin_l2(const L2<R>& A, const typename cplx<R>::type* __restrict__ x,
-                                                        const typename cplx<R>::type* __restrict__ b, R w,
-                                                        const Geom& gc, const typename cplx<R>::type* __restrict__ e,
-                                                        long long f, int i0, int i1, int i2) {
-  typedef typename cplx<R>::type C;
-  C v = mk((R)0, (R)0);
-  if (XIN & XIN_X) v += x[f];
-  if (XIN & XIN_Z) v += w * cdiv(b[f], A.get(A.center(), f));
-  if (XIN & XIN_E) v += prolong_at(gc, e, i0, i1, i2, A.g.dim);
-  return v;
-}
-
-template <typename R, int XIN>
-__device__ __forceinline__ void apply_l2(const L2<R>& A, const typename cplx<R>::type* __restrict__ x,
-                                         const typename cplx<R>::type* __restrict__ b, R w_in, const Geom& gc,
-                                         const typename cplx<R>::type* __restrict__ e, long long f, int i0,
-                                         int i1, int i2, typename cplx<R>::type& Ax,
-                                         typename cplx<R>::type& xc, typename cplx<R>::type& D) {
-  typedef typename cplx<R>::type C;
-  const Geom& g = A.g;
-  Ax = mk((R)0, (R)0);
-  int r2 = g.dim == 3 ? 1 : 0;
-  for (int d2 = -r2; d2 <= r2; ++d2) {
-    int j2 = i2 + d2;
-    if (j2 < 0 || j2 > g.n[2]) continue;
-    for (int d1 = -1; d1 <= 1; ++d1) {
-      int j1 = i1 + d1;
-      if (j1 < 0 || j1 > g.n[1]) continue;
-      for (int d0 = -1; d0 <= 1; ++d0) {
-        int j0 = i0 + d0;
-        if (j0 < 0 || j0 > g.n[0]) continue;
-        int k = (d0 + 1) + 3 * (d1 + 1) + (g.dim == 3 ? 9 * (d2 + 1) : 0);
-        long long j = j0 + (long long)g.N[0] * (j1 + (long long)g.N[1] * j2);
-        C xj = xin_l2<R, XIN>(A, x, b, w_in, gc, e, j, j0, j1, j2);
-        if (k == A.center()) xc = xj;
-        Ax += A.get(k, f) * xj;
-      }
-    }
-  }
-  D = A.get(A.center(), f);
-}
-
-template <typename R, int XIN>
-__global__ void __launch_bounds__(256) k_l2_sweep(L2<R> A, const typename cplx<R>::type* __restrict__ x,
-                                                  const typename cplx<R>::type* __restrict__ b, R w_in, Geom gc,
-                                                  const typename cplx<R>::type* __restrict__ e, R w,
-                                                  typename cplx<R>::type* __restrict__ out) {
-  typedef typename cplx<R>::type C;
-  const Geom& g = A.g;
-  long long nb = (g.tot + 255) / 256;
-  long long f = xcd_block(nb) * 256 + threadIdx.x;
-  if (f >= g.tot) return;
-  int i0, i1, i2;
-  decode(g, f, i0, i1, i2);
-  C Ax, xc, D;
-  apply_l2<R, XIN>(A, x, b, w_in, gc, e, f, i0, i1, i2, Ax, xc, D);
-  out[f] = xc + w * cdiv(b[f] - Ax, D);
-}
-
-template <typename R, int XIN>
-__global__ void __launch_bounds__(256) k_l2_restrict(L2<R> A, const typename cplx<R>::type* __restrict__ x,
-                                                     const typename cplx<R>::type* __restrict__ b, R w_in,
-                                                     Geom gc, const typename cplx<R>::type* __restrict__ e,
-                                                     Geom g3, typename cplx<R>::type* __restrict__ b3) {
-  typedef typename cplx<R>::type C;
-  const Geom& g = A.g;
-  long long nb = (g3.tot + 255) / 256;
-  long long I = xcd_block(nb) * 256 + threadIdx.x;
-  if (I >= g3.tot) return;
-  int I0, I1, I2;
-  decode(g3, I, I0, I1, I2);
-  C acc = mk((R)0, (R)0);
-  int r2 = g.dim == 3 ? 1 : 0;
-  for (int o2 = -r2; o2 <= r2; ++o2) {
-    int f2 = 2 * I2 + o2;
-    if (f2 < 0 || f2 > g.n[2]) continue;
-    R w2 = (g.dim == 3) ? (o2 == 0 ? (R)0.5 : (R)0.25) : (R)1;
-    for (int o1 = -1; o1 <= 1; ++o1) {
-      int f1 = 2 * I1 + o1;
-      if (f1 < 0 || f1 > g.n[1]) continue;
-      R w1 = o1 == 0 ? (R)0.5 : (R)0.25;
-      for (int o0 = -1; o0 <= 1; ++o0) {
-        int f0 = 2 * I0 + o0;
-        if (f0 < 0 || f0 > g.n[0]) continue;
-        R w0 = o0 == 0 ? (R)0.5 : (R)0.25;
-        long long f = f0 + (long long)g.N[0] * (f1 + (long long)g.N[1] * f2);
-        C Ax, xc, D;
-        apply_l2<R, XIN>(A, x, b, w_in, gc, e, f, f0, f1, f2, Ax, xc, D);
-        acc += (w0 * w1 * w2) * (b[f] - Ax);
-      }
-    }
-  }
-  b3[I] = acc;
-}
-
 // ------------------------------- launchers ---------------------------------
 static inline unsigned grid_for(long long n) { return (unsigned)((n + 255) / 256); }
 static inline unsigned grid_xcd(long long n) {
@@ -319,68 +317,91 @@ static inline unsigned grid_xcd(long long n) {
   long long per = (nb + 7) / 8;
   return (unsigned)(per * 8);
 }
+static inline TileGrid tiles(const Geom& g, int bx, int by, int bz) {
+  TileGrid t;
+  t.nt[0] = (g.N[0] + bx - 1) / bx;
+  t.nt[1] = (g.N[1] + by - 1) / by;
+  t.nt[2] = (g.N[2] + bz - 1) / bz;
+  t.ntiles = (long long)t.nt[0] * t.nt[1] * t.nt[2];
+  return t;
+}
+static inline unsigned grid_tiles(const TileGrid& t) { return (unsigned)((t.ntiles + 7) / 8 * 8); }
+
+template <int DIM, class Op, typename CB, typename CO>
+void sweep_dim(const Op& op, int xin, const typename Op::C* x, const CB* b, typename Op::Real w_in,
+               const Geom& gc, const typename Op::C* e, typename Op::Real w, CO* out, hipStream_t s) {
+  TileGrid tg = tiles(op.geom(), SBox<DIM>::x, SBox<DIM>::y, SBox<DIM>::z);
+  dim3 grid(grid_tiles(tg)), blk(256);
+#define SW(F) hipLaunchKernelGGL((k_sweep<DIM, Op, CB, CO, F>), grid, blk, 0, s, op, x, b, w_in, gc, e, w, out, tg)
+  switch (xin) {
+    case 0: SW(0); break;
+    case XIN_X: SW(XIN_X); break;
+    case XIN_Z: SW(XIN_Z); break;
+    case XIN_E: SW(XIN_E); break;
+    case XIN_X | XIN_E: SW(XIN_X | XIN_E); break;
+    case XIN_Z | XIN_E: SW(XIN_Z | XIN_E); break;
+    default: break;
+  }
+#undef SW
+}
+
+template <int DIM, class Op, typename CB>
+void restrict_dim(const Op& op, int xin, const typename Op::C* x, const CB* b, typename Op::Real w_in,
+                  const Geom& g2, typename Op::C* b2, hipStream_t s) {
+  typedef typename Op::C C;
+  TileGrid tg = tiles(g2, RBox<DIM, sizeof(C)>::x, RBox<DIM, sizeof(C)>::y, RBox<DIM, sizeof(C)>::z);
+  dim3 grid(grid_tiles(tg)), blk(256);
+#define RS(F) hipLaunchKernelGGL((k_restrict<DIM, Op, CB, F>), grid, blk, 0, s, op, x, b, w_in, g2, b2, tg)
+  switch (xin) {
+    case 0: RS(0); break;
+    case XIN_X: RS(XIN_X); break;
+    case XIN_Z: RS(XIN_Z); break;
+    default: break;
+  }
+#undef RS
+}
 
 template <typename R, typename CB, typename CO>
 void l1_sweep(const L1<R>& A, int xin, const typename cplx<R>::type* x, const CB* b, R w_in, const Geom& gc,
               const typename cplx<R>::type* e, R w, CO* out, hipStream_t s) {
-  dim3 grid(grid_xcd(A.op.g.tot)), blk(256);
-#define L1S(F) hipLaunchKernelGGL((k_l1_sweep<R, CB, CO, F>), grid, blk, 0, s, A, x, b, w_in, gc, e, w, out)
-  switch (xin) {
-    case 0: L1S(0); break;
-    case XIN_X: L1S(XIN_X); break;
-    case XIN_Z: L1S(XIN_Z); break;
-    case XIN_E: L1S(XIN_E); break;
-    case XIN_X | XIN_E: L1S(XIN_X | XIN_E); break;
-    case XIN_Z | XIN_E: L1S(XIN_Z | XIN_E); break;
-    default: break;
-  }
-#undef L1S
+  if (A.op.g.dim == 2)
+    sweep_dim<2>(Op1<2, R>{A}, xin, x, b, w_in, gc, e, w, out, s);
+  else
+    sweep_dim<3>(Op1<3, R>{A}, xin, x, b, w_in, gc, e, w, out, s);
 }
 
 template <typename R, typename CB>
 void l1_restrict(const L1<R>& A, int xin, const typename cplx<R>::type* x, const CB* b, R w_in, const Geom& gc,
                  const typename cplx<R>::type* e, const Geom& g2, typename cplx<R>::type* b2, hipStream_t s) {
-  dim3 grid(grid_xcd(g2.tot)), blk(256);
-#define L1R(F) hipLaunchKernelGGL((k_l1_restrict<R, CB, F>), grid, blk, 0, s, A, x, b, w_in, gc, e, g2, b2)
-  switch (xin) {
-    case 0: L1R(0); break;
-    case XIN_X: L1R(XIN_X); break;
-    case XIN_Z: L1R(XIN_Z); break;
-    default: break;
-  }
-#undef L1R
+  (void)gc;
+  (void)e;
+  if (A.op.g.dim == 2)
+    restrict_dim<2>(Op1<2, R>{A}, xin, x, b, w_in, g2, b2, s);
+  else
+    restrict_dim<3>(Op1<3, R>{A}, xin, x, b, w_in, g2, b2, s);
 }
 
 template <typename R>
 void l2_sweep(const L2<R>& A, int xin, const typename cplx<R>::type* x, const typename cplx<R>::type* b, R w_in,
               const Geom& gc, const typename cplx<R>::type* e, R w, typename cplx<R>::type* out, hipStream_t s) {
-  dim3 grid(grid_xcd(A.g.tot)), blk(256);
-#define L2S(F) hipLaunchKernelGGL((k_l2_sweep<R, F>), grid, blk, 0, s, A, x, b, w_in, gc, e, w, out)
-  switch (xin) {
-    case 0: L2S(0); break;
-    case XIN_X: L2S(XIN_X); break;
-    case XIN_Z: L2S(XIN_Z); break;
-    case XIN_E: L2S(XIN_E); break;
-    case XIN_X | XIN_E: L2S(XIN_X | XIN_E); break;
-    case XIN_Z | XIN_E: L2S(XIN_Z | XIN_E); break;
-    default: break;
-  }
-#undef L2S
+  typedef typename cplx<R>::type C;
+  if (A.g.dim == 2)
+    sweep_dim<2, Op2<2, R>, C, C>(Op2<2, R>{A}, xin, x, b, w_in, gc, e, w, out, s);
+  else
+    sweep_dim<3, Op2<3, R>, C, C>(Op2<3, R>{A}, xin, x, b, w_in, gc, e, w, out, s);
 }
 
 template <typename R>
 void l2_restrict(const L2<R>& A, int xin, const typename cplx<R>::type* x, const typename cplx<R>::type* b,
                  R w_in, const Geom& gc, const typename cplx<R>::type* e, const Geom& g3,
                  typename cplx<R>::type* b3, hipStream_t s) {
-  dim3 grid(grid_xcd(g3.tot)), blk(256);
-#define L2R(F) hipLaunchKernelGGL((k_l2_restrict<R, F>), grid, blk, 0, s, A, x, b, w_in, gc, e, g3, b3)
-  switch (xin) {
-    case 0: L2R(0); break;
-    case XIN_X: L2R(XIN_X); break;
-    case XIN_Z: L2R(XIN_Z); break;
-    default: break;
-  }
-#undef L2R
+  typedef typename cplx<R>::type C;
+  (void)gc;
+  (void)e;
+  if (A.g.dim == 2)
+    restrict_dim<2, Op2<2, R>, C>(Op2<2, R>{A}, xin, x, b, w_in, g3, b3, s);
+  else
+    restrict_dim<3, Op2<3, R>, C>(Op2<3, R>{A}, xin, x, b, w_in, g3, b3, s);
 }
 
 void l1_apply64(const L1<double>& A, const void* x, int x_is_f32, cd* y, hipStream_t s) {

@@ -169,7 +169,18 @@ def config1(n: int = 128) -> Problem:
 
 # level-2 real shifts: the same grid-to-grid analysis between levels 1 and 2
 # (e = r_2 / (2 r_1) - 1) for the contract stack; used where both coarse grids are shifted.
-ALPHA2_STAR = {(2, 10.0): 1.0360, (2, 12.0): 1.0255}
+# Regenerated by tests/golden/make_alpha.py like ALPHA_STAR.
+ALPHA2_STAR = {
+    (2, 10.0): 1.0360, (2, 32.0 / 3.0): 1.0315, (2, 34.0 / 3.0): 1.0280, (2, 12.0): 1.0255,
+    (3, 10.0): 1.0315, (3, 11.0): 1.0260, (3, 12.0): 1.0220,
+}
+
+
+def alpha2_for(dim: int, G: float) -> float:
+    for (d, g), a in ALPHA2_STAR.items():
+        if d == dim and abs(g - G) < 1e-9:
+            return a
+    raise KeyError((dim, G))
 
 CFG2_BETA = 0.1
 
@@ -185,7 +196,7 @@ def config2(n: int = 1024, seed: int = 2000) -> Problem:
     L = 20 if n >= 128 else max(2, (20 * n) // 1024 + 2)
     return Problem("cfg2_2d_layered_%d" % n, dim, (n, n), h, kap, omega_for_G(G, h, kap.max()),
                    ((L, L), (L, L)), SIGMA_MAX, alpha_for(dim, G), CFG2_BETA, [(n // 2, n // 2)], G,
-                   alpha2=ALPHA2_STAR[(2, G)], nu_pre=1, nu_post=1)
+                   alpha2=alpha2_for(2, G), nu_pre=1, nu_post=1)
 
 
 def config3(n: int = 256, seed: int = 3000) -> Problem:
@@ -208,7 +219,8 @@ CFG4_G = (10.0, 32.0 / 3.0, 34.0 / 3.0, 12.0)
 
 def config4_instance(i: int, per_size: int = 32, sizes=CFG4_SIZES, n_src: int = 8) -> Problem:
     """instance i of the batched 2D workload: sizes in blocks of per_size, frequency index
-    i mod 4 (G from 10 to 12), layered medium seeded 4000+i, 8 seeded random sources."""
+    i mod 4 (G from 10 to 12), layered medium seeded 4000+i, 8 seeded random sources;
+    the same shifts and (1,1) smoothing as the 1024^2 layered workload."""
     n = sizes[(i // per_size) % len(sizes)]
     G = CFG4_G[i % 4]
     dim = 2
@@ -217,7 +229,8 @@ def config4_instance(i: int, per_size: int = 32, sizes=CFG4_SIZES, n_src: int = 
     L = 20
     srcs = random_sources((n, n), ((L, L), (L, L)), n_src, 40000 + i)
     return Problem("cfg4_inst%d_%d" % (i, n), dim, (n, n), h, kap, omega_for_G(G, h, kap.max()),
-                   ((L, L), (L, L)), SIGMA_MAX, alpha_for(dim, G), 0.0, srcs, G)
+                   ((L, L), (L, L)), SIGMA_MAX, alpha_for(dim, G), CFG2_BETA, srcs, G,
+                   alpha2=alpha2_for(dim, G), nu_pre=1, nu_post=1)
 
 
 def config5(n: int = 128, seed: int = 5000, smooth_cells: float = 16.0):

@@ -37,6 +37,18 @@ def small_problem(dim, n=None, seed=7, beta=0.03, alpha2=1.0):
     return p
 
 
+def rect_problem(n, seed=11, G=10.0, beta=0.05, alpha2=1.03):
+    """layered medium on a non-square grid (several kernel tiles per axis with ragged
+    last tiles); layer of 4 cells on every face."""
+    dim = len(n)
+    h = 1.0 / max(n)
+    kap = synth.layered_slowness(n, 4, 3.0, seed)
+    layer = tuple((4, 4) for _ in range(dim))
+    return synth.Problem("rect_%s" % "x".join(map(str, n)), dim, tuple(n), h, kap,
+                         synth.omega_for_G(G, h, kap.max()), layer, synth.SIGMA_MAX,
+                         synth.alpha_for(dim, 10.0), beta, [tuple(k // 2 for k in n)], G, alpha2=alpha2)
+
+
 def oracle_hierarchy(p, **kw):
     args = dict(alpha2=getattr(p, "alpha2", 1.0))
     args.update(kw)

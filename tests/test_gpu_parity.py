@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 import torch
 
-from tests.gpu_helpers import oracle_hierarchy, rel, small_problem, stencil_arrays
+from tests.gpu_helpers import oracle_hierarchy, rect_problem, rel, small_problem, stencil_arrays
 
 pytestmark = pytest.mark.gpu
 
@@ -82,6 +82,22 @@ def test_cycle(case, cycle, nu):
     s = from_problem(p, cycle=cycle, nu=nu, cycle_prec="f64")
     zc = s.vcycle(r, op=HELM_OP_C).cpu().numpy()
     assert rel(zc, Hc.precond(r)) < 1e-10
+
+
+@pytest.mark.parametrize("n", [(136, 72), (40, 24, 32)])
+@pytest.mark.parametrize("nu", [(1, 1), (2, 2)])
+def test_cycle_rectangular_multi_tile(n, nu):
+    """non-square grids: several stencil tiles per axis with ragged last tiles on every level."""
+    p = rect_problem(n)
+    print("cycle rect", n, nu, flush=True)
+    H = oracle_hierarchy(p, cycle=2, nu_pre=nu[0], nu_post=nu[1])
+    r = _rand(p.N, 6)
+    ref = H.precond(r)
+    for prec, tol in (("f64", 1e-10), ("f32", 1e-4)):
+        s = from_problem(p, cycle=2, nu=nu, cycle_prec=prec)
+        z = s.vcycle(r).cpu().numpy()
+        assert rel(z, ref) < tol, (prec, rel(z, ref))
+        s.close()
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])

@@ -104,3 +104,20 @@ def test_contract_stack_alpha_constants_2d(G):
 def test_contract_stack_alpha_constant_3d():
     a, e = A.alpha_star("p7", "fw", 12.0, lo=1.09, hi=1.11, exhaustive=True)
     assert a == pytest.approx(synth.alpha_for(3, 12.0), abs=1e-9)
+
+
+@pytest.mark.parametrize("G", [10.0, 12.0])
+def test_level2_shift_constants_2d(G):
+    """the level-2 shift of the two-shift variant (Remark 4.1) from the grid-1-to-2 analysis."""
+    a, e = A.alpha2_star("p5", "fw", G, lo=1.0, hi=1.06)
+    assert a == pytest.approx(synth.alpha2_for(2, G), abs=1e-9)
+    assert 0.005 < e < 0.015
+
+
+def test_level2_error_vanishes_without_coarsening_error_at_low_frequency():
+    """as kh -> 0 both discrete dispersion curves approach the continuous one, so the
+    unshifted level-2 error tends to zero quadratically in kh."""
+    e1 = np.max(np.abs(A.eg_level2("p5", "fw", 40.0, 1.0)))
+    e2 = np.max(np.abs(A.eg_level2("p5", "fw", 80.0, 1.0)))
+    assert e2 < e1 < 0.05
+    assert 3.0 < e1 / e2 < 5.0
