@@ -203,7 +203,10 @@ int helm_get_timing(helm_ctx* ctx, double* t, int n);
  * [4] entries of the forward factor blocks sum(nF*nS), [5] entries of the backward blocks
  * sum(nS*nB), [6] update entries sum(nB), [7] separator entries sum(nS) (= N3),
  * [8] forward and [9] backward substitution launches per coarsest solve, [10] workspace
- * bytes, [11] largest front size nF, [12] bytes per complex of the cycle (8 or 16).
+ * bytes, [11] largest front size nF, [12] bytes per complex of the cycle (8 or 16),
+ * [13] leaf box size and [14] root merge limit of the nested dissection, [15] 1 if the
+ * schedule came from the autotuner cache (HELM_TUNE_CACHE), [16] number of tree-block
+ * launches per direction, [17..20] the heights closing them (-1 beyond).
  * Returns the number of entries written (at most n). */
 int helm_get_info(helm_ctx* ctx, long long* out, int n);
 

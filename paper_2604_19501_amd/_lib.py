@@ -17,6 +17,10 @@ import torch  # noqa: F401
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libhelm.so")
+# schedules picked by the autotuner (paper_2604_19501_amd/tune.py); the library reads the
+# file named by HELM_TUNE_CACHE when it plans a context
+TUNE_CACHE = os.path.join(HERE, "tune_cache.json")
+os.environ.setdefault("HELM_TUNE_CACHE", TUNE_CACHE)
 HEADER = os.path.join(os.path.dirname(HERE), "include", "helm.h")
 
 if not os.path.exists(LIBPATH):

@@ -39,14 +39,13 @@ template <typename C>
 void nd_finalize(const NDFrontDev* fr, const int* ids, int nids, long long max_n, const cd* Fp, const int* perm,
                  C* Lp, C* Wp, hipStream_t s);
 template <typename C>
-void nd_fwd(int kind, int ntasks, size_t lds, const NDFrontDev* fr, const int* idx, const int* cptr, const int* cidx,
-            const C* Lp, C* upd, const int* task_off, const NDItem* items, const C* r, C* x, C* gvec, int cap,
-            int conj, hipStream_t s);
+void nd_fwd(const NDLaunchDev& L, const NDFrontDev* fr, const int* idx, const int* cptr, const int* cidx,
+            const C* Lp, C* upd, const C* r, C* x, C* gvec, int cap, int conj, hipStream_t s);
 void nd_panel_lds(const NDFrontDev* fr, const int* ids, int nids, int max_nF, cd* Fp, int* perm, int* swp, int k0,
                   int kb, int* err, hipStream_t s);
 template <typename C>
-void nd_bwd(int kind, int ntasks, size_t lds, const NDFrontDev* fr, const int* idx, const C* Wp, const int* task_off,
-            const NDItem* items, C* x, C* gvec, int cap, int conj, hipStream_t s);
+void nd_bwd(const NDLaunchDev& L, const NDFrontDev* fr, const int* idx, const int* cidx, const C* Wp, C* upd, C* x,
+            C* gvec, int cap, int conj, hipStream_t s);
 void grad_accumulate(const FineOp& op, double omega, const cd* u, const cd* lam, double* g, int first,
                      hipStream_t s);
 
@@ -101,8 +100,7 @@ struct NDDev {        // device-side ND tables (pointers into the workspace)
   long long* toff = nullptr;
   cd *F = nullptr, *T = nullptr;
   void *L = nullptr, *W = nullptr, *upd = nullptr, *gvec = nullptr;
-  std::vector<int*> task_off[2];
-  std::vector<NDItem*> items[2];
+  std::vector<NDLaunchDev> launch[2];   // forward, backward
   int gvec_cap = 0;
 };
 
@@ -158,6 +156,8 @@ struct helm_ctx {
   std::vector<hipEvent_t> evpool;
   size_t lds_limit = 65536;     // LDS bytes for substitution vectors
   size_t lds_panel = 0;         // LDS bytes for a resident factorisation panel (device maximum - 2 KB)
+  bool tuned = false;           // schedule parameters came from the autotuner cache
+  int nd_leaf = 0, nd_root = 0;  // nested-dissection leaf size and root merge limit in use
   std::vector<helm_ctx*> sub;   // batched form: one context per instance
   std::vector<hipStream_t> bstreams;   // batched form: streams of the concurrent instances
   // one captured graph per (operator, Arnoldi index j): cycle on V_j + Arnoldi step
@@ -216,11 +216,87 @@ int env_int(const char* name, int dflt) {
   return v && *v ? atoi(v) : dflt;
 }
 
+// schedule parameters of the coarsest solve picked by the autotuner: the JSON file named
+// by HELM_TUNE_CACHE maps "nd:<dim>:<n0>x<n1>x<n2>:<f32|f64>" to an object with integer
+// "leaf" and "root" and a string "cuts"; returns false when the file or the key is absent
+struct TunedND {
+  int leaf = -1, root = -1;
+  std::string cuts;
+  bool has_cuts = false;
+};
+bool tuned_nd(const helm_ctx* c, TunedND& t) {
+  const char* path = getenv("HELM_TUNE_CACHE");
+  if (!path || !*path) return false;
+  FILE* f = fopen(path, "rb");
+  if (!f) return false;
+  std::string txt;
+  char buf[4096];
+  size_t n;
+  while ((n = fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, n);
+  fclose(f);
+  char key[128];
+  snprintf(key, sizeof key, "\"nd:%d:%dx%dx%d:%s\"", c->grid.dim, c->grid.n[0], c->grid.n[1],
+           c->grid.dim == 3 ? c->grid.n[2] : 0, c->f32 ? "f32" : "f64");
+  size_t k = txt.find(key);
+  if (k == std::string::npos) return false;
+  size_t ob = txt.find('{', k), oe = txt.find('}', k);
+  if (ob == std::string::npos || oe == std::string::npos || oe < ob) return false;
+  const std::string obj = txt.substr(ob, oe - ob + 1);
+  auto num = [&](const char* name, int& out) {
+    size_t p = obj.find(name);
+    if (p == std::string::npos) return;
+    p = obj.find(':', p);
+    if (p != std::string::npos) out = atoi(obj.c_str() + p + 1);
+  };
+  num("\"leaf\"", t.leaf);
+  num("\"root\"", t.root);
+  size_t p = obj.find("\"cuts\"");
+  if (p != std::string::npos) {
+    size_t q0 = obj.find('"', obj.find(':', p));
+    size_t q1 = q0 == std::string::npos ? q0 : obj.find('"', q0 + 1);
+    if (q0 != std::string::npos && q1 != std::string::npos) {
+      t.cuts = obj.substr(q0 + 1, q1 - q0 - 1);
+      t.has_cuts = true;
+    }
+  }
+  return true;
+}
+
+std::vector<int> parse_cuts(const char* v) {
+  std::vector<int> cuts;
+  if (!strcmp(v, "none")) {
+    cuts.push_back(-1);
+    return cuts;
+  }
+  for (const char* p = v; *p;) {
+    char* e = nullptr;
+    long h = strtol(p, &e, 10);
+    if (e == p) break;
+    cuts.push_back((int)h);
+    p = *e == ',' ? e + 1 : e;
+  }
+  return cuts;
+}
+
+// nested-dissection parameters: environment (HELM_ND_LEAF, HELM_ND_ROOT, HELM_ND_CUTS),
+// else the autotuner's cache, else defaults and the planner's cost model
 void build_plan(helm_ctx* c) {
-  const int leaf = env_int("HELM_ND_LEAF", c->grid.dim == 3 ? 8 : 32);
-  const int subtree = env_int("HELM_ND_SUBTREE", c->grid.dim == 3 ? 512 : 256);
-  const int merge = env_int("HELM_ND_ROOT", c->grid.dim == 3 ? 1 : 1100);
-  nd_plan(c->g3, leaf, 16, subtree, merge, c->plan);
+  TunedND tn;
+  const bool tuned = tuned_nd(c, tn);
+  const int leaf = env_int("HELM_ND_LEAF", tuned && tn.leaf > 0 ? tn.leaf : (c->grid.dim == 3 ? 8 : 32));
+  const int merge = env_int("HELM_ND_ROOT", tuned && tn.root > 0 ? tn.root : (c->grid.dim == 3 ? 1 : 1100));
+  const int lds = env_int("HELM_ND_LDS", 65536);
+  // cuts: heights closing the tree-block launches ("3,6,8"), "none" for none, empty for
+  // the cost model's choice
+  std::vector<int> cuts;
+  if (const char* v = getenv("HELM_ND_CUTS"))
+    cuts = parse_cuts(v);
+  else if (tuned && tn.has_cuts)
+    cuts = parse_cuts(tn.cuts.c_str());
+  c->tuned = tuned;
+  c->nd_leaf = leaf;
+  c->nd_root = merge;
+  nd_plan(c->g3, leaf, 16, merge, (int)c->csz, lds, cuts, c->plan);
   NDPlan& P = c->plan;
   c->hlist.clear();
   c->hlist_toff.clear();
@@ -298,22 +374,40 @@ size_t carve(helm_ctx* c, void* ws) {
   d.upd = cv.take<char>(cs * std::max<long long>(1, P.upd_total));
   for (int fb = 0; fb < 2; ++fb) {
     std::vector<NDLaunch>& Ls = fb == 0 ? P.fwd : P.bwd;
-    d.task_off[fb].assign(Ls.size(), nullptr);
-    d.items[fb].assign(Ls.size(), nullptr);
+    d.launch[fb].assign(Ls.size(), NDLaunchDev());
     for (size_t l = 0; l < Ls.size(); ++l) {
-      d.task_off[fb][l] = cv.take<int>(Ls[l].task_off.size());
-      d.items[fb][l] = cv.take<NDItem>(Ls[l].items.size());
+      const NDLaunch& L = Ls[l];
+      NDLaunchDev& D = d.launch[fb][l];
+      D.kind = L.kind;
+      D.threads = L.threads;
+      D.lds_bytes = L.lds_bytes;
+      if (L.kind == 2) {
+        D.ntasks = (int)L.tasks.size();
+        D.tasks = cv.take<NDTask>(std::max<size_t>(1, L.tasks.size()));
+        D.stages = cv.take<NDStage>(std::max<size_t>(1, L.stages.size()));
+        D.gath = cv.take<NDGather>(std::max<size_t>(1, L.gath.size()));
+        D.segs = cv.take<NDSeg>(std::max<size_t>(1, L.segs.size()));
+        D.outs = cv.take<NDOut>(std::max<size_t>(1, L.outs.size()));
+        D.dst = cv.take<int>(std::max<size_t>(1, L.dst.size()));
+      } else {
+        D.ntasks = (int)L.task_off.size() - 1;
+        D.task_off = cv.take<int>(L.task_off.size());
+        D.items = cv.take<NDItem>(L.items.size());
+      }
     }
   }
   // global fall-back vectors for launches whose vectors do not fit in LDS
   // (a subtree task holds one vector per wavefront)
   long long gcap = 0, gneed = 0;
   for (int fb = 0; fb < 2; ++fb)
-    for (auto& L : (fb == 0 ? P.fwd : P.bwd)) {
-      int per = L.kind == 0 ? 4 : 1;
-      if ((size_t)L.max_rows_vec * cs * per > c->lds_limit) {
+    for (size_t l = 0; l < (fb == 0 ? P.fwd : P.bwd).size(); ++l) {
+      const NDLaunch& L = (fb == 0 ? P.fwd : P.bwd)[l];
+      if (L.kind != 1) continue;
+      const size_t need = (size_t)L.max_rows_vec * cs;
+      d.launch[fb][l].shm = need <= c->lds_limit ? std::max<size_t>(need, 16) : 0;
+      if (need > c->lds_limit) {
         gcap = std::max<long long>(gcap, L.max_rows_vec);
-        gneed = std::max<long long>(gneed, (long long)(L.task_off.size() - 1) * per);
+        gneed = std::max<long long>(gneed, (long long)(L.task_off.size() - 1));
       }
     }
   d.gvec_cap = (int)gcap;
@@ -411,27 +505,15 @@ void ev_flush(helm_ctx* c) {
 template <typename C>
 void nd_solve(helm_ctx* c, const C* r, C* x, int conj, hipStream_t s) {
   NDDev& d = c->nd;
-  NDPlan& P = c->plan;
-  for (int fb = 0; fb < 2; ++fb) {
-    std::vector<NDLaunch>& Ls = fb == 0 ? P.fwd : P.bwd;
-    for (size_t l = 0; l < Ls.size(); ++l) {
-      const NDLaunch& L = Ls[l];
-      int ntasks = (int)L.task_off.size() - 1;
-      int per = L.kind == 0 ? 4 : 1;
-      size_t need = (size_t)L.max_rows_vec * sizeof(C) * per;
-      bool lds = need <= c->lds_limit;
-      C* gv = lds ? nullptr : (C*)d.gvec;
-      int cap = lds ? L.max_rows_vec : d.gvec_cap;
-      size_t shm = lds ? std::max<size_t>(need, 16) : 0;
-      if (fb == 0)
-        TIMED(c, KT_ND_FWD, s,
-              nd_fwd<C>(L.kind, ntasks, shm, d.fronts, d.idx, d.cptr, d.cidx, (const C*)d.L, (C*)d.upd,
-                        d.task_off[0][l], d.items[0][l], r, x, gv, cap, conj, s));
-      else
-        TIMED(c, KT_ND_BWD, s,
-              nd_bwd<C>(L.kind, ntasks, shm, d.fronts, d.idx, (const C*)d.W, d.task_off[1][l], d.items[1][l], x, gv,
-                        cap, conj, s));
-    }
+  for (const NDLaunchDev& L : d.launch[0]) {
+    C* gv = L.kind == 1 && L.shm == 0 ? (C*)d.gvec : nullptr;
+    TIMED(c, KT_ND_FWD, s,
+          nd_fwd<C>(L, d.fronts, d.idx, d.cptr, d.cidx, (const C*)d.L, (C*)d.upd, r, x, gv, d.gvec_cap, conj, s));
+  }
+  for (const NDLaunchDev& L : d.launch[1]) {
+    C* gv = L.kind == 1 && L.shm == 0 ? (C*)d.gvec : nullptr;
+    TIMED(c, KT_ND_BWD, s,
+          nd_bwd<C>(L, d.fronts, d.idx, d.cidx, (const C*)d.W, (C*)d.upd, x, gv, d.gvec_cap, conj, s));
   }
 }
 
@@ -781,8 +863,18 @@ int helm_setup(const helm_grid* grid, const double* slowness, double omega, cons
     for (int fb = 0; fb < 2; ++fb) {
       std::vector<NDLaunch>& Ls = fb == 0 ? P.fwd : P.bwd;
       for (size_t l = 0; l < Ls.size(); ++l) {
-        up(d.task_off[fb][l], Ls[l].task_off, s);
-        up(d.items[fb][l], Ls[l].items, s);
+        NDLaunchDev& D = d.launch[fb][l];
+        if (Ls[l].kind == 2) {
+          up((NDTask*)D.tasks, Ls[l].tasks, s);
+          up((NDStage*)D.stages, Ls[l].stages, s);
+          up((NDGather*)D.gath, Ls[l].gath, s);
+          up((NDSeg*)D.segs, Ls[l].segs, s);
+          up((NDOut*)D.outs, Ls[l].outs, s);
+          up((int*)D.dst, Ls[l].dst, s);
+        } else {
+          up((int*)D.task_off, Ls[l].task_off, s);
+          up((NDItem*)D.items, Ls[l].items, s);
+        }
       }
     }
     numeric_setup(c.get(), slowness, s);
@@ -970,10 +1062,12 @@ int helm_get_info(helm_ctx* c, long long* out, int n) {
     sB += f.nB;
     maxF = std::max<long long>(maxF, f.nF);
   }
-  long long v[13] = {c->g1.tot, c->g2.tot, c->g3.tot, (long long)P.fronts.size(), P.L_total, P.W_total, sB,
+  long long v[21] = {c->g1.tot, c->g2.tot, c->g3.tot, (long long)P.fronts.size(), P.L_total, P.W_total, sB,
                      c->g3.tot, (long long)P.fwd.size(), (long long)P.bwd.size(), (long long)c->ws_needed, maxF,
-                     (long long)c->csz};
-  int m = std::min(n, 13);
+                     (long long)c->csz, c->nd_leaf, c->nd_root, c->tuned ? 1 : 0, (long long)P.cuts.size(),
+                     -1, -1, -1, -1};
+  for (size_t i = 0; i < P.cuts.size() && i < 4; ++i) v[17 + i] = P.cuts[i];
+  int m = std::min(n, 21);
   for (int i = 0; i < m; ++i) out[i] = v[i];
   return m;
 }

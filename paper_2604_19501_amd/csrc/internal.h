@@ -158,16 +158,60 @@ struct NDAsm {          // F[row][col] += coef[cidx]
   long long cidx;
 };
 
-struct NDItem {         // one work item of the solve: rows [r0, r1) of a front
+struct NDItem {         // one work item of a multi-block launch: rows [r0, r1) of a front
   int front, r0, r1;
-  int stage;            // subtree tasks: items of one stage are independent (one per wavefront)
+  int stage;
 };
 
-struct NDLaunch {       // tasks of one kernel launch (task t = items[task_off[t] .. task_off[t+1]))
-  int kind = 0;         // 0: one work-group per subtree, one front per wavefront; 1: row chunks of big fronts
-  std::vector<int> task_off;
+// Tree-block launches: one work-group walks the fronts of a subtree level by level.
+// Per level ("stage"): gather the fronts' input vectors into LDS, partial matrix-vector
+// products over row blocks of at most 64 rows and k ranges of at most 16 ("segments",
+// one wavefront each), then sum the partials of every row block and write the results
+// ("outputs").  A work-group first copies its task's schedule into LDS; indices inside
+// a task are relative to the task's first gather / segment / output / destination.
+struct NDTask {
+  int st0, st1, g0, g1, s0, s1, o0, o1, d0, d1;
+};
+struct NDStage {
+  int g0, g1, s0, s1, o0, o1;
+};
+struct NDGather {       // vec[slot] = (rid >= 0 ? src[rid] : 0) + upd[u0] + upd[u1] + sum upd[cidx[ca .. cb))
+  int slot, rid, u0, u1, ca, cb;
+};
+struct NDSeg {          // part[pslot + l] = sum_{k0 <= k < k1} M[m_off + k ld + r0 + l] vec[vslot + k], l < nr
+  long long m_off;
+  int ld, r0, nr, k0, k1, vslot, pslot, pad;
+};
+struct NDOut {          // rows [r0, r0 + nr): y = sum of nparts partial blocks of 64; destinations dst[d ..)
+  int r0, nr, vslot, pslot, nparts, d;   // dst >= 0: x index; dst < 0: update index -dst - 1
+};
+
+struct NDLaunch {       // one kernel launch of a substitution
+  int kind = 1;         // 1: row chunks of big fronts (one work-group per item); 2: tree blocks
+  std::vector<int> task_off;   // kind 1: items[task_off[t] ..); kind 2: stages[task_off[t] ..)
   std::vector<NDItem> items;
-  int max_rows_vec = 0; // vector entries per front (nF forward, nB backward)
+  int max_rows_vec = 0; // kind 1: vector entries per work-group (nF forward, nB backward)
+  std::vector<NDTask> tasks;
+  std::vector<NDStage> stages;
+  std::vector<NDGather> gath;
+  std::vector<NDSeg> segs;
+  std::vector<NDOut> outs;
+  std::vector<int> dst;
+  int lds_bytes = 0;    // kind 2: schedule + vectors + partials per work-group
+  int threads = 256;
+};
+
+struct NDLaunchDev {    // device copy of an NDLaunch, as the kernels see it
+  int kind = 1, ntasks = 0, threads = 256, lds_bytes = 0;
+  size_t shm = 0;       // kind 1: dynamic LDS bytes for the gathered vector (0: global fall-back)
+  const int* task_off = nullptr;
+  const NDItem* items = nullptr;
+  const NDTask* tasks = nullptr;
+  const NDStage* stages = nullptr;
+  const NDGather* gath = nullptr;
+  const NDSeg* segs = nullptr;
+  const NDOut* outs = nullptr;
+  const int* dst = nullptr;
 };
 
 struct NDPlan {
@@ -183,8 +227,13 @@ struct NDPlan {
   long long T_scratch = 0;              // doubles2 of panel row buffer (max over heights)
   int max_nS = 0, max_nB = 0, max_nF = 0;
   std::vector<NDLaunch> fwd, bwd;
+  std::vector<int> cuts;                // heights closing the tree-block launches
 };
 
-void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int subtree_nodes, int root_merge, NDPlan& plan);
+// elem_bytes: bytes of a factor entry (cycle precision); lds_bytes: LDS available to a
+// tree block; cuts: heights closing the tree-block launches (empty: chosen by the cost
+// model, {-1}: no tree blocks)
+void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int root_merge, int elem_bytes, int lds_bytes,
+             const std::vector<int>& cuts, NDPlan& plan);
 
 }  // namespace helm

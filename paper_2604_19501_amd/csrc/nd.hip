@@ -353,11 +353,6 @@ __device__ __forceinline__ C cmul_conj(C a, C x, int conj) {   // (conj? conj(a)
   return a * x;
 }
 
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // f_S (and v_B) entry i of front f: right-hand side on S plus the children's updates
 // (contribution list cptr[i] .. cptr[i+1] of absolute indices into the update pool)
@@ -373,94 +368,134 @@ __device__ __forceinline__ C gather_entry(const NDFrontDev& f, const int* __rest
   return v;
 }
 
-// y_i = sum_k M[k*ld + i] v[k] for rows i in [i0, i1) by one wavefront: `lpr` lanes per row
-// (power of two) split k, the row groups walk the rows; loads unrolled for memory-level
-// parallelism; epi(i, y_i) is called by the first lane of each group.
-template <typename C, typename Epi>
-__device__ __forceinline__ void gemv_wave(const C* __restrict__ M, long long ld, int i0, int i1, int K,
-                                          const C* __restrict__ v, int conj, Epi epi) {
-  typedef decltype(v[0].x) R;
-  const int lane = threadIdx.x & 63;
-  const int rows = i1 - i0;
-  int lpr = 1;
-  while (lpr < 64 && rows * lpr * 2 <= 64 && K >= 4 * lpr) lpr *= 2;
-  const int g = lane / lpr, sub = lane % lpr, rpp = 64 / lpr;
-  for (int base = i0; base < i1; base += rpp) {
-    const int i = base + g;
-    C acc = mk((R)0, (R)0);
-    if (i < i1) {
-      const C* col = M + i;
-      int k = sub;
-#pragma unroll 16
-      for (; k < K; k += lpr) acc += cmul_conj(col[(long long)k * ld], v[k], conj);
-    }
-    for (int o = lpr >> 1; o > 0; o >>= 1) {
-      acc.x += __shfl_xor(acc.x, o, 64);
-      acc.y += __shfl_xor(acc.y, o, 64);
-    }
-    if (sub == 0 && i < i1) epi(i, acc);
+__device__ __forceinline__ size_t al16(size_t v) { return (v + 15) & ~(size_t)15; }
+
+// copy n bytes (a multiple of 4) from global memory to LDS with the whole work-group;
+// four independent loads per thread and round before the stores
+__device__ __forceinline__ void copy_lds(void* dst, const void* src, size_t n) {
+  const int* s = (const int*)src;
+  int* d = (int*)dst;
+  const int nw = (int)(n / 4), bd = blockDim.x;
+  for (int w = threadIdx.x; w < nw; w += 4 * bd) {
+    int v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v[q] = s[min(w + q * bd, nw - 1)];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (w + q * bd < nw) d[w + q * bd] = v[q];
   }
 }
 
-// forward substitution, small fronts: one work-group per subtree, one front per wavefront
-// per stage; [g_S; t_B] = L f_S with L column major (ld nF).
-template <typename C>
-__global__ void __launch_bounds__(256) k_nd_fwd_small(const NDFrontDev* __restrict__ fr, const int* __restrict__ idx,
-                                                      const int* __restrict__ cptr, const int* __restrict__ cidx,
-                                                      const C* __restrict__ Lp,
-                                                      C* __restrict__ upd, const int* __restrict__ task_off,
-                                                      const NDItem* __restrict__ items, const C* __restrict__ r,
-                                                      C* __restrict__ x, C* __restrict__ gvec, int cap, int conj) {
-  extern __shared__ char smem[];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  C* vec = (gvec ? gvec + (long long)blockIdx.x * 4 * cap : (C*)smem) + (long long)wv * cap;
-  const int beg = task_off[blockIdx.x], end = task_off[blockIdx.x + 1];
-  for (int it = beg; it < end;) {
-    const int stage = items[it].stage;
-    int send = it;
-    while (send < end && items[send].stage == stage) ++send;
-    for (int q = it + wv; q < send; q += 4) {
-      const NDFrontDev f = fr[items[q].front];
-      const int* id = idx + f.idx_off;
-      for (int i = lane; i < f.nF; i += 64) vec[i] = gather_entry(f, cptr, cidx, id, upd, r, i);
-      wave_sync();
-      gemv_wave(Lp + f.L_off, f.nF, 0, f.nF, f.nS, vec, conj, [&](int i, C acc) {
-        if (i < f.nS)
-          x[id[i]] = acc;
-        else
-          upd[f.upd_off + i - f.nS] = vec[i] - acc;
-      });
-      wave_sync();
-    }
-    __syncthreads();
-    it = send;
-  }
+// a segment is processed by a whole wavefront: keep its fields in scalar registers
+__device__ __forceinline__ int ufl(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ NDSeg uniform_seg(NDSeg a) {
+  NDSeg b;
+  b.m_off = ((long long)ufl((int)(a.m_off >> 32)) << 32) | (unsigned)ufl((int)(a.m_off & 0xffffffffLL));
+  b.ld = ufl(a.ld);
+  b.r0 = ufl(a.r0);
+  b.nr = ufl(a.nr);
+  b.k0 = ufl(a.k0);
+  b.k1 = ufl(a.k1);
+  b.vslot = ufl(a.vslot);
+  b.pslot = ufl(a.pslot);
+  b.pad = 0;
+  return b;
 }
 
-// backward substitution, small fronts: x_S = g_S + W x_B (W column major, ld nS)
-template <typename C>
-__global__ void __launch_bounds__(256) k_nd_bwd_small(const NDFrontDev* __restrict__ fr, const int* __restrict__ idx,
-                                                      const C* __restrict__ Wp, const int* __restrict__ task_off,
-                                                      const NDItem* __restrict__ items, C* __restrict__ x,
-                                                      C* __restrict__ gvec, int cap, int conj) {
-  extern __shared__ char smem[];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  C* vec = (gvec ? gvec + (long long)blockIdx.x * 4 * cap : (C*)smem) + (long long)wv * cap;
-  const int beg = task_off[blockIdx.x], end = task_off[blockIdx.x + 1];
-  for (int it = beg; it < end;) {
-    const int stage = items[it].stage;
-    int send = it;
-    while (send < end && items[send].stage == stage) ++send;
-    for (int q = it + wv; q < send; q += 4) {
-      const NDFrontDev f = fr[items[q].front];
-      const int* id = idx + f.idx_off;
-      for (int j = lane; j < f.nB; j += 64) vec[j] = x[id[f.nS + j]];
-      wave_sync();
-      gemv_wave(Wp + f.W_off, f.nS, 0, f.nS, f.nB, vec, conj, [&](int i, C acc) { x[id[i]] = x[id[i]] + acc; });
-      wave_sync();
+// Tree-block substitution: one work-group per subtree task, one stage per level.
+//   gathers:  vec[slot] = src[rid] (+ children's updates)           all threads
+//   segments: partial products of <= 64 rows over <= 16 columns       one wavefront, two at a time
+//   outputs:  sum of a row block's partials, write x or the update    one wavefront each
+// forward (FWD = 1): M = L = [A^-1; C A^-1] (ld nF), src = r;  rows < nS give x_S = g_S,
+//                    rows >= nS the update v_B - C A^-1 f_S of the parent
+// backward:          M = W = -A^-1 B (ld nS), src = x (the boundary solution);  x_S += W x_B
+// The task's schedule is copied to LDS first, so a stage costs two dependent global
+// accesses (gathered values, matrix entries) besides its barriers.
+template <typename C, int FWD>
+__global__ void __launch_bounds__(1024) k_nd_tree(const NDTask* __restrict__ tasks,
+                                                  const NDStage* __restrict__ stages,
+                                                  const NDGather* __restrict__ gath, const NDSeg* __restrict__ segs,
+                                                  const NDOut* __restrict__ outs, const int* __restrict__ dst,
+                                                  const int* __restrict__ cidx, const C* __restrict__ M,
+                                                  C* __restrict__ upd, const C* __restrict__ src,
+                                                  C* __restrict__ x, int conj) {
+  typedef decltype(src[0].x) R;
+  extern __shared__ __align__(16) char smem[];
+  const NDTask T = tasks[blockIdx.x];
+  const int nst = T.st1 - T.st0, ng = T.g1 - T.g0, nsg = T.s1 - T.s0, no = T.o1 - T.o0, nd = T.d1 - T.d0;
+  char* p = smem;
+  NDStage* lst = (NDStage*)p;
+  p += al16(sizeof(NDStage) * nst);
+  NDGather* lg = (NDGather*)p;
+  p += al16(sizeof(NDGather) * ng);
+  NDSeg* lsg = (NDSeg*)p;
+  p += al16(sizeof(NDSeg) * nsg);
+  NDOut* lo = (NDOut*)p;
+  p += al16(sizeof(NDOut) * no);
+  int* ldst = (int*)p;
+  p += al16(sizeof(int) * nd);
+  C* work = (C*)p;
+  copy_lds(lst, stages + T.st0, sizeof(NDStage) * nst);
+  copy_lds(lg, gath + T.g0, sizeof(NDGather) * ng);
+  copy_lds(lsg, segs + T.s0, sizeof(NDSeg) * nsg);
+  copy_lds(lo, outs + T.o0, sizeof(NDOut) * no);
+  copy_lds(ldst, dst + T.d0, sizeof(int) * nd);
+  __syncthreads();
+  const int nw = blockDim.x >> 6, wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int st = 0; st < nst; ++st) {
+    const NDStage S = lst[st];
+    // loads are unconditional (clamped indices, zero weights) so that a wavefront keeps
+    // all of them in flight instead of waiting on each one
+    for (int e = S.g0 + (int)threadIdx.x; e < S.g1; e += blockDim.x) {
+      const NDGather g = lg[e];
+      const C v0 = src[max(g.rid, 0)], u0 = upd[max(g.u0, 0)], u1 = upd[max(g.u1, 0)];
+      C v = mk((R)0, (R)0);
+      if (g.rid >= 0) v += v0;
+      if (g.u0 >= 0) v += u0;
+      if (g.u1 >= 0) v += u1;
+      for (int q = g.ca; q < g.cb; ++q) v += upd[cidx[q]];
+      work[g.slot] = v;
     }
     __syncthreads();
-    it = send;
+    // NSEG segments per wavefront at a time, 16 matrix loads each in flight
+    constexpr int NSEG = 1;
+    for (int s0 = S.s0 + wv; s0 < S.s1; s0 += NSEG * nw) {
+      NDSeg sg[NSEG];
+      C mv[NSEG][16];
+#pragma unroll
+      for (int j = 0; j < NSEG; ++j) {
+        sg[j] = uniform_seg(lsg[min(s0 + j * nw, S.s1 - 1)]);
+        const C* col = M + sg[j].m_off + sg[j].r0 + min(lane, sg[j].nr - 1);
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) mv[j][kk] = col[(long long)min(sg[j].k0 + kk, sg[j].k1 - 1) * sg[j].ld];
+      }
+#pragma unroll
+      for (int j = 0; j < NSEG; ++j) {
+        C acc = mk((R)0, (R)0);
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk)
+          if (sg[j].k0 + kk < sg[j].k1) acc += cmul_conj(mv[j][kk], work[sg[j].vslot + sg[j].k0 + kk], conj);
+        if (s0 + j * nw < S.s1) work[sg[j].pslot + lane] = acc;
+      }
+    }
+    __syncthreads();
+    for (int o = S.o0 + wv; o < S.o1; o += nw) {
+      const NDOut ob = lo[o];
+      if (lane < ob.nr) {
+        C acc = mk((R)0, (R)0);
+        for (int q = 0; q < ob.nparts; ++q) acc += work[ob.pslot + 64 * q + lane];
+        const int d = ldst[ob.d + lane];
+        if (FWD) {
+          if (d >= 0)
+            x[d] = acc;
+          else
+            upd[-d - 1] = work[ob.vslot + ob.r0 + lane] - acc;
+        } else {
+          x[d] = x[d] + acc;
+        }
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -578,38 +613,51 @@ void nd_finalize(const NDFrontDev* fr, const int* ids, int nids, long long max_n
   unsigned gx = (unsigned)std::min<long long>(1024, std::max<long long>(1, (max_n + 255) / 256));
   hipLaunchKernelGGL((k_nd_finalize<C>), dim3(gx, nids), dim3(256), 0, s, fr, ids, Fp, perm, Lp, Wp);
 }
+// LDS bytes above the default limit need the attribute on the kernel
+template <typename C, int FWD>
+static void tree_attr(size_t lds) {
+  if (lds > 65536)
+    (void)hipFuncSetAttribute((const void*)k_nd_tree<C, FWD>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
 template <typename C>
-void nd_fwd(int kind, int ntasks, size_t lds, const NDFrontDev* fr, const int* idx, const int* cptr,
-            const int* cidx, const C* Lp, C* upd, const int* task_off, const NDItem* items, const C* r, C* x,
-            C* gvec, int cap, int conj, hipStream_t s) {
-  if (kind == 0)
-    hipLaunchKernelGGL((k_nd_fwd_small<C>), dim3(ntasks), dim3(256), lds, s, fr, idx, cptr, cidx, Lp, upd, task_off,
-                       items, r, x, gvec, cap, conj);
-  else
-    hipLaunchKernelGGL((k_nd_fwd_big<C>), dim3(ntasks), dim3(256), lds, s, fr, idx, cptr, cidx, Lp, upd, items, r, x,
-                       gvec, cap, conj);
+void nd_fwd(const NDLaunchDev& L, const NDFrontDev* fr, const int* idx, const int* cptr, const int* cidx,
+            const C* Lp, C* upd, const C* r, C* x, C* gvec, int cap, int conj, hipStream_t s) {
+  if (L.kind == 2) {
+    size_t lds = (size_t)L.lds_bytes;
+    tree_attr<C, 1>(lds);
+    hipLaunchKernelGGL((k_nd_tree<C, 1>), dim3(L.ntasks), dim3(L.threads), lds, s, L.tasks, L.stages, L.gath,
+                       L.segs, L.outs, L.dst, cidx, Lp, upd, r, x, conj);
+  } else {
+    hipLaunchKernelGGL((k_nd_fwd_big<C>), dim3(L.ntasks), dim3(256), L.shm, s, fr, idx, cptr, cidx, Lp, upd,
+                       L.items, r, x, gvec, cap, conj);
+  }
 }
 template <typename C>
-void nd_bwd(int kind, int ntasks, size_t lds, const NDFrontDev* fr, const int* idx, const C* Wp, const int* task_off,
-            const NDItem* items, C* x, C* gvec, int cap, int conj, hipStream_t s) {
-  if (kind == 0)
-    hipLaunchKernelGGL((k_nd_bwd_small<C>), dim3(ntasks), dim3(256), lds, s, fr, idx, Wp, task_off, items, x, gvec,
-                       cap, conj);
-  else
-    hipLaunchKernelGGL((k_nd_bwd_big<C>), dim3(ntasks), dim3(256), lds, s, fr, idx, Wp, items, x, gvec, cap, conj);
+void nd_bwd(const NDLaunchDev& L, const NDFrontDev* fr, const int* idx, const int* cidx, const C* Wp, C* upd, C* x,
+            C* gvec, int cap, int conj, hipStream_t s) {
+  if (L.kind == 2) {
+    size_t lds = (size_t)L.lds_bytes;
+    tree_attr<C, 0>(lds);
+    hipLaunchKernelGGL((k_nd_tree<C, 0>), dim3(L.ntasks), dim3(L.threads), lds, s, L.tasks, L.stages, L.gath,
+                       L.segs, L.outs, L.dst, cidx, Wp, upd, (const C*)x, x, conj);
+  } else {
+    hipLaunchKernelGGL((k_nd_bwd_big<C>), dim3(L.ntasks), dim3(256), L.shm, s, fr, idx, Wp, L.items, x, gvec, cap,
+                       conj);
+  }
 }
 
 template void nd_finalize<cf>(const NDFrontDev*, const int*, int, long long, const cd*, const int*,
                                   cf*, cf*, hipStream_t);
 template void nd_finalize<cd>(const NDFrontDev*, const int*, int, long long, const cd*, const int*,
                                    cd*, cd*, hipStream_t);
-template void nd_fwd<cf>(int, int, size_t, const NDFrontDev*, const int*, const int*, const int*, const cf*, cf*,
-                         const int*, const NDItem*, const cf*, cf*, cf*, int, int, hipStream_t);
-template void nd_fwd<cd>(int, int, size_t, const NDFrontDev*, const int*, const int*, const int*, const cd*, cd*,
-                         const int*, const NDItem*, const cd*, cd*, cd*, int, int, hipStream_t);
-template void nd_bwd<cf>(int, int, size_t, const NDFrontDev*, const int*, const cf*, const int*, const NDItem*, cf*,
-                         cf*, int, int, hipStream_t);
-template void nd_bwd<cd>(int, int, size_t, const NDFrontDev*, const int*, const cd*, const int*, const NDItem*, cd*,
-                         cd*, int, int, hipStream_t);
+template void nd_fwd<cf>(const NDLaunchDev&, const NDFrontDev*, const int*, const int*, const int*, const cf*, cf*,
+                         const cf*, cf*, cf*, int, int, hipStream_t);
+template void nd_fwd<cd>(const NDLaunchDev&, const NDFrontDev*, const int*, const int*, const int*, const cd*, cd*,
+                         const cd*, cd*, cd*, int, int, hipStream_t);
+template void nd_bwd<cf>(const NDLaunchDev&, const NDFrontDev*, const int*, const int*, const cf*, cf*, cf*, cf*, int,
+                         int, hipStream_t);
+template void nd_bwd<cd>(const NDLaunchDev&, const NDFrontDev*, const int*, const int*, const cd*, cd*, cd*, cd*, int,
+                         int, hipStream_t);
 
 }  // namespace helm

@@ -94,7 +94,8 @@ struct Builder {
 
 }  // namespace
 
-void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int subtree_nodes, int root_merge, NDPlan& plan) {
+void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int root_merge, int elem_bytes, int lds_bytes,
+             const std::vector<int>& cuts, NDPlan& plan) {
   Builder bd;
   bd.g = g3;
   bd.leaf_max = std::max(leaf_max, 1);
@@ -278,59 +279,248 @@ void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int subtree_nodes, in
     Tmax = std::max(Tmax, s);
   }
   plan.T_scratch = Tmax;
-  std::vector<long long> subn(nf, 0);
-  for (int t = nf - 1; t >= 0; --t) {
-    subn[t] = plan.fronts[t].nS;
-    for (int c : kids[t]) subn[t] += subn[c];
-  }
 
   // ---------------- solve schedules ----------------
-  // fronts of height <= hcut are handled by one work-group per subtree, stage by
-  // stage (heights ascending forward, descending backward) with one front per
-  // wavefront; higher fronts by one launch per height with chunks of rows_chunk rows.
-  int hcut = -1;
-  for (int h = 0; h <= plan.max_height; ++h) {
-    bool ok = true;
-    for (int t : plan.by_height[h]) ok = ok && subn[t] <= subtree_nodes && plan.fronts[t].nF <= 1024;
-    if (!ok) break;
-    hcut = h;
+  // The lower part of the tree runs as tree-block launches: launch (c, b] gives every
+  // subtree of fronts with height in (c, b] to one work-group, which walks it level by
+  // level (forward ascending, backward descending) with work-group barriers.  Fronts
+  // above the last cut run one multi-block launch per height (rows_chunk rows per
+  // work-group).  The cuts minimise a cost model of launch and level latencies and of
+  // the bandwidth one work-group (tree blocks) or the whole chip (multi-block) can pull.
+  const int H = plan.max_height;
+  const int KS = 16;                                   // k range of one segment
+  auto nparts = [&](int K) { return std::max(1, (K + KS - 1) / KS); };
+  auto al16 = [](long long v) { return (v + 15) / 16 * 16; };
+  // LDS of one front in a stage: work entries (vector + partials) and schedule bytes
+  auto work_entries = [&](const NDFrontDev& f, int dir) -> long long {
+    const int R = dir == 0 ? f.nF : f.nS, K = dir == 0 ? f.nS : f.nB;
+    if (R == 0 || K == 0) return 0;
+    return (long long)(dir == 0 ? f.nF : f.nB) + 64LL * ((R + 63) / 64) * nparts(K);
+  };
+  auto sched_bytes = [&](const NDFrontDev& f, int dir) -> long long {
+    const int R = dir == 0 ? f.nF : f.nS, K = dir == 0 ? f.nS : f.nB;
+    if (R == 0 || K == 0) return 0;
+    const long long rb = (R + 63) / 64;
+    return (long long)sizeof(NDGather) * (dir == 0 ? f.nF : f.nB) + (long long)sizeof(NDSeg) * rb * nparts(K) +
+           (long long)sizeof(NDOut) * rb + 4LL * R + (long long)sizeof(NDStage);
+  };
+  std::vector<double> fbytes(nf);
+  for (int t = 0; t < nf; ++t) {
+    const NDFrontDev& f = plan.fronts[t];
+    fbytes[t] = (double)elem_bytes * ((double)f.nF * f.nS + (double)f.nS * f.nB) + 24.0 * (f.nF + f.nB);
   }
+  // launch latency, latency of one level of a tree block (gather, products, outputs and
+  // their barriers), bandwidth of one tree-block work-group, of the chip and of one
+  // multi-block work-group; per direction
+  const double a_launch = 3e-6, a_stage = 5e-6, bw_block = 30e9, bw_chip = 4e12, bw_chunk = 40e9;
+  // task root of front t for cut b: its highest ancestor (itself included) of height <= b
+  auto task_root = [&](int t, int b) {
+    while (par[t] >= 0 && plan.fronts[par[t]].height <= b) t = par[t];
+    return t;
+  };
+  // fronts of heights (c, b] grouped by task; empty if some task does not fit in LDS
+  auto group = [&](int c, int b, std::vector<std::vector<int>>& tasks) -> bool {
+    tasks.clear();
+    std::vector<int> rootid(nf, -1);
+    for (int t = 0; t < nf; ++t) {
+      int h = plan.fronts[t].height;
+      if (h <= c || h > b) continue;
+      int r = task_root(t, b);
+      if (rootid[r] < 0) {
+        rootid[r] = (int)tasks.size();
+        tasks.emplace_back();
+      }
+      tasks[rootid[r]].push_back(t);
+    }
+    for (auto& tk : tasks)
+      for (int dir = 0; dir < 2; ++dir) {
+        long long sch = 0;
+        std::vector<long long> work(H + 1, 0);
+        for (int t : tk) {
+          sch += sched_bytes(plan.fronts[t], dir);
+          work[plan.fronts[t].height] += work_entries(plan.fronts[t], dir);
+        }
+        long long wmax = *std::max_element(work.begin(), work.end());
+        if (al16(sch) + 6 * 16 + wmax * elem_bytes > lds_bytes) return false;
+      }
+    return !tasks.empty();
+  };
+  auto cost_tree = [&](int c, int b) -> double {       // +inf if a task does not fit
+    std::vector<std::vector<int>> tasks;
+    if (!group(c, b, tasks)) return 1e30;
+    double tot = 2.0 * a_launch;
+    for (int h = c + 1; h <= b; ++h) {
+      double mx = 0.0;
+      bool any = false;
+      for (auto& tk : tasks) {
+        double acc = 0.0;
+        for (int t : tk)
+          if (plan.fronts[t].height == h) {
+            acc += fbytes[t];
+            any = true;
+          }
+        mx = std::max(mx, acc);
+      }
+      if (any) tot += 2.0 * a_stage + mx / bw_block;
+    }
+    return tot;
+  };
+  auto cost_chunks = [&](int h) -> double {
+    double by = 0.0, blocks = 0.0;
+    for (int t : plan.by_height[h]) {
+      by += fbytes[t];
+      blocks += (plan.fronts[t].nF + rows_chunk - 1) / rows_chunk;
+    }
+    if (plan.by_height[h].empty()) return 0.0;
+    return 2.0 * (a_launch + a_stage) + by / std::min(bw_chip, blocks * bw_chunk);
+  };
+  std::vector<int> cut;
+  if (!cuts.empty()) {
+    // requested cuts, ascending, up to the first whose tasks would not fit in LDS
+    std::vector<std::vector<int>> tmp;
+    for (int c : cuts) {
+      if (c < 0 || c > H || (!cut.empty() && c <= cut.back())) continue;
+      if (!group(cut.empty() ? -1 : cut.back(), c, tmp)) break;
+      cut.push_back(c);
+    }
+  } else {
+    // best[b + 1]: cost of tree-block launches covering heights <= b, from[]: its last cut
+    std::vector<double> best(H + 2, 1e30);
+    std::vector<int> from(H + 2, -2);
+    best[0] = 0.0;
+    for (int b = 0; b <= H; ++b)
+      for (int c = -1; c < b; ++c) {
+        if (best[c + 1] >= 1e29) continue;
+        double v = best[c + 1] + cost_tree(c, b);
+        if (v < best[b + 1]) {
+          best[b + 1] = v;
+          from[b + 1] = c;
+        }
+      }
+    std::vector<double> chunks(H + 2, 0.0);        // multi-block launches of heights > e
+    for (int h = H; h >= 0; --h) chunks[h] = chunks[h + 1] + cost_chunks(h);
+    double bestv = 1e30;
+    int beste = -1;
+    for (int e = -1; e <= H; ++e) {
+      double v = best[e + 1] + chunks[e + 1];
+      if (v < bestv) {
+        bestv = v;
+        beste = e;
+      }
+    }
+    for (int e = beste; e >= 0; e = from[e + 1]) cut.push_back(e);
+    std::reverse(cut.begin(), cut.end());
+  }
+  plan.cuts = cut;
+
   plan.fwd.clear();
   plan.bwd.clear();
-  if (hcut >= 0) {
+  std::vector<NDLaunch> bwd_tree;
+  int lo = -1;
+  for (int b : cut) {
+    std::vector<std::vector<int>> tasks;
+    group(lo, b, tasks);
     NDLaunch fl, bl;
-    fl.kind = bl.kind = 0;
-    fl.task_off.push_back(0);
-    bl.task_off.push_back(0);
-    for (int t = 0; t < nf; ++t) {
-      bool root = plan.fronts[t].height <= hcut && (par[t] < 0 || plan.fronts[par[t]].height > hcut);
-      if (!root) continue;
-      std::vector<int> sub;
-      std::function<void(int)> walk = [&](int u) {
-        sub.push_back(u);
-        for (int c : kids[u]) walk(c);
-      };
-      walk(t);
-      std::stable_sort(sub.begin(), sub.end(),
-                       [&](int a, int b) { return plan.fronts[a].height < plan.fronts[b].height; });
-      for (int u : sub) {
-        const NDFrontDev& f = plan.fronts[u];
-        fl.items.push_back({u, 0, f.nF, f.height});
-        fl.max_rows_vec = std::max(fl.max_rows_vec, f.nF);
+    fl.kind = bl.kind = 2;
+    fl.threads = bl.threads = 64;
+    for (auto& tk : tasks) {
+      for (int dir = 0; dir < 2; ++dir) {
+        NDLaunch& L = dir == 0 ? fl : bl;
+        NDTask T;
+        T.st0 = (int)L.stages.size();
+        T.g0 = (int)L.gath.size();
+        T.s0 = (int)L.segs.size();
+        T.o0 = (int)L.outs.size();
+        T.d0 = (int)L.dst.size();
+        std::vector<std::vector<int>> byh(b + 1);
+        for (int u : tk) byh[plan.fronts[u].height].push_back(u);
+        long long wmax = 0;
+        for (int step = 0; step <= b - lo - 1; ++step) {
+          const int h = dir == 0 ? lo + 1 + step : b - step;
+          NDStage st{(int)L.gath.size() - T.g0, 0, (int)L.segs.size() - T.s0, 0, (int)L.outs.size() - T.o0, 0};
+          int vs = 0;
+          long long vec_total = 0;
+          for (int u : byh[h]) vec_total += work_entries(plan.fronts[u], dir) > 0
+                                                ? (dir == 0 ? plan.fronts[u].nF : plan.fronts[u].nB) : 0;
+          int ps = (int)vec_total;
+          for (int u : byh[h]) {
+            const NDFrontDev& f = plan.fronts[u];
+            const int R = dir == 0 ? f.nF : f.nS, K = dir == 0 ? f.nS : f.nB;
+            if (R == 0 || K == 0) continue;
+            const int* ids = plan.idx.data() + f.idx_off;
+            if (dir == 0) {
+              for (int i = 0; i < f.nF; ++i) {
+                int ca = plan.cptr[f.inv_off + i], cb = plan.cptr[f.inv_off + i + 1];
+                NDGather g{vs + i, i < f.nS ? ids[i] : -1, -1, -1, 0, 0};
+                if (ca < cb) g.u0 = plan.cidx[ca++];
+                if (ca < cb) g.u1 = plan.cidx[ca++];
+                g.ca = ca;
+                g.cb = cb;
+                L.gath.push_back(g);
+              }
+            } else {
+              for (int j = 0; j < f.nB; ++j) L.gath.push_back({vs + j, ids[f.nS + j], -1, -1, 0, 0});
+            }
+            const int np = nparts(K);
+            for (int r0 = 0; r0 < R; r0 += 64) {
+              const int nr = std::min(64, R - r0);
+              for (int p = 0; p < np; ++p) {
+                NDSeg sg;
+                sg.m_off = dir == 0 ? f.L_off : f.W_off;
+                sg.ld = dir == 0 ? f.nF : f.nS;
+                sg.r0 = r0;
+                sg.nr = nr;
+                sg.k0 = p * KS;
+                sg.k1 = std::min(K, (p + 1) * KS);
+                sg.vslot = vs;
+                sg.pslot = ps + 64 * p;
+                sg.pad = 0;
+                L.segs.push_back(sg);
+              }
+              L.outs.push_back({r0, nr, vs, ps, np, (int)L.dst.size() - T.d0});
+              for (int i = r0; i < r0 + nr; ++i)
+                L.dst.push_back(dir == 1 || i < f.nS ? ids[i] : -(int)(f.upd_off + i - f.nS) - 1);
+              ps += 64 * np;
+            }
+            vs += dir == 0 ? f.nF : f.nB;
+          }
+          st.g1 = (int)L.gath.size() - T.g0;
+          st.s1 = (int)L.segs.size() - T.s0;
+          st.o1 = (int)L.outs.size() - T.o0;
+          wmax = std::max<long long>(wmax, ps);
+          if (st.s1 > st.s0) L.stages.push_back(st);
+        }
+        T.st1 = (int)L.stages.size();
+        T.g1 = (int)L.gath.size();
+        T.s1 = (int)L.segs.size();
+        T.o1 = (int)L.outs.size();
+        T.d1 = (int)L.dst.size();
+        const long long sch = al16((long long)sizeof(NDStage) * (T.st1 - T.st0)) +
+                              al16((long long)sizeof(NDGather) * (T.g1 - T.g0)) +
+                              al16((long long)sizeof(NDSeg) * (T.s1 - T.s0)) +
+                              al16((long long)sizeof(NDOut) * (T.o1 - T.o0)) + al16(4LL * (T.d1 - T.d0));
+        const long long need = sch + wmax * elem_bytes;
+        if (need > lds_bytes) throw std::runtime_error("nd_plan: tree-block task exceeds LDS");
+        if (T.st1 > T.st0) {
+          L.tasks.push_back(T);
+          L.lds_bytes = std::max<int>(L.lds_bytes, (int)need);
+          // wavefronts: one per segment of the widest stage, at most 16
+          const int per = 1;
+          for (int st = T.st0; st < T.st1; ++st) {
+            const int ns = L.stages[st].s1 - L.stages[st].s0;
+            L.threads = std::max(L.threads, 64 * std::min(16, (ns + per - 1) / per));
+          }
+        }
       }
-      for (auto it = sub.rbegin(); it != sub.rend(); ++it) {
-        const NDFrontDev& f = plan.fronts[*it];
-        bl.items.push_back({*it, 0, f.nS, f.height});
-        bl.max_rows_vec = std::max(bl.max_rows_vec, f.nB);
-      }
-      fl.task_off.push_back((int)fl.items.size());
-      bl.task_off.push_back((int)bl.items.size());
     }
+    fl.task_off.assign(1, 0);
+    bl.task_off.assign(1, 0);
     plan.fwd.push_back(fl);
-    plan.bwd.push_back(bl);
+    bwd_tree.push_back(bl);
+    lo = b;
   }
   std::vector<NDLaunch> bwd_high;
-  for (int h = hcut + 1; h <= plan.max_height; ++h) {
+  for (int h = lo + 1; h <= plan.max_height; ++h) {
     NDLaunch fl, bl;
     fl.kind = bl.kind = 1;
     fl.task_off.push_back(0);
@@ -353,7 +543,8 @@ void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int subtree_nodes, in
     if (!bl.items.empty()) bwd_high.push_back(bl);
   }
   std::vector<NDLaunch> bwd_all(bwd_high.rbegin(), bwd_high.rend());
-  for (auto& l : plan.bwd) bwd_all.push_back(l);
+  for (auto it = bwd_tree.rbegin(); it != bwd_tree.rend(); ++it)
+    if (!it->tasks.empty()) bwd_all.push_back(*it);
   plan.bwd = bwd_all;
 }
 

@@ -198,12 +198,15 @@ class Solver:
         return g
 
     INFO_KEYS = ("N1", "N2", "N3", "fronts", "L_entries", "W_entries", "upd_entries", "sep_entries",
-                 "fwd_launches", "bwd_launches", "workspace_bytes", "max_front", "cycle_complex_bytes")
+                 "fwd_launches", "bwd_launches", "workspace_bytes", "max_front", "cycle_complex_bytes",
+                 "nd_leaf", "nd_root", "nd_tuned", "nd_tree_launches")
 
     def info(self) -> dict:
-        v = (C.c_longlong * 13)()
-        L.check(L.lib.helm_get_info(self.ctx, v, 13), "helm_get_info")
-        return {k: int(v[i]) for i, k in enumerate(self.INFO_KEYS)}
+        v = (C.c_longlong * 21)()
+        L.check(L.lib.helm_get_info(self.ctx, v, 21), "helm_get_info")
+        out = {k: int(v[i]) for i, k in enumerate(self.INFO_KEYS)}
+        out["nd_cuts"] = [int(v[17 + i]) for i in range(min(4, out["nd_tree_launches"]))]
+        return out
 
     def set_timing(self, on: bool = True):
         L.lib.helm_set_timing(self.ctx, 1 if on else 0)

@@ -1,0 +1,143 @@
+"""Autotuner of the coarsest-solve schedule.
+
+The exact coarsest solve (nested dissection, see csrc/nd_plan.cpp) has three schedule
+parameters that change its speed but not its result: the leaf box size, the size up to
+which the top separators are merged into one root front, and the tree heights at which
+the tree-block launches end (HELM_ND_CUTS).  For a grid shape and cycle precision this
+tool times FGMRES iterations of a seeded problem of that shape under every candidate
+schedule and records the best-scoring one in a JSON cache, which libhelm reads when it plans a
+context of that shape (file named by HELM_TUNE_CACHE; the package sets it to
+tune_cache.json next to the library unless the caller set it).
+
+    python -m paper_2604_19501_amd.tune --n 1024 1024 --prec f32 [--its 150] [--out FILE]
+
+Each candidate is scored by its numerical set-up time (coefficients, Galerkin operators,
+factorisation) plus --its times its per-iteration time: a larger root front shortens the
+substitutions but lengthens the factorisation.  Both times are minima over repeats,
+after a warm-up (which also captures the per-iteration graphs).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import time
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from .solver import Solver
+
+
+def _candidates(dim: int):
+    if dim == 2:
+        leaves, roots = (16, 32, 64), (600, 1100, 2200)
+    else:
+        leaves, roots = (8, 16), (1,)
+    cuts = ["", "none"] + [str(h) for h in range(0, 7)] + ["2,4", "3,5", "2,5", "3,6", "1,3"]
+    for leaf in leaves:
+        for root in roots:
+            for c in cuts:
+                yield leaf, root, c
+
+
+def _problem(n, G=10.0, layer=8):
+    """homogeneous medium, G points per wavelength, absorbing layer on every face; the
+    schedule's cost does not depend on the medium's values."""
+    dim = len(n)
+    h = 1.0 / max(n)
+    kappa = np.ones(tuple(k + 1 for k in reversed(n)))
+    omega = 2.0 * math.pi / (G * h)
+    return dim, h, kappa, omega, tuple((layer, layer) for _ in range(dim))
+
+
+def time_schedule(n, prec, leaf, root, cuts, iters=30, repeats=2):
+    """(seconds per FGMRES iteration, seconds per numerical set-up, plan info)"""
+    env = {"HELM_ND_LEAF": str(leaf), "HELM_ND_ROOT": str(root), "HELM_ND_CUTS": cuts}
+    saved = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
+    try:
+        dim, h, kappa, omega, layer = _problem(n)
+        s = Solver(n, h, kappa, omega, layer=layer, sigma_max=2.0, alpha=1.1, alpha2=1.0, beta=0.1,
+                   nu=(1, 1), cycle_prec=prec)
+        info = s.info()
+        q = np.zeros(int(np.prod([k + 1 for k in n])), np.complex128)
+        q[q.size // 2] = 1.0
+        s.solve(q, tol=1e-300, max_iter=iters)
+        best, setup = float("inf"), float("inf")
+        for _ in range(repeats):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, it = s.solve(q, tol=1e-300, max_iter=iters)
+            torch.cuda.synchronize()
+            best = min(best, (time.perf_counter() - t0) / max(1, it["iterations"]))
+            t0 = time.perf_counter()
+            s.refactor()
+            torch.cuda.synchronize()
+            setup = min(setup, time.perf_counter() - t0)
+        s.close()
+        return best, setup, info
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+        torch.cuda.empty_cache()
+
+
+def tune(n, prec="f32", out=None, its=150, verbose=True):
+    n = tuple(int(k) for k in n)
+    dim = len(n)
+    key = "nd:%d:%s:%s" % (dim, "x".join(str(k) for k in (n + (0,) * (3 - dim))), prec)
+    results, seen = [], set()
+    for leaf, root, cuts in _candidates(dim):
+        try:
+            t, ts, info = time_schedule(n, prec, leaf, root, cuts)
+        except L.HelmError as e:
+            if verbose:
+                print("  leaf %d root %d cuts %r: %s" % (leaf, root, cuts, e), flush=True)
+            continue
+        eff = (leaf, root, tuple(info["nd_cuts"]))
+        if eff in seen:            # the planner dropped cuts that do not fit: same schedule
+            continue
+        seen.add(eff)
+        results.append({"leaf": leaf, "root": root, "cuts": ",".join(map(str, info["nd_cuts"])) or "none",
+                        "us_per_it": round(t * 1e6, 2), "setup_ms": round(ts * 1e3, 3),
+                        "score_ms": round((ts + its * t) * 1e3, 3)})
+        if verbose:
+            print("  leaf %3d root %5d cuts %-8s -> %8.1f us/iteration, set-up %8.2f ms, score %8.2f ms" % (
+                leaf, root, results[-1]["cuts"], t * 1e6, ts * 1e3, results[-1]["score_ms"]), flush=True)
+    results.sort(key=lambda r: r["score_ms"])
+    best = dict(results[0])
+    best["device"] = torch.cuda.get_device_name(0)
+    best["score"] = "setup + %d iterations" % its
+    best["runners_up"] = results[1:6]
+    path = out or os.environ.get("HELM_TUNE_CACHE") or L.TUNE_CACHE
+    cache = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            cache = json.load(f)
+    cache[key] = best
+    with open(path, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    if verbose:
+        print("%s -> leaf %d root %d cuts %s (%.1f us/iteration, set-up %.2f ms), written to %s" % (
+            key, best["leaf"], best["root"], best["cuts"], best["us_per_it"], best["setup_ms"], path), flush=True)
+    return key, best
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n", type=int, nargs="+", required=True, help="cells per axis (2 or 3 values)")
+    ap.add_argument("--prec", choices=("f32", "f64"), default="f32")
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--its", type=int, default=150, help="iterations per set-up in the score")
+    a = ap.parse_args()
+    tune(a.n, a.prec, a.out, a.its)
+
+
+if __name__ == "__main__":
+    main()

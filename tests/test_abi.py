@@ -67,3 +67,28 @@ def test_setup_rejects_bad_arguments_before_device_work():
     assert L.lib.helm_destroy(None) == 0
     assert L.lib.helm_apply(None, 0, 0, None, None, None) == L.HELM_EINVAL
     assert L.lib.helm_solve(None, 0, None, None, 1e-6, 10, None, None) == L.HELM_EINVAL
+
+
+def test_tuning_cache_changes_the_plan(tmp_path, monkeypatch):
+    """the coarsest-solve schedule is read from the autotuner's cache when the context is
+    planned (visible on the CPU through the workspace size, which depends on the leaf size)."""
+    import json
+    def ws():
+        st, b = _bytes((256, 256), cycle_prec="f32")
+        assert st == 0
+        return b
+    monkeypatch.delenv("HELM_TUNE_CACHE", raising=False)
+    base = ws()
+    path = tmp_path / "cache.json"
+    key = "nd:2:256x256x0:f32"
+    sizes = {}
+    for leaf in (16, 64):
+        path.write_text(json.dumps({key: {"leaf": leaf, "root": 1100, "cuts": "1"}}))
+        monkeypatch.setenv("HELM_TUNE_CACHE", str(path))
+        sizes[leaf] = ws()
+    assert sizes[16] != sizes[64]
+    monkeypatch.setenv("HELM_TUNE_CACHE", str(tmp_path / "missing.json"))
+    assert ws() == base
+    path.write_text("{ not json")
+    monkeypatch.setenv("HELM_TUNE_CACHE", str(path))
+    assert ws() == base

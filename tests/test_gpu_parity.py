@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 import torch
 
+import synth
 from tests.gpu_helpers import oracle_hierarchy, rect_problem, rel, small_problem, stencil_arrays
 
 pytestmark = pytest.mark.gpu
@@ -65,6 +66,38 @@ def test_coarse_solve(case, prec, tol):
     assert rel(e, H.lu3.solve(r)) < tol
     ec = s.coarse_solve(r, op=HELM_OP_C).cpu().numpy()
     assert rel(ec, np.conj(H.lu3.solve(np.conj(r)))) < tol
+
+
+@pytest.mark.parametrize("dim,n", [(2, 256), (3, 64)])
+@pytest.mark.parametrize("cuts", ["none", "", "1", "0,1,2,3"])
+def test_coarse_solve_schedules(monkeypatch, dim, n, cuts):
+    """the exact coarsest solve under every kind of substitution schedule: multi-block
+    launches only, the planner's choice, one tree-block launch, one per level."""
+    monkeypatch.setenv("HELM_ND_CUTS", cuts)
+    p = synth.config2(n) if dim == 2 else synth.config3(n)
+    print("coarse schedule", dim, n, repr(cuts), flush=True)
+    H = oracle_hierarchy(p, nu_pre=1, nu_post=1)
+    for prec, tol in (("f64", 1e-10), ("f32", 1e-4)):
+        s = from_problem(p, nu=(1, 1), cycle_prec=prec)
+        r = _rand(s.level_size(3), 4)
+        e = s.coarse_solve(r).cpu().numpy()
+        assert rel(e, H.lu3.solve(r)) < tol, (prec, rel(e, H.lu3.solve(r)))
+        ec = s.coarse_solve(r, op=HELM_OP_C).cpu().numpy()
+        assert rel(ec, np.conj(H.lu3.solve(np.conj(r)))) < tol
+        s.close()
+
+
+def test_coarse_solve_full_size_2d():
+    """the coarsest level of the 1024^2 layered workload (66049 unknowns)."""
+    p = synth.config2(1024)
+    H = oracle_hierarchy(p)
+    r = _rand(H.lu3.shape[0], 12)
+    ref = H.lu3.solve(r)
+    for prec, tol in (("f64", 1e-10), ("f32", 1e-4)):
+        s = from_problem(p, nu=(1, 1), cycle_prec=prec)
+        e = s.coarse_solve(r).cpu().numpy()
+        assert rel(e, ref) < tol, (prec, rel(e, ref))
+        s.close()
 
 
 @pytest.mark.parametrize("cycle,nu", [(2, (1, 1)), (2, (2, 2)), (1, (1, 1)), (2, (0, 1)), (2, (1, 0))])
