@@ -97,7 +97,8 @@ class Hierarchy:
 def from_problem(prob, conj=False, **kw) -> Hierarchy:
     args = dict(alpha=prob.alpha, alpha2=getattr(prob, "alpha2", 1.0), beta=prob.beta, cycle=prob.cycle,
                 nu_pre=prob.nu_pre,
-                nu_post=prob.nu_post, jacobi=(prob.jacobi, prob.jacobi))
+                nu_post=prob.nu_post,
+                jacobi=tuple(prob.jacobi) if np.ndim(prob.jacobi) else (prob.jacobi, prob.jacobi))
     args.update(kw)
     return Hierarchy(prob.n, prob.h, prob.slowness ** 2, prob.omega, prob.layer, prob.sigma_max,
                      conj=conj, **args)

@@ -33,7 +33,7 @@ from .solver import Solver
 
 def _candidates(dim: int):
     if dim == 2:
-        leaves, roots = (16, 32, 64), (600, 1100, 2200)
+        leaves, roots = (16, 32, 64), (100, 300, 600, 1100, 2200)
     else:
         leaves, roots = (8, 16), (1,)
     cuts = ["", "none"] + [str(h) for h in range(0, 7)] + ["2,4", "3,5", "2,5", "3,6", "1,3"]

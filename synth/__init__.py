@@ -142,7 +142,7 @@ class Problem:
     cycle: int = 2          # 1 = V, 2 = W
     nu_pre: int = 2
     nu_post: int = 2
-    jacobi: float = 0.8
+    jacobi: object = 0.8    # damping weight, or (level 1, level 2)
     restart: int = 20
     tol: float = 1e-6
 
@@ -199,6 +199,12 @@ def config2(n: int = 1024, seed: int = 2000) -> Problem:
                    alpha2=alpha2_for(2, G), nu_pre=1, nu_post=1)
 
 
+# 3D workloads: the paper's 3D smoothing (W(1,1), damping 0.6 on level 1 and 0.4 on level 2,
+# Sec. 5.2) with a modest complex shift of the preconditioner
+CFG3_JACOBI = (0.6, 0.4)
+CFG3_BETA = 0.05
+
+
 def config3(n: int = 256, seed: int = 3000) -> Problem:
     """3D layered: 6 layers + noise smoothed over 8 cells, G = 12, 12-cell layer on five faces
     (none on the top face), one source 10 cells below the centre of the top face."""
@@ -209,8 +215,8 @@ def config3(n: int = 256, seed: int = 3000) -> Problem:
     L = 12 if n >= 64 else max(2, (12 * n) // 256 + 2)
     depth = min(10, n // 2)
     return Problem("cfg3_3d_layered_%d" % n, dim, (n, n, n), h, kap, omega_for_G(G, h, kap.max()),
-                   ((L, L), (L, L), (0, L)), SIGMA_MAX, alpha_for(dim, G), 0.0,
-                   [(n // 2, n // 2, depth)], G)
+                   ((L, L), (L, L), (0, L)), SIGMA_MAX, alpha_for(dim, G), CFG3_BETA,
+                   [(n // 2, n // 2, depth)], G, nu_pre=1, nu_post=1, jacobi=CFG3_JACOBI)
 
 
 CFG4_SIZES = (256, 512, 768)
@@ -251,7 +257,8 @@ def config5(n: int = 128, seed: int = 5000, smooth_cells: float = 16.0):
     srcs = [(a, b, 0) for b in lat for a in lat]
     kmax = max(kap_ref.max(), kap0.max())
     prob = Problem("cfg5_3d_grad_%d" % n, dim, (n, n, n), h, kap0, omega_for_G(G, h, kmax),
-                   ((L, L), (L, L), (0, L)), SIGMA_MAX, alpha_for(dim, G), 0.0, srcs, G)
+                   ((L, L), (L, L), (0, L)), SIGMA_MAX, alpha_for(dim, G), CFG3_BETA, srcs, G,
+                   nu_pre=1, nu_post=1, jacobi=CFG3_JACOBI)
     rec = np.array([flat_index((n, n, n), (i0, i1, 0)) for i1 in range(n + 1) for i0 in range(n + 1)],
                    dtype=np.int64)
     return prob, m_ref, rec
