@@ -29,8 +29,8 @@ void nd_assemble(const NDFrontDev* fr, const int* ids, int nids, int max_asm, co
                  cd* Fp, hipStream_t s);
 void nd_extend(const NDFrontDev* fr, const int* ids, int nids, long long max_nb2, const int* children,
                const long long* child_map_off, const int* maps, cd* Fp, int slot, hipStream_t s);
-void nd_panel(const NDFrontDev* fr, const int* ids, int nids, cd* Fp, int* perm, int k0, int kb, int* err,
-              hipStream_t s);
+void nd_panel_multi(const NDFrontDev* fr, const int* ids, int nids, int max_nF, cd* Fp, int* perm, int* swp,
+                    PivCand* cand, cd* rkb, int k0, int kb, int max_nS, int* err, hipStream_t s);
 void nd_save_t(const NDFrontDev* fr, const int* ids, int nids, const long long* toff, long long max_n, cd* Fp,
                cd* T, int k0, int kb, hipStream_t s);
 void nd_gemm(const NDFrontDev* fr, const int* ids, int nids, const long long* toff, int max_nF, cd* Fp,
@@ -98,7 +98,8 @@ struct NDDev {        // device-side ND tables (pointers into the workspace)
   long long* child_map_off = nullptr;
   NDAsm* asmv = nullptr;
   long long* toff = nullptr;
-  cd *F = nullptr, *T = nullptr;
+  cd *F = nullptr, *T = nullptr, *rkb = nullptr;
+  PivCand* cand = nullptr;
   void *L = nullptr, *W = nullptr, *upd = nullptr, *gvec = nullptr;
   std::vector<NDLaunchDev> launch[2];   // forward, backward
   int gvec_cap = 0;
@@ -359,8 +360,16 @@ size_t carve(helm_ctx* c, void* ws) {
   d.child_map_off = cv.take<long long>(std::max<size_t>(1, P.child_map_off.size()));
   {
     size_t mx = 1;
-    for (auto& h : P.by_height) mx = std::max(mx, h.size());
+    size_t nc = 1;     // pivot candidates of the multi-work-group panels: fronts x row blocks of 64
+    for (auto& h : P.by_height) {
+      mx = std::max(mx, h.size());
+      int mf = 0;
+      for (int t : h) mf = std::max(mf, P.fronts[t].nF);
+      nc = std::max(nc, h.size() * (size_t)((mf + 63) / 64));
+    }
     d.swp = cv.take<int>(32 * mx);
+    d.cand = cv.take<PivCand>(nc);
+    d.rkb = cv.take<cd>(33 * mx);
   }
   d.asmv = cv.take<NDAsm>(P.asmv.size());
   d.perm = cv.take<int>(P.perm_total);
@@ -454,7 +463,8 @@ void nd_factor(helm_ctx* c, hipStream_t s) {
       if (lds_panel)
         nd_panel_lds(d.fronts, ids, hi.count, hi.max_nF, d.F, d.perm, d.swp, k0, kb, d.err, s);
       else
-        nd_panel(d.fronts, ids, hi.count, d.F, d.perm, k0, kb, d.err, s);
+        nd_panel_multi(d.fronts, ids, hi.count, hi.max_nF, d.F, d.perm, d.swp, d.cand, d.rkb, k0, kb, hi.max_nS,
+                       d.err, s);
       nd_save_t(d.fronts, ids, hi.count, toff, hi.max_T, d.F, d.T, k0, kb, s);
       nd_gemm(d.fronts, ids, hi.count, toff, hi.max_nF, d.F, d.T, k0, kb, s);
     }
@@ -841,6 +851,9 @@ int helm_setup(const helm_grid* grid, const double* slowness, double omega, cons
       CK(hipGetDevice(&dev));
       CK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
       c->lds_panel = lds > 4096 ? (size_t)lds - 2048 : 0;
+      // HELM_ND_LDS_PANEL caps the LDS-resident panel (bytes; 0: every panel takes the
+      // multi-work-group path)
+      if (getenv("HELM_ND_LDS_PANEL")) c->lds_panel = std::min<size_t>(c->lds_panel, (size_t)env_int("HELM_ND_LDS_PANEL", 0));
       if (env_int("HELM_VERBOSE", 0)) fprintf(stderr, "helm: LDS per block %d bytes\n", lds);
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;

@@ -153,6 +153,11 @@ struct NDFrontDev {
   int pad;
 };
 
+struct PivCand {        // a row block's pivot candidate: largest |F[i][k]| and its row
+  double v;
+  int i, pad;
+};
+
 struct NDAsm {          // F[row][col] += coef[cidx]
   int row, col;
   long long cidx;

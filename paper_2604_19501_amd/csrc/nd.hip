@@ -55,84 +55,6 @@ __global__ void __launch_bounds__(256) k_nd_extend(const NDFrontDev* __restrict_
   }
 }
 
-// panel [k0, k0 + kbb) of every front of one height: one work-group per front
-__global__ void __launch_bounds__(256) k_nd_panel(const NDFrontDev* __restrict__ fr, const int* __restrict__ ids,
-                                                  cd* __restrict__ Fp, int* __restrict__ perm, int k0, int kb,
-                                                  int* __restrict__ err) {
-  const NDFrontDev f = fr[ids[blockIdx.x]];
-  if (f.nS <= k0) return;
-  const int kbb = min(kb, f.nS - k0);
-  const int nF = f.nF;
-  cd* F = Fp + f.F_off;
-  int* pm = perm + f.perm_off;
-  __shared__ double s_val[256];
-  __shared__ int s_idx[256];
-  __shared__ cd s_rk[64];
-  const int tid = threadIdx.x;
-  for (int k = k0; k < k0 + kbb; ++k) {
-    // pivot: largest |F[i][k]| among the not yet exchanged S rows i >= k
-    double best = -1.0;
-    int bi = k;
-    for (int i = k + tid; i < f.nS; i += blockDim.x) {
-      double v = abs2(F[(long long)i * nF + k]);
-      if (v > best) { best = v; bi = i; }
-    }
-    s_val[tid] = best;
-    s_idx[tid] = bi;
-    __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-      if (tid < w) {
-        double o = s_val[tid + w];
-        int oi = s_idx[tid + w];
-        if (o > s_val[tid] || (o == s_val[tid] && oi < s_idx[tid])) { s_val[tid] = o; s_idx[tid] = oi; }
-      }
-      __syncthreads();
-    }
-    const int p = s_idx[0];
-    const double pv = s_val[0];
-    __syncthreads();
-    if (p != k) {
-      for (int j = tid; j < nF; j += blockDim.x) {
-        cd t = F[(long long)k * nF + j];
-        F[(long long)k * nF + j] = F[(long long)p * nF + j];
-        F[(long long)p * nF + j] = t;
-      }
-      if (tid == 0) {
-        int t = pm[k];
-        pm[k] = pm[p];
-        pm[p] = t;
-      }
-      __syncthreads();
-    }
-    if (tid < kbb) s_rk[tid] = F[(long long)k * nF + k0 + tid];
-    __syncthreads();
-    cd piv = s_rk[k - k0];
-    if (!(pv > 0.0)) {
-      if (tid == 0) atomicOr(err, 1);
-      piv = mk(1.0, 0.0);
-    }
-    const cd inv = cdiv(mk(1.0, 0.0), piv);
-    for (int i = tid; i < nF; i += blockDim.x) {
-      if (i == k) continue;
-      cd* row = F + (long long)i * nF + k0;
-      cd ck = row[k - k0] * inv;      // F'[i][k] = F[i][k] / piv
-      for (int jj = 0; jj < kbb; ++jj) {
-        if (jj == k - k0) continue;
-        row[jj] -= ck * s_rk[jj];
-      }
-      row[k - k0] = ck;
-    }
-    if (tid < kbb) {
-      cd* rowk = F + (long long)k * nF + k0;
-      if (tid == k - k0)
-        rowk[tid] = inv;
-      else
-        rowk[tid] = -(s_rk[tid] * inv);
-    }
-    __syncthreads();
-  }
-}
-
 // Panel [k0, k0 + kbb) of every front of one height with the panel block (nF x KB)
 // resident in LDS: one 1024-thread work-group per front; per pivot a block-wide
 // argmax, an LDS row swap and the exchange update of the panel columns.  Row swaps
@@ -219,6 +141,153 @@ __global__ void __launch_bounds__(1024) k_nd_panel_lds(const NDFrontDev* __restr
   for (int e = tid; e < nF * kbb; e += nt) {
     int i = e / kbb, jj = e % kbb;
     F[(long long)i * nF + k0 + jj] = P[i * KB + jj];
+  }
+}
+
+// Panel [k0, k0 + kbb) of fronts too large for an LDS-resident panel: every pivot step
+// is spread over work-groups of PROWS rows.
+//   k_piv_search   argmax of |F[i][k0]| over the S rows i >= k0 of each row block
+//   k_piv_select   one work-group per front: reduce the block candidates (ties: lower
+//                  row), swap the two rows' panel entries, stage the pivot row and its
+//                  inverse; the swap of the other columns is recorded (k_nd_swap_rest)
+//   k_piv_update   the exchange of pivot k on the panel columns of a row block, and the
+//                  block's candidate for the next pivot column
+// Arithmetic and pivot choice are those of the single-work-group exchange, so the
+// factors do not depend on which path a front takes.
+#define PROWS 64
+__device__ __forceinline__ void cand_argmax(double v, int i, double* sv, int* si, int nt) {
+  // block-wide (nt threads) argmax with the lower index on ties; result in sv[0], si[0]
+  for (int o = 32; o > 0; o >>= 1) {
+    double ov = __shfl_xor(v, o, 64);
+    int oi = __shfl_xor(i, o, 64);
+    if (ov > v || (ov == v && oi < i)) { v = ov; i = oi; }
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) { sv[w] = v; si[w] = i; }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int q = 1; q < nt / 64; ++q)
+      if (sv[q] > sv[0] || (sv[q] == sv[0] && si[q] < si[0])) { sv[0] = sv[q]; si[0] = si[q]; }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(256) k_piv_search(const NDFrontDev* __restrict__ fr, const int* __restrict__ ids,
+                                                    const cd* __restrict__ Fp, int k, PivCand* __restrict__ cand,
+                                                    int nblk) {
+  __shared__ double sv[4];
+  __shared__ int si[4];
+  const NDFrontDev f = fr[ids[blockIdx.y]];
+  if (f.nS <= k || (int)blockIdx.x * PROWS >= f.nF) return;
+  const cd* F = Fp + f.F_off;
+  double best = -1.0;
+  int bi = 0x7fffffff;
+  const int r0 = max(k, (int)blockIdx.x * PROWS), r1 = min(f.nS, ((int)blockIdx.x + 1) * PROWS);
+  for (int i = r0 + (int)threadIdx.x; i < r1; i += blockDim.x) {
+    double v = abs2(F[(long long)i * f.nF + k]);
+    if (v > best) { best = v; bi = i; }
+  }
+  cand_argmax(best, bi, sv, si, blockDim.x);
+  if (threadIdx.x == 0) cand[(long long)blockIdx.y * nblk + blockIdx.x] = PivCand{sv[0], si[0], 0};
+}
+
+__global__ void __launch_bounds__(64) k_piv_select(const NDFrontDev* __restrict__ fr, const int* __restrict__ ids,
+                                                   cd* __restrict__ Fp, int* __restrict__ perm, int* __restrict__ swp,
+                                                   int k0, int kb, int kk, const PivCand* __restrict__ cand, int nblk,
+                                                   cd* __restrict__ rkb, int* __restrict__ err) {
+  const NDFrontDev f = fr[ids[blockIdx.x]];
+  const int k = k0 + kk;
+  if (f.nS <= k) return;
+  const int kbb = min(kb, f.nS - k0);
+  const int nb = (f.nF + PROWS - 1) / PROWS;
+  __shared__ double sv[1];
+  __shared__ int si[1];
+  // candidates of the blocks that hold S rows >= k
+  double best = -1.0;
+  int bi = 0x7fffffff;
+  for (int b = (int)threadIdx.x + k / PROWS; b < nb && b * PROWS < f.nS; b += 64) {
+    PivCand c = cand[(long long)blockIdx.x * nblk + b];
+    if (c.v > best || (c.v == best && c.i < bi)) { best = c.v; bi = c.i; }
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    double ov = __shfl_xor(best, o, 64);
+    int oi = __shfl_xor(bi, o, 64);
+    if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+  }
+  if (threadIdx.x == 0) { sv[0] = best; si[0] = bi; }
+  __syncthreads();
+  const double pv = sv[0];
+  const int p = pv >= 0.0 && si[0] < f.nS ? si[0] : k;
+  cd* F = Fp + f.F_off;
+  cd* rk = rkb + (long long)blockIdx.x * 33;
+  const int t = threadIdx.x;
+  if (t < kbb) {
+    cd a = F[(long long)k * f.nF + k0 + t];
+    if (p != k) {
+      cd b = F[(long long)p * f.nF + k0 + t];
+      F[(long long)k * f.nF + k0 + t] = b;
+      F[(long long)p * f.nF + k0 + t] = a;
+      a = b;
+    }
+    rk[t] = a;
+  }
+  __syncthreads();
+  if (t == 0) {
+    swp[(long long)blockIdx.x * 32 + kk] = p;
+    if (p != k) {
+      int q = perm[f.perm_off + k];
+      perm[f.perm_off + k] = perm[f.perm_off + p];
+      perm[f.perm_off + p] = q;
+    }
+    cd piv = rk[kk];
+    if (!(pv > 0.0)) {
+      atomicOr(err, 1);
+      piv = mk(1.0, 0.0);
+    }
+    rk[32] = cdiv(mk(1.0, 0.0), piv);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_piv_update(const NDFrontDev* __restrict__ fr, const int* __restrict__ ids,
+                                                    cd* __restrict__ Fp, int k0, int kb, int kk,
+                                                    const cd* __restrict__ rkb, PivCand* __restrict__ cand,
+                                                    int nblk) {
+  __shared__ cd srk[33];
+  __shared__ double sv[4];
+  __shared__ int si[4];
+  const NDFrontDev f = fr[ids[blockIdx.y]];
+  const int k = k0 + kk;
+  if (f.nS <= k || (int)blockIdx.x * PROWS >= f.nF) return;
+  const int kbb = min(kb, f.nS - k0);
+  if (threadIdx.x < 33) srk[threadIdx.x] = rkb[(long long)blockIdx.y * 33 + threadIdx.x];
+  __syncthreads();
+  const cd inv = srk[32];
+  cd* F = Fp + f.F_off;
+  const int jj = threadIdx.x & 31, rsub = threadIdx.x >> 5;        // 8 rows per pass, lanes along columns
+  const bool next = kk + 1 < kbb;
+  double best = -1.0;
+  int bi = 0x7fffffff;
+  const int r0 = (int)blockIdx.x * PROWS, r1 = min(f.nF, r0 + PROWS);
+  for (int i = r0 + rsub; i < r1; i += 8) {
+    cd* row = F + (long long)i * f.nF + k0;
+    if (i == k) {
+      if (jj < kbb) row[jj] = jj == kk ? inv : -(srk[jj] * inv);
+      continue;
+    }
+    const cd ck = row[kk] * inv;             // every lane of the row reads it before lane kk writes
+    cd nv = mk(0.0, 0.0);
+    if (jj < kbb) {
+      nv = jj == kk ? ck : row[jj] - ck * srk[jj];
+      row[jj] = nv;
+    }
+    if (next && jj == kk + 1 && i > k && i < f.nS) {
+      double v = abs2(nv);
+      if (v > best) { best = v; bi = i; }
+    }
+  }
+  if (next) {
+    cand_argmax(best, bi, sv, si, blockDim.x);
+    if (threadIdx.x == 0) cand[(long long)blockIdx.y * nblk + blockIdx.x] = PivCand{sv[0], si[0], 0};
   }
 }
 
@@ -584,9 +653,18 @@ void nd_extend(const NDFrontDev* fr, const int* ids, int nids, long long max_nb2
   unsigned gx = (unsigned)std::min<long long>(2048, std::max<long long>(1, (max_nb2 + 255) / 256));
   hipLaunchKernelGGL(k_nd_extend, dim3(gx, nids), dim3(256), 0, s, fr, ids, children, child_map_off, maps, Fp, slot);
 }
-void nd_panel(const NDFrontDev* fr, const int* ids, int nids, cd* Fp, int* perm, int k0, int kb, int* err,
-              hipStream_t s) {
-  hipLaunchKernelGGL(k_nd_panel, dim3(nids), dim3(256), 0, s, fr, ids, Fp, perm, k0, kb, err);
+void nd_panel_multi(const NDFrontDev* fr, const int* ids, int nids, int max_nF, cd* Fp, int* perm, int* swp,
+                    PivCand* cand, cd* rkb, int k0, int kb, int max_nS, int* err, hipStream_t s) {
+  const int nblk = (max_nF + PROWS - 1) / PROWS;
+  const int kbb = std::min(kb, max_nS - k0);
+  hipLaunchKernelGGL(k_piv_search, dim3(nblk, nids), dim3(256), 0, s, fr, ids, Fp, k0, cand, nblk);
+  for (int kk = 0; kk < kbb; ++kk) {
+    hipLaunchKernelGGL(k_piv_select, dim3(nids), dim3(64), 0, s, fr, ids, Fp, perm, swp, k0, kb, kk, cand, nblk, rkb,
+                       err);
+    hipLaunchKernelGGL(k_piv_update, dim3(nblk, nids), dim3(256), 0, s, fr, ids, Fp, k0, kb, kk, rkb, cand, nblk);
+  }
+  unsigned gx = (unsigned)std::min(64, std::max(1, (max_nF + 255) / 256));
+  hipLaunchKernelGGL(k_nd_swap_rest, dim3(gx, nids), dim3(256), 0, s, fr, ids, Fp, swp, k0, kb);
 }
 void nd_panel_lds(const NDFrontDev* fr, const int* ids, int nids, int max_nF, cd* Fp, int* perm, int* swp, int k0,
                   int kb, int* err, hipStream_t s) {
