@@ -40,12 +40,12 @@ void nd_finalize(const NDFrontDev* fr, const int* ids, int nids, long long max_n
                  C* Lp, C* Wp, hipStream_t s);
 template <typename C>
 void nd_fwd(const NDLaunchDev& L, const NDFrontDev* fr, const int* idx, const int* cptr, const int* cidx,
-            const C* Lp, C* upd, const C* r, C* x, C* gvec, int cap, int conj, hipStream_t s);
+            const C* Lp, C* upd, const C* r, C* x, C* gvec, int cap, int conj, C* gbuf, C* P, hipStream_t s);
 void nd_panel_lds(const NDFrontDev* fr, const int* ids, int nids, int max_nF, cd* Fp, int* perm, int* swp, int k0,
                   int kb, int* err, hipStream_t s);
 template <typename C>
 void nd_bwd(const NDLaunchDev& L, const NDFrontDev* fr, const int* idx, const int* cidx, const C* Wp, C* upd, C* x,
-            C* gvec, int cap, int conj, hipStream_t s);
+            C* gvec, int cap, int conj, C* gbuf, C* P, hipStream_t s);
 void grad_accumulate(const FineOp& op, double omega, const cd* u, const cd* lam, double* g, int first,
                      hipStream_t s);
 
@@ -101,6 +101,7 @@ struct NDDev {        // device-side ND tables (pointers into the workspace)
   cd *F = nullptr, *T = nullptr, *rkb = nullptr;
   PivCand* cand = nullptr;
   void *L = nullptr, *W = nullptr, *upd = nullptr, *gvec = nullptr;
+  void *gbuf = nullptr, *part = nullptr;     // split-K launches: gathered vectors, partial products
   std::vector<NDLaunchDev> launch[2];   // forward, backward
   int gvec_cap = 0;
 };
@@ -297,7 +298,9 @@ void build_plan(helm_ctx* c) {
   c->tuned = tuned;
   c->nd_leaf = leaf;
   c->nd_root = merge;
-  nd_plan(c->g3, leaf, 16, merge, (int)c->csz, lds, cuts, c->plan);
+  // heights above the tree blocks with at least this many factor bytes use split-K launches
+  const long long splitk = (long long)env_int("HELM_ND_SPLITK_KB", 4096) * 1024;
+  nd_plan(c->g3, leaf, 16, merge, (int)c->csz, lds, cuts, splitk, c->plan);
   NDPlan& P = c->plan;
   c->hlist.clear();
   c->hlist_toff.clear();
@@ -381,6 +384,7 @@ size_t carve(helm_ctx* c, void* ws) {
   d.L = cv.take<char>(cs * P.L_total);
   d.W = cv.take<char>(cs * std::max<long long>(1, P.W_total));
   d.upd = cv.take<char>(cs * std::max<long long>(1, P.upd_total));
+  long long gbuf_max = 1, part_max = 1;      // split-K buffers (entries)
   for (int fb = 0; fb < 2; ++fb) {
     std::vector<NDLaunch>& Ls = fb == 0 ? P.fwd : P.bwd;
     d.launch[fb].assign(Ls.size(), NDLaunchDev());
@@ -398,6 +402,15 @@ size_t carve(helm_ctx* c, void* ws) {
         D.segs = cv.take<NDSeg>(std::max<size_t>(1, L.segs.size()));
         D.outs = cv.take<NDOut>(std::max<size_t>(1, L.outs.size()));
         D.dst = cv.take<int>(std::max<size_t>(1, L.dst.size()));
+      } else if (L.kind == 3) {
+        D.ngath = (int)L.gath.size();
+        D.ntiles = (int)L.tiles.size();
+        D.nrt = (int)L.rtiles.size();
+        D.gath = cv.take<NDGather>(std::max<size_t>(1, L.gath.size()));
+        D.tiles = cv.take<NDTile>(std::max<size_t>(1, L.tiles.size()));
+        D.rtiles = cv.take<NDRowTile>(std::max<size_t>(1, L.rtiles.size()));
+        gbuf_max = std::max(gbuf_max, L.gbuf_elems);
+        part_max = std::max(part_max, L.p_elems);
       } else {
         D.ntasks = (int)L.task_off.size() - 1;
         D.task_off = cv.take<int>(L.task_off.size());
@@ -421,6 +434,8 @@ size_t carve(helm_ctx* c, void* ws) {
     }
   d.gvec_cap = (int)gcap;
   d.gvec = gcap ? cv.take<char>(cs * gcap * gneed) : nullptr;
+  d.gbuf = cv.take<char>(cs * gbuf_max);
+  d.part = cv.take<char>(cs * part_max);
   // Krylov
   c->V = cv.take<cd>((size_t)(m + 1) * g1.tot);
   c->Z = cv.take<char>(cs * (size_t)m * g1.tot);
@@ -518,12 +533,14 @@ void nd_solve(helm_ctx* c, const C* r, C* x, int conj, hipStream_t s) {
   for (const NDLaunchDev& L : d.launch[0]) {
     C* gv = L.kind == 1 && L.shm == 0 ? (C*)d.gvec : nullptr;
     TIMED(c, KT_ND_FWD, s,
-          nd_fwd<C>(L, d.fronts, d.idx, d.cptr, d.cidx, (const C*)d.L, (C*)d.upd, r, x, gv, d.gvec_cap, conj, s));
+          nd_fwd<C>(L, d.fronts, d.idx, d.cptr, d.cidx, (const C*)d.L, (C*)d.upd, r, x, gv, d.gvec_cap, conj,
+                    (C*)d.gbuf, (C*)d.part, s));
   }
   for (const NDLaunchDev& L : d.launch[1]) {
     C* gv = L.kind == 1 && L.shm == 0 ? (C*)d.gvec : nullptr;
     TIMED(c, KT_ND_BWD, s,
-          nd_bwd<C>(L, d.fronts, d.idx, d.cidx, (const C*)d.W, (C*)d.upd, x, gv, d.gvec_cap, conj, s));
+          nd_bwd<C>(L, d.fronts, d.idx, d.cidx, (const C*)d.W, (C*)d.upd, x, gv, d.gvec_cap, conj, (C*)d.gbuf,
+                    (C*)d.part, s));
   }
 }
 
@@ -884,6 +901,10 @@ int helm_setup(const helm_grid* grid, const double* slowness, double omega, cons
           up((NDSeg*)D.segs, Ls[l].segs, s);
           up((NDOut*)D.outs, Ls[l].outs, s);
           up((int*)D.dst, Ls[l].dst, s);
+        } else if (Ls[l].kind == 3) {
+          up((NDGather*)D.gath, Ls[l].gath, s);
+          up((NDTile*)D.tiles, Ls[l].tiles, s);
+          up((NDRowTile*)D.rtiles, Ls[l].rtiles, s);
         } else {
           up((int*)D.task_off, Ls[l].task_off, s);
           up((NDItem*)D.items, Ls[l].items, s);

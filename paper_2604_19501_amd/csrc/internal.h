@@ -191,8 +191,22 @@ struct NDOut {          // rows [r0, r0 + nr): y = sum of nparts partial blocks 
   int r0, nr, vslot, pslot, nparts, d;   // dst >= 0: x index; dst < 0: update index -dst - 1
 };
 
+// Split-K launches for heights with large fronts: every front's input vector is gathered
+// once (flat gather list -> gather buffer), tiles of 256 rows x at most 128 columns write
+// partial products (one row per thread, so a column is read in 2 KB runs), and row
+// tiles sum their partials in a fixed order and write x or the update.
+struct NDTile {
+  int front, r0, k0, k1;
+  int pslot;            // partial sums P[pslot + t], t < 256
+  int voff;             // the front's vector in the gather buffer
+};
+struct NDRowTile {
+  int front, r0, nkt, pslot, voff, pad;
+};
+
 struct NDLaunch {       // one kernel launch of a substitution
-  int kind = 1;         // 1: row chunks of big fronts (one work-group per item); 2: tree blocks
+  int kind = 1;         // 1: row chunks of big fronts (one work-group per item); 2: tree blocks;
+                        // 3: split-K tiles (gather, tiles, row sums: three kernels)
   std::vector<int> task_off;   // kind 1: items[task_off[t] ..); kind 2: stages[task_off[t] ..)
   std::vector<NDItem> items;
   int max_rows_vec = 0; // kind 1: vector entries per work-group (nF forward, nB backward)
@@ -202,6 +216,9 @@ struct NDLaunch {       // one kernel launch of a substitution
   std::vector<NDSeg> segs;
   std::vector<NDOut> outs;
   std::vector<int> dst;
+  std::vector<NDTile> tiles;        // kind 3 (with gath: the flat gather list)
+  std::vector<NDRowTile> rtiles;
+  long long gbuf_elems = 0, p_elems = 0;
   int lds_bytes = 0;    // kind 2: schedule + vectors + partials per work-group
   int threads = 256;
 };
@@ -217,6 +234,9 @@ struct NDLaunchDev {    // device copy of an NDLaunch, as the kernels see it
   const NDSeg* segs = nullptr;
   const NDOut* outs = nullptr;
   const int* dst = nullptr;
+  int ngath = 0, ntiles = 0, nrt = 0;
+  const NDTile* tiles = nullptr;
+  const NDRowTile* rtiles = nullptr;
 };
 
 struct NDPlan {
@@ -238,7 +258,9 @@ struct NDPlan {
 // elem_bytes: bytes of a factor entry (cycle precision); lds_bytes: LDS available to a
 // tree block; cuts: heights closing the tree-block launches (empty: chosen by the cost
 // model, {-1}: no tree blocks)
+// splitk_bytes: heights above the tree blocks whose factor blocks hold at least this many
+// bytes (per direction) use split-K launches
 void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int root_merge, int elem_bytes, int lds_bytes,
-             const std::vector<int>& cuts, NDPlan& plan);
+             const std::vector<int>& cuts, long long splitk_bytes, NDPlan& plan);
 
 }  // namespace helm

@@ -578,10 +578,17 @@ __device__ __forceinline__ C gemv_block16(const C* __restrict__ M, long long ld,
   const int i = r0 + row;
   const int kq = (K + 15) / 16, kb = ks * kq, ke = min(K, kb + kq);
   C acc = mk((R)0, (R)0);
-  if (i < r1) {
+  if (i < r1 && kb < ke) {
+    // 16 matrix entries in flight per thread: load all (clamped), then accumulate
     const C* col = M + i;
-#pragma unroll 16
-    for (int k = kb; k < ke; ++k) acc += cmul_conj(col[(long long)k * ld], v[k], conj);
+    for (int k = kb; k < ke; k += 16) {
+      C m[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) m[q] = col[(long long)min(k + q, ke - 1) * ld];
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        if (k + q < ke) acc += cmul_conj(m[q], v[k + q], conj);
+    }
   }
   red[threadIdx.x] = acc;
   __syncthreads();
@@ -634,6 +641,86 @@ __global__ void __launch_bounds__(256) k_nd_bwd_big(const NDFrontDev* __restrict
   C acc = gemv_block16(Wp + f.W_off, f.nS, item.r0, item.r1, f.nB, vec, conj, red);
   const int i = item.r0 + threadIdx.x;
   if (threadIdx.x < 16 && i < item.r1) x[id[i]] = x[id[i]] + acc;
+}
+
+// ---- split-K launches (kind 3) -------------------------------------------
+// flat gather of the fronts' input vectors into gbuf
+template <typename C>
+__global__ void __launch_bounds__(256) k_nd_gather(const NDGather* __restrict__ gath, int n,
+                                                   const int* __restrict__ cidx, const C* __restrict__ upd,
+                                                   const C* __restrict__ src, C* __restrict__ gbuf) {
+  typedef decltype(src[0].x) R;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const NDGather g = gath[e];
+  const C v0 = src[max(g.rid, 0)], u0 = upd[max(g.u0, 0)], u1 = upd[max(g.u1, 0)];
+  C v = mk((R)0, (R)0);
+  if (g.rid >= 0) v += v0;
+  if (g.u0 >= 0) v += u0;
+  if (g.u1 >= 0) v += u1;
+  for (int q = g.ca; q < g.cb; ++q) v += upd[cidx[q]];
+  gbuf[g.slot] = v;
+}
+
+// P[pslot + t] = sum_{k0 <= k < k1} M[k ld + r0 + t] vec[k]: one row per thread, 16 loads in flight
+template <typename C, int FWD>
+__global__ void __launch_bounds__(256) k_nd_tile(const NDFrontDev* __restrict__ fr, const C* __restrict__ Mp,
+                                                 const NDTile* __restrict__ tiles, const C* __restrict__ gbuf,
+                                                 C* __restrict__ P, int conj) {
+  typedef decltype(gbuf[0].x) R;
+  __shared__ C vec[128];
+  const NDTile t = tiles[blockIdx.x];
+  const NDFrontDev f = fr[t.front];
+  const int ld = FWD ? f.nF : f.nS, rows = FWD ? f.nF : f.nS;
+  const int nk = t.k1 - t.k0;
+  if ((int)threadIdx.x < nk) vec[threadIdx.x] = gbuf[t.voff + t.k0 + threadIdx.x];
+  __syncthreads();
+  const int i = min(t.r0 + (int)threadIdx.x, rows - 1);
+  const C* col = Mp + (FWD ? f.L_off : f.W_off) + (long long)t.k0 * ld + i;
+  C acc = mk((R)0, (R)0);
+  for (int k = 0; k < nk; k += 16) {
+    C m[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) m[q] = col[(long long)min(k + q, nk - 1) * ld];
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+      if (k + q < nk) acc += cmul_conj(m[q], vec[k + q], conj);
+  }
+  P[t.pslot + threadIdx.x] = acc;
+}
+
+// rows of a row tile: the partials summed in k order, then x (or the update) written
+template <typename C, int FWD>
+__global__ void __launch_bounds__(256) k_nd_rowsum(const NDFrontDev* __restrict__ fr, const int* __restrict__ idx,
+                                                   const NDRowTile* __restrict__ rt, const C* __restrict__ P,
+                                                   const C* __restrict__ gbuf, C* __restrict__ upd,
+                                                   C* __restrict__ x) {
+  typedef decltype(gbuf[0].x) R;
+  const NDRowTile t = rt[blockIdx.x];
+  const NDFrontDev f = fr[t.front];
+  const int i = t.r0 + threadIdx.x;
+  if (i >= (FWD ? f.nF : f.nS)) return;
+  C acc = mk((R)0, (R)0);
+  for (int q = 0; q < t.nkt; ++q) acc += P[t.pslot + 256 * q + threadIdx.x];
+  if (FWD) {
+    if (i < f.nS)
+      x[idx[f.idx_off + i]] = acc;
+    else
+      upd[f.upd_off + i - f.nS] = gbuf[t.voff + i] - acc;
+  } else {
+    const int id = idx[f.idx_off + i];
+    x[id] = x[id] + acc;
+  }
+}
+
+template <typename C, int FWD>
+static void splitk(const NDLaunchDev& L, const NDFrontDev* fr, const int* idx, const int* cidx, const C* M, C* upd,
+                   const C* src, C* x, C* gbuf, C* P, int conj, hipStream_t s) {
+  hipLaunchKernelGGL((k_nd_gather<C>), dim3((L.ngath + 255) / 256), dim3(256), 0, s, L.gath, L.ngath, cidx,
+                     (const C*)upd, src, gbuf);
+  hipLaunchKernelGGL((k_nd_tile<C, FWD>), dim3(L.ntiles), dim3(256), 0, s, fr, M, L.tiles, (const C*)gbuf, P, conj);
+  hipLaunchKernelGGL((k_nd_rowsum<C, FWD>), dim3(L.nrt), dim3(256), 0, s, fr, idx, L.rtiles, (const C*)P,
+                     (const C*)gbuf, upd, x);
 }
 
 // ------------------------------------------------------------- launchers ----
@@ -700,8 +787,10 @@ static void tree_attr(size_t lds) {
 
 template <typename C>
 void nd_fwd(const NDLaunchDev& L, const NDFrontDev* fr, const int* idx, const int* cptr, const int* cidx,
-            const C* Lp, C* upd, const C* r, C* x, C* gvec, int cap, int conj, hipStream_t s) {
-  if (L.kind == 2) {
+            const C* Lp, C* upd, const C* r, C* x, C* gvec, int cap, int conj, C* gbuf, C* P, hipStream_t s) {
+  if (L.kind == 3) {
+    splitk<C, 1>(L, fr, idx, cidx, Lp, upd, r, x, gbuf, P, conj, s);
+  } else if (L.kind == 2) {
     size_t lds = (size_t)L.lds_bytes;
     tree_attr<C, 1>(lds);
     hipLaunchKernelGGL((k_nd_tree<C, 1>), dim3(L.ntasks), dim3(L.threads), lds, s, L.tasks, L.stages, L.gath,
@@ -713,8 +802,10 @@ void nd_fwd(const NDLaunchDev& L, const NDFrontDev* fr, const int* idx, const in
 }
 template <typename C>
 void nd_bwd(const NDLaunchDev& L, const NDFrontDev* fr, const int* idx, const int* cidx, const C* Wp, C* upd, C* x,
-            C* gvec, int cap, int conj, hipStream_t s) {
-  if (L.kind == 2) {
+            C* gvec, int cap, int conj, C* gbuf, C* P, hipStream_t s) {
+  if (L.kind == 3) {
+    splitk<C, 0>(L, fr, idx, cidx, Wp, upd, (const C*)x, x, gbuf, P, conj, s);
+  } else if (L.kind == 2) {
     size_t lds = (size_t)L.lds_bytes;
     tree_attr<C, 0>(lds);
     hipLaunchKernelGGL((k_nd_tree<C, 0>), dim3(L.ntasks), dim3(L.threads), lds, s, L.tasks, L.stages, L.gath,
@@ -730,12 +821,12 @@ template void nd_finalize<cf>(const NDFrontDev*, const int*, int, long long, con
 template void nd_finalize<cd>(const NDFrontDev*, const int*, int, long long, const cd*, const int*,
                                    cd*, cd*, hipStream_t);
 template void nd_fwd<cf>(const NDLaunchDev&, const NDFrontDev*, const int*, const int*, const int*, const cf*, cf*,
-                         const cf*, cf*, cf*, int, int, hipStream_t);
+                         const cf*, cf*, cf*, int, int, cf*, cf*, hipStream_t);
 template void nd_fwd<cd>(const NDLaunchDev&, const NDFrontDev*, const int*, const int*, const int*, const cd*, cd*,
-                         const cd*, cd*, cd*, int, int, hipStream_t);
+                         const cd*, cd*, cd*, int, int, cd*, cd*, hipStream_t);
 template void nd_bwd<cf>(const NDLaunchDev&, const NDFrontDev*, const int*, const int*, const cf*, cf*, cf*, cf*, int,
-                         int, hipStream_t);
+                         int, cf*, cf*, hipStream_t);
 template void nd_bwd<cd>(const NDLaunchDev&, const NDFrontDev*, const int*, const int*, const cd*, cd*, cd*, cd*, int,
-                         int, hipStream_t);
+                         int, cd*, cd*, hipStream_t);
 
 }  // namespace helm

@@ -95,7 +95,7 @@ struct Builder {
 }  // namespace
 
 void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int root_merge, int elem_bytes, int lds_bytes,
-             const std::vector<int>& cuts, NDPlan& plan) {
+             const std::vector<int>& cuts, long long splitk_bytes, NDPlan& plan) {
   Builder bd;
   bd.g = g3;
   bd.leaf_max = std::max(leaf_max, 1);
@@ -520,27 +520,77 @@ void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int root_merge, int e
     lo = b;
   }
   std::vector<NDLaunch> bwd_high;
+  const int KT = 128;                                  // columns of a split-K tile
+  auto build_splitk = [&](NDLaunch& L, int h, int dir) {
+    L.kind = 3;
+    for (int t : plan.by_height[h]) {
+      const NDFrontDev& f = plan.fronts[t];
+      const int R = dir == 0 ? f.nF : f.nS, K = dir == 0 ? f.nS : f.nB;
+      if (R == 0 || K == 0) continue;
+      const int* ids = plan.idx.data() + f.idx_off;
+      const int voff = (int)L.gbuf_elems;
+      if (dir == 0) {
+        for (int i = 0; i < f.nF; ++i) {
+          int ca = plan.cptr[f.inv_off + i], cb = plan.cptr[f.inv_off + i + 1];
+          NDGather g{voff + i, i < f.nS ? ids[i] : -1, -1, -1, 0, 0};
+          if (ca < cb) g.u0 = plan.cidx[ca++];
+          if (ca < cb) g.u1 = plan.cidx[ca++];
+          g.ca = ca;
+          g.cb = cb;
+          L.gath.push_back(g);
+        }
+      } else {
+        for (int j = 0; j < f.nB; ++j) L.gath.push_back({voff + j, ids[f.nS + j], -1, -1, 0, 0});
+      }
+      L.gbuf_elems += dir == 0 ? f.nF : f.nB;
+      const int nkt = (K + KT - 1) / KT;
+      for (int r0 = 0; r0 < R; r0 += 256) {
+        const int ps0 = (int)L.p_elems;
+        for (int kt = 0; kt < nkt; ++kt) {
+          L.tiles.push_back({t, r0, kt * KT, std::min(K, (kt + 1) * KT), (int)L.p_elems, voff});
+          L.p_elems += 256;
+        }
+        L.rtiles.push_back({t, r0, nkt, ps0, voff, 0});
+      }
+    }
+  };
   for (int h = lo + 1; h <= plan.max_height; ++h) {
     NDLaunch fl, bl;
     fl.kind = bl.kind = 1;
     fl.task_off.push_back(0);
     bl.task_off.push_back(0);
+    long long bf = 0, bb = 0;
     for (int t : plan.by_height[h]) {
-      const NDFrontDev& f = plan.fronts[t];
-      for (int r = 0; r < f.nF; r += rows_chunk) {
-        fl.items.push_back({t, r, std::min(f.nF, r + rows_chunk), h});
-        fl.task_off.push_back((int)fl.items.size());
-      }
-      if (f.nB > 0)          // a front without boundary has nothing to back-substitute
-        for (int r = 0; r < f.nS; r += rows_chunk) {
-          bl.items.push_back({t, r, std::min(f.nS, r + rows_chunk), h});
-          bl.task_off.push_back((int)bl.items.size());
+      bf += (long long)plan.fronts[t].nF * plan.fronts[t].nS * elem_bytes;
+      bb += (long long)plan.fronts[t].nS * plan.fronts[t].nB * elem_bytes;
+    }
+    if (bf >= splitk_bytes) {
+      build_splitk(fl, h, 0);
+    } else {
+      for (int t : plan.by_height[h]) {
+        const NDFrontDev& f = plan.fronts[t];
+        for (int r = 0; r < f.nF; r += rows_chunk) {
+          fl.items.push_back({t, r, std::min(f.nF, r + rows_chunk), h});
+          fl.task_off.push_back((int)fl.items.size());
         }
-      fl.max_rows_vec = std::max(fl.max_rows_vec, f.nF);
-      bl.max_rows_vec = std::max(bl.max_rows_vec, f.nB);
+        fl.max_rows_vec = std::max(fl.max_rows_vec, f.nF);
+      }
+    }
+    if (bb >= splitk_bytes && bb > 0) {
+      build_splitk(bl, h, 1);
+    } else {
+      for (int t : plan.by_height[h]) {
+        const NDFrontDev& f = plan.fronts[t];
+        if (f.nB > 0)          // a front without boundary has nothing to back-substitute
+          for (int r = 0; r < f.nS; r += rows_chunk) {
+            bl.items.push_back({t, r, std::min(f.nS, r + rows_chunk), h});
+            bl.task_off.push_back((int)bl.items.size());
+          }
+        bl.max_rows_vec = std::max(bl.max_rows_vec, f.nB);
+      }
     }
     plan.fwd.push_back(fl);
-    if (!bl.items.empty()) bwd_high.push_back(bl);
+    if (!bl.items.empty() || !bl.tiles.empty()) bwd_high.push_back(bl);
   }
   std::vector<NDLaunch> bwd_all(bwd_high.rbegin(), bwd_high.rend());
   for (auto it = bwd_tree.rbegin(); it != bwd_tree.rend(); ++it)

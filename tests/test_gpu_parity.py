@@ -69,17 +69,21 @@ def test_coarse_solve(case, prec, tol):
 
 
 @pytest.mark.parametrize("dim,n", [(2, 256), (3, 64)])
-@pytest.mark.parametrize("cuts,panel", [("none", "lds"), ("", "lds"), ("1", "lds"), ("0,1,2,3", "lds"),
-                                        ("", "multi")])
-def test_coarse_solve_schedules(monkeypatch, dim, n, cuts, panel):
-    """the exact coarsest solve under every kind of substitution schedule (multi-block
-    launches only, the planner's choice, one tree-block launch, one per level) and with
-    both factorisation panel paths (LDS-resident, multi-work-group)."""
+@pytest.mark.parametrize("cuts,panel,splitk", [("none", "lds", None), ("", "lds", None), ("1", "lds", None),
+                                               ("0,1,2,3", "lds", None), ("", "multi", None), ("none", "lds", 0),
+                                               ("1", "multi", 0)])
+def test_coarse_solve_schedules(monkeypatch, dim, n, cuts, panel, splitk):
+    """the exact coarsest solve under every kind of substitution schedule (row-chunk
+    launches only, the planner's choice, one tree-block launch, one per level, split-K
+    launches for every height above the tree blocks) and with both factorisation panel
+    paths (LDS-resident, multi-work-group)."""
     monkeypatch.setenv("HELM_ND_CUTS", cuts)
     if panel == "multi":
         monkeypatch.setenv("HELM_ND_LDS_PANEL", "0")
+    if splitk is not None:
+        monkeypatch.setenv("HELM_ND_SPLITK_KB", str(splitk))
     p = synth.config2(n) if dim == 2 else synth.config3(n)
-    print("coarse schedule", dim, n, repr(cuts), panel, flush=True)
+    print("coarse schedule", dim, n, repr(cuts), panel, splitk, flush=True)
     H = oracle_hierarchy(p, nu_pre=1, nu_post=1)
     for prec, tol in (("f64", 1e-10), ("f32", 1e-4)):
         s = from_problem(p, nu=(1, 1), cycle_prec=prec)
