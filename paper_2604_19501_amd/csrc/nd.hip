@@ -471,6 +471,14 @@ __device__ __forceinline__ NDSeg uniform_seg(NDSeg a) {
   return b;
 }
 
+// the 16 matrix entries of a segment for one lane (row and column indices clamped)
+template <typename C>
+__device__ __forceinline__ void load_seg(const C* __restrict__ M, const NDSeg& sg, int lane, C* m) {
+  const C* col = M + sg.m_off + sg.r0 + min(lane, sg.nr - 1);
+#pragma unroll
+  for (int kk = 0; kk < 16; ++kk) m[kk] = col[(long long)min(sg.k0 + kk, sg.k1 - 1) * sg.ld];
+}
+
 // Tree-block substitution: one work-group per subtree task, one stage per level.
 //   gathers:  vec[slot] = src[rid] (+ children's updates)           all threads
 //   segments: partial products of <= 64 rows over <= 16 columns       one wavefront, two at a time
@@ -511,6 +519,16 @@ __global__ void __launch_bounds__(1024) k_nd_tree(const NDTask* __restrict__ tas
   copy_lds(ldst, dst + T.d0, sizeof(int) * nd);
   __syncthreads();
   const int nw = blockDim.x >> 6, wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // prefetching holds a second segment in registers: FP32 only (FP64 would spill)
+  constexpr bool PF = sizeof(C) == 8;
+  NDSeg psg;
+  C pm[PF ? 16 : 1];
+  bool have_pf = false;
+  if (PF && nst > 0 && lst[0].s0 + wv < lst[0].s1) {
+    psg = uniform_seg(lsg[lst[0].s0 + wv]);
+    load_seg(M, psg, lane, pm);
+    have_pf = true;
+  }
   for (int st = 0; st < nst; ++st) {
     const NDStage S = lst[st];
     // loads are unconditional (clamped indices, zero weights) so that a wavefront keeps
@@ -526,25 +544,34 @@ __global__ void __launch_bounds__(1024) k_nd_tree(const NDTask* __restrict__ tas
       work[g.slot] = v;
     }
     __syncthreads();
-    // NSEG segments per wavefront at a time, 16 matrix loads each in flight
-    constexpr int NSEG = 1;
-    for (int s0 = S.s0 + wv; s0 < S.s1; s0 += NSEG * nw) {
-      NDSeg sg[NSEG];
-      C mv[NSEG][16];
+    // one segment per wavefront at a time, 16 matrix loads in flight; the first segment of
+    // a wavefront in a stage was prefetched during the previous stage (the matrix does not
+    // depend on the previous stage's results)
+    for (int s0 = S.s0 + wv; s0 < S.s1; s0 += nw) {
+      NDSeg sg;
+      C mv[16];
+      if (PF && s0 == S.s0 + wv && have_pf) {
+        sg = psg;
 #pragma unroll
-      for (int j = 0; j < NSEG; ++j) {
-        sg[j] = uniform_seg(lsg[min(s0 + j * nw, S.s1 - 1)]);
-        const C* col = M + sg[j].m_off + sg[j].r0 + min(lane, sg[j].nr - 1);
-#pragma unroll
-        for (int kk = 0; kk < 16; ++kk) mv[j][kk] = col[(long long)min(sg[j].k0 + kk, sg[j].k1 - 1) * sg[j].ld];
+        for (int kk = 0; kk < 16; ++kk) mv[kk] = pm[PF ? kk : 0];
+      } else {
+        sg = uniform_seg(lsg[s0]);
+        load_seg(M, sg, lane, mv);
       }
+      C acc = mk((R)0, (R)0);
 #pragma unroll
-      for (int j = 0; j < NSEG; ++j) {
-        C acc = mk((R)0, (R)0);
-#pragma unroll
-        for (int kk = 0; kk < 16; ++kk)
-          if (sg[j].k0 + kk < sg[j].k1) acc += cmul_conj(mv[j][kk], work[sg[j].vslot + sg[j].k0 + kk], conj);
-        if (s0 + j * nw < S.s1) work[sg[j].pslot + lane] = acc;
+      for (int kk = 0; kk < 16; ++kk)
+        if (sg.k0 + kk < sg.k1) acc += cmul_conj(mv[kk], work[sg.vslot + sg.k0 + kk], conj);
+      work[sg.pslot + lane] = acc;
+    }
+    // prefetch this wavefront's first segment of the next stage
+    have_pf = false;
+    if (PF && st + 1 < nst) {
+      const NDStage S2 = lst[st + 1];
+      if (S2.s0 + wv < S2.s1) {
+        psg = uniform_seg(lsg[S2.s0 + wv]);
+        load_seg(M, psg, lane, pm);
+        have_pf = true;
       }
     }
     __syncthreads();
