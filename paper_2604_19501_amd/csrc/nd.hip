@@ -333,9 +333,15 @@ __global__ void __launch_bounds__(256) k_nd_save_t(const NDFrontDev* __restrict_
   }
 }
 
-// F[:, J] -= F[:, K] * T   (complex FP64 GEMM, 64x64 tiles, 4x4 per thread)
+// F[:, J] -= F[:, K] * T  (complex FP64 GEMM on the matrix cores).  A work-group owns a
+// 64 x 64 tile of C = F[:, J]; each wavefront a 32 x 32 quarter as 2 x 2 blocks of the
+// 16 x 16 x 4 FP64 MFMA, real and imaginary parts accumulated separately:
+//   Cr += Ar Br - Ai Bi,  Ci += Ar Bi + Ai Br  (four real MFMAs per k group).
+// MFMA lane layout: A[m][k] from lane m + 16 k, B[k][n] from lane n + 16 k, and lane l
+// holds D[l / 16 + 4 i][l % 16], i < 4.  Panels of A and B pass through LDS, 16 k at a time.
 #define GT 64
 #define GK 16
+typedef double mfma_d4 __attribute__((ext_vector_type(4)));
 __global__ void __launch_bounds__(256) k_nd_gemm(const NDFrontDev* __restrict__ fr, const int* __restrict__ ids,
                                                  const long long* __restrict__ toff, cd* __restrict__ Fp,
                                                  const cd* __restrict__ T, int k0, int kb) {
@@ -350,10 +356,15 @@ __global__ void __launch_bounds__(256) k_nd_gemm(const NDFrontDev* __restrict__ 
   const cd* Tt = T + toff[blockIdx.y];
   __shared__ cd sA[GK][GT + 1];
   __shared__ cd sB[GK][GT + 1];
-  const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
-  cd acc[4][4];
-  for (int a = 0; a < 4; ++a)
-    for (int b = 0; b < 4; ++b) acc[a][b] = mk(0.0, 0.0);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int wr = (wv >> 1) * 32, wc = (wv & 1) * 32;       // wavefront's quarter of the tile
+  mfma_d4 accr[2][2], acci[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      accr[a][b] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+      acci[a][b] = mfma_d4{0.0, 0.0, 0.0, 0.0};
+    }
+  const int lm = lane & 15, lk = lane >> 4;
   for (int kk0 = 0; kk0 < kbb; kk0 += GK) {
     for (int p = threadIdx.x; p < GK * GT; p += 256) {
       int kk = p % GK, r = p / GK;                 // A tile: consecutive threads along a row
@@ -364,27 +375,39 @@ __global__ void __launch_bounds__(256) k_nd_gemm(const NDFrontDev* __restrict__ 
       sB[kk2][c] = (col < Ncol && kq2 < kbb) ? Tt[(long long)kq2 * Ncol + col] : mk(0.0, 0.0);
     }
     __syncthreads();
-    for (int kk = 0; kk < GK; ++kk) {
-      cd a[4], b[4];
-      for (int q = 0; q < 4; ++q) {
-        a[q] = sA[kk][ty + 16 * q];
-        b[q] = sB[kk][tx + 16 * q];
+#pragma unroll
+    for (int k4 = 0; k4 < GK; k4 += 4) {
+      cd av[2], bv[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        av[q] = sA[k4 + lk][wr + 16 * q + lm];
+        bv[q] = sB[k4 + lk][wc + 16 * q + lm];
       }
-      for (int qa = 0; qa < 4; ++qa)
-        for (int qb = 0; qb < 4; ++qb) acc[qa][qb] += a[qa] * b[qb];
+#pragma unroll
+      for (int qa = 0; qa < 2; ++qa)
+#pragma unroll
+        for (int qb = 0; qb < 2; ++qb) {
+          accr[qa][qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[qa].x, bv[qb].x, accr[qa][qb], 0, 0, 0);
+          accr[qa][qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[qa].y, bv[qb].y, accr[qa][qb], 0, 0, 0);
+          acci[qa][qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[qa].x, bv[qb].y, acci[qa][qb], 0, 0, 0);
+          acci[qa][qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[qa].y, bv[qb].x, acci[qa][qb], 0, 0, 0);
+        }
     }
     __syncthreads();
   }
-  for (int qa = 0; qa < 4; ++qa) {
-    int row = tm * GT + ty + 16 * qa;
-    if (row >= M) continue;
-    for (int qb = 0; qb < 4; ++qb) {
-      int col = tn * GT + tx + 16 * qb;
-      if (col >= Ncol) continue;
-      int j = col < k0 ? col : col + kbb;
-      F[(long long)row * f.nF + j] -= acc[qa][qb];
-    }
-  }
+#pragma unroll
+  for (int qa = 0; qa < 2; ++qa)
+#pragma unroll
+    for (int qb = 0; qb < 2; ++qb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = tm * GT + wr + 16 * qa + lk + 4 * i;
+        const int col = tn * GT + wc + 16 * qb + lm;
+        if (row >= M || col >= Ncol) continue;
+        const int j = col < k0 ? col : col + kbb;
+        cd* c = F + (long long)row * f.nF + j;
+        *c -= mk(accr[qa][qb][i], acci[qa][qb][i]);
+      }
 }
 
 template <typename C>
