@@ -41,7 +41,8 @@ void nd_finalize(const NDFrontDev* fr, const int* ids, int nids, long long max_n
 template <typename C>
 void nd_fwd(const NDLaunchDev& L, const NDFrontDev* fr, const int* idx, const int* cptr, const int* cidx,
             const C* Lp, C* upd, const C* r, C* x, C* gvec, int cap, int conj, C* gbuf, C* P, hipStream_t s);
-void nd_panel_lds(const NDFrontDev* fr, const int* ids, int nids, int max_nF, cd* Fp, int* perm, int* swp, int k0,
+int panel_reg_kb(int nF);
+void nd_panel_reg(const NDFrontDev* fr, const int* ids, int nids, int max_nF, cd* Fp, int* perm, int* swp, int k0,
                   int kb, int* err, hipStream_t s);
 template <typename C>
 void nd_bwd(const NDLaunchDev& L, const NDFrontDev* fr, const int* idx, const int* cidx, const C* Wp, C* upd, C* x,
@@ -149,7 +150,9 @@ struct helm_ctx {
   KrylovState* st = nullptr;
   KrylovArgs ka;
   size_t ws_needed = 0;
-  char* hstate = nullptr;    // pinned host copy of the scalar block of KrylovState
+  char* hstate = nullptr;    // pinned host copy of the scalar block of KrylovState (slot 0),
+                             // slots 1, 2: read-backs of alternate queued iterations
+  hipEvent_t itev[2] = {nullptr, nullptr};   // completion of the queued iterations
   int timing = 0;
   double times[5] = {0, 0, 0, 0, 0};
   double kt_ms[KT_N] = {0};
@@ -469,14 +472,14 @@ void nd_factor(helm_ctx* c, hipStream_t s) {
     nd_assemble(d.fronts, ids, hi.count, hi.max_asm, d.asmv, c->coef3_64, d.F, s);
     for (int slot = 0; slot < hi.max_child; ++slot)
       nd_extend(d.fronts, ids, hi.count, hi.max_nb2, d.children, d.child_map_off, d.maps, d.F, slot, s);
-    // panel width: the LDS-resident panel kernel when a panel of >= 8 columns fits
-    int kb = 32;
-    while (kb > 8 && (size_t)hi.max_nF * kb * sizeof(cd) > c->lds_panel) kb /= 2;
-    const bool lds_panel = (size_t)hi.max_nF * kb * sizeof(cd) <= c->lds_panel;
-    if (!lds_panel) kb = ND_KB;
+    // the register-resident panel (one work-group per front) when the fronts are small
+    // enough; otherwise the panel is spread over many work-groups
+    const int kreg = panel_reg_kb(hi.max_nF);
+    const bool reg_panel = kreg > 0 && c->lds_panel > 0;
+    const int kb = reg_panel ? kreg : ND_KB;
     for (int k0 = 0; k0 < hi.max_nS; k0 += kb) {
-      if (lds_panel)
-        nd_panel_lds(d.fronts, ids, hi.count, hi.max_nF, d.F, d.perm, d.swp, k0, kb, d.err, s);
+      if (reg_panel)
+        nd_panel_reg(d.fronts, ids, hi.count, hi.max_nF, d.F, d.perm, d.swp, k0, kb, d.err, s);
       else
         nd_panel_multi(d.fronts, ids, hi.count, hi.max_nF, d.F, d.perm, d.swp, d.cand, d.rkb, k0, kb, hi.max_nS,
                        d.err, s);
@@ -649,6 +652,8 @@ struct Cycle {
   }
 };
 
+constexpr size_t HSLOT = 1024;   // bytes between the slots of hstate
+static_assert(offsetof(KrylovState, hist) - offsetof(KrylovState, bnorm) <= HSLOT, "state slot too small");
 void read_state(helm_ctx* c, hipStream_t s) {
   CK(hipMemcpyAsync(c->hstate, (char*)c->st + offsetof(KrylovState, bnorm),
                     offsetof(KrylovState, hist) - offsetof(KrylovState, bnorm), hipMemcpyDeviceToHost, s));
@@ -748,18 +753,41 @@ int solve_impl(helm_ctx* c, int op, const cd* b, cd* x, double tol, int max_iter
       if (its >= max_iter) { status = HELM_ENOCONV; break; }
       kr_scale_v0(a, s);
       int k = 0;
-      for (int j = 0; j < m; ++j) {
-        if (use_graphs) {
+      if (use_graphs) {
+        // iteration q + 1 is queued before the state of iteration q is read back, so the
+        // device does not wait for the host between iterations.  An iteration queued after
+        // the one that converged finds the done flag set: its Krylov kernels return at once
+        // and leave the basis, the Hessenberg column and the counters as they are.
+        const size_t sb = offsetof(KrylovState, hist) - offsetof(KrylovState, bnorm);
+        auto queue = [&](int j) {
           CK(hipGraphLaunch(c->gexec[op][j], s));
-        } else {
+          CK(hipMemcpyAsync(c->hstate + HSLOT * (1 + (j & 1)), (char*)c->st + offsetof(KrylovState, bnorm), sb,
+                            hipMemcpyDeviceToHost, s));
+          CK(hipEventRecord(c->itev[j & 1], s));
+        };
+        for (hipEvent_t& e : c->itev)
+          if (!e) CK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        int q = 0;                   // iterations of this cycle queued
+        queue(q++);
+        while (k < q) {
+          if (q < m && its + (q - k) < max_iter) queue(q++);
+          CK(hipEventSynchronize(c->itev[k & 1]));
+          std::memcpy(c->hstate, c->hstate + HSLOT * (1 + (k & 1)), sb);
+          ++its;
+          ++k;
+          est = h->est;
+          if (h->nonfinite || h->done || its >= max_iter) break;
+        }
+      } else {
+        for (int j = 0; j < m; ++j) {
           cyc.template run<C>(c->V + (size_t)j * N, (C*)c->Z + (size_t)j * N);
           TIMED(c, KT_APPLY_DOT, s, kr_arnoldi(a, (const char*)c->Z + (size_t)j * N * c->csz, c->f32, j, tol, s));
+          ++its;
+          k = j + 1;
+          read_state(c, s);
+          est = h->est;
+          if (h->nonfinite || h->done || its >= max_iter) break;
         }
-        ++its;
-        k = j + 1;
-        read_state(c, s);
-        est = h->est;
-        if (h->nonfinite || h->done || its >= max_iter) break;
       }
       if (h->nonfinite) { status = HELM_ENONFINITE; break; }
       kr_update_x(a, c->Z, c->f32, N, k, x, s);
@@ -969,6 +997,9 @@ int helm_destroy(helm_ctx* ctx) {
   if (ctx->cap) (void)hipStreamDestroy(ctx->cap);
   for (hipStream_t t : ctx->bstreams) (void)hipStreamDestroy(t);
   if (ctx->hstate) (void)hipHostFree(ctx->hstate);
+  for (hipEvent_t e : ctx->itev)
+    if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : ctx->evpool) (void)hipEventDestroy(e);
   delete ctx;
   return HELM_OK;
 }
@@ -1222,11 +1253,18 @@ int helm_solve_batched(helm_ctx* ctx, int op, int n_rhs, const int* inst_of_rhs,
     CK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
     CK(hipEventRecord(ready, s));
     for (int w = 0; w < nst; ++w) CK(hipStreamWaitEvent(ctx->bstreams[w], ready, 0));
+    // a new host thread starts on device 0: the workers take the caller's device
+    int dev = 0;
+    CK(hipGetDevice(&dev));
     std::vector<std::thread> pool;
     for (int w = 0; w < nst; ++w)
       pool.emplace_back([&, w]() {
-        int dev = 0;
-        (void)hipGetDevice(&dev);
+        if (hipSetDevice(dev) != hipSuccess) {
+          errs[w] = "hipSetDevice failed in a batch worker";
+          for (int k = 0; k < n_rhs; ++k)
+            if (inst_of_rhs[k] % nst == w) status[k] = HELM_EDEVICE;
+          return;
+        }
         for (int k = 0; k < n_rhs; ++k) {
           if (inst_of_rhs[k] % nst != w) continue;
           helm_ctx* c = ctx->sub.empty() ? ctx : ctx->sub[inst_of_rhs[k]];

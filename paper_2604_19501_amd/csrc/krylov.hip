@@ -56,17 +56,20 @@ __device__ __forceinline__ cd apply_h(const KrylovArgs& a, const CX* __restrict_
   cd c = a.s * mk(mm, -mm * sig);
   if (a.conj) c.y = -c.y;
   cd D = mk(2.0 * g.dim * a.op.inv_h2 - c.x, -c.y);
-  cd nb = mk(0.0, 0.0);
+  // neighbours outside the grid are read at f and weighted 0, so that every load is
+  // issued unconditionally (loads under a branch are waited for one by one)
   long long s1 = g.N[0], s2 = (long long)g.N[0] * g.N[1];
-  if (i0 > 0) nb += to_d(x[f - 1]);
-  if (i0 < g.n[0]) nb += to_d(x[f + 1]);
-  if (i1 > 0) nb += to_d(x[f - s1]);
-  if (i1 < g.n[1]) nb += to_d(x[f + s1]);
+  const bool b0 = i0 > 0, b1 = i0 < g.n[0], b2 = i1 > 0, b3 = i1 < g.n[1];
+  cd x0 = to_d(x[f]);
+  cd xa = to_d(x[b0 ? f - 1 : f]), xb = to_d(x[b1 ? f + 1 : f]);
+  cd xc = to_d(x[b2 ? f - s1 : f]), xd = to_d(x[b3 ? f + s1 : f]);
+  cd nb = (b0 ? 1.0 : 0.0) * xa + (b1 ? 1.0 : 0.0) * xb + (b2 ? 1.0 : 0.0) * xc + (b3 ? 1.0 : 0.0) * xd;
   if (g.dim == 3) {
-    if (i2 > 0) nb += to_d(x[f - s2]);
-    if (i2 < g.n[2]) nb += to_d(x[f + s2]);
+    const bool b4 = i2 > 0, b5 = i2 < g.n[2];
+    cd xe = to_d(x[b4 ? f - s2 : f]), xf = to_d(x[b5 ? f + s2 : f]);
+    nb += (b4 ? 1.0 : 0.0) * xe + (b5 ? 1.0 : 0.0) * xf;
   }
-  return D * to_d(x[f]) - a.op.inv_h2 * nb;
+  return D * x0 - a.op.inv_h2 * nb;
 }
 
 // wave-level partial sums of nv values, then one fixed-order sum over the 4 waves per value
@@ -77,33 +80,40 @@ __device__ __forceinline__ void store_partials(cd (*red)[2 * KMAXM + 3], int nv,
 }
 
 // w = H z_j (FP64); partials of <V_i, w> (values 0..j), <V_i, V_j> (values j+1..2j+1) and
-// ||w||^2 (value 2j+2, real part)
+// ||w||^2 (value 2j+2, real part).  Nodes past the end are clamped to the last node and
+// weighted 0; basis vector i + 1 is loaded while vector i is reduced.
 template <typename CZ>
 __global__ void __launch_bounds__(256) k_arnoldi_dots(KrylovArgs a, const CZ* __restrict__ z, int j) {
   __shared__ cd red[4][2 * KMAXM + 3];
+  if (a.st->done) return;          // an iteration queued after convergence: nothing to do
   const long long N = a.op.g.tot;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  cd w[KNPT], vj[KNPT];
+  long long f[KNPT];
+  double on[KNPT];
+  for (int q = 0; q < KNPT; ++q) {
+    long long t = node_of(q);
+    on[q] = t < N ? 1.0 : 0.0;
+    f[q] = t < N ? t : N - 1;
+  }
+  cd w[KNPT], vj[KNPT], nx[KNPT];
+  for (int q = 0; q < KNPT; ++q) {
+    vj[q] = on[q] * a.V[(long long)j * a.ldv + f[q]];
+    nx[q] = a.V[f[q]];
+  }
   double nw = 0.0;
   for (int q = 0; q < KNPT; ++q) {
-    long long f = node_of(q);
-    w[q] = mk(0.0, 0.0);
-    vj[q] = mk(0.0, 0.0);
-    if (f < N) {
-      w[q] = apply_h(a, z, f);
-      vj[q] = a.V[(long long)j * a.ldv + f];
-      nw += abs2(w[q]);
-    }
+    w[q] = on[q] * apply_h(a, z, f[q]);
+    nw += abs2(w[q]);
   }
   for (int i = 0; i <= j; ++i) {
+    cd vi[KNPT];
+    for (int q = 0; q < KNPT; ++q) vi[q] = nx[q];
+    const long long in = (long long)(i < j ? i + 1 : j) * a.ldv;   // the last pass reloads V_j
+    for (int q = 0; q < KNPT; ++q) nx[q] = a.V[in + f[q]];
     cd s1 = mk(0.0, 0.0), s2 = mk(0.0, 0.0);
     for (int q = 0; q < KNPT; ++q) {
-      long long f = node_of(q);
-      if (f < N) {
-        cd vi = i == j ? vj[q] : a.V[(long long)i * a.ldv + f];
-        s1 += cmulc(vi, w[q]);
-        s2 += cmulc(vi, vj[q]);
-      }
+      s1 += cmulc(vi[q], w[q]);
+      s2 += cmulc(vi[q], vj[q]);
     }
     s1 = wsum(s1);
     s2 = wsum(s2);
@@ -166,7 +176,9 @@ __device__ inline void givens(cd a, cd b, double& c, cd& s, cd& r) {
 __global__ void __launch_bounds__(64) k_givens(KrylovArgs a, int j, double tol) {
   __shared__ cd sh1[KMAXM + 1], sg[KMAXM + 1], sc[KMAXM + 1], col[KMAXM + 2], ssn[KMAXM];
   __shared__ double scs[KMAXM], r1[64], r2[64];
+  __shared__ cd sG[(KMAXM + 1) * (KMAXM + 1)];
   KrylovState* st = a.st;
+  if (st->done) return;            // converged in an earlier column: the state stays as it is
   const int t = threadIdx.x, ld = KMAXM + 1;
   for (int i = t; i <= j; i += 64) {
     sh1[i] = st->h1[i];
@@ -176,13 +188,16 @@ __global__ void __launch_bounds__(64) k_givens(KrylovArgs a, int j, double tol) 
     scs[i] = st->cs[i];
     ssn[i] = st->sn[i];
   }
+  // G(i, k): k < j from earlier columns, column / row j from this pass; staged in LDS so
+  // that the products below do not wait on global loads one by one
+  for (int e = t; e < j * j; e += 64) sG[(e % j) + ld * (e / j)] = st->G[(e % j) + ld * (e / j)];
   __syncthreads();
-  // G(i, k): k < j from earlier columns, column / row j from this pass
-  auto gik = [&](int i, int k) -> cd {
-    if (k == j) return sg[i];
-    if (i == j) return conjc(sg[k]);
-    return st->G[i + ld * k];
-  };
+  for (int i = t; i <= j; i += 64) {
+    sG[j + ld * i] = conjc(sg[i]);
+    sG[i + ld * j] = sg[i];                    // the diagonal entry as summed
+  }
+  __syncthreads();
+  auto gik = [&](int i, int k) -> cd { return sG[i + ld * k]; };
   // c = h1 + (h1 - G h1)
   for (int i = t; i <= j; i += 64) {
     cd gh = mk(0.0, 0.0);
@@ -245,29 +260,40 @@ __global__ void __launch_bounds__(64) k_givens(KrylovArgs a, int j, double tol) 
   for (int i = t; i <= j; i += 64) st->c[i] = sc[i];
 }
 
-// V_{j+1} = (H z_j - sum_i c_i V_i) / h_{j+1,j}
+// V_{j+1} = (H z_j - sum_i c_i V_i) / h_{j+1,j}.  The blocks take the nodes in reverse
+// order: the dots pass just streamed the same basis front to back, so its last part is
+// the most likely to still be in the memory-side cache.
 template <typename CZ>
 __global__ void __launch_bounds__(256) k_arnoldi_update(KrylovArgs a, const CZ* __restrict__ z, int j) {
   __shared__ cd sc[KMAXM + 1];
   __shared__ double sinv;
+  if (a.st->done) return;
   if (threadIdx.x <= j) sc[threadIdx.x] = a.st->c[threadIdx.x];
   if (threadIdx.x == 0) sinv = a.st->hnext > 0.0 ? 1.0 / a.st->hnext : 0.0;
-  __syncthreads();
   const long long N = a.op.g.tot;
-  cd w[KNPT];
+  const long long blk = (long long)gridDim.x - 1 - blockIdx.x;
+  long long f[KNPT];
+  bool ok[KNPT];
   for (int q = 0; q < KNPT; ++q) {
-    long long f = node_of(q);
-    w[q] = f < N ? apply_h(a, z, f) : mk(0.0, 0.0);
+    long long t = (blk * KNPT + q) * 256 + threadIdx.x;
+    ok[q] = t < N;
+    f[q] = ok[q] ? t : N - 1;
   }
-  for (int i = 0; i <= j; ++i)
-    for (int q = 0; q < KNPT; ++q) {
-      long long f = node_of(q);
-      if (f < N) w[q] -= sc[i] * a.V[(long long)i * a.ldv + f];
-    }
-  for (int q = 0; q < KNPT; ++q) {
-    long long f = node_of(q);
-    if (f < N) a.V[(long long)(j + 1) * a.ldv + f] = sinv * w[q];
+  cd w[KNPT], nx[KNPT];
+  for (int q = 0; q < KNPT; ++q) nx[q] = a.V[f[q]];
+  for (int q = 0; q < KNPT; ++q) w[q] = apply_h(a, z, f[q]);
+  __syncthreads();
+  for (int i = 0; i <= j; ++i) {
+    cd vi[KNPT];
+    for (int q = 0; q < KNPT; ++q) vi[q] = nx[q];
+    const long long in = (long long)(i < j ? i + 1 : j) * a.ldv;   // the last pass reloads V_j
+    for (int q = 0; q < KNPT; ++q) nx[q] = a.V[in + f[q]];
+    const cd ci = sc[i];
+    for (int q = 0; q < KNPT; ++q) w[q] -= ci * vi[q];
   }
+  const double si = sinv;
+  for (int q = 0; q < KNPT; ++q)
+    if (ok[q]) a.V[(long long)(j + 1) * a.ldv + f[q]] = si * w[q];
 }
 
 // restart bookkeeping from tmp = (||r||^2, ||b||^2): beta0, g = beta0 e1

@@ -16,6 +16,8 @@
 // Solve (per right-hand side, cycle precision): forward over the tree bottom-up,
 //     [g_S; t_B] = [A^-1; C A^-1] f_S,   u_B = v_B - t_B  (passed to the parent),
 // then backward top-down,  x_S = g_S + (-A^-1 B) x_B.
+#include <stdexcept>
+
 #include "internal.h"
 
 namespace helm {
@@ -55,92 +57,167 @@ __global__ void __launch_bounds__(256) k_nd_extend(const NDFrontDev* __restrict_
   }
 }
 
-// Panel [k0, k0 + kbb) of every front of one height with the panel block (nF x KB)
-// resident in LDS: one 1024-thread work-group per front; per pivot a block-wide
-// argmax, an LDS row swap and the exchange update of the panel columns.  Row swaps
-// of the columns outside the panel are recorded in swp and applied by
-// k_nd_swap_rest.
-__device__ __forceinline__ void argmax_block1024(double v, int idx, double* sv, int* si, double& bv, int& bi) {
-  for (int o = 32; o > 0; o >>= 1) {
-    double ov = __shfl_xor(v, o, 64);
-    int oi = __shfl_xor(idx, o, 64);
-    if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
-  }
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (lane == 0) { sv[w] = v; si[w] = idx; }
-  __syncthreads();
-  bv = sv[0];
-  bi = si[0];
-  for (int q = 1; q < (int)(blockDim.x >> 6); ++q)
-    if (sv[q] > bv || (sv[q] == bv && si[q] < bi)) { bv = sv[q]; bi = si[q]; }
-  __syncthreads();
+// Panel [k0, k0 + kbb) of every front of one height with the panel block held in
+// registers: one NT-thread work-group per front, thread t owning rows t, t + NT, ...
+// (R rows of KB entries each, and the rows' permutation entries).  Per pivot: a
+// block-wide argmax (the candidates come out of the previous pivot's update), the
+// exchange of rows k and p through LDS (the new pivot row is then read by every thread),
+// and the exchange update of each owned row in registers.  Row swaps of the columns
+// outside the panel are recorded in swp and applied by k_nd_swap_rest.
+// (v, i) <- the larger value, the lower index on ties; branch-free
+__device__ __forceinline__ void amax_step(double& v, int& i, double ov, int oi) {
+  const bool t = (ov > v) | ((ov == v) & (oi < i));
+  v = t ? ov : v;
+  i = t ? oi : i;
 }
 
-__global__ void __launch_bounds__(1024) k_nd_panel_lds(const NDFrontDev* __restrict__ fr, const int* __restrict__ ids,
-                                                       cd* __restrict__ Fp, int* __restrict__ perm,
-                                                       int* __restrict__ swp, int k0, int KB, int* __restrict__ err) {
-  extern __shared__ char smem[];
-  cd* P = (cd*)smem;                                   // nF x KB
-  __shared__ cd s_rk[32];
+// one argmax step against the lane chosen by a DPP permutation (quad_perm / mirrors)
+template <int CTRL>
+__device__ __forceinline__ void amax_dpp(double& v, int& i) {
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, false);
+  const int oi = __builtin_amdgcn_mov_dpp(i, CTRL, 0xf, 0xf, false);
+  amax_step(v, i, __hiloint2double(hi, lo), oi);
+}
+
+// argmax over the 16 lanes of each DPP row: xor 1, xor 2 (quad permutations), then the
+// half-row and row mirrors; every lane of a row ends with the row's result
+__device__ __forceinline__ void amax_row16(double& v, int& i) {
+  amax_dpp<0xB1>(v, i);
+  amax_dpp<0x4E>(v, i);
+  amax_dpp<0x141>(v, i);
+  amax_dpp<0x140>(v, i);
+}
+
+__device__ __forceinline__ void amax_lane(double& v, int& i, double w, int j, int lane) {
+  amax_step(v, i, __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(w), lane),
+                                   __builtin_amdgcn_readlane(__double2loint(w), lane)),
+            __builtin_amdgcn_readlane(j, lane));
+}
+
+// block-wide argmax (at most 16 waves); the result is uniform.  sv / si may be rewritten
+// only after a later barrier.
+__device__ __forceinline__ void argmax_block(double v, int idx, double* sv, int* si, double& bv, int& bi) {
+  amax_row16(v, idx);
+  double w = v;
+  int j = idx;
+  v = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(w), 0), __builtin_amdgcn_readlane(__double2loint(w), 0));
+  idx = __builtin_amdgcn_readlane(j, 0);
+  amax_lane(v, idx, w, j, 16);
+  amax_lane(v, idx, w, j, 32);
+  amax_lane(v, idx, w, j, 48);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (int)(blockDim.x >> 6);
+  if (lane == 0) { sv[wv] = v; si[wv] = idx; }
+  __syncthreads();
+  v = lane < nw ? sv[lane] : -2.0;
+  idx = lane < nw ? si[lane] : 0x7fffffff;
+  amax_row16(v, idx);
+  bv = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 0), __builtin_amdgcn_readlane(__double2loint(v), 0));
+  bi = __builtin_amdgcn_readlane(idx, 0);
+}
+
+// panel width of the register panel for fronts of up to nF rows (0: too large for it)
+int panel_reg_kb(int nF) { return nF <= 256 ? 32 : nF <= 1024 ? 16 : nF <= 2048 ? 8 : 0; }
+
+// The column loop stays rolled (an unrolled one overflows the instruction cache); so that
+// registers are still indexed by constants, a thread's KB entries of a row are kept
+// rotated: before pivot kk, slot jj holds panel column (kk + jj) mod KB, the update of
+// pivot kk writes column (kk + 1 + jj) mod KB into slot jj.
+template <int KB, int R, int NT>
+__global__ void __launch_bounds__(NT) k_nd_panel_reg(const NDFrontDev* __restrict__ fr, const int* __restrict__ ids,
+                                                     cd* __restrict__ Fp, int* __restrict__ perm,
+                                                     int* __restrict__ swp, int k0, int* __restrict__ err) {
+  __shared__ cd s_rk[KB], s_rp[KB];      // rows p (the new pivot row k) and k before the swap, by column
+  __shared__ int s_pp, s_pk;              // their permutation entries
   __shared__ double s_v[16];
   __shared__ int s_i[16];
   const NDFrontDev f = fr[ids[blockIdx.x]];
   if (f.nS <= k0) return;
   const int kbb = min(KB, f.nS - k0);
-  const int nF = f.nF, tid = threadIdx.x, nt = blockDim.x;
+  const int nF = f.nF, nS = f.nS, tid = threadIdx.x, w0 = tid & ~63;
   cd* F = Fp + f.F_off;
   int* pm = perm + f.perm_off;
   int* sw = swp + (long long)blockIdx.x * 32;
-  for (int e = tid; e < nF * kbb; e += nt) {
-    int i = e / kbb, jj = e % kbb;
-    P[i * KB + jj] = F[(long long)i * nF + k0 + jj];
+  cd a[R][KB];
+  int pr[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = min(tid + r * NT, nF - 1);
+    const long long row = (long long)i * nF + k0;
+#pragma unroll
+    for (int jj = 0; jj < KB; ++jj) a[r][jj] = F[row + min(jj, kbb - 1)];
+    pr[r] = pm[min(i, nS - 1)];
   }
-  __syncthreads();
+  double best = -1.0;
+  int bi = k0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = tid + r * NT;
+    if (i >= k0 && i < nS) amax_step(best, bi, abs2(a[r][0]), i);
+  }
   for (int kk = 0; kk < kbb; ++kk) {
     const int k = k0 + kk;
-    double best = -1.0;
-    int bi = k;
-    for (int i = k + tid; i < f.nS; i += nt) {
-      double v = abs2(P[i * KB + kk]);
-      if (v > best || (v == best && i < bi)) { best = v; bi = i; }
-    }
     double pv;
     int p;
-    argmax_block1024(best, bi, s_v, s_i, pv, p);
-    if (p != k && tid < kbb) {
-      cd t = P[k * KB + tid];
-      P[k * KB + tid] = P[p * KB + tid];
-      P[p * KB + tid] = t;
+    argmax_block(best, bi, s_v, s_i, pv, p);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = tid + r * NT;
+      if (i == p) {
+#pragma unroll
+        for (int jj = 0; jj < KB; ++jj) s_rk[(kk + jj) % KB] = a[r][jj];
+        s_pp = pr[r];
+      }
+      if (i == k) {
+#pragma unroll
+        for (int jj = 0; jj < KB; ++jj) s_rp[(kk + jj) % KB] = a[r][jj];
+        s_pk = pr[r];
+      }
     }
     if (tid == 0) {
       sw[kk] = p;
-      if (p != k) {
-        int t = pm[k];
-        pm[k] = pm[p];
-        pm[p] = t;
-      }
       if (!(pv > 0.0)) atomicOr(err, 1);
     }
-    __syncthreads();
-    if (tid < kbb) s_rk[tid] = P[k * KB + tid];
     __syncthreads();
     cd piv = s_rk[kk];
     if (!(pv > 0.0)) piv = mk(1.0, 0.0);
     const cd inv = cdiv(mk(1.0, 0.0), piv);
-    for (int i = tid; i < nF; i += nt) {
-      if (i == k) continue;
-      cd* row = P + i * KB;
-      cd ck = row[kk] * inv;
-      for (int jj = 0; jj < kbb; ++jj)
-        if (jj != kk) row[jj] -= ck * s_rk[jj];
-      row[kk] = ck;
+    best = -1.0;
+    bi = k + 1;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (w0 + r * NT >= nF) continue;           // the wave's rows of this slot are all padding
+      const int i = tid + r * NT;
+      if (i == p && p != k) {                    // row p takes the old row k
+#pragma unroll
+        for (int jj = 0; jj < KB; ++jj) a[r][jj] = s_rp[(kk + jj) % KB];
+        pr[r] = s_pk;
+      }
+      if (i == k) {                              // the pivot row after the exchange
+#pragma unroll
+        for (int jj = 0; jj + 1 < KB; ++jj) a[r][jj] = -(s_rk[(kk + 1 + jj) % KB] * inv);
+        a[r][KB - 1] = inv;
+        pr[r] = s_pp;
+      } else {                                   // exchange update, shifted by one slot
+        const cd ck = a[r][0] * inv;
+#pragma unroll
+        for (int jj = 0; jj + 1 < KB; ++jj) a[r][jj] = a[r][jj + 1] - ck * s_rk[(kk + 1 + jj) % KB];
+        a[r][KB - 1] = ck;
+        if (kk + 1 < kbb && i > k && i < nS) amax_step(best, bi, abs2(a[r][0]), i);
+      }
     }
-    if (tid < kbb) P[k * KB + tid] = (tid == kk) ? inv : -(s_rk[tid] * inv);
-    __syncthreads();
   }
-  for (int e = tid; e < nF * kbb; e += nt) {
-    int i = e / kbb, jj = e % kbb;
-    F[(long long)i * nF + k0 + jj] = P[i * KB + jj];
+  // slot jj now holds column (kbb + jj) mod KB
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int i = tid + r * NT;
+    if (i < nF)
+#pragma unroll
+      for (int jj = 0; jj < KB; ++jj) {
+        const int c = (kbb + jj) % KB;
+        if (c < kbb) F[(long long)i * nF + k0 + c] = a[r][jj];
+      }
+    if (i >= k0 && i < nS) pm[i] = pr[r];
   }
 }
 
@@ -803,12 +880,21 @@ void nd_panel_multi(const NDFrontDev* fr, const int* ids, int nids, int max_nF, 
   unsigned gx = (unsigned)std::min(64, std::max(1, (max_nF + 255) / 256));
   hipLaunchKernelGGL(k_nd_swap_rest, dim3(gx, nids), dim3(256), 0, s, fr, ids, Fp, swp, k0, kb);
 }
-void nd_panel_lds(const NDFrontDev* fr, const int* ids, int nids, int max_nF, cd* Fp, int* perm, int* swp, int k0,
+void nd_panel_reg(const NDFrontDev* fr, const int* ids, int nids, int max_nF, cd* Fp, int* perm, int* swp, int k0,
                   int kb, int* err, hipStream_t s) {
-  size_t lds = (size_t)max_nF * kb * sizeof(cd);
-  if (lds > 65536) (void)hipFuncSetAttribute((const void*)k_nd_panel_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                             (int)lds);
-  hipLaunchKernelGGL(k_nd_panel_lds, dim3(nids), dim3(1024), lds, s, fr, ids, Fp, perm, swp, k0, kb, err);
+  // variants: rows per thread R x panel width KB <= 32 entries in registers
+  if (kb == 32 && max_nF <= 128)
+    hipLaunchKernelGGL((k_nd_panel_reg<32, 1, 128>), dim3(nids), dim3(128), 0, s, fr, ids, Fp, perm, swp, k0, err);
+  else if (kb == 32 && max_nF <= 256)
+    hipLaunchKernelGGL((k_nd_panel_reg<32, 1, 256>), dim3(nids), dim3(256), 0, s, fr, ids, Fp, perm, swp, k0, err);
+  else if (kb == 16 && max_nF <= 512)
+    hipLaunchKernelGGL((k_nd_panel_reg<16, 2, 256>), dim3(nids), dim3(256), 0, s, fr, ids, Fp, perm, swp, k0, err);
+  else if (kb == 16 && max_nF <= 1024)
+    hipLaunchKernelGGL((k_nd_panel_reg<16, 2, 512>), dim3(nids), dim3(512), 0, s, fr, ids, Fp, perm, swp, k0, err);
+  else if (kb == 8 && max_nF <= 2048)
+    hipLaunchKernelGGL((k_nd_panel_reg<8, 4, 512>), dim3(nids), dim3(512), 0, s, fr, ids, Fp, perm, swp, k0, err);
+  else
+    throw std::runtime_error("register panel: unsupported front size / panel width");
   unsigned gx = (unsigned)std::min(64, std::max(1, (max_nF + 255) / 256));
   hipLaunchKernelGGL(k_nd_swap_rest, dim3(gx, nids), dim3(256), 0, s, fr, ids, Fp, swp, k0, kb);
 }
