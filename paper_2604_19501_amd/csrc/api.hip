@@ -45,6 +45,9 @@ int panel_reg_kb(int nF);
 void nd_panel_reg(const NDFrontDev* fr, const int* ids, int nids, int max_nF, cd* Fp, int* perm, int* swp, int k0,
                   int kb, int* err, hipStream_t s);
 template <typename C>
+void nd_flow(const NDFlowDev& d, const NDFrontDev* fr, const int* idx, const int* cptr, const int* cidx, const C* Lp,
+             const C* Wp, C* upd, const C* r, C* x, C* gbuf, int conj, hipStream_t s);
+template <typename C>
 void nd_bwd(const NDLaunchDev& L, const NDFrontDev* fr, const int* idx, const int* cidx, const C* Wp, C* upd, C* x,
             C* gvec, int cap, int conj, C* gbuf, C* P, hipStream_t s);
 void grad_accumulate(const FineOp& op, double omega, const cd* u, const cd* lam, double* g, int first,
@@ -105,6 +108,8 @@ struct NDDev {        // device-side ND tables (pointers into the workspace)
   void *gbuf = nullptr, *part = nullptr;     // split-K launches: gathered vectors, partial products
   std::vector<NDLaunchDev> launch[2];   // forward, backward
   int gvec_cap = 0;
+  NDFlowDev flow;                       // dataflow substitution (one launch per solve)
+  void* fgbuf = nullptr;                // its gather buffer
 };
 
 // kernel classes timed with HIP events when timing is on
@@ -140,6 +145,8 @@ struct helm_ctx {
        *x3 = nullptr;
   cd *r3d = nullptr, *e3d = nullptr;
   NDPlan plan;
+  NDFlow flow;          // dataflow task queue (used when use_flow)
+  int use_flow = 0;
   NDDev nd;
   std::vector<HeightInfo> hinfo;
   std::vector<long long> hlist_toff;
@@ -305,6 +312,10 @@ void build_plan(helm_ctx* c) {
   const long long splitk = (long long)env_int("HELM_ND_SPLITK_KB", 4096) * 1024;
   nd_plan(c->g3, leaf, 16, merge, (int)c->csz, lds, cuts, splitk, c->plan);
   NDPlan& P = c->plan;
+  // HELM_ND_FLOW=1: the substitutions run as one dataflow launch each solve
+  // (heights above the tree-block launches)
+  c->use_flow = env_int("HELM_ND_FLOW", 0);
+  if (c->use_flow) nd_flow_plan(P, P.cuts.empty() || P.cuts[0] < 0 ? 0 : P.cuts.back() + 1, c->flow);
   c->hlist.clear();
   c->hlist_toff.clear();
   c->hinfo.clear();
@@ -439,6 +450,18 @@ size_t carve(helm_ctx* c, void* ws) {
   d.gvec = gcap ? cv.take<char>(cs * gcap * gneed) : nullptr;
   d.gbuf = cv.take<char>(cs * gbuf_max);
   d.part = cv.take<char>(cs * part_max);
+  if (c->use_flow) {
+    const NDFlow& F = c->flow;
+    d.flow.tasks = cv.take<NDFlowTask>(std::max<size_t>(1, F.tasks.size()));
+    d.flow.sigs = cv.take<int>(std::max<size_t>(1, F.sigs.size()));
+    d.flow.ctr = cv.take<int>(F.nctr + 3);
+    d.flow.ntasks = (int)F.tasks.size();
+    d.flow.nctr = F.nctr;
+    d.flow.vec_max = F.vec_max;
+    d.flow.grid = std::max(1, std::min(d.flow.ntasks, env_int("HELM_ND_FLOW_GRID", 2048)));
+    d.flow.spin_limit = env_int("HELM_ND_FLOW_SPIN", 1 << 20);
+    d.fgbuf = cv.take<char>(cs * F.gbuf);
+  }
   // Krylov
   c->V = cv.take<cd>((size_t)(m + 1) * g1.tot);
   c->Z = cv.take<char>(cs * (size_t)m * g1.tot);
@@ -533,6 +556,22 @@ void ev_flush(helm_ctx* c) {
 template <typename C>
 void nd_solve(helm_ctx* c, const C* r, C* x, int conj, hipStream_t s) {
   NDDev& d = c->nd;
+  if (c->use_flow) {      // tree-block launches, the dataflow launch, tree-block launches
+    for (const NDLaunchDev& L : d.launch[0])
+      if (L.kind == 2)
+        TIMED(c, KT_ND_FWD, s,
+              nd_fwd<C>(L, d.fronts, d.idx, d.cptr, d.cidx, (const C*)d.L, (C*)d.upd, r, x, nullptr, 0, conj,
+                        (C*)d.gbuf, (C*)d.part, s));
+    TIMED(c, KT_ND_FWD, s,
+          nd_flow<C>(d.flow, d.fronts, d.idx, d.cptr, d.cidx, (const C*)d.L, (const C*)d.W, (C*)d.upd, r, x,
+                     (C*)d.fgbuf, conj, s));
+    for (const NDLaunchDev& L : d.launch[1])
+      if (L.kind == 2)
+        TIMED(c, KT_ND_BWD, s,
+              nd_bwd<C>(L, d.fronts, d.idx, d.cidx, (const C*)d.W, (C*)d.upd, x, nullptr, 0, conj, (C*)d.gbuf,
+                        (C*)d.part, s));
+    return;
+  }
   for (const NDLaunchDev& L : d.launch[0]) {
     C* gv = L.kind == 1 && L.shm == 0 ? (C*)d.gvec : nullptr;
     TIMED(c, KT_ND_FWD, s,
@@ -918,6 +957,11 @@ int helm_setup(const helm_grid* grid, const double* slowness, double omega, cons
     up(d.asmv, P.asmv, s);
     up(d.hlist, c->hlist, s);
     up(d.toff, c->hlist_toff, s);
+    if (c->use_flow) {
+      up((NDFlowTask*)d.flow.tasks, c->flow.tasks, s);
+      up((int*)d.flow.sigs, c->flow.sigs, s);
+      CK(hipMemsetAsync(d.flow.ctr, 0, sizeof(int) * (c->flow.nctr + 3), s));
+    }
     for (int fb = 0; fb < 2; ++fb) {
       std::vector<NDLaunch>& Ls = fb == 0 ? P.fwd : P.bwd;
       for (size_t l = 0; l < Ls.size(); ++l) {
@@ -1085,6 +1129,15 @@ int helm_solve(helm_ctx* c, int op, const void* rhs, void* x, double tol, int ma
     int st = c->f32 ? solve_impl<float>(c, op, (const cd*)rhs, (cd*)x, tol, max_iter, info, s)
                     : solve_impl<double>(c, op, (const cd*)rhs, (cd*)x, tol, max_iter, info, s);
     CK(hipGetLastError());
+    if (c->use_flow) {     // a dataflow wait that gave up leaves its flag (the stream is idle here)
+      int* flag = c->nd.flow.ctr + c->nd.flow.nctr + 2;
+      int e = 0;
+      CK(hipMemcpy(&e, flag, sizeof(int), hipMemcpyDeviceToHost));
+      if (e) {
+        CK(hipMemset(flag, 0, sizeof(int)));
+        return fail(HELM_EDEVICE, "coarsest-grid substitution: a dataflow wait timed out");
+      }
+    }
     return st;
   } catch (DevErr& e) {
     return fail(HELM_EDEVICE, "%s", e.what());

@@ -141,28 +141,44 @@ __device__ __forceinline__ bool tile_origin(const TileGrid& tg, int bx, int by, 
   return true;
 }
 
-// stage x_in on the box [s0, s0+SX) x [s1, s1+SY) x [s2, s2+SZ)
-template <int DIM, int XIN, class Op, typename C, typename CB, typename R>
+// clamp a node to the grid (loads then stay in bounds and are issued unconditionally;
+// the caller zeroes what lies outside)
+__device__ __forceinline__ void clamp_node(const Geom& g, int& i0, int& i1, int& i2) {
+  i0 = min(max(i0, 0), g.n[0]);
+  i1 = min(max(i1, 0), g.n[1]);
+  i2 = min(max(i2, 0), g.n[2]);
+}
+
+// stage x_in on the box [s0, s0+SX) x [s1, s1+SY) x [s2, s2+SZ); every thread's loads of
+// all its nodes are issued before any is used (unrolled, indices clamped)
+template <int DIM, int XIN, int SX, int SY, int SZ, class Op, typename C, typename CB, typename R>
 __device__ __forceinline__ void stage_xin(const Op& op, const C* __restrict__ x, const CB* __restrict__ b, R w_in,
                                           const C* es, int ex, int ey, int c0, int c1, int c2, int s0, int s1,
-                                          int s2, int SX, int SY, int SZ, C* xs) {
+                                          int s2, C* xs) {
   const Geom& g = op.geom();
-  const int tot = SX * SY * SZ;
-  for (int k = threadIdx.x; k < tot; k += 256) {
+  constexpr int tot = SX * SY * SZ, NIT = (tot + 255) / 256;
+  for (int i4 = 0; i4 < NIT; i4 += 4)          // groups of 4 passes bound the registers in 3D
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int it = i4 + u;
+    if (NIT % 4 != 0 && it >= NIT) break;
+    const int k = min((int)threadIdx.x + 256 * it, tot - 1);
     const int a = k % SX, q = k / SX;
     const int i0 = s0 + a, i1 = s1 + q % SY, i2 = s2 + q / SY;
+    int j0 = i0, j1 = i1, j2 = i2;
+    clamp_node(g, j0, j1, j2);
+    const long long f = flat(g, j0, j1, j2);
     C v = mk((R)0, (R)0);
-    if (inside(g, i0, i1, i2)) {
-      const long long f = flat(g, i0, i1, i2);
-      if (XIN & XIN_X) v += x[f];
-      if (XIN & XIN_Z) v += w_in * cdiv(conv<C>::from(b[f]), op.diag(f, i0, i1, i2));
-      if (XIN & XIN_E) v += prolong_lds<DIM>(es, ex, ey, c0, c1, c2, i0, i1, i2);
-    }
-    xs[k] = v;
+    if (XIN & XIN_X) v += x[f];
+    if (XIN & XIN_Z) v += w_in * cdiv(conv<C>::from(b[f]), op.diag(f, j0, j1, j2));
+    if (XIN & XIN_E) v += prolong_lds<DIM>(es, ex, ey, c0, c1, c2, j0, j1, j2);
+    if (!inside(g, i0, i1, i2)) v = mk((R)0, (R)0);
+    if ((int)threadIdx.x + 256 * it < tot) xs[k] = v;
   }
 }
 
-// x_out = x_in + w D^{-1}(b - A x_in) on one box (w = 0: materialise x_in)
+// x_out = x_in + w D^{-1}(b - A x_in) on one box (w = 0: materialise x_in).  The output
+// nodes' b and D are loaded before the staging barriers, so their latency overlaps it.
 template <int DIM, class Op, typename CB, typename CO, int XIN>
 __global__ void __launch_bounds__(256) k_sweep(Op op, const typename Op::C* __restrict__ x,
                                                const CB* __restrict__ b, typename Op::Real w_in, Geom gc,
@@ -173,6 +189,7 @@ __global__ void __launch_bounds__(256) k_sweep(Op op, const typename Op::C* __re
   constexpr int TX = SBox<DIM>::x, TY = SBox<DIM>::y, TZ = SBox<DIM>::z;
   constexpr int SX = TX + 2, SY = TY + 2, SZ = DIM == 3 ? TZ + 2 : 1;
   constexpr int EX = TX / 2 + 3, EY = TY / 2 + 3, EZ = DIM == 3 ? TZ / 2 + 3 : 1;
+  constexpr int NOUT = TX * TY * TZ / 256;
   __shared__ C xs[SX * SY * SZ];
   __shared__ C es[(XIN & XIN_E) ? EX * EY * EZ : 1];
   const Geom& g = op.geom();
@@ -181,26 +198,43 @@ __global__ void __launch_bounds__(256) k_sweep(Op op, const typename Op::C* __re
   const int s0 = o0 - 1, s1 = o1 - 1, s2 = DIM == 3 ? o2 - 1 : 0;
   const int c0 = s0 >> 1, c1 = s1 >> 1, c2 = s2 >> 1;   // floor: s may be -1
   if (XIN & XIN_E) {
-    for (int k = threadIdx.x; k < EX * EY * EZ; k += 256) {
+    constexpr int tot = EX * EY * EZ, NIT = (tot + 255) / 256;
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int k = min((int)threadIdx.x + 256 * it, tot - 1);
       const int a = k % EX, q = k / EX;
       const int j0 = c0 + a, j1 = c1 + q % EY, j2 = (DIM == 3 ? c2 : 0) + q / EY;
-      C v = mk((R)0, (R)0);
-      if (inside(gc, j0, j1, j2)) v = e[flat(gc, j0, j1, j2)];
-      es[k] = v;
+      int l0 = j0, l1 = j1, l2 = j2;
+      clamp_node(gc, l0, l1, l2);
+      C v = e[flat(gc, l0, l1, l2)];
+      if (!inside(gc, j0, j1, j2)) v = mk((R)0, (R)0);
+      if ((int)threadIdx.x + 256 * it < tot) es[k] = v;
     }
-    __syncthreads();
   }
-  stage_xin<DIM, XIN>(op, x, b, w_in, es, EX, EY, c0, c1, c2, s0, s1, s2, SX, SY, SZ, xs);
+  C bo[NOUT], Do[NOUT];
+#pragma unroll
+  for (int it = 0; it < NOUT; ++it) {
+    const int k = (int)threadIdx.x + 256 * it;
+    const int a = k % TX, q = k / TX;
+    int i0 = o0 + a, i1 = o1 + q % TY, i2 = o2 + q / TY;
+    clamp_node(g, i0, i1, i2);
+    const long long f = flat(g, i0, i1, i2);
+    bo[it] = conv<C>::from(b[f]);
+    Do[it] = op.diag(f, i0, i1, i2);
+  }
+  if (XIN & XIN_E) __syncthreads();
+  stage_xin<DIM, XIN, SX, SY, SZ>(op, x, b, w_in, es, EX, EY, c0, c1, c2, s0, s1, s2, xs);
   __syncthreads();
-  for (int k = threadIdx.x; k < TX * TY * TZ; k += 256) {
+#pragma unroll
+  for (int it = 0; it < NOUT; ++it) {
+    const int k = (int)threadIdx.x + 256 * it;
     const int a = k % TX, q = k / TX;
     const int i0 = o0 + a, i1 = o1 + q % TY, i2 = o2 + q / TY;
     if (!inside(g, i0, i1, i2)) continue;
     const long long f = flat(g, i0, i1, i2);
     const int kk = (a + 1) + SX * ((q % TY + 1) + SY * (DIM == 3 ? q / TY + 1 : 0));
-    const C D = op.diag(f, i0, i1, i2);
-    const C r = conv<C>::from(b[f]) - op.ax(xs, kk, SX, SX * SY, f, D);
-    out[f] = conv<CO>::from(xs[kk] + w * cdiv(r, D));
+    const C r = bo[it] - op.ax(xs, kk, SX, SX * SY, f, Do[it]);
+    out[f] = conv<CO>::from(xs[kk] + w * cdiv(r, Do[it]));
   }
 }
 
@@ -220,21 +254,48 @@ __global__ void __launch_bounds__(256) k_restrict(Op op, const typename Op::C* _
   int O0, O1, O2;
   if (!tile_origin(tg, CX, CY, CZ, O0, O1, O2)) return;
   const int r0 = 2 * O0 - 1, r1 = 2 * O1 - 1, r2 = DIM == 3 ? 2 * O2 - 1 : 0;
+  // the residual footprint's b and D, loaded before the staging barrier when it takes at
+  // most 4 passes (2D); otherwise in the residual loop
+  constexpr int RT = RX * RY * RZ, NR = (RT + 255) / 256;
+  constexpr bool PRE = NR <= 4;
+  C bv[PRE ? NR : 1], Dv[PRE ? NR : 1];
+  auto load_bd = [&](int it, C& bb, C& dd) {
+    const int k = min((int)threadIdx.x + 256 * it, RT - 1);
+    const int a = k % RX, q = k / RX;
+    int i0 = r0 + a, i1 = r1 + q % RY, i2 = r2 + q / RY;
+    clamp_node(g, i0, i1, i2);
+    const long long f = flat(g, i0, i1, i2);
+    bb = conv<C>::from(b[f]);
+    dd = XIN ? op.diag(f, i0, i1, i2) : mk((R)0, (R)0);
+  };
+  if (PRE)
+#pragma unroll
+    for (int it = 0; it < (PRE ? NR : 1); ++it) load_bd(it, bv[it], Dv[it]);
   if (XIN) {
-    stage_xin<DIM, XIN>(op, x, b, w_in, (const C*)nullptr, 1, 1, 0, 0, 0, r0 - 1, r1 - 1,
-                        DIM == 3 ? r2 - 1 : 0, SX, SY, SZ, xs);
+    stage_xin<DIM, XIN, SX, SY, SZ>(op, x, b, w_in, (const C*)nullptr, 1, 1, 0, 0, 0, r0 - 1, r1 - 1,
+                                    DIM == 3 ? r2 - 1 : 0, xs);
     __syncthreads();
   }
-  for (int k = threadIdx.x; k < RX * RY * RZ; k += 256) {
+#pragma unroll(PRE ? NR : 4)
+  for (int it = 0; it < NR; ++it) {
+    const int k = (int)threadIdx.x + 256 * it;
+    if (k >= RT) continue;
+    C bb, dd;
+    if (PRE) {
+      bb = bv[PRE ? it : 0];
+      dd = Dv[PRE ? it : 0];
+    } else {
+      load_bd(it, bb, dd);
+    }
     const int a = k % RX, q = k / RX;
     const int i0 = r0 + a, i1 = r1 + q % RY, i2 = r2 + q / RY;
     C v = mk((R)0, (R)0);
     if (inside(g, i0, i1, i2)) {
       const long long f = flat(g, i0, i1, i2);
-      v = conv<C>::from(b[f]);
+      v = bb;
       if (XIN) {
         const int kk = (a + 1) + SX * ((q % RY + 1) + SY * (DIM == 3 ? q / RY + 1 : 0));
-        v -= op.ax(xs, kk, SX, SX * SY, f, op.diag(f, i0, i1, i2));
+        v -= op.ax(xs, kk, SX, SX * SY, f, dd);
       }
     }
     rs[k] = v;
