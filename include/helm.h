@@ -150,7 +150,8 @@ int helm_destroy(helm_ctx* ctx);
 
 /* ---- batched form: many media / frequencies / grid sizes, many right-hand sides ---- */
 
-/* Workspace for n_inst instances (grids[i]) and at most max_rhs simultaneous right-hand sides. */
+/* Workspace for n_inst instances (grids[i]), each solving up to min(max_rhs, 16) right-hand
+ * sides in lock-step (every vector buffer of an instance is carved that many times). */
 int helm_workspace_bytes_batched(int n_inst, const helm_grid* grids, const helm_mg* mg,
                                  int max_rhs, size_t* bytes);
 
@@ -161,11 +162,17 @@ int helm_setup_batched(int n_inst, const helm_grid* grids, const double* const* 
                        const double* omega, const helm_shift* shift, const helm_mg* mg,
                        int max_rhs, void* ws, size_t ws_bytes, void* stream, helm_ctx** out);
 
-/* Solve n_rhs systems in lock step; rhs k belongs to instance inst_of_rhs[k].
- *   rhs, x: host arrays of n_rhs device pointers (c128[N1(inst)] each)
+/* Solve n_rhs systems; rhs k belongs to instance inst_of_rhs[k].
+ *   rhs, x: host arrays of n_rhs device pointers (c128[N1(inst)] each; x holds the initial
+ *           guess and receives the solution; rhs[k] != x[k])
  *   info:   host array of n_rhs structs (may be NULL)
- * Converged right-hand sides stop iterating while the others continue.  Returns the
- * worst status over the right-hand sides. */
+ * An instance's right-hand sides are taken in order, in groups of up to its lock-step
+ * capacity: a group runs every kernel once for all its right-hand sides (grid y), each
+ * with its own FGMRES state; one that has converged or stopped does no more Krylov work
+ * while the others continue.  Instances run concurrently on library-owned streams
+ * (HELM_BATCH_STREAMS, default 8).  Each result, status and iteration count equals that
+ * of helm_solve on the instance.  Returns the worst status over the right-hand sides
+ * (the most severe error, else the largest warning). */
 int helm_solve_batched(helm_ctx* ctx, int op, int n_rhs, const int* inst_of_rhs,
                        const void* const* rhs, void* const* x, double tol, int max_iter,
                        helm_solve_info* info, void* stream);

@@ -40,7 +40,8 @@ void nd_finalize(const NDFrontDev* fr, const int* ids, int nids, long long max_n
                  C* Lp, C* Wp, hipStream_t s);
 template <typename C>
 void nd_fwd(const NDLaunchDev& L, const NDFrontDev* fr, const int* idx, const int* cptr, const int* cidx,
-            const C* Lp, C* upd, const C* r, C* x, C* gvec, int cap, int conj, C* gbuf, C* P, hipStream_t s);
+            const C* Lp, C* upd, const C* r, C* x, C* gvec, int cap, int conj, C* gbuf, C* P, const NDRhs& rh,
+            hipStream_t s);
 int panel_reg_kb(int nF);
 void nd_panel_reg(const NDFrontDev* fr, const int* ids, int nids, int max_nF, cd* Fp, int* perm, int* swp, int k0,
                   int kb, int* err, hipStream_t s);
@@ -49,7 +50,7 @@ void nd_flow(const NDFlowDev& d, const NDFrontDev* fr, const int* idx, const int
              const C* Wp, C* upd, const C* r, C* x, C* gbuf, int conj, hipStream_t s);
 template <typename C>
 void nd_bwd(const NDLaunchDev& L, const NDFrontDev* fr, const int* idx, const int* cidx, const C* Wp, C* upd, C* x,
-            C* gvec, int cap, int conj, C* gbuf, C* P, hipStream_t s);
+            C* gvec, int cap, int conj, C* gbuf, C* P, const NDRhs& rh, hipStream_t s);
 void grad_accumulate(const FineOp& op, double omega, const cd* u, const cd* lam, double* g, int first,
                      hipStream_t s);
 
@@ -110,6 +111,7 @@ struct NDDev {        // device-side ND tables (pointers into the workspace)
   int gvec_cap = 0;
   NDFlowDev flow;                       // dataflow substitution (one launch per solve)
   void* fgbuf = nullptr;                // its gather buffer
+  long long gbuf_n = 1, part_n = 1, gvec_n = 0;   // entries per right-hand side of gbuf, part, gvec
 };
 
 // kernel classes timed with HIP events when timing is on
@@ -155,10 +157,16 @@ struct helm_ctx {
   cd *V = nullptr, *part = nullptr;
   void* Z = nullptr;
   KrylovState* st = nullptr;
+  // right-hand sides solved in lock-step: capacity (buffers are carved for it) and the
+  // count of the current solve; with a capacity above 1, contiguous copies of the
+  // right-hand sides and solutions
+  int rcap = 1, nr = 1;
+  cd *Bm = nullptr, *Xm = nullptr;
   KrylovArgs ka;
   size_t ws_needed = 0;
-  char* hstate = nullptr;    // pinned host copy of the scalar block of KrylovState (slot 0),
+  char* hstate = nullptr;    // pinned host copy of the scalar blocks of the states (slot 0),
                              // slots 1, 2: read-backs of alternate queued iterations
+  char* hstate_dev = nullptr;   // its device mapping
   hipEvent_t itev[2] = {nullptr, nullptr};   // completion of the queued iterations
   int timing = 0;
   double times[5] = {0, 0, 0, 0, 0};
@@ -176,6 +184,7 @@ struct helm_ctx {
   hipStream_t cap = nullptr;    // library-owned stream used only for capture
   std::vector<hipGraphExec_t> gexec[2];
   double gtol[2] = {-1.0, -1.0};
+  int gnr[2] = {0, 0};          // right-hand side count the graphs were captured for
   int graphs = 1;
 };
 
@@ -358,13 +367,14 @@ size_t carve(helm_ctx* c, void* ws) {
   c->coef2_32 = c->f32 ? cv.take<cf>((size_t)K * g2.tot) : nullptr;
   c->tmp2 = cv.take<cd>((size_t)K * g2.tot);
   c->coef3_64 = cv.take<cd>((size_t)K * g3.tot);
-  c->x1a = cv.take<char>(cs * g1.tot);
-  c->x1b = cv.take<char>(cs * g1.tot);
-  c->b2 = cv.take<char>(cs * g2.tot);
-  c->x2a = cv.take<char>(cs * g2.tot);
-  c->x2b = cv.take<char>(cs * g2.tot);
-  c->b3 = cv.take<char>(cs * g3.tot);
-  c->x3 = cv.take<char>(cs * g3.tot);
+  const size_t rc = (size_t)c->rcap;
+  c->x1a = cv.take<char>(rc * cs * g1.tot);
+  c->x1b = cv.take<char>(rc * cs * g1.tot);
+  c->b2 = cv.take<char>(rc * cs * g2.tot);
+  c->x2a = cv.take<char>(rc * cs * g2.tot);
+  c->x2b = cv.take<char>(rc * cs * g2.tot);
+  c->b3 = cv.take<char>(rc * cs * g3.tot);
+  c->x3 = cv.take<char>(rc * cs * g3.tot);
   c->r3d = cv.take<cd>(g3.tot);
   c->e3d = cv.take<cd>(g3.tot);
   // ND tables
@@ -397,7 +407,7 @@ size_t carve(helm_ctx* c, void* ws) {
   d.T = cv.take<cd>(std::max<long long>(1, P.T_scratch));
   d.L = cv.take<char>(cs * P.L_total);
   d.W = cv.take<char>(cs * std::max<long long>(1, P.W_total));
-  d.upd = cv.take<char>(cs * std::max<long long>(1, P.upd_total));
+  d.upd = cv.take<char>(rc * cs * std::max<long long>(1, P.upd_total));
   long long gbuf_max = 1, part_max = 1;      // split-K buffers (entries)
   for (int fb = 0; fb < 2; ++fb) {
     std::vector<NDLaunch>& Ls = fb == 0 ? P.fwd : P.bwd;
@@ -447,9 +457,12 @@ size_t carve(helm_ctx* c, void* ws) {
       }
     }
   d.gvec_cap = (int)gcap;
-  d.gvec = gcap ? cv.take<char>(cs * gcap * gneed) : nullptr;
-  d.gbuf = cv.take<char>(cs * gbuf_max);
-  d.part = cv.take<char>(cs * part_max);
+  d.gvec_n = gcap * gneed;
+  d.gvec = gcap ? cv.take<char>(rc * cs * gcap * gneed) : nullptr;
+  d.gbuf_n = gbuf_max;
+  d.part_n = part_max;
+  d.gbuf = cv.take<char>(rc * cs * gbuf_max);
+  d.part = cv.take<char>(rc * cs * part_max);
   if (c->use_flow) {
     const NDFlow& F = c->flow;
     d.flow.tasks = cv.take<NDFlowTask>(std::max<size_t>(1, F.tasks.size()));
@@ -463,11 +476,13 @@ size_t carve(helm_ctx* c, void* ws) {
     d.fgbuf = cv.take<char>(cs * F.gbuf);
   }
   // Krylov
-  c->V = cv.take<cd>((size_t)(m + 1) * g1.tot);
-  c->Z = cv.take<char>(cs * (size_t)m * g1.tot);
+  c->V = cv.take<cd>(rc * (m + 1) * g1.tot);
+  c->Z = cv.take<char>(rc * cs * (size_t)m * g1.tot);
   long long nblk = (g1.tot + 256 * KNPT - 1) / (256 * KNPT);
-  c->part = cv.take<cd>((size_t)(2 * KMAXM + 3) * nblk);
-  c->st = cv.take<KrylovState>(1);
+  c->part = cv.take<cd>(rc * (2 * KMAXM + 3) * nblk);
+  c->st = cv.take<KrylovState>(rc);
+  c->Bm = rc > 1 ? cv.take<cd>(rc * g1.tot) : nullptr;
+  c->Xm = rc > 1 ? cv.take<cd>(rc * g1.tot) : nullptr;
   return cv.off;
 }
 
@@ -556,12 +571,19 @@ void ev_flush(helm_ctx* c) {
 template <typename C>
 void nd_solve(helm_ctx* c, const C* r, C* x, int conj, hipStream_t s) {
   NDDev& d = c->nd;
-  if (c->use_flow) {      // tree-block launches, the dataflow launch, tree-block launches
+  NDRhs rh;
+  rh.n = c->nr;
+  rh.vec = c->g3.tot;
+  rh.upd = std::max<long long>(1, c->plan.upd_total);
+  rh.gbuf = d.gbuf_n;
+  rh.part = d.part_n;
+  rh.gvec = d.gvec_n;
+  if (c->use_flow && c->nr == 1) {      // tree-block launches, the dataflow launch, tree-block launches
     for (const NDLaunchDev& L : d.launch[0])
       if (L.kind == 2)
         TIMED(c, KT_ND_FWD, s,
               nd_fwd<C>(L, d.fronts, d.idx, d.cptr, d.cidx, (const C*)d.L, (C*)d.upd, r, x, nullptr, 0, conj,
-                        (C*)d.gbuf, (C*)d.part, s));
+                        (C*)d.gbuf, (C*)d.part, rh, s));
     TIMED(c, KT_ND_FWD, s,
           nd_flow<C>(d.flow, d.fronts, d.idx, d.cptr, d.cidx, (const C*)d.L, (const C*)d.W, (C*)d.upd, r, x,
                      (C*)d.fgbuf, conj, s));
@@ -569,20 +591,20 @@ void nd_solve(helm_ctx* c, const C* r, C* x, int conj, hipStream_t s) {
       if (L.kind == 2)
         TIMED(c, KT_ND_BWD, s,
               nd_bwd<C>(L, d.fronts, d.idx, d.cidx, (const C*)d.W, (C*)d.upd, x, nullptr, 0, conj, (C*)d.gbuf,
-                        (C*)d.part, s));
+                        (C*)d.part, rh, s));
     return;
   }
   for (const NDLaunchDev& L : d.launch[0]) {
     C* gv = L.kind == 1 && L.shm == 0 ? (C*)d.gvec : nullptr;
     TIMED(c, KT_ND_FWD, s,
           nd_fwd<C>(L, d.fronts, d.idx, d.cptr, d.cidx, (const C*)d.L, (C*)d.upd, r, x, gv, d.gvec_cap, conj,
-                    (C*)d.gbuf, (C*)d.part, s));
+                    (C*)d.gbuf, (C*)d.part, rh, s));
   }
   for (const NDLaunchDev& L : d.launch[1]) {
     C* gv = L.kind == 1 && L.shm == 0 ? (C*)d.gvec : nullptr;
     TIMED(c, KT_ND_BWD, s,
           nd_bwd<C>(L, d.fronts, d.idx, d.cidx, (const C*)d.W, (C*)d.upd, x, gv, d.gvec_cap, conj, (C*)d.gbuf,
-                    (C*)d.part, s));
+                    (C*)d.part, rh, s));
   }
 }
 
@@ -635,12 +657,12 @@ struct Cycle {
   template <typename CO>
   St<C> adv1(St<C> st, const cd* b, const C* e, CO* out) {
     R w = (R)c->mg.jacobi[0];
-    TIMED(c, KT_L1_SWEEP, s, (l1_sweep<R, cd, CO>(A1, st.xin, st.x, b, w, c->g2, e, w, out, s)));
+    TIMED(c, KT_L1_SWEEP, s, (l1_sweep<R, cd, CO>(A1, st.xin, st.x, b, w, c->g2, e, w, out, c->nr, s)));
     return St<C>{XIN_X, (C*)out};
   }
   St<C> adv2(St<C> st, const C* b, const C* e, C* out) {
     R w = (R)c->mg.jacobi[1];
-    TIMED(c, KT_L2_SWEEP, s, (l2_sweep<R>(A2, st.xin, st.x, b, w, c->g3, e, w, out, s)));
+    TIMED(c, KT_L2_SWEEP, s, (l2_sweep<R>(A2, st.xin, st.x, b, w, c->g3, e, w, out, c->nr, s)));
     return St<C>{XIN_X, out};
   }
   C* other(C* cur, C* a, C* b) { return cur == a ? b : a; }
@@ -657,7 +679,8 @@ struct Cycle {
       if (s1.xin == 0) s1 = St<C>{XIN_Z, nullptr};
       else s1 = adv1<C>(s1, b1, nullptr, other(s1.x, x1a, x1b));
     }
-    TIMED(c, KT_L1_RESTRICT, s, (l1_restrict<R, cd>(A1, s1.xin, s1.x, b1, w1, c->g2, nullptr, c->g2, b2, s)));
+    TIMED(c, KT_L1_RESTRICT, s,
+          (l1_restrict<R, cd>(A1, s1.xin, s1.x, b1, w1, c->g2, nullptr, c->g2, b2, c->nr, s)));
     // ---- level 2 visits
     St<C> s2{0, nullptr};
     for (int v = 0; v < mg.cycle; ++v) {
@@ -665,13 +688,14 @@ struct Cycle {
         if (s2.xin == 0) s2 = St<C>{XIN_Z, nullptr};
         else s2 = adv2(s2, b2, nullptr, other(s2.x, x2a, x2b));
       }
-      TIMED(c, KT_L2_RESTRICT, s, (l2_restrict<R>(A2, s2.xin, s2.x, b2, w2, c->g3, nullptr, c->g3, b3, s)));
+      TIMED(c, KT_L2_RESTRICT, s,
+            (l2_restrict<R>(A2, s2.xin, s2.x, b2, w2, c->g3, nullptr, c->g3, b3, c->nr, s)));
       nd_solve<C>(c, b3, x3, conj, s);
       s2.xin |= XIN_E;
       for (int k = 0; k < mg.nu_post; ++k) s2 = adv2(s2, b2, x3, other(s2.x, x2a, x2b));
       if (s2.xin != XIN_X) {   // materialise (no post-relaxation)
         R w0 = 0;
-        l2_sweep<R>(A2, s2.xin, s2.x, b2, w2, c->g3, x3, w0, other(s2.x, x2a, x2b), s);
+        l2_sweep<R>(A2, s2.xin, s2.x, b2, w2, c->g3, x3, w0, other(s2.x, x2a, x2b), c->nr, s);
         s2 = St<C>{XIN_X, other(s2.x, x2a, x2b)};
       }
     }
@@ -679,7 +703,7 @@ struct Cycle {
     s1.xin |= XIN_E;
     const C* e2 = s2.x;
     if (mg.nu_post == 0) {
-      l1_sweep<R, cd, CO>(A1, s1.xin, s1.x, b1, w1, c->g2, e2, (R)0, out, s);
+      l1_sweep<R, cd, CO>(A1, s1.xin, s1.x, b1, w1, c->g2, e2, (R)0, out, c->nr, s);
       return;
     }
     for (int k = 0; k < mg.nu_post; ++k) {
@@ -691,18 +715,28 @@ struct Cycle {
   }
 };
 
-constexpr size_t HSLOT = 1024;   // bytes between the slots of hstate
-static_assert(offsetof(KrylovState, hist) - offsetof(KrylovState, bnorm) <= HSLOT, "state slot too small");
-void read_state(helm_ctx* c, hipStream_t s) {
-  CK(hipMemcpyAsync(c->hstate, (char*)c->st + offsetof(KrylovState, bnorm),
-                    offsetof(KrylovState, hist) - offsetof(KrylovState, bnorm), hipMemcpyDeviceToHost, s));
-  CK(hipStreamSynchronize(s));
-}
+// the scalar block of KrylovState, as read back by the host
 struct HostScalars {
   double bnorm, beta0, est, hnext, true_rel;
-  int its, done, nonfinite, pad;
+  int its, done, final, nonfinite, kcols, maxit;
 };
-inline HostScalars* hs(helm_ctx* c) { return (HostScalars*)c->hstate; }
+static_assert(sizeof(HostScalars) == offsetof(KrylovState, hist) - offsetof(KrylovState, bnorm),
+              "HostScalars must mirror the scalar block of KrylovState");
+constexpr size_t HSLOT = 1024;   // bytes between the slots of hstate (16 right-hand sides)
+constexpr int RMAX = (int)(HSLOT / sizeof(HostScalars));
+inline HostScalars* hs(helm_ctx* c, int slot = 0) { return (HostScalars*)(c->hstate + HSLOT * slot); }
+// the scalar blocks of the nr states into slot `slot` of hstate (asynchronous: one small
+// kernel writes them into the pinned buffer through its device mapping)
+void read_states_async(helm_ctx* c, int slot, hipStream_t s) {
+  KrylovArgs a;
+  a.st = c->st;
+  a.nrhs = c->nr;
+  kr_pack_states(a, c->hstate_dev + HSLOT * slot, s);
+}
+void read_states(helm_ctx* c, hipStream_t s) {
+  read_states_async(c, 0, s);
+  CK(hipStreamSynchronize(s));
+}
 
 KrylovArgs make_kargs(helm_ctx* c, int op) {
   KrylovArgs a;
@@ -711,11 +745,13 @@ KrylovArgs make_kargs(helm_ctx* c, int op) {
   a.conj = op;
   a.m64 = c->m64;
   a.V = c->V;
-  a.ldv = c->g1.tot;
+  a.ldv = (long long)c->nr * c->g1.tot;
   a.part = c->part;
   a.nblk = (int)((c->g1.tot + 256 * KNPT - 1) / (256 * KNPT));
   a.pcap = a.nblk;
   a.st = c->st;
+  a.nrhs = c->nr;
+  a.pstride = (long long)(2 * KMAXM + 3) * a.pcap;
   return a;
 }
 
@@ -727,26 +763,27 @@ void drop_graphs(helm_ctx* c) {
   }
 }
 
-// capture the m per-iteration graphs of operator op (kernel arguments are fixed: buffers,
-// shifts, tolerance), once per context until the frequency or shifts change
+// capture the m per-iteration graphs of operator op for the current right-hand side count
+// (kernel arguments are fixed: buffers, shifts, tolerance), once per context until the
+// frequency, the shifts or the count change
 template <typename R>
 void iter_graphs(helm_ctx* c, int op, double tol) {
   typedef typename cplx<R>::type C;
   const int m = c->mg.restart;
-  if ((int)c->gexec[op].size() == m && c->gtol[op] == tol) return;
+  if ((int)c->gexec[op].size() == m && c->gtol[op] == tol && c->gnr[op] == c->nr) return;
   for (hipGraphExec_t g : c->gexec[op]) (void)hipGraphExecDestroy(g);
   c->gexec[op].clear();
   if (!c->cap) CK(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));
   KrylovArgs a = make_kargs(c, op);
   Cycle<R> cyc(c, op, c->cap);
-  const long long N = c->g1.tot;
+  const size_t NJ = (size_t)c->nr * c->g1.tot;    // entries between basis vectors
   const int saved = c->timing;
   c->timing = 0;
   for (int j = 0; j < m; ++j) {
     hipGraph_t g = nullptr;
     CK(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
-    cyc.template run<C>(c->V + (size_t)j * N, (C*)c->Z + (size_t)j * N);
-    kr_arnoldi(a, (const char*)c->Z + (size_t)j * N * c->csz, c->f32, j, tol, c->cap);
+    cyc.template run<C>(c->V + j * NJ, (C*)c->Z + j * NJ);
+    kr_arnoldi(a, (const char*)c->Z + j * NJ * c->csz, c->f32, j, tol, c->cap);
     CK(hipStreamEndCapture(c->cap, &g));
     hipGraphExec_t e = nullptr;
     CK(hipGraphInstantiate(&e, g, nullptr, nullptr, 0));
@@ -755,16 +792,22 @@ void iter_graphs(helm_ctx* c, int op, double tol) {
   }
   c->timing = saved;
   c->gtol[op] = tol;
+  c->gnr[op] = c->nr;
 }
 
+// FGMRES(m) on nr right-hand sides in lock-step: b, x hold right-hand side r at r N1.
+// Each has its own Krylov state; one that has converged (or stopped) keeps its state
+// done, and its Krylov kernels do nothing.  info: nr entries (or NULL).
 template <typename R>
-int solve_impl(helm_ctx* c, int op, const cd* b, cd* x, double tol, int max_iter, helm_solve_info* info,
+int solve_impl(helm_ctx* c, int op, int nr, const cd* b, cd* x, double tol, int max_iter, helm_solve_info* info,
                hipStream_t s) {
+  c->nr = nr;
   KrylovArgs a = make_kargs(c, op);
   Cycle<R> cyc(c, op, s);
   typedef typename cplx<R>::type C;
   const int m = c->mg.restart;
   const long long N = c->g1.tot;
+  const size_t NJ = (size_t)nr * N;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (c->timing) {
     CK(hipEventCreate(&e0));
@@ -773,73 +816,112 @@ int solve_impl(helm_ctx* c, int op, const cd* b, cd* x, double tol, int max_iter
   }
   const bool use_graphs = c->graphs && !c->timing;
   if (use_graphs) iter_graphs<R>(c, op, tol);
-  kr_init(a, s);
+  kr_init(a, max_iter, s);
   kr_residual(a, x, b, 1, s);
-  read_state(c, s);
-  int status = HELM_OK, its = 0, restarts = 0;
-  double est = 0.0, true_rel = 0.0;
-  HostScalars* h = hs(c);
-  if (!std::isfinite(h->bnorm) || !std::isfinite(h->beta0)) {
-    status = HELM_ENONFINITE;
-  } else if (h->bnorm == 0.0) {
-    kr_zero(x, N, s);
-    CK(hipStreamSynchronize(s));
-  } else {
-    true_rel = h->beta0 / h->bnorm;
-    est = true_rel;
-    double prev_rel = true_rel;
-    while (true_rel > tol) {
-      if (its >= max_iter) { status = HELM_ENOCONV; break; }
-      kr_scale_v0(a, s);
-      int k = 0;
-      if (use_graphs) {
-        // iteration q + 1 is queued before the state of iteration q is read back, so the
-        // device does not wait for the host between iterations.  An iteration queued after
-        // the one that converged finds the done flag set: its Krylov kernels return at once
-        // and leave the basis, the Hessenberg column and the counters as they are.
-        const size_t sb = offsetof(KrylovState, hist) - offsetof(KrylovState, bnorm);
-        auto queue = [&](int j) {
-          CK(hipGraphLaunch(c->gexec[op][j], s));
-          CK(hipMemcpyAsync(c->hstate + HSLOT * (1 + (j & 1)), (char*)c->st + offsetof(KrylovState, bnorm), sb,
-                            hipMemcpyDeviceToHost, s));
-          CK(hipEventRecord(c->itev[j & 1], s));
-        };
-        for (hipEvent_t& e : c->itev)
-          if (!e) CK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-        int q = 0;                   // iterations of this cycle queued
-        queue(q++);
-        while (k < q) {
-          if (q < m && its + (q - k) < max_iter) queue(q++);
-          CK(hipEventSynchronize(c->itev[k & 1]));
-          std::memcpy(c->hstate, c->hstate + HSLOT * (1 + (k & 1)), sb);
-          ++its;
-          ++k;
-          est = h->est;
-          if (h->nonfinite || h->done || its >= max_iter) break;
-        }
-      } else {
-        for (int j = 0; j < m; ++j) {
-          cyc.template run<C>(c->V + (size_t)j * N, (C*)c->Z + (size_t)j * N);
-          TIMED(c, KT_APPLY_DOT, s, kr_arnoldi(a, (const char*)c->Z + (size_t)j * N * c->csz, c->f32, j, tol, s));
-          ++its;
-          k = j + 1;
-          read_state(c, s);
-          est = h->est;
-          if (h->nonfinite || h->done || its >= max_iter) break;
+  read_states(c, s);
+  std::vector<int> status(nr, HELM_OK), its(nr, 0), restarts(nr, 0), kc(nr, 0);
+  std::vector<double> est(nr, 0.0), true_rel(nr, 0.0), prev_rel(nr, 0.0);
+  std::vector<char> fin(nr, 0);
+  unsigned newly = 0;
+  for (int r = 0; r < nr; ++r) {
+    const HostScalars& h = hs(c)[r];
+    if (!std::isfinite(h.bnorm) || !std::isfinite(h.beta0)) {
+      status[r] = HELM_ENONFINITE;
+      fin[r] = 1;
+    } else if (h.bnorm == 0.0) {
+      kr_zero(x + r * N, N, s);
+      fin[r] = 1;
+    } else {
+      true_rel[r] = est[r] = prev_rel[r] = h.beta0 / h.bnorm;
+      if (true_rel[r] <= tol) fin[r] = 1;
+    }
+    if (fin[r]) newly |= 1u << r;
+  }
+  if (newly) kr_finalize(a, newly, s);
+  auto active = [&]() {
+    for (int r = 0; r < nr; ++r)
+      if (!fin[r]) return true;
+    return false;
+  };
+  // every unfinished right-hand side's column is done (converged, stopped or non-finite)
+  auto all_done = [&](const HostScalars* h) {
+    for (int r = 0; r < nr; ++r)
+      if (!fin[r] && !h[r].done && !h[r].nonfinite) return false;
+    return true;
+  };
+  while (active()) {
+    kr_scale_v0(a, s);
+    if (use_graphs) {
+      // iteration q + 1 is queued before the states of iteration q are read back, so the
+      // device does not wait for the host between iterations.  An iteration queued after
+      // a right-hand side's last one finds its done flag set: its Krylov kernels return at
+      // once and leave its basis, Hessenberg column and counters as they are.
+      auto queue = [&](int j) {
+        CK(hipGraphLaunch(c->gexec[op][j], s));
+        read_states_async(c, 1 + (j & 1), s);
+        CK(hipEventRecord(c->itev[j & 1], s));
+      };
+      for (hipEvent_t& e : c->itev)
+        if (!e) CK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      int q = 0, k = 0;          // iterations of this cycle queued, read
+      queue(q++);
+      while (k < q) {
+        if (q < m) queue(q++);
+        CK(hipEventSynchronize(c->itev[k & 1]));
+        std::memcpy(hs(c), hs(c, 1 + (k & 1)), sizeof(HostScalars) * nr);
+        ++k;
+        if (all_done(hs(c))) break;
+      }
+    } else {
+      for (int j = 0; j < m; ++j) {
+        cyc.template run<C>(c->V + j * NJ, (C*)c->Z + j * NJ);
+        TIMED(c, KT_APPLY_DOT, s, kr_arnoldi(a, (const char*)c->Z + j * NJ * c->csz, c->f32, j, tol, s));
+        read_states(c, s);
+        if (all_done(hs(c))) break;
+      }
+    }
+    for (int r = 0; r < nr; ++r)
+      if (!fin[r]) {
+        const HostScalars& h = hs(c)[r];
+        its[r] = h.its;
+        est[r] = h.est;
+        kc[r] = h.kcols;
+        if (h.nonfinite) {
+          status[r] = HELM_ENONFINITE;
+          fin[r] = 2;           // finished with no update of x
         }
       }
-      if (h->nonfinite) { status = HELM_ENONFINITE; break; }
-      kr_update_x(a, c->Z, c->f32, N, k, x, s);
-      kr_residual(a, x, b, 0, s);
-      read_state(c, s);
-      true_rel = h->beta0 / h->bnorm;
-      if (!std::isfinite(true_rel)) { status = HELM_ENONFINITE; break; }
-      if (true_rel <= tol) break;
-      if (its >= max_iter) { status = HELM_ENOCONV; break; }
-      if (k == m && true_rel >= prev_rel * (1.0 - 1e-12)) { status = HELM_ESTAGNATE; break; }
-      prev_rel = true_rel;
-      ++restarts;
+    kr_update_x(a, c->Z, c->f32, (long long)NJ, x, s);
+    kr_residual(a, x, b, 0, s);
+    read_states(c, s);
+    newly = 0;
+    for (int r = 0; r < nr; ++r) {
+      if (fin[r] == 2) {
+        fin[r] = 1;
+        newly |= 1u << r;
+        continue;
+      }
+      if (fin[r]) continue;
+      const HostScalars& h = hs(c)[r];
+      true_rel[r] = h.beta0 / h.bnorm;
+      if (!std::isfinite(true_rel[r])) {
+        status[r] = HELM_ENONFINITE;
+        fin[r] = 1;
+      } else if (true_rel[r] <= tol) {
+        fin[r] = 1;
+      } else if (its[r] >= max_iter) {
+        status[r] = HELM_ENOCONV;
+        fin[r] = 1;
+      } else if (kc[r] == m && true_rel[r] >= prev_rel[r] * (1.0 - 1e-12)) {
+        status[r] = HELM_ESTAGNATE;
+        fin[r] = 1;
+      } else {
+        prev_rel[r] = true_rel[r];
+        ++restarts[r];
+      }
+      if (fin[r]) newly |= 1u << r;
     }
+    if (newly) kr_finalize(a, newly, s);
   }
   if (c->timing) {
     CK(hipEventRecord(e1, s));
@@ -852,19 +934,25 @@ int solve_impl(helm_ctx* c, int op, const cd* b, cd* x, double tol, int max_iter
   }
   CK(hipStreamSynchronize(s));
   ev_flush(c);
-  if (info) {
-    info->iterations = its;
-    info->restarts = restarts;
-    info->status = status;
-    info->est_rel_residual = est;
-    info->true_rel_residual = true_rel;
-    if (info->history && info->history_cap > 0 && its > 0) {
-      int n = std::min(std::min(its, info->history_cap), KMAXIT);
-      CK(hipMemcpy(info->history, (char*)c->st + offsetof(KrylovState, hist), n * sizeof(double),
-                   hipMemcpyDeviceToHost));
+  int worst = HELM_OK;
+  for (int r = 0; r < nr; ++r) {
+    if (info) {
+      helm_solve_info& I = info[r];
+      I.iterations = its[r];
+      I.restarts = restarts[r];
+      I.status = status[r];
+      I.est_rel_residual = est[r];
+      I.true_rel_residual = true_rel[r];
+      if (I.history && I.history_cap > 0 && its[r] > 0) {
+        int n = std::min(std::min(its[r], I.history_cap), KMAXIT);
+        CK(hipMemcpy(I.history, (char*)(c->st + r) + offsetof(KrylovState, hist), n * sizeof(double),
+                     hipMemcpyDeviceToHost));
+      }
     }
+    if (status[r] < 0 && worst >= 0) worst = status[r];
+    else if (worst >= 0) worst = std::max(worst, status[r]);
   }
-  return status;
+  return worst;
 }
 
 }  // namespace
@@ -888,7 +976,8 @@ const char* helm_status_str(int st) {
 
 const char* helm_last_error(void) { return g_err; }
 
-int helm_workspace_bytes(const helm_grid* grid, const helm_mg* mg, size_t* bytes) {
+// rcap: right-hand sides a context solves in lock-step (its buffers are carved for them)
+static int ws_bytes_rcap(const helm_grid* grid, const helm_mg* mg, int rcap, size_t* bytes) {
   int v = validate(grid, mg);
   if (v) return v;
   if (!bytes) return fail(HELM_EINVAL, "bytes is NULL");
@@ -896,6 +985,7 @@ int helm_workspace_bytes(const helm_grid* grid, const helm_mg* mg, size_t* bytes
     helm_ctx c;
     c.grid = *grid;
     c.mg = *mg;
+    c.rcap = rcap;
     init_geometry(&c);
     build_plan(&c);
     *bytes = carve(&c, nullptr);
@@ -905,8 +995,12 @@ int helm_workspace_bytes(const helm_grid* grid, const helm_mg* mg, size_t* bytes
   }
 }
 
-int helm_setup(const helm_grid* grid, const double* slowness, double omega, const helm_shift* shift,
-               const helm_mg* mg, void* ws, size_t ws_bytes, void* stream, helm_ctx** out) {
+int helm_workspace_bytes(const helm_grid* grid, const helm_mg* mg, size_t* bytes) {
+  return ws_bytes_rcap(grid, mg, 1, bytes);
+}
+
+static int setup_rcap(const helm_grid* grid, const double* slowness, double omega, const helm_shift* shift,
+                      const helm_mg* mg, int rcap, void* ws, size_t ws_bytes, void* stream, helm_ctx** out) {
   int v = validate(grid, mg);
   if (v) return v;
   if (!slowness || !shift || !out) return fail(HELM_EINVAL, "NULL slowness/shift/out");
@@ -922,6 +1016,7 @@ int helm_setup(const helm_grid* grid, const double* slowness, double omega, cons
     c->mg = *mg;
     c->shift = *shift;
     c->omega = omega;
+    c->rcap = rcap;
     c->graphs = env_int("HELM_GRAPHS", 1);
     init_geometry(c.get());
     build_plan(c.get());
@@ -929,7 +1024,8 @@ int helm_setup(const helm_grid* grid, const double* slowness, double omega, cons
     if (ws_bytes < need) return fail(HELM_EWORKSPACE, "workspace too small: %zu < %zu", ws_bytes, need);
     c->ws_needed = need;
     carve(c.get(), ws);
-    CK(hipHostMalloc((void**)&c->hstate, 4096, hipHostMallocDefault));
+    CK(hipHostMalloc((void**)&c->hstate, 4096, hipHostMallocMapped | hipHostMallocCoherent));
+    CK(hipHostGetDevicePointer((void**)&c->hstate_dev, c->hstate, 0));
     {
       int dev = 0, lds = 0;
       CK(hipGetDevice(&dev));
@@ -1009,6 +1105,11 @@ int helm_setup(const helm_grid* grid, const double* slowness, double omega, cons
   return HELM_OK;
 }
 
+int helm_setup(const helm_grid* grid, const double* slowness, double omega, const helm_shift* shift,
+               const helm_mg* mg, void* ws, size_t ws_bytes, void* stream, helm_ctx** out) {
+  return setup_rcap(grid, slowness, omega, shift, mg, 1, ws, ws_bytes, stream, out);
+}
+
 int helm_refactor(helm_ctx* c, const double* slowness, double omega, const helm_shift* shift, void* stream) {
   if (!c || !slowness || !shift) return fail(HELM_EINVAL, "NULL argument");
   if (!c->sub.empty()) return fail(HELM_EINVAL, "helm_refactor takes a single-instance context");
@@ -1082,6 +1183,7 @@ int helm_vcycle(helm_ctx* c, int op, const void* r, void* z, void* stream) {
   if (op != HELM_OP_N && op != HELM_OP_C) return fail(HELM_EINVAL, "op must be HELM_OP_N or HELM_OP_C");
   if (r == z) return fail(HELM_EINVAL, "r and z must differ");
   hipStream_t s = (hipStream_t)stream;
+  c->nr = 1;
   try {
     if (c->f32) {
       Cycle<float> cyc(c, op, s);
@@ -1102,6 +1204,7 @@ int helm_coarse_solve(helm_ctx* c, int op, const void* r, void* e, void* stream)
   if (op != HELM_OP_N && op != HELM_OP_C) return fail(HELM_EINVAL, "op must be HELM_OP_N or HELM_OP_C");
   if (r == e) return fail(HELM_EINVAL, "r and e must differ");
   hipStream_t s = (hipStream_t)stream;
+  c->nr = 1;
   try {
     if (c->f32) {
       cast_d2f((const cd*)r, (cf*)c->b3, c->g3.tot, s);
@@ -1126,8 +1229,8 @@ int helm_solve(helm_ctx* c, int op, const void* rhs, void* x, double tol, int ma
   if (rhs == x) return fail(HELM_EINVAL, "rhs and x must differ");
   hipStream_t s = (hipStream_t)stream;
   try {
-    int st = c->f32 ? solve_impl<float>(c, op, (const cd*)rhs, (cd*)x, tol, max_iter, info, s)
-                    : solve_impl<double>(c, op, (const cd*)rhs, (cd*)x, tol, max_iter, info, s);
+    int st = c->f32 ? solve_impl<float>(c, op, 1, (const cd*)rhs, (cd*)x, tol, max_iter, info, s)
+                    : solve_impl<double>(c, op, 1, (const cd*)rhs, (cd*)x, tol, max_iter, info, s);
     CK(hipGetLastError());
     if (c->use_flow) {     // a dataflow wait that gave up leaves its flag (the stream is idle here)
       int* flag = c->nd.flow.ctr + c->nd.flow.nctr + 2;
@@ -1237,13 +1340,16 @@ int helm_grad_m(helm_ctx* c, int n_src, const void* const* u, const void* const*
 // their instance's hierarchy.
 extern "C" {
 
+// right-hand sides per instance solved in lock-step (at most RMAX)
+static int batch_rcap(int max_rhs) { return std::max(1, std::min(max_rhs, RMAX)); }
+
 int helm_workspace_bytes_batched(int n_inst, const helm_grid* grids, const helm_mg* mg, int max_rhs,
                                  size_t* bytes) {
   if (n_inst < 1 || !grids || !mg || !bytes || max_rhs < 1) return fail(HELM_EINVAL, "bad arguments");
   size_t tot = 0;
   for (int i = 0; i < n_inst; ++i) {
     size_t b = 0;
-    int v = helm_workspace_bytes(&grids[i], mg, &b);
+    int v = ws_bytes_rcap(&grids[i], mg, batch_rcap(max_rhs), &b);
     if (v) return v;
     tot += al(b);
   }
@@ -1262,15 +1368,16 @@ int helm_setup_batched(int n_inst, const helm_grid* grids, const double* const* 
   if (!ws || ((uintptr_t)ws % ALIGN) != 0 || ws_bytes < need)
     return fail(HELM_EWORKSPACE, "workspace NULL, misaligned or too small (%zu < %zu)", ws_bytes, need);
   *out = nullptr;
+  const int rcap = batch_rcap(max_rhs);
   std::unique_ptr<helm_ctx> b(new helm_ctx());
   b->grid = grids[0];
   b->mg = *mg;
   char* p = (char*)ws;
   for (int i = 0; i < n_inst; ++i) {
     size_t bi = 0;
-    helm_workspace_bytes(&grids[i], mg, &bi);
+    ws_bytes_rcap(&grids[i], mg, rcap, &bi);
     helm_ctx* c = nullptr;
-    int r = helm_setup(&grids[i], slowness[i], omega[i], &shift[i], mg, p, al(bi), stream, &c);
+    int r = setup_rcap(&grids[i], slowness[i], omega[i], &shift[i], mg, rcap, p, al(bi), stream, &c);
     if (r) {
       for (helm_ctx* q : b->sub) helm_destroy(q);
       return r;
@@ -1286,14 +1393,23 @@ int helm_solve_batched(helm_ctx* ctx, int op, int n_rhs, const int* inst_of_rhs,
                        void* const* x, double tol, int max_iter, helm_solve_info* info, void* stream) {
   if (!ctx || n_rhs < 1 || !inst_of_rhs || !rhs || !x) return fail(HELM_EINVAL, "bad arguments");
   if (op != HELM_OP_N && op != HELM_OP_C) return fail(HELM_EINVAL, "op must be HELM_OP_N or HELM_OP_C");
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(HELM_EINVAL, "tol must be positive");
+  if (max_iter < 1) return fail(HELM_EINVAL, "max_iter must be >= 1");
   const int ninst = ctx->sub.empty() ? 1 : (int)ctx->sub.size();
-  for (int k = 0; k < n_rhs; ++k)
-    if (inst_of_rhs[k] < 0 || inst_of_rhs[k] >= ninst || !rhs[k] || !x[k])
+  std::vector<std::vector<int>> by(ninst);      // right-hand sides of each instance, in order
+  for (int k = 0; k < n_rhs; ++k) {
+    if (inst_of_rhs[k] < 0 || inst_of_rhs[k] >= ninst || !rhs[k] || !x[k] || rhs[k] == x[k])
       return fail(HELM_EINVAL, "bad right-hand side %d", k);
+    by[inst_of_rhs[k]].push_back(k);
+  }
+  std::vector<int> busy;
+  for (int i = 0; i < ninst; ++i)
+    if (!by[i].empty()) busy.push_back(i);
   hipStream_t s = (hipStream_t)stream;
   // instances are independent: they run concurrently on library-owned streams (one host
-  // worker per stream); the right-hand sides of one instance run in order on its stream.
-  const int nst = std::max(1, std::min(env_int("HELM_BATCH_STREAMS", 8), ninst));
+  // worker per stream); an instance's right-hand sides are solved in lock-step groups of
+  // up to its capacity, one group after the other on its stream
+  const int nst = std::max(1, std::min(env_int("HELM_BATCH_STREAMS", 8), (int)busy.size()));
   std::vector<int> status(n_rhs, HELM_OK);
   std::vector<std::string> errs(nst);
   try {
@@ -1312,19 +1428,60 @@ int helm_solve_batched(helm_ctx* ctx, int op, int n_rhs, const int* inst_of_rhs,
     std::vector<std::thread> pool;
     for (int w = 0; w < nst; ++w)
       pool.emplace_back([&, w]() {
+        const hipStream_t sw = ctx->bstreams[w];
         if (hipSetDevice(dev) != hipSuccess) {
           errs[w] = "hipSetDevice failed in a batch worker";
-          for (int k = 0; k < n_rhs; ++k)
-            if (inst_of_rhs[k] % nst == w) status[k] = HELM_EDEVICE;
+          for (size_t q = w; q < busy.size(); q += nst)
+            for (int k : by[busy[q]]) status[k] = HELM_EDEVICE;
           return;
         }
-        for (int k = 0; k < n_rhs; ++k) {
-          if (inst_of_rhs[k] % nst != w) continue;
-          helm_ctx* c = ctx->sub.empty() ? ctx : ctx->sub[inst_of_rhs[k]];
-          status[k] = helm_solve(c, op, rhs[k], x[k], tol, max_iter, info ? &info[k] : nullptr, ctx->bstreams[w]);
-          if (status[k] < 0) {
-            errs[w] = helm_last_error();
-            return;
+        for (size_t q = w; q < busy.size(); q += nst) {
+          const int i = busy[q];
+          helm_ctx* c = ctx->sub.empty() ? ctx : ctx->sub[i];
+          const std::vector<int>& ks = by[i];
+          if (c->rcap == 1) {
+            for (int k : ks) {
+              status[k] = helm_solve(c, op, rhs[k], x[k], tol, max_iter, info ? &info[k] : nullptr, sw);
+              if (status[k] < 0) {
+                errs[w] = helm_last_error();
+                return;
+              }
+            }
+            continue;
+          }
+          const long long N = c->g1.tot;
+          const size_t vb = sizeof(cd) * (size_t)N;
+          for (size_t t0 = 0; t0 < ks.size(); t0 += c->rcap) {
+            const int nr = (int)std::min<size_t>(c->rcap, ks.size() - t0);
+            helm_solve_info tmp[RMAX];
+            try {
+              for (int t = 0; t < nr; ++t) {
+                const int k = ks[t0 + t];
+                tmp[t] = helm_solve_info{};
+                if (info) {
+                  tmp[t].history = info[k].history;
+                  tmp[t].history_cap = info[k].history_cap;
+                }
+                CK(hipMemcpyAsync(c->Bm + t * N, rhs[k], vb, hipMemcpyDeviceToDevice, sw));
+                CK(hipMemcpyAsync(c->Xm + t * N, x[k], vb, hipMemcpyDeviceToDevice, sw));
+              }
+              if (c->f32)
+                solve_impl<float>(c, op, nr, c->Bm, c->Xm, tol, max_iter, tmp, sw);
+              else
+                solve_impl<double>(c, op, nr, c->Bm, c->Xm, tol, max_iter, tmp, sw);
+              for (int t = 0; t < nr; ++t)
+                CK(hipMemcpyAsync(x[ks[t0 + t]], c->Xm + t * N, vb, hipMemcpyDeviceToDevice, sw));
+              CK(hipStreamSynchronize(sw));
+            } catch (DevErr& e) {
+              errs[w] = e.what();
+              for (int t = 0; t < nr; ++t) status[ks[t0 + t]] = HELM_EDEVICE;
+              return;
+            }
+            for (int t = 0; t < nr; ++t) {
+              const int k = ks[t0 + t];
+              status[k] = tmp[t].status;
+              if (info) info[k] = tmp[t];
+            }
           }
         }
       });

@@ -223,6 +223,18 @@ struct NDLaunch {       // one kernel launch of a substitution
   int threads = 256;
 };
 
+// several right-hand sides substituted by one launch (grid y): strides, in entries,
+// between the vectors of consecutive right-hand sides
+struct NDRhs {
+  int n = 1;             // right-hand sides
+  int pad = 0;
+  long long vec = 0;     // r and x (N3)
+  long long upd = 0;     // update pool
+  long long gbuf = 0;    // split-K gathered vectors
+  long long part = 0;    // split-K partial products
+  long long gvec = 0;    // row-chunk launches' global vectors
+};
+
 struct NDLaunchDev {    // device copy of an NDLaunch, as the kernels see it
   int kind = 1, ntasks = 0, threads = 256, lds_bytes = 0;
   size_t shm = 0;       // kind 1: dynamic LDS bytes for the gathered vector (0: global fall-back)

@@ -18,29 +18,44 @@ struct KrylovState {
   cd c[KMAXM + 1];               // Hessenberg column before rotation (h1 + h2)
   cd tmp[2];
   double bnorm, beta0, est, hnext, true_rel;
-  int its, done, nonfinite, pad;
+  int its, done;
+  int final;          // set by the host when this right-hand side is finished: every later
+                      // restart keeps it done
+  int nonfinite;
+  int kcols;          // Arnoldi columns completed in the current cycle
+  int maxit;          // iteration limit (the column that reaches it ends the solve)
   double hist[KMAXIT];
   cd G[(KMAXM + 1) * (KMAXM + 1)];   // Gram matrix of the stored basis, leading dimension KMAXM + 1
 };
 
+// nrhs right-hand sides are iterated in lock-step (grid y): right-hand side r has state
+// st[r], basis vector j at V + j ldv + r N (ldv = nrhs N) and its partial sums at
+// part + r pstride; the other vectors of right-hand side r follow those of r - 1 at N.
 struct KrylovArgs {
   FineOp op;
   cd s;           // omega^2 (the unshifted outer operator)
   int conj;
   const double* m64;
-  cd* V;          // basis, restart + 1 vectors
+  cd* V;          // basis, restart + 1 vectors per right-hand side
   long long ldv;
   cd* part;       // partial sums, value-major: part[i * pcap + block]
   int pcap;
   int nblk;            // blocks of the node kernels = ceil(N / (256 * KNPT))
   KrylovState* st;
+  int nrhs;
+  long long pstride;
 };
 
-void kr_init(const KrylovArgs& a, hipStream_t s);
+void kr_init(const KrylovArgs& a, int max_iter, hipStream_t s);
 void kr_residual(const KrylovArgs& a, const cd* x, const cd* b, int with_b, hipStream_t s);
 void kr_scale_v0(const KrylovArgs& a, hipStream_t s);
 void kr_arnoldi(const KrylovArgs& a, const void* z, int z_f32, int j, double tol, hipStream_t s);
-void kr_update_x(const KrylovArgs& a, const void* Z, int z_f32, long long ldz, int k, cd* x, hipStream_t s);
+// x += Z y over each right-hand side's columns of the current cycle (Z: ldz between columns)
+void kr_update_x(const KrylovArgs& a, const void* Z, int z_f32, long long ldz, cd* x, hipStream_t s);
 void kr_zero(cd* x, long long n, hipStream_t s);
+// copy the nrhs scalar blocks (bnorm .. hist) into host memory mapped for the device
+void kr_pack_states(const KrylovArgs& a, void* host_dst, hipStream_t s);
+// mark the right-hand sides of a bit mask finished (their kernels do nothing from now on)
+void kr_finalize(const KrylovArgs& a, unsigned mask, hipStream_t s);
 
 }  // namespace helm

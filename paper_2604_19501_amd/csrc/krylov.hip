@@ -41,6 +41,18 @@ __device__ __forceinline__ void block_sum(cd v, cd* lds, cd* out) {
   __syncthreads();
 }
 
+// the per-right-hand-side pointers of right-hand side blockIdx.y (kept apart from the
+// argument block, which must stay in kernel-argument memory)
+struct RhsPtr {
+  cd* V;
+  KrylovState* st;
+  cd* part;
+};
+__device__ __forceinline__ RhsPtr at_rhs(const KrylovArgs& a) {
+  const long long r = blockIdx.y;
+  return RhsPtr{a.V + r * a.op.g.tot, a.st + r, a.part + r * a.pstride};
+}
+
 __device__ __forceinline__ long long node_of(int q) {
   return ((long long)blockIdx.x * KNPT + q) * 256 + threadIdx.x;
 }
@@ -85,7 +97,9 @@ __device__ __forceinline__ void store_partials(cd (*red)[2 * KMAXM + 3], int nv,
 template <typename CZ>
 __global__ void __launch_bounds__(256) k_arnoldi_dots(KrylovArgs a, const CZ* __restrict__ z, int j) {
   __shared__ cd red[4][2 * KMAXM + 3];
-  if (a.st->done) return;          // an iteration queued after convergence: nothing to do
+  const RhsPtr p = at_rhs(a);
+  z += blockIdx.y * a.op.g.tot;
+  if (p.st->done) return;          // an iteration queued after convergence: nothing to do
   const long long N = a.op.g.tot;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   long long f[KNPT];
@@ -97,8 +111,8 @@ __global__ void __launch_bounds__(256) k_arnoldi_dots(KrylovArgs a, const CZ* __
   }
   cd w[KNPT], vj[KNPT], nx[KNPT];
   for (int q = 0; q < KNPT; ++q) {
-    vj[q] = on[q] * a.V[(long long)j * a.ldv + f[q]];
-    nx[q] = a.V[f[q]];
+    vj[q] = on[q] * p.V[(long long)j * a.ldv + f[q]];
+    nx[q] = p.V[f[q]];
   }
   double nw = 0.0;
   for (int q = 0; q < KNPT; ++q) {
@@ -109,7 +123,7 @@ __global__ void __launch_bounds__(256) k_arnoldi_dots(KrylovArgs a, const CZ* __
     cd vi[KNPT];
     for (int q = 0; q < KNPT; ++q) vi[q] = nx[q];
     const long long in = (long long)(i < j ? i + 1 : j) * a.ldv;   // the last pass reloads V_j
-    for (int q = 0; q < KNPT; ++q) nx[q] = a.V[in + f[q]];
+    for (int q = 0; q < KNPT; ++q) nx[q] = p.V[in + f[q]];
     cd s1 = mk(0.0, 0.0), s2 = mk(0.0, 0.0);
     for (int q = 0; q < KNPT; ++q) {
       s1 += cmulc(vi[q], w[q]);
@@ -124,32 +138,37 @@ __global__ void __launch_bounds__(256) k_arnoldi_dots(KrylovArgs a, const CZ* __
   }
   cd t = wsum(mk(nw, 0.0));
   if (lane == 0) red[wv][2 * j + 2] = t;
-  store_partials(red, 2 * j + 3, a.part, a.pcap);
+  store_partials(red, 2 * j + 3, p.part, a.pcap);
 }
 
 // r = b - H x (FP64) into V_0; partials of (||r||^2, ||b||^2) in slot 0
 __global__ void __launch_bounds__(256) k_residual(KrylovArgs a, const cd* __restrict__ x,
                                                   const cd* __restrict__ b) {
   __shared__ cd lds[4];
+  const RhsPtr p = at_rhs(a);
+  x += blockIdx.y * a.op.g.tot;
+  b += blockIdx.y * a.op.g.tot;
   const long long N = a.op.g.tot;
   cd v = mk(0.0, 0.0);
   for (int q = 0; q < KNPT; ++q) {
     long long f = node_of(q);
     if (f < N) {
       cd res = b[f] - apply_h(a, x, f);
-      a.V[f] = res;
+      p.V[f] = res;
       v += mk(abs2(res), abs2(b[f]));
     }
   }
-  block_sum(v, lds, a.part + blockIdx.x);
+  block_sum(v, lds, p.part + blockIdx.x);
 }
 
-// one block per value: dst[i] = sum over blocks of part[i]
-__global__ void __launch_bounds__(256) k_fin_sum(KrylovArgs a, cd* dst) {
+// one block per value: dst[i] = sum over blocks of part[i] (dst: the state member at off)
+__global__ void __launch_bounds__(256) k_fin_sum(KrylovArgs a, size_t off) {
   __shared__ cd lds[4];
+  const RhsPtr p = at_rhs(a);
+  cd* dst = (cd*)((char*)p.st + off);
   const int i = blockIdx.x;
   cd v = mk(0.0, 0.0);
-  for (int b = threadIdx.x; b < a.nblk; b += 256) v += a.part[(long long)i * a.pcap + b];
+  for (int b = threadIdx.x; b < a.nblk; b += 256) v += p.part[(long long)i * a.pcap + b];
   block_sum(v, lds, dst + i);
 }
 
@@ -174,10 +193,11 @@ __device__ inline void givens(cd a, cd b, double& c, cd& s, cd& r) {
 // sums of k_arnoldi_dots.  Lane i owns row i of the Gram products; the serial part
 // (rotations of the column) runs on lane 0 out of LDS.
 __global__ void __launch_bounds__(64) k_givens(KrylovArgs a, int j, double tol) {
+  const RhsPtr p = at_rhs(a);
   __shared__ cd sh1[KMAXM + 1], sg[KMAXM + 1], sc[KMAXM + 1], col[KMAXM + 2], ssn[KMAXM];
   __shared__ double scs[KMAXM], r1[64], r2[64];
   __shared__ cd sG[(KMAXM + 1) * (KMAXM + 1)];
-  KrylovState* st = a.st;
+  KrylovState* st = p.st;
   if (st->done) return;            // converged in an earlier column: the state stays as it is
   const int t = threadIdx.x, ld = KMAXM + 1;
   for (int i = t; i <= j; i += 64) {
@@ -251,9 +271,10 @@ __global__ void __launch_bounds__(64) k_givens(KrylovArgs a, int j, double tol) 
     st->est = est;
     if (st->its < KMAXIT) st->hist[st->its] = est;
     st->its += 1;
+    st->kcols = j + 1;
     bool fin = isfinite(est) && isfinite(hn);
     if (!fin) st->nonfinite = 1;
-    st->done = (est <= tol || !fin || hn == 0.0) ? 1 : 0;
+    st->done = (est <= tol || !fin || hn == 0.0 || st->its >= st->maxit) ? 1 : 0;
   }
   __syncthreads();
   for (int i = t; i <= j + 1; i += 64) st->H[i + ld * j] = col[i];
@@ -267,9 +288,11 @@ template <typename CZ>
 __global__ void __launch_bounds__(256) k_arnoldi_update(KrylovArgs a, const CZ* __restrict__ z, int j) {
   __shared__ cd sc[KMAXM + 1];
   __shared__ double sinv;
-  if (a.st->done) return;
-  if (threadIdx.x <= j) sc[threadIdx.x] = a.st->c[threadIdx.x];
-  if (threadIdx.x == 0) sinv = a.st->hnext > 0.0 ? 1.0 / a.st->hnext : 0.0;
+  const RhsPtr p = at_rhs(a);
+  z += blockIdx.y * a.op.g.tot;
+  if (p.st->done) return;
+  if (threadIdx.x <= j) sc[threadIdx.x] = p.st->c[threadIdx.x];
+  if (threadIdx.x == 0) sinv = p.st->hnext > 0.0 ? 1.0 / p.st->hnext : 0.0;
   const long long N = a.op.g.tot;
   const long long blk = (long long)gridDim.x - 1 - blockIdx.x;
   long long f[KNPT];
@@ -280,49 +303,55 @@ __global__ void __launch_bounds__(256) k_arnoldi_update(KrylovArgs a, const CZ* 
     f[q] = ok[q] ? t : N - 1;
   }
   cd w[KNPT], nx[KNPT];
-  for (int q = 0; q < KNPT; ++q) nx[q] = a.V[f[q]];
+  for (int q = 0; q < KNPT; ++q) nx[q] = p.V[f[q]];
   for (int q = 0; q < KNPT; ++q) w[q] = apply_h(a, z, f[q]);
   __syncthreads();
   for (int i = 0; i <= j; ++i) {
     cd vi[KNPT];
     for (int q = 0; q < KNPT; ++q) vi[q] = nx[q];
     const long long in = (long long)(i < j ? i + 1 : j) * a.ldv;   // the last pass reloads V_j
-    for (int q = 0; q < KNPT; ++q) nx[q] = a.V[in + f[q]];
+    for (int q = 0; q < KNPT; ++q) nx[q] = p.V[in + f[q]];
     const cd ci = sc[i];
     for (int q = 0; q < KNPT; ++q) w[q] -= ci * vi[q];
   }
   const double si = sinv;
   for (int q = 0; q < KNPT; ++q)
-    if (ok[q]) a.V[(long long)(j + 1) * a.ldv + f[q]] = si * w[q];
+    if (ok[q]) p.V[(long long)(j + 1) * a.ldv + f[q]] = si * w[q];
 }
 
 // restart bookkeeping from tmp = (||r||^2, ||b||^2): beta0, g = beta0 e1
 __global__ void k_fin_residual(KrylovArgs a, int set_b) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  KrylovState* st = a.st;
+  const RhsPtr p = at_rhs(a);
+  KrylovState* st = p.st;
   if (set_b) st->bnorm = sqrt(st->tmp[0].y);
   double b0 = sqrt(st->tmp[0].x);
   st->beta0 = b0;
   st->g[0] = mk(b0, 0.0);
   for (int i = 1; i <= KMAXM; ++i) st->g[i] = mk(0.0, 0.0);
   st->true_rel = st->bnorm > 0.0 ? b0 / st->bnorm : 0.0;
-  st->done = 0;
+  st->done = st->final;
+  st->kcols = 0;
   if (!isfinite(b0)) st->nonfinite = 1;
 }
 
 __global__ void __launch_bounds__(256) k_scale_v0(KrylovArgs a) {
-  double s = a.st->beta0 > 0.0 ? 1.0 / a.st->beta0 : 0.0;
+  const RhsPtr p = at_rhs(a);
+  double s = p.st->beta0 > 0.0 ? 1.0 / p.st->beta0 : 0.0;
   const long long N = a.op.g.tot;
   for (int q = 0; q < KNPT; ++q) {
     long long f = node_of(q);
-    if (f < N) a.V[f] = s * a.V[f];
+    if (f < N) p.V[f] = s * p.V[f];
   }
 }
 
-// y = R^{-1} g on the k x k upper triangle of the rotated Hessenberg matrix
-__global__ void k_solve_y(KrylovArgs a, int k) {
+// y = R^{-1} g on the k x k upper triangle of the rotated Hessenberg matrix (k: the
+// columns of the current cycle)
+__global__ void k_solve_y(KrylovArgs a) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  KrylovState* st = a.st;
+  const RhsPtr p = at_rhs(a);
+  KrylovState* st = p.st;
+  const int k = st->nonfinite ? 0 : st->kcols;     // a non-finite column leaves x as it is
   const int ld = KMAXM + 1;
   for (int i = k - 1; i >= 0; --i) {
     cd acc = st->g[i];
@@ -333,10 +362,14 @@ __global__ void k_solve_y(KrylovArgs a, int k) {
 
 // x += sum_i y_i Z_i
 template <typename CZ>
-__global__ void __launch_bounds__(256) k_update_x(KrylovArgs a, const CZ* __restrict__ Z, long long ldz, int k,
+__global__ void __launch_bounds__(256) k_update_x(KrylovArgs a, const CZ* __restrict__ Z, long long ldz,
                                                   cd* __restrict__ x) {
   __shared__ cd sy[KMAXM];
-  if (threadIdx.x < k) sy[threadIdx.x] = a.st->y[threadIdx.x];
+  const RhsPtr p = at_rhs(a);
+  Z += blockIdx.y * a.op.g.tot;
+  x += blockIdx.y * a.op.g.tot;
+  const int k = p.st->nonfinite ? 0 : p.st->kcols;
+  if (threadIdx.x < k) sy[threadIdx.x] = p.st->y[threadIdx.x];
   __syncthreads();
   const long long N = a.op.g.tot;
   for (int q = 0; q < KNPT; ++q) {
@@ -353,47 +386,75 @@ __global__ void k_zero_c128(cd* __restrict__ x, long long n) {
     x[i] = mk(0.0, 0.0);
 }
 
-__global__ void k_init_state(KrylovState* st) {
+__global__ void k_init_state(KrylovState* st, int maxit) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st += blockIdx.y;
     st->its = 0;
     st->nonfinite = 0;
     st->done = 0;
+    st->final = 0;
+    st->kcols = 0;
+    st->maxit = maxit;
+  }
+}
+
+// the scalar blocks (bnorm .. hist) of the nrhs states, packed one after the other into
+// host-visible memory (pinned, written through), for the host to read after an event
+__global__ void k_pack_states(const KrylovState* st, char* dst, int nrhs) {
+  constexpr int W = (int)((offsetof(KrylovState, hist) - offsetof(KrylovState, bnorm)) / 4);
+  for (int e = threadIdx.x; e < nrhs * W; e += blockDim.x) {
+    const int r = e / W, q = e % W;
+    ((int*)dst)[e] = ((const int*)((const char*)(st + r) + offsetof(KrylovState, bnorm)))[q];
+  }
+  __threadfence_system();
+}
+
+// right-hand sides in mask: finished, done from now on
+__global__ void k_finalize(KrylovState* st, unsigned mask) {
+  if (threadIdx.x == 0 && ((mask >> blockIdx.y) & 1u)) {
+    st[blockIdx.y].done = 1;
+    st[blockIdx.y].final = 1;
   }
 }
 
 // ------------------------------------------------------------- launchers ----
-// device address of a cd array member of the (device-resident) state
-static inline cd* st_field(const KrylovArgs& a, size_t off) { return (cd*)((char*)a.st + off); }
-
-void kr_init(const KrylovArgs& a, hipStream_t s) { hipLaunchKernelGGL(k_init_state, dim3(1), dim3(1), 0, s, a.st); }
+void kr_pack_states(const KrylovArgs& a, void* host_dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack_states, dim3(1), dim3(256), 0, s, a.st, (char*)host_dst, a.nrhs);
+}
+void kr_finalize(const KrylovArgs& a, unsigned mask, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(1, a.nrhs), dim3(1), 0, s, a.st, mask);
+}
+void kr_init(const KrylovArgs& a, int max_iter, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_state, dim3(1, a.nrhs), dim3(1), 0, s, a.st, max_iter);
+}
 void kr_residual(const KrylovArgs& a, const cd* x, const cd* b, int with_b, hipStream_t s) {
-  hipLaunchKernelGGL(k_residual, dim3(a.nblk), dim3(256), 0, s, a, x, b);
-  hipLaunchKernelGGL(k_fin_sum, dim3(1), dim3(256), 0, s, a, st_field(a, offsetof(KrylovState, tmp)));
-  hipLaunchKernelGGL(k_fin_residual, dim3(1), dim3(1), 0, s, a, with_b);
+  hipLaunchKernelGGL(k_residual, dim3(a.nblk, a.nrhs), dim3(256), 0, s, a, x, b);
+  hipLaunchKernelGGL(k_fin_sum, dim3(1, a.nrhs), dim3(256), 0, s, a, offsetof(KrylovState, tmp));
+  hipLaunchKernelGGL(k_fin_residual, dim3(1, a.nrhs), dim3(1), 0, s, a, with_b);
 }
 void kr_scale_v0(const KrylovArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_scale_v0, dim3(a.nblk), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_scale_v0, dim3(a.nblk, a.nrhs), dim3(256), 0, s, a);
 }
 void kr_arnoldi(const KrylovArgs& a, const void* z, int z_f32, int j, double tol, hipStream_t s) {
-  dim3 g(a.nblk);
+  dim3 g(a.nblk, a.nrhs);
   if (z_f32)
     hipLaunchKernelGGL((k_arnoldi_dots<cf>), g, dim3(256), 0, s, a, (const cf*)z, j);
   else
     hipLaunchKernelGGL((k_arnoldi_dots<cd>), g, dim3(256), 0, s, a, (const cd*)z, j);
-  hipLaunchKernelGGL(k_fin_sum, dim3(2 * j + 3), dim3(256), 0, s, a, st_field(a, offsetof(KrylovState, h1)));
-  hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, s, a, j, tol);
+  hipLaunchKernelGGL(k_fin_sum, dim3(2 * j + 3, a.nrhs), dim3(256), 0, s, a, offsetof(KrylovState, h1));
+  hipLaunchKernelGGL(k_givens, dim3(1, a.nrhs), dim3(64), 0, s, a, j, tol);
   if (z_f32)
     hipLaunchKernelGGL((k_arnoldi_update<cf>), g, dim3(256), 0, s, a, (const cf*)z, j);
   else
     hipLaunchKernelGGL((k_arnoldi_update<cd>), g, dim3(256), 0, s, a, (const cd*)z, j);
 }
-void kr_update_x(const KrylovArgs& a, const void* Z, int z_f32, long long ldz, int k, cd* x, hipStream_t s) {
-  hipLaunchKernelGGL(k_solve_y, dim3(1), dim3(1), 0, s, a, k);
-  dim3 g(a.nblk);
+void kr_update_x(const KrylovArgs& a, const void* Z, int z_f32, long long ldz, cd* x, hipStream_t s) {
+  hipLaunchKernelGGL(k_solve_y, dim3(1, a.nrhs), dim3(1), 0, s, a);
+  dim3 g(a.nblk, a.nrhs);
   if (z_f32)
-    hipLaunchKernelGGL((k_update_x<cf>), g, dim3(256), 0, s, a, (const cf*)Z, ldz, k, x);
+    hipLaunchKernelGGL((k_update_x<cf>), g, dim3(256), 0, s, a, (const cf*)Z, ldz, x);
   else
-    hipLaunchKernelGGL((k_update_x<cd>), g, dim3(256), 0, s, a, (const cd*)Z, ldz, k, x);
+    hipLaunchKernelGGL((k_update_x<cd>), g, dim3(256), 0, s, a, (const cd*)Z, ldz, x);
 }
 void kr_zero(cd* x, long long n, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_c128, dim3(1024), dim3(256), 0, s, x, n);

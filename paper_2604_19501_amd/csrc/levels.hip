@@ -193,6 +193,12 @@ __global__ void __launch_bounds__(256) k_sweep(Op op, const typename Op::C* __re
   __shared__ C xs[SX * SY * SZ];
   __shared__ C es[(XIN & XIN_E) ? EX * EY * EZ : 1];
   const Geom& g = op.geom();
+  // right-hand side blockIdx.y: its vectors follow each other, one level-size apart
+  const long long ry = blockIdx.y;
+  if (XIN & XIN_X) x += ry * g.tot;
+  b += ry * g.tot;
+  if (XIN & XIN_E) e += ry * gc.tot;
+  out += ry * g.tot;
   int o0, o1, o2;
   if (!tile_origin(tg, TX, TY, TZ, o0, o1, o2)) return;
   const int s0 = o0 - 1, s1 = o1 - 1, s2 = DIM == 3 ? o2 - 1 : 0;
@@ -251,6 +257,10 @@ __global__ void __launch_bounds__(256) k_restrict(Op op, const typename Op::C* _
   __shared__ C xs[XIN ? SX * SY * SZ : 1];
   __shared__ C rs[RX * RY * RZ];
   const Geom& g = op.geom();
+  const long long ry = blockIdx.y;           // right-hand side
+  if (XIN & XIN_X) x += ry * g.tot;
+  b += ry * g.tot;
+  b2 += ry * g2.tot;
   int O0, O1, O2;
   if (!tile_origin(tg, CX, CY, CZ, O0, O1, O2)) return;
   const int r0 = 2 * O0 - 1, r1 = 2 * O1 - 1, r2 = DIM == 3 ? 2 * O2 - 1 : 0;
@@ -390,9 +400,9 @@ static inline unsigned grid_tiles(const TileGrid& t) { return (unsigned)((t.ntil
 
 template <int DIM, class Op, typename CB, typename CO>
 void sweep_dim(const Op& op, int xin, const typename Op::C* x, const CB* b, typename Op::Real w_in,
-               const Geom& gc, const typename Op::C* e, typename Op::Real w, CO* out, hipStream_t s) {
+               const Geom& gc, const typename Op::C* e, typename Op::Real w, CO* out, int nrhs, hipStream_t s) {
   TileGrid tg = tiles(op.geom(), SBox<DIM>::x, SBox<DIM>::y, SBox<DIM>::z);
-  dim3 grid(grid_tiles(tg)), blk(256);
+  dim3 grid(grid_tiles(tg), nrhs), blk(256);
 #define SW(F) hipLaunchKernelGGL((k_sweep<DIM, Op, CB, CO, F>), grid, blk, 0, s, op, x, b, w_in, gc, e, w, out, tg)
   switch (xin) {
     case 0: SW(0); break;
@@ -408,10 +418,10 @@ void sweep_dim(const Op& op, int xin, const typename Op::C* x, const CB* b, type
 
 template <int DIM, class Op, typename CB>
 void restrict_dim(const Op& op, int xin, const typename Op::C* x, const CB* b, typename Op::Real w_in,
-                  const Geom& g2, typename Op::C* b2, hipStream_t s) {
+                  const Geom& g2, typename Op::C* b2, int nrhs, hipStream_t s) {
   typedef typename Op::C C;
   TileGrid tg = tiles(g2, RBox<DIM, sizeof(C)>::x, RBox<DIM, sizeof(C)>::y, RBox<DIM, sizeof(C)>::z);
-  dim3 grid(grid_tiles(tg)), blk(256);
+  dim3 grid(grid_tiles(tg), nrhs), blk(256);
 #define RS(F) hipLaunchKernelGGL((k_restrict<DIM, Op, CB, F>), grid, blk, 0, s, op, x, b, w_in, g2, b2, tg)
   switch (xin) {
     case 0: RS(0); break;
@@ -424,45 +434,47 @@ void restrict_dim(const Op& op, int xin, const typename Op::C* x, const CB* b, t
 
 template <typename R, typename CB, typename CO>
 void l1_sweep(const L1<R>& A, int xin, const typename cplx<R>::type* x, const CB* b, R w_in, const Geom& gc,
-              const typename cplx<R>::type* e, R w, CO* out, hipStream_t s) {
+              const typename cplx<R>::type* e, R w, CO* out, int nrhs, hipStream_t s) {
   if (A.op.g.dim == 2)
-    sweep_dim<2>(Op1<2, R>{A}, xin, x, b, w_in, gc, e, w, out, s);
+    sweep_dim<2>(Op1<2, R>{A}, xin, x, b, w_in, gc, e, w, out, nrhs, s);
   else
-    sweep_dim<3>(Op1<3, R>{A}, xin, x, b, w_in, gc, e, w, out, s);
+    sweep_dim<3>(Op1<3, R>{A}, xin, x, b, w_in, gc, e, w, out, nrhs, s);
 }
 
 template <typename R, typename CB>
 void l1_restrict(const L1<R>& A, int xin, const typename cplx<R>::type* x, const CB* b, R w_in, const Geom& gc,
-                 const typename cplx<R>::type* e, const Geom& g2, typename cplx<R>::type* b2, hipStream_t s) {
+                 const typename cplx<R>::type* e, const Geom& g2, typename cplx<R>::type* b2, int nrhs,
+                 hipStream_t s) {
   (void)gc;
   (void)e;
   if (A.op.g.dim == 2)
-    restrict_dim<2>(Op1<2, R>{A}, xin, x, b, w_in, g2, b2, s);
+    restrict_dim<2>(Op1<2, R>{A}, xin, x, b, w_in, g2, b2, nrhs, s);
   else
-    restrict_dim<3>(Op1<3, R>{A}, xin, x, b, w_in, g2, b2, s);
+    restrict_dim<3>(Op1<3, R>{A}, xin, x, b, w_in, g2, b2, nrhs, s);
 }
 
 template <typename R>
 void l2_sweep(const L2<R>& A, int xin, const typename cplx<R>::type* x, const typename cplx<R>::type* b, R w_in,
-              const Geom& gc, const typename cplx<R>::type* e, R w, typename cplx<R>::type* out, hipStream_t s) {
+              const Geom& gc, const typename cplx<R>::type* e, R w, typename cplx<R>::type* out, int nrhs,
+              hipStream_t s) {
   typedef typename cplx<R>::type C;
   if (A.g.dim == 2)
-    sweep_dim<2, Op2<2, R>, C, C>(Op2<2, R>{A}, xin, x, b, w_in, gc, e, w, out, s);
+    sweep_dim<2, Op2<2, R>, C, C>(Op2<2, R>{A}, xin, x, b, w_in, gc, e, w, out, nrhs, s);
   else
-    sweep_dim<3, Op2<3, R>, C, C>(Op2<3, R>{A}, xin, x, b, w_in, gc, e, w, out, s);
+    sweep_dim<3, Op2<3, R>, C, C>(Op2<3, R>{A}, xin, x, b, w_in, gc, e, w, out, nrhs, s);
 }
 
 template <typename R>
 void l2_restrict(const L2<R>& A, int xin, const typename cplx<R>::type* x, const typename cplx<R>::type* b,
                  R w_in, const Geom& gc, const typename cplx<R>::type* e, const Geom& g3,
-                 typename cplx<R>::type* b3, hipStream_t s) {
+                 typename cplx<R>::type* b3, int nrhs, hipStream_t s) {
   typedef typename cplx<R>::type C;
   (void)gc;
   (void)e;
   if (A.g.dim == 2)
-    restrict_dim<2, Op2<2, R>, C>(Op2<2, R>{A}, xin, x, b, w_in, g3, b3, s);
+    restrict_dim<2, Op2<2, R>, C>(Op2<2, R>{A}, xin, x, b, w_in, g3, b3, nrhs, s);
   else
-    restrict_dim<3, Op2<3, R>, C>(Op2<3, R>{A}, xin, x, b, w_in, g3, b3, s);
+    restrict_dim<3, Op2<3, R>, C>(Op2<3, R>{A}, xin, x, b, w_in, g3, b3, nrhs, s);
 }
 
 void l1_apply64(const L1<double>& A, const void* x, int x_is_f32, cd* y, hipStream_t s) {
@@ -480,22 +492,22 @@ void l1_apply32(const L1<float>& A, const cf* x, cf* y, hipStream_t s) {
 
 // explicit instantiations used by the cycle driver
 template void l1_sweep<float, cd, cf>(const L1<float>&, int, const cf*, const cd*, float,
-                                               const Geom&, const cf*, float, cf*, hipStream_t);
+                                               const Geom&, const cf*, float, cf*, int, hipStream_t);
 template void l1_sweep<float, cd, cd>(const L1<float>&, int, const cf*, const cd*, float,
-                                                const Geom&, const cf*, float, cd*, hipStream_t);
+                                                const Geom&, const cf*, float, cd*, int, hipStream_t);
 template void l1_sweep<double, cd, cd>(const L1<double>&, int, const cd*, const cd*, double,
-                                                 const Geom&, const cd*, double, cd*, hipStream_t);
+                                                 const Geom&, const cd*, double, cd*, int, hipStream_t);
 template void l1_restrict<float, cd>(const L1<float>&, int, const cf*, const cd*, float,
-                                          const Geom&, const cf*, const Geom&, cf*, hipStream_t);
+                                          const Geom&, const cf*, const Geom&, cf*, int, hipStream_t);
 template void l1_restrict<double, cd>(const L1<double>&, int, const cd*, const cd*, double,
-                                           const Geom&, const cd*, const Geom&, cd*, hipStream_t);
+                                           const Geom&, const cd*, const Geom&, cd*, int, hipStream_t);
 template void l2_sweep<float>(const L2<float>&, int, const cf*, const cf*, float, const Geom&,
-                              const cf*, float, cf*, hipStream_t);
+                              const cf*, float, cf*, int, hipStream_t);
 template void l2_sweep<double>(const L2<double>&, int, const cd*, const cd*, double, const Geom&,
-                               const cd*, double, cd*, hipStream_t);
+                               const cd*, double, cd*, int, hipStream_t);
 template void l2_restrict<float>(const L2<float>&, int, const cf*, const cf*, float, const Geom&,
-                                 const cf*, const Geom&, cf*, hipStream_t);
+                                 const cf*, const Geom&, cf*, int, hipStream_t);
 template void l2_restrict<double>(const L2<double>&, int, const cd*, const cd*, double, const Geom&,
-                                  const cd*, const Geom&, cd*, hipStream_t);
+                                  const cd*, const Geom&, cd*, int, hipStream_t);
 
 }  // namespace helm

@@ -47,19 +47,23 @@ struct L2 {
 };
 
 
+// nrhs right-hand sides at once: the vectors of right-hand side r follow those of r - 1
+// at one level size (x, b, out at the operator's level, e at the coarse level)
 template <typename R, typename CB, typename CO>
 void l1_sweep(const L1<R>& A, int xin, const typename cplx<R>::type* x, const CB* b, R w_in, const Geom& gc,
-              const typename cplx<R>::type* e, R w, CO* out, hipStream_t s);
+              const typename cplx<R>::type* e, R w, CO* out, int nrhs, hipStream_t s);
 template <typename R, typename CB>
 void l1_restrict(const L1<R>& A, int xin, const typename cplx<R>::type* x, const CB* b, R w_in, const Geom& gc,
-                 const typename cplx<R>::type* e, const Geom& g2, typename cplx<R>::type* b2, hipStream_t s);
+                 const typename cplx<R>::type* e, const Geom& g2, typename cplx<R>::type* b2, int nrhs,
+                 hipStream_t s);
 template <typename R>
 void l2_sweep(const L2<R>& A, int xin, const typename cplx<R>::type* x, const typename cplx<R>::type* b, R w_in,
-              const Geom& gc, const typename cplx<R>::type* e, R w, typename cplx<R>::type* out, hipStream_t s);
+              const Geom& gc, const typename cplx<R>::type* e, R w, typename cplx<R>::type* out, int nrhs,
+              hipStream_t s);
 template <typename R>
 void l2_restrict(const L2<R>& A, int xin, const typename cplx<R>::type* x, const typename cplx<R>::type* b,
                  R w_in, const Geom& gc, const typename cplx<R>::type* e, const Geom& g3,
-                 typename cplx<R>::type* b3, hipStream_t s);
+                 typename cplx<R>::type* b3, int nrhs, hipStream_t s);
 void l1_apply64(const L1<double>& A, const void* x, int x_is_f32, cd* y, hipStream_t s);
 void l1_apply32(const L1<float>& A, const cf* x, cf* y, hipStream_t s);
 

@@ -595,9 +595,12 @@ __global__ void __launch_bounds__(1024) k_nd_tree(const NDTask* __restrict__ tas
                                                   const NDOut* __restrict__ outs, const int* __restrict__ dst,
                                                   const int* __restrict__ cidx, const C* __restrict__ M,
                                                   C* __restrict__ upd, const C* __restrict__ src,
-                                                  C* __restrict__ x, int conj) {
+                                                  C* __restrict__ x, int conj, NDRhs rh) {
   typedef decltype(src[0].x) R;
   extern __shared__ __align__(16) char smem[];
+  upd += blockIdx.y * rh.upd;          // right-hand side blockIdx.y
+  src += blockIdx.y * rh.vec;
+  x += blockIdx.y * rh.vec;
   const NDTask T = tasks[blockIdx.x];
   const int nst = T.st1 - T.st0, ng = T.g1 - T.g0, nsg = T.s1 - T.s0, no = T.o1 - T.o0, nd = T.d1 - T.d0;
   char* p = smem;
@@ -732,10 +735,13 @@ __global__ void __launch_bounds__(256) k_nd_fwd_big(const NDFrontDev* __restrict
                                                     const C* __restrict__ Lp,
                                                     C* __restrict__ upd, const NDItem* __restrict__ items,
                                                     const C* __restrict__ r, C* __restrict__ x,
-                                                    C* __restrict__ gvec, int cap, int conj) {
+                                                    C* __restrict__ gvec, int cap, int conj, NDRhs rh) {
   extern __shared__ char smem[];
   __shared__ C red[256];
-  C* vec = gvec ? gvec + (long long)blockIdx.x * cap : (C*)smem;
+  upd += blockIdx.y * rh.upd;
+  r += blockIdx.y * rh.vec;
+  x += blockIdx.y * rh.vec;
+  C* vec = gvec ? gvec + blockIdx.y * rh.gvec + (long long)blockIdx.x * cap : (C*)smem;
   const NDItem item = items[blockIdx.x];
   const NDFrontDev f = fr[item.front];
   const int* id = idx + f.idx_off;
@@ -756,10 +762,12 @@ __global__ void __launch_bounds__(256) k_nd_fwd_big(const NDFrontDev* __restrict
 template <typename C>
 __global__ void __launch_bounds__(256) k_nd_bwd_big(const NDFrontDev* __restrict__ fr, const int* __restrict__ idx,
                                                     const C* __restrict__ Wp, const NDItem* __restrict__ items,
-                                                    C* __restrict__ x, C* __restrict__ gvec, int cap, int conj) {
+                                                    C* __restrict__ x, C* __restrict__ gvec, int cap, int conj,
+                                                    NDRhs rh) {
   extern __shared__ char smem[];
   __shared__ C red[256];
-  C* vec = gvec ? gvec + (long long)blockIdx.x * cap : (C*)smem;
+  x += blockIdx.y * rh.vec;
+  C* vec = gvec ? gvec + blockIdx.y * rh.gvec + (long long)blockIdx.x * cap : (C*)smem;
   const NDItem item = items[blockIdx.x];
   const NDFrontDev f = fr[item.front];
   const int* id = idx + f.idx_off;
@@ -775,10 +783,13 @@ __global__ void __launch_bounds__(256) k_nd_bwd_big(const NDFrontDev* __restrict
 template <typename C>
 __global__ void __launch_bounds__(256) k_nd_gather(const NDGather* __restrict__ gath, int n,
                                                    const int* __restrict__ cidx, const C* __restrict__ upd,
-                                                   const C* __restrict__ src, C* __restrict__ gbuf) {
+                                                   const C* __restrict__ src, C* __restrict__ gbuf, NDRhs rh) {
   typedef decltype(src[0].x) R;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
+  upd += blockIdx.y * rh.upd;
+  src += blockIdx.y * rh.vec;
+  gbuf += blockIdx.y * rh.gbuf;
   const NDGather g = gath[e];
   const C v0 = src[max(g.rid, 0)], u0 = upd[max(g.u0, 0)], u1 = upd[max(g.u1, 0)];
   C v = mk((R)0, (R)0);
@@ -793,9 +804,11 @@ __global__ void __launch_bounds__(256) k_nd_gather(const NDGather* __restrict__ 
 template <typename C, int FWD>
 __global__ void __launch_bounds__(256) k_nd_tile(const NDFrontDev* __restrict__ fr, const C* __restrict__ Mp,
                                                  const NDTile* __restrict__ tiles, const C* __restrict__ gbuf,
-                                                 C* __restrict__ P, int conj) {
+                                                 C* __restrict__ P, int conj, NDRhs rh) {
   typedef decltype(gbuf[0].x) R;
   __shared__ C vec[128];
+  gbuf += blockIdx.y * rh.gbuf;
+  P += blockIdx.y * rh.part;
   const NDTile t = tiles[blockIdx.x];
   const NDFrontDev f = fr[t.front];
   const int ld = FWD ? f.nF : f.nS, rows = FWD ? f.nF : f.nS;
@@ -821,8 +834,12 @@ template <typename C, int FWD>
 __global__ void __launch_bounds__(256) k_nd_rowsum(const NDFrontDev* __restrict__ fr, const int* __restrict__ idx,
                                                    const NDRowTile* __restrict__ rt, const C* __restrict__ P,
                                                    const C* __restrict__ gbuf, C* __restrict__ upd,
-                                                   C* __restrict__ x) {
+                                                   C* __restrict__ x, NDRhs rh) {
   typedef decltype(gbuf[0].x) R;
+  P += blockIdx.y * rh.part;
+  gbuf += blockIdx.y * rh.gbuf;
+  upd += blockIdx.y * rh.upd;
+  x += blockIdx.y * rh.vec;
   const NDRowTile t = rt[blockIdx.x];
   const NDFrontDev f = fr[t.front];
   const int i = t.r0 + threadIdx.x;
@@ -842,12 +859,13 @@ __global__ void __launch_bounds__(256) k_nd_rowsum(const NDFrontDev* __restrict_
 
 template <typename C, int FWD>
 static void splitk(const NDLaunchDev& L, const NDFrontDev* fr, const int* idx, const int* cidx, const C* M, C* upd,
-                   const C* src, C* x, C* gbuf, C* P, int conj, hipStream_t s) {
-  hipLaunchKernelGGL((k_nd_gather<C>), dim3((L.ngath + 255) / 256), dim3(256), 0, s, L.gath, L.ngath, cidx,
-                     (const C*)upd, src, gbuf);
-  hipLaunchKernelGGL((k_nd_tile<C, FWD>), dim3(L.ntiles), dim3(256), 0, s, fr, M, L.tiles, (const C*)gbuf, P, conj);
-  hipLaunchKernelGGL((k_nd_rowsum<C, FWD>), dim3(L.nrt), dim3(256), 0, s, fr, idx, L.rtiles, (const C*)P,
-                     (const C*)gbuf, upd, x);
+                   const C* src, C* x, C* gbuf, C* P, int conj, const NDRhs& rh, hipStream_t s) {
+  hipLaunchKernelGGL((k_nd_gather<C>), dim3((L.ngath + 255) / 256, rh.n), dim3(256), 0, s, L.gath, L.ngath, cidx,
+                     (const C*)upd, src, gbuf, rh);
+  hipLaunchKernelGGL((k_nd_tile<C, FWD>), dim3(L.ntiles, rh.n), dim3(256), 0, s, fr, M, L.tiles, (const C*)gbuf, P,
+                     conj, rh);
+  hipLaunchKernelGGL((k_nd_rowsum<C, FWD>), dim3(L.nrt, rh.n), dim3(256), 0, s, fr, idx, L.rtiles, (const C*)P,
+                     (const C*)gbuf, upd, x, rh);
 }
 
 // ------------------------------------------------------------- launchers ----
@@ -923,32 +941,33 @@ static void tree_attr(size_t lds) {
 
 template <typename C>
 void nd_fwd(const NDLaunchDev& L, const NDFrontDev* fr, const int* idx, const int* cptr, const int* cidx,
-            const C* Lp, C* upd, const C* r, C* x, C* gvec, int cap, int conj, C* gbuf, C* P, hipStream_t s) {
+            const C* Lp, C* upd, const C* r, C* x, C* gvec, int cap, int conj, C* gbuf, C* P, const NDRhs& rh,
+            hipStream_t s) {
   if (L.kind == 3) {
-    splitk<C, 1>(L, fr, idx, cidx, Lp, upd, r, x, gbuf, P, conj, s);
+    splitk<C, 1>(L, fr, idx, cidx, Lp, upd, r, x, gbuf, P, conj, rh, s);
   } else if (L.kind == 2) {
     size_t lds = (size_t)L.lds_bytes;
     tree_attr<C, 1>(lds);
-    hipLaunchKernelGGL((k_nd_tree<C, 1>), dim3(L.ntasks), dim3(L.threads), lds, s, L.tasks, L.stages, L.gath,
-                       L.segs, L.outs, L.dst, cidx, Lp, upd, r, x, conj);
+    hipLaunchKernelGGL((k_nd_tree<C, 1>), dim3(L.ntasks, rh.n), dim3(L.threads), lds, s, L.tasks, L.stages, L.gath,
+                       L.segs, L.outs, L.dst, cidx, Lp, upd, r, x, conj, rh);
   } else {
-    hipLaunchKernelGGL((k_nd_fwd_big<C>), dim3(L.ntasks), dim3(256), L.shm, s, fr, idx, cptr, cidx, Lp, upd,
-                       L.items, r, x, gvec, cap, conj);
+    hipLaunchKernelGGL((k_nd_fwd_big<C>), dim3(L.ntasks, rh.n), dim3(256), L.shm, s, fr, idx, cptr, cidx, Lp, upd,
+                       L.items, r, x, gvec, cap, conj, rh);
   }
 }
 template <typename C>
 void nd_bwd(const NDLaunchDev& L, const NDFrontDev* fr, const int* idx, const int* cidx, const C* Wp, C* upd, C* x,
-            C* gvec, int cap, int conj, C* gbuf, C* P, hipStream_t s) {
+            C* gvec, int cap, int conj, C* gbuf, C* P, const NDRhs& rh, hipStream_t s) {
   if (L.kind == 3) {
-    splitk<C, 0>(L, fr, idx, cidx, Wp, upd, (const C*)x, x, gbuf, P, conj, s);
+    splitk<C, 0>(L, fr, idx, cidx, Wp, upd, (const C*)x, x, gbuf, P, conj, rh, s);
   } else if (L.kind == 2) {
     size_t lds = (size_t)L.lds_bytes;
     tree_attr<C, 0>(lds);
-    hipLaunchKernelGGL((k_nd_tree<C, 0>), dim3(L.ntasks), dim3(L.threads), lds, s, L.tasks, L.stages, L.gath,
-                       L.segs, L.outs, L.dst, cidx, Wp, upd, (const C*)x, x, conj);
+    hipLaunchKernelGGL((k_nd_tree<C, 0>), dim3(L.ntasks, rh.n), dim3(L.threads), lds, s, L.tasks, L.stages, L.gath,
+                       L.segs, L.outs, L.dst, cidx, Wp, upd, (const C*)x, x, conj, rh);
   } else {
-    hipLaunchKernelGGL((k_nd_bwd_big<C>), dim3(L.ntasks), dim3(256), L.shm, s, fr, idx, Wp, L.items, x, gvec, cap,
-                       conj);
+    hipLaunchKernelGGL((k_nd_bwd_big<C>), dim3(L.ntasks, rh.n), dim3(256), L.shm, s, fr, idx, Wp, L.items, x, gvec,
+                       cap, conj, rh);
   }
 }
 
@@ -957,22 +976,21 @@ template void nd_finalize<cf>(const NDFrontDev*, const int*, int, long long, con
 template void nd_finalize<cd>(const NDFrontDev*, const int*, int, long long, const cd*, const int*,
                                    cd*, cd*, hipStream_t);
 template void nd_fwd<cf>(const NDLaunchDev&, const NDFrontDev*, const int*, const int*, const int*, const cf*, cf*,
-                         const cf*, cf*, cf*, int, int, cf*, cf*, hipStream_t);
+                         const cf*, cf*, cf*, int, int, cf*, cf*, const NDRhs&, hipStream_t);
 template void nd_fwd<cd>(const NDLaunchDev&, const NDFrontDev*, const int*, const int*, const int*, const cd*, cd*,
-                         const cd*, cd*, cd*, int, int, cd*, cd*, hipStream_t);
+                         const cd*, cd*, cd*, int, int, cd*, cd*, const NDRhs&, hipStream_t);
 template void nd_bwd<cf>(const NDLaunchDev&, const NDFrontDev*, const int*, const int*, const cf*, cf*, cf*, cf*, int,
-                         int, cf*, cf*, hipStream_t);
+                         int, cf*, cf*, const NDRhs&, hipStream_t);
 template void nd_bwd<cd>(const NDLaunchDev&, const NDFrontDev*, const int*, const int*, const cd*, cd*, cd*, cd*, int,
-                         int, cd*, cd*, hipStream_t);
+                         int, cd*, cd*, const NDRhs&, hipStream_t);
 
 
 // ---- dataflow substitution -------------------------------------------------
 // Row task products: rows [r0, r1) (at most rt) of M (column-major, leading dimension ld)
 // times v[0 .. K).  Thread t takes row t mod rt and the column slice t / rt; slices are
 // summed within a wavefront by shuffles, then over the four wavefronts in a fixed order.
-// The sum for row r0 + t is returned to threads t < rt.
-// the same product with the thread's matrix entries already in registers (m[q] for
-// column kb + q, at most 32 of them, loaded before the task's wait)
+// The sum for row r0 + t is returned to threads t < rt.  The thread's matrix entries (at
+// most 32, column kb + q in m[q]) are loaded before the task's wait.
 template <typename C>
 __device__ __forceinline__ void flow_load(const C* __restrict__ M, long long ld, int r0, int r1, int K, int rt,
                                           C (&m)[32]) {

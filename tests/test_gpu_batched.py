@@ -37,3 +37,26 @@ def test_batched_matches_single():
         assert i1["iterations"] == info["iterations"]
         assert torch.equal(x1, x)
         s.close()
+
+
+@pytest.mark.parametrize("max_iter", [400, 9])
+def test_lockstep_groups_with_mixed_outcomes(max_iter):
+    """five right-hand sides of one instance solved in lock-step groups of at most 2: a
+    zero right-hand side (x = 0 at once), point sources at different places and a scaled
+    copy; with max_iter = 9 the solves stop unconverged, each after its own count.  Every
+    solution, status and iteration count equals the single solve's."""
+    p = synth.config4_instance(1, per_size=2, sizes=(64, 96, 128), n_src=3)
+    b = BatchedSolver([instance_dict(p)], nu=(1, 1), cycle_prec="f32", max_rhs=2)
+    q = [p.rhs(0), np.zeros_like(p.rhs(0)), p.rhs(1), 1e3 * p.rhs(2), p.rhs(2)]
+    xs, infos = b.solve(q, [0] * len(q), tol=1e-6, max_iter=max_iter)
+    torch.cuda.synchronize()
+    s = from_problem(p, nu=(1, 1), cycle_prec="f32")
+    for j in range(len(q)):
+        x1, i1 = s.solve(q[j], tol=1e-6, max_iter=max_iter)
+        assert (i1["status"], i1["iterations"]) == (infos[j]["status"], infos[j]["iterations"]), j
+        assert torch.equal(x1, xs[j]), j
+    assert infos[1]["iterations"] == 0 and not torch.any(xs[1] != 0)
+    if max_iter == 9:
+        assert all(i["status"] != 0 for k, i in enumerate(infos) if k != 1)
+    s.close()
+    b.close()
