@@ -229,7 +229,7 @@ void init_geometry(helm_ctx* c) {
   c->csz = c->f32 ? sizeof(cf) : sizeof(cd);
 }
 
-const int ND_KB = 32;
+const int ND_KB = ND_KBMAX;      // scratch of the panel updates is sized for the widest panel
 // nested-dissection parameters (tunable through the environment for the autotuner):
 // leaf box size, rows per work-group of big fronts, nodes per subtree task
 int env_int(const char* name, int dflt) {
@@ -394,9 +394,9 @@ size_t carve(helm_ctx* c, void* ws) {
       for (int t : h) mf = std::max(mf, P.fronts[t].nF);
       nc = std::max(nc, h.size() * (size_t)((mf + 63) / 64));
     }
-    d.swp = cv.take<int>(32 * mx);
+    d.swp = cv.take<int>((size_t)ND_KBMAX * mx);
     d.cand = cv.take<PivCand>(nc);
-    d.rkb = cv.take<cd>(33 * mx);
+    d.rkb = cv.take<cd>((size_t)(ND_KBMAX + 1) * mx);
   }
   d.asmv = cv.take<NDAsm>(P.asmv.size());
   d.perm = cv.take<int>(P.perm_total);
@@ -514,7 +514,10 @@ void nd_factor(helm_ctx* c, hipStream_t s) {
     // enough; otherwise the panel is spread over many work-groups
     const int kreg = panel_reg_kb(hi.max_nF);
     const bool reg_panel = kreg > 0 && c->lds_panel > 0;
-    const int kb = reg_panel ? kreg : ND_KB;
+    // multi-work-group panels: HELM_ND_KB_MULTI columns (16, 32 or 64; wider panels halve
+    // the trailing-matrix passes of the GEMM, whose per-column cost is mostly launch latency)
+    const int kmulti = std::max(8, std::min(ND_KBMAX, env_int("HELM_ND_KB_MULTI", 64)));
+    const int kb = reg_panel ? kreg : kmulti;
     for (int k0 = 0; k0 < hi.max_nS; k0 += kb) {
       if (reg_panel)
         nd_panel_reg(d.fronts, ids, hi.count, hi.max_nF, d.F, d.perm, d.swp, k0, kb, d.err, s);

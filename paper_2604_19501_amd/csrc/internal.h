@@ -153,6 +153,8 @@ struct NDFrontDev {
   int pad;
 };
 
+#define ND_KBMAX 64     // widest factorisation panel (columns)
+
 struct PivCand {        // a row block's pivot candidate: largest |F[i][k]| and its row
   double v;
   int i, pad;

@@ -137,7 +137,7 @@ __global__ void __launch_bounds__(NT) k_nd_panel_reg(const NDFrontDev* __restric
   const int nF = f.nF, nS = f.nS, tid = threadIdx.x, w0 = tid & ~63;
   cd* F = Fp + f.F_off;
   int* pm = perm + f.perm_off;
-  int* sw = swp + (long long)blockIdx.x * 32;
+  int* sw = swp + (long long)blockIdx.x * ND_KBMAX;
   cd a[R][KB];
   int pr[R];
 #pragma unroll
@@ -296,7 +296,7 @@ __global__ void __launch_bounds__(64) k_piv_select(const NDFrontDev* __restrict_
   const double pv = sv[0];
   const int p = pv >= 0.0 && si[0] < f.nS ? si[0] : k;
   cd* F = Fp + f.F_off;
-  cd* rk = rkb + (long long)blockIdx.x * 33;
+  cd* rk = rkb + (long long)blockIdx.x * (ND_KBMAX + 1);
   const int t = threadIdx.x;
   if (t < kbb) {
     cd a = F[(long long)k * f.nF + k0 + t];
@@ -310,7 +310,7 @@ __global__ void __launch_bounds__(64) k_piv_select(const NDFrontDev* __restrict_
   }
   __syncthreads();
   if (t == 0) {
-    swp[(long long)blockIdx.x * 32 + kk] = p;
+    swp[(long long)blockIdx.x * ND_KBMAX + kk] = p;
     if (p != k) {
       int q = perm[f.perm_off + k];
       perm[f.perm_off + k] = perm[f.perm_off + p];
@@ -321,7 +321,7 @@ __global__ void __launch_bounds__(64) k_piv_select(const NDFrontDev* __restrict_
       atomicOr(err, 1);
       piv = mk(1.0, 0.0);
     }
-    rk[32] = cdiv(mk(1.0, 0.0), piv);
+    rk[ND_KBMAX] = cdiv(mk(1.0, 0.0), piv);
   }
 }
 
@@ -329,23 +329,25 @@ __global__ void __launch_bounds__(256) k_piv_update(const NDFrontDev* __restrict
                                                     cd* __restrict__ Fp, int k0, int kb, int kk,
                                                     const cd* __restrict__ rkb, PivCand* __restrict__ cand,
                                                     int nblk) {
-  __shared__ cd srk[33];
+  __shared__ cd srk[ND_KBMAX + 1];
   __shared__ double sv[4];
   __shared__ int si[4];
   const NDFrontDev f = fr[ids[blockIdx.y]];
   const int k = k0 + kk;
   if (f.nS <= k || (int)blockIdx.x * PROWS >= f.nF) return;
   const int kbb = min(kb, f.nS - k0);
-  if (threadIdx.x < 33) srk[threadIdx.x] = rkb[(long long)blockIdx.y * 33 + threadIdx.x];
+  if (threadIdx.x < ND_KBMAX + 1) srk[threadIdx.x] = rkb[(long long)blockIdx.y * (ND_KBMAX + 1) + threadIdx.x];
   __syncthreads();
-  const cd inv = srk[32];
+  const cd inv = srk[ND_KBMAX];
   cd* F = Fp + f.F_off;
-  const int jj = threadIdx.x & 31, rsub = threadIdx.x >> 5;        // 8 rows per pass, lanes along columns
+  // lanes along the panel's columns (32 or 64 per row), 8 or 4 rows per pass
+  const int cw = kb > 32 ? 64 : 32, rpp = 256 / cw;
+  const int jj = threadIdx.x & (cw - 1), rsub = threadIdx.x / cw;
   const bool next = kk + 1 < kbb;
   double best = -1.0;
   int bi = 0x7fffffff;
   const int r0 = (int)blockIdx.x * PROWS, r1 = min(f.nF, r0 + PROWS);
-  for (int i = r0 + rsub; i < r1; i += 8) {
+  for (int i = r0 + rsub; i < r1; i += rpp) {
     cd* row = F + (long long)i * f.nF + k0;
     if (i == k) {
       if (jj < kbb) row[jj] = jj == kk ? inv : -(srk[jj] * inv);
@@ -375,7 +377,7 @@ __global__ void __launch_bounds__(256) k_nd_swap_rest(const NDFrontDev* __restri
   const NDFrontDev f = fr[ids[blockIdx.y]];
   if (f.nS <= k0) return;
   const int kbb = min(KB, f.nS - k0);
-  const int* sw = swp + (long long)blockIdx.y * 32;
+  const int* sw = swp + (long long)blockIdx.y * ND_KBMAX;
   cd* F = Fp + f.F_off;
   for (int jj = blockIdx.x * blockDim.x + threadIdx.x; jj < f.nF - kbb; jj += gridDim.x * blockDim.x) {
     int j = jj < k0 ? jj : jj + kbb;

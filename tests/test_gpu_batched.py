@@ -39,12 +39,12 @@ def test_batched_matches_single():
         s.close()
 
 
-@pytest.mark.parametrize("max_iter", [400, 9])
+@pytest.mark.parametrize("max_iter", [400, 3])
 def test_lockstep_groups_with_mixed_outcomes(max_iter):
     """five right-hand sides of one instance solved in lock-step groups of at most 2: a
     zero right-hand side (x = 0 at once), point sources at different places and a scaled
-    copy; with max_iter = 9 the solves stop unconverged, each after its own count.  Every
-    solution, status and iteration count equals the single solve's."""
+    copy; with max_iter = 3 the solves stop unconverged.  Every solution, status and
+    iteration count equals the single solve's."""
     p = synth.config4_instance(1, per_size=2, sizes=(64, 96, 128), n_src=3)
     b = BatchedSolver([instance_dict(p)], nu=(1, 1), cycle_prec="f32", max_rhs=2)
     q = [p.rhs(0), np.zeros_like(p.rhs(0)), p.rhs(1), 1e3 * p.rhs(2), p.rhs(2)]
@@ -56,7 +56,8 @@ def test_lockstep_groups_with_mixed_outcomes(max_iter):
         assert (i1["status"], i1["iterations"]) == (infos[j]["status"], infos[j]["iterations"]), j
         assert torch.equal(x1, xs[j]), j
     assert infos[1]["iterations"] == 0 and not torch.any(xs[1] != 0)
-    if max_iter == 9:
-        assert all(i["status"] != 0 for k, i in enumerate(infos) if k != 1)
+    if max_iter == 3:
+        from paper_2604_19501_amd import _lib as L
+        assert all(i["status"] == L.HELM_ENOCONV and i["iterations"] == 3 for k, i in enumerate(infos) if k != 1)
     s.close()
     b.close()
