@@ -178,12 +178,14 @@ struct NDItem {         // one work item of a multi-block launch: rows [r0, r1) 
 // a task are relative to the task's first gather / segment / output / destination.
 struct NDTask {
   int st0, st1, g0, g1, s0, s1, o0, o1, d0, d1;
+  int nlu;              // forward: entries of the LDS copy of the task's internal update vectors
+  int pad;
 };
 struct NDStage {
   int g0, g1, s0, s1, o0, o1;
 };
 struct NDGather {       // vec[slot] = (rid >= 0 ? src[rid] : 0) + upd[u0] + upd[u1] + sum upd[cidx[ca .. cb))
-  int slot, rid, u0, u1, ca, cb;
+  int slot, rid, u0, u1, ca, cb;   // u0, u1: -1 none; <= -2 (tree blocks): LDS update entry -u - 2
 };
 struct NDSeg {          // part[pslot + l] = sum_{k0 <= k < k1} M[m_off + k ld + r0 + l] vec[vslot + k], l < nr
   long long m_off;
@@ -191,6 +193,7 @@ struct NDSeg {          // part[pslot + l] = sum_{k0 <= k < k1} M[m_off + k ld +
 };
 struct NDOut {          // rows [r0, r0 + nr): y = sum of nparts partial blocks of 64; destinations dst[d ..)
   int r0, nr, vslot, pslot, nparts, d;   // dst >= 0: x index; dst < 0: update index -dst - 1
+  int lu, lu_on;        // lu_on: row r0 + l's update also goes to LDS update entry lu + l
 };
 
 // Split-K launches for heights with large fronts: every front's input vector is gathered

@@ -616,12 +616,30 @@ __global__ void __launch_bounds__(1024) k_nd_tree(const NDTask* __restrict__ tas
   p += al16(sizeof(NDOut) * no);
   int* ldst = (int*)p;
   p += al16(sizeof(int) * nd);
+  // values forwarded between the task's levels: forward, the update vectors of fronts whose
+  // parent is in the task; backward, the solution x_S of fronts with a descendant in it
+  C* lupd = (C*)p;
+  p += al16(sizeof(C) * T.nlu);
+  C* lsrc = (C*)p;                     // per gather: r (forward) or x from outside the task
+  p += al16(sizeof(C) * ng);
+  C* lxg = (C*)p;                      // backward: x_S before the update, per output row
+  p += al16(sizeof(C) * (FWD ? 0 : nd));
   C* work = (C*)p;
   copy_lds(lst, stages + T.st0, sizeof(NDStage) * nst);
   copy_lds(lg, gath + T.g0, sizeof(NDGather) * ng);
   copy_lds(lsg, segs + T.s0, sizeof(NDSeg) * nsg);
   copy_lds(lo, outs + T.o0, sizeof(NDOut) * no);
   copy_lds(ldst, dst + T.d0, sizeof(int) * nd);
+  __syncthreads();
+  // one round trip for every stage's inputs that do not change during the launch: r
+  // (forward); x of fronts above the task and x_S before the update (backward)
+  for (int e = threadIdx.x; e < ng; e += blockDim.x) {
+    const NDGather g = lg[e];
+    const C v = src[max(g.rid, 0)];
+    lsrc[e] = g.rid >= 0 && (FWD || g.u0 == -1) ? v : mk((R)0, (R)0);
+  }
+  if (!FWD)
+    for (int e = threadIdx.x; e < nd; e += blockDim.x) lxg[e] = x[max(ldst[e], 0)];
   __syncthreads();
   const int nw = blockDim.x >> 6, wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   // prefetching holds a second segment in registers: FP32 only (FP64 would spill)
@@ -640,12 +658,22 @@ __global__ void __launch_bounds__(1024) k_nd_tree(const NDTask* __restrict__ tas
     // all of them in flight instead of waiting on each one
     for (int e = S.g0 + (int)threadIdx.x; e < S.g1; e += blockDim.x) {
       const NDGather g = lg[e];
-      const C v0 = src[max(g.rid, 0)], u0 = upd[max(g.u0, 0)], u1 = upd[max(g.u1, 0)];
       C v = mk((R)0, (R)0);
-      if (g.rid >= 0) v += v0;
-      if (g.u0 >= 0) v += u0;
-      if (g.u1 >= 0) v += u1;
-      for (int q = g.ca; q < g.cb; ++q) v += upd[cidx[q]];
+      if (FWD) {
+        // rhs from LDS; contributions of the task's own fronts from LDS, of fronts below
+        // the task (the previous launch) from global memory
+        v = lsrc[e];
+        if (g.u0 >= 0 || g.u1 >= 0) {
+          const C u0 = upd[max(g.u0, 0)], u1 = upd[max(g.u1, 0)];
+          if (g.u0 >= 0) v += u0;
+          if (g.u1 >= 0) v += u1;
+        }
+        if (g.u0 <= -2) v += lupd[-g.u0 - 2];
+        if (g.u1 <= -2) v += lupd[-g.u1 - 2];
+        for (int q = g.ca; q < g.cb; ++q) v += upd[cidx[q]];
+      } else {
+        v = g.u0 <= -2 ? lupd[-g.u0 - 2] : lsrc[e];    // x_B: from a task level above, or prefetched
+      }
       work[g.slot] = v;
     }
     __syncthreads();
@@ -687,12 +715,17 @@ __global__ void __launch_bounds__(1024) k_nd_tree(const NDTask* __restrict__ tas
         for (int q = 0; q < ob.nparts; ++q) acc += work[ob.pslot + 64 * q + lane];
         const int d = ldst[ob.d + lane];
         if (FWD) {
-          if (d >= 0)
+          if (d >= 0) {
             x[d] = acc;
-          else
-            upd[-d - 1] = work[ob.vslot + ob.r0 + lane] - acc;
+          } else {
+            const C u = work[ob.vslot + ob.r0 + lane] - acc;
+            upd[-d - 1] = u;
+            if (ob.lu_on) lupd[ob.lu + lane] = u;   // row >= nS: read by the parent's gather
+          }
         } else {
-          x[d] = x[d] + acc;
+          const C nx = lxg[ob.d + lane] + acc;
+          x[d] = nx;
+          if (ob.lu_on) lupd[ob.lu + lane] = nx;     // read by the gathers of lower levels
         }
       }
     }

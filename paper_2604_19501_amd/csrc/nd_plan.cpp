@@ -21,6 +21,8 @@
 #include <cassert>
 #include <cstdio>
 #include <functional>
+#include <map>
+#include <set>
 #include <numeric>
 #include <stdexcept>
 
@@ -334,14 +336,20 @@ void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int root_merge, int e
     }
     for (auto& tk : tasks)
       for (int dir = 0; dir < 2; ++dir) {
-        long long sch = 0;
+        long long sch = 0, lu = 0;
         std::vector<long long> work(H + 1, 0);
         for (int t : tk) {
           sch += sched_bytes(plan.fronts[t], dir);
           work[plan.fronts[t].height] += work_entries(plan.fronts[t], dir);
+          if (dir == 0 && par[t] >= 0 && plan.fronts[par[t]].height <= b) lu += plan.fronts[t].nB;
+          if (dir == 0) lu += plan.fronts[t].nF;       // the prefetched right-hand side entries
+          // backward: forwarded x_S of in-task ancestors (bound: every front's), prefetched
+          // x_B and x_S
+          if (dir == 1) lu += 2LL * plan.fronts[t].nS + plan.fronts[t].nB;
         }
         long long wmax = *std::max_element(work.begin(), work.end());
-        if (al16(sch) + 6 * 16 + wmax * elem_bytes > lds_bytes) return false;
+        // (+ the alignment of the LDS areas: up to 15 entries each, and 64 bytes)
+        if (al16(sch) + 6 * 16 + 64 + (wmax + lu + 48) * elem_bytes > lds_bytes) return false;
       }
     return !tasks.empty();
   };
@@ -415,6 +423,15 @@ void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int root_merge, int e
 
   plan.fwd.clear();
   plan.bwd.clear();
+  // front and S position owning each level-3 node (backward tree tasks forward x in LDS)
+  std::vector<int> node_front(g3.tot, -1), node_pos(g3.tot, -1);
+  for (int t = 0; t < nf; ++t) {
+    const NDFrontDev& f = plan.fronts[t];
+    for (int i = 0; i < f.nS; ++i) {
+      node_front[plan.idx[f.idx_off + i]] = t;
+      node_pos[plan.idx[f.idx_off + i]] = i;
+    }
+  }
   std::vector<NDLaunch> bwd_tree;
   int lo = -1;
   for (int b : cut) {
@@ -435,6 +452,43 @@ void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int root_merge, int e
         std::vector<std::vector<int>> byh(b + 1);
         for (int u : tk) byh[plan.fronts[u].height].push_back(u);
         long long wmax = 0;
+        // forward: the update vectors of fronts whose parent is in the task are also kept in
+        // LDS (entries lu_off[u] ..), where the parent's gathers read them
+        std::map<int, int> lu_off;
+        int nlu = 0;
+        // (only fronts that have work in this direction write their outputs; the others'
+        // values are read from global memory)
+        if (dir == 0) {
+          for (int u : tk)
+            if (par[u] >= 0 && plan.fronts[par[u]].height <= b && plan.fronts[u].nS > 0 && plan.fronts[u].nB > 0) {
+              lu_off[u] = nlu;
+              nlu += plan.fronts[u].nB;
+            }
+        } else {
+          // backward: the solution x_S of fronts with a descendant in the task is also kept
+          // in LDS (entries lu_off[a] + S position), where the descendants' gathers read it;
+          // a front without a boundary has no backward work (its x_S is final already)
+          std::set<int> inner;
+          for (int u : tk)
+            if (par[u] >= 0 && plan.fronts[par[u]].height <= b) inner.insert(par[u]);
+          for (int a : inner)
+            if (plan.fronts[a].nS > 0 && plan.fronts[a].nB > 0) {
+              lu_off[a] = nlu;
+              nlu += plan.fronts[a].nS;
+            }
+        }
+        // LDS entry of update index q from a child of f, or -1 when that child is outside
+        auto lds_of = [&](const NDFrontDev& f, int q) -> int {
+          for (int k = 0; k < f.nchild; ++k) {
+            const int c = plan.children[f.child_off + k];
+            const NDFrontDev& C = plan.fronts[c];
+            if (q >= C.upd_off && q < C.upd_off + C.nB) {
+              auto it = lu_off.find(c);
+              return it == lu_off.end() ? -1 : it->second + (int)(q - C.upd_off);
+            }
+          }
+          return -1;
+        };
         for (int step = 0; step <= b - lo - 1; ++step) {
           const int h = dir == 0 ? lo + 1 + step : b - step;
           NDStage st{(int)L.gath.size() - T.g0, 0, (int)L.segs.size() - T.s0, 0, (int)L.outs.size() - T.o0, 0};
@@ -452,14 +506,24 @@ void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int root_merge, int e
               for (int i = 0; i < f.nF; ++i) {
                 int ca = plan.cptr[f.inv_off + i], cb = plan.cptr[f.inv_off + i + 1];
                 NDGather g{vs + i, i < f.nS ? ids[i] : -1, -1, -1, 0, 0};
-                if (ca < cb) g.u0 = plan.cidx[ca++];
-                if (ca < cb) g.u1 = plan.cidx[ca++];
+                auto enc = [&](int q) {
+                  const int l = lds_of(f, q);
+                  return l >= 0 ? -l - 2 : q;
+                };
+                if (ca < cb) g.u0 = enc(plan.cidx[ca++]);
+                if (ca < cb) g.u1 = enc(plan.cidx[ca++]);
                 g.ca = ca;
                 g.cb = cb;
                 L.gath.push_back(g);
               }
             } else {
-              for (int j = 0; j < f.nB; ++j) L.gath.push_back({vs + j, ids[f.nS + j], -1, -1, 0, 0});
+              for (int j = 0; j < f.nB; ++j) {
+                NDGather g{vs + j, ids[f.nS + j], -1, -1, 0, 0};
+                const int node = ids[f.nS + j];
+                auto it = lu_off.find(node_front[node]);
+                if (it != lu_off.end()) g.u0 = -(it->second + node_pos[node]) - 2;
+                L.gath.push_back(g);
+              }
             }
             const int np = nparts(K);
             for (int r0 = 0; r0 < R; r0 += 64) {
@@ -477,7 +541,14 @@ void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int root_merge, int e
                 sg.pad = 0;
                 L.segs.push_back(sg);
               }
-              L.outs.push_back({r0, nr, vs, ps, np, (int)L.dst.size() - T.d0});
+              NDOut ob{r0, nr, vs, ps, np, (int)L.dst.size() - T.d0, 0, 0};
+              auto it = lu_off.find(u);
+              if (it != lu_off.end()) {
+                // forward: row i >= nS -> entry lu_off + i - nS; backward: row i -> lu_off + i
+                ob.lu = dir == 0 ? it->second - f.nS + r0 : it->second + r0;
+                ob.lu_on = 1;
+              }
+              L.outs.push_back(ob);
               for (int i = r0; i < r0 + nr; ++i)
                 L.dst.push_back(dir == 1 || i < f.nS ? ids[i] : -(int)(f.upd_off + i - f.nS) - 1);
               ps += 64 * np;
@@ -499,7 +570,11 @@ void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int root_merge, int e
                               al16((long long)sizeof(NDGather) * (T.g1 - T.g0)) +
                               al16((long long)sizeof(NDSeg) * (T.s1 - T.s0)) +
                               al16((long long)sizeof(NDOut) * (T.o1 - T.o0)) + al16(4LL * (T.d1 - T.d0));
-        const long long need = sch + wmax * elem_bytes;
+        T.nlu = nlu;
+        T.pad = 0;
+        const long long need = sch +
+                               (wmax + nlu + al16(T.g1 - T.g0) + (dir == 1 ? al16(T.d1 - T.d0) : 0)) * elem_bytes +
+                               64;
         if (need > lds_bytes) throw std::runtime_error("nd_plan: tree-block task exceeds LDS");
         if (T.st1 > T.st0) {
           L.tasks.push_back(T);
