@@ -88,34 +88,55 @@ def timed_steps(s, p, q, steps, warmup, refactor=True):
     return (time.perf_counter() - t0) / steps, its, info
 
 
-def bytes_model(cls, p, info, iters, restart):
+def bytes_model(cls, p, info, iters, restart, nr=1):
     """algorithmic HBM bytes of one launch of a kernel class.
 
     Per-unit figures: fine node N1, level-2 node N2, factor entry / update entry of the
-    coarsest elimination (info from helm_get_info), cb = bytes of a cycle complex."""
+    coarsest elimination (info from helm_get_info), cb = bytes of a cycle complex.  nr
+    right-hand sides iterated in lock-step share the operator data (m, the level-2
+    coefficients, the factors and the gather indices) and bring their own vectors."""
     d = p.dim
     N1, N2, N3 = info["N1"], info["N2"], info["N3"]
     cb = info["cycle_complex_bytes"]
     K = 3 ** d
-    if cls == "l1_restrict":      # b (c128) + m (f32) per fine node, r2 per level-2 node
-        return N1 * (16 + 4) + N2 * cb
-    if cls == "l1_sweep":         # b (c128) + m (f32) + z out per fine node, e2 per level-2 node
-        return N1 * (16 + 4 + cb) + N2 * cb
-    if cls == "l2_sweep":         # coefficients (K) + b2 + x in + x out per level-2 node
-        return N2 * cb * (K + 3)
-    if cls == "l2_restrict":      # coefficients + b2 + x per level-2 node
-        return N2 * cb * (K + 2)
+    U = info["upd_entries"]
+    if cls == "l1_restrict":      # b (c128) per fine node and r2 per level-2 node per rhs; m (f32)
+        return N1 * (16 * nr + 4) + N2 * cb * nr
+    if cls == "l1_sweep":         # b (c128) + z out per fine node and e2 per level-2 node per rhs; m
+        return N1 * ((16 + cb) * nr + 4) + N2 * cb * nr
+    if cls == "l2_sweep":         # coefficients (K) + b2, x in, x out per level-2 node
+        return N2 * cb * (K + 3 * nr)
+    if cls == "l2_restrict":      # coefficients + b2, x per level-2 node
+        return N2 * cb * (K + 2 * nr)
     if cls == "nd_fwd":           # [A^-1; C A^-1] once, right-hand side gather, updates written and read
-        per_solve = (info["L_entries"] * cb + N3 * (cb + 4) + info["upd_entries"] * (2 * cb + 4) + N3 * cb)
+        per_solve = info["L_entries"] * cb + 4 * (N3 + U) + nr * (2 * N3 * cb + 2 * U * cb)
         return per_solve / info["fwd_launches"]
     if cls == "nd_bwd":           # -A^-1 B once, boundary gather, g read and x written
-        per_solve = info["W_entries"] * cb + info["upd_entries"] * (cb + 4) + 2 * N3 * cb
+        per_solve = info["W_entries"] * cb + 4 * U + nr * (U * cb + 2 * N3 * cb)
         return per_solve / max(1, info["bwd_launches"])
     if cls == "arnoldi":          # two passes, each reading z, m and V_0..V_j; V_{j+1} written
         js = [k % restart for k in range(iters)]
         jm = sum(js) / max(1, len(js))
-        return N1 * (2 * (cb + 8) + 16 + 32 * (jm + 1))
+        return N1 * (2 * 8 + nr * (2 * cb + 16 + 32 * (jm + 1)))
     return None
+
+
+def roofline_of(kt, B_of, traffic_of=lambda cls: None):
+    """per-class achieved GB/s and the roofline record of the class with the most time;
+    kt = {class: (ms, launches)}, B_of(class) = algorithmic bytes per launch"""
+    gbs = {}
+    for k, (ms, cnt) in kt.items():
+        B = B_of(k)
+        if B is not None and cnt > 0 and ms > 0:
+            gbs[k] = B / (ms / cnt / 1e3) / 1e9
+    dom = max(kt.items(), key=lambda kv: kv[1][0])[0]
+    ms, cnt = kt[dom]
+    B = B_of(dom)
+    avg_s = ms / cnt / 1e3
+    roof = {"bound": "hbm", "achieved": B / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": B / avg_s / 1e9 / HBM_PEAK_GBS, "traffic": traffic_of(dom), "kernel": dom, "bytes_per_launch": B,
+            "avg_launch_us": avg_s * 1e6, "share_of_instrumented_solve": ms / sum(v[0] for v in kt.values())}
+    return {k: round(v, 1) for k, v in gbs.items()}, roof
 
 
 def instrumented(s, p, q, its):
@@ -128,21 +149,9 @@ def instrumented(s, p, q, its):
     kt = s.kernel_times()
     s.set_timing(False)
     sinfo = s.info()
-    gbs = {}
-    for k, (ms, cnt) in kt.items():
-        B = bytes_model(k, p, sinfo, its, p.restart)
-        if B is not None and cnt > 0 and ms > 0:
-            gbs[k] = B / (ms / cnt / 1e3) / 1e9
-    dom = max(kt.items(), key=lambda kv: kv[1][0])[0]
-    ms, cnt = kt[dom]
-    B = bytes_model(dom, p, sinfo, its, p.restart)
-    avg_s = ms / cnt / 1e3
-    traffic = measured_traffic(dom) if (p.dim == 2 and p.n[0] == 1024) else None
-    roof = {"bound": "hbm", "achieved": B / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": B / avg_s / 1e9 / HBM_PEAK_GBS, "traffic": traffic, "kernel": dom, "bytes_per_launch": B,
-            "avg_launch_us": avg_s * 1e6, "share_of_instrumented_solve": ms / sum(v[0] for v in kt.values())}
-    return ({k: round(v[0], 4) for k, v in kt.items()}, {k: v[1] for k, v in kt.items()},
-            {k: round(v, 1) for k, v in gbs.items()}, roof, sinfo)
+    gbs, roof = roofline_of(kt, lambda k: bytes_model(k, p, sinfo, its, p.restart),
+                            lambda k: measured_traffic(k) if (p.dim == 2 and p.n[0] == 1024) else None)
+    return ({k: round(v[0], 4) for k, v in kt.items()}, {k: v[1] for k, v in kt.items()}, gbs, roof, sinfo)
 
 
 # ------------------------------------------------------------------ oracle baselines
@@ -282,8 +291,27 @@ def workload_cfg4(args):
                    "iterations_mean": float(np.mean(its)), "iterations_max": int(max(its)),
                    "worst_true_rel_residual": worst, "status_nonzero": sum(1 for i in infos if i["status"] != 0)},
         "batch_setup_s": t_setup,
-        "roofline": None,
     }
+    # per-class HIP-event timings (graphs bypassed) of one lock-step group at full width: the
+    # first 768^2 instance with its first source in all 8 slots, so every launch carries 8
+    # active right-hand sides
+    ii = 2 * per
+    pi = probs[ii]
+    q0 = torch.from_numpy(pi.rhs(0)).cuda()
+    b.set_timing(True)
+    _, inf8 = b.solve([q0] * 8, [ii] * 8, tol=1e-6, max_iter=2000)
+    sync()
+    kt = b.kernel_times()
+    b.set_timing(False)
+    info_i = b.instance_info(ii)
+    it8 = inf8[0]["iterations"]
+    gbs, roof = roofline_of(kt, lambda k: bytes_model(k, pi, info_i, it8, pi.restart, nr=8))
+    roof["measured_on"] = ("one 768^2 instance, 8 lock-step right-hand sides (%d iterations), per-launch "
+                           "HIP events on its stream" % it8)
+    out["kernel_ms"] = {k: round(v[0], 4) for k, v in kt.items()}
+    out["kernel_launches"] = {k: v[1] for k, v in kt.items()}
+    out["kernel_achieved_GBs"] = gbs
+    out["roofline"] = roof
     if not args.no_cpu_baseline:
         tot, sample = 0.0, []
         for size_idx in range(3):

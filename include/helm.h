@@ -196,7 +196,8 @@ const char* helm_status_str(int status);
 const char* helm_last_error(void);
 
 /* Device timing (HIP events), recorded while enabled by helm_set_timing(ctx, 1), which also
- * clears the accumulators.  helm_get_timing fills host array t[0..n): [0] last solve total ms,
+ * clears the accumulators (on every instance of a batched context; its class sums are then
+ * summed over the instances).  helm_get_timing fills host array t[0..n): [0] last solve total ms,
  * [1..3] reserved (0), [4] last setup ms, then for kernel class k = 0..9 (level-1 sweep,
  * level-1 residual+restriction, level-2 sweep, level-2 residual+restriction, coarsest
  * forward substitution, coarsest backward substitution, Arnoldi step (apply, two
@@ -216,6 +217,10 @@ int helm_get_timing(helm_ctx* ctx, double* t, int n);
  * launches per direction, [17..20] the heights closing them (-1 beyond).
  * Returns the number of entries written (at most n). */
 int helm_get_info(helm_ctx* ctx, long long* out, int n);
+
+/* The same sizes for instance inst of a batched context (inst 0 of a single-instance
+ * context).  HELM_EINVAL for an instance that does not exist. */
+int helm_get_instance_info(helm_ctx* ctx, int inst, long long* out, int n);
 
 /* Number of unknowns on level lev (1..3) of instance inst. */
 long long helm_level_size(helm_ctx* ctx, int inst, int lev);

@@ -79,6 +79,7 @@ _SIG = {
     "helm_get_timing": (C.c_int, [P, C.POINTER(C.c_double), C.c_int]),
     "helm_level_size": (C.c_longlong, [P, C.c_int, C.c_int]),
     "helm_get_info": (C.c_int, [P, C.POINTER(C.c_longlong), C.c_int]),
+    "helm_get_instance_info": (C.c_int, [P, C.c_int, C.POINTER(C.c_longlong), C.c_int]),
     "helm_get_coefficients": (C.c_int, [P, C.c_int, P]),
 }
 for _name, (_res, _args) in _SIG.items():

@@ -16,7 +16,7 @@ import numpy as np
 import torch
 
 from . import _lib as L
-from .solver import _dev_tensor, _stream_ptr, make_grid, make_mg
+from .solver import _dev_tensor, _stream_ptr, kernel_times, make_grid, make_mg, parse_info
 
 
 class BatchedSolver:
@@ -59,6 +59,20 @@ class BatchedSolver:
         out = [dict(status=infos[k].status, iterations=infos[k].iterations,
                     true_rel_residual=infos[k].true_rel_residual) for k in range(n)]
         return xs, out
+
+    def instance_info(self, inst: int) -> dict:
+        """sizes of instance inst (helm_get_info's fields)"""
+        v = (C.c_longlong * 21)()
+        L.check(L.lib.helm_get_instance_info(self.ctx, int(inst), v, 21), "helm_get_instance_info")
+        return parse_info(v)
+
+    def set_timing(self, on: bool = True):
+        """per-kernel-class HIP-event timing on every instance (graphs are bypassed meanwhile)"""
+        L.check(L.lib.helm_set_timing(self.ctx, 1 if on else 0), "helm_set_timing")
+
+    def kernel_times(self) -> dict:
+        """{class: (ms, launches)} summed over the instances since set_timing(True)"""
+        return kernel_times(self.ctx)
 
     def close(self):
         if getattr(self, "ctx", None):

@@ -1257,6 +1257,7 @@ int helm_set_timing(helm_ctx* c, int on) {
     c->kt_ms[k] = 0.0;
     c->kt_cnt[k] = 0;
   }
+  for (helm_ctx* u : c->sub) helm_set_timing(u, on);
   return HELM_OK;
 }
 
@@ -1264,13 +1265,19 @@ int helm_get_timing(helm_ctx* c, double* t, int n) {
   if (!c || !t || n < 0) return fail(HELM_EINVAL, "bad arguments");
   try {
     ev_flush(c);
+    for (helm_ctx* u : c->sub) ev_flush(u);
   } catch (DevErr& e) {
     return fail(HELM_EDEVICE, "%s", e.what());
   }
   std::vector<double> v(c->times, c->times + 5);
   for (int k = 0; k < KT_N; ++k) {
-    v.push_back(c->kt_ms[k]);
-    v.push_back((double)c->kt_cnt[k]);
+    double ms = c->kt_ms[k], cnt = (double)c->kt_cnt[k];
+    for (helm_ctx* u : c->sub) {           // batched: the sums over the instances
+      ms += u->kt_ms[k];
+      cnt += (double)u->kt_cnt[k];
+    }
+    v.push_back(ms);
+    v.push_back(cnt);
   }
   int m = std::min<int>(n, (int)v.size());
   for (int i = 0; i < m; ++i) t[i] = v[i];
@@ -1296,8 +1303,24 @@ int helm_get_info(helm_ctx* c, long long* out, int n) {
   return m;
 }
 
+int helm_get_instance_info(helm_ctx* c, int inst, long long* out, int n) {
+  if (!c) return fail(HELM_EINVAL, "NULL context");
+  if (c->sub.empty()) {
+    if (inst != 0) return fail(HELM_EINVAL, "instance %d of a single-instance context", inst);
+    return helm_get_info(c, out, n);
+  }
+  if (inst < 0 || inst >= (int)c->sub.size()) return fail(HELM_EINVAL, "no instance %d", inst);
+  return helm_get_info(c->sub[inst], out, n);
+}
+
 long long helm_level_size(helm_ctx* c, int inst, int lev) {
-  if (!c || inst != 0) return -1;
+  if (!c) return -1;
+  if (!c->sub.empty()) {
+    if (inst < 0 || inst >= (int)c->sub.size()) return -1;
+    c = c->sub[inst];
+  } else if (inst != 0) {
+    return -1;
+  }
   if (lev == 1) return c->g1.tot;
   if (lev == 2) return c->g2.tot;
   if (lev == 3) return c->g3.tot;

@@ -254,8 +254,14 @@ __global__ void __launch_bounds__(256) k_restrict(Op op, const typename Op::C* _
   constexpr int CX = RBox<DIM, sizeof(C)>::x, CY = RBox<DIM, sizeof(C)>::y, CZ = RBox<DIM, sizeof(C)>::z;
   constexpr int RX = 2 * CX + 1, RY = 2 * CY + 1, RZ = DIM == 3 ? 2 * CZ + 1 : 1;
   constexpr int SX = RX + 2, SY = RY + 2, SZ = DIM == 3 ? RZ + 2 : 1;
+  constexpr int RT = RX * RY * RZ, NR = (RT + 255) / 256;
+  // 3D: the residuals are held in registers until every thread has read the staged
+  // iterate, then written over it, which halves the block's LDS (4 blocks per CU
+  // instead of 2)
+  constexpr bool ALIAS = XIN != 0 && DIM == 3;
   __shared__ C xs[XIN ? SX * SY * SZ : 1];
-  __shared__ C rs[RX * RY * RZ];
+  __shared__ C rs_own[ALIAS ? 1 : RT];
+  C* rs = ALIAS ? xs : rs_own;
   const Geom& g = op.geom();
   const long long ry = blockIdx.y;           // right-hand side
   if (XIN & XIN_X) x += ry * g.tot;
@@ -266,7 +272,6 @@ __global__ void __launch_bounds__(256) k_restrict(Op op, const typename Op::C* _
   const int r0 = 2 * O0 - 1, r1 = 2 * O1 - 1, r2 = DIM == 3 ? 2 * O2 - 1 : 0;
   // the residual footprint's b and D, loaded before the staging barrier when it takes at
   // most 4 passes (2D); otherwise in the residual loop
-  constexpr int RT = RX * RY * RZ, NR = (RT + 255) / 256;
   constexpr bool PRE = NR <= 4;
   C bv[PRE ? NR : 1], Dv[PRE ? NR : 1];
   auto load_bd = [&](int it, C& bb, C& dd) {
@@ -286,7 +291,8 @@ __global__ void __launch_bounds__(256) k_restrict(Op op, const typename Op::C* _
                                     DIM == 3 ? r2 - 1 : 0, xs);
     __syncthreads();
   }
-#pragma unroll(PRE ? NR : 4)
+  C rv[ALIAS ? NR : 1];
+#pragma unroll(PRE || ALIAS ? NR : 4)
   for (int it = 0; it < NR; ++it) {
     const int k = (int)threadIdx.x + 256 * it;
     if (k >= RT) continue;
@@ -308,7 +314,16 @@ __global__ void __launch_bounds__(256) k_restrict(Op op, const typename Op::C* _
         v -= op.ax(xs, kk, SX, SX * SY, f, dd);
       }
     }
-    rs[k] = v;
+    if (ALIAS)
+      rv[ALIAS ? it : 0] = v;
+    else
+      rs[k] = v;
+  }
+  if (ALIAS) {
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < (ALIAS ? NR : 0); ++it)
+      if ((int)threadIdx.x + 256 * it < RT) rs[(int)threadIdx.x + 256 * it] = rv[it];
   }
   __syncthreads();
   for (int k = threadIdx.x; k < CX * CY * CZ; k += 256) {

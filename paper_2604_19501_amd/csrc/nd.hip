@@ -279,6 +279,11 @@ __global__ void __launch_bounds__(64) k_piv_select(const NDFrontDev* __restrict_
   const int nb = (f.nF + PROWS - 1) / PROWS;
   __shared__ double sv[1];
   __shared__ int si[1];
+  cd* F = Fp + f.F_off;
+  const int t = threadIdx.x;
+  // row k's panel entries do not depend on the pivot: their load overlaps the reduction
+  cd a = mk(0.0, 0.0);
+  if (t < kbb) a = F[(long long)k * f.nF + k0 + t];
   // candidates of the blocks that hold S rows >= k
   double best = -1.0;
   int bi = 0x7fffffff;
@@ -295,11 +300,8 @@ __global__ void __launch_bounds__(64) k_piv_select(const NDFrontDev* __restrict_
   __syncthreads();
   const double pv = sv[0];
   const int p = pv >= 0.0 && si[0] < f.nS ? si[0] : k;
-  cd* F = Fp + f.F_off;
   cd* rk = rkb + (long long)blockIdx.x * (ND_KBMAX + 1);
-  const int t = threadIdx.x;
   if (t < kbb) {
-    cd a = F[(long long)k * f.nF + k0 + t];
     if (p != k) {
       cd b = F[(long long)p * f.nF + k0 + t];
       F[(long long)k * f.nF + k0 + t] = b;
@@ -325,10 +327,15 @@ __global__ void __launch_bounds__(64) k_piv_select(const NDFrontDev* __restrict_
   }
 }
 
+// CW lanes per row (the panel's width rounded up to 32 or 64), 256 / CW rows per pass.  All
+// loads of the block's rows are issued before the first store, so one memory round trip
+// serves the whole block; lane kk's store of row[kk] follows every read of it in the wave.
+template <int CW>
 __global__ void __launch_bounds__(256) k_piv_update(const NDFrontDev* __restrict__ fr, const int* __restrict__ ids,
                                                     cd* __restrict__ Fp, int k0, int kb, int kk,
                                                     const cd* __restrict__ rkb, PivCand* __restrict__ cand,
                                                     int nblk) {
+  constexpr int RPP = 256 / CW, NP = PROWS / RPP;
   __shared__ cd srk[ND_KBMAX + 1];
   __shared__ double sv[4];
   __shared__ int si[4];
@@ -337,26 +344,35 @@ __global__ void __launch_bounds__(256) k_piv_update(const NDFrontDev* __restrict
   if (f.nS <= k || (int)blockIdx.x * PROWS >= f.nF) return;
   const int kbb = min(kb, f.nS - k0);
   if (threadIdx.x < ND_KBMAX + 1) srk[threadIdx.x] = rkb[(long long)blockIdx.y * (ND_KBMAX + 1) + threadIdx.x];
+  cd* F = Fp + f.F_off;
+  const int jj = threadIdx.x & (CW - 1), rsub = threadIdx.x / CW;
+  const int r0 = (int)blockIdx.x * PROWS + rsub;
+  const int jl = min(jj, kbb - 1);
+  cd ckv[NP], rv[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    const long long i = min(r0 + RPP * q, f.nF - 1);
+    ckv[q] = F[i * f.nF + k0 + kk];
+    rv[q] = F[i * f.nF + k0 + jl];
+  }
   __syncthreads();
   const cd inv = srk[ND_KBMAX];
-  cd* F = Fp + f.F_off;
-  // lanes along the panel's columns (32 or 64 per row), 8 or 4 rows per pass
-  const int cw = kb > 32 ? 64 : 32, rpp = 256 / cw;
-  const int jj = threadIdx.x & (cw - 1), rsub = threadIdx.x / cw;
   const bool next = kk + 1 < kbb;
   double best = -1.0;
   int bi = 0x7fffffff;
-  const int r0 = (int)blockIdx.x * PROWS, r1 = min(f.nF, r0 + PROWS);
-  for (int i = r0 + rsub; i < r1; i += rpp) {
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    const int i = r0 + RPP * q;
+    if (i >= f.nF) continue;
     cd* row = F + (long long)i * f.nF + k0;
     if (i == k) {
       if (jj < kbb) row[jj] = jj == kk ? inv : -(srk[jj] * inv);
       continue;
     }
-    const cd ck = row[kk] * inv;             // every lane of the row reads it before lane kk writes
+    const cd ck = ckv[q] * inv;
     cd nv = mk(0.0, 0.0);
     if (jj < kbb) {
-      nv = jj == kk ? ck : row[jj] - ck * srk[jj];
+      nv = jj == kk ? ck : rv[q] - ck * srk[jj];
       row[jj] = nv;
     }
     if (next && jj == kk + 1 && i > k && i < f.nS) {
@@ -928,7 +944,12 @@ void nd_panel_multi(const NDFrontDev* fr, const int* ids, int nids, int max_nF, 
   for (int kk = 0; kk < kbb; ++kk) {
     hipLaunchKernelGGL(k_piv_select, dim3(nids), dim3(64), 0, s, fr, ids, Fp, perm, swp, k0, kb, kk, cand, nblk, rkb,
                        err);
-    hipLaunchKernelGGL(k_piv_update, dim3(nblk, nids), dim3(256), 0, s, fr, ids, Fp, k0, kb, kk, rkb, cand, nblk);
+    if (kb > 32)
+      hipLaunchKernelGGL(k_piv_update<64>, dim3(nblk, nids), dim3(256), 0, s, fr, ids, Fp, k0, kb, kk, rkb, cand,
+                         nblk);
+    else
+      hipLaunchKernelGGL(k_piv_update<32>, dim3(nblk, nids), dim3(256), 0, s, fr, ids, Fp, k0, kb, kk, rkb, cand,
+                         nblk);
   }
   unsigned gx = (unsigned)std::min(64, std::max(1, (max_nF + 255) / 256));
   hipLaunchKernelGGL(k_nd_swap_rest, dim3(gx, nids), dim3(256), 0, s, fr, ids, Fp, swp, k0, kb);

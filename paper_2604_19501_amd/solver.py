@@ -20,6 +20,26 @@ import torch
 from . import _lib as L
 
 
+INFO_KEYS = ("N1", "N2", "N3", "fronts", "L_entries", "W_entries", "upd_entries", "sep_entries",
+             "fwd_launches", "bwd_launches", "workspace_bytes", "max_front", "cycle_complex_bytes",
+             "nd_leaf", "nd_root", "nd_tuned", "nd_tree_launches")
+KERNEL_CLASSES = ("l1_sweep", "l1_restrict", "l2_sweep", "l2_restrict", "nd_fwd", "nd_bwd", "arnoldi")
+
+
+def parse_info(v) -> dict:
+    """the 21 integers of helm_get_info as a dict"""
+    out = {k: int(v[i]) for i, k in enumerate(INFO_KEYS)}
+    out["nd_cuts"] = [int(v[17 + i]) for i in range(min(4, out["nd_tree_launches"]))]
+    return out
+
+
+def kernel_times(ctx) -> dict:
+    """{class: (ms, launches)} accumulated since helm_set_timing(ctx, 1)"""
+    t = (C.c_double * 25)()
+    L.lib.helm_get_timing(ctx, t, 25)
+    return {k: (t[5 + 2 * i], int(t[6 + 2 * i])) for i, k in enumerate(KERNEL_CLASSES)}
+
+
 def _stream_ptr(device) -> int:
     return torch.cuda.current_stream(device).cuda_stream
 
@@ -105,13 +125,11 @@ class Solver:
         L.check(L.lib.helm_refactor(self.ctx, C.c_void_p(self._kap.data_ptr()), self.omega, C.byref(self.shift),
                                     self._s()), "helm_refactor")
 
-    KERNEL_CLASSES = ("l1_sweep", "l1_restrict", "l2_sweep", "l2_restrict", "nd_fwd", "nd_bwd", "arnoldi")
+    KERNEL_CLASSES = KERNEL_CLASSES
 
     def kernel_times(self):
         """{class: (ms, launches)} accumulated since set_timing(True)."""
-        t = (C.c_double * 25)()
-        L.lib.helm_get_timing(self.ctx, t, 25)
-        return {k: (t[5 + 2 * i], int(t[6 + 2 * i])) for i, k in enumerate(self.KERNEL_CLASSES)}
+        return kernel_times(self.ctx)
 
     # -- lifetime
     def close(self):
@@ -197,16 +215,11 @@ class Solver:
                                   self._s()), "helm_grad_m")
         return g
 
-    INFO_KEYS = ("N1", "N2", "N3", "fronts", "L_entries", "W_entries", "upd_entries", "sep_entries",
-                 "fwd_launches", "bwd_launches", "workspace_bytes", "max_front", "cycle_complex_bytes",
-                 "nd_leaf", "nd_root", "nd_tuned", "nd_tree_launches")
 
     def info(self) -> dict:
         v = (C.c_longlong * 21)()
         L.check(L.lib.helm_get_info(self.ctx, v, 21), "helm_get_info")
-        out = {k: int(v[i]) for i, k in enumerate(self.INFO_KEYS)}
-        out["nd_cuts"] = [int(v[17 + i]) for i in range(min(4, out["nd_tree_launches"]))]
-        return out
+        return parse_info(v)
 
     def set_timing(self, on: bool = True):
         L.lib.helm_set_timing(self.ctx, 1 if on else 0)

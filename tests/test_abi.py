@@ -67,6 +67,9 @@ def test_setup_rejects_bad_arguments_before_device_work():
     assert L.lib.helm_destroy(None) == 0
     assert L.lib.helm_apply(None, 0, 0, None, None, None) == L.HELM_EINVAL
     assert L.lib.helm_solve(None, 0, None, None, 1e-6, 10, None, None) == L.HELM_EINVAL
+    v = (C.c_longlong * 21)()
+    assert L.lib.helm_get_instance_info(None, 0, v, 21) == L.HELM_EINVAL
+    assert L.lib.helm_level_size(None, 0, 1) == -1
 
 
 def test_tuning_cache_changes_the_plan(tmp_path, monkeypatch):

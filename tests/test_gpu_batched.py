@@ -13,6 +13,7 @@ pytest.importorskip("paper_2604_19501_amd._lib")
 from paper_2604_19501_amd import from_problem  # noqa: E402
 from paper_2604_19501_amd.batched import BatchedSolver, instance_dict  # noqa: E402
 from oracle import operators as ops  # noqa: E402
+from paper_2604_19501_amd import _lib as L  # noqa: E402
 
 
 def test_batched_matches_single():
@@ -25,6 +26,9 @@ def test_batched_matches_single():
             inst.append(i)
     xs, infos = b.solve(rhs, inst, tol=1e-6, max_iter=400)
     torch.cuda.synchronize()
+    for i, p in enumerate(probs):
+        assert b.instance_info(i)["N1"] == p.N
+        assert L.lib.helm_level_size(b.ctx, i, 1) == p.N
     for j, (x, info, i) in enumerate(zip(xs, infos, inst)):
         p = probs[i]
         assert info["status"] == 0, (j, info)
@@ -57,7 +61,6 @@ def test_lockstep_groups_with_mixed_outcomes(max_iter):
         assert torch.equal(x1, xs[j]), j
     assert infos[1]["iterations"] == 0 and not torch.any(xs[1] != 0)
     if max_iter == 3:
-        from paper_2604_19501_amd import _lib as L
         assert all(i["status"] == L.HELM_ENOCONV and i["iterations"] == 3 for k, i in enumerate(infos) if k != 1)
     s.close()
     b.close()
