@@ -32,9 +32,9 @@ void nd_extend(const NDFrontDev* fr, const int* ids, int nids, long long max_nb2
 void nd_panel_multi(const NDFrontDev* fr, const int* ids, int nids, int max_nF, cd* Fp, int* perm, int* swp,
                     PivCand* cand, cd* rkb, int k0, int kb, int max_nS, int* err, hipStream_t s);
 void nd_save_t(const NDFrontDev* fr, const int* ids, int nids, const long long* toff, long long max_n, cd* Fp,
-               cd* T, int k0, int kb, hipStream_t s);
-void nd_gemm(const NDFrontDev* fr, const int* ids, int nids, const long long* toff, int max_nF, cd* Fp,
-             const cd* T, int k0, int kb, hipStream_t s);
+               cd* T, int k0, int kb, int u0, int un, hipStream_t s);
+void nd_gemm(const NDFrontDev* fr, const int* ids, int nids, const long long* toff, int max_rows, int max_cols,
+             cd* Fp, const cd* T, int k0, int kb, int u0, int un, hipStream_t s);
 template <typename C>
 void nd_finalize(const NDFrontDev* fr, const int* ids, int nids, long long max_n, const cd* Fp, const int* perm,
                  C* Lp, C* Wp, hipStream_t s);
@@ -229,7 +229,7 @@ void init_geometry(helm_ctx* c) {
   c->csz = c->f32 ? sizeof(cf) : sizeof(cd);
 }
 
-const int ND_KB = ND_KBMAX;      // scratch of the panel updates is sized for the widest panel
+const int ND_KB = ND_KBOUT;      // scratch of the exchange updates is sized for the widest column block
 // nested-dissection parameters (tunable through the environment for the autotuner):
 // leaf box size, rows per work-group of big fronts, nodes per subtree task
 int env_int(const char* name, int dflt) {
@@ -515,17 +515,28 @@ void nd_factor(helm_ctx* c, hipStream_t s) {
     const int kreg = panel_reg_kb(hi.max_nF);
     const bool reg_panel = kreg > 0 && c->lds_panel > 0;
     // multi-work-group panels: HELM_ND_KB_MULTI columns (16, 32 or 64; wider panels halve
-    // the trailing-matrix passes of the GEMM, whose per-column cost is mostly launch latency)
+    // the trailing-matrix passes of the GEMM, whose per-column cost is mostly launch latency),
+    // grouped into blocks of HELM_ND_KB_OUTER columns: the panels of a block update each
+    // other, and the rest of the front takes one trailing update per block (the GEMM streams
+    // the front once per block instead of once per panel)
     const int kmulti = std::max(8, std::min(ND_KBMAX, env_int("HELM_ND_KB_MULTI", 64)));
     const int kb = reg_panel ? kreg : kmulti;
-    for (int k0 = 0; k0 < hi.max_nS; k0 += kb) {
-      if (reg_panel)
+    const int kout = reg_panel ? kb : std::max(1, std::min(ND_KBOUT, env_int("HELM_ND_KB_OUTER", ND_KBOUT)) / kb) * kb;
+    for (int k0 = 0; k0 < hi.max_nS; k0 += kout) {
+      if (reg_panel) {
         nd_panel_reg(d.fronts, ids, hi.count, hi.max_nF, d.F, d.perm, d.swp, k0, kb, d.err, s);
-      else
-        nd_panel_multi(d.fronts, ids, hi.count, hi.max_nF, d.F, d.perm, d.swp, d.cand, d.rkb, k0, kb, hi.max_nS,
-                       d.err, s);
-      nd_save_t(d.fronts, ids, hi.count, toff, hi.max_T, d.F, d.T, k0, kb, s);
-      nd_gemm(d.fronts, ids, hi.count, toff, hi.max_nF, d.F, d.T, k0, kb, s);
+      } else {
+        for (int k1 = k0; k1 < std::min(k0 + kout, hi.max_nS); k1 += kb) {
+          nd_panel_multi(d.fronts, ids, hi.count, hi.max_nF, d.F, d.perm, d.swp, d.cand, d.rkb, k1, kb, hi.max_nS,
+                         d.err, s);
+          if (kout > kb) {        // the block's other panels
+            nd_save_t(d.fronts, ids, hi.count, toff, (long long)kb * kout, d.F, d.T, k1, kb, k0, kout, s);
+            nd_gemm(d.fronts, ids, hi.count, toff, hi.max_nF, kout, d.F, d.T, k1, kb, k0, kout, s);
+          }
+        }
+      }
+      nd_save_t(d.fronts, ids, hi.count, toff, hi.max_T, d.F, d.T, k0, kout, 0, -1, s);
+      nd_gemm(d.fronts, ids, hi.count, toff, hi.max_nF, hi.max_nF, d.F, d.T, k0, kout, 0, -1, s);
     }
     if (c->f32)
       nd_finalize<cf>(d.fronts, ids, hi.count, hi.max_fin, d.F, d.perm, (cf*)d.L, (cf*)d.W, s);

@@ -154,6 +154,7 @@ struct NDFrontDev {
 };
 
 #define ND_KBMAX 64     // widest factorisation panel (columns)
+#define ND_KBOUT 128    // widest column block of the trailing exchange update
 
 struct PivCand {        // a row block's pivot candidate: largest |F[i][k]| and its row
   double v;

@@ -408,21 +408,41 @@ __global__ void __launch_bounds__(256) k_nd_swap_rest(const NDFrontDev* __restri
   }
 }
 
-// T = F[K rows][J columns] (J = all columns outside K), then zero those entries
+// Columns J of an exchange update: the front's columns [lo, hi) without the pivot block
+// K = [k0, k0 + kbb).  un < 0: [lo, hi) = [0, nF), the trailing update of every other
+// column; otherwise [u0, min(u0 + un, nS)), the other panels of one column block, which
+// the block's pivots reach before the trailing update does.
+struct ColMap {
+  int lo, k0, kbb, ncol;
+  __device__ __forceinline__ int col(int c) const {
+    const int j = lo + c;
+    return j >= k0 ? j + kbb : j;
+  }
+};
+__device__ __forceinline__ bool col_map(const NDFrontDev& f, int k0, int kb, int u0, int un, ColMap& m) {
+  m.kbb = min(kb, f.nS - k0);
+  if (m.kbb <= 0) return false;
+  m.lo = un < 0 ? 0 : u0;
+  const int hi = un < 0 ? f.nF : min(u0 + un, f.nS);
+  m.k0 = k0;
+  m.ncol = hi - m.lo - m.kbb;
+  return m.ncol > 0;
+}
+
+// T = F[K rows][J columns], then zero those entries
 __global__ void __launch_bounds__(256) k_nd_save_t(const NDFrontDev* __restrict__ fr, const int* __restrict__ ids,
                                                    const long long* __restrict__ toff, cd* __restrict__ Fp,
-                                                   cd* __restrict__ T, int k0, int kb) {
+                                                   cd* __restrict__ T, int k0, int kb, int u0, int un) {
   const NDFrontDev f = fr[ids[blockIdx.y]];
-  if (f.nS <= k0) return;
-  const int kbb = min(kb, f.nS - k0);
-  const int ncol = f.nF - kbb;
+  ColMap cm;
+  if (!col_map(f, k0, kb, u0, un, cm)) return;
+  const int ncol = cm.ncol;
   cd* F = Fp + f.F_off;
   cd* Tt = T + toff[blockIdx.y];
-  long long n = (long long)kbb * ncol;
+  long long n = (long long)cm.kbb * ncol;
   for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += (long long)gridDim.x * blockDim.x) {
     int kk = (int)(p / ncol), jj = (int)(p % ncol);
-    int j = jj < k0 ? jj : jj + kbb;
-    long long a = (long long)(k0 + kk) * f.nF + j;
+    long long a = (long long)(k0 + kk) * f.nF + cm.col(jj);
     Tt[p] = F[a];
     F[a] = mk(0.0, 0.0);
   }
@@ -437,13 +457,14 @@ __global__ void __launch_bounds__(256) k_nd_save_t(const NDFrontDev* __restrict_
 #define GT 64
 #define GK 16
 typedef double mfma_d4 __attribute__((ext_vector_type(4)));
-__global__ void __launch_bounds__(256) k_nd_gemm(const NDFrontDev* __restrict__ fr, const int* __restrict__ ids,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) k_nd_gemm(const NDFrontDev* __restrict__ fr, const int* __restrict__ ids,
                                                  const long long* __restrict__ toff, cd* __restrict__ Fp,
-                                                 const cd* __restrict__ T, int k0, int kb) {
+                                                 const cd* __restrict__ T, int k0, int kb, int u0, int un) {
   const NDFrontDev f = fr[ids[blockIdx.y]];
-  if (f.nS <= k0) return;
-  const int kbb = min(kb, f.nS - k0);
-  const int M = f.nF, Ncol = f.nF - kbb;
+  ColMap cm;
+  if (!col_map(f, k0, kb, u0, un, cm)) return;
+  const int kbb = cm.kbb;
+  const int M = f.nF, Ncol = cm.ncol;
   const int tilesN = (Ncol + GT - 1) / GT, tilesM = (M + GT - 1) / GT;
   if ((int)blockIdx.x >= tilesM * tilesN) return;
   const int tm = blockIdx.x / tilesN, tn = blockIdx.x % tilesN;
@@ -460,16 +481,31 @@ __global__ void __launch_bounds__(256) k_nd_gemm(const NDFrontDev* __restrict__ 
       acci[a][b] = mfma_d4{0.0, 0.0, 0.0, 0.0};
     }
   const int lm = lane & 15, lk = lane >> 4;
+  // the next k slice is loaded into registers while the matrix cores work on this one
+  constexpr int NLD = GK * GT / 256;
+  cd ra[NLD], rb[NLD];
+  auto load = [&](int kk0) {
+#pragma unroll
+    for (int it = 0; it < NLD; ++it) {
+      const int p = (int)threadIdx.x + 256 * it;
+      const int kk = p % GK, r = p / GK;             // A tile: consecutive threads along a row
+      const int row = tm * GT + r, kq = kk0 + kk;
+      ra[it] = (row < M && kq < kbb) ? F[(long long)row * f.nF + k0 + kq] : mk(0.0, 0.0);
+      const int kk2 = p / GT, c = p % GT;            // B tile: consecutive threads along a row of T
+      const int col = tn * GT + c, kq2 = kk0 + kk2;
+      rb[it] = (col < Ncol && kq2 < kbb) ? Tt[(long long)kq2 * Ncol + col] : mk(0.0, 0.0);
+    }
+  };
+  load(0);
   for (int kk0 = 0; kk0 < kbb; kk0 += GK) {
-    for (int p = threadIdx.x; p < GK * GT; p += 256) {
-      int kk = p % GK, r = p / GK;                 // A tile: consecutive threads along a row
-      int row = tm * GT + r, kq = kk0 + kk;
-      sA[kk][r] = (row < M && kq < kbb) ? F[(long long)row * f.nF + k0 + kq] : mk(0.0, 0.0);
-      int kk2 = p / GT, c = p % GT;                // B tile: consecutive threads along a row of T
-      int col = tn * GT + c, kq2 = kk0 + kk2;
-      sB[kk2][c] = (col < Ncol && kq2 < kbb) ? Tt[(long long)kq2 * Ncol + col] : mk(0.0, 0.0);
+#pragma unroll
+    for (int it = 0; it < NLD; ++it) {
+      const int p = (int)threadIdx.x + 256 * it;
+      sA[p % GK][p / GK] = ra[it];
+      sB[p / GT][p % GT] = rb[it];
     }
     __syncthreads();
+    if (kk0 + GK < kbb) load(kk0 + GK);
 #pragma unroll
     for (int k4 = 0; k4 < GK; k4 += 4) {
       cd av[2], bv[2];
@@ -499,8 +535,7 @@ __global__ void __launch_bounds__(256) k_nd_gemm(const NDFrontDev* __restrict__ 
         const int row = tm * GT + wr + 16 * qa + lk + 4 * i;
         const int col = tn * GT + wc + 16 * qb + lm;
         if (row >= M || col >= Ncol) continue;
-        const int j = col < k0 ? col : col + kbb;
-        cd* c = F + (long long)row * f.nF + j;
+        cd* c = F + (long long)row * f.nF + cm.col(col);
         *c -= mk(accr[qa][qb][i], acci[qa][qb][i]);
       }
 }
@@ -973,14 +1008,14 @@ void nd_panel_reg(const NDFrontDev* fr, const int* ids, int nids, int max_nF, cd
   hipLaunchKernelGGL(k_nd_swap_rest, dim3(gx, nids), dim3(256), 0, s, fr, ids, Fp, swp, k0, kb);
 }
 void nd_save_t(const NDFrontDev* fr, const int* ids, int nids, const long long* toff, long long max_n,
-               cd* Fp, cd* T, int k0, int kb, hipStream_t s) {
+               cd* Fp, cd* T, int k0, int kb, int u0, int un, hipStream_t s) {
   unsigned gx = (unsigned)std::min<long long>(1024, std::max<long long>(1, (max_n + 255) / 256));
-  hipLaunchKernelGGL(k_nd_save_t, dim3(gx, nids), dim3(256), 0, s, fr, ids, toff, Fp, T, k0, kb);
+  hipLaunchKernelGGL(k_nd_save_t, dim3(gx, nids), dim3(256), 0, s, fr, ids, toff, Fp, T, k0, kb, u0, un);
 }
-void nd_gemm(const NDFrontDev* fr, const int* ids, int nids, const long long* toff, int max_nF, cd* Fp,
-             const cd* T, int k0, int kb, hipStream_t s) {
-  int tiles = ((max_nF + GT - 1) / GT) * ((max_nF + GT - 1) / GT);
-  hipLaunchKernelGGL(k_nd_gemm, dim3(tiles, nids), dim3(256), 0, s, fr, ids, toff, Fp, T, k0, kb);
+void nd_gemm(const NDFrontDev* fr, const int* ids, int nids, const long long* toff, int max_rows, int max_cols,
+             cd* Fp, const cd* T, int k0, int kb, int u0, int un, hipStream_t s) {
+  int tiles = ((max_rows + GT - 1) / GT) * ((max_cols + GT - 1) / GT);
+  hipLaunchKernelGGL(k_nd_gemm, dim3(tiles, nids), dim3(256), 0, s, fr, ids, toff, Fp, T, k0, kb, u0, un);
 }
 template <typename C>
 void nd_finalize(const NDFrontDev* fr, const int* ids, int nids, long long max_n, const cd* Fp,

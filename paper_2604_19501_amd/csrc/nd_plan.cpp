@@ -273,11 +273,12 @@ void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int root_merge, int e
   plan.perm_total = P;
   plan.by_height.assign(plan.max_height + 1, std::vector<int>());
   for (int t = 0; t < nf; ++t) plan.by_height[plan.fronts[t].height].push_back(t);
-  // panel row buffer: kb rows of every front of one height (kb <= ND_KBMAX)
+  // pivot-row buffer of the exchange updates: the rows of one column block (at most
+  // ND_KBOUT) of every front of one height
   long long Tmax = 0;
   for (auto& ids : plan.by_height) {
     long long s = 0;
-    for (int t : ids) s += (long long)ND_KBMAX * plan.fronts[t].nF;
+    for (int t : ids) s += (long long)ND_KBOUT * plan.fronts[t].nF;
     Tmax = std::max(Tmax, s);
   }
   plan.T_scratch = Tmax;

@@ -71,15 +71,20 @@ def test_coarse_solve(case, prec, tol):
 @pytest.mark.parametrize("dim,n", [(2, 256), (3, 64)])
 @pytest.mark.parametrize("cuts,panel,splitk", [("none", "lds", None), ("", "lds", None), ("1", "lds", None),
                                                ("0,1,2,3", "lds", None), ("", "multi", None), ("none", "lds", 0),
-                                               ("1", "multi", 0)])
+                                               ("1", "multi", 0), ("", "multi32", None), ("", "multi_unblocked", None)])
 def test_coarse_solve_schedules(monkeypatch, dim, n, cuts, panel, splitk):
     """the exact coarsest solve under every kind of substitution schedule (row-chunk
     launches only, the planner's choice, one tree-block launch, one per level, split-K
     launches for every height above the tree blocks) and with both factorisation panel
-    paths (LDS-resident, multi-work-group)."""
+    paths (LDS-resident; multi-work-group panels of 64 or 32 columns in blocks of 128 with
+    one trailing update per block, or one trailing update per 64-column panel)."""
     monkeypatch.setenv("HELM_ND_CUTS", cuts)
-    if panel == "multi":
+    if panel.startswith("multi"):
         monkeypatch.setenv("HELM_ND_LDS_PANEL", "0")
+    if panel == "multi32":
+        monkeypatch.setenv("HELM_ND_KB_MULTI", "32")
+    if panel == "multi_unblocked":
+        monkeypatch.setenv("HELM_ND_KB_OUTER", "64")
     if splitk is not None:
         monkeypatch.setenv("HELM_ND_SPLITK_KB", str(splitk))
     p = synth.config2(n) if dim == 2 else synth.config3(n)
