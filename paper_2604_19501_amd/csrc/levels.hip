@@ -21,6 +21,14 @@ namespace helm {
 
 
 
+// a / d for the Jacobi updates: in the FP32 cycle one hardware reciprocal of |d|^2 (about
+// 1 ulp) replaces two IEEE divisions; FP64 keeps the exact quotient
+__device__ __forceinline__ cf jdiv(cf a, cf d) {
+  const float r = __builtin_amdgcn_rcpf(d.x * d.x + d.y * d.y);
+  return mk((a.x * d.x + a.y * d.y) * r, (a.y * d.x - a.x * d.y) * r);
+}
+__device__ __forceinline__ cd jdiv(cd a, cd d) { return cdiv(a, d); }
+
 // contiguous-slab block order: hardware dispatches block b to XCD b % 8
 __device__ __forceinline__ long long xcd_block(long long nblocks) {
   long long b = blockIdx.x;
@@ -57,12 +65,12 @@ __device__ __forceinline__ long long flat(const Geom& g, int i0, int i1, int i2)
 //
 // Box shapes (threads = 256):
 //   sweeps       2D 32 x 16            3D 32 x 8 x 4
-//   restrictions 2D 16 x 8 coarse      3D 16 x 4 x 4 coarse (8 x 4 x 4 in FP64)
+//   restrictions 2D 16 x 8 coarse      3D 8 x 4 x 4 coarse
 template <int DIM> struct SBox {
   static constexpr int x = 32, y = DIM == 2 ? 16 : 8, z = DIM == 2 ? 1 : 4;
 };
 template <int DIM, int CSZ> struct RBox {
-  static constexpr int x = DIM == 2 ? 16 : (CSZ == 8 ? 16 : 8), y = DIM == 2 ? 8 : 4, z = DIM == 2 ? 1 : 4;
+  static constexpr int x = DIM == 2 ? 16 : 8, y = DIM == 2 ? 8 : 4, z = DIM == 2 ? 1 : 4;
 };
 
 // level-1 operator H_s with x from LDS (centre index k, strides sy, sz)
@@ -73,6 +81,10 @@ struct Op1 {
   L1<R> A;
   __host__ __device__ __forceinline__ const Geom& geom() const { return A.op.g; }
   __device__ __forceinline__ C diag(long long f, int i0, int i1, int i2) const { return A.diag(f, i0, i1, i2); }
+  // the diagonal in two steps, so that the load can be issued early: aux(f), then diag_aux
+  typedef R Aux;
+  __device__ __forceinline__ Aux aux(long long f) const { return A.m[f]; }
+  __device__ __forceinline__ C diag_aux(Aux mm, int i0, int i1, int i2) const { return A.diag_m(mm, i0, i1, i2); }
   __device__ __forceinline__ C ax(const C* xs, int k, int sy, int sz, long long, C D) const {
     C nb = (xs[k - 1] + xs[k + 1]) + (xs[k - sy] + xs[k + sy]);
     if (DIM == 3) nb += xs[k - sz] + xs[k + sz];
@@ -88,6 +100,9 @@ struct Op2 {
   L2<R> A;
   __host__ __device__ __forceinline__ const Geom& geom() const { return A.g; }
   __device__ __forceinline__ C diag(long long f, int, int, int) const { return A.get(DIM == 2 ? 4 : 13, f); }
+  typedef C Aux;
+  __device__ __forceinline__ Aux aux(long long f) const { return A.get(DIM == 2 ? 4 : 13, f); }
+  __device__ __forceinline__ C diag_aux(Aux d, int, int, int) const { return d; }
   __device__ __forceinline__ C ax(const C* xs, int k, int sy, int sz, long long f, C D) const {
     C acc = D * xs[k];
 #pragma unroll
@@ -170,7 +185,7 @@ __device__ __forceinline__ void stage_xin(const Op& op, const C* __restrict__ x,
     const long long f = flat(g, j0, j1, j2);
     C v = mk((R)0, (R)0);
     if (XIN & XIN_X) v += x[f];
-    if (XIN & XIN_Z) v += w_in * cdiv(conv<C>::from(b[f]), op.diag(f, j0, j1, j2));
+    if (XIN & XIN_Z) v += w_in * jdiv(conv<C>::from(b[f]), op.diag(f, j0, j1, j2));
     if (XIN & XIN_E) v += prolong_lds<DIM>(es, ex, ey, c0, c1, c2, j0, j1, j2);
     if (!inside(g, i0, i1, i2)) v = mk((R)0, (R)0);
     if ((int)threadIdx.x + 256 * it < tot) xs[k] = v;
@@ -228,8 +243,44 @@ __global__ void __launch_bounds__(256) k_sweep(Op op, const typename Op::C* __re
     bo[it] = conv<C>::from(b[f]);
     Do[it] = op.diag(f, i0, i1, i2);
   }
-  if (XIN & XIN_E) __syncthreads();
-  stage_xin<DIM, XIN, SX, SY, SZ>(op, x, b, w_in, es, EX, EY, c0, c1, c2, s0, s1, s2, xs);
+  constexpr int STOT = SX * SY * SZ, SIT = (STOT + 255) / 256;
+  if ((XIN & XIN_E) && SIT <= 4) {
+    // the staged nodes' inputs are loaded before the barrier that publishes e, so one
+    // memory round trip serves the block
+    typename Op::C rx[SIT];
+    CB rb[SIT];
+    typename Op::Aux ra[SIT];
+#pragma unroll
+    for (int it = 0; it < SIT; ++it) {
+      const int k = min((int)threadIdx.x + 256 * it, STOT - 1);
+      const int a = k % SX, q = k / SX;
+      int j0 = s0 + a, j1 = s1 + q % SY, j2 = s2 + q / SY;
+      clamp_node(g, j0, j1, j2);
+      const long long f = flat(g, j0, j1, j2);
+      if (XIN & XIN_X) rx[it] = x[f];
+      if (XIN & XIN_Z) {
+        rb[it] = b[f];
+        ra[it] = op.aux(f);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < SIT; ++it) {
+      const int k = min((int)threadIdx.x + 256 * it, STOT - 1);
+      const int a = k % SX, q = k / SX;
+      const int i0 = s0 + a, i1 = s1 + q % SY, i2 = s2 + q / SY;
+      int j0 = i0, j1 = i1, j2 = i2;
+      clamp_node(g, j0, j1, j2);
+      C v = prolong_lds<DIM>(es, EX, EY, c0, c1, c2, j0, j1, j2);
+      if (XIN & XIN_X) v += rx[it];
+      if (XIN & XIN_Z) v += w_in * jdiv(conv<C>::from(rb[it]), op.diag_aux(ra[it], j0, j1, j2));
+      if (!inside(g, i0, i1, i2)) v = mk((R)0, (R)0);
+      if ((int)threadIdx.x + 256 * it < STOT) xs[k] = v;
+    }
+  } else {
+    if (XIN & XIN_E) __syncthreads();
+    stage_xin<DIM, XIN, SX, SY, SZ>(op, x, b, w_in, es, EX, EY, c0, c1, c2, s0, s1, s2, xs);
+  }
   __syncthreads();
 #pragma unroll
   for (int it = 0; it < NOUT; ++it) {
@@ -240,7 +291,7 @@ __global__ void __launch_bounds__(256) k_sweep(Op op, const typename Op::C* __re
     const long long f = flat(g, i0, i1, i2);
     const int kk = (a + 1) + SX * ((q % TY + 1) + SY * (DIM == 3 ? q / TY + 1 : 0));
     const C r = bo[it] - op.ax(xs, kk, SX, SX * SY, f, Do[it]);
-    out[f] = conv<CO>::from(xs[kk] + w * cdiv(r, Do[it]));
+    out[f] = conv<CO>::from(xs[kk] + w * jdiv(r, Do[it]));
   }
 }
 

@@ -10,6 +10,28 @@ enum : int { XIN_X = 1, XIN_Z = 2, XIN_E = 4 };
 
 // ----------------------------- level 1 -------------------------------------
 // complex coefficient c = s * m * (1 - i sigma) and diagonal 2d/h^2 - c
+// sigma of the absorbing layer in the arithmetic of the operator: the FP32 cycle evaluates
+// it in FP32 (one FP32 division per axis inside a layer instead of an FP64 one)
+template <typename R>
+__device__ __forceinline__ R layer_sigma_r(const FineOp& op, int i0, int i1, int i2) {
+  if (sizeof(R) == 8) return (R)layer_sigma(op, i0, i1, i2);
+  const int ii[3] = {i0, i1, i2};
+  float s = 0.f;
+  for (int a = 0; a < op.g.dim; ++a) {
+    const int lo = op.layer[a][0], hi = op.layer[a][1], i = ii[a];
+    if (lo > 0 && i < lo) {
+      const float t = (float)(lo - i) / (float)lo;
+      s += t * t;
+    }
+    const int th = op.g.n[a] - hi;
+    if (hi > 0 && i > th) {
+      const float t = (float)(i - th) / (float)hi;
+      s += t * t;
+    }
+  }
+  return (R)((float)op.sigma_max * s);
+}
+
 template <typename R>
 struct L1 {
   typedef typename cplx<R>::type C;
@@ -17,18 +39,20 @@ struct L1 {
   C s;                 // (1 - i beta) omega^2 (times alpha^2 for a shifted operator)
   const R* m;          // squared slowness
   int conj;            // 1: coefficients of conj(H) (the adjoint, H being complex symmetric)
-  __device__ __forceinline__ C coef(long long f, int i0, int i1, int i2) const {
-    R sig = (R)layer_sigma(op, i0, i1, i2);
-    R mm = m[f];
+  // the coefficient and the diagonal from the node's squared slowness mm = m[f]
+  __device__ __forceinline__ C coef_m(R mm, int i0, int i1, int i2) const {
+    R sig = layer_sigma_r<R>(op, i0, i1, i2);
     C c = mk(mm, -mm * sig);        // m (1 - i sigma)
     C r = s * c;
     if (conj) r.y = -r.y;
     return r;
   }
-  __device__ __forceinline__ C diag(long long f, int i0, int i1, int i2) const {
-    C c = coef(f, i0, i1, i2);
+  __device__ __forceinline__ C diag_m(R mm, int i0, int i1, int i2) const {
+    C c = coef_m(mm, i0, i1, i2);
     return mk((R)(2.0 * op.g.dim * op.inv_h2) - c.x, -c.y);
   }
+  __device__ __forceinline__ C coef(long long f, int i0, int i1, int i2) const { return coef_m(m[f], i0, i1, i2); }
+  __device__ __forceinline__ C diag(long long f, int i0, int i1, int i2) const { return diag_m(m[f], i0, i1, i2); }
 };
 
 // ----------------------------- level 2 -------------------------------------
