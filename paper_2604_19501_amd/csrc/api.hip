@@ -387,12 +387,12 @@ size_t carve(helm_ctx* c, void* ws) {
   d.child_map_off = cv.take<long long>(std::max<size_t>(1, P.child_map_off.size()));
   {
     size_t mx = 1;
-    size_t nc = 1;     // pivot candidates of the multi-work-group panels: fronts x row blocks of 64
+    size_t nc = 1;     // pivot candidates of the multi-work-group panels: fronts x row blocks of 32
     for (auto& h : P.by_height) {
       mx = std::max(mx, h.size());
       int mf = 0;
       for (int t : h) mf = std::max(mf, P.fronts[t].nF);
-      nc = std::max(nc, h.size() * (size_t)((mf + 63) / 64));
+      nc = std::max(nc, h.size() * (size_t)((mf + 31) / 32));
     }
     d.swp = cv.take<int>((size_t)ND_KBMAX * mx);
     d.cand = cv.take<PivCand>(nc);

@@ -231,7 +231,7 @@ __global__ void __launch_bounds__(NT) k_nd_panel_reg(const NDFrontDev* __restric
 //                  block's candidate for the next pivot column
 // Arithmetic and pivot choice are those of the single-work-group exchange, so the
 // factors do not depend on which path a front takes.
-#define PROWS 64
+#define PROWS 32
 __device__ __forceinline__ void cand_argmax(double v, int i, double* sv, int* si, int nt) {
   // block-wide (nt threads) argmax with the lower index on ties; result in sv[0], si[0]
   for (int o = 32; o > 0; o >>= 1) {
