@@ -624,17 +624,23 @@ __device__ __forceinline__ NDSeg uniform_seg(NDSeg a) {
   return b;
 }
 
+// A segment of at most 16 (32) rows spreads 4 (2) groups of 16 columns over the wavefront:
+// lane l takes row l mod g and columns k0 + 16 (l / g) .. + 16, g = lanes per group.
+__device__ __forceinline__ int seg_group(const NDSeg& sg) { return sg.nr <= 16 ? 16 : sg.nr <= 32 ? 32 : 64; }
+
 // the 16 matrix entries of a segment for one lane (row and column indices clamped)
 template <typename C>
 __device__ __forceinline__ void load_seg(const C* __restrict__ M, const NDSeg& sg, int lane, C* m) {
-  const C* col = M + sg.m_off + sg.r0 + min(lane, sg.nr - 1);
+  const int gs = seg_group(sg), kq = sg.k0 + (lane / gs) * 16;
+  const C* col = M + sg.m_off + sg.r0 + min(lane & (gs - 1), sg.nr - 1);
 #pragma unroll
-  for (int kk = 0; kk < 16; ++kk) m[kk] = col[(long long)min(sg.k0 + kk, sg.k1 - 1) * sg.ld];
+  for (int kk = 0; kk < 16; ++kk) m[kk] = col[(long long)min(kq + kk, sg.k1 - 1) * sg.ld];
 }
 
 // Tree-block substitution: one work-group per subtree task, one stage per level.
 //   gathers:  vec[slot] = src[rid] (+ children's updates)           all threads
 //   segments: partial products of <= 64 rows over <= 16 columns       one wavefront, two at a time
+//             (<= 32 rows over <= 32 columns, <= 16 rows over <= 64 columns)
 //   outputs:  sum of a row block's partials, write x or the update    one wavefront each
 // forward (FWD = 1): M = L = [A^-1; C A^-1] (ld nF), src = r;  rows < nS give x_S = g_S,
 //                    rows >= nS the update v_B - C A^-1 f_S of the parent
@@ -742,10 +748,15 @@ __global__ void __launch_bounds__(1024) k_nd_tree(const NDTask* __restrict__ tas
         sg = uniform_seg(lsg[s0]);
         load_seg(M, sg, lane, mv);
       }
+      const int gs = seg_group(sg), kq = sg.k0 + (lane / gs) * 16;
       C acc = mk((R)0, (R)0);
 #pragma unroll
       for (int kk = 0; kk < 16; ++kk)
-        if (sg.k0 + kk < sg.k1) acc += cmul_conj(mv[kk], work[sg.vslot + sg.k0 + kk], conj);
+        if (kq + kk < sg.k1) acc += cmul_conj(mv[kk], work[sg.vslot + kq + kk], conj);
+      for (int o = gs; o < 64; o <<= 1) {      // sum the column groups (every lane gets its row's sum)
+        acc.x += __shfl_xor(acc.x, o, 64);
+        acc.y += __shfl_xor(acc.y, o, 64);
+      }
       work[sg.pslot + lane] = acc;
     }
     // prefetch this wavefront's first segment of the next stage

@@ -291,7 +291,7 @@ void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int root_merge, int e
   // work-group).  The cuts minimise a cost model of launch and level latencies and of
   // the bandwidth one work-group (tree blocks) or the whole chip (multi-block) can pull.
   const int H = plan.max_height;
-  const int KS = 16;                                   // k range of one segment
+  const int KS = 16;                                   // k range of one segment of 64 rows
   auto nparts = [&](int K) { return std::max(1, (K + KS - 1) / KS); };
   auto al16 = [](long long v) { return (v + 15) / 16 * 16; };
   // LDS of one front in a stage: work entries (vector + partials) and schedule bytes
@@ -526,17 +526,19 @@ void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int root_merge, int e
                 L.gath.push_back(g);
               }
             }
-            const int np = nparts(K);
             for (int r0 = 0; r0 < R; r0 += 64) {
               const int nr = std::min(64, R - r0);
+              // a wavefront covers 64 rows x 16 columns, 32 x 32 or 16 x 64
+              const int kse = nr <= 16 ? 4 * KS : nr <= 32 ? 2 * KS : KS;
+              const int np = std::max(1, (K + kse - 1) / kse);
               for (int p = 0; p < np; ++p) {
                 NDSeg sg;
                 sg.m_off = dir == 0 ? f.L_off : f.W_off;
                 sg.ld = dir == 0 ? f.nF : f.nS;
                 sg.r0 = r0;
                 sg.nr = nr;
-                sg.k0 = p * KS;
-                sg.k1 = std::min(K, (p + 1) * KS);
+                sg.k0 = p * kse;
+                sg.k1 = std::min(K, (p + 1) * kse);
                 sg.vslot = vs;
                 sg.pslot = ps + 64 * p;
                 sg.pad = 0;
