@@ -169,6 +169,10 @@ struct NDAsm {          // F[row][col] += coef[cidx]
 struct NDItem {         // one work item of a multi-block launch: rows [r0, r1) of a front
   int front, r0, r1;
   int stage;
+  // the front's fields the work item needs (copied, so a work-group reads one record)
+  int nS, nF, nB, pad;
+  long long m_off;      // L_off (forward) or W_off (backward)
+  long long idx_off, inv_off, upd_off;
 };
 
 // Tree-block launches: one work-group walks the fronts of a subtree level by level.

@@ -577,9 +577,10 @@ __device__ __forceinline__ C cmul_conj(C a, C x, int conj) {   // (conj? conj(a)
 
 
 // f_S (and v_B) entry i of front f: right-hand side on S plus the children's updates
-// (contribution list cptr[i] .. cptr[i+1] of absolute indices into the update pool)
-template <typename C>
-__device__ __forceinline__ C gather_entry(const NDFrontDev& f, const int* __restrict__ cptr,
+// (contribution list cptr[i] .. cptr[i+1] of absolute indices into the update pool); F is
+// the front record or a work item carrying its fields
+template <typename C, typename F>
+__device__ __forceinline__ C gather_entry(const F& f, const int* __restrict__ cptr,
                                           const int* __restrict__ cidx, const int* __restrict__ id,
                                           const C* __restrict__ upd, const C* __restrict__ r, int i) {
   typedef decltype(r[0].x) R;
@@ -797,18 +798,31 @@ __global__ void __launch_bounds__(1024) k_nd_tree(const NDTask* __restrict__ tas
 
 // rows [r0, r1) (at most 16) of a big front: 16 row lanes x 16 k-splits per work-group,
 // partial sums reduced through LDS; consecutive threads read consecutive rows of one column.
+// gemv16_load issues the thread's first 16 matrix entries, which do not depend on v, so
+// callers start it before gathering v; gemv16_finish does the rest.
 template <typename C>
-__device__ __forceinline__ C gemv_block16(const C* __restrict__ M, long long ld, int r0, int r1, int K,
-                                          const C* __restrict__ v, int conj, C* red) {
+__device__ __forceinline__ void gemv16_load(const C* __restrict__ M, long long ld, int r0, int r1, int K, C* m) {
+  const int row = threadIdx.x & 15, ks = threadIdx.x >> 4;
+  const int kq = (K + 15) / 16, kb = ks * kq, ke = min(K, kb + kq);
+  const C* col = M + min(r0 + row, r1 - 1);
+#pragma unroll
+  for (int q = 0; q < 16; ++q) m[q] = col[(long long)max(0, min(kb + q, ke - 1)) * ld];
+}
+template <typename C>
+__device__ __forceinline__ C gemv16_finish(const C* __restrict__ M, long long ld, int r0, int r1, int K,
+                                           const C* __restrict__ v, int conj, C* red, const C* m0) {
   typedef decltype(v[0].x) R;
   const int row = threadIdx.x & 15, ks = threadIdx.x >> 4;
   const int i = r0 + row;
   const int kq = (K + 15) / 16, kb = ks * kq, ke = min(K, kb + kq);
   C acc = mk((R)0, (R)0);
   if (i < r1 && kb < ke) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+      if (kb + q < ke) acc += cmul_conj(m0[q], v[kb + q], conj);
     // 16 matrix entries in flight per thread: load all (clamped), then accumulate
     const C* col = M + i;
-    for (int k = kb; k < ke; k += 16) {
+    for (int k = kb + 16; k < ke; k += 16) {
       C m[16];
 #pragma unroll
       for (int q = 0; q < 16; ++q) m[q] = col[(long long)min(k + q, ke - 1) * ld];
@@ -839,16 +853,16 @@ __global__ void __launch_bounds__(256) k_nd_fwd_big(const NDFrontDev* __restrict
   r += blockIdx.y * rh.vec;
   x += blockIdx.y * rh.vec;
   C* vec = gvec ? gvec + blockIdx.y * rh.gvec + (long long)blockIdx.x * cap : (C*)smem;
-  const NDItem item = items[blockIdx.x];
-  const NDFrontDev f = fr[item.front];
+  const NDItem f = items[blockIdx.x];
   const int* id = idx + f.idx_off;
+  C m0[16];
+  gemv16_load(Lp + f.m_off, f.nF, f.r0, f.r1, f.nS, m0);
   for (int i = threadIdx.x; i < f.nS; i += 256) vec[i] = gather_entry(f, cptr, cidx, id, upd, r, i);
-  for (int i = max(item.r0, f.nS) + threadIdx.x; i < item.r1; i += 256)
-    vec[i] = gather_entry(f, cptr, cidx, id, upd, r, i);
+  for (int i = max(f.r0, f.nS) + threadIdx.x; i < f.r1; i += 256) vec[i] = gather_entry(f, cptr, cidx, id, upd, r, i);
   __syncthreads();
-  C acc = gemv_block16(Lp + f.L_off, f.nF, item.r0, item.r1, f.nS, vec, conj, red);
-  const int i = item.r0 + threadIdx.x;
-  if (threadIdx.x < 16 && i < item.r1) {
+  C acc = gemv16_finish(Lp + f.m_off, f.nF, f.r0, f.r1, f.nS, vec, conj, red, m0);
+  const int i = f.r0 + threadIdx.x;
+  if (threadIdx.x < 16 && i < f.r1) {
     if (i < f.nS)
       x[id[i]] = acc;
     else
@@ -865,14 +879,16 @@ __global__ void __launch_bounds__(256) k_nd_bwd_big(const NDFrontDev* __restrict
   __shared__ C red[256];
   x += blockIdx.y * rh.vec;
   C* vec = gvec ? gvec + blockIdx.y * rh.gvec + (long long)blockIdx.x * cap : (C*)smem;
-  const NDItem item = items[blockIdx.x];
-  const NDFrontDev f = fr[item.front];
+  const NDItem f = items[blockIdx.x];
   const int* id = idx + f.idx_off;
+  C m0[16];
+  gemv16_load(Wp + f.m_off, f.nS, f.r0, f.r1, f.nB, m0);
+  const int i = f.r0 + threadIdx.x;
+  const int di = threadIdx.x < 16 && i < f.r1 ? id[i] : 0;
   for (int j = threadIdx.x; j < f.nB; j += 256) vec[j] = x[id[f.nS + j]];
   __syncthreads();
-  C acc = gemv_block16(Wp + f.W_off, f.nS, item.r0, item.r1, f.nB, vec, conj, red);
-  const int i = item.r0 + threadIdx.x;
-  if (threadIdx.x < 16 && i < item.r1) x[id[i]] = x[id[i]] + acc;
+  C acc = gemv16_finish(Wp + f.m_off, f.nS, f.r0, f.r1, f.nB, vec, conj, red, m0);
+  if (threadIdx.x < 16 && i < f.r1) x[di] = x[di] + acc;
 }
 
 // ---- split-K launches (kind 3) -------------------------------------------

@@ -648,7 +648,8 @@ void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int root_merge, int e
       for (int t : plan.by_height[h]) {
         const NDFrontDev& f = plan.fronts[t];
         for (int r = 0; r < f.nF; r += rows_chunk) {
-          fl.items.push_back({t, r, std::min(f.nF, r + rows_chunk), h});
+          fl.items.push_back({t, r, std::min(f.nF, r + rows_chunk), h, f.nS, f.nF, f.nB, 0, f.L_off, f.idx_off,
+                              f.inv_off, f.upd_off});
           fl.task_off.push_back((int)fl.items.size());
         }
         fl.max_rows_vec = std::max(fl.max_rows_vec, f.nF);
@@ -661,7 +662,8 @@ void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int root_merge, int e
         const NDFrontDev& f = plan.fronts[t];
         if (f.nB > 0)          // a front without boundary has nothing to back-substitute
           for (int r = 0; r < f.nS; r += rows_chunk) {
-            bl.items.push_back({t, r, std::min(f.nS, r + rows_chunk), h});
+            bl.items.push_back({t, r, std::min(f.nS, r + rows_chunk), h, f.nS, f.nF, f.nB, 0, f.W_off, f.idx_off,
+                                f.inv_off, f.upd_off});
             bl.task_off.push_back((int)bl.items.size());
           }
         bl.max_rows_vec = std::max(bl.max_rows_vec, f.nB);
