@@ -689,6 +689,18 @@ __global__ void __launch_bounds__(1024) k_nd_tree(const NDTask* __restrict__ tas
   copy_lds(lo, outs + T.o0, sizeof(NDOut) * no);
   copy_lds(ldst, dst + T.d0, sizeof(int) * nd);
   __syncthreads();
+  const int nw = blockDim.x >> 6, wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  // prefetching holds a second segment in registers: FP32 only (FP64 would spill).  The
+  // first stage's segments are requested together with the launch-invariant inputs below.
+  constexpr bool PF = sizeof(C) == 8;
+  NDSeg psg;
+  C pm[PF ? 16 : 1];
+  bool have_pf = false;
+  if (PF && nst > 0 && lst[0].s0 + wv < lst[0].s1) {
+    psg = uniform_seg(lsg[lst[0].s0 + wv]);
+    load_seg(M, psg, lane, pm);
+    have_pf = true;
+  }
   // one round trip for every stage's inputs that do not change during the launch: r
   // (forward); x of fronts above the task and x_S before the update (backward)
   for (int e = threadIdx.x; e < ng; e += blockDim.x) {
@@ -699,17 +711,6 @@ __global__ void __launch_bounds__(1024) k_nd_tree(const NDTask* __restrict__ tas
   if (!FWD)
     for (int e = threadIdx.x; e < nd; e += blockDim.x) lxg[e] = x[max(ldst[e], 0)];
   __syncthreads();
-  const int nw = blockDim.x >> 6, wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  // prefetching holds a second segment in registers: FP32 only (FP64 would spill)
-  constexpr bool PF = sizeof(C) == 8;
-  NDSeg psg;
-  C pm[PF ? 16 : 1];
-  bool have_pf = false;
-  if (PF && nst > 0 && lst[0].s0 + wv < lst[0].s1) {
-    psg = uniform_seg(lsg[lst[0].s0 + wv]);
-    load_seg(M, psg, lane, pm);
-    have_pf = true;
-  }
   for (int st = 0; st < nst; ++st) {
     const NDStage S = lst[st];
     // loads are unconditional (clamped indices, zero weights) so that a wavefront keeps
