@@ -593,19 +593,39 @@ __device__ __forceinline__ C gather_entry(const F& f, const int* __restrict__ cp
 
 __device__ __forceinline__ size_t al16(size_t v) { return (v + 15) & ~(size_t)15; }
 
-// copy n bytes (a multiple of 4) from global memory to LDS with the whole work-group;
-// four independent loads per thread and round before the stores
-__device__ __forceinline__ void copy_lds(void* dst, const void* src, size_t n) {
-  const int* s = (const int*)src;
-  int* d = (int*)dst;
-  const int nw = (int)(n / 4), bd = blockDim.x;
-  for (int w = threadIdx.x; w < nw; w += 4 * bd) {
-    int v[4];
+// the five parts of a task's schedule copied to LDS in one pass: eight independent loads
+// per thread and round before the stores (word w of the concatenation belongs to part r
+// when end[r - 1] <= w < end[r])
+struct LdsCopy5 {
+  const int *s0, *s1, *s2, *s3, *s4;
+  int *d0, *d1, *d2, *d3, *d4;
+  int end[5];
+};
+__device__ __forceinline__ void copy_lds5(const LdsCopy5& c) {
+  const int tot = c.end[4], bd = blockDim.x;
+  for (int w0 = threadIdx.x; w0 < tot; w0 += 8 * bd) {
+    int v[8];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) v[q] = s[min(w + q * bd, nw - 1)];
+    for (int q = 0; q < 8; ++q) {
+      const int w = min(w0 + q * bd, tot - 1);
+      const int* sp = w < c.end[0] ? c.s0 + w
+                    : w < c.end[1] ? c.s1 + (w - c.end[0])
+                    : w < c.end[2] ? c.s2 + (w - c.end[1])
+                    : w < c.end[3] ? c.s3 + (w - c.end[2])
+                                   : c.s4 + (w - c.end[3]);
+      v[q] = *sp;
+    }
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-      if (w + q * bd < nw) d[w + q * bd] = v[q];
+    for (int q = 0; q < 8; ++q) {
+      const int w = w0 + q * bd;
+      if (w >= tot) continue;
+      int* dp = w < c.end[0] ? c.d0 + w
+              : w < c.end[1] ? c.d1 + (w - c.end[0])
+              : w < c.end[2] ? c.d2 + (w - c.end[1])
+              : w < c.end[3] ? c.d3 + (w - c.end[2])
+                             : c.d4 + (w - c.end[3]);
+      *dp = v[q];
+    }
   }
 }
 
@@ -683,11 +703,39 @@ __global__ void __launch_bounds__(1024) k_nd_tree(const NDTask* __restrict__ tas
   C* lxg = (C*)p;                      // backward: x_S before the update, per output row
   p += al16(sizeof(C) * (FWD ? 0 : nd));
   C* work = (C*)p;
-  copy_lds(lst, stages + T.st0, sizeof(NDStage) * nst);
-  copy_lds(lg, gath + T.g0, sizeof(NDGather) * ng);
-  copy_lds(lsg, segs + T.s0, sizeof(NDSeg) * nsg);
-  copy_lds(lo, outs + T.o0, sizeof(NDOut) * no);
-  copy_lds(ldst, dst + T.d0, sizeof(int) * nd);
+  // the launch-invariant inputs of the first 2 x blockDim gathers (and backward outputs)
+  // take their indices from the schedule in global memory, so their loads overlap the copy
+  const int bd = blockDim.x, tid = threadIdx.x;
+  C pre[2], prx[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    pre[j] = prx[j] = mk((R)0, (R)0);
+    if (ng > 0) {
+      const NDGather g = gath[T.g0 + min(tid + j * bd, ng - 1)];
+      const C v = src[max(g.rid, 0)];
+      pre[j] = g.rid >= 0 && (FWD || g.u0 == -1) ? v : mk((R)0, (R)0);
+    }
+    if (!FWD && nd > 0) prx[j] = x[max(dst[T.d0 + min(tid + j * bd, nd - 1)], 0)];
+  }
+  {
+    LdsCopy5 c;
+    c.s0 = (const int*)(stages + T.st0);
+    c.s1 = (const int*)(gath + T.g0);
+    c.s2 = (const int*)(segs + T.s0);
+    c.s3 = (const int*)(outs + T.o0);
+    c.s4 = dst + T.d0;
+    c.d0 = (int*)lst;
+    c.d1 = (int*)lg;
+    c.d2 = (int*)lsg;
+    c.d3 = (int*)lo;
+    c.d4 = ldst;
+    c.end[0] = (int)(sizeof(NDStage) / 4) * nst;
+    c.end[1] = c.end[0] + (int)(sizeof(NDGather) / 4) * ng;
+    c.end[2] = c.end[1] + (int)(sizeof(NDSeg) / 4) * nsg;
+    c.end[3] = c.end[2] + (int)(sizeof(NDOut) / 4) * no;
+    c.end[4] = c.end[3] + nd;
+    copy_lds5(c);
+  }
   __syncthreads();
   const int nw = blockDim.x >> 6, wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   // prefetching holds a second segment in registers: FP32 only (FP64 would spill).  The
@@ -701,15 +749,20 @@ __global__ void __launch_bounds__(1024) k_nd_tree(const NDTask* __restrict__ tas
     load_seg(M, psg, lane, pm);
     have_pf = true;
   }
-  // one round trip for every stage's inputs that do not change during the launch: r
-  // (forward); x of fronts above the task and x_S before the update (backward)
-  for (int e = threadIdx.x; e < ng; e += blockDim.x) {
+  // every stage's inputs that do not change during the launch: r (forward); x of fronts
+  // above the task and x_S before the update (backward)
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    if (tid + j * bd < ng) lsrc[tid + j * bd] = pre[j];
+    if (!FWD && tid + j * bd < nd) lxg[tid + j * bd] = prx[j];
+  }
+  for (int e = tid + 2 * bd; e < ng; e += bd) {
     const NDGather g = lg[e];
     const C v = src[max(g.rid, 0)];
     lsrc[e] = g.rid >= 0 && (FWD || g.u0 == -1) ? v : mk((R)0, (R)0);
   }
   if (!FWD)
-    for (int e = threadIdx.x; e < nd; e += blockDim.x) lxg[e] = x[max(ldst[e], 0)];
+    for (int e = tid + 2 * bd; e < nd; e += bd) lxg[e] = x[max(ldst[e], 0)];
   __syncthreads();
   for (int st = 0; st < nst; ++st) {
     const NDStage S = lst[st];
