@@ -162,6 +162,14 @@ int helm_setup_batched(int n_inst, const helm_grid* grids, const double* const* 
                        const double* omega, const helm_shift* shift, const helm_mg* mg,
                        int max_rhs, void* ws, size_t ws_bytes, void* stream, helm_ctx** out);
 
+/* One instance (as helm_workspace_bytes / helm_setup) that can also solve up to
+ * min(max_rhs, 16) right-hand sides in lock-step through helm_solve_batched with every
+ * inst_of_rhs[k] = 0, e.g. the sources of one medium (Sec. 5).  helm_refactor, helm_solve,
+ * helm_grad_m and the other single-instance calls work on it as on a helm_setup context. */
+int helm_workspace_bytes_multi(const helm_grid* grid, const helm_mg* mg, int max_rhs, size_t* bytes);
+int helm_setup_multi(const helm_grid* grid, const double* slowness, double omega, const helm_shift* shift,
+                     const helm_mg* mg, int max_rhs, void* ws, size_t ws_bytes, void* stream, helm_ctx** out);
+
 /* Solve n_rhs systems; rhs k belongs to instance inst_of_rhs[k].
  *   rhs, x: host arrays of n_rhs device pointers (c128[N1(inst)] each; x holds the initial
  *           guess and receives the solution; rhs[k] != x[k])

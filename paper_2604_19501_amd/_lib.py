@@ -80,6 +80,9 @@ _SIG = {
     "helm_level_size": (C.c_longlong, [P, C.c_int, C.c_int]),
     "helm_get_info": (C.c_int, [P, C.POINTER(C.c_longlong), C.c_int]),
     "helm_get_instance_info": (C.c_int, [P, C.c_int, C.POINTER(C.c_longlong), C.c_int]),
+    "helm_workspace_bytes_multi": (C.c_int, [C.POINTER(Grid), C.POINTER(MG), C.c_int, C.POINTER(C.c_size_t)]),
+    "helm_setup_multi": (C.c_int, [C.POINTER(Grid), P, C.c_double, C.POINTER(Shift), C.POINTER(MG), C.c_int, P,
+                                   C.c_size_t, P, C.POINTER(P)]),
     "helm_get_coefficients": (C.c_int, [P, C.c_int, P]),
 }
 for _name, (_res, _args) in _SIG.items():

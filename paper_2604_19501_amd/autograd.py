@@ -11,8 +11,10 @@ sources q_s, receivers given as flat node indices (sampling operator P) and data
 The backward pass solves the adjoint systems H^H lambda_s = P^T (P u_s - d_s) with the
 same preconditioner on the conjugate-transpose operator (op = HELM_OP_C) and forms
 dL/dm_j = sum_s omega^2 Re(conj(lambda_s[j]) (1 - i sigma_j) u_s[j]) in the library's
-gradient kernel.  Every solve and the gradient run in libhelm; this module only
-orders the calls.
+gradient kernel.  A solver built with max_rhs > 1 solves the sources, and then the
+adjoint systems, in lock-step groups (Solver.solve_many); each solution equals the one of
+a separate solve.  Every solve and the gradient run in libhelm; this module only orders
+the calls.
 """
 from __future__ import annotations
 
@@ -24,16 +26,30 @@ from . import _lib as L
 from .solver import Solver
 
 
+def _solve_all(solver: Solver, rhs, tol, max_iter, op, what):
+    """solutions of op(H) x = rhs[k]: lock-step groups when the solver has the capacity"""
+    if getattr(solver, "max_rhs", 1) > 1 and len(rhs) > 1:
+        xs, infos = solver.solve_many(rhs, tol=tol, max_iter=max_iter, op=op)
+    else:
+        xs, infos = [], []
+        for q in rhs:
+            x, info = solver.solve(q, tol=tol, max_iter=max_iter, op=op)
+            xs.append(x)
+            infos.append(info)
+    for k, info in enumerate(infos):
+        if info["status"] != 0:
+            raise L.HelmError(info["status"], "%s solve %d" % (what, k))
+    return xs
+
+
 class _Misfit(torch.autograd.Function):
     @staticmethod
     def forward(ctx, m, solver: Solver, sources, receivers, data, tol, max_iter):
         solver.refactor(slowness=torch.sqrt(m.detach()).to(torch.float64))
         us, res = [], []
         loss = torch.zeros((), dtype=torch.float64, device=m.device)
-        for s, q in enumerate(sources):
-            u, info = solver.solve(q, tol=tol, max_iter=max_iter)
-            if info["status"] != 0:
-                raise L.HelmError(info["status"], "forward solve %d" % s)
+        sols = _solve_all(solver, sources, tol, max_iter, L.HELM_OP_N, "forward")
+        for s, u in enumerate(sols):
             r = u[receivers] - data[s]
             loss = loss + 0.5 * torch.sum(r.real ** 2 + r.imag ** 2)
             us.append(u)
@@ -45,14 +61,12 @@ class _Misfit(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gout):
         solver = ctx.solver
-        lams = []
-        for s, r in enumerate(ctx.res):
+        rhss = []
+        for r in ctx.res:
             rhs = torch.zeros(ctx.N, dtype=torch.complex128, device=r.device)
             rhs.index_put_((ctx.receivers,), r, accumulate=True)
-            lam, info = solver.solve(rhs, tol=ctx.tol, max_iter=ctx.max_iter, op=L.HELM_OP_C)
-            if info["status"] != 0:
-                raise L.HelmError(info["status"], "adjoint solve %d" % s)
-            lams.append(lam)
+            rhss.append(rhs)
+        lams = _solve_all(solver, rhss, ctx.tol, ctx.max_iter, L.HELM_OP_C, "adjoint")
         g = solver.grad_m(ctx.us, lams)
         return gout * g, None, None, None, None, None, None
 

@@ -1394,6 +1394,17 @@ int helm_workspace_bytes_batched(int n_inst, const helm_grid* grids, const helm_
   return HELM_OK;
 }
 
+int helm_workspace_bytes_multi(const helm_grid* grid, const helm_mg* mg, int max_rhs, size_t* bytes) {
+  if (!grid || !mg || !bytes || max_rhs < 1) return fail(HELM_EINVAL, "bad arguments");
+  return ws_bytes_rcap(grid, mg, batch_rcap(max_rhs), bytes);
+}
+
+int helm_setup_multi(const helm_grid* grid, const double* slowness, double omega, const helm_shift* shift,
+                     const helm_mg* mg, int max_rhs, void* ws, size_t ws_bytes, void* stream, helm_ctx** out) {
+  if (max_rhs < 1) return fail(HELM_EINVAL, "max_rhs must be >= 1");
+  return setup_rcap(grid, slowness, omega, shift, mg, batch_rcap(max_rhs), ws, ws_bytes, stream, out);
+}
+
 int helm_setup_batched(int n_inst, const helm_grid* grids, const double* const* slowness, const double* omega,
                        const helm_shift* shift, const helm_mg* mg, int max_rhs, void* ws, size_t ws_bytes,
                        void* stream, helm_ctx** out) {

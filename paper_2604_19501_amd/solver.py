@@ -84,10 +84,12 @@ def workspace_bytes(n, h, layer, sigma_max, **mg_kw) -> int:
 
 
 class Solver:
-    """one medium / frequency: owns the workspace tensor and the library context."""
+    """one medium / frequency: owns the workspace tensor and the library context.  With
+    max_rhs > 1 the context can also solve up to max_rhs right-hand sides in lock-step
+    (solve_many)."""
 
     def __init__(self, n, h, slowness, omega, layer, sigma_max, alpha=1.0, alpha2=1.0, beta=0.0, cycle=2,
-                 nu=(1, 1), jacobi=0.8, cycle_prec="f32", restart=20, device="cuda:0"):
+                 nu=(1, 1), jacobi=0.8, cycle_prec="f32", restart=20, device="cuda:0", max_rhs=1):
         self.device = torch.device(device)
         self.n = tuple(int(k) for k in n)
         self.dim = len(self.n)
@@ -96,8 +98,14 @@ class Solver:
         self.mg = make_mg(cycle, nu, jacobi, cycle_prec, restart)
         self.shift = L.Shift(float(alpha), float(alpha2), float(beta))
         self.omega = float(omega)
+        self.max_rhs = int(max_rhs)
         b = C.c_size_t()
-        L.check(L.lib.helm_workspace_bytes(C.byref(self.grid), C.byref(self.mg), C.byref(b)), "helm_workspace_bytes")
+        if self.max_rhs > 1:
+            L.check(L.lib.helm_workspace_bytes_multi(C.byref(self.grid), C.byref(self.mg), self.max_rhs, C.byref(b)),
+                    "helm_workspace_bytes_multi")
+        else:
+            L.check(L.lib.helm_workspace_bytes(C.byref(self.grid), C.byref(self.mg), C.byref(b)),
+                    "helm_workspace_bytes")
         self.ws_bytes = int(b.value)
         self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
         base = self.ws.data_ptr()
@@ -107,9 +115,15 @@ class Solver:
             raise ValueError("slowness has %d entries, grid has %d nodes" % (kap.numel(), self.N))
         self._kap = kap
         ctx = C.c_void_p()
-        L.check(L.lib.helm_setup(C.byref(self.grid), C.c_void_p(kap.data_ptr()), self.omega, C.byref(self.shift),
-                                 C.byref(self.mg), C.c_void_p(self._ws_ptr), self.ws_bytes,
-                                 C.c_void_p(_stream_ptr(self.device)), C.byref(ctx)), "helm_setup")
+        if self.max_rhs > 1:
+            L.check(L.lib.helm_setup_multi(C.byref(self.grid), C.c_void_p(kap.data_ptr()), self.omega,
+                                           C.byref(self.shift), C.byref(self.mg), self.max_rhs,
+                                           C.c_void_p(self._ws_ptr), self.ws_bytes,
+                                           C.c_void_p(_stream_ptr(self.device)), C.byref(ctx)), "helm_setup_multi")
+        else:
+            L.check(L.lib.helm_setup(C.byref(self.grid), C.c_void_p(kap.data_ptr()), self.omega,
+                                     C.byref(self.shift), C.byref(self.mg), C.c_void_p(self._ws_ptr), self.ws_bytes,
+                                     C.c_void_p(_stream_ptr(self.device)), C.byref(ctx)), "helm_setup")
         self.ctx = ctx
 
     def refactor(self, slowness=None, omega=None, alpha=None, alpha2=None, beta=None):
@@ -194,6 +208,21 @@ class Solver:
         if history:
             out["history"] = [hist[i] for i in range(min(info.iterations, max_iter))]
         return x, out
+
+    def solve_many(self, rhs: Sequence, tol: float = 1e-6, max_iter: int = 500, op: int = L.HELM_OP_N):
+        """solve for every right-hand side from a zero guess, in lock-step groups of up to
+        max_rhs; each result equals solve()'s.  Returns (solutions, infos)."""
+        n = len(rhs)
+        bs = [_dev_tensor(r, torch.complex128, self.device) for r in rhs]
+        xs = [torch.zeros_like(b) for b in bs]
+        rp = (C.c_void_p * n)(*[b.data_ptr() for b in bs])
+        xp = (C.c_void_p * n)(*[x.data_ptr() for x in xs])
+        ii = (C.c_int * n)(*([0] * n))
+        infos = (L.SolveInfo * n)()
+        st = L.lib.helm_solve_batched(self.ctx, op, n, ii, rp, xp, float(tol), int(max_iter), infos, self._s())
+        L.check(st, "helm_solve_batched")
+        return xs, [dict(status=infos[k].status, iterations=infos[k].iterations,
+                         true_rel_residual=infos[k].true_rel_residual) for k in range(n)]
 
     def coefficients(self, lev: int) -> np.ndarray:
         """stored Galerkin coefficients of level 2 or 3: array (3^d, N_lev) complex128."""

@@ -6,7 +6,9 @@
 * against central finite differences of the GPU loss (step 1e-4, 20 seeded
   directions with max |v| = 1): relative agreement <= 1e-5;
 * the full-size 128^3 workload (16 sources on the top face, receivers on the whole
-  top face, zero data): finite-difference agreement on 3 directions.
+  top face, zero data, the sources solved in lock-step): finite-difference agreement on
+  3 directions;
+* lock-step source solves give the separate solves' loss and gradient bit for bit.
 """
 import numpy as np
 import pytest
@@ -52,8 +54,8 @@ def test_gradient_matches_oracle(dim, n):
     assert np.linalg.norm(g - g_ref) <= 1e-5 * np.linalg.norm(g_ref)
 
 
-def _fd_check(p, m0, src, recs, data, ndir, seed, tol_rel=1e-5):
-    s = from_problem(p, cycle_prec="f32")
+def _fd_check(p, m0, src, recs, data, ndir, seed, tol_rel=1e-5, max_rhs=1):
+    s = from_problem(p, cycle_prec="f32", max_rhs=max_rhs)
     m = torch.tensor(m0, dtype=torch.float64, device="cuda", requires_grad=True)
     loss = helmholtz_misfit(m, s, src, recs, data, tol=1e-10)
     loss.backward()
@@ -90,5 +92,25 @@ def test_gradient_full_size_workload():
     m0 = p.slowness.ravel() ** 2
     src = [torch.from_numpy(synth.point_rhs(p.n, pos)).cuda() for pos in p.sources]
     data = [torch.zeros(len(rec), dtype=torch.complex128, device="cuda") for _ in p.sources]
-    w = _fd_check(p, m0, src, torch.from_numpy(rec).cuda(), data, 3, 13)
-    print("worst relative FD mismatch at 128^3: %.2e" % w)
+    w = _fd_check(p, m0, src, torch.from_numpy(rec).cuda(), data, 3, 13, max_rhs=16)
+    print("worst relative FD mismatch at 128^3 (lock-step sources): %.2e" % w)
+
+
+def test_lockstep_misfit_equals_separate_solves():
+    """a solver with room for 4 right-hand sides in lock-step (max_rhs = 4, groups of 4 and
+    of 1 for 5 sources) gives the same loss and gradient, bit for bit, as separate solves"""
+    p, m_ref, m0, Q, rec = _setup(3, 16, 5, seed=21)
+    D = 0.5 * np.ones((len(rec), 5), np.complex128)
+    src = [torch.from_numpy(Q[:, k]).cuda() for k in range(5)]
+    data = [torch.from_numpy(D[:, k]).cuda() for k in range(5)]
+    recs = torch.from_numpy(rec).cuda()
+    out = []
+    for mr in (1, 4):
+        s = from_problem(p, cycle_prec="f32", max_rhs=mr)
+        m = torch.tensor(m0, dtype=torch.float64, device="cuda", requires_grad=True)
+        loss = helmholtz_misfit(m, s, src, recs, data, tol=1e-10)
+        loss.backward()
+        out.append((loss.detach().clone(), m.grad.detach().clone()))
+        s.close()
+    assert torch.equal(out[0][0], out[1][0])
+    assert torch.equal(out[0][1], out[1][1])
