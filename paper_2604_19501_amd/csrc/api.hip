@@ -1,5 +1,6 @@
 // C ABI of libhelm: validation, workspace layout, setup, cycle and FGMRES drivers.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -1456,7 +1457,16 @@ int helm_solve_batched(helm_ctx* ctx, int op, int n_rhs, const int* inst_of_rhs,
   hipStream_t s = (hipStream_t)stream;
   // instances are independent: they run concurrently on library-owned streams (one host
   // worker per stream); an instance's right-hand sides are solved in lock-step groups of
-  // up to its capacity, one group after the other on its stream
+  // up to its capacity, one group after the other on its stream.  Workers take the next
+  // instance when they finish one, larger grids first, so that the short solves fill in
+  // at the end.
+  std::stable_sort(busy.begin(), busy.end(), [&](int a, int b) {
+    const long long na = ctx->sub.empty() ? ctx->g1.tot : ctx->sub[a]->g1.tot;
+    const long long nb = ctx->sub.empty() ? ctx->g1.tot : ctx->sub[b]->g1.tot;
+    return na > nb;
+  });
+  std::atomic<size_t> next_inst{0};
+  std::vector<char> taken(busy.size(), 0);
   const int nst = std::max(1, std::min(env_int("HELM_BATCH_STREAMS", 8), (int)busy.size()));
   std::vector<int> status(n_rhs, HELM_OK);
   std::vector<std::string> errs(nst);
@@ -1479,11 +1489,12 @@ int helm_solve_batched(helm_ctx* ctx, int op, int n_rhs, const int* inst_of_rhs,
         const hipStream_t sw = ctx->bstreams[w];
         if (hipSetDevice(dev) != hipSuccess) {
           errs[w] = "hipSetDevice failed in a batch worker";
-          for (size_t q = w; q < busy.size(); q += nst)
-            for (int k : by[busy[q]]) status[k] = HELM_EDEVICE;
           return;
         }
-        for (size_t q = w; q < busy.size(); q += nst) {
+        for (;;) {
+          const size_t q = next_inst.fetch_add(1);
+          if (q >= busy.size()) break;
+          taken[q] = 1;
           const int i = busy[q];
           helm_ctx* c = ctx->sub.empty() ? ctx : ctx->sub[i];
           const std::vector<int>& ks = by[i];
@@ -1534,6 +1545,9 @@ int helm_solve_batched(helm_ctx* ctx, int op, int n_rhs, const int* inst_of_rhs,
         }
       });
     for (auto& t : pool) t.join();
+    for (size_t q = 0; q < busy.size(); ++q)      // left over by workers that could not start
+      if (!taken[q])
+        for (int k : by[busy[q]]) status[k] = HELM_EDEVICE;
     for (int w = 0; w < nst; ++w) {
       CK(hipEventRecord(ready, ctx->bstreams[w]));
       CK(hipStreamWaitEvent(s, ready, 0));
