@@ -514,13 +514,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))
         av[q] = sA[k4 + lk][wr + 16 * q + lm];
         bv[q] = sB[k4 + lk][wc + 16 * q + lm];
       }
+      // the four products of a block go to two accumulators: issue them in rounds over the
+      // eight accumulators, so that no MFMA waits for the one just before it
 #pragma unroll
       for (int qa = 0; qa < 2; ++qa)
 #pragma unroll
         for (int qb = 0; qb < 2; ++qb) {
           accr[qa][qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[qa].x, bv[qb].x, accr[qa][qb], 0, 0, 0);
-          accr[qa][qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[qa].y, bv[qb].y, accr[qa][qb], 0, 0, 0);
           acci[qa][qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[qa].x, bv[qb].y, acci[qa][qb], 0, 0, 0);
+        }
+#pragma unroll
+      for (int qa = 0; qa < 2; ++qa)
+#pragma unroll
+        for (int qb = 0; qb < 2; ++qb) {
+          accr[qa][qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[qa].y, bv[qb].y, accr[qa][qb], 0, 0, 0);
           acci[qa][qb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[qa].y, bv[qb].x, acci[qa][qb], 0, 0, 0);
         }
     }
