@@ -440,6 +440,7 @@ size_t carve(helm_ctx* c, void* ws) {
         D.ntasks = (int)L.task_off.size() - 1;
         D.task_off = cv.take<int>(L.task_off.size());
         D.items = cv.take<NDItem>(L.items.size());
+        D.gath = cv.take<NDGather>(std::max<size_t>(1, L.gath.size()));
       }
     }
   }
@@ -1091,6 +1092,7 @@ static int setup_rcap(const helm_grid* grid, const double* slowness, double omeg
         } else {
           up((int*)D.task_off, Ls[l].task_off, s);
           up((NDItem*)D.items, Ls[l].items, s);
+          up((NDGather*)D.gath, Ls[l].gath, s);
         }
       }
     }

@@ -170,7 +170,8 @@ struct NDItem {         // one work item of a multi-block launch: rows [r0, r1) 
   int front, r0, r1;
   int stage;
   // the front's fields the work item needs (copied, so a work-group reads one record)
-  int nS, nF, nB, pad;
+  int nS, nF, nB;
+  int g0;               // forward: the front's gather list (one entry per front row) in the launch's gath
   long long m_off;      // L_off (forward) or W_off (backward)
   long long idx_off, inv_off, upd_off;
 };

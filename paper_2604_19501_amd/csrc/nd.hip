@@ -583,6 +583,20 @@ __device__ __forceinline__ C cmul_conj(C a, C x, int conj) {   // (conj? conj(a)
 }
 
 
+// one entry of a gather list: r at the row's node (rid >= 0), the first two updates inline
+// and the rest through cidx; every load of the first level is issued unconditionally
+template <typename C>
+__device__ __forceinline__ C gather_list(const NDGather& g, const int* __restrict__ cidx, const C* __restrict__ upd,
+                                         const C* __restrict__ r) {
+  typedef decltype(r[0].x) R;
+  const C a = r[max(g.rid, 0)], u0 = upd[max(g.u0, 0)], u1 = upd[max(g.u1, 0)];
+  C v = g.rid >= 0 ? a : mk((R)0, (R)0);
+  if (g.u0 >= 0) v += u0;
+  if (g.u1 >= 0) v += u1;
+  for (int q = g.ca; q < g.cb; ++q) v += upd[cidx[q]];
+  return v;
+}
+
 // f_S (and v_B) entry i of front f: right-hand side on S plus the children's updates
 // (contribution list cptr[i] .. cptr[i+1] of absolute indices into the update pool); F is
 // the front record or a work item carrying its fields
@@ -902,9 +916,8 @@ __device__ __forceinline__ C gemv16_finish(const C* __restrict__ M, long long ld
 
 // forward substitution, big fronts: one work-group per chunk of at most 64 rows
 template <typename C>
-__global__ void __launch_bounds__(256) k_nd_fwd_big(const NDFrontDev* __restrict__ fr, const int* __restrict__ idx,
-                                                    const int* __restrict__ cptr, const int* __restrict__ cidx,
-                                                    const C* __restrict__ Lp,
+__global__ void __launch_bounds__(256) k_nd_fwd_big(const NDGather* __restrict__ gath, const int* __restrict__ idx,
+                                                    const int* __restrict__ cidx, const C* __restrict__ Lp,
                                                     C* __restrict__ upd, const NDItem* __restrict__ items,
                                                     const C* __restrict__ r, C* __restrict__ x,
                                                     C* __restrict__ gvec, int cap, int conj, NDRhs rh) {
@@ -918,8 +931,9 @@ __global__ void __launch_bounds__(256) k_nd_fwd_big(const NDFrontDev* __restrict
   const int* id = idx + f.idx_off;
   C m0[16];
   gemv16_load(Lp + f.m_off, f.nF, f.r0, f.r1, f.nS, m0);
-  for (int i = threadIdx.x; i < f.nS; i += 256) vec[i] = gather_entry(f, cptr, cidx, id, upd, r, i);
-  for (int i = max(f.r0, f.nS) + threadIdx.x; i < f.r1; i += 256) vec[i] = gather_entry(f, cptr, cidx, id, upd, r, i);
+  const NDGather* gl = gath + f.g0;
+  for (int i = threadIdx.x; i < f.nS; i += 256) vec[i] = gather_list(gl[i], cidx, upd, r);
+  for (int i = max(f.r0, f.nS) + threadIdx.x; i < f.r1; i += 256) vec[i] = gather_list(gl[i], cidx, upd, r);
   __syncthreads();
   C acc = gemv16_finish(Lp + f.m_off, f.nF, f.r0, f.r1, f.nS, vec, conj, red, m0);
   const int i = f.r0 + threadIdx.x;
@@ -1130,7 +1144,7 @@ void nd_fwd(const NDLaunchDev& L, const NDFrontDev* fr, const int* idx, const in
     hipLaunchKernelGGL((k_nd_tree<C, 1>), dim3(L.ntasks, rh.n), dim3(L.threads), lds, s, L.tasks, L.stages, L.gath,
                        L.segs, L.outs, L.dst, cidx, Lp, upd, r, x, conj, rh);
   } else {
-    hipLaunchKernelGGL((k_nd_fwd_big<C>), dim3(L.ntasks, rh.n), dim3(256), L.shm, s, fr, idx, cptr, cidx, Lp, upd,
+    hipLaunchKernelGGL((k_nd_fwd_big<C>), dim3(L.ntasks, rh.n), dim3(256), L.shm, s, L.gath, idx, cidx, Lp, upd,
                        L.items, r, x, gvec, cap, conj, rh);
   }
 }

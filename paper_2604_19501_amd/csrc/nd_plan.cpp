@@ -647,8 +647,22 @@ void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int root_merge, int e
     } else {
       for (int t : plan.by_height[h]) {
         const NDFrontDev& f = plan.fronts[t];
+        // the front's gather list: row i reads r at its node (i < nS) and the children's
+        // updates, the first two inline
+        const int g0 = (int)fl.gath.size();
+        const int* ids = plan.idx.data() + f.idx_off;
+        for (int i = 0; i < f.nF; ++i) {
+          int ca = plan.cptr[f.inv_off + i];
+          const int cb = plan.cptr[f.inv_off + i + 1];
+          NDGather g{i, i < f.nS ? ids[i] : -1, -1, -1, 0, 0};
+          if (ca < cb) g.u0 = plan.cidx[ca++];
+          if (ca < cb) g.u1 = plan.cidx[ca++];
+          g.ca = ca;
+          g.cb = cb;
+          fl.gath.push_back(g);
+        }
         for (int r = 0; r < f.nF; r += rows_chunk) {
-          fl.items.push_back({t, r, std::min(f.nF, r + rows_chunk), h, f.nS, f.nF, f.nB, 0, f.L_off, f.idx_off,
+          fl.items.push_back({t, r, std::min(f.nF, r + rows_chunk), h, f.nS, f.nF, f.nB, g0, f.L_off, f.idx_off,
                               f.inv_off, f.upd_off});
           fl.task_off.push_back((int)fl.items.size());
         }
