@@ -51,6 +51,28 @@ def test_workspace_query_and_validation():
     assert _bytes((32, 32), restart=40)[1] > b
 
 
+def test_lockstep_capacity_workspace():
+    """a single-instance context with lock-step capacity r needs more workspace than r = 1;
+    the capacity is capped at 16, and r < 1 is rejected before any device work"""
+    g = make_grid((32, 32), 1 / 32, ((2, 2), (2, 2)), 2.0)
+    m = make_mg()
+    sizes = {}
+    for r in (1, 4, 16, 64):
+        b = C.c_size_t()
+        assert L.lib.helm_workspace_bytes_multi(C.byref(g), C.byref(m), r, C.byref(b)) == 0
+        sizes[r] = b.value
+    single = C.c_size_t()
+    assert L.lib.helm_workspace_bytes(C.byref(g), C.byref(m), C.byref(single)) == 0
+    assert sizes[1] == single.value
+    assert sizes[1] < sizes[4] < sizes[16] == sizes[64]
+    b = C.c_size_t()
+    assert L.lib.helm_workspace_bytes_multi(C.byref(g), C.byref(m), 0, C.byref(b)) == L.HELM_EINVAL
+    ctx = C.c_void_p()
+    s = L.Shift(1.0, 1.0, 0.0)
+    assert L.lib.helm_setup_multi(C.byref(g), None, 10.0, C.byref(s), C.byref(m), 0, None, 0, None,
+                                  C.byref(ctx)) == L.HELM_EINVAL
+
+
 def test_setup_rejects_bad_arguments_before_device_work():
     g = make_grid((32, 32), 1 / 32, ((2, 2), (2, 2)), 2.0)
     m = make_mg()
