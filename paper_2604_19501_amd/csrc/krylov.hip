@@ -200,6 +200,18 @@ __global__ void __launch_bounds__(64) k_givens(KrylovArgs a, int j, double tol) 
   KrylovState* st = p.st;
   if (st->done) return;            // converged in an earlier column: the state stays as it is
   const int t = threadIdx.x, ld = KMAXM + 1;
+  // the scalars the serial part needs, loaded now so that their latency overlaps the
+  // products below (the stores into the state would otherwise keep them in order)
+  double nw2 = 0.0, bnorm = 1.0;
+  cd gj = mk(0.0, 0.0);
+  int its = 0, maxit = 0;
+  if (t == 0) {
+    nw2 = st->h1[2 * j + 2].x;
+    gj = st->g[j];
+    bnorm = st->bnorm;
+    its = st->its;
+    maxit = st->maxit;
+  }
   for (int i = t; i <= j; i += 64) {
     sh1[i] = st->h1[i];
     sg[i] = st->h1[j + 1 + i];                 // G(i, j) = <V_i, V_j>
@@ -246,7 +258,6 @@ __global__ void __launch_bounds__(64) k_givens(KrylovArgs a, int j, double tol) 
       ch += r1[i];
       cgc += r2[i];
     }
-    const double nw2 = st->h1[2 * j + 2].x;
     const double n2 = nw2 - 2.0 * ch + cgc;     // ||w - V c||^2
     const double hn = n2 > 0.0 ? sqrt(n2) : 0.0;
     for (int i = 0; i <= j; ++i) col[i] = sc[i];
@@ -264,17 +275,17 @@ __global__ void __launch_bounds__(64) k_givens(KrylovArgs a, int j, double tol) 
     st->sn[j] = s;
     col[j] = r;
     col[j + 1] = mk(0.0, 0.0);
-    cd gj = st->g[j];
-    st->g[j + 1] = -(conjc(s) * gj);
+    const cd gnext = -(conjc(s) * gj);
+    st->g[j + 1] = gnext;
     st->g[j] = c * gj;
-    double est = sqrt(abs2(st->g[j + 1])) / st->bnorm;
+    double est = sqrt(abs2(gnext)) / bnorm;
     st->est = est;
-    if (st->its < KMAXIT) st->hist[st->its] = est;
-    st->its += 1;
+    if (its < KMAXIT) st->hist[its] = est;
+    st->its = its + 1;
     st->kcols = j + 1;
     bool fin = isfinite(est) && isfinite(hn);
     if (!fin) st->nonfinite = 1;
-    st->done = (est <= tol || !fin || hn == 0.0 || st->its >= st->maxit) ? 1 : 0;
+    st->done = (est <= tol || !fin || hn == 0.0 || its + 1 >= maxit) ? 1 : 0;
   }
   __syncthreads();
   for (int i = t; i <= j + 1; i += 64) st->H[i + ld * j] = col[i];
