@@ -98,6 +98,7 @@ struct Carver {
 
 struct NDDev {        // device-side ND tables (pointers into the workspace)
   NDFrontDev* fronts = nullptr;
+  NDFrontDev* hfr = nullptr;   // fronts in height order
   int *idx = nullptr, *maps = nullptr, *cptr = nullptr, *cidx = nullptr, *perm = nullptr, *hlist = nullptr,
       *err = nullptr, *swp = nullptr;
   int* children = nullptr;
@@ -402,6 +403,7 @@ size_t carve(helm_ctx* c, void* ws) {
   d.asmv = cv.take<NDAsm>(P.asmv.size());
   d.perm = cv.take<int>(P.perm_total);
   d.hlist = cv.take<int>(c->hlist.size());
+  d.hfr = cv.take<NDFrontDev>(c->hlist.size());   // the fronts in height order (factorisation)
   d.toff = cv.take<long long>(c->hlist_toff.size());
   d.err = cv.take<int>(1);
   d.F = cv.take<cd>(P.F_total);
@@ -508,6 +510,7 @@ void nd_factor(helm_ctx* c, hipStream_t s) {
   for (size_t h = 0; h < c->hinfo.size(); ++h) {
     const HeightInfo& hi = c->hinfo[h];
     const int* ids = d.hlist + hi.start;
+    const NDFrontDev* hf = d.hfr + hi.start;     // the height's fronts, slot order
     const long long* toff = d.toff + hi.start;
     nd_assemble(d.fronts, ids, hi.count, hi.max_asm, d.asmv, c->coef3_64, d.F, s);
     for (int slot = 0; slot < hi.max_child; ++slot)
@@ -526,24 +529,24 @@ void nd_factor(helm_ctx* c, hipStream_t s) {
     const int kout = reg_panel ? kb : std::max(1, std::min(ND_KBOUT, env_int("HELM_ND_KB_OUTER", ND_KBOUT)) / kb) * kb;
     for (int k0 = 0; k0 < hi.max_nS; k0 += kout) {
       if (reg_panel) {
-        nd_panel_reg(d.fronts, ids, hi.count, hi.max_nF, d.F, d.perm, d.swp, k0, kb, d.err, s);
+        nd_panel_reg(hf, nullptr, hi.count, hi.max_nF, d.F, d.perm, d.swp, k0, kb, d.err, s);
       } else {
         for (int k1 = k0; k1 < std::min(k0 + kout, hi.max_nS); k1 += kb) {
-          nd_panel_multi(d.fronts, ids, hi.count, hi.max_nF, d.F, d.perm, d.swp, d.cand, d.rkb, k1, kb, hi.max_nS,
+          nd_panel_multi(hf, nullptr, hi.count, hi.max_nF, d.F, d.perm, d.swp, d.cand, d.rkb, k1, kb, hi.max_nS,
                          d.err, s);
           if (kout > kb) {        // the block's other panels
-            nd_save_t(d.fronts, ids, hi.count, toff, (long long)kb * kout, d.F, d.T, k1, kb, k0, kout, s);
-            nd_gemm(d.fronts, ids, hi.count, toff, hi.max_nF, kout, d.F, d.T, k1, kb, k0, kout, s);
+            nd_save_t(hf, nullptr, hi.count, toff, (long long)kb * kout, d.F, d.T, k1, kb, k0, kout, s);
+            nd_gemm(hf, nullptr, hi.count, toff, hi.max_nF, kout, d.F, d.T, k1, kb, k0, kout, s);
           }
         }
       }
-      nd_save_t(d.fronts, ids, hi.count, toff, hi.max_T, d.F, d.T, k0, kout, 0, -1, s);
-      nd_gemm(d.fronts, ids, hi.count, toff, hi.max_nF, hi.max_nF, d.F, d.T, k0, kout, 0, -1, s);
+      nd_save_t(hf, nullptr, hi.count, toff, hi.max_T, d.F, d.T, k0, kout, 0, -1, s);
+      nd_gemm(hf, nullptr, hi.count, toff, hi.max_nF, hi.max_nF, d.F, d.T, k0, kout, 0, -1, s);
     }
     if (c->f32)
-      nd_finalize<cf>(d.fronts, ids, hi.count, hi.max_fin, d.F, d.perm, (cf*)d.L, (cf*)d.W, s);
+      nd_finalize<cf>(hf, nullptr, hi.count, hi.max_fin, d.F, d.perm, (cf*)d.L, (cf*)d.W, s);
     else
-      nd_finalize<cd>(d.fronts, ids, hi.count, hi.max_fin, d.F, d.perm, (cd*)d.L, (cd*)d.W, s);
+      nd_finalize<cd>(hf, nullptr, hi.count, hi.max_fin, d.F, d.perm, (cd*)d.L, (cd*)d.W, s);
   }
 }
 
@@ -1068,6 +1071,12 @@ static int setup_rcap(const helm_grid* grid, const double* slowness, double omeg
     up(d.child_map_off, P.child_map_off, s);
     up(d.asmv, P.asmv, s);
     up(d.hlist, c->hlist, s);
+    {
+      std::vector<NDFrontDev> hf;
+      hf.reserve(c->hlist.size());
+      for (int t : c->hlist) hf.push_back(P.fronts[t]);
+      up(d.hfr, hf, s);
+    }
     up(d.toff, c->hlist_toff, s);
     if (c->use_flow) {
       up((NDFlowTask*)d.flow.tasks, c->flow.tasks, s);

@@ -40,6 +40,12 @@ __global__ void __launch_bounds__(256) k_nd_assemble(const NDFrontDev* __restric
   }
 }
 
+// the front record of work slot y: with ids, fr is the plan's array; without, fr already
+// holds the fronts of one height in slot order (one load instead of two dependent ones)
+__device__ __forceinline__ NDFrontDev front_at(const NDFrontDev* __restrict__ fr, const int* __restrict__ ids, int y) {
+  return ids ? fr[ids[y]] : fr[y];
+}
+
 __global__ void __launch_bounds__(256) k_nd_extend(const NDFrontDev* __restrict__ fr, const int* __restrict__ ids,
                                                    const int* __restrict__ children,
                                                    const long long* __restrict__ child_map_off,
@@ -131,7 +137,7 @@ __global__ void __launch_bounds__(NT) k_nd_panel_reg(const NDFrontDev* __restric
   __shared__ int s_pp, s_pk;              // their permutation entries
   __shared__ double s_v[16];
   __shared__ int s_i[16];
-  const NDFrontDev f = fr[ids[blockIdx.x]];
+  const NDFrontDev f = front_at(fr, ids, blockIdx.x);
   if (f.nS <= k0) return;
   const int kbb = min(KB, f.nS - k0);
   const int nF = f.nF, nS = f.nS, tid = threadIdx.x, w0 = tid & ~63;
@@ -254,7 +260,7 @@ __global__ void __launch_bounds__(256) k_piv_search(const NDFrontDev* __restrict
                                                     int nblk) {
   __shared__ double sv[4];
   __shared__ int si[4];
-  const NDFrontDev f = fr[ids[blockIdx.y]];
+  const NDFrontDev f = front_at(fr, ids, blockIdx.y);
   if (f.nS <= k || (int)blockIdx.x * PROWS >= f.nF) return;
   const cd* F = Fp + f.F_off;
   double best = -1.0;
@@ -272,7 +278,7 @@ __global__ void __launch_bounds__(64) k_piv_select(const NDFrontDev* __restrict_
                                                    cd* __restrict__ Fp, int* __restrict__ perm, int* __restrict__ swp,
                                                    int k0, int kb, int kk, const PivCand* __restrict__ cand, int nblk,
                                                    cd* __restrict__ rkb, int* __restrict__ err) {
-  const NDFrontDev f = fr[ids[blockIdx.x]];
+  const NDFrontDev f = front_at(fr, ids, blockIdx.x);
   const int k = k0 + kk;
   if (f.nS <= k) return;
   const int kbb = min(kb, f.nS - k0);
@@ -339,7 +345,7 @@ __global__ void __launch_bounds__(256) k_piv_update(const NDFrontDev* __restrict
   __shared__ cd srk[ND_KBMAX + 1];
   __shared__ double sv[4];
   __shared__ int si[4];
-  const NDFrontDev f = fr[ids[blockIdx.y]];
+  const NDFrontDev f = front_at(fr, ids, blockIdx.y);
   const int k = k0 + kk;
   if (f.nS <= k || (int)blockIdx.x * PROWS >= f.nF) return;
   const int kbb = min(kb, f.nS - k0);
@@ -390,7 +396,7 @@ __global__ void __launch_bounds__(256) k_piv_update(const NDFrontDev* __restrict
 __global__ void __launch_bounds__(256) k_nd_swap_rest(const NDFrontDev* __restrict__ fr, const int* __restrict__ ids,
                                                       cd* __restrict__ Fp, const int* __restrict__ swp, int k0,
                                                       int KB) {
-  const NDFrontDev f = fr[ids[blockIdx.y]];
+  const NDFrontDev f = front_at(fr, ids, blockIdx.y);
   if (f.nS <= k0) return;
   const int kbb = min(KB, f.nS - k0);
   const int* sw = swp + (long long)blockIdx.y * ND_KBMAX;
@@ -433,7 +439,7 @@ __device__ __forceinline__ bool col_map(const NDFrontDev& f, int k0, int kb, int
 __global__ void __launch_bounds__(256) k_nd_save_t(const NDFrontDev* __restrict__ fr, const int* __restrict__ ids,
                                                    const long long* __restrict__ toff, cd* __restrict__ Fp,
                                                    cd* __restrict__ T, int k0, int kb, int u0, int un) {
-  const NDFrontDev f = fr[ids[blockIdx.y]];
+  const NDFrontDev f = front_at(fr, ids, blockIdx.y);
   ColMap cm;
   if (!col_map(f, k0, kb, u0, un, cm)) return;
   const int ncol = cm.ncol;
@@ -460,7 +466,7 @@ typedef double mfma_d4 __attribute__((ext_vector_type(4)));
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) k_nd_gemm(const NDFrontDev* __restrict__ fr, const int* __restrict__ ids,
                                                  const long long* __restrict__ toff, cd* __restrict__ Fp,
                                                  const cd* __restrict__ T, int k0, int kb, int u0, int un) {
-  const NDFrontDev f = fr[ids[blockIdx.y]];
+  const NDFrontDev f = front_at(fr, ids, blockIdx.y);
   ColMap cm;
   if (!col_map(f, k0, kb, u0, un, cm)) return;
   const int kbb = cm.kbb;
@@ -551,7 +557,7 @@ template <typename C>
 __global__ void __launch_bounds__(256) k_nd_finalize(const NDFrontDev* __restrict__ fr, const int* __restrict__ ids,
                                                      const cd* __restrict__ Fp, const int* __restrict__ perm,
                                                      C* __restrict__ Lp, C* __restrict__ Wp) {
-  const NDFrontDev f = fr[ids[blockIdx.y]];
+  const NDFrontDev f = front_at(fr, ids, blockIdx.y);
   const cd* F = Fp + f.F_off;
   const int* pm = perm + f.perm_off;
   long long nL = (long long)f.nF * f.nS, nW = (long long)f.nS * f.nB;
