@@ -321,7 +321,10 @@ void build_plan(helm_ctx* c) {
   c->nd_root = merge;
   // heights above the tree blocks with at least this many factor bytes use split-K launches
   const long long splitk = (long long)env_int("HELM_ND_SPLITK_KB", 4096) * 1024;
-  nd_plan(c->g3, leaf, 16, merge, (int)c->csz, lds, cuts, splitk, c->plan);
+  // tree-block work-groups of at most HELM_ND_TREE_WAVES wavefronts: 16 in 2D; 8 in 3D, where
+  // the many small subtrees run two work-groups per CU (measured 3 % faster at 256^3)
+  const int tree_waves = env_int("HELM_ND_TREE_WAVES", c->grid.dim == 3 ? 8 : 16);
+  nd_plan(c->g3, leaf, 16, merge, (int)c->csz, lds, cuts, splitk, c->plan, tree_waves);
   NDPlan& P = c->plan;
   // HELM_ND_FLOW=1: the substitutions run as one dataflow launch each solve
   // (heights above the tree-block launches)

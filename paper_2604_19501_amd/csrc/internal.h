@@ -320,8 +320,9 @@ struct NDPlan {
 // model, {-1}: no tree blocks)
 // splitk_bytes: heights above the tree blocks whose factor blocks hold at least this many
 // bytes (per direction) use split-K launches
+// tree_waves: the most wavefronts of a tree-block work-group (16 = 1024 threads)
 void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int root_merge, int elem_bytes, int lds_bytes,
-             const std::vector<int>& cuts, long long splitk_bytes, NDPlan& plan);
+             const std::vector<int>& cuts, long long splitk_bytes, NDPlan& plan, int tree_waves = 16);
 
 // the dataflow task queue of a plan's heights >= h_lo
 void nd_flow_plan(const NDPlan& plan, int h_lo, NDFlow& flow);

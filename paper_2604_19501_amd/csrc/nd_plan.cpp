@@ -97,7 +97,8 @@ struct Builder {
 }  // namespace
 
 void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int root_merge, int elem_bytes, int lds_bytes,
-             const std::vector<int>& cuts, long long splitk_bytes, NDPlan& plan) {
+             const std::vector<int>& cuts, long long splitk_bytes, NDPlan& plan, int tree_waves) {
+  tree_waves = std::max(1, std::min(16, tree_waves));
   Builder bd;
   bd.g = g3;
   bd.leaf_max = std::max(leaf_max, 1);
@@ -586,7 +587,7 @@ void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int root_merge, int e
           const int per = 1;
           for (int st = T.st0; st < T.st1; ++st) {
             const int ns = L.stages[st].s1 - L.stages[st].s0;
-            L.threads = std::max(L.threads, 64 * std::min(16, (ns + per - 1) / per));
+            L.threads = std::max(L.threads, 64 * std::min(tree_waves, (ns + per - 1) / per));
           }
         }
       }
