@@ -104,10 +104,13 @@ def bytes_model(cls, p, info, iters, restart, nr=1):
         return N1 * (16 * nr + 4) + N2 * cb * nr
     if cls == "l1_sweep":         # b (c128) + z out per fine node and e2 per level-2 node per rhs; m
         return N1 * ((16 + cb) * nr + 4) + N2 * cb * nr
-    if cls == "l2_sweep":         # coefficients (K) + b2, x in, x out per level-2 node
-        return N2 * cb * (K + 3 * nr)
+    # level-2 coefficients: the 3D FP32 cycle stores the complex-symmetric operator's centre
+    # and the directions after it (14 planes), otherwise all K
+    S = K // 2 + 1 if (cb == 8 and d == 3) else K
+    if cls == "l2_sweep":         # coefficients + b2, x in, x out per level-2 node
+        return N2 * cb * (S + 3 * nr)
     if cls == "l2_restrict":      # coefficients + b2, x per level-2 node
-        return N2 * cb * (K + 2 * nr)
+        return N2 * cb * (S + 2 * nr)
     if cls == "nd_fwd":           # [A^-1; C A^-1] once, right-hand side gather, updates written and read
         per_solve = info["L_entries"] * cb + 4 * (N3 + U) + nr * (2 * N3 * cb + 2 * U * cb)
         return per_solve / info["fwd_launches"]

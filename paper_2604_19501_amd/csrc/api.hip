@@ -231,6 +231,9 @@ void init_geometry(helm_ctx* c) {
   c->csz = c->f32 ? sizeof(cf) : sizeof(cd);
 }
 
+// planes of the FP32 level-2 coefficients: 3D keeps the symmetric half (centre onwards;
+// the level kernels' Op2<3, float> reads them so)
+static inline int sym2_planes(int dim) { return dim == 3 ? 14 : 9; }
 const int ND_KB = ND_KBOUT;      // scratch of the exchange updates is sized for the widest column block
 // nested-dissection parameters (tunable through the environment for the autotuner):
 // leaf box size, rows per work-group of big fronts, nodes per subtree task
@@ -369,7 +372,10 @@ size_t carve(helm_ctx* c, void* ws) {
   c->m64 = cv.take<double>(g1.tot);
   c->m32 = cv.take<float>(g1.tot);
   c->coef2_64 = cv.take<cd>((size_t)K * g2.tot);
-  c->coef2_32 = c->f32 ? cv.take<cf>((size_t)K * g2.tot) : nullptr;
+  // the 3D FP32 cycle keeps the complex-symmetric level-2 operator's centre and the 13
+  // directions after it (14 of 27 planes); in 2D the mirrored reads cost more than the
+  // 4 of 9 planes they save (measured), so all 9 are kept
+  c->coef2_32 = c->f32 ? cv.take<cf>((size_t)sym2_planes(g2.dim) * g2.tot) : nullptr;
   c->tmp2 = cv.take<cd>((size_t)K * g2.tot);
   c->coef3_64 = cv.take<cd>((size_t)K * g3.tot);
   const size_t rc = (size_t)c->rcap;
@@ -640,7 +646,9 @@ void numeric_setup(helm_ctx* c, const double* slowness, hipStream_t s) {
   // a1: level-2 Galerkin operator of H_beta^{alpha2}
   gal_fine(c->op, shift_scalar(shift->alpha2, shift->beta, omega), c->m64, c->g2, c->coef2_64, s);
   const int K = stencil_points(c->grid.dim);
-  if (c->f32) cast_d2f(c->coef2_64, c->coef2_32, (long long)K * c->g2.tot, s);
+  if (c->f32)
+    cast_d2f(c->coef2_64 + (long long)(K - sym2_planes(c->g2.dim)) * c->g2.tot, c->coef2_32,
+             (long long)sym2_planes(c->g2.dim) * c->g2.tot, s);
   // a2: real-shifted level-3 operator R2 (R1 H_beta^alpha P1) P2
   gal_fine(c->op, shift_scalar(shift->alpha, shift->beta, omega), c->m64, c->g2, c->tmp2, s);
   gal_coarse(c->g2, c->tmp2, c->g3, c->coef3_64, s);

@@ -92,16 +92,19 @@ struct Op1 {
   }
 };
 
-// level-2 Galerkin operator (3^d stored coefficients per node)
+// level-2 Galerkin operator (3^d coefficients per node; the 3D FP32 cycle stores the
+// complex-symmetric operator from its centre on)
 template <int DIM, typename R>
 struct Op2 {
   typedef R Real;
   typedef typename cplx<R>::type C;
+  static constexpr bool SYM = DIM == 3 && sizeof(R) == 4;
   L2<R> A;
   __host__ __device__ __forceinline__ const Geom& geom() const { return A.g; }
-  __device__ __forceinline__ C diag(long long f, int, int, int) const { return A.get(DIM == 2 ? 4 : 13, f); }
+  __device__ __forceinline__ C coef_at(int k, long long f) const { return SYM ? A.get_sym3(k, f) : A.get(k, f); }
+  __device__ __forceinline__ C diag(long long f, int, int, int) const { return coef_at(DIM == 2 ? 4 : 13, f); }
   typedef C Aux;
-  __device__ __forceinline__ Aux aux(long long f) const { return A.get(DIM == 2 ? 4 : 13, f); }
+  __device__ __forceinline__ Aux aux(long long f) const { return coef_at(DIM == 2 ? 4 : 13, f); }
   __device__ __forceinline__ C diag_aux(Aux d, int, int, int) const { return d; }
   __device__ __forceinline__ C ax(const C* xs, int k, int sy, int sz, long long f, C D) const {
     C acc = D * xs[k];
@@ -113,7 +116,7 @@ struct Op2 {
         for (int d0 = -1; d0 <= 1; ++d0) {
           if (d0 == 0 && d1 == 0 && d2 == 0) continue;
           const int kk = (d0 + 1) + 3 * (d1 + 1) + (DIM == 3 ? 9 * (d2 + 1) : 0);
-          acc += A.get(kk, f) * xs[k + d0 + sy * d1 + sz * d2];
+          acc += coef_at(kk, f) * xs[k + d0 + sy * d1 + sz * d2];
         }
     return acc;
   }

@@ -60,10 +60,27 @@ template <typename R>
 struct L2 {
   typedef typename cplx<R>::type C;
   Geom g;
-  const C* coef;     // 3^d * N, SoA
+  const C* coef;     // SoA, plane k at coef[k * N]: 3^d planes, or (SYM2) the centre and the
+                     // 13 directions after it
   int conj;          // use conj(coef) (adjoint)
   __device__ __forceinline__ C get(int k, long long i) const {
     C c = coef[(long long)k * g.tot + i];
+    if (conj) c.y = -c.y;
+    return c;
+  }
+  // coefficient k of node i of the complex-symmetric 3D operator stored from its centre on:
+  // A(i, i + d) = A(i + d, i), so a direction before the centre reads the mirrored one at
+  // the neighbour.  Where i + d lies outside the grid the product is with a zero iterate;
+  // the index is clamped into the array.
+  __device__ __forceinline__ C get_sym3(int k, long long i) const {
+    C c;
+    if (k >= 13) {
+      c = coef[(long long)(k - 13) * g.tot + i];
+    } else {
+      const long long off = (k % 3 - 1) + (long long)g.N[0] * ((k / 3) % 3 - 1 + (long long)g.N[1] * (k / 9 - 1));
+      const long long j = min(max(i + off, 0LL), g.tot - 1);
+      c = coef[(long long)(13 - k) * g.tot + j];
+    }
     if (conj) c.y = -c.y;
     return c;
   }
