@@ -127,6 +127,7 @@ struct Pending {
 struct HeightInfo {
   int start, count, max_asm, max_nS, max_nF, max_child;
   long long max_nb2, max_T, max_fin;
+  long long f_bytes;      // the fronts' dense matrices, FP64 complex
 };
 
 }  // namespace
@@ -355,6 +356,7 @@ void build_plan(helm_ctx* c) {
       hi.max_nb2 = std::max(hi.max_nb2, (long long)nbc * nbc);
       hi.max_T = std::max(hi.max_T, (long long)ND_KB * f.nF);
       hi.max_fin = std::max(hi.max_fin, (long long)f.nF * f.nS + (long long)f.nS * f.nB);
+      hi.f_bytes += (long long)sizeof(cd) * f.nF * f.nF;
     }
     c->hinfo.push_back(hi);
   }
@@ -529,24 +531,30 @@ void nd_factor(helm_ctx* c, hipStream_t s) {
     const int kreg = panel_reg_kb(hi.max_nF);
     const bool reg_panel = kreg > 0 && c->lds_panel > 0;
     // multi-work-group panels: HELM_ND_KB_MULTI columns (16, 32 or 64; wider panels halve
-    // the trailing-matrix passes of the GEMM, whose per-column cost is mostly launch latency),
-    // grouped into blocks of HELM_ND_KB_OUTER columns: the panels of a block update each
-    // other, and the rest of the front takes one trailing update per block (the GEMM streams
-    // the front once per block instead of once per panel)
+    // the trailing-matrix passes of the GEMM, whose per-column cost is mostly launch latency).
+    // Panels are grouped into blocks of HELM_ND_KB_OUTER columns: the panels of a block
+    // update each other, and the rest of the front takes one trailing update per block, so
+    // the GEMM streams the front once per block instead of once per panel.  For the 8- to
+    // 32-column register panels that pass is bound by the fronts' traffic, and blocking
+    // pays once the height's fronts hold at least HELM_ND_REG_BLOCK_MB megabytes and have
+    // at least two blocks' worth of rows; below that every pass costs about one launch (and
+    // a block covers most of a small front), so the block's two extra launches do not pay.
     const int kmulti = std::max(8, std::min(ND_KBMAX, env_int("HELM_ND_KB_MULTI", 64)));
     const int kb = reg_panel ? kreg : kmulti;
-    const int kout = reg_panel ? kb : std::max(1, std::min(ND_KBOUT, env_int("HELM_ND_KB_OUTER", ND_KBOUT)) / kb) * kb;
+    const int reg_mb = env_int("HELM_ND_REG_BLOCK_MB", 32);
+    const bool blocked = !reg_panel || (hi.f_bytes >= (long long)reg_mb * 1000000 &&
+                                        (reg_mb == 0 || hi.max_nF >= 2 * ND_KBOUT));
+    const int kout = blocked ? std::max(1, std::min(ND_KBOUT, env_int("HELM_ND_KB_OUTER", ND_KBOUT)) / kb) * kb : kb;
     for (int k0 = 0; k0 < hi.max_nS; k0 += kout) {
-      if (reg_panel) {
-        nd_panel_reg(hf, nullptr, hi.count, hi.max_nF, d.F, d.perm, d.swp, k0, kb, d.err, s);
-      } else {
-        for (int k1 = k0; k1 < std::min(k0 + kout, hi.max_nS); k1 += kb) {
+      for (int k1 = k0; k1 < std::min(k0 + kout, hi.max_nS); k1 += kb) {
+        if (reg_panel)
+          nd_panel_reg(hf, nullptr, hi.count, hi.max_nF, d.F, d.perm, d.swp, k1, kb, d.err, s);
+        else
           nd_panel_multi(hf, nullptr, hi.count, hi.max_nF, d.F, d.perm, d.swp, d.cand, d.rkb, k1, kb, hi.max_nS,
                          d.err, s);
-          if (kout > kb) {        // the block's other panels
-            nd_save_t(hf, nullptr, hi.count, toff, (long long)kb * kout, d.F, d.T, k1, kb, k0, kout, s);
-            nd_gemm(hf, nullptr, hi.count, toff, hi.max_nF, kout, d.F, d.T, k1, kb, k0, kout, s);
-          }
+        if (kout > kb) {        // the block's other panels, earlier ones included
+          nd_save_t(hf, nullptr, hi.count, toff, (long long)kb * kout, d.F, d.T, k1, kb, k0, kout, s);
+          nd_gemm(hf, nullptr, hi.count, toff, hi.max_nF, kout, d.F, d.T, k1, kb, k0, kout, s);
         }
       }
       nd_save_t(hf, nullptr, hi.count, toff, hi.max_T, d.F, d.T, k0, kout, 0, -1, s);

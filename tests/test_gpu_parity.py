@@ -72,7 +72,7 @@ def test_coarse_solve(case, prec, tol):
 @pytest.mark.parametrize("cuts,panel,splitk", [("none", "lds", None), ("", "lds", None), ("1", "lds", None),
                                                ("0,1,2,3", "lds", None), ("", "multi", None), ("none", "lds", 0),
                                                ("1", "multi", 0), ("", "multi32", None), ("", "multi_unblocked", None),
-                                               ("", "lds_waves4", None)])
+                                               ("", "lds_waves4", None), ("", "lds_blocked", None)])
 def test_coarse_solve_schedules(monkeypatch, dim, n, cuts, panel, splitk):
     """the exact coarsest solve under every kind of substitution schedule (row-chunk
     launches only, the planner's choice, one tree-block launch, one per level, split-K
@@ -88,6 +88,8 @@ def test_coarse_solve_schedules(monkeypatch, dim, n, cuts, panel, splitk):
         monkeypatch.setenv("HELM_ND_KB_OUTER", "64")
     if panel == "lds_waves4":          # tree-block work-groups of 4 wavefronts
         monkeypatch.setenv("HELM_ND_TREE_WAVES", "4")
+    if panel == "lds_blocked":         # register panels grouped into 128-column blocks at every height
+        monkeypatch.setenv("HELM_ND_REG_BLOCK_MB", "0")
     if splitk is not None:
         monkeypatch.setenv("HELM_ND_SPLITK_KB", str(splitk))
     p = synth.config2(n) if dim == 2 else synth.config3(n)
