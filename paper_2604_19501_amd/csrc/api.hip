@@ -530,8 +530,9 @@ void nd_factor(helm_ctx* c, hipStream_t s) {
     // enough; otherwise the panel is spread over many work-groups
     const int kreg = panel_reg_kb(hi.max_nF);
     const bool reg_panel = kreg > 0 && c->lds_panel > 0;
-    // multi-work-group panels: HELM_ND_KB_MULTI columns (16, 32 or 64; wider panels halve
-    // the trailing-matrix passes of the GEMM, whose per-column cost is mostly launch latency).
+    // multi-work-group panels: HELM_ND_KB_MULTI columns (16, 32 or 64).  Every pivot step
+    // reads and writes its panel over all rows of the front, so with the trailing passes
+    // taken per block the narrower 32-column panel is the faster one.
     // Panels are grouped into blocks of HELM_ND_KB_OUTER columns: the panels of a block
     // update each other, and the rest of the front takes one trailing update per block, so
     // the GEMM streams the front once per block instead of once per panel.  For the 8- to
@@ -539,7 +540,7 @@ void nd_factor(helm_ctx* c, hipStream_t s) {
     // pays once the height's fronts hold at least HELM_ND_REG_BLOCK_MB megabytes and have
     // at least two blocks' worth of rows; below that every pass costs about one launch (and
     // a block covers most of a small front), so the block's two extra launches do not pay.
-    const int kmulti = std::max(8, std::min(ND_KBMAX, env_int("HELM_ND_KB_MULTI", 64)));
+    const int kmulti = std::max(8, std::min(ND_KBMAX, env_int("HELM_ND_KB_MULTI", 32)));
     const int kb = reg_panel ? kreg : kmulti;
     const int reg_mb = env_int("HELM_ND_REG_BLOCK_MB", 32);
     const bool blocked = !reg_panel || (hi.f_bytes >= (long long)reg_mb * 1000000 &&

@@ -71,7 +71,7 @@ def test_coarse_solve(case, prec, tol):
 @pytest.mark.parametrize("dim,n", [(2, 256), (3, 64)])
 @pytest.mark.parametrize("cuts,panel,splitk", [("none", "lds", None), ("", "lds", None), ("1", "lds", None),
                                                ("0,1,2,3", "lds", None), ("", "multi", None), ("none", "lds", 0),
-                                               ("1", "multi", 0), ("", "multi32", None), ("", "multi_unblocked", None),
+                                               ("1", "multi", 0), ("", "multi64", None), ("", "multi_unblocked", None),
                                                ("", "lds_waves4", None), ("", "lds_blocked", None)])
 def test_coarse_solve_schedules(monkeypatch, dim, n, cuts, panel, splitk):
     """the exact coarsest solve under every kind of substitution schedule (row-chunk
@@ -82,8 +82,8 @@ def test_coarse_solve_schedules(monkeypatch, dim, n, cuts, panel, splitk):
     monkeypatch.setenv("HELM_ND_CUTS", cuts)
     if panel.startswith("multi"):
         monkeypatch.setenv("HELM_ND_LDS_PANEL", "0")
-    if panel == "multi32":
-        monkeypatch.setenv("HELM_ND_KB_MULTI", "32")
+    if panel == "multi64":
+        monkeypatch.setenv("HELM_ND_KB_MULTI", "64")
     if panel == "multi_unblocked":
         monkeypatch.setenv("HELM_ND_KB_OUTER", "64")
     if panel == "lds_waves4":          # tree-block work-groups of 4 wavefronts
