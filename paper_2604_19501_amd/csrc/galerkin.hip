@@ -39,39 +39,74 @@ __device__ __forceinline__ void scatter_parents(int dim, const int* gI, const in
       }
 }
 
-// fine operator -Lap_h - s m (1 - i sigma) -> level 2
+// a * P(g, J) into acc[J - I] for the parents J of the fine node g = 2 I + (d0, d1, d2),
+// -2 <= d <= 2: along an axis an even d has the one parent I + d/2 (weight 1), an odd d
+// the two parents I + (d -+ 1)/2 (weight 1/2 each).  Called from fully unrolled loops, so
+// every index of acc is a constant and acc stays in registers.
+template <int DIM>
+__device__ __forceinline__ void add_parents(int d0, int d1, int d2, cd a, cd* acc) {
+  const bool od0 = d0 & 1, od1 = d1 & 1, od2 = DIM == 3 && (d2 & 1);
+  const double w = (od0 ? 0.5 : 1.0) * (od1 ? 0.5 : 1.0) * (od2 ? 0.5 : 1.0);
+#pragma unroll
+  for (int b2 = 0; b2 < 2; ++b2)
+#pragma unroll
+    for (int b1 = 0; b1 < 2; ++b1)
+#pragma unroll
+      for (int b0 = 0; b0 < 2; ++b0) {
+        if ((od0 || !b0) && (od1 || !b1) && (od2 || !b2)) {
+          const int J0 = od0 ? (b0 ? d0 + 1 : d0 - 1) / 2 : d0 / 2;
+          const int J1 = od1 ? (b1 ? d1 + 1 : d1 - 1) / 2 : d1 / 2;
+          const int J2 = DIM == 3 ? (od2 ? (b2 ? d2 + 1 : d2 - 1) / 2 : d2 / 2) : 0;
+          acc[(J0 + 1) + 3 * (J1 + 1) + (DIM == 3 ? 9 * (J2 + 1) : 0)] += w * a;
+        }
+      }
+}
+
+// fine operator -Lap_h - s m (1 - i sigma) -> level 2.  Fine nodes outside the grid add
+// zero terms, so the loops have constant trip counts.
+template <int DIM>
 __global__ void __launch_bounds__(128) k_gal_fine(FineOp op, cd s, const double* __restrict__ m,
                                                   Geom gc, cd* __restrict__ out) {
+  constexpr int R2 = DIM == 3 ? 1 : 0, K = DIM == 3 ? 27 : 9;
   long long I = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (I >= gc.tot) return;
   const Geom& g = op.g;
-  int dim = g.dim;
-  int Ic[3] = {(int)(I % gc.N[0]), (int)((I / gc.N[0]) % gc.N[1]), (int)(I / ((long long)gc.N[0] * gc.N[1]))};
-  cd acc[27];
-  for (int k = 0; k < 27; ++k) acc[k] = mk(0.0, 0.0);
-  int r2 = dim == 3 ? 1 : 0;
-  double ih = op.inv_h2;
-  for (int o2 = -r2; o2 <= r2; ++o2)
+  const int Ic[3] = {(int)(I % gc.N[0]), (int)((I / gc.N[0]) % gc.N[1]),
+                     DIM == 3 ? (int)(I / ((long long)gc.N[0] * gc.N[1])) : 0};
+  cd acc[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) acc[k] = mk(0.0, 0.0);
+  const double ih = op.inv_h2;
+#pragma unroll
+  for (int o2 = -R2; o2 <= R2; ++o2)
+#pragma unroll
     for (int o1 = -1; o1 <= 1; ++o1)
+#pragma unroll
       for (int o0 = -1; o0 <= 1; ++o0) {
-        int f[3] = {2 * Ic[0] + o0, 2 * Ic[1] + o1, dim == 3 ? 2 * Ic[2] + o2 : 0};
-        if (f[0] < 0 || f[0] > g.n[0] || f[1] < 0 || f[1] > g.n[1] || f[2] < 0 || f[2] > g.n[2]) continue;
-        double wR = (o0 == 0 ? 0.5 : 0.25) * (o1 == 0 ? 0.5 : 0.25) * (dim == 3 ? (o2 == 0 ? 0.5 : 0.25) : 1.0);
-        long long fl = f[0] + (long long)g.N[0] * (f[1] + (long long)g.N[1] * f[2]);
-        double sig = layer_sigma(op, f[0], f[1], f[2]);
-        double mm = m[fl];
-        cd c = s * mk(mm, -mm * sig);
-        cd diag = mk(2.0 * dim * ih - c.x, -c.y);
-        scatter_parents(dim, f, Ic, wR * diag, acc);
-        for (int a = 0; a < dim; ++a)
+        const int f[3] = {2 * Ic[0] + o0, 2 * Ic[1] + o1, 2 * Ic[2] + o2};
+        const bool in = f[0] >= 0 && f[0] <= g.n[0] && f[1] >= 0 && f[1] <= g.n[1] &&
+                        (DIM == 2 || (f[2] >= 0 && f[2] <= g.n[2]));
+        const double wR = (o0 == 0 ? 0.5 : 0.25) * (o1 == 0 ? 0.5 : 0.25) * (DIM == 3 ? (o2 == 0 ? 0.5 : 0.25) : 1.0);
+        cd diag = mk(0.0, 0.0);
+        if (in) {
+          const long long fl = f[0] + (long long)g.N[0] * (f[1] + (long long)g.N[1] * f[2]);
+          const double sig = layer_sigma(op, f[0], f[1], f[2]);
+          const double mm = m[fl];
+          const cd c = s * mk(mm, -mm * sig);
+          diag = mk(2.0 * DIM * ih - c.x, -c.y);
+        }
+        add_parents<DIM>(o0, o1, o2, wR * diag, acc);
+#pragma unroll
+        for (int a = 0; a < DIM; ++a)
+#pragma unroll
           for (int sgn = -1; sgn <= 1; sgn += 2) {
-            int gI[3] = {f[0], f[1], f[2]};
-            gI[a] += sgn;
-            if (gI[a] < 0 || gI[a] > g.n[a]) continue;
-            scatter_parents(dim, gI, Ic, mk(-wR * ih, 0.0), acc);
+            const int ga = f[a] + sgn;
+            const bool ing = in && ga >= 0 && ga <= g.n[a];
+            add_parents<DIM>(o0 + (a == 0 ? sgn : 0), o1 + (a == 1 ? sgn : 0), o2 + (a == 2 ? sgn : 0),
+                             ing ? mk(-wR * ih, 0.0) : mk(0.0, 0.0), acc);
           }
       }
-  int K = dim == 3 ? 27 : 9;
+#pragma unroll
   for (int k = 0; k < K; ++k) out[(long long)k * gc.tot + I] = acc[k];
 }
 
@@ -121,7 +156,11 @@ __global__ void k_square(const double* __restrict__ kap, double* __restrict__ m6
 }
 
 void gal_fine(const FineOp& op, cd s, const double* m, const Geom& gc, cd* out, hipStream_t st) {
-  hipLaunchKernelGGL(k_gal_fine, dim3((unsigned)((gc.tot + 127) / 128)), dim3(128), 0, st, op, s, m, gc, out);
+  const dim3 grid((unsigned)((gc.tot + 127) / 128));
+  if (op.g.dim == 3)
+    hipLaunchKernelGGL(k_gal_fine<3>, grid, dim3(128), 0, st, op, s, m, gc, out);
+  else
+    hipLaunchKernelGGL(k_gal_fine<2>, grid, dim3(128), 0, st, op, s, m, gc, out);
 }
 void gal_coarse(const Geom& g, const cd* A, const Geom& gc, cd* out, hipStream_t st) {
   hipLaunchKernelGGL(k_gal_coarse, dim3((unsigned)((gc.tot + 127) / 128)), dim3(128), 0, st, g, A, gc, out);
