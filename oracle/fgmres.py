@@ -47,7 +47,10 @@ def givens(a: complex, b: complex):
 
 
 def fgmres(apply_H: Callable, precond: Callable, b: np.ndarray, x0=None, tol=1e-6,
-           restart=20, max_iter=500) -> Result:
+           restart=20, max_iter=500, trace=None) -> Result:
+    """trace: optional list; every restart cycle appends a dict with the cycle's starting
+    iterate, its preconditioned directions Z (N x k), the iterate it returns and the
+    Givens estimate at its end (a record for tests, no effect on the arithmetic)."""
     b = np.asarray(b, np.complex128)
     x = np.zeros_like(b) if x0 is None else np.array(x0, np.complex128)
     bnorm = np.linalg.norm(b)
@@ -103,13 +106,17 @@ def fgmres(apply_H: Callable, precond: Callable, b: np.ndarray, x0=None, tol=1e-
         y = np.zeros(k, np.complex128)
         for i in range(k - 1, -1, -1):
             y[i] = (g[i] - Hh[i, i + 1:k] @ y[i + 1:k]) / Hh[i, i]
+        x_start = x
         for i in range(k):
             x = x + y[i] * Z[i]
+        if trace is not None:
+            trace.append(dict(x_start=x_start.copy(), Z=np.stack(Z[:k], 1), x_end=x.copy(),
+                              est=abs(g[k]) / bnorm, k=k))
         r = b - apply_H(x)
     return Result(x, its, max(cycles - 1, 0), converged, hist, float(np.linalg.norm(r) / bnorm))
 
 
-def solve(hier, b, tol=1e-6, restart=20, max_iter=500, x0=None) -> Result:
+def solve(hier, b, tol=1e-6, restart=20, max_iter=500, x0=None, trace=None) -> Result:
     """FGMRES on the hierarchy's outer operator H, preconditioned by one cycle."""
     return fgmres(lambda v: hier.H @ v, hier.precond, b, x0=x0, tol=tol, restart=restart,
-                  max_iter=max_iter)
+                  max_iter=max_iter, trace=trace)

@@ -121,3 +121,37 @@ def test_level2_error_vanishes_without_coarsening_error_at_low_frequency():
     e2 = np.max(np.abs(A.eg_level2("p5", "fw", 80.0, 1.0)))
     assert e2 < e1 < 0.05
     assert 3.0 < e1 / e2 < 5.0
+
+
+def _closed_form_axis_errors(kh, alpha, alpha2):
+    """errors along a grid axis from the 1-D Galerkin factors of the contract stack
+    (level 2: M = [1 6 1]/8, T = (2h)^-2 [-1 2 -1]; level 3: M = [5 22 5]/32, T = (4h)^-2
+    [-1 2 -1]; the other axes contribute their zero-frequency factors M(0) = 1, T(0) = 0):
+      fine     cos t   = 1 - (kh)^2 / 2
+      level 2  cos t2  = (2 - 3 a2^2 (kh)^2) / (2 + a2^2 (kh)^2)
+      level 3  cos t3  = (4 - 22 a^2 (kh)^2) / (4 + 10 a^2 (kh)^2)
+    and e2 = t2 / (2 t) - 1, e3 = t3 / (4 t) - 1 (eq. (4.8) and its grid-1-to-2 analogue)."""
+    t = math.acos(1.0 - kh * kh / 2.0)
+    c2 = (alpha2 * kh) ** 2
+    c3 = (alpha * kh) ** 2
+    t2 = math.acos((2.0 - 3.0 * c2) / (2.0 + c2))
+    t3 = math.acos((4.0 - 22.0 * c3) / (4.0 + 10.0 * c3))
+    return t2 / (2.0 * t) - 1.0, t3 / (4.0 * t) - 1.0
+
+
+@pytest.mark.parametrize("G", [10.0, 11.0, 12.0, 16.0])
+@pytest.mark.parametrize("alpha", [1.0, 1.06, 1.1170])
+def test_contract_stack_errors_along_an_axis_match_closed_forms(G, alpha):
+    """e_g (level 3) and the level-2 error at phi = 0 from the stencil convolution, the symbol
+    and the root search, against the closed forms of the 1-D Galerkin factors; in 3D along
+    the first axis through the 27-point coarsest stencil."""
+    kh = 2.0 * math.pi / G
+    e2_ref, e3_ref = _closed_form_axis_errors(kh, alpha, alpha)
+    assert A.eg("p5", "fw", G, alpha)[0] == pytest.approx(e3_ref, abs=1e-12)
+    assert A.eg_level2("p5", "fw", G, alpha)[0] == pytest.approx(e2_ref, abs=1e-12)
+    u = np.array([1.0, 0.0, 0.0])
+    r1 = A.ray_radius(A.fine_stencil("p7", kh), u)
+    r3 = A.ray_radius(A.coarse_stencil("p7", "fw", kh, alpha), u)
+    r2 = A.ray_radius(A.level2_stencil("p7", "fw", kh, alpha), u)
+    assert r3 / (4.0 * r1) - 1.0 == pytest.approx(e3_ref, abs=1e-12)
+    assert r2 / (2.0 * r1) - 1.0 == pytest.approx(e2_ref, abs=1e-12)

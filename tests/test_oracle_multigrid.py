@@ -116,3 +116,79 @@ def test_fgmres_zero_rhs():
     H = _hier()
     r = fgmres.solve(H, np.zeros(H.H.shape[0], np.complex128))
     assert r.iterations == 0 and r.converged and np.all(r.x == 0)
+
+
+# ---------------------------------------------------------------- restart branch of FGMRES
+@pytest.mark.parametrize("restart", [3, 4])
+def test_fgmres_restart_cycles_minimise_the_residual(restart):
+    """restarted FGMRES (Saad 1993): every restart cycle returns the iterate of smallest
+    residual norm over x_start + span(Z) of that cycle, checked against a dense least-squares
+    solve on the stored directions; cycles chain (each starts from the previous end, with the
+    true residual); the Givens estimate at a cycle's end is the true residual of its iterate;
+    iterations and restarts add up over the cycles."""
+    prob = synth.config1(16)
+    H = multigrid.from_problem(prob, nu_pre=1, nu_post=1)
+    b = prob.rhs()
+    trace = []
+    res = fgmres.solve(H, b, tol=1e-10, restart=restart, max_iter=400, trace=trace)
+    assert res.converged and res.true_rel_residual <= 1e-10
+    assert len(trace) >= 3                                    # several restarts happen
+    assert res.restarts == len(trace) - 1
+    assert res.iterations == sum(t["k"] for t in trace) == len(res.history)
+    assert all(t["k"] == restart for t in trace[:-1])
+    bn = np.linalg.norm(b)
+    A = H.H.toarray()
+    for c, t in enumerate(trace):
+        if c > 0:
+            assert np.array_equal(t["x_start"], trace[c - 1]["x_end"])
+        r0 = b - A @ t["x_start"]
+        y, *_ = np.linalg.lstsq(A @ t["Z"], r0, rcond=None)
+        x_ls = t["x_start"] + t["Z"] @ y
+        step = np.linalg.norm(t["x_end"] - t["x_start"])
+        # (late cycles take steps near the rounding level of x itself)
+        assert np.linalg.norm(t["x_end"] - x_ls) <= 1e-8 * step + 1e-13 * np.linalg.norm(t["x_end"]), c
+        true_rel = np.linalg.norm(b - A @ t["x_end"]) / bn
+        assert abs(t["est"] - true_rel) <= 1e-9 * max(true_rel, 1e-12) + 1e-14, (c, t["est"], true_rel)
+    # restarting changes the iterates but not the limit: same solution as restart = 20
+    ref = fgmres.solve(H, b, tol=1e-10, restart=20, max_iter=400)
+    assert np.linalg.norm(res.x - ref.x) <= 1e-7 * np.linalg.norm(ref.x)
+    assert res.iterations > ref.iterations
+
+
+# ---------------------------------------------------------------- cycle composition, eq. (2.1)
+def _dense_cycle_operator(H, gamma, nu1, nu2, w):
+    """M^{-1} of the 3-level cycle from a zero guess, composed from the matrix form of the
+    two-grid operator (eq. (2.1)): with S_l = I - w_l D_l^{-1} A_l,
+      E_2 = S_2^nu2 (I - P_2 A_3^{-1} R_2 A_2) S_2^nu1,   B_2 = (I - E_2^gamma) A_2^{-1}
+      (gamma cycles on level 2 from a zero guess, each on the updated residual),
+      E_1 = S_1^nu2 (I - P_1 B_2 R_1 A_1) S_1^nu1,        M^{-1} = (I - E_1) A_1^{-1}."""
+    A1, A2, A3 = (a.toarray() for a in H.A)
+    R1, R2 = H.R1.toarray(), H.R2.toarray()
+    P1, P2 = H.P1.toarray(), H.P2.toarray()
+    mp = np.linalg.matrix_power
+    I1, I2 = np.eye(A1.shape[0]), np.eye(A2.shape[0])
+    S1 = I1 - w[0] * (A1 / np.diag(A1)[:, None])
+    S2 = I2 - w[1] * (A2 / np.diag(A2)[:, None])
+    E2 = mp(S2, nu2) @ (I2 - P2 @ np.linalg.solve(A3, R2 @ A2)) @ mp(S2, nu1)
+    B2 = (I2 - mp(E2, gamma)) @ np.linalg.inv(A2)
+    E1 = mp(S1, nu2) @ (I1 - P1 @ B2 @ R1 @ A1) @ mp(S1, nu1)
+    return (I1 - E1) @ np.linalg.inv(A1)
+
+
+@pytest.mark.parametrize("n,gamma,nu", [((8, 8), 2, (1, 2)), ((8, 8), 1, (2, 1)), ((8, 8), 2, (0, 1)),
+                                        ((8, 4, 8), 2, (1, 2))])
+def test_cycle_equals_dense_composition_of_eq_2_1(n, gamma, nu):
+    """the recursive cycle (W: two level-2 visits, the second on the updated residual) equals,
+    column by column, the dense operator composed from eq. (2.1) with per-level damping weights
+    (0.6, 0.4), the level-2 shift alpha2 and the real-shifted coarsest operator."""
+    H = _hier(n, alpha=1.12, alpha2=1.03, beta=0.05, cycle=gamma, nu_pre=nu[0], nu_post=nu[1],
+              jacobi=(0.6, 0.4))
+    Md = _dense_cycle_operator(H, gamma, nu[0], nu[1], (0.6, 0.4))
+    N = H.A[0].shape[0]
+    cols = np.stack([H.precond(np.eye(N, dtype=np.complex128)[:, j]) for j in range(N)], 1)
+    assert np.max(np.abs(cols - Md)) <= 1e-12 * np.max(np.abs(Md))
+    # the composition is sensitive to what it pins: swapped weights or sweep counts differ
+    assert np.max(np.abs(_dense_cycle_operator(H, gamma, nu[0], nu[1], (0.4, 0.6)) - Md)) > 1e-3 * np.max(np.abs(Md))
+    if nu[0] != nu[1]:
+        assert np.max(np.abs(_dense_cycle_operator(H, gamma, nu[1], nu[0], (0.6, 0.4)) - Md)) > 1e-3 * np.max(np.abs(Md))
+    assert np.max(np.abs(_dense_cycle_operator(H, 3 - gamma, nu[0], nu[1], (0.6, 0.4)) - Md)) > 1e-6 * np.max(np.abs(Md))
