@@ -39,7 +39,10 @@
  * Errors: every call returns an int status.  0 = success, negative = error
  * (nothing was computed or the outputs are undefined), positive = warning
  * (outputs valid, see the code).  No exception crosses the ABI.  Argument
- * validation happens before any device call.
+ * validation happens before any device call.  The calls that work on one hierarchy
+ * (helm_refactor, helm_refactor_m, helm_apply, helm_vcycle, helm_coarse_solve,
+ * helm_solve, helm_grad_m, helm_get_coefficients, helm_get_info) return HELM_EINVAL for
+ * the parent context of helm_setup_batched.
  */
 #ifndef HELM_H
 #define HELM_H
@@ -122,6 +125,12 @@ int helm_setup(const helm_grid* grid, const double* slowness, double omega,
  * factorisation) for a new medium / frequency / shift on the same grid, reusing the
  * context's symbolic structure and workspace.  Arguments as in helm_setup. */
 int helm_refactor(helm_ctx* ctx, const double* slowness, double omega, const helm_shift* shift, void* stream);
+
+/* helm_refactor for a medium given as its squared slowness m = kappa^2 (device, N1 doubles,
+ * m > 0), the variable of eq. (1.1)'s coefficient k^2 = omega^2 m.  Callers that
+ * differentiate with respect to m (helm_grad_m) pass it here unchanged instead of forming
+ * sqrt(m) for helm_refactor to square again. */
+int helm_refactor_m(helm_ctx* ctx, const double* m, double omega, const helm_shift* shift, void* stream);
 
 /* y = H x (op HELM_OP_N) or y = H^H x (HELM_OP_C), the unshifted operator of eq. (1.1).
  * prec HELM_F64: x, y device c128[N1]; HELM_F32: x, y device c64[N1].  x != y. */

@@ -61,6 +61,7 @@ _SIG = {
     "helm_setup": (C.c_int, [C.POINTER(Grid), P, C.c_double, C.POINTER(Shift), C.POINTER(MG), P, C.c_size_t, P,
                              C.POINTER(P)]),
     "helm_refactor": (C.c_int, [P, P, C.c_double, C.POINTER(Shift), P]),
+    "helm_refactor_m": (C.c_int, [P, P, C.c_double, C.POINTER(Shift), P]),
     "helm_apply": (C.c_int, [P, C.c_int, C.c_int, P, P, P]),
     "helm_vcycle": (C.c_int, [P, C.c_int, P, P, P]),
     "helm_solve": (C.c_int, [P, C.c_int, P, P, C.c_double, C.c_int, C.POINTER(SolveInfo), P]),

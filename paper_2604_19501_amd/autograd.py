@@ -8,9 +8,11 @@ sources q_s, receivers given as flat node indices (sampling operator P) and data
 
     L(m) = 1/2 sum_s || P u_s - d_s ||^2,   H(m) u_s = q_s.
 
-The backward pass solves the adjoint systems H^H lambda_s = P^T (P u_s - d_s) with the
-same preconditioner on the conjugate-transpose operator (op = HELM_OP_C) and forms
-dL/dm_j = sum_s omega^2 Re(conj(lambda_s[j]) (1 - i sigma_j) u_s[j]) in the library's
+The medium is handed to the library as m itself (helm_refactor_m).  The backward pass
+first sets the solver up for the forward pass's medium again if it has been refactored
+since (another loss evaluated with the same solver), then solves the adjoint systems
+H^H lambda_s = P^T (P u_s - d_s) with the same preconditioner on the conjugate-transpose
+operator (op = HELM_OP_C) and forms dL/dm_j = sum_s omega^2 Re(conj(lambda_s[j]) (1 - i sigma_j) u_s[j]) in the library's
 gradient kernel.  A solver built with max_rhs > 1 solves the sources, and then the
 adjoint systems, in lock-step groups (Solver.solve_many); each solution equals the one of
 a separate solve.  Every solve and the gradient run in libhelm; this module only orders
@@ -45,7 +47,13 @@ def _solve_all(solver: Solver, rhs, tol, max_iter, op, what):
 class _Misfit(torch.autograd.Function):
     @staticmethod
     def forward(ctx, m, solver: Solver, sources, receivers, data, tol, max_iter):
-        solver.refactor(slowness=torch.sqrt(m.detach()).to(torch.float64))
+        md = m.detach().to(torch.float64).contiguous().clone()
+        solver.refactor(m=md)
+        # the medium, frequency and shifts the forward solves used: the backward pass needs the
+        # same operator, and the solver may have been set up for another medium meanwhile
+        ctx.m_saved, ctx.version = md, solver.medium_version
+        ctx.omega = solver.omega
+        ctx.shift = (solver.shift.alpha, solver.shift.alpha2, solver.shift.beta)
         us, res = [], []
         loss = torch.zeros((), dtype=torch.float64, device=m.device)
         sols = _solve_all(solver, sources, tol, max_iter, L.HELM_OP_N, "forward")
@@ -61,6 +69,9 @@ class _Misfit(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gout):
         solver = ctx.solver
+        if solver.medium_version != ctx.version:        # refactored since this forward pass
+            a, a2, b = ctx.shift
+            solver.refactor(m=ctx.m_saved, omega=ctx.omega, alpha=a, alpha2=a2, beta=b)
         rhss = []
         for r in ctx.res:
             rhs = torch.zeros(ctx.N, dtype=torch.complex128, device=r.device)

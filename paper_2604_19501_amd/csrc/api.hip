@@ -23,7 +23,7 @@ void gal_fine(const FineOp& op, cd s, const double* m, const Geom& gc, cd* out, 
 void gal_coarse(const Geom& g, const cd* A, const Geom& gc, cd* out, hipStream_t st);
 void cast_d2f(const cd* a, cf* b, long long n, hipStream_t st);
 void cast_f2d(const cf* a, cd* b, long long n, hipStream_t st);
-void square_slowness(const double* kap, double* m64, float* m32, long long n, hipStream_t st);
+void square_slowness(const double* kap, double* m64, float* m32, long long n, int is_m, hipStream_t st);
 void nd_zero(cd* p, long long n, hipStream_t s);
 void nd_iota(int* perm, const NDFrontDev* fr, int nfronts, hipStream_t s);
 void nd_assemble(const NDFrontDev* fr, const int* ids, int nids, int max_asm, const NDAsm* asmv, const cd* coef,
@@ -46,9 +46,6 @@ void nd_fwd(const NDLaunchDev& L, const NDFrontDev* fr, const int* idx, const in
 int panel_reg_kb(int nF);
 void nd_panel_reg(const NDFrontDev* fr, const int* ids, int nids, int max_nF, cd* Fp, int* perm, int* swp, int k0,
                   int kb, int* err, hipStream_t s);
-template <typename C>
-void nd_flow(const NDFlowDev& d, const NDFrontDev* fr, const int* idx, const int* cptr, const int* cidx, const C* Lp,
-             const C* Wp, C* upd, const C* r, C* x, C* gbuf, int conj, hipStream_t s);
 template <typename C>
 void nd_bwd(const NDLaunchDev& L, const NDFrontDev* fr, const int* idx, const int* cidx, const C* Wp, C* upd, C* x,
             C* gvec, int cap, int conj, C* gbuf, C* P, const NDRhs& rh, hipStream_t s);
@@ -111,8 +108,6 @@ struct NDDev {        // device-side ND tables (pointers into the workspace)
   void *gbuf = nullptr, *part = nullptr;     // split-K launches: gathered vectors, partial products
   std::vector<NDLaunchDev> launch[2];   // forward, backward
   int gvec_cap = 0;
-  NDFlowDev flow;                       // dataflow substitution (one launch per solve)
-  void* fgbuf = nullptr;                // its gather buffer
   long long gbuf_n = 1, part_n = 1, gvec_n = 0;   // entries per right-hand side of gbuf, part, gvec
 };
 
@@ -150,8 +145,6 @@ struct helm_ctx {
        *x3 = nullptr;
   cd *r3d = nullptr, *e3d = nullptr;
   NDPlan plan;
-  NDFlow flow;          // dataflow task queue (used when use_flow)
-  int use_flow = 0;
   NDDev nd;
   std::vector<HeightInfo> hinfo;
   std::vector<long long> hlist_toff;
@@ -189,6 +182,7 @@ struct helm_ctx {
   double gtol[2] = {-1.0, -1.0};
   int gnr[2] = {0, 0};          // right-hand side count the graphs were captured for
   int graphs = 1;
+  double arnoldi_guard = 1e-8;  // relative size of ||w - V c||^2 below which an Arnoldi column ends the cycle
 };
 
 namespace {
@@ -215,6 +209,13 @@ int validate(const helm_grid* g, const helm_mg* mg) {
   long long N1 = 1;
   for (int a = 0; a < g->dim; ++a) N1 *= (g->n[a] + 1);
   if (N1 > (1LL << 31) - 1) return fail(HELM_EINVAL, "grid too large (N1 > 2^31-1)");
+  return HELM_OK;
+}
+
+// the calls that work on one hierarchy refuse the parent of a batched context: its
+// instances live in its sub-contexts, and it holds no device state of its own
+int need_single(const helm_ctx* c, const char* who) {
+  if (!c->sub.empty()) return fail(HELM_EINVAL, "%s takes a single-instance context (this one is batched)", who);
   return HELM_OK;
 }
 
@@ -330,10 +331,6 @@ void build_plan(helm_ctx* c) {
   const int tree_waves = env_int("HELM_ND_TREE_WAVES", c->grid.dim == 3 ? 8 : 16);
   nd_plan(c->g3, leaf, 16, merge, (int)c->csz, lds, cuts, splitk, c->plan, tree_waves);
   NDPlan& P = c->plan;
-  // HELM_ND_FLOW=1: the substitutions run as one dataflow launch each solve
-  // (heights above the tree-block launches)
-  c->use_flow = env_int("HELM_ND_FLOW", 0);
-  if (c->use_flow) nd_flow_plan(P, P.cuts.empty() || P.cuts[0] < 0 ? 0 : P.cuts.back() + 1, c->flow);
   c->hlist.clear();
   c->hlist_toff.clear();
   c->hinfo.clear();
@@ -478,18 +475,6 @@ size_t carve(helm_ctx* c, void* ws) {
   d.part_n = part_max;
   d.gbuf = cv.take<char>(rc * cs * gbuf_max);
   d.part = cv.take<char>(rc * cs * part_max);
-  if (c->use_flow) {
-    const NDFlow& F = c->flow;
-    d.flow.tasks = cv.take<NDFlowTask>(std::max<size_t>(1, F.tasks.size()));
-    d.flow.sigs = cv.take<int>(std::max<size_t>(1, F.sigs.size()));
-    d.flow.ctr = cv.take<int>(F.nctr + 3);
-    d.flow.ntasks = (int)F.tasks.size();
-    d.flow.nctr = F.nctr;
-    d.flow.vec_max = F.vec_max;
-    d.flow.grid = std::max(1, std::min(d.flow.ntasks, env_int("HELM_ND_FLOW_GRID", 2048)));
-    d.flow.spin_limit = env_int("HELM_ND_FLOW_SPIN", 1 << 20);
-    d.fgbuf = cv.take<char>(cs * F.gbuf);
-  }
   // Krylov
   c->V = cv.take<cd>(rc * (m + 1) * g1.tot);
   c->Z = cv.take<char>(rc * cs * (size_t)m * g1.tot);
@@ -615,22 +600,6 @@ void nd_solve(helm_ctx* c, const C* r, C* x, int conj, hipStream_t s) {
   rh.gbuf = d.gbuf_n;
   rh.part = d.part_n;
   rh.gvec = d.gvec_n;
-  if (c->use_flow && c->nr == 1) {      // tree-block launches, the dataflow launch, tree-block launches
-    for (const NDLaunchDev& L : d.launch[0])
-      if (L.kind == 2)
-        TIMED(c, KT_ND_FWD, s,
-              nd_fwd<C>(L, d.fronts, d.idx, d.cptr, d.cidx, (const C*)d.L, (C*)d.upd, r, x, nullptr, 0, conj,
-                        (C*)d.gbuf, (C*)d.part, rh, s));
-    TIMED(c, KT_ND_FWD, s,
-          nd_flow<C>(d.flow, d.fronts, d.idx, d.cptr, d.cidx, (const C*)d.L, (const C*)d.W, (C*)d.upd, r, x,
-                     (C*)d.fgbuf, conj, s));
-    for (const NDLaunchDev& L : d.launch[1])
-      if (L.kind == 2)
-        TIMED(c, KT_ND_BWD, s,
-              nd_bwd<C>(L, d.fronts, d.idx, d.cidx, (const C*)d.W, (C*)d.upd, x, nullptr, 0, conj, (C*)d.gbuf,
-                        (C*)d.part, rh, s));
-    return;
-  }
   for (const NDLaunchDev& L : d.launch[0]) {
     C* gv = L.kind == 1 && L.shm == 0 ? (C*)d.gvec : nullptr;
     TIMED(c, KT_ND_FWD, s,
@@ -646,12 +615,13 @@ void nd_solve(helm_ctx* c, const C* r, C* x, int conj, hipStream_t s) {
 }
 
 
-// a0-a3: coefficients, Galerkin operators, real-shifted coarsest operator, factorisation
-void numeric_setup(helm_ctx* c, const double* slowness, hipStream_t s) {
+// a0-a3: coefficients, Galerkin operators, real-shifted coarsest operator, factorisation.
+// medium: the slowness kappa (is_m = 0) or its square m (is_m = 1) at every node
+void numeric_setup(helm_ctx* c, const double* medium, int is_m, hipStream_t s) {
   const helm_shift* shift = &c->shift;
   const double omega = c->omega;
   // a0: m = kappa^2 (FP64 and FP32)
-  square_slowness(slowness, c->m64, c->m32, c->g1.tot, s);
+  square_slowness(medium, c->m64, c->m32, c->g1.tot, is_m, s);
   // a1: level-2 Galerkin operator of H_beta^{alpha2}
   gal_fine(c->op, shift_scalar(shift->alpha2, shift->beta, omega), c->m64, c->g2, c->coef2_64, s);
   const int K = stencil_points(c->grid.dim);
@@ -791,6 +761,7 @@ KrylovArgs make_kargs(helm_ctx* c, int op) {
   a.st = c->st;
   a.nrhs = c->nr;
   a.pstride = (long long)(2 * KMAXM + 3) * a.pcap;
+  a.guard = c->arnoldi_guard;
   return a;
 }
 
@@ -1057,6 +1028,8 @@ static int setup_rcap(const helm_grid* grid, const double* slowness, double omeg
     c->omega = omega;
     c->rcap = rcap;
     c->graphs = env_int("HELM_GRAPHS", 1);
+    // HELM_ARNOLDI_GUARD (tests): the cancellation threshold of the Arnoldi norm formula
+    if (const char* g = getenv("HELM_ARNOLDI_GUARD")) c->arnoldi_guard = atof(g);
     init_geometry(c.get());
     build_plan(c.get());
     size_t need = carve(c.get(), nullptr);
@@ -1098,11 +1071,6 @@ static int setup_rcap(const helm_grid* grid, const double* slowness, double omeg
       up(d.hfr, hf, s);
     }
     up(d.toff, c->hlist_toff, s);
-    if (c->use_flow) {
-      up((NDFlowTask*)d.flow.tasks, c->flow.tasks, s);
-      up((int*)d.flow.sigs, c->flow.sigs, s);
-      CK(hipMemsetAsync(d.flow.ctr, 0, sizeof(int) * (c->flow.nctr + 3), s));
-    }
     for (int fb = 0; fb < 2; ++fb) {
       std::vector<NDLaunch>& Ls = fb == 0 ? P.fwd : P.bwd;
       for (size_t l = 0; l < Ls.size(); ++l) {
@@ -1125,7 +1093,7 @@ static int setup_rcap(const helm_grid* grid, const double* slowness, double omeg
         }
       }
     }
-    numeric_setup(c.get(), slowness, s);
+    numeric_setup(c.get(), slowness, 0, s);
     CK(hipEventRecord(e1, s));
     CK(hipStreamSynchronize(s));
     CK(hipGetLastError());
@@ -1156,9 +1124,10 @@ int helm_setup(const helm_grid* grid, const double* slowness, double omega, cons
   return setup_rcap(grid, slowness, omega, shift, mg, 1, ws, ws_bytes, stream, out);
 }
 
-int helm_refactor(helm_ctx* c, const double* slowness, double omega, const helm_shift* shift, void* stream) {
-  if (!c || !slowness || !shift) return fail(HELM_EINVAL, "NULL argument");
-  if (!c->sub.empty()) return fail(HELM_EINVAL, "helm_refactor takes a single-instance context");
+static int refactor_impl(helm_ctx* c, const double* medium, int is_m, double omega, const helm_shift* shift,
+                         void* stream) {
+  if (!c || !medium || !shift) return fail(HELM_EINVAL, "NULL argument");
+  if (int v = need_single(c, "helm_refactor")) return v;
   if (!(omega > 0.0) || !std::isfinite(omega)) return fail(HELM_EINVAL, "omega must be positive and finite");
   if (!std::isfinite(shift->alpha) || !std::isfinite(shift->alpha2) || !std::isfinite(shift->beta))
     return fail(HELM_EINVAL, "shift parameters must be finite");
@@ -1169,7 +1138,7 @@ int helm_refactor(helm_ctx* c, const double* slowness, double omega, const helm_
       drop_graphs(c);          // captured kernel arguments hold the shifted coefficients' scalars
     c->omega = omega;
     c->shift = *shift;
-    numeric_setup(c, slowness, s);
+    numeric_setup(c, medium, is_m, s);
     int err = 0;
     CK(hipMemcpyAsync(c->hstate, c->nd.err, sizeof(int), hipMemcpyDeviceToHost, s));
     CK(hipStreamSynchronize(s));
@@ -1179,6 +1148,14 @@ int helm_refactor(helm_ctx* c, const double* slowness, double omega, const helm_
     return fail(HELM_EDEVICE, "%s", e.what());
   }
   return HELM_OK;
+}
+
+int helm_refactor(helm_ctx* c, const double* slowness, double omega, const helm_shift* shift, void* stream) {
+  return refactor_impl(c, slowness, 0, omega, shift, stream);
+}
+
+int helm_refactor_m(helm_ctx* c, const double* m, double omega, const helm_shift* shift, void* stream) {
+  return refactor_impl(c, m, 1, omega, shift, stream);
 }
 
 int helm_destroy(helm_ctx* ctx) {
@@ -1200,6 +1177,7 @@ int helm_apply(helm_ctx* c, int op, int prec, const void* x, void* y, void* stre
   if (op != HELM_OP_N && op != HELM_OP_C) return fail(HELM_EINVAL, "op must be HELM_OP_N or HELM_OP_C");
   if (prec != HELM_F64 && prec != HELM_F32) return fail(HELM_EINVAL, "prec must be HELM_F64 or HELM_F32");
   if (x == y) return fail(HELM_EINVAL, "x and y must differ");
+  if (int v = need_single(c, "helm_apply")) return v;
   hipStream_t s = (hipStream_t)stream;
   try {
     if (prec == HELM_F64) {
@@ -1228,6 +1206,7 @@ int helm_vcycle(helm_ctx* c, int op, const void* r, void* z, void* stream) {
   if (!c || !r || !z) return fail(HELM_EINVAL, "NULL argument");
   if (op != HELM_OP_N && op != HELM_OP_C) return fail(HELM_EINVAL, "op must be HELM_OP_N or HELM_OP_C");
   if (r == z) return fail(HELM_EINVAL, "r and z must differ");
+  if (int v = need_single(c, "helm_vcycle")) return v;
   hipStream_t s = (hipStream_t)stream;
   c->nr = 1;
   try {
@@ -1249,6 +1228,7 @@ int helm_coarse_solve(helm_ctx* c, int op, const void* r, void* e, void* stream)
   if (!c || !r || !e) return fail(HELM_EINVAL, "NULL argument");
   if (op != HELM_OP_N && op != HELM_OP_C) return fail(HELM_EINVAL, "op must be HELM_OP_N or HELM_OP_C");
   if (r == e) return fail(HELM_EINVAL, "r and e must differ");
+  if (int v = need_single(c, "helm_coarse_solve")) return v;
   hipStream_t s = (hipStream_t)stream;
   c->nr = 1;
   try {
@@ -1273,20 +1253,12 @@ int helm_solve(helm_ctx* c, int op, const void* rhs, void* x, double tol, int ma
   if (!(tol > 0.0) || !std::isfinite(tol)) return fail(HELM_EINVAL, "tol must be positive");
   if (max_iter < 1) return fail(HELM_EINVAL, "max_iter must be >= 1");
   if (rhs == x) return fail(HELM_EINVAL, "rhs and x must differ");
+  if (int v = need_single(c, "helm_solve")) return v;
   hipStream_t s = (hipStream_t)stream;
   try {
     int st = c->f32 ? solve_impl<float>(c, op, 1, (const cd*)rhs, (cd*)x, tol, max_iter, info, s)
                     : solve_impl<double>(c, op, 1, (const cd*)rhs, (cd*)x, tol, max_iter, info, s);
     CK(hipGetLastError());
-    if (c->use_flow) {     // a dataflow wait that gave up leaves its flag (the stream is idle here)
-      int* flag = c->nd.flow.ctr + c->nd.flow.nctr + 2;
-      int e = 0;
-      CK(hipMemcpy(&e, flag, sizeof(int), hipMemcpyDeviceToHost));
-      if (e) {
-        CK(hipMemset(flag, 0, sizeof(int)));
-        return fail(HELM_EDEVICE, "coarsest-grid substitution: a dataflow wait timed out");
-      }
-    }
     return st;
   } catch (DevErr& e) {
     return fail(HELM_EDEVICE, "%s", e.what());
@@ -1373,6 +1345,7 @@ long long helm_level_size(helm_ctx* c, int inst, int lev) {
 int helm_get_coefficients(helm_ctx* c, int lev, double* out) {
   if (!c || !out) return fail(HELM_EINVAL, "NULL argument");
   if (lev != 2 && lev != 3) return fail(HELM_EINVAL, "lev must be 2 or 3");
+  if (int v = need_single(c, "helm_get_coefficients")) return v;
   try {
     const Geom& g = lev == 2 ? c->g2 : c->g3;
     const cd* src = lev == 2 ? c->coef2_64 : c->coef3_64;
@@ -1389,6 +1362,7 @@ int helm_grad_m(helm_ctx* c, int n_src, const void* const* u, const void* const*
   if (!c || !u || !lambda || !g || n_src < 1) return fail(HELM_EINVAL, "bad arguments");
   for (int k = 0; k < n_src; ++k)
     if (!u[k] || !lambda[k]) return fail(HELM_EINVAL, "NULL source pointer %d", k);
+  if (int v = need_single(c, "helm_grad_m")) return v;
   hipStream_t s = (hipStream_t)stream;
   try {
     for (int k = 0; k < n_src; ++k)

@@ -146,10 +146,11 @@ __global__ void k_cast_d2f(const cd* __restrict__ a, cf* __restrict__ b, long lo
     b[i] = to_f(a[i]);
 }
 
+// m = kappa^2 from the slowness (is_m = 0), or m taken as given (is_m = 1)
 __global__ void k_square(const double* __restrict__ kap, double* __restrict__ m64, float* __restrict__ m32,
-                         long long n) {
+                         long long n, int is_m) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-    double v = kap[i] * kap[i];
+    double v = is_m ? kap[i] : kap[i] * kap[i];
     m64[i] = v;
     m32[i] = (float)v;
   }
@@ -168,8 +169,8 @@ void gal_coarse(const Geom& g, const cd* A, const Geom& gc, cd* out, hipStream_t
 void cast_d2f(const cd* a, cf* b, long long n, hipStream_t st) {
   hipLaunchKernelGGL(k_cast_d2f, dim3(1024), dim3(256), 0, st, a, b, n);
 }
-void square_slowness(const double* kap, double* m64, float* m32, long long n, hipStream_t st) {
-  hipLaunchKernelGGL(k_square, dim3(1024), dim3(256), 0, st, kap, m64, m32, n);
+void square_slowness(const double* kap, double* m64, float* m32, long long n, int is_m, hipStream_t st) {
+  hipLaunchKernelGGL(k_square, dim3(1024), dim3(256), 0, st, kap, m64, m32, n, is_m);
 }
 
 }  // namespace helm

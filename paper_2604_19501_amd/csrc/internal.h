@@ -262,43 +262,6 @@ struct NDLaunchDev {    // device copy of an NDLaunch, as the kernels see it
   const NDRowTile* rtiles = nullptr;
 };
 
-// Dataflow substitution: one persistent launch per solve works through a queue of tasks
-// in an order that respects the tree (forward by height, then backward by height
-// descending); a task waits for one counter to reach a target and, when done, increments
-// a list of counters.  Counters per front f: 4f children's forward tasks done, 4f+1 the
-// front's solution final, 4f+2 forward gather done, 4f+3 backward gather done.
-struct NDFlowTask {
-  int kind;          // 0 forward rows (gather in the task), 1 forward gather, 2 forward rows from
-                     // the gathered vector, 3 backward rows, 4 backward gather, 5 backward rows
-                     // from the gathered vector
-  int front;
-  int r0, r1;        // rows of the front's factor block (one pass of rt rows)
-  int wait, target;  // counter and value to wait for (target 0: no wait)
-  int sig0, nsig;    // counters incremented when done: sigs[sig0 .. sig0 + nsig)
-  int rt;            // rows per pass: 256 / rt threads share a row's columns
-  int pad;
-  long long goff;    // gathered vector (kinds 1, 2, 4, 5) in the gather buffer
-};
-
-struct NDFlow {
-  std::vector<NDFlowTask> tasks;
-  std::vector<int> sigs;
-  int nctr = 0;          // counters (4 per front)
-  int nfwd = 0;          // tasks of the forward part
-  long long gbuf = 0;    // entries of the gather buffer
-  int vec_max = 1;       // entries of a task's LDS vector
-  int h_lo = 0;          // lowest height queued
-};
-
-
-struct NDFlowDev {     // device copy of an NDFlow
-  const NDFlowTask* tasks = nullptr;
-  const int* sigs = nullptr;
-  int* ctr = nullptr;    // nctr counters, then queue head, exit count, error flag (zeroed at set-up)
-  int ntasks = 0, nctr = 0, vec_max = 1, grid = 1;
-  int spin_limit = 1 << 20;
-};
-
 struct NDPlan {
   Geom g;                               // level-3 geometry
   std::vector<NDFrontDev> fronts;
@@ -324,7 +287,5 @@ struct NDPlan {
 void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int root_merge, int elem_bytes, int lds_bytes,
              const std::vector<int>& cuts, long long splitk_bytes, NDPlan& plan, int tree_waves = 16);
 
-// the dataflow task queue of a plan's heights >= h_lo
-void nd_flow_plan(const NDPlan& plan, int h_lo, NDFlow& flow);
 
 }  // namespace helm

@@ -44,6 +44,7 @@ struct KrylovArgs {
   KrylovState* st;
   int nrhs;
   long long pstride;
+  double guard;        // ||w - V c||^2 below guard ||w||^2 ends the restart cycle (cancellation)
 };
 
 void kr_init(const KrylovArgs& a, int max_iter, hipStream_t s);

@@ -260,6 +260,12 @@ __global__ void __launch_bounds__(64) k_givens(KrylovArgs a, int j, double tol) 
     }
     const double n2 = nw2 - 2.0 * ch + cgc;     // ||w - V c||^2
     const double hn = n2 > 0.0 ? sqrt(n2) : 0.0;
+    // the formula subtracts quantities of size ||w||^2: when ||w - V c|| << ||w|| (w almost
+    // in the span of the basis) its rounding error swamps the value, so the column's
+    // h_{j+1,j} and the next basis vector cannot be trusted.  The column is kept (its
+    // rotation uses hn, which only enters through c^2 + hn^2 there) and the cycle ends:
+    // the solution is updated and the restart recomputes the true residual in FP64.
+    const bool cancel = n2 < a.guard * nw2;
     for (int i = 0; i <= j; ++i) col[i] = sc[i];
     col[j + 1] = mk(hn, 0.0);
     st->hnext = hn;
@@ -285,7 +291,7 @@ __global__ void __launch_bounds__(64) k_givens(KrylovArgs a, int j, double tol) 
     st->kcols = j + 1;
     bool fin = isfinite(est) && isfinite(hn);
     if (!fin) st->nonfinite = 1;
-    st->done = (est <= tol || !fin || hn == 0.0 || its + 1 >= maxit) ? 1 : 0;
+    st->done = (est <= tol || !fin || hn == 0.0 || cancel || its + 1 >= maxit) ? 1 : 0;
   }
   __syncthreads();
   for (int i = t; i <= j + 1; i += 64) st->H[i + ld * j] = col[i];

@@ -1184,202 +1184,4 @@ template void nd_bwd<cd>(const NDLaunchDev&, const NDFrontDev*, const int*, cons
                          int, cd*, cd*, const NDRhs&, hipStream_t);
 
 
-// ---- dataflow substitution -------------------------------------------------
-// Row task products: rows [r0, r1) (at most rt) of M (column-major, leading dimension ld)
-// times v[0 .. K).  Thread t takes row t mod rt and the column slice t / rt; slices are
-// summed within a wavefront by shuffles, then over the four wavefronts in a fixed order.
-// The sum for row r0 + t is returned to threads t < rt.  The thread's matrix entries (at
-// most 32, column kb + q in m[q]) are loaded before the task's wait.
-template <typename C>
-__device__ __forceinline__ void flow_load(const C* __restrict__ M, long long ld, int r0, int r1, int K, int rt,
-                                          C (&m)[32]) {
-  const int tid = threadIdx.x, ks = tid / rt, row = tid - ks * rt, nks = 256 / rt;
-  const int i = min(r0 + row, r1 - 1);
-  const int kq = (K + nks - 1) / nks, kb = ks * kq, ke = min(K, kb + kq);
-  const C* col = M + i;
-#pragma unroll
-  for (int q = 0; q < 32; ++q) m[q] = col[(long long)max(0, min(kb + q, ke - 1)) * ld];
-}
-template <typename C>
-__device__ __forceinline__ C flow_gemv_pre(const C (&m)[32], int r0, int r1, int K, const C* v, int conj, int rt,
-                                           C* red) {
-  typedef decltype(v[0].x) R;
-  const int tid = threadIdx.x, ks = tid / rt, row = tid - ks * rt, nks = 256 / rt;
-  const int i = r0 + row;
-  const int kq = (K + nks - 1) / nks, kb = ks * kq, ke = min(K, kb + kq);
-  C acc = mk((R)0, (R)0);
-  if (i < r1)
-#pragma unroll
-    for (int q = 0; q < 32; ++q)
-      if (kb + q < ke) acc += cmul_conj(m[q], v[kb + q], conj);
-  if (rt < 64)
-    for (int o = rt; o < 64; o <<= 1) {
-      acc.x += __shfl_xor(acc.x, o, 64);
-      acc.y += __shfl_xor(acc.y, o, 64);
-    }
-  red[tid] = acc;
-  __syncthreads();
-  C tot = mk((R)0, (R)0);
-  if (tid < rt) {
-    if (rt < 64)
-      for (int q = 0; q < 4; ++q) tot += red[q * 64 + tid];
-    else
-      for (int q = 0; q < nks; ++q) tot += red[q * rt + tid];
-  }
-  return tot;
-}
-
-__device__ __forceinline__ int ld_agent(const int* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ int add_agent(int* p, int v) {
-  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Values passed between the launch's work-groups (x, the update vectors, the gathered
-// vectors) are written and read at device scope (written through to, and read from, the
-// level that all XCDs share), 8 bytes at a time; this replaces cache-wide release and
-// acquire fences, which cost about 60 ns each per work-group on this chip.
-__device__ __forceinline__ cf ld_coh(const cf* p) {
-  const unsigned long long u =
-      __hip_atomic_load((const unsigned long long*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  return __builtin_bit_cast(cf, u);
-}
-__device__ __forceinline__ void st_coh(cf* p, cf v) {
-  __hip_atomic_store((unsigned long long*)p, __builtin_bit_cast(unsigned long long, v), __ATOMIC_RELAXED,
-                     __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ cd ld_coh(const cd* p) {
-  const double* d = (const double*)p;
-  return mk(__hip_atomic_load(d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
-            __hip_atomic_load(d + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-}
-__device__ __forceinline__ void st_coh(cd* p, cd v) {
-  double* d = (double*)p;
-  __hip_atomic_store(d, v.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  __hip_atomic_store(d + 1, v.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-template <typename C>
-__device__ __forceinline__ C gather_coh(const NDFrontDev& f, const int* __restrict__ cptr, const int* __restrict__ cidx,
-                                        const int* __restrict__ id, const C* upd, const C* __restrict__ r, int i) {
-  typedef decltype(r[0].x) R;
-  C v = i < f.nS ? r[id[i]] : mk((R)0, (R)0);
-  const int* cp = cptr + f.inv_off;
-  const int a = cp[i], b = cp[i + 1];
-  for (int q = a; q < b; ++q) v += ld_coh(upd + cidx[q]);
-  return v;
-}
-
-// One launch runs both substitutions of the heights it was planned for: every work-group
-// claims task indices from a counter (the next one while it works on the current one)
-// and, for each, waits for its counter, does the work, waits for its stores to complete
-// and increments the counters of the tasks that depend on it.  Tasks are queued so that a
-// task only waits for tasks queued before it, which work-groups already running hold, so
-// the launch cannot deadlock however many of its work-groups are resident.  A wait gives
-// up after spin_limit polls and raises the error flag.  The last work-group to leave
-// clears the counters and the queue for the next launch (the error flag stays).
-template <typename C>
-__global__ void __launch_bounds__(256) k_nd_flow(const NDFlowTask* __restrict__ tasks, int ntasks,
-                                                 const int* __restrict__ sigs, int* ctr, int nctr,
-                                                 const NDFrontDev* __restrict__ fr, const int* __restrict__ idx,
-                                                 const int* __restrict__ cptr, const int* __restrict__ cidx,
-                                                 const C* __restrict__ Lp, const C* __restrict__ Wp, C* upd,
-                                                 const C* __restrict__ r, C* x, C* gbuf, int conj, int spin_limit) {
-  extern __shared__ __align__(16) char smem[];
-  C* lvec = (C*)smem;
-  __shared__ C red[256];
-  __shared__ int s_next;
-  int* head = ctr + nctr;
-  int* exitc = head + 1;
-  int* err = head + 2;
-  const int tid = threadIdx.x;
-  if (tid == 0) s_next = add_agent(head, 1);
-  __syncthreads();
-  int t = __builtin_amdgcn_readfirstlane(s_next);
-  while (t < ntasks) {
-    const NDFlowTask T = tasks[t];
-    const NDFrontDev f = fr[T.front];
-    const int* id = idx + f.idx_off;
-    // the factor entries of a row task do not depend on the wait: load them first
-    C m[32];
-    if (T.kind == 0 || T.kind == 2)
-      flow_load(Lp + f.L_off, f.nF, T.r0, T.r1, f.nS, T.rt, m);
-    else if (T.kind == 3 || T.kind == 5)
-      flow_load(Wp + f.W_off, f.nS, T.r0, T.r1, f.nB, T.rt, m);
-    __syncthreads();
-    if (tid == 0) {
-      s_next = add_agent(head, 1);
-      if (T.target > 0) {
-        int n = 0;
-        while (ld_agent(ctr + T.wait) < T.target) {
-          if (++n > spin_limit || ld_agent(err)) {      // after one wait gave up, none waits
-            __hip_atomic_fetch_or(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-        }
-      }
-    }
-    __syncthreads();
-    if (T.kind == 0 || T.kind == 2) {                 // forward rows
-      // LDS: the input f_S at [0, nS), then the B entries of this task's rows at nS + (i - r0)
-      const int b0 = max(T.r0, f.nS);
-      if (T.kind == 0) {
-        for (int i = tid; i < f.nS; i += 256) lvec[i] = gather_coh(f, cptr, cidx, id, upd, r, i);
-        for (int i = b0 + tid; i < T.r1; i += 256) lvec[f.nS + i - T.r0] = gather_coh(f, cptr, cidx, id, upd, r, i);
-      } else {
-        for (int i = tid; i < f.nS; i += 256) lvec[i] = ld_coh(gbuf + T.goff + i);
-        for (int i = b0 + tid; i < T.r1; i += 256) lvec[f.nS + i - T.r0] = ld_coh(gbuf + T.goff + i);
-      }
-      __syncthreads();
-      const C acc = flow_gemv_pre(m, T.r0, T.r1, f.nS, (const C*)lvec, conj, T.rt, red);
-      const int i = T.r0 + tid;
-      if (tid < T.rt && i < T.r1) {
-        if (i < f.nS)
-          st_coh(x + id[i], acc);
-        else
-          st_coh(upd + f.upd_off + i - f.nS, lvec[f.nS + i - T.r0] - acc);
-      }
-    } else if (T.kind == 1) {                        // forward gather
-      for (int i = tid; i < f.nF; i += 256) st_coh(gbuf + T.goff + i, gather_coh(f, cptr, cidx, id, upd, r, i));
-    } else if (T.kind == 4) {                        // backward gather
-      for (int k = tid; k < f.nB; k += 256) st_coh(gbuf + T.goff + k, ld_coh(x + id[f.nS + k]));
-    } else {                                         // backward rows
-      if (T.kind == 3)
-        for (int k = tid; k < f.nB; k += 256) lvec[k] = ld_coh(x + id[f.nS + k]);
-      else
-        for (int k = tid; k < f.nB; k += 256) lvec[k] = ld_coh(gbuf + T.goff + k);
-      __syncthreads();
-      const C acc = flow_gemv_pre(m, T.r0, T.r1, f.nB, (const C*)lvec, conj, T.rt, red);
-      const int i = T.r0 + tid;
-      if (tid < T.rt && i < T.r1) st_coh(x + id[i], ld_coh(x + id[i]) + acc);
-    }
-    __builtin_amdgcn_s_waitcnt(0);                   // this work-group's stores have completed
-    __syncthreads();
-    if (tid == 0)
-      for (int q = 0; q < T.nsig; ++q) add_agent(ctr + sigs[T.sig0 + q], 1);
-    t = __builtin_amdgcn_readfirstlane(s_next);
-  }
-  __syncthreads();
-  if (tid == 0) s_next = add_agent(exitc, 1) == (int)gridDim.x - 1;
-  __syncthreads();
-  if (s_next)
-    for (int i = tid; i < nctr + 2; i += 256) __hip_atomic_store(ctr + i, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-template <typename C>
-void nd_flow(const NDFlowDev& d, const NDFrontDev* fr, const int* idx, const int* cptr, const int* cidx, const C* Lp,
-             const C* Wp, C* upd, const C* r, C* x, C* gbuf, int conj, hipStream_t s) {
-  if (d.ntasks <= 0) return;
-  const size_t lds = (size_t)d.vec_max * sizeof(C);
-  if (lds > 65536) (void)hipFuncSetAttribute((const void*)k_nd_flow<C>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL((k_nd_flow<C>), dim3(d.grid), dim3(256), lds, s, d.tasks, d.ntasks, d.sigs, d.ctr, d.nctr, fr, idx,
-                     cptr, cidx, Lp, Wp, upd, r, x, gbuf, conj, d.spin_limit);
-}
-template void nd_flow<cf>(const NDFlowDev&, const NDFrontDev*, const int*, const int*, const int*, const cf*, const cf*,
-                          cf*, const cf*, cf*, cf*, int, hipStream_t);
-template void nd_flow<cd>(const NDFlowDev&, const NDFrontDev*, const int*, const int*, const int*, const cd*, const cd*,
-                          cd*, const cd*, cd*, cd*, int, hipStream_t);
-
 }  // namespace helm

@@ -694,111 +694,4 @@ void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int root_merge, int e
 }
 
 
-// ---- dataflow task queue --------------------------------------------------
-// Only the fronts of heights >= h_lo are queued (the tree-block launches take the lower
-// heights before and after).
-// Row tasks: a work-group of 256 threads takes rt rows, 256 / rt threads per row splitting
-// the columns so that no thread has more than 32 (rt >= 4).  A front whose forward (or
-// backward) part needs 8 or more row tasks gets one gather task writing the vector to the
-// gather buffer, which its row tasks then read.  A task stages in LDS its input vector
-// and, forward, the boundary entries of its own rows.
-void nd_flow_plan(const NDPlan& plan, int h_lo, NDFlow& flow) {
-  const int nf = (int)plan.fronts.size();
-  flow = NDFlow();
-  flow.nctr = 4 * nf;
-  flow.h_lo = h_lo;
-  std::vector<int> parent(nf, -1);
-  for (int f = 0; f < nf; ++f) {
-    const NDFrontDev& F = plan.fronts[f];
-    for (int q = 0; q < F.nchild; ++q) parent[plan.children[F.child_off + q]] = f;
-  }
-  auto rows_geom = [](int K, int& rt) {
-    int ks = 1;
-    while (ks < 64 && (K + ks - 1) / ks > 32) ks *= 2;
-    rt = 256 / ks;
-  };
-  std::vector<int> rtF(nf), ntF(nf), rtB(nf), ntB(nf, 0);
-  std::vector<char> gF(nf), gB(nf);
-  for (int f = 0; f < nf; ++f) {
-    const NDFrontDev& F = plan.fronts[f];
-    rows_geom(F.nS, rtF[f]);
-    ntF[f] = (F.nF + rtF[f] - 1) / rtF[f];
-    gF[f] = ntF[f] >= 8;
-    if (F.nB > 0) {
-      if (parent[f] < 0) throw std::runtime_error("nd_flow_plan: front with a boundary but no parent");
-      rows_geom(F.nB, rtB[f]);
-      ntB[f] = (F.nS + rtB[f] - 1) / rtB[f];
-      gB[f] = ntB[f] >= 8;
-    }
-  }
-  auto U = [](int f) { return 4 * f; };
-  auto D = [](int f) { return 4 * f + 1; };
-  auto GF = [](int f) { return 4 * f + 2; };
-  auto GB = [](int f) { return 4 * f + 3; };
-  auto add = [&](int kind, int f, int r0, int r1, int wait, int target, std::vector<int> sig, int rt, long long goff) {
-    NDFlowTask t{};
-    t.kind = kind;
-    t.front = f;
-    t.r0 = r0;
-    t.r1 = r1;
-    t.wait = target > 0 ? wait : 0;
-    t.target = target;
-    t.sig0 = (int)flow.sigs.size();
-    t.nsig = (int)sig.size();
-    for (int q : sig) flow.sigs.push_back(q);
-    t.rt = rt;
-    t.goff = goff;
-    flow.tasks.push_back(t);
-  };
-  // fronts below h_lo are substituted by other launches (before and after this one): a
-  // front at h_lo waits for no child
-  for (int h = h_lo; h <= plan.max_height; ++h)
-    for (int f : plan.by_height[h]) {
-      const NDFrontDev& F = plan.fronts[f];
-      int utarget = 0;
-      for (int q = 0; q < F.nchild; ++q) {
-        const int c = plan.children[F.child_off + q];
-        if (plan.fronts[c].height >= h_lo) utarget += ntF[c];
-      }
-      std::vector<int> sig;
-      if (parent[f] >= 0) sig.push_back(U(parent[f]));
-      if (F.nB == 0) sig.push_back(D(f));          // no back-substitution: x_S is final
-      flow.vec_max = std::max(flow.vec_max, F.nS + rtF[f]);
-      if (gF[f]) {
-        const long long goff = flow.gbuf;
-        flow.gbuf += F.nF;
-        add(1, f, 0, F.nF, U(f), utarget, {GF(f)}, 256, goff);
-        for (int r = 0; r < F.nF; r += rtF[f]) add(2, f, r, std::min(F.nF, r + rtF[f]), GF(f), 1, sig, rtF[f], goff);
-      } else {
-        for (int r = 0; r < F.nF; r += rtF[f]) add(0, f, r, std::min(F.nF, r + rtF[f]), U(f), utarget, sig, rtF[f], 0);
-      }
-    }
-  flow.nfwd = (int)flow.tasks.size();
-  for (int h = plan.max_height; h >= h_lo; --h)
-    for (int f : plan.by_height[h]) {
-      const NDFrontDev& F = plan.fronts[f];
-      if (F.nB == 0) continue;
-      const int p = parent[f];
-      const NDFrontDev& P = plan.fronts[p];
-      const int dtarget = P.nB > 0 ? ntB[p] : ntF[p];
-      flow.vec_max = std::max(flow.vec_max, F.nB);
-      if (gB[f]) {
-        const long long goff = flow.gbuf;
-        flow.gbuf += F.nB;
-        add(4, f, 0, F.nB, D(p), dtarget, {GB(f)}, 256, goff);
-        for (int r = 0; r < F.nS; r += rtB[f]) add(5, f, r, std::min(F.nS, r + rtB[f]), GB(f), 1, {D(f)}, rtB[f], goff);
-      } else {
-        for (int r = 0; r < F.nS; r += rtB[f]) add(3, f, r, std::min(F.nS, r + rtB[f]), D(p), dtarget, {D(f)}, rtB[f], 0);
-      }
-    }
-  // every wait must name a counter that tasks earlier in the queue complete
-  std::vector<int> sigd(flow.nctr, 0);
-  for (const NDFlowTask& t : flow.tasks) {
-    if (t.target > 0 && (t.wait < 0 || t.wait >= flow.nctr || sigd[t.wait] < t.target))
-      throw std::runtime_error("nd_flow_plan: task waits for a counter not completed before it");
-    for (int q = 0; q < t.nsig; ++q) ++sigd[flow.sigs[t.sig0 + q]];
-  }
-  flow.gbuf = std::max<long long>(flow.gbuf, 1);
-}
-
 }  // namespace helm

@@ -114,6 +114,8 @@ class Solver:
         if kap.numel() != self.N:
             raise ValueError("slowness has %d entries, grid has %d nodes" % (kap.numel(), self.N))
         self._kap = kap
+        self._medium = (kap, False)     # the medium the context was factored for: (tensor, is_m)
+        self.medium_version = 0         # incremented by every refactor
         ctx = C.c_void_p()
         if self.max_rhs > 1:
             L.check(L.lib.helm_setup_multi(C.byref(self.grid), C.c_void_p(kap.data_ptr()), self.omega,
@@ -126,18 +128,26 @@ class Solver:
                                      C.c_void_p(_stream_ptr(self.device)), C.byref(ctx)), "helm_setup")
         self.ctx = ctx
 
-    def refactor(self, slowness=None, omega=None, alpha=None, alpha2=None, beta=None):
+    def refactor(self, slowness=None, omega=None, alpha=None, alpha2=None, beta=None, m=None):
         """numerical setup again (coefficients, Galerkin operators, coarsest factorisation) for a
-        new medium / frequency / shift on the same grid."""
+        new medium / frequency / shift on the same grid.  The medium is given as the slowness
+        or as its square m (helm_refactor_m); without either the current one is kept."""
+        if slowness is not None and m is not None:
+            raise ValueError("give the slowness or m, not both")
         if slowness is not None:
-            self._kap = _dev_tensor(slowness, torch.float64, self.device)
+            self._medium = (_dev_tensor(slowness, torch.float64, self.device), False)
+        elif m is not None:
+            self._medium = (_dev_tensor(m, torch.float64, self.device), True)
         if omega is not None:
             self.omega = float(omega)
         for name, v in (("alpha", alpha), ("alpha2", alpha2), ("beta", beta)):
             if v is not None:
                 setattr(self.shift, name, float(v))
-        L.check(L.lib.helm_refactor(self.ctx, C.c_void_p(self._kap.data_ptr()), self.omega, C.byref(self.shift),
-                                    self._s()), "helm_refactor")
+        t, is_m = self._medium
+        f = L.lib.helm_refactor_m if is_m else L.lib.helm_refactor
+        L.check(f(self.ctx, C.c_void_p(t.data_ptr()), self.omega, C.byref(self.shift), self._s()),
+                "helm_refactor_m" if is_m else "helm_refactor")
+        self.medium_version += 1
 
     KERNEL_CLASSES = KERNEL_CLASSES
 

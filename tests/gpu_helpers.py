@@ -59,3 +59,11 @@ def rel(a, b):
     a = np.asarray(a)
     b = np.asarray(b)
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def maxabs_rel(a, b):
+    """element-wise relative difference max_i |a_i - b_i| / max_i |b_i|: a single wrong node
+    shows here at its own size instead of being averaged over the grid as in `rel`."""
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))

@@ -118,20 +118,3 @@ def test_tuning_cache_changes_the_plan(tmp_path, monkeypatch):
     path.write_text("{ not json")
     monkeypatch.setenv("HELM_TUNE_CACHE", str(path))
     assert ws() == base
-
-
-@pytest.mark.parametrize("n,leaf,root", [((256, 256), 64, 600), ((128, 128), 32, 1100), ((256, 256), 16, 100),
-                                         ((64, 64, 64), 8, 1), ((128, 128, 128), 16, 1)])
-def test_dataflow_plan_is_a_valid_queue(monkeypatch, n, leaf, root):
-    """the dataflow substitution's task queue (HELM_ND_FLOW=1) is built when the context is
-    planned; the planner refuses a queue in which a task waits for a counter that tasks
-    queued before it do not complete, so a successful workspace query on the CPU shows the
-    queue cannot deadlock.  It also needs its own buffers (counters, tasks, gather buffer)."""
-    monkeypatch.setenv("HELM_ND_LEAF", str(leaf))
-    monkeypatch.setenv("HELM_ND_ROOT", str(root))
-    monkeypatch.delenv("HELM_ND_FLOW", raising=False)
-    st0, b0 = _bytes(n, cycle_prec="f32")
-    monkeypatch.setenv("HELM_ND_FLOW", "1")
-    st1, b1 = _bytes(n, cycle_prec="f32")
-    assert st0 == 0 and st1 == 0, L.lib.helm_last_error()
-    assert b1 > b0

@@ -7,7 +7,9 @@
   directions with max |v| = 1): relative agreement <= 1e-5;
 * the full-size 128^3 workload (16 sources on the top face, receivers on the whole
   top face, zero data, the sources solved in lock-step): finite-difference agreement on
-  3 directions;
+  20 seeded directions;
+* a solver refactored for another medium between a loss and its backward pass gives the
+  gradient of the medium the loss was evaluated at;
 * lock-step source solves give the separate solves' loss and gradient bit for bit.
 """
 import numpy as np
@@ -92,7 +94,7 @@ def test_gradient_full_size_workload():
     m0 = p.slowness.ravel() ** 2
     src = [torch.from_numpy(synth.point_rhs(p.n, pos)).cuda() for pos in p.sources]
     data = [torch.zeros(len(rec), dtype=torch.complex128, device="cuda") for _ in p.sources]
-    w = _fd_check(p, m0, src, torch.from_numpy(rec).cuda(), data, 3, 13, max_rhs=16)
+    w = _fd_check(p, m0, src, torch.from_numpy(rec).cuda(), data, 20, 13, max_rhs=16)
     print("worst relative FD mismatch at 128^3 (lock-step sources): %.2e" % w)
 
 
@@ -114,3 +116,33 @@ def test_lockstep_misfit_equals_separate_solves():
         s.close()
     assert torch.equal(out[0][0], out[1][0])
     assert torch.equal(out[0][1], out[1][1])
+
+
+def test_backward_after_the_solver_moved_to_another_medium():
+    """two losses evaluated with one solver at different media, then backward on the first:
+    the gradient equals (bit for bit) the one of a fresh solver at the first medium"""
+    p, m_ref, m0, Q, rec = _setup(2, 32, 2, seed=17)
+    D = np.zeros((len(rec), 2), np.complex128)
+    src = [torch.from_numpy(Q[:, k]).cuda() for k in range(2)]
+    data = [torch.from_numpy(D[:, k]).cuda() for k in range(2)]
+    recs = torch.from_numpy(rec).cuda()
+    s = from_problem(p, cycle_prec="f32")
+    m1 = torch.tensor(m0, dtype=torch.float64, device="cuda", requires_grad=True)
+    m2 = torch.tensor(m_ref, dtype=torch.float64, device="cuda", requires_grad=True)
+    l1 = helmholtz_misfit(m1, s, src, recs, data, tol=1e-10)
+    l2 = helmholtz_misfit(m2, s, src, recs, data, tol=1e-10)
+    l1.backward()
+    s2 = from_problem(p, cycle_prec="f32")
+    m1b = torch.tensor(m0, dtype=torch.float64, device="cuda", requires_grad=True)
+    l1b = helmholtz_misfit(m1b, s2, src, recs, data, tol=1e-10)
+    l1b.backward()
+    assert torch.equal(l1.detach(), l1b.detach())
+    assert torch.equal(m1.grad, m1b.grad)
+    l2.backward()                        # and back again for the second medium
+    s2.refactor(m=torch.tensor(m_ref, dtype=torch.float64, device="cuda"))
+    m2b = torch.tensor(m_ref, dtype=torch.float64, device="cuda", requires_grad=True)
+    l2b = helmholtz_misfit(m2b, s2, src, recs, data, tol=1e-10)
+    l2b.backward()
+    assert torch.equal(m2.grad, m2b.grad)
+    s.close()
+    s2.close()
