@@ -104,11 +104,21 @@ struct NDDev {        // device-side ND tables (pointers into the workspace)
   long long* toff = nullptr;
   cd *F = nullptr, *T = nullptr, *rkb = nullptr;
   PivCand* cand = nullptr;
-  void *L = nullptr, *W = nullptr, *upd = nullptr, *gvec = nullptr;
-  void *gbuf = nullptr, *part = nullptr;     // split-K launches: gathered vectors, partial products
+  void *L = nullptr, *W = nullptr;
   std::vector<NDLaunchDev> launch[2];   // forward, backward
   int gvec_cap = 0;
   long long gbuf_n = 1, part_n = 1, gvec_n = 0;   // entries per right-hand side of gbuf, part, gvec
+};
+
+// Per-call scratch of one cycle: the iterates and right-hand sides of levels 1-3 and the
+// coarsest solve's update pool, global gather vectors (launches whose vectors do not fit
+// in LDS) and split-K gathered vectors and partial products.  Nothing in it needs to
+// start at zero: every entry is written before it is read within the call.  Sized for
+// rc right-hand sides in lock-step.
+struct CycleScratch {
+  void *x1a = nullptr, *x1b = nullptr, *b2 = nullptr, *x2a = nullptr, *x2b = nullptr, *b3 = nullptr,
+       *x3 = nullptr;
+  void *upd = nullptr, *gvec = nullptr, *gbuf = nullptr, *part = nullptr;
 };
 
 // kernel classes timed with HIP events when timing is on
@@ -141,8 +151,7 @@ struct helm_ctx {
   float* m32 = nullptr;
   cd *coef2_64 = nullptr, *coef3_64 = nullptr, *tmp2 = nullptr;
   cf* coef2_32 = nullptr;
-  void *x1a = nullptr, *x1b = nullptr, *b2 = nullptr, *x2a = nullptr, *x2b = nullptr, *b3 = nullptr,
-       *x3 = nullptr;
+  CycleScratch scr;     // the cycle's scratch in the workspace
   cd *r3d = nullptr, *e3d = nullptr;
   NDPlan plan;
   NDDev nd;
@@ -359,6 +368,26 @@ void build_plan(helm_ctx* c) {
   }
 }
 
+// the cycle's per-call scratch for rc right-hand sides, taken from cv (the sizes of the
+// coarsest solve's buffers, d.*_n, must have been set)
+CycleScratch carve_scratch(const helm_ctx* c, Carver& cv, int rc) {
+  const size_t cs = c->csz, r = (size_t)rc;
+  const NDDev& d = c->nd;
+  CycleScratch w;
+  w.x1a = cv.take<char>(r * cs * c->g1.tot);
+  w.x1b = cv.take<char>(r * cs * c->g1.tot);
+  w.b2 = cv.take<char>(r * cs * c->g2.tot);
+  w.x2a = cv.take<char>(r * cs * c->g2.tot);
+  w.x2b = cv.take<char>(r * cs * c->g2.tot);
+  w.b3 = cv.take<char>(r * cs * c->g3.tot);
+  w.x3 = cv.take<char>(r * cs * c->g3.tot);
+  w.upd = cv.take<char>(r * cs * std::max<long long>(1, c->plan.upd_total));
+  w.gvec = d.gvec_n ? cv.take<char>(r * cs * d.gvec_n) : nullptr;
+  w.gbuf = cv.take<char>(r * cs * d.gbuf_n);
+  w.part = cv.take<char>(r * cs * d.part_n);
+  return w;
+}
+
 // carve every device buffer; returns the bytes used
 size_t carve(helm_ctx* c, void* ws) {
   Carver cv(ws);
@@ -378,13 +407,6 @@ size_t carve(helm_ctx* c, void* ws) {
   c->tmp2 = cv.take<cd>((size_t)K * g2.tot);
   c->coef3_64 = cv.take<cd>((size_t)K * g3.tot);
   const size_t rc = (size_t)c->rcap;
-  c->x1a = cv.take<char>(rc * cs * g1.tot);
-  c->x1b = cv.take<char>(rc * cs * g1.tot);
-  c->b2 = cv.take<char>(rc * cs * g2.tot);
-  c->x2a = cv.take<char>(rc * cs * g2.tot);
-  c->x2b = cv.take<char>(rc * cs * g2.tot);
-  c->b3 = cv.take<char>(rc * cs * g3.tot);
-  c->x3 = cv.take<char>(rc * cs * g3.tot);
   c->r3d = cv.take<cd>(g3.tot);
   c->e3d = cv.take<cd>(g3.tot);
   // ND tables
@@ -418,7 +440,6 @@ size_t carve(helm_ctx* c, void* ws) {
   d.T = cv.take<cd>(std::max<long long>(1, P.T_scratch));
   d.L = cv.take<char>(cs * P.L_total);
   d.W = cv.take<char>(cs * std::max<long long>(1, P.W_total));
-  d.upd = cv.take<char>(rc * cs * std::max<long long>(1, P.upd_total));
   long long gbuf_max = 1, part_max = 1;      // split-K buffers (entries)
   for (int fb = 0; fb < 2; ++fb) {
     std::vector<NDLaunch>& Ls = fb == 0 ? P.fwd : P.bwd;
@@ -470,11 +491,9 @@ size_t carve(helm_ctx* c, void* ws) {
     }
   d.gvec_cap = (int)gcap;
   d.gvec_n = gcap * gneed;
-  d.gvec = gcap ? cv.take<char>(rc * cs * gcap * gneed) : nullptr;
   d.gbuf_n = gbuf_max;
   d.part_n = part_max;
-  d.gbuf = cv.take<char>(rc * cs * gbuf_max);
-  d.part = cv.take<char>(rc * cs * part_max);
+  c->scr = carve_scratch(c, cv, (int)rc);
   // Krylov
   c->V = cv.take<cd>(rc * (m + 1) * g1.tot);
   c->Z = cv.take<char>(rc * cs * (size_t)m * g1.tot);
@@ -591,7 +610,7 @@ void ev_flush(helm_ctx* c) {
   } while (0)
 
 template <typename C>
-void nd_solve(helm_ctx* c, const C* r, C* x, int conj, hipStream_t s) {
+void nd_solve(helm_ctx* c, const CycleScratch& w, const C* r, C* x, int conj, hipStream_t s) {
   NDDev& d = c->nd;
   NDRhs rh;
   rh.n = c->nr;
@@ -601,16 +620,16 @@ void nd_solve(helm_ctx* c, const C* r, C* x, int conj, hipStream_t s) {
   rh.part = d.part_n;
   rh.gvec = d.gvec_n;
   for (const NDLaunchDev& L : d.launch[0]) {
-    C* gv = L.kind == 1 && L.shm == 0 ? (C*)d.gvec : nullptr;
+    C* gv = L.kind == 1 && L.shm == 0 ? (C*)w.gvec : nullptr;
     TIMED(c, KT_ND_FWD, s,
-          nd_fwd<C>(L, d.fronts, d.idx, d.cptr, d.cidx, (const C*)d.L, (C*)d.upd, r, x, gv, d.gvec_cap, conj,
-                    (C*)d.gbuf, (C*)d.part, rh, s));
+          nd_fwd<C>(L, d.fronts, d.idx, d.cptr, d.cidx, (const C*)d.L, (C*)w.upd, r, x, gv, d.gvec_cap, conj,
+                    (C*)w.gbuf, (C*)w.part, rh, s));
   }
   for (const NDLaunchDev& L : d.launch[1]) {
-    C* gv = L.kind == 1 && L.shm == 0 ? (C*)d.gvec : nullptr;
+    C* gv = L.kind == 1 && L.shm == 0 ? (C*)w.gvec : nullptr;
     TIMED(c, KT_ND_BWD, s,
-          nd_bwd<C>(L, d.fronts, d.idx, d.cidx, (const C*)d.W, (C*)d.upd, x, gv, d.gvec_cap, conj, (C*)d.gbuf,
-                    (C*)d.part, rh, s));
+          nd_bwd<C>(L, d.fronts, d.idx, d.cidx, (const C*)d.W, (C*)w.upd, x, gv, d.gvec_cap, conj, (C*)w.gbuf,
+                    (C*)w.part, rh, s));
   }
 }
 
@@ -648,10 +667,12 @@ struct Cycle {
   helm_ctx* c;
   int conj;
   hipStream_t s;
+  CycleScratch w;       // where the iterates and the coarsest solve's buffers live
   L1<R> A1;
   L2<R> A2;
 
-  Cycle(helm_ctx* ctx, int op, hipStream_t st) : c(ctx), conj(op), s(st) {
+  Cycle(helm_ctx* ctx, int op, hipStream_t st) : Cycle(ctx, op, st, ctx->scr) {}
+  Cycle(helm_ctx* ctx, int op, hipStream_t st, const CycleScratch& scr) : c(ctx), conj(op), s(st), w(scr) {
     A1.op = c->op;
     cd sb = shift_scalar(1.0, c->shift.beta, c->omega);
     A1.s = mk((R)sb.x, (R)sb.y);
@@ -679,8 +700,8 @@ struct Cycle {
   template <typename CO>
   void run(const cd* b1, CO* out) {
     const helm_mg& mg = c->mg;
-    C *x1a = (C*)c->x1a, *x1b = (C*)c->x1b, *x2a = (C*)c->x2a, *x2b = (C*)c->x2b;
-    C *b2 = (C*)c->b2, *b3 = (C*)c->b3, *x3 = (C*)c->x3;
+    C *x1a = (C*)w.x1a, *x1b = (C*)w.x1b, *x2a = (C*)w.x2a, *x2b = (C*)w.x2b;
+    C *b2 = (C*)w.b2, *b3 = (C*)w.b3, *x3 = (C*)w.x3;
     R w1 = (R)mg.jacobi[0], w2 = (R)mg.jacobi[1];
     // ---- level 1 pre-relaxation
     St<C> s1{0, nullptr};
@@ -699,7 +720,7 @@ struct Cycle {
       }
       TIMED(c, KT_L2_RESTRICT, s,
             (l2_restrict<R>(A2, s2.xin, s2.x, b2, w2, c->g3, nullptr, c->g3, b3, c->nr, s)));
-      nd_solve<C>(c, b3, x3, conj, s);
+      nd_solve<C>(c, w, b3, x3, conj, s);
       s2.xin |= XIN_E;
       for (int k = 0; k < mg.nu_post; ++k) s2 = adv2(s2, b2, x3, other(s2.x, x2a, x2b));
       if (s2.xin != XIN_X) {   // materialise (no post-relaxation)
@@ -1233,11 +1254,11 @@ int helm_coarse_solve(helm_ctx* c, int op, const void* r, void* e, void* stream)
   c->nr = 1;
   try {
     if (c->f32) {
-      cast_d2f((const cd*)r, (cf*)c->b3, c->g3.tot, s);
-      nd_solve<cf>(c, (const cf*)c->b3, (cf*)c->x3, op, s);
-      cast_f2d((const cf*)c->x3, (cd*)e, c->g3.tot, s);
+      cast_d2f((const cd*)r, (cf*)c->scr.b3, c->g3.tot, s);
+      nd_solve<cf>(c, c->scr, (const cf*)c->scr.b3, (cf*)c->scr.x3, op, s);
+      cast_f2d((const cf*)c->scr.x3, (cd*)e, c->g3.tot, s);
     } else {
-      nd_solve<cd>(c, (const cd*)r, (cd*)e, op, s);
+      nd_solve<cd>(c, c->scr, (const cd*)r, (cd*)e, op, s);
     }
     CK(hipGetLastError());
   } catch (DevErr& ex) {
