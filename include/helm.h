@@ -141,6 +141,26 @@ int helm_apply(helm_ctx* ctx, int op, int prec, const void* x, void* y, void* st
  * cycle precision).  r != z. */
 int helm_vcycle(helm_ctx* ctx, int op, const void* r, void* z, void* stream);
 
+/* Size of the static device array helm_vcycle_noalloc takes its scratch from (64 MiB on
+ * every device the library runs on, held until the process ends). */
+#define HELM_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/* helm_vcycle for callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same cycle and kernels,
+ * with its per-call scratch (level iterates, coarsest-solve update pool, gather and
+ * partial-product buffers) taken from a static device array of HELM_NOALLOC_SCRATCH_BYTES
+ * instead of the context's workspace.  It calls no hipMalloc, hipFree or other allocating
+ * routine (per-kernel timing is skipped for the call).  The operator data stay in the
+ * context's workspace; r and z as in helm_vcycle.
+ * Limit: returns HELM_EINVAL, before any device work, when the grid's scratch exceeds the
+ * array (2D up to 1024^2 in either cycle precision, 3D up to 128^3 with the FP32 cycle fit;
+ * the message gives the size needed).
+ * Sharing: every call on one device uses that device's one array; calls that overlap in
+ * time on one device (another stream, another thread) race and give undefined results.
+ * Nothing in the array needs to start at zero (every entry is written before it is read),
+ * so it keeps the last call's contents without harm. */
+int helm_vcycle_noalloc(helm_ctx* ctx, int op, const void* r, void* z, void* stream);
+
 /* Solve op(H) x = rhs by FGMRES(restart) preconditioned by one cycle per iteration.
  *   rhs: device c128[N1];  x: device c128[N1], initial guess on entry, solution on exit
  *   tol: relative-residual tolerance (> 0);  max_iter >= 1

@@ -64,6 +64,7 @@ _SIG = {
     "helm_refactor_m": (C.c_int, [P, P, C.c_double, C.POINTER(Shift), P]),
     "helm_apply": (C.c_int, [P, C.c_int, C.c_int, P, P, P]),
     "helm_vcycle": (C.c_int, [P, C.c_int, P, P, P]),
+    "helm_vcycle_noalloc": (C.c_int, [P, C.c_int, P, P, P]),
     "helm_solve": (C.c_int, [P, C.c_int, P, P, C.c_double, C.c_int, C.POINTER(SolveInfo), P]),
     "helm_coarse_solve": (C.c_int, [P, C.c_int, P, P, P]),
     "helm_destroy": (C.c_int, [P]),

@@ -8,6 +8,7 @@
 #include <cstdlib>
 #include <cstddef>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <thread>
@@ -1592,6 +1593,76 @@ int helm_solve_batched(helm_ctx* ctx, int op, int n_rhs, const int* inst_of_rhs,
     worst = std::max(worst, status[k]);
   }
   return worst;
+}
+
+}  // extern "C"
+
+// =========================================================================== cycle without allocation
+// helm_vcycle_noalloc takes the cycle's per-call scratch from a fixed device array instead of
+// the context's workspace, for callers that cannot allocate.  Every device the library runs
+// on holds its own copy of the array from the library's load until the process ends.  In
+// host code `scratch` names a host-side stand-in: its device address on the current device
+// comes from hipGetSymbolAddress, resolved once per device and kept in g_scratch.
+static __device__ __align__(256) char scratch[HELM_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[SCRATCH_MAX_DEVICES] = {nullptr};
+
+// the array's address on the current device (resolved on the first call on that device)
+void* scratch_on_current_device() {
+  int dev = 0;
+  CK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) throw DevErr("device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    CK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr || ((uintptr_t)ptr % ALIGN) != 0) throw DevErr("scratch array has no aligned device address");
+    g_scratch[dev] = ptr;
+  }
+  return g_scratch[dev];
+}
+}  // namespace
+
+extern "C" {
+
+int helm_vcycle_noalloc(helm_ctx* c, int op, const void* r, void* z, void* stream) {
+  if (!c || !r || !z) return fail(HELM_EINVAL, "NULL argument");
+  if (op != HELM_OP_N && op != HELM_OP_C) return fail(HELM_EINVAL, "op must be HELM_OP_N or HELM_OP_C");
+  if (r == z) return fail(HELM_EINVAL, "r and z must differ");
+  if (int v = need_single(c, "helm_vcycle_noalloc")) return v;
+  size_t need = 0;
+  {
+    Carver probe(nullptr);
+    carve_scratch(c, probe, 1);
+    need = probe.off;
+  }
+  if (need > HELM_NOALLOC_SCRATCH_BYTES)
+    return fail(HELM_EINVAL, "helm_vcycle_noalloc: this grid needs %zu bytes of scratch, the static array holds %zu",
+                need, (size_t)HELM_NOALLOC_SCRATCH_BYTES);
+  hipStream_t s = (hipStream_t)stream;
+  const int saved_timing = c->timing;
+  try {
+    Carver cv(scratch_on_current_device());
+    const CycleScratch w = carve_scratch(c, cv, 1);
+    c->nr = 1;
+    c->timing = 0;            // timing would create events
+    if (c->f32) {
+      Cycle<float> cyc(c, op, s, w);
+      cyc.template run<cd>((const cd*)r, (cd*)z);
+    } else {
+      Cycle<double> cyc(c, op, s, w);
+      cyc.template run<cd>((const cd*)r, (cd*)z);
+    }
+    c->timing = saved_timing;
+    CK(hipGetLastError());
+  } catch (DevErr& e) {
+    c->timing = saved_timing;
+    return fail(HELM_EDEVICE, "%s", e.what());
+  }
+  return HELM_OK;
 }
 
 }  // extern "C"
