@@ -247,7 +247,7 @@ int helm_get_timing(helm_ctx* ctx, double* t, int n);
  * [0] N1, [1] N2, [2] N3 unknowns per level, [3] fronts of the coarsest elimination,
  * [4] entries of the forward factor blocks sum(nF*nS), [5] entries of the backward blocks
  * sum(nS*nB), [6] update entries sum(nB), [7] separator entries sum(nS) (= N3),
- * [8] forward and [9] backward substitution launches per coarsest solve, [10] workspace
+ * [8] forward and [9] backward substitution kernel launches per coarsest solve, [10] workspace
  * bytes, [11] largest front size nF, [12] bytes per complex of the cycle (8 or 16),
  * [13] leaf box size and [14] root merge limit of the nested dissection, [15] 1 if the
  * schedule came from the autotuner cache (HELM_TUNE_CACHE), [16] number of tree-block

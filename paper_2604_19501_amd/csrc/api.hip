@@ -128,6 +128,7 @@ enum KClass { KT_L1_SWEEP, KT_L1_RESTRICT, KT_L2_SWEEP, KT_L2_RESTRICT, KT_ND_FW
 struct Pending {
   int cls;
   hipEvent_t a, b;
+  int launches;       // kernel launches between the two events
 };
 
 struct HeightInfo {
@@ -220,6 +221,14 @@ int validate(const helm_grid* g, const helm_mg* mg) {
   for (int a = 0; a < g->dim; ++a) N1 *= (g->n[a] + 1);
   if (N1 > (1LL << 31) - 1) return fail(HELM_EINVAL, "grid too large (N1 > 2^31-1)");
   return HELM_OK;
+}
+
+// kernels one substitution step launches (a split-K step: gather, tiles, row sums)
+int nd_step_kernels(int kind) { return kind == 3 ? 3 : 1; }
+int nd_kernels(const std::vector<NDLaunchDev>& Ls) {
+  int k = 0;
+  for (const NDLaunchDev& L : Ls) k += nd_step_kernels(L.kind);
+  return k;
 }
 
 // the calls that work on one hierarchy refuse the parent of a batched context: its
@@ -589,7 +598,7 @@ void ev_flush(helm_ctx* c) {
     float ms = 0;
     CK(hipEventElapsedTime(&ms, p.a, p.b));
     c->kt_ms[p.cls] += ms;
-    c->kt_cnt[p.cls] += 1;
+    c->kt_cnt[p.cls] += p.launches;
     c->evpool.push_back(p.a);
     c->evpool.push_back(p.b);
   }
@@ -606,7 +615,7 @@ void ev_flush(helm_ctx* c) {
     if ((c)->timing) {                                          \
       hipEvent_t b_ = ev_get(c);                                \
       CK(hipEventRecord(b_, s));                                \
-      (c)->pending.push_back(Pending{cls, a_, b_});             \
+      (c)->pending.push_back(Pending{cls, a_, b_, 1});          \
     }                                                           \
   } while (0)
 
@@ -620,17 +629,29 @@ void nd_solve(helm_ctx* c, const CycleScratch& w, const C* r, C* x, int conj, hi
   rh.gbuf = d.gbuf_n;
   rh.part = d.part_n;
   rh.gvec = d.gvec_n;
+  // timing: one event pair around each direction's launches (they run back to back), so
+  // that the per-launch average carries no per-launch event overhead
+  hipEvent_t e0 = nullptr;
+  if (c->timing) CK(hipEventRecord(e0 = ev_get(c), s));
   for (const NDLaunchDev& L : d.launch[0]) {
     C* gv = L.kind == 1 && L.shm == 0 ? (C*)w.gvec : nullptr;
-    TIMED(c, KT_ND_FWD, s,
-          nd_fwd<C>(L, d.fronts, d.idx, d.cptr, d.cidx, (const C*)d.L, (C*)w.upd, r, x, gv, d.gvec_cap, conj,
-                    (C*)w.gbuf, (C*)w.part, rh, s));
+    nd_fwd<C>(L, d.fronts, d.idx, d.cptr, d.cidx, (const C*)d.L, (C*)w.upd, r, x, gv, d.gvec_cap, conj,
+              (C*)w.gbuf, (C*)w.part, rh, s);
+  }
+  hipEvent_t e1 = nullptr;
+  if (c->timing) {
+    CK(hipEventRecord(e1 = ev_get(c), s));
+    c->pending.push_back(Pending{KT_ND_FWD, e0, e1, nd_kernels(d.launch[0])});
   }
   for (const NDLaunchDev& L : d.launch[1]) {
     C* gv = L.kind == 1 && L.shm == 0 ? (C*)w.gvec : nullptr;
-    TIMED(c, KT_ND_BWD, s,
-          nd_bwd<C>(L, d.fronts, d.idx, d.cidx, (const C*)d.W, (C*)w.upd, x, gv, d.gvec_cap, conj, (C*)w.gbuf,
-                    (C*)w.part, rh, s));
+    nd_bwd<C>(L, d.fronts, d.idx, d.cidx, (const C*)d.W, (C*)w.upd, x, gv, d.gvec_cap, conj, (C*)w.gbuf,
+              (C*)w.part, rh, s);
+  }
+  if (c->timing && !d.launch[1].empty()) {
+    hipEvent_t e2 = ev_get(c);
+    CK(hipEventRecord(e2, s));
+    c->pending.push_back(Pending{KT_ND_BWD, e1, e2, nd_kernels(d.launch[1])});
   }
 }
 
@@ -906,6 +927,7 @@ int solve_impl(helm_ctx* c, int op, int nr, const cd* b, cd* x, double tol, int 
       }
     } else {
       for (int j = 0; j < m; ++j) {
+        if (c->timing) kr_hold(150, s);     // the iteration's launches are queued before they run
         cyc.template run<C>(c->V + j * NJ, (C*)c->Z + j * NJ);
         TIMED(c, KT_APPLY_DOT, s, kr_arnoldi(a, (const char*)c->Z + j * NJ * c->csz, c->f32, j, tol, s));
         read_states(c, s);
@@ -1331,7 +1353,8 @@ int helm_get_info(helm_ctx* c, long long* out, int n) {
     maxF = std::max<long long>(maxF, f.nF);
   }
   long long v[21] = {c->g1.tot, c->g2.tot, c->g3.tot, (long long)P.fronts.size(), P.L_total, P.W_total, sB,
-                     c->g3.tot, (long long)P.fwd.size(), (long long)P.bwd.size(), (long long)c->ws_needed, maxF,
+                     c->g3.tot, (long long)nd_kernels(c->nd.launch[0]), (long long)nd_kernels(c->nd.launch[1]),
+                     (long long)c->ws_needed, maxF,
                      (long long)c->csz, c->nd_leaf, c->nd_root, c->tuned ? 1 : 0, (long long)P.cuts.size(),
                      -1, -1, -1, -1};
   for (size_t i = 0; i < P.cuts.size() && i < 4; ++i) v[17 + i] = P.cuts[i];

@@ -54,6 +54,8 @@ void kr_arnoldi(const KrylovArgs& a, const void* z, int z_f32, int j, double tol
 // x += Z y over each right-hand side's columns of the current cycle (Z: ldz between columns)
 void kr_update_x(const KrylovArgs& a, const void* Z, int z_f32, long long ldz, cd* x, hipStream_t s);
 void kr_zero(cd* x, long long n, hipStream_t s);
+// timing runs: hold the stream for about rounds x 3.4 us
+void kr_hold(int rounds, hipStream_t s);
 // copy the nrhs scalar blocks (bnorm .. hist) into host memory mapped for the device
 void kr_pack_states(const KrylovArgs& a, void* host_dst, hipStream_t s);
 // mark the right-hand sides of a bit mask finished (their kernels do nothing from now on)

@@ -434,7 +434,15 @@ __global__ void k_finalize(KrylovState* st, unsigned mask) {
   }
 }
 
+// timing runs only: keeps the stream busy for about rounds x 3.4 us (s_sleep 127 = 8128
+// clocks) so that the host has queued the launches that follow, with their timing events,
+// before the device reaches them; the event pairs then time the kernels, not host gaps
+__global__ void k_hold(int rounds) {
+  for (int i = 0; i < rounds; ++i) __builtin_amdgcn_s_sleep(127);
+}
+
 // ------------------------------------------------------------- launchers ----
+void kr_hold(int rounds, hipStream_t s) { hipLaunchKernelGGL(k_hold, dim3(1), dim3(64), 0, s, rounds); }
 void kr_pack_states(const KrylovArgs& a, void* host_dst, hipStream_t s) {
   hipLaunchKernelGGL(k_pack_states, dim3(1), dim3(256), 0, s, a.st, (char*)host_dst, a.nrhs);
 }
