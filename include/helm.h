@@ -41,8 +41,8 @@
  * (outputs valid, see the code).  No exception crosses the ABI.  Argument
  * validation happens before any device call.  The calls that work on one hierarchy
  * (helm_refactor, helm_refactor_m, helm_apply, helm_vcycle, helm_coarse_solve,
- * helm_solve, helm_grad_m, helm_get_coefficients, helm_get_info) return HELM_EINVAL for
- * the parent context of helm_setup_batched.
+ * helm_solve, helm_iterate, helm_grad_m, helm_get_coefficients, helm_get_info) return
+ * HELM_EINVAL for the parent context of helm_setup_batched.
  */
 #ifndef HELM_H
 #define HELM_H
@@ -169,6 +169,16 @@ int helm_vcycle_noalloc(helm_ctx* ctx, int op, const void* r, void* z, void* str
  * or HELM_ESTAGNATE otherwise.  A zero rhs returns x = 0 after 0 iterations. */
 int helm_solve(helm_ctx* ctx, int op, const void* rhs, void* x, double tol, int max_iter,
                helm_solve_info* info, void* stream);
+
+/* The cycle as a stand-alone solver (Sec. 5.1: the method "as a solver", the counts in
+ * parentheses of Table 3): the stationary iteration x <- x + M^{-1} (rhs - op(H) x) with one
+ * cycle per iteration, the residual recomputed in FP64 after each, until
+ * ||rhs - op(H) x|| <= tol ||rhs||.  Arguments and info as in helm_solve: iterations = cycles
+ * applied, restarts = 0, est_rel_residual = true_rel_residual = the last relative residual,
+ * history = the relative residual after every cycle.  Returns HELM_ENOCONV when max_iter is
+ * reached or the residual grows beyond 1e8 ||rhs|| (divergence), HELM_ENONFINITE on a NaN. */
+int helm_iterate(helm_ctx* ctx, int op, const void* rhs, void* x, double tol, int max_iter,
+                 helm_solve_info* info, void* stream);
 
 /* e = A3^{-1} r on the coarsest level (op HELM_OP_C: conj(A3)^{-1} r) with the factors the
  * cycle uses.  r, e: device c128[N3], N3 = helm_level_size(ctx, 0, 3).  For checking. */

@@ -12,7 +12,7 @@ The cycle follows the two-grid algorithm of Sec. 2 (pre-relax, restrict the
 residual, coarse solve, correct, post-relax) applied recursively; gamma = 1 gives
 a V-cycle and gamma = 2 a W-cycle (two recursive calls, the second on the
 updated residual).  Relaxation is damped Jacobi x <- x + w D^{-1}(b - A x)
-(Sec. 5.1).
+(Sec. 5.1).  `stationary` uses the cycle as a solver on its own.
 """
 from __future__ import annotations
 
@@ -92,6 +92,31 @@ class Hierarchy:
     def precond(self, v: np.ndarray) -> np.ndarray:
         """M^{-1} v: one cycle on the fine level from a zero initial guess."""
         return self.cycle(0, v)
+
+
+def stationary(hier: Hierarchy, b: np.ndarray, tol: float = 1e-6, max_iter: int = 500, x0=None):
+    """the cycle used as a solver on its own (Sec. 5.1, the counts in parentheses of Table 3):
+    the stationary iteration x <- x + M^{-1}(b - H x) until ||b - H x|| <= tol ||b||, or until
+    the residual exceeds 1e8 ||b|| (divergence).  Returns (x, cycles, relative residual after
+    every cycle)."""
+    b = np.asarray(b, np.complex128)
+    x = np.zeros_like(b) if x0 is None else np.array(x0, np.complex128)
+    bn = np.linalg.norm(b)
+    if bn == 0.0:
+        return np.zeros_like(b), 0, []
+    r = b - hier.H @ x
+    rel = np.linalg.norm(r) / bn
+    hist = []
+    its = 0
+    while rel > tol and its < max_iter:
+        x = x + hier.precond(r)
+        r = b - hier.H @ x
+        rel = np.linalg.norm(r) / bn
+        its += 1
+        hist.append(rel)
+        if not np.isfinite(rel) or rel > 1e8:
+            break
+    return x, its, hist
 
 
 def from_problem(prob, conj=False, **kw) -> Hierarchy:

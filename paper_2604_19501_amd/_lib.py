@@ -67,6 +67,7 @@ _SIG = {
     "helm_vcycle_noalloc": (C.c_int, [P, C.c_int, P, P, P]),
     "helm_solve": (C.c_int, [P, C.c_int, P, P, C.c_double, C.c_int, C.POINTER(SolveInfo), P]),
     "helm_coarse_solve": (C.c_int, [P, C.c_int, P, P, P]),
+    "helm_iterate": (C.c_int, [P, C.c_int, P, P, C.c_double, C.c_int, C.POINTER(SolveInfo), P]),
     "helm_destroy": (C.c_int, [P]),
     "helm_workspace_bytes_batched": (C.c_int, [C.c_int, C.POINTER(Grid), C.POINTER(MG), C.c_int,
                                                C.POINTER(C.c_size_t)]),

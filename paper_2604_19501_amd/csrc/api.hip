@@ -1009,6 +1009,62 @@ int solve_impl(helm_ctx* c, int op, int nr, const cd* b, cd* x, double tol, int 
   return worst;
 }
 
+// The cycle as a stand-alone solver (the stationary iteration x <- x + M^{-1}(b - op(H) x),
+// the paper's use of the method "as a solver"): one cycle, the update and the FP64 residual
+// per iteration, the host reading the residual norm after each.  info->history receives the
+// relative residual after every cycle.  A residual that grows beyond 1e8 ||b|| ends the
+// iteration (HELM_ENOCONV).
+template <typename R>
+int stationary_impl(helm_ctx* c, int op, const cd* b, cd* x, double tol, int max_iter, helm_solve_info* info,
+                    hipStream_t s) {
+  typedef typename cplx<R>::type C;
+  c->nr = 1;
+  KrylovArgs a = make_kargs(c, op);
+  Cycle<R> cyc(c, op, s);
+  const long long N = c->g1.tot;
+  kr_init(a, max_iter, s);
+  kr_residual(a, x, b, 1, s);         // V_0 = b - op(H) x, ||b||, ||V_0||
+  read_states(c, s);
+  const double bnorm = hs(c)->bnorm;
+  double rel = hs(c)->beta0 / bnorm;
+  int status = HELM_OK, its = 0;
+  std::vector<double> hist;
+  if (!std::isfinite(bnorm) || !std::isfinite(hs(c)->beta0)) {
+    status = HELM_ENONFINITE;
+  } else if (bnorm == 0.0) {
+    kr_zero(x, N, s);
+    rel = 0.0;
+  } else {
+    while (rel > tol && its < max_iter) {
+      cyc.template run<C>(c->V, (C*)c->Z);           // z = M^{-1} r
+      kr_add_z(a, c->Z, c->f32, x, s);               // x += z
+      kr_residual(a, x, b, 0, s);                    // r = b - op(H) x, in FP64
+      read_states(c, s);
+      ++its;
+      rel = hs(c)->beta0 / bnorm;
+      hist.push_back(rel);
+      if (!std::isfinite(rel)) {
+        status = HELM_ENONFINITE;
+        break;
+      }
+      if (rel > 1e8) break;
+    }
+    if (status == HELM_OK && rel > tol) status = HELM_ENOCONV;
+  }
+  CK(hipStreamSynchronize(s));
+  ev_flush(c);
+  if (info) {
+    info->iterations = its;
+    info->restarts = 0;
+    info->status = status;
+    info->est_rel_residual = rel;
+    info->true_rel_residual = rel;
+    if (info->history && info->history_cap > 0)
+      for (int k = 0; k < std::min(its, info->history_cap); ++k) info->history[k] = hist[k];
+  }
+  return status;
+}
+
 }  // namespace
 
 // =========================================================================== C ABI
@@ -1302,6 +1358,25 @@ int helm_solve(helm_ctx* c, int op, const void* rhs, void* x, double tol, int ma
   try {
     int st = c->f32 ? solve_impl<float>(c, op, 1, (const cd*)rhs, (cd*)x, tol, max_iter, info, s)
                     : solve_impl<double>(c, op, 1, (const cd*)rhs, (cd*)x, tol, max_iter, info, s);
+    CK(hipGetLastError());
+    return st;
+  } catch (DevErr& e) {
+    return fail(HELM_EDEVICE, "%s", e.what());
+  }
+}
+
+int helm_iterate(helm_ctx* c, int op, const void* rhs, void* x, double tol, int max_iter, helm_solve_info* info,
+                 void* stream) {
+  if (!c || !rhs || !x) return fail(HELM_EINVAL, "NULL argument");
+  if (op != HELM_OP_N && op != HELM_OP_C) return fail(HELM_EINVAL, "op must be HELM_OP_N or HELM_OP_C");
+  if (!(tol > 0.0) || !std::isfinite(tol)) return fail(HELM_EINVAL, "tol must be positive");
+  if (max_iter < 1) return fail(HELM_EINVAL, "max_iter must be >= 1");
+  if (rhs == x) return fail(HELM_EINVAL, "rhs and x must differ");
+  if (int v = need_single(c, "helm_iterate")) return v;
+  hipStream_t s = (hipStream_t)stream;
+  try {
+    int st = c->f32 ? stationary_impl<float>(c, op, (const cd*)rhs, (cd*)x, tol, max_iter, info, s)
+                    : stationary_impl<double>(c, op, (const cd*)rhs, (cd*)x, tol, max_iter, info, s);
     CK(hipGetLastError());
     return st;
   } catch (DevErr& e) {

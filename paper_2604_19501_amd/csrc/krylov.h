@@ -53,6 +53,8 @@ void kr_scale_v0(const KrylovArgs& a, hipStream_t s);
 void kr_arnoldi(const KrylovArgs& a, const void* z, int z_f32, int j, double tol, hipStream_t s);
 // x += Z y over each right-hand side's columns of the current cycle (Z: ldz between columns)
 void kr_update_x(const KrylovArgs& a, const void* Z, int z_f32, long long ldz, cd* x, hipStream_t s);
+// x += z (the stationary iteration's update; z in cycle precision)
+void kr_add_z(const KrylovArgs& a, const void* z, int z_f32, cd* x, hipStream_t s);
 void kr_zero(cd* x, long long n, hipStream_t s);
 // timing runs: hold the stream for about rounds x 3.4 us
 void kr_hold(int rounds, hipStream_t s);

@@ -398,6 +398,18 @@ __global__ void __launch_bounds__(256) k_update_x(KrylovArgs a, const CZ* __rest
   }
 }
 
+// x += z over nr right-hand sides (z in cycle precision)
+template <typename CZ>
+__global__ void __launch_bounds__(256) k_add_z(KrylovArgs a, const CZ* __restrict__ z, cd* __restrict__ x) {
+  const long long N = a.op.g.tot;
+  z += blockIdx.y * N;
+  x += blockIdx.y * N;
+  for (int q = 0; q < KNPT; ++q) {
+    long long f = node_of(q);
+    if (f < N) x[f] += to_d(z[f]);
+  }
+}
+
 __global__ void k_zero_c128(cd* __restrict__ x, long long n) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
     x[i] = mk(0.0, 0.0);
@@ -480,6 +492,13 @@ void kr_update_x(const KrylovArgs& a, const void* Z, int z_f32, long long ldz, c
     hipLaunchKernelGGL((k_update_x<cf>), g, dim3(256), 0, s, a, (const cf*)Z, ldz, x);
   else
     hipLaunchKernelGGL((k_update_x<cd>), g, dim3(256), 0, s, a, (const cd*)Z, ldz, x);
+}
+void kr_add_z(const KrylovArgs& a, const void* z, int z_f32, cd* x, hipStream_t s) {
+  dim3 g(a.nblk, a.nrhs);
+  if (z_f32)
+    hipLaunchKernelGGL((k_add_z<cf>), g, dim3(256), 0, s, a, (const cf*)z, x);
+  else
+    hipLaunchKernelGGL((k_add_z<cd>), g, dim3(256), 0, s, a, (const cd*)z, x);
 }
 void kr_zero(cd* x, long long n, hipStream_t s) {
   hipLaunchKernelGGL(k_zero_c128, dim3(1024), dim3(256), 0, s, x, n);

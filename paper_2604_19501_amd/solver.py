@@ -219,6 +219,25 @@ class Solver:
             out["history"] = [hist[i] for i in range(min(info.iterations, max_iter))]
         return x, out
 
+    def iterate(self, rhs, x0=None, tol: float = 1e-6, max_iter: int = 500, op: int = L.HELM_OP_N,
+                history: bool = False) -> Tuple[torch.Tensor, dict]:
+        """the cycle as a stand-alone solver, x <- x + M^{-1}(b - op(H) x) (helm_iterate)"""
+        b = _dev_tensor(rhs, torch.complex128, self.device)
+        x = torch.zeros_like(b) if x0 is None else _dev_tensor(x0, torch.complex128, self.device).clone()
+        info = L.SolveInfo()
+        hist = None
+        if history:
+            hist = (C.c_double * max_iter)()
+            info.history = C.cast(hist, C.POINTER(C.c_double))
+            info.history_cap = max_iter
+        st = L.lib.helm_iterate(self.ctx, op, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr()), float(tol),
+                                int(max_iter), C.byref(info), self._s())
+        L.check(st, "helm_iterate")
+        out = dict(status=st, iterations=info.iterations, true_rel_residual=info.true_rel_residual)
+        if history:
+            out["history"] = [hist[i] for i in range(min(info.iterations, max_iter))]
+        return x, out
+
     def solve_many(self, rhs: Sequence, tol: float = 1e-6, max_iter: int = 500, op: int = L.HELM_OP_N):
         """solve for every right-hand side from a zero guess, in lock-step groups of up to
         max_rhs; each result equals solve()'s.  Returns (solutions, infos)."""

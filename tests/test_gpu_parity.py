@@ -267,3 +267,46 @@ def test_arnoldi_cancellation_guard_ends_the_cycle(monkeypatch):
         assert abs(info["iterations"] - ref.iterations) <= 1
         assert info["restarts"] == info["iterations"] - 1
         s.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_iterate_cycle_as_solver(case, prec):
+    """the cycle as a stand-alone solver (helm_iterate) against the oracle's stationary
+    iteration: the same number of cycles (+-1), the residual history cycle by cycle (FP64
+    cycle 1e-9, FP32 cycle 1e-4 relative), the final true residual."""
+    dim, p, H = case
+    from oracle import multigrid
+    q = p.rhs()
+    xo, its_o, hist_o = multigrid.stationary(H, q, tol=1e-6, max_iter=300)
+    s = from_problem(p, nu=(1, 1), cycle_prec=prec)
+    x, info = s.iterate(q, tol=1e-6, max_iter=300, history=True)
+    xg = x.cpu().numpy()
+    res = np.linalg.norm(q - H.H @ xg) / np.linalg.norm(q)
+    print("iterate dim %d %s: %d cycles (oracle %d), residual %.2e" % (dim, prec, info["iterations"], its_o, res))
+    assert info["status"] == 0 and res <= 1e-6
+    assert abs(info["iterations"] - its_o) <= 1
+    k = min(len(hist_o), len(info["history"]))
+    hg, ho = np.array(info["history"][:k]), np.array(hist_o[:k])
+    assert np.max(np.abs(hg - ho) / ho) <= (1e-9 if prec == "f64" else 1e-4)
+    assert rel(xg, xo) <= (1e-9 if prec == "f64" else 1e-4)
+    s.close()
+
+
+def test_alpha_sweep_matches_oracle_factors():
+    """convergence factors of the cycle as a solver at several real shifts (the Fig. 3
+    analogue) equal the oracle's stationary iteration's within 2 %."""
+    from oracle import multigrid
+    from paper_2604_19501_amd import sweep as sw
+    n, G = (64, 64), 12.0
+    alphas = [1.0, 1.08, 1.117, 1.16]
+    gpu = sw.sweep(n, G, alphas, nu=2, cycles=40, prec="f64")
+    dim, h, kappa, omega, layer = sw.homogeneous(n, G)
+    q = np.zeros(int(np.prod([k + 1 for k in n])), np.complex128)
+    q[q.size // 2] = 1.0
+    for a, r in zip(alphas, gpu):
+        H = multigrid.Hierarchy(n, h, kappa.ravel() ** 2, omega, layer, 2.0, alpha=a, beta=0.0, cycle=2,
+                                nu_pre=2, nu_post=2, jacobi=(0.8, 0.8))
+        _, its, hist = multigrid.stationary(H, q, tol=1e-300, max_iter=40)
+        fo = sw.factor(hist)
+        print("alpha %.3f: factor gpu %.4f oracle %.4f" % (a, r["factor"], fo))
+        assert abs(r["factor"] - fo) <= 0.02 * fo

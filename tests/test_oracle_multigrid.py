@@ -192,3 +192,35 @@ def test_cycle_equals_dense_composition_of_eq_2_1(n, gamma, nu):
     if nu[0] != nu[1]:
         assert np.max(np.abs(_dense_cycle_operator(H, gamma, nu[1], nu[0], (0.6, 0.4)) - Md)) > 1e-3 * np.max(np.abs(Md))
     assert np.max(np.abs(_dense_cycle_operator(H, 3 - gamma, nu[0], nu[1], (0.6, 0.4)) - Md)) > 1e-6 * np.max(np.abs(Md))
+
+
+
+# ---------------------------------------------------------------- the cycle as a solver
+def test_stationary_iteration_matches_its_closed_form():
+    """k cycles of x <- x + M^{-1}(b - H x) from zero give x_k = (I - (I - M^{-1}H)^k) H^{-1} b,
+    with M^{-1} the dense composition of eq. (2.1); the residual then contracts per cycle at
+    the spectral radius of I - H M^{-1}."""
+    H = _hier((8, 8), alpha=1.12, alpha2=1.03, beta=0.05, cycle=2, nu_pre=1, nu_post=1, jacobi=(0.6, 0.4))
+    Md = _dense_cycle_operator(H, 2, 1, 1, (0.6, 0.4))
+    A = H.H.toarray()
+    N = A.shape[0]
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    x, its, hist = multigrid.stationary(H, b, tol=1e-300, max_iter=6)
+    E = np.eye(N) - Md @ A
+    xk = (np.eye(N) - np.linalg.matrix_power(E, 6)) @ np.linalg.solve(A, b)
+    assert its == 6 and len(hist) == 6
+    assert np.linalg.norm(x - xk) <= 1e-11 * np.linalg.norm(xk)
+    rho = np.max(np.abs(np.linalg.eigvals(np.eye(N) - A @ Md)))
+    x, its, hist = multigrid.stationary(H, b, tol=1e-300, max_iter=60)
+    rate = (hist[-1] / hist[-11]) ** 0.1
+    assert abs(rate - rho) <= 0.05 * rho, (rate, rho)
+
+
+def test_stationary_stops_on_divergence_and_at_zero():
+    H = _hier((16, 16), alpha=1.6, cycle=2, nu_pre=3, nu_post=3, jacobi=(1.6, 1.6))     # unstable smoother
+    b = np.ones(H.H.shape[0], np.complex128)
+    x, its, hist = multigrid.stationary(H, b, tol=1e-6, max_iter=500)
+    assert hist[-1] > 1e8 and its < 500
+    x, its, hist = multigrid.stationary(H, np.zeros_like(b))
+    assert its == 0 and not np.any(x)
