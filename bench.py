@@ -123,10 +123,11 @@ def bytes_model(cls, p, info, iters, restart, nr=1):
     cb = info["cycle_complex_bytes"]
     K = 3 ** d
     U = info["upd_entries"]
-    if cls == "l1_restrict":      # b (c128) per fine node and r2 per level-2 node per rhs; m (f32)
-        return N1 * (16 * nr + 4) + N2 * cb * nr
-    if cls == "l1_sweep":         # b (c128) + z out per fine node and e2 per level-2 node per rhs; m
-        return N1 * ((16 + cb) * nr + 4) + N2 * cb * nr
+    # the level-1 diagonal: precomputed complex FP32 (the FP32 cycle) or m in FP64 (8 B either way)
+    if cls == "l1_restrict":      # b (c128) per fine node and r2 per level-2 node per rhs; the diagonal
+        return N1 * (16 * nr + 8) + N2 * cb * nr
+    if cls == "l1_sweep":         # b (c128) + z out per fine node and e2 per level-2 node per rhs; diagonal
+        return N1 * ((16 + cb) * nr + 8) + N2 * cb * nr
     # level-2 coefficients: the 3D FP32 cycle stores the complex-symmetric operator's centre
     # and the directions after it (14 planes), otherwise all K
     S = K // 2 + 1 if (cb == 8 and d == 3) else K
@@ -528,7 +529,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--pmc-pass", action="store_true",
                     help="for hardware-counter runs: a 256 MiB device copy (calibrates FETCH_SIZE/WRITE_SIZE "
-                         "against known bytes) followed by one setup+solve step of the cfg2 workload")
+                         "against known bytes) followed by one setup+solve step of the cfg2 workload (cfg3 with "
+                         "--workload cfg3)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the solver has no multi-GPU path (requested --gpus %d)" % args.gpus,
@@ -538,7 +540,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.pmc_pass:
         import synth
-        p = synth.config2(args.n)
+        p = synth.config3(256) if args.workload == "cfg3" else synth.config2(args.n)
         q = torch.from_numpy(p.rhs()).cuda()
         a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")      # 256 MiB
         b = torch.empty_like(a)

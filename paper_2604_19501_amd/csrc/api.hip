@@ -151,6 +151,7 @@ struct helm_ctx {
   // device state
   double *m64 = nullptr;
   float* m32 = nullptr;
+  cf* dg32 = nullptr;   // FP32 cycle: diagonal of the level-1 operator H_beta
   cd *coef2_64 = nullptr, *coef3_64 = nullptr, *tmp2 = nullptr;
   cf* coef2_32 = nullptr;
   CycleScratch scr;     // the cycle's scratch in the workspace
@@ -248,6 +249,7 @@ void init_geometry(helm_ctx* c) {
   for (int a = 0; a < 3; ++a)
     for (int s = 0; s < 2; ++s) c->op.layer[a][s] = a < c->grid.dim ? c->grid.layer[a][s] : 0;
   c->op.sigma_max = c->grid.sigma_max;
+  set_layer_profile(c->op);
   c->f32 = c->mg.cycle_prec == HELM_F32;
   c->csz = c->f32 ? sizeof(cf) : sizeof(cd);
 }
@@ -409,6 +411,7 @@ size_t carve(helm_ctx* c, void* ws) {
   NDDev& d = c->nd;
   c->m64 = cv.take<double>(g1.tot);
   c->m32 = cv.take<float>(g1.tot);
+  c->dg32 = c->f32 ? cv.take<cf>(g1.tot) : nullptr;
   c->coef2_64 = cv.take<cd>((size_t)K * g2.tot);
   // the 3D FP32 cycle keeps the complex-symmetric level-2 operator's centre and the 13
   // directions after it (14 of 27 planes); in 2D the mirrored reads cost more than the
@@ -661,8 +664,17 @@ void nd_solve(helm_ctx* c, const CycleScratch& w, const C* r, C* x, int conj, hi
 void numeric_setup(helm_ctx* c, const double* medium, int is_m, hipStream_t s) {
   const helm_shift* shift = &c->shift;
   const double omega = c->omega;
-  // a0: m = kappa^2 (FP64 and FP32)
+  // a0: m = kappa^2 (FP64 and FP32); the FP32 cycle's level-1 diagonal
   square_slowness(medium, c->m64, c->m32, c->g1.tot, is_m, s);
+  if (c->f32) {
+    L1<float> A;
+    A.op = c->op;
+    const cd sb = shift_scalar(1.0, shift->beta, omega);
+    A.s = mk((float)sb.x, (float)sb.y);
+    A.m = c->m32;
+    A.conj = 0;
+    l1_diag32(A, c->dg32, s);
+  }
   // a1: level-2 Galerkin operator of H_beta^{alpha2}
   gal_fine(c->op, shift_scalar(shift->alpha2, shift->beta, omega), c->m64, c->g2, c->coef2_64, s);
   const int K = stencil_points(c->grid.dim);
@@ -700,6 +712,7 @@ struct Cycle {
     A1.s = mk((R)sb.x, (R)sb.y);
     A1.m = (const R*)(sizeof(R) == 4 ? (const void*)c->m32 : (const void*)c->m64);
     A1.conj = op;
+    A1.dg = (const C*)(sizeof(R) == 4 ? (const void*)c->dg32 : nullptr);
     A2.g = c->g2;
     A2.coef = (const C*)(sizeof(R) == 4 ? (const void*)c->coef2_32 : (const void*)c->coef2_64);
     A2.conj = op;
@@ -816,6 +829,11 @@ void drop_graphs(helm_ctx* c) {
   }
 }
 
+// capture and instantiation are serialised over the process: batched solves run one host
+// worker per stream, and the HIP runtime's capture bookkeeping is not relied on to be
+// safe for concurrent captures from several threads
+std::mutex g_capture_mu;
+
 // capture the m per-iteration graphs of operator op for the current right-hand side count
 // (kernel arguments are fixed: buffers, shifts, tolerance), once per context until the
 // frequency, the shifts or the count change
@@ -824,6 +842,7 @@ void iter_graphs(helm_ctx* c, int op, double tol) {
   typedef typename cplx<R>::type C;
   const int m = c->mg.restart;
   if ((int)c->gexec[op].size() == m && c->gtol[op] == tol && c->gnr[op] == c->nr) return;
+  std::lock_guard<std::mutex> lock(g_capture_mu);
   for (hipGraphExec_t g : c->gexec[op]) (void)hipGraphExecDestroy(g);
   c->gexec[op].clear();
   if (!c->cap) CK(hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking));

@@ -66,6 +66,21 @@ __host__ __device__ inline cf to_f(cd a) { return mk((float)a.x, (float)a.y); }
 __host__ __device__ inline cf to_f(cf a) { return a; }
 __host__ __device__ inline cd to_d(cf a) { return mk((double)a.x, (double)a.y); }
 __host__ __device__ inline cd to_d(cd a) { return a; }
+// streaming accesses of vectors that a pass reads or writes once (the Krylov basis):
+// marked non-temporal so that they do not displace the data reused from pass to pass
+// (the coarsest factors, the level-2 coefficients) in the caches
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ cd ld_nt(const cd* p) {
+  const dvec2 v = __builtin_nontemporal_load((const dvec2*)p);
+  return mk(v.x, v.y);
+}
+__device__ __forceinline__ void st_nt(cd* p, cd v) {
+  dvec2 w;
+  w.x = v.x;
+  w.y = v.y;
+  __builtin_nontemporal_store(w, (dvec2*)p);
+}
+
 template <typename C> struct conv;
 template <> struct conv<cf> {
   __host__ __device__ static cf from(cd a) { return to_f(a); }
@@ -108,23 +123,36 @@ struct FineOp {
   double inv_h2;
   int layer[3][2];
   double sigma_max;
+  // the layer profile's per-axis constants (set by set_layer_profile): reciprocal widths
+  // (0 where a face has no layer) in FP64 and FP32, and the first node past the high face's
+  // inner edge
+  double inv_w[3][2];
+  float inv_wf[3][2];
+  int inner_hi[3];
 };
 
+// the profile's constants of op.layer and op.g
+inline void set_layer_profile(FineOp& op) {
+  for (int a = 0; a < 3; ++a) {
+    for (int s = 0; s < 2; ++s) {
+      const int w = a < op.g.dim ? op.layer[a][s] : 0;
+      op.inv_w[a][s] = w > 0 ? 1.0 / w : 0.0;
+      op.inv_wf[a][s] = (float)op.inv_w[a][s];
+    }
+    op.inner_hi[a] = op.g.n[a] - (a < op.g.dim ? op.layer[a][1] : 0);
+  }
+}
+
+// sigma = sigma_max * sum over axes of (depth into the layer / width)^2, without branches:
+// the depth below the low face's inner edge is max(lo - i, 0), past the high face's
+// max(i - (n - hi), 0), and a face without a layer has reciprocal width 0
 __host__ __device__ inline double layer_sigma(const FineOp& op, int i0, int i1, int i2) {
-  int ii[3] = {i0, i1, i2};
+  const int ii[3] = {i0, i1, i2};
   double s = 0.0;
   for (int a = 0; a < op.g.dim; ++a) {
-    int lo = op.layer[a][0], hi = op.layer[a][1];
-    int i = ii[a];
-    if (lo > 0 && i < lo) {
-      double t = (double)(lo - i) / lo;
-      s += t * t;
-    }
-    int th = op.g.n[a] - hi;
-    if (hi > 0 && i > th) {
-      double t = (double)(i - th) / hi;
-      s += t * t;
-    }
+    const double tl = (double)max(op.layer[a][0] - ii[a], 0) * op.inv_w[a][0];
+    const double th = (double)max(ii[a] - op.inner_hi[a], 0) * op.inv_w[a][1];
+    s += tl * tl + th * th;
   }
   return op.sigma_max * s;
 }

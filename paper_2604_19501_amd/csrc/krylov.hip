@@ -300,7 +300,9 @@ __global__ void __launch_bounds__(64) k_givens(KrylovArgs a, int j, double tol) 
 
 // V_{j+1} = (H z_j - sum_i c_i V_i) / h_{j+1,j}.  The blocks take the nodes in reverse
 // order: the dots pass just streamed the same basis front to back, so its last part is
-// the most likely to still be in the memory-side cache.
+// the most likely to still be in the memory-side cache.  This pass is the basis's last
+// reader in the iteration: its loads are non-temporal, so that they do not displace the
+// data the next iteration's cycle reuses (the coarsest factors, the level-2 coefficients).
 template <typename CZ>
 __global__ void __launch_bounds__(256) k_arnoldi_update(KrylovArgs a, const CZ* __restrict__ z, int j) {
   __shared__ cd sc[KMAXM + 1];
@@ -320,14 +322,14 @@ __global__ void __launch_bounds__(256) k_arnoldi_update(KrylovArgs a, const CZ* 
     f[q] = ok[q] ? t : N - 1;
   }
   cd w[KNPT], nx[KNPT];
-  for (int q = 0; q < KNPT; ++q) nx[q] = p.V[f[q]];
+  for (int q = 0; q < KNPT; ++q) nx[q] = ld_nt(p.V + f[q]);
   for (int q = 0; q < KNPT; ++q) w[q] = apply_h(a, z, f[q]);
   __syncthreads();
   for (int i = 0; i <= j; ++i) {
     cd vi[KNPT];
     for (int q = 0; q < KNPT; ++q) vi[q] = nx[q];
     const long long in = (long long)(i < j ? i + 1 : j) * a.ldv;   // the last pass reloads V_j
-    for (int q = 0; q < KNPT; ++q) nx[q] = p.V[in + f[q]];
+    for (int q = 0; q < KNPT; ++q) nx[q] = ld_nt(p.V + in + f[q]);
     const cd ci = sc[i];
     for (int q = 0; q < KNPT; ++q) w[q] -= ci * vi[q];
   }

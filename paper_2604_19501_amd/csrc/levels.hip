@@ -15,6 +15,8 @@
 //
 // Threads map to nodes x-fastest (coalesced); blocks are remapped so that each
 // of the 8 XCDs sweeps a contiguous slab, keeping neighbour planes in its L2.
+#include <type_traits>
+
 #include "levels_api.h"
 
 namespace helm {
@@ -48,8 +50,10 @@ __device__ __forceinline__ void decode(const Geom& g, long long f, int& i0, int&
 __device__ __forceinline__ bool inside(const Geom& g, int i0, int i1, int i2) {
   return i0 >= 0 && i0 <= g.n[0] && i1 >= 0 && i1 <= g.n[1] && i2 >= 0 && i2 <= g.n[2];
 }
-__device__ __forceinline__ long long flat(const Geom& g, int i0, int i1, int i2) {
-  return i0 + (long long)g.N[0] * (i1 + (long long)g.N[1] * i2);
+// node index in 32 bits (grids are validated to hold fewer than 2^31 nodes); the
+// right-hand side offsets are applied to the base pointers
+__device__ __forceinline__ int flat(const Geom& g, int i0, int i1, int i2) {
+  return i0 + g.N[0] * (i1 + g.N[1] * i2);
 }
 
 // ----------------------------------------------------------------------------
@@ -73,18 +77,36 @@ template <int DIM, int CSZ> struct RBox {
   static constexpr int x = DIM == 2 ? 16 : 8, y = DIM == 2 ? 8 : 4, z = DIM == 2 ? 1 : 4;
 };
 
-// level-1 operator H_s with x from LDS (centre index k, strides sy, sz)
+// level-1 operator H_s with x from LDS (centre index k, strides sy, sz).  The FP32 cycle
+// reads its diagonal from the array precomputed at set-up (one 8-byte load per node instead
+// of the squared slowness, the layer profile and the complex coefficient: the level-1
+// kernels are bound by instruction issue as much as by memory); FP64 evaluates it from m.
 template <int DIM, typename R>
 struct Op1 {
   typedef R Real;
   typedef typename cplx<R>::type C;
+  static constexpr bool DG = sizeof(R) == 4;
   L1<R> A;
   __host__ __device__ __forceinline__ const Geom& geom() const { return A.op.g; }
-  __device__ __forceinline__ C diag(long long f, int i0, int i1, int i2) const { return A.diag(f, i0, i1, i2); }
+  __device__ __forceinline__ C dg_at(long long f) const {
+    C d = A.dg[f];
+    if (A.conj) d.y = -d.y;
+    return d;
+  }
+  __device__ __forceinline__ C diag(long long f, int i0, int i1, int i2) const {
+    if constexpr (DG) return dg_at(f);
+    else return A.diag(f, i0, i1, i2);
+  }
   // the diagonal in two steps, so that the load can be issued early: aux(f), then diag_aux
-  typedef R Aux;
-  __device__ __forceinline__ Aux aux(long long f) const { return A.m[f]; }
-  __device__ __forceinline__ C diag_aux(Aux mm, int i0, int i1, int i2) const { return A.diag_m(mm, i0, i1, i2); }
+  typedef typename std::conditional<DG, C, R>::type Aux;
+  __device__ __forceinline__ Aux aux(long long f) const {
+    if constexpr (DG) return dg_at(f);
+    else return A.m[f];
+  }
+  __device__ __forceinline__ C diag_aux(Aux a, int i0, int i1, int i2) const {
+    if constexpr (DG) return a;
+    else return A.diag_m(a, i0, i1, i2);
+  }
   __device__ __forceinline__ C ax(const C* xs, int k, int sy, int sz, long long, C D) const {
     C nb = (xs[k - 1] + xs[k + 1]) + (xs[k - sy] + xs[k + sy]);
     if (DIM == 3) nb += xs[k - sz] + xs[k + sz];
@@ -145,17 +167,20 @@ __device__ __forceinline__ C prolong_lds(const C* es, int ex, int ey, int c0, in
 
 struct TileGrid {
   int nt[3];
-  long long ntiles;
+  int ntiles;
 };
 
+// the block's tile, in 32-bit arithmetic on values uniform over the block
 __device__ __forceinline__ bool tile_origin(const TileGrid& tg, int bx, int by, int bz, int& o0, int& o1,
                                            int& o2) {
-  long long t = xcd_block(tg.ntiles);
+  const int b = blockIdx.x, per = (tg.ntiles + 7) >> 3;
+  const int t = __builtin_amdgcn_readfirstlane((b & 7) * per + (b >> 3));
   if (t >= tg.ntiles) return false;
-  o0 = (int)(t % tg.nt[0]) * bx;
-  long long q = t / tg.nt[0];
-  o1 = (int)(q % tg.nt[1]) * by;
-  o2 = (int)(q / tg.nt[1]) * bz;
+  const int q = t / tg.nt[0];
+  o0 = (t - q * tg.nt[0]) * bx;
+  const int q2 = q / tg.nt[1];
+  o1 = (q - q2 * tg.nt[1]) * by;
+  o2 = q2 * bz;
   return true;
 }
 
@@ -167,31 +192,70 @@ __device__ __forceinline__ void clamp_node(const Geom& g, int& i0, int& i1, int&
   i2 = min(max(i2, 0), g.n[2]);
 }
 
-// stage x_in on the box [s0, s0+SX) x [s1, s1+SY) x [s2, s2+SZ); every thread's loads of
-// all its nodes are issued before any is used (unrolled, indices clamped)
+// stage x_in on the box [s0, s0+SX) x [s1, s1+SY) x [s2, s2+SZ).  2D: the loads of all of
+// a thread's nodes are issued into registers first, then the values are formed and stored,
+// so the block waits for memory once.  3D (8 or 9 passes): groups of 4 unrolled passes
+// leave the scheduling to the compiler, which keeps the registers at about 70 and 7
+// wavefronts per SIMD; explicit register staging of every pass measured slower there
+// (about 100 registers, 4 wavefronts per SIMD).  Indices are clamped so every load is
+// issued.
 template <int DIM, int XIN, int SX, int SY, int SZ, class Op, typename C, typename CB, typename R>
 __device__ __forceinline__ void stage_xin(const Op& op, const C* __restrict__ x, const CB* __restrict__ b, R w_in,
                                           const C* es, int ex, int ey, int c0, int c1, int c2, int s0, int s1,
                                           int s2, C* xs) {
   const Geom& g = op.geom();
   constexpr int tot = SX * SY * SZ, NIT = (tot + 255) / 256;
-  for (int i4 = 0; i4 < NIT; i4 += 4)          // groups of 4 passes bound the registers in 3D
+  if constexpr (DIM == 2) {
+    C rx[(XIN & XIN_X) ? NIT : 1];
+    CB rb[(XIN & XIN_Z) ? NIT : 1];
+    typename Op::Aux ra[(XIN & XIN_Z) ? NIT : 1];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int it = i4 + u;
-    if (NIT % 4 != 0 && it >= NIT) break;
-    const int k = min((int)threadIdx.x + 256 * it, tot - 1);
-    const int a = k % SX, q = k / SX;
-    const int i0 = s0 + a, i1 = s1 + q % SY, i2 = s2 + q / SY;
-    int j0 = i0, j1 = i1, j2 = i2;
-    clamp_node(g, j0, j1, j2);
-    const long long f = flat(g, j0, j1, j2);
-    C v = mk((R)0, (R)0);
-    if (XIN & XIN_X) v += x[f];
-    if (XIN & XIN_Z) v += w_in * jdiv(conv<C>::from(b[f]), op.diag(f, j0, j1, j2));
-    if (XIN & XIN_E) v += prolong_lds<DIM>(es, ex, ey, c0, c1, c2, j0, j1, j2);
-    if (!inside(g, i0, i1, i2)) v = mk((R)0, (R)0);
-    if ((int)threadIdx.x + 256 * it < tot) xs[k] = v;
+    for (int u = 0; u < NIT; ++u) {
+      const int k = min((int)threadIdx.x + 256 * u, tot - 1);
+      const int a = k % SX, q = k / SX;
+      int j0 = s0 + a, j1 = s1 + q % SY, j2 = s2 + q / SY;
+      clamp_node(g, j0, j1, j2);
+      const int f = flat(g, j0, j1, j2);
+      if (XIN & XIN_X) rx[(XIN & XIN_X) ? u : 0] = x[f];
+      if (XIN & XIN_Z) {
+        rb[(XIN & XIN_Z) ? u : 0] = b[f];
+        ra[(XIN & XIN_Z) ? u : 0] = op.aux(f);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NIT; ++u) {
+      const int k = min((int)threadIdx.x + 256 * u, tot - 1);
+      const int a = k % SX, q = k / SX;
+      const int i0 = s0 + a, i1 = s1 + q % SY, i2 = s2 + q / SY;
+      int j0 = i0, j1 = i1, j2 = i2;
+      clamp_node(g, j0, j1, j2);
+      C v = mk((R)0, (R)0);
+      if (XIN & XIN_X) v += rx[(XIN & XIN_X) ? u : 0];
+      if (XIN & XIN_Z)
+        v += w_in * jdiv(conv<C>::from(rb[(XIN & XIN_Z) ? u : 0]), op.diag_aux(ra[(XIN & XIN_Z) ? u : 0], j0, j1, j2));
+      if (XIN & XIN_E) v += prolong_lds<DIM>(es, ex, ey, c0, c1, c2, j0, j1, j2);
+      if (!inside(g, i0, i1, i2)) v = mk((R)0, (R)0);
+      if ((int)threadIdx.x + 256 * u < tot) xs[k] = v;
+    }
+  } else {
+    for (int i4 = 0; i4 < NIT; i4 += 4)
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int it = i4 + u;
+      if (NIT % 4 != 0 && it >= NIT) break;
+      const int k = min((int)threadIdx.x + 256 * it, tot - 1);
+      const int a = k % SX, q = k / SX;
+      const int i0 = s0 + a, i1 = s1 + q % SY, i2 = s2 + q / SY;
+      int j0 = i0, j1 = i1, j2 = i2;
+      clamp_node(g, j0, j1, j2);
+      const int f = flat(g, j0, j1, j2);
+      C v = mk((R)0, (R)0);
+      if (XIN & XIN_X) v += x[f];
+      if (XIN & XIN_Z) v += w_in * jdiv(conv<C>::from(b[f]), op.diag(f, j0, j1, j2));
+      if (XIN & XIN_E) v += prolong_lds<DIM>(es, ex, ey, c0, c1, c2, j0, j1, j2);
+      if (!inside(g, i0, i1, i2)) v = mk((R)0, (R)0);
+      if ((int)threadIdx.x + 256 * it < tot) xs[k] = v;
+    }
   }
 }
 
@@ -242,7 +306,7 @@ __global__ void __launch_bounds__(256) k_sweep(Op op, const typename Op::C* __re
     const int a = k % TX, q = k / TX;
     int i0 = o0 + a, i1 = o1 + q % TY, i2 = o2 + q / TY;
     clamp_node(g, i0, i1, i2);
-    const long long f = flat(g, i0, i1, i2);
+    const int f = flat(g, i0, i1, i2);
     bo[it] = conv<C>::from(b[f]);
     Do[it] = op.diag(f, i0, i1, i2);
   }
@@ -259,7 +323,7 @@ __global__ void __launch_bounds__(256) k_sweep(Op op, const typename Op::C* __re
       const int a = k % SX, q = k / SX;
       int j0 = s0 + a, j1 = s1 + q % SY, j2 = s2 + q / SY;
       clamp_node(g, j0, j1, j2);
-      const long long f = flat(g, j0, j1, j2);
+      const int f = flat(g, j0, j1, j2);
       if (XIN & XIN_X) rx[it] = x[f];
       if (XIN & XIN_Z) {
         rb[it] = b[f];
@@ -291,7 +355,7 @@ __global__ void __launch_bounds__(256) k_sweep(Op op, const typename Op::C* __re
     const int a = k % TX, q = k / TX;
     const int i0 = o0 + a, i1 = o1 + q % TY, i2 = o2 + q / TY;
     if (!inside(g, i0, i1, i2)) continue;
-    const long long f = flat(g, i0, i1, i2);
+    const int f = flat(g, i0, i1, i2);
     const int kk = (a + 1) + SX * ((q % TY + 1) + SY * (DIM == 3 ? q / TY + 1 : 0));
     const C r = bo[it] - op.ax(xs, kk, SX, SX * SY, f, Do[it]);
     out[f] = conv<CO>::from(xs[kk] + w * jdiv(r, Do[it]));
@@ -333,7 +397,7 @@ __global__ void __launch_bounds__(256) k_restrict(Op op, const typename Op::C* _
     const int a = k % RX, q = k / RX;
     int i0 = r0 + a, i1 = r1 + q % RY, i2 = r2 + q / RY;
     clamp_node(g, i0, i1, i2);
-    const long long f = flat(g, i0, i1, i2);
+    const int f = flat(g, i0, i1, i2);
     bb = conv<C>::from(b[f]);
     dd = XIN ? op.diag(f, i0, i1, i2) : mk((R)0, (R)0);
   };
@@ -361,7 +425,7 @@ __global__ void __launch_bounds__(256) k_restrict(Op op, const typename Op::C* _
     const int i0 = r0 + a, i1 = r1 + q % RY, i2 = r2 + q / RY;
     C v = mk((R)0, (R)0);
     if (inside(g, i0, i1, i2)) {
-      const long long f = flat(g, i0, i1, i2);
+      const int f = flat(g, i0, i1, i2);
       v = bb;
       if (XIN) {
         const int kk = (a + 1) + SX * ((q % RY + 1) + SY * (DIM == 3 ? q / RY + 1 : 0));
@@ -462,7 +526,7 @@ static inline TileGrid tiles(const Geom& g, int bx, int by, int bz) {
   t.nt[0] = (g.N[0] + bx - 1) / bx;
   t.nt[1] = (g.N[1] + by - 1) / by;
   t.nt[2] = (g.N[2] + bz - 1) / bz;
-  t.ntiles = (long long)t.nt[0] * t.nt[1] * t.nt[2];
+  t.ntiles = t.nt[0] * t.nt[1] * t.nt[2];
   return t;
 }
 static inline unsigned grid_tiles(const TileGrid& t) { return (unsigned)((t.ntiles + 7) / 8 * 8); }
@@ -552,6 +616,20 @@ void l1_apply64(const L1<double>& A, const void* x, int x_is_f32, cd* y, hipStre
     hipLaunchKernelGGL((k_l1_apply64<cf>), grid, blk, 0, s, A, (const cf*)x, y);
   else
     hipLaunchKernelGGL((k_l1_apply64<cd>), grid, blk, 0, s, A, (const cd*)x, y);
+}
+
+__global__ void __launch_bounds__(256) k_l1_diag32(L1<float> A, cf* __restrict__ dg) {
+  const Geom& g = A.op.g;
+  for (long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x; f < g.tot;
+       f += (long long)gridDim.x * blockDim.x) {
+    int i0, i1, i2;
+    decode(g, f, i0, i1, i2);
+    dg[f] = A.diag(f, i0, i1, i2);
+  }
+}
+
+void l1_diag32(const L1<float>& A, cf* dg, hipStream_t s) {
+  hipLaunchKernelGGL(k_l1_diag32, dim3(2048), dim3(256), 0, s, A, dg);
 }
 
 void l1_apply32(const L1<float>& A, const cf* x, cf* y, hipStream_t s) {

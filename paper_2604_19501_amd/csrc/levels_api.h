@@ -11,23 +11,16 @@ enum : int { XIN_X = 1, XIN_Z = 2, XIN_E = 4 };
 // ----------------------------- level 1 -------------------------------------
 // complex coefficient c = s * m * (1 - i sigma) and diagonal 2d/h^2 - c
 // sigma of the absorbing layer in the arithmetic of the operator: the FP32 cycle evaluates
-// it in FP32 (one FP32 division per axis inside a layer instead of an FP64 one)
+// it in FP32 (reciprocal widths multiplied, no division, no branch)
 template <typename R>
 __device__ __forceinline__ R layer_sigma_r(const FineOp& op, int i0, int i1, int i2) {
   if (sizeof(R) == 8) return (R)layer_sigma(op, i0, i1, i2);
   const int ii[3] = {i0, i1, i2};
   float s = 0.f;
   for (int a = 0; a < op.g.dim; ++a) {
-    const int lo = op.layer[a][0], hi = op.layer[a][1], i = ii[a];
-    if (lo > 0 && i < lo) {
-      const float t = (float)(lo - i) / (float)lo;
-      s += t * t;
-    }
-    const int th = op.g.n[a] - hi;
-    if (hi > 0 && i > th) {
-      const float t = (float)(i - th) / (float)hi;
-      s += t * t;
-    }
+    const float tl = (float)max(op.layer[a][0] - ii[a], 0) * op.inv_wf[a][0];
+    const float th = (float)max(ii[a] - op.inner_hi[a], 0) * op.inv_wf[a][1];
+    s += tl * tl + th * th;
   }
   return (R)((float)op.sigma_max * s);
 }
@@ -39,6 +32,8 @@ struct L1 {
   C s;                 // (1 - i beta) omega^2 (times alpha^2 for a shifted operator)
   const R* m;          // squared slowness
   int conj;            // 1: coefficients of conj(H) (the adjoint, H being complex symmetric)
+  const C* dg = nullptr;   // the FP32 cycle: its diagonal precomputed at set-up (of the
+                           // operator, not of its conjugate), read instead of m
   // the coefficient and the diagonal from the node's squared slowness mm = m[f]
   __device__ __forceinline__ C coef_m(R mm, int i0, int i1, int i2) const {
     R sig = layer_sigma_r<R>(op, i0, i1, i2);
@@ -106,6 +101,8 @@ void l2_restrict(const L2<R>& A, int xin, const typename cplx<R>::type* x, const
                  R w_in, const Geom& gc, const typename cplx<R>::type* e, const Geom& g3,
                  typename cplx<R>::type* b3, int nrhs, hipStream_t s);
 void l1_apply64(const L1<double>& A, const void* x, int x_is_f32, cd* y, hipStream_t s);
+// dg[f] = the diagonal of A at every node (set-up of the FP32 cycle's level-1 operator)
+void l1_diag32(const L1<float>& A, cf* dg, hipStream_t s);
 void l1_apply32(const L1<float>& A, const cf* x, cf* y, hipStream_t s);
 
 }  // namespace helm
