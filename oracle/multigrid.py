@@ -26,9 +26,13 @@ from . import operators as ops
 
 
 class Hierarchy:
+    """stack 'p5fw': the 5/7-point operator with full weighting and linear interpolation;
+    'compact': the paper's compact fourth-order operator (eqs. (3.1)/(3.2)) with the transfers
+    named by `transfer` ('cubic', eq. (3.3); 'levdep', eq. (3.4); 'fw')."""
+
     def __init__(self, n, h, m, omega, layer, sigma_max, alpha=1.0, beta=0.0,
                  alpha2=1.0, cycle=2, nu_pre=1, nu_post=1, jacobi=(0.8, 0.8),
-                 conj=False, r_scale=1.0, p_scale=1.0):
+                 conj=False, r_scale=1.0, p_scale=1.0, stack="p5fw", transfer=None):
         n = tuple(int(k) for k in n)
         assert all(k % 4 == 0 for k in n), "three levels need n divisible by 4"
         self.n1, self.n2, self.n3 = n, ops.coarse(n), ops.coarse(ops.coarse(n))
@@ -36,16 +40,19 @@ class Hierarchy:
         self.sigma = ops.layer_sigma(n, layer, sigma_max)
         self.m = np.asarray(m, np.float64).ravel()
         self.omega = omega
+        op = ops.helmholtz if stack == "p5fw" else ops.helmholtz_compact
+        transfer = transfer or ("fw" if stack == "p5fw" else "cubic")
         # the operator the outer Krylov method solves (no shifts)
-        self.H = ops.helmholtz(n, h, self.m, omega, self.sigma)
-        A1 = ops.helmholtz(n, h, self.m, omega, self.sigma, beta=beta)
-        A1_a2 = A1 if alpha2 == 1.0 else ops.helmholtz(n, h, self.m, omega, self.sigma, beta=beta,
-                                                       alpha=alpha2)
-        A1_a = ops.helmholtz(n, h, self.m, omega, self.sigma, beta=beta, alpha=alpha)
-        self.R1 = r_scale * ops.restriction(self.n1)
-        self.P1 = p_scale * ops.prolongation(self.n1)
-        self.R2 = r_scale * ops.restriction(self.n2)
-        self.P2 = p_scale * ops.prolongation(self.n2)
+        self.H = op(n, h, self.m, omega, self.sigma)
+        A1 = op(n, h, self.m, omega, self.sigma, beta=beta)
+        A1_a2 = A1 if alpha2 == 1.0 else op(n, h, self.m, omega, self.sigma, beta=beta, alpha=alpha2)
+        A1_a = op(n, h, self.m, omega, self.sigma, beta=beta, alpha=alpha)
+        R1, P1 = ops.transfers(self.n1, transfer, 1)
+        R2, P2 = ops.transfers(self.n2, transfer, 2)
+        self.R1 = r_scale * R1
+        self.P1 = p_scale * P1
+        self.R2 = r_scale * R2
+        self.P2 = p_scale * P2
         A2 = ops.galerkin(self.R1, A1_a2, self.P1)
         A3 = ops.galerkin(self.R2, ops.galerkin(self.R1, A1_a, self.P1), self.P2)
         if conj:

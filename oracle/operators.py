@@ -19,6 +19,11 @@ Transfers (contract stack): 1-D full weighting R = [1 2 1]/4 on coarse nodes
 I = 0..n/2 (fine node 2I and its neighbours, truncated at the ends) and
 P = 2 R^T (linear interpolation); in d dimensions the Kronecker products, so
 P = 2^d R^T.  Galerkin coarsening is eq. (2.2): A_c = R A P.
+
+The paper's own stack (Sec. 3.1) is here too: the compact fourth-order 9-point (2D, eq.
+(3.1)) and 19-point (3D, eq. (3.2)) operators H = L_h - M_h diag(c), and the high-order
+transfers R = (x) [1 4 6 4 1]/16 (eq. (3.3)) and their level-dependent variant with full
+weighting from level 2 to 3 (eq. (3.4)), prolongation 2^d R^T in every case.
 """
 from __future__ import annotations
 
@@ -61,6 +66,72 @@ def neg_laplacian(n: Sequence[int], h: float) -> sp.csr_matrix:
         term = kron_axes(mats)
         out = term if out is None else out + term
     return out.tocsr()
+
+
+def compact_laplacian(n: Sequence[int], h: float) -> sp.csr_matrix:
+    """the fourth-order compact Laplacian of eq. (3.1) (2D) / eq. (3.2) (3D) with zero ghost
+    values, as Kronecker products of T = tridiag(-1, 2, -1)/h^2: L5 - (h^2/6) T (x) T in 2D and
+    L7 - (h^2/6)(T(x)T(x)I + T(x)I(x)T + I(x)T(x)T) in 3D (L5, L7: the 5/7-point sums)."""
+    d = len(n)
+    Ns = nodes(n)
+    T = [lap1d(n[a], h) for a in range(d)]
+    Id = [sp.identity(Ns[a], format="csr") for a in range(d)]
+    out = neg_laplacian(n, h)
+    for a in range(d):
+        for b in range(a + 1, d):
+            mats = list(Id)
+            mats[a], mats[b] = T[a], T[b]
+            out = out - (h * h / 6.0) * kron_axes(mats)
+    return out.tocsr()
+
+
+def compact_mass(n: Sequence[int], h: float) -> sp.csr_matrix:
+    """the mass operator of eqs. (3.1)/(3.2): I - (h^2/12) L5 (2D, [0 1 0; 1 8 1; 0 1 0]/12)
+    and I - (h^2/12) L7 (3D, centre 6/12 and the six face neighbours 1/12)."""
+    N = int(np.prod(nodes(n)))
+    return (sp.identity(N, format="csr") - (h * h / 12.0) * neg_laplacian(n, h)).tocsr()
+
+
+def helmholtz_compact(n, h, m, omega, sigma, beta=0.0, alpha=1.0) -> sp.csr_matrix:
+    """H = L_h - M_h diag(c), the compact fourth-order operator with the zeroth-order
+    coefficient c of `coefficient` (eq. (1.1), (3.1)/(3.2), the shifts of (3.5))."""
+    c = coefficient(m, omega, sigma, beta, alpha)
+    L = compact_laplacian(n, h).astype(np.complex128)
+    return (L - compact_mass(n, h).astype(np.complex128) @ sp.diags(c)).tocsr()
+
+
+def restriction1d_cubic(n: int) -> sp.csr_matrix:
+    """the high-order restriction [1 4 6 4 1]/16 (eq. (3.3)) from nodes 0..n onto 0..n/2"""
+    assert n % 2 == 0
+    nc = n // 2
+    rows, cols, vals = [], [], []
+    for I in range(nc + 1):
+        for o, w in ((-2, 1 / 16), (-1, 4 / 16), (0, 6 / 16), (1, 4 / 16), (2, 1 / 16)):
+            f = 2 * I + o
+            if 0 <= f <= n:
+                rows.append(I)
+                cols.append(f)
+                vals.append(w)
+    return sp.csr_matrix((vals, (rows, cols)), shape=(nc + 1, n + 1))
+
+
+def transfers(n: Sequence[int], kind: str, level: int):
+    """(R, P) between level `level` (1 = fine, grid n) and the next: kind 'fw' (full
+    weighting, linear interpolation), 'cubic' (eq. (3.3) both ways) or 'levdep' (eq. (3.4):
+    cubic except the restriction from level 2 to 3, which is full weighting); P = 2^d R^T of
+    the interpolating restriction in every case."""
+    d = len(n)
+    cub = kron_axes([restriction1d_cubic(k) for k in n])
+    fw = restriction(n)
+    if kind == "fw":
+        R, Rp = fw, fw
+    elif kind == "cubic":
+        R, Rp = cub, cub
+    elif kind == "levdep":
+        R, Rp = (cub if level == 1 else fw), cub
+    else:
+        raise ValueError(kind)
+    return R.tocsr(), ((2.0 ** d) * Rp.T).tocsr()
 
 
 def layer_sigma(n: Sequence[int], layer, sigma_max: float) -> np.ndarray:
