@@ -261,7 +261,8 @@ int helm_get_timing(helm_ctx* ctx, double* t, int n);
  * bytes, [11] largest front size nF, [12] bytes per complex of the cycle (8 or 16),
  * [13] leaf box size and [14] root merge limit of the nested dissection, [15] 1 if the
  * schedule came from the autotuner cache (HELM_TUNE_CACHE), [16] number of tree-block
- * launches per direction, [17..20] the heights closing them (-1 beyond).
+ * launches per direction, [17..20] the heights closing them (-1 beyond), [21] bit mask of
+ * the dissection-tree heights whose fronts were merged into their parents.
  * Returns the number of entries written (at most n). */
 int helm_get_info(helm_ctx* ctx, long long* out, int n);
 

@@ -62,8 +62,8 @@ class BatchedSolver:
 
     def instance_info(self, inst: int) -> dict:
         """sizes of instance inst (helm_get_info's fields)"""
-        v = (C.c_longlong * 21)()
-        L.check(L.lib.helm_get_instance_info(self.ctx, int(inst), v, 21), "helm_get_instance_info")
+        v = (C.c_longlong * 22)()
+        L.check(L.lib.helm_get_instance_info(self.ctx, int(inst), v, 22), "helm_get_instance_info")
         return parse_info(v)
 
     def set_timing(self, on: bool = True):

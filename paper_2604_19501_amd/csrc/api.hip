@@ -186,6 +186,7 @@ struct helm_ctx {
   size_t lds_panel = 0;         // LDS bytes for a resident factorisation panel (device maximum - 2 KB)
   bool tuned = false;           // schedule parameters came from the autotuner cache
   int nd_leaf = 0, nd_root = 0;  // nested-dissection leaf size and root merge limit in use
+  long long nd_merge = 0;        // bit h: fronts of dissection height h merged into their parents
   std::vector<helm_ctx*> sub;   // batched form: one context per instance
   std::vector<hipStream_t> bstreams;   // batched form: streams of the concurrent instances
   // one captured graph per (operator, Arnoldi index j): cycle on V_j + Arnoldi step
@@ -266,12 +267,13 @@ int env_int(const char* name, int dflt) {
 }
 
 // schedule parameters of the coarsest solve picked by the autotuner: the JSON file named
-// by HELM_TUNE_CACHE maps "nd:<dim>:<n0>x<n1>x<n2>:<f32|f64>" to an object with integer
-// "leaf" and "root" and a string "cuts"; returns false when the file or the key is absent
+// by HELM_TUNE_CACHE maps "nd:<dim>:<n0>x<n1>x<n2>:<f32|f64>" to an object with integers
+// "leaf", "root" and "splitk_kb" and strings "cuts" and "merge"; returns false when the file
+// or the key is absent
 struct TunedND {
-  int leaf = -1, root = -1;
-  std::string cuts;
-  bool has_cuts = false;
+  int leaf = -1, root = -1, splitk_kb = -1;
+  std::string cuts, merge;
+  bool has_cuts = false, has_merge = false;
 };
 bool tuned_nd(const helm_ctx* c, TunedND& t) {
   const char* path = getenv("HELM_TUNE_CACHE");
@@ -299,15 +301,19 @@ bool tuned_nd(const helm_ctx* c, TunedND& t) {
   };
   num("\"leaf\"", t.leaf);
   num("\"root\"", t.root);
-  size_t p = obj.find("\"cuts\"");
-  if (p != std::string::npos) {
+  num("\"splitk_kb\"", t.splitk_kb);
+  auto str = [&](const char* name, std::string& out, bool& has) {
+    size_t p = obj.find(name);
+    if (p == std::string::npos) return;
     size_t q0 = obj.find('"', obj.find(':', p));
     size_t q1 = q0 == std::string::npos ? q0 : obj.find('"', q0 + 1);
     if (q0 != std::string::npos && q1 != std::string::npos) {
-      t.cuts = obj.substr(q0 + 1, q1 - q0 - 1);
-      t.has_cuts = true;
+      out = obj.substr(q0 + 1, q1 - q0 - 1);
+      has = true;
     }
-  }
+  };
+  str("\"cuts\"", t.cuts, t.has_cuts);
+  str("\"merge\"", t.merge, t.has_merge);
   return true;
 }
 
@@ -327,8 +333,8 @@ std::vector<int> parse_cuts(const char* v) {
   return cuts;
 }
 
-// nested-dissection parameters: environment (HELM_ND_LEAF, HELM_ND_ROOT, HELM_ND_CUTS),
-// else the autotuner's cache, else defaults and the planner's cost model
+// nested-dissection parameters: environment (HELM_ND_LEAF, HELM_ND_ROOT, HELM_ND_CUTS,
+// HELM_ND_MERGE), else the autotuner's cache, else defaults and the planner's cost model
 void build_plan(helm_ctx* c) {
   TunedND tn;
   const bool tuned = tuned_nd(c, tn);
@@ -342,15 +348,29 @@ void build_plan(helm_ctx* c) {
     cuts = parse_cuts(v);
   else if (tuned && tn.has_cuts)
     cuts = parse_cuts(tn.cuts.c_str());
+  // merged heights: "1,3,5" (heights of the dissection tree whose fronts join their
+  // parents), "none" or empty for none
+  std::vector<int> mh;
+  {
+    const char* v = getenv("HELM_ND_MERGE");
+    std::string mv = v ? std::string(v) : (tuned && tn.has_merge ? tn.merge : std::string());
+    if (!mv.empty() && mv != "none") mh = parse_cuts(mv.c_str());
+  }
+  c->nd_merge = 0;
+  for (int h : mh) {
+    if (h < 0 || h > 62) throw std::runtime_error("HELM_ND_MERGE: heights 0..62");
+    c->nd_merge |= 1LL << h;
+  }
   c->tuned = tuned;
   c->nd_leaf = leaf;
   c->nd_root = merge;
   // heights above the tree blocks with at least this many factor bytes use split-K launches
-  const long long splitk = (long long)env_int("HELM_ND_SPLITK_KB", 4096) * 1024;
+  const long long splitk =
+      (long long)env_int("HELM_ND_SPLITK_KB", tuned && tn.splitk_kb > 0 ? tn.splitk_kb : 4096) * 1024;
   // tree-block work-groups of at most HELM_ND_TREE_WAVES wavefronts: 16 in 2D; 8 in 3D, where
   // the many small subtrees run two work-groups per CU (measured 3 % faster at 256^3)
   const int tree_waves = env_int("HELM_ND_TREE_WAVES", c->grid.dim == 3 ? 8 : 16);
-  nd_plan(c->g3, leaf, 16, merge, (int)c->csz, lds, cuts, splitk, c->plan, tree_waves);
+  nd_plan(c->g3, leaf, 16, merge, (int)c->csz, lds, cuts, splitk, c->plan, tree_waves, mh);
   NDPlan& P = c->plan;
   c->hlist.clear();
   c->hlist_toff.clear();
@@ -1446,13 +1466,13 @@ int helm_get_info(helm_ctx* c, long long* out, int n) {
     sB += f.nB;
     maxF = std::max<long long>(maxF, f.nF);
   }
-  long long v[21] = {c->g1.tot, c->g2.tot, c->g3.tot, (long long)P.fronts.size(), P.L_total, P.W_total, sB,
+  long long v[22] = {c->g1.tot, c->g2.tot, c->g3.tot, (long long)P.fronts.size(), P.L_total, P.W_total, sB,
                      c->g3.tot, (long long)nd_kernels(c->nd.launch[0]), (long long)nd_kernels(c->nd.launch[1]),
                      (long long)c->ws_needed, maxF,
                      (long long)c->csz, c->nd_leaf, c->nd_root, c->tuned ? 1 : 0, (long long)P.cuts.size(),
-                     -1, -1, -1, -1};
+                     -1, -1, -1, -1, c->nd_merge};
   for (size_t i = 0; i < P.cuts.size() && i < 4; ++i) v[17 + i] = P.cuts[i];
-  int m = std::min(n, 21);
+  int m = std::min(n, 22);
   for (int i = 0; i < m; ++i) out[i] = v[i];
   return m;
 }

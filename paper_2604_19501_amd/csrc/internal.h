@@ -312,8 +312,11 @@ struct NDPlan {
 // splitk_bytes: heights above the tree blocks whose factor blocks hold at least this many
 // bytes (per direction) use split-K launches
 // tree_waves: the most wavefronts of a tree-block work-group (16 = 1024 threads)
+// merge_heights: heights of the dissection tree (leaves 0, before any merge) whose fronts are
+// merged into their parents (fewer levels, larger fronts)
 void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int root_merge, int elem_bytes, int lds_bytes,
-             const std::vector<int>& cuts, long long splitk_bytes, NDPlan& plan, int tree_waves = 16);
+             const std::vector<int>& cuts, long long splitk_bytes, NDPlan& plan, int tree_waves = 16,
+             const std::vector<int>& merge_heights = std::vector<int>());
 
 
 }  // namespace helm

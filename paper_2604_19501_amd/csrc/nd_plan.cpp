@@ -97,7 +97,8 @@ struct Builder {
 }  // namespace
 
 void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int root_merge, int elem_bytes, int lds_bytes,
-             const std::vector<int>& cuts, long long splitk_bytes, NDPlan& plan, int tree_waves) {
+             const std::vector<int>& cuts, long long splitk_bytes, NDPlan& plan, int tree_waves,
+             const std::vector<int>& merge_heights) {
   tree_waves = std::max(1, std::min(16, tree_waves));
   Builder bd;
   bd.g = g3;
@@ -109,8 +110,34 @@ void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int root_merge, int e
   }
   bd.build(rootbox, -1);
   const int nraw = (int)bd.box.size();
-  // ---- merge whole levels of separators into the root while its separator stays <= root_merge
   std::vector<char> alive(nraw, 1);
+  // ---- amalgamation: every front whose height in the dissection tree (leaves 0) is listed
+  // in merge_heights joins its separator to its parent's, and its children become the
+  // parent's.  The parent's box contains the child's, so its boundary is unchanged and the
+  // elimination stays exact; the tree loses those levels, at the price of larger fronts.
+  if (!merge_heights.empty()) {
+    std::vector<int> hraw(nraw, 0), host(nraw);
+    for (int t = nraw - 1; t >= 0; --t)        // children have larger ids than their parent
+      for (int c : bd.kids[t]) hraw[t] = std::max(hraw[t], hraw[c] + 1);
+    std::set<int> mh(merge_heights.begin(), merge_heights.end());
+    for (int t = 0; t < nraw; ++t) {
+      host[t] = t;
+      if (t == 0 || !mh.count(hraw[t])) continue;
+      const int q = host[bd.parent[t]];        // resolved first: parents precede children
+      bd.S[q].insert(bd.S[q].end(), bd.S[t].begin(), bd.S[t].end());
+      alive[t] = 0;
+      host[t] = q;
+    }
+    for (int t = 0; t < nraw; ++t) bd.kids[t].clear();
+    for (int t = 1; t < nraw; ++t)
+      if (alive[t]) {
+        bd.parent[t] = host[bd.parent[t]];
+        bd.kids[bd.parent[t]].push_back(t);
+      }
+    for (int t = 0; t < nraw; ++t)
+      if (alive[t]) std::sort(bd.S[t].begin(), bd.S[t].end());
+  }
+  // ---- merge whole levels of separators into the root while its separator stays <= root_merge
   {
     std::vector<int> frontier = bd.kids[0];
     while (!frontier.empty()) {

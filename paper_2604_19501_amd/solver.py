@@ -27,9 +27,10 @@ KERNEL_CLASSES = ("l1_sweep", "l1_restrict", "l2_sweep", "l2_restrict", "nd_fwd"
 
 
 def parse_info(v) -> dict:
-    """the 21 integers of helm_get_info as a dict"""
+    """the 22 integers of helm_get_info as a dict"""
     out = {k: int(v[i]) for i, k in enumerate(INFO_KEYS)}
     out["nd_cuts"] = [int(v[17 + i]) for i in range(min(4, out["nd_tree_launches"]))]
+    out["nd_merge"] = [h for h in range(63) if (int(v[21]) >> h) & 1]
     return out
 
 
@@ -275,8 +276,8 @@ class Solver:
 
 
     def info(self) -> dict:
-        v = (C.c_longlong * 21)()
-        L.check(L.lib.helm_get_info(self.ctx, v, 21), "helm_get_info")
+        v = (C.c_longlong * 22)()
+        L.check(L.lib.helm_get_info(self.ctx, v, 22), "helm_get_info")
         return parse_info(v)
 
     def set_timing(self, on: bool = True):

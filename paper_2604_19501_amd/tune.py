@@ -1,9 +1,11 @@
 """Autotuner of the coarsest-solve schedule.
 
-The exact coarsest solve (nested dissection, see csrc/nd_plan.cpp) has three schedule
+The exact coarsest solve (nested dissection, see csrc/nd_plan.cpp) has five schedule
 parameters that change its speed but not its result: the leaf box size, the size up to
-which the top separators are merged into one root front, and the tree heights at which
-the tree-block launches end (HELM_ND_CUTS).  For a grid shape and cycle precision this
+which the top separators are merged into one root front, the dissection-tree heights whose
+fronts are merged into their parents (HELM_ND_MERGE: fewer dependent levels, larger
+fronts), the tree heights at which the tree-block launches end (HELM_ND_CUTS) and the
+factor bytes per height from which a height takes split-K launches (HELM_ND_SPLITK_KB).  For a grid shape and cycle precision this
 tool times FGMRES iterations of a seeded problem of that shape under every candidate
 schedule and records the best-scoring one in a JSON cache, which libhelm reads when it plans a
 context of that shape (file named by HELM_TUNE_CACHE; the package sets it to
@@ -31,7 +33,25 @@ from . import _lib as L
 from .solver import Solver
 
 
+# merged-height sets: every second level (odd or even heights), two of every three, and
+# every second level above the lower tree only; heights past the tree's are ignored
+MERGES = {
+    "none": "none",
+    "odd": ",".join(str(h) for h in range(1, 40, 2)),
+    "even": ",".join(str(h) for h in range(2, 40, 2)),
+    "two_of_three": ",".join(str(h) for h in range(1, 40) if h % 3),
+    "odd_from_5": ",".join(str(h) for h in range(5, 40, 2)),
+}
+
+
+SPLITK_DEFAULT_KB = 4096
+SPLITK_OFF_KB = 1 << 30
+
+
 def _candidates(dim: int):
+    """(leaf, root, cuts, merge, splitk_kb) in two stages: the grid of leaf x root x cuts
+    without merged heights, then every merged-height set with the cuts and both split-K
+    thresholds under the best stage-one leaf sizes and root limits (_stage_two)."""
     if dim == 2:
         leaves, roots = (16, 32, 64), (100, 300, 600, 1100, 2200)
     else:
@@ -40,7 +60,25 @@ def _candidates(dim: int):
     for leaf in leaves:
         for root in roots:
             for c in cuts:
-                yield leaf, root, c
+                yield leaf, root, c, "none", SPLITK_DEFAULT_KB
+
+
+def _stage_two(results, top=3):
+    cuts = ["", "none"] + [str(h) for h in range(0, 5)] + ["1,3", "2,4", "1,2", "2,3"]
+    seen = set()
+    for r in sorted(results, key=lambda r: r["score_ms"]):
+        lr = (r["leaf"], r["root"])
+        if lr in seen:
+            continue
+        seen.add(lr)
+        if len(seen) > top:
+            break
+        for name, m in MERGES.items():
+            for sk in (SPLITK_DEFAULT_KB, SPLITK_OFF_KB):
+                if name == "none" and sk == SPLITK_DEFAULT_KB:
+                    continue           # stage one
+                for c in cuts:
+                    yield lr[0], lr[1], c, m, sk
 
 
 def _problem(n, G=10.0, layer=8):
@@ -53,9 +91,10 @@ def _problem(n, G=10.0, layer=8):
     return dim, h, kappa, omega, tuple((layer, layer) for _ in range(dim))
 
 
-def time_schedule(n, prec, leaf, root, cuts, iters=30, repeats=2):
+def time_schedule(n, prec, leaf, root, cuts, iters=30, repeats=2, merge="none", splitk_kb=SPLITK_DEFAULT_KB):
     """(seconds per FGMRES iteration, seconds per numerical set-up, plan info)"""
-    env = {"HELM_ND_LEAF": str(leaf), "HELM_ND_ROOT": str(root), "HELM_ND_CUTS": cuts}
+    env = {"HELM_ND_LEAF": str(leaf), "HELM_ND_ROOT": str(root), "HELM_ND_CUTS": cuts,
+           "HELM_ND_MERGE": merge, "HELM_ND_SPLITK_KB": str(splitk_kb)}
     saved = {k: os.environ.get(k) for k in env}
     os.environ.update(env)
     try:
@@ -93,23 +132,31 @@ def tune(n, prec="f32", out=None, its=150, verbose=True):
     dim = len(n)
     key = "nd:%d:%s:%s" % (dim, "x".join(str(k) for k in (n + (0,) * (3 - dim))), prec)
     results, seen = [], set()
-    for leaf, root, cuts in _candidates(dim):
-        try:
-            t, ts, info = time_schedule(n, prec, leaf, root, cuts)
-        except L.HelmError as e:
+
+    def run(cands):
+        for leaf, root, cuts, merge, sk in cands:
+            try:
+                t, ts, info = time_schedule(n, prec, leaf, root, cuts, merge=merge, splitk_kb=sk)
+            except L.HelmError as e:
+                if verbose:
+                    print("  leaf %d root %d cuts %r merge %r: %s" % (leaf, root, cuts, merge, e), flush=True)
+                continue
+            eff = (leaf, root, tuple(info["nd_cuts"]), tuple(info["nd_merge"]), info["fwd_launches"],
+                   info["bwd_launches"])
+            if eff in seen:            # the planner dropped cuts that do not fit: same schedule
+                continue
+            seen.add(eff)
+            results.append({"leaf": leaf, "root": root, "cuts": ",".join(map(str, info["nd_cuts"])) or "none",
+                            "merge": ",".join(map(str, info["nd_merge"])) or "none", "splitk_kb": sk,
+                            "us_per_it": round(t * 1e6, 2), "setup_ms": round(ts * 1e3, 3),
+                            "score_ms": round((ts + its * t) * 1e3, 3)})
             if verbose:
-                print("  leaf %d root %d cuts %r: %s" % (leaf, root, cuts, e), flush=True)
-            continue
-        eff = (leaf, root, tuple(info["nd_cuts"]))
-        if eff in seen:            # the planner dropped cuts that do not fit: same schedule
-            continue
-        seen.add(eff)
-        results.append({"leaf": leaf, "root": root, "cuts": ",".join(map(str, info["nd_cuts"])) or "none",
-                        "us_per_it": round(t * 1e6, 2), "setup_ms": round(ts * 1e3, 3),
-                        "score_ms": round((ts + its * t) * 1e3, 3)})
-        if verbose:
-            print("  leaf %3d root %5d cuts %-8s -> %8.1f us/iteration, set-up %8.2f ms, score %8.2f ms" % (
-                leaf, root, results[-1]["cuts"], t * 1e6, ts * 1e3, results[-1]["score_ms"]), flush=True)
+                print("  leaf %3d root %5d cuts %-8s merge %-12s split-K %10d KB -> %8.1f us/iteration, "
+                      "set-up %8.2f ms, score %8.2f ms" % (leaf, root, results[-1]["cuts"], results[-1]["merge"][:12],
+                                                          sk, t * 1e6, ts * 1e3, results[-1]["score_ms"]), flush=True)
+
+    run(_candidates(dim))
+    run(list(_stage_two(results, top=3 if dim == 2 else 1)))
     results.sort(key=lambda r: r["score_ms"])
     best = dict(results[0])
     best["device"] = torch.cuda.get_device_name(0)
@@ -124,8 +171,9 @@ def tune(n, prec="f32", out=None, its=150, verbose=True):
     with open(path, "w") as f:
         json.dump(cache, f, indent=1, sort_keys=True)
     if verbose:
-        print("%s -> leaf %d root %d cuts %s (%.1f us/iteration, set-up %.2f ms), written to %s" % (
-            key, best["leaf"], best["root"], best["cuts"], best["us_per_it"], best["setup_ms"], path), flush=True)
+        print("%s -> leaf %d root %d cuts %s merge %s (%.1f us/iteration, set-up %.2f ms), written to %s" % (
+            key, best["leaf"], best["root"], best["cuts"], best["merge"], best["us_per_it"], best["setup_ms"],
+            path), flush=True)
     return key, best
 
 

@@ -26,6 +26,7 @@ pytestmark = pytest.mark.gpu
 L = pytest.importorskip("paper_2604_19501_amd._lib")
 from paper_2604_19501_amd import HELM_OP_C, HELM_OP_N, from_problem  # noqa: E402
 from oracle import fgmres  # noqa: E402
+from paper_2604_19501_amd.tune import MERGES  # noqa: E402
 
 
 def _rand(N, seed):
@@ -80,14 +81,20 @@ def test_coarse_solve(case, prec, tol):
 @pytest.mark.parametrize("cuts,panel,splitk", [("none", "lds", None), ("", "lds", None), ("1", "lds", None),
                                                ("0,1,2,3", "lds", None), ("", "multi", None), ("none", "lds", 0),
                                                ("1", "multi", 0), ("", "multi64", None), ("", "multi_unblocked", None),
-                                               ("", "lds_waves4", None), ("", "lds_blocked", None)])
+                                               ("", "lds_waves4", None), ("", "lds_blocked", None),
+                                               ("", "lds_merge_odd", None), ("1", "lds_merge_even", 0),
+                                               ("none", "multi_merge_two_of_three", None)])
 def test_coarse_solve_schedules(monkeypatch, dim, n, cuts, panel, splitk):
     """the exact coarsest solve under every kind of substitution schedule (row-chunk
     launches only, the planner's choice, one tree-block launch, one per level, split-K
-    launches for every height above the tree blocks) and with both factorisation panel
+    launches for every height above the tree blocks), with both factorisation panel
     paths (LDS-resident; multi-work-group panels of 64 or 32 columns in blocks of 128 with
-    one trailing update per block, or one trailing update per 64-column panel)."""
+    one trailing update per block, or one trailing update per 64-column panel) and with
+    dissection levels merged into their parents (every second level, two of every three)."""
     monkeypatch.setenv("HELM_ND_CUTS", cuts)
+    for name, heights in MERGES.items():
+        if panel.endswith("_merge_" + name):
+            monkeypatch.setenv("HELM_ND_MERGE", heights)
     if panel.startswith("multi"):
         monkeypatch.setenv("HELM_ND_LDS_PANEL", "0")
     if panel == "multi64":
