@@ -471,8 +471,8 @@ size_t carve(helm_ctx* c, void* ws) {
   d.err = cv.take<int>(1);
   d.F = cv.take<cd>(P.F_total);
   d.T = cv.take<cd>(std::max<long long>(1, P.T_scratch));
-  d.L = cv.take<char>(cs * P.L_total);
-  d.W = cv.take<char>(cs * std::max<long long>(1, P.W_total));
+  d.L = cv.take<char>(cs * P.L_alloc);
+  d.W = cv.take<char>(cs * std::max<long long>(1, P.W_alloc));
   long long gbuf_max = 1, part_max = 1;      // split-K buffers (entries)
   for (int fb = 0; fb < 2; ++fb) {
     std::vector<NDLaunch>& Ls = fb == 0 ? P.fwd : P.bwd;

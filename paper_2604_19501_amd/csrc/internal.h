@@ -172,12 +172,15 @@ struct NDFrontDev {
   long long inv_off;    // nF+1 ints at cptr[inv_off]: contributions to position i are
                         // cidx[cptr[i] .. cptr[i+1]) (absolute indices into the update pool)
   long long F_off;      // nF*nF cd (row major), setup scratch; holds Schur block for parent
-  long long L_off;      // nF x nS column major (ld nF): left block column [A^-1; C A^-1] (cycle precision)
-  long long W_off;      // nS x nB column major (ld nS): top-right block -A^-1 B          (cycle precision)
+  long long L_off;      // nF x nS column major (ld ldL): left block column [A^-1; C A^-1] (cycle precision)
+  long long W_off;      // nS x nB column major (ld ldW): top-right block -A^-1 B          (cycle precision)
   long long upd_off;    // nB update vector (cycle precision)
   long long perm_off;   // nS ints
   long long asm_off;    // assembly entries
   int asm_cnt;
+  // leading dimensions of L and W: nF and nS rounded up to 128 bytes, with L_off and W_off
+  // multiples of 128 bytes, so that a column run of a row chunk starts on a cache line
+  int ldL, ldW;
   int pad;
 };
 
@@ -200,6 +203,7 @@ struct NDItem {         // one work item of a multi-block launch: rows [r0, r1) 
   // the front's fields the work item needs (copied, so a work-group reads one record)
   int nS, nF, nB;
   int g0;               // forward: the front's gather list (one entry per front row) in the launch's gath
+  int ld, pad;          // leading dimension of the block (ldL forward, ldW backward)
   long long m_off;      // L_off (forward) or W_off (backward)
   long long idx_off, inv_off, upd_off;
 };
@@ -300,6 +304,7 @@ struct NDPlan {
   std::vector<std::vector<int>> by_height;   // front ids per height
   int max_height = 0;
   long long F_total = 0, L_total = 0, W_total = 0, upd_total = 0, perm_total = 0;
+  long long L_alloc = 0, W_alloc = 0;   // entries of the padded L and W storage
   long long T_scratch = 0;              // doubles2 of panel row buffer (max over heights)
   int max_nS = 0, max_nB = 0, max_nF = 0;
   std::vector<NDLaunch> fwd, bwd;

@@ -563,13 +563,13 @@ __global__ void __launch_bounds__(256) k_nd_finalize(const NDFrontDev* __restric
   long long nL = (long long)f.nF * f.nS, nW = (long long)f.nS * f.nB;
   for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < nL + nW;
        p += (long long)gridDim.x * blockDim.x) {
-    if (p < nL) {                 // column pm[k] of L (column major, ld nF) <- column k of F
+    if (p < nL) {                 // column pm[k] of L (column major, ld ldL) <- column k of F
       int i = (int)(p / f.nS), k = (int)(p % f.nS);
-      Lp[f.L_off + (long long)pm[k] * f.nF + i] = conv<C>::from(F[(long long)i * f.nF + k]);
-    } else {                      // W (column major, ld nS) <- F[0:nS, nS:nF]
+      Lp[f.L_off + (long long)pm[k] * f.ldL + i] = conv<C>::from(F[(long long)i * f.nF + k]);
+    } else {                      // W (column major, ld ldW) <- F[0:nS, nS:nF]
       long long q = p - nL;
       int i = (int)(q / f.nB), j = (int)(q % f.nB);
-      Wp[f.W_off + (long long)j * f.nS + i] = conv<C>::from(F[(long long)i * f.nF + f.nS + j]);
+      Wp[f.W_off + (long long)j * f.ldW + i] = conv<C>::from(F[(long long)i * f.nF + f.nS + j]);
     }
   }
 }
@@ -690,9 +690,9 @@ __device__ __forceinline__ void load_seg(const C* __restrict__ M, const NDSeg& s
 //   segments: partial products of <= 64 rows over <= 16 columns       one wavefront, two at a time
 //             (<= 32 rows over <= 32 columns, <= 16 rows over <= 64 columns)
 //   outputs:  sum of a row block's partials, write x or the update    one wavefront each
-// forward (FWD = 1): M = L = [A^-1; C A^-1] (ld nF), src = r;  rows < nS give x_S = g_S,
+// forward (FWD = 1): M = L = [A^-1; C A^-1] (ld ldL), src = r;  rows < nS give x_S = g_S,
 //                    rows >= nS the update v_B - C A^-1 f_S of the parent
-// backward:          M = W = -A^-1 B (ld nS), src = x (the boundary solution);  x_S += W x_B
+// backward:          M = W = -A^-1 B (ld ldW), src = x (the boundary solution);  x_S += W x_B
 // The task's schedule is copied to LDS first, so a stage costs two dependent global
 // accesses (gathered values, matrix entries) besides its barriers.
 template <typename C, int FWD>
@@ -936,12 +936,12 @@ __global__ void __launch_bounds__(256) k_nd_fwd_big(const NDGather* __restrict__
   const NDItem f = items[blockIdx.x];
   const int* id = idx + f.idx_off;
   C m0[16];
-  gemv16_load(Lp + f.m_off, f.nF, f.r0, f.r1, f.nS, m0);
+  gemv16_load(Lp + f.m_off, f.ld, f.r0, f.r1, f.nS, m0);
   const NDGather* gl = gath + f.g0;
   for (int i = threadIdx.x; i < f.nS; i += 256) vec[i] = gather_list(gl[i], cidx, upd, r);
   for (int i = max(f.r0, f.nS) + threadIdx.x; i < f.r1; i += 256) vec[i] = gather_list(gl[i], cidx, upd, r);
   __syncthreads();
-  C acc = gemv16_finish(Lp + f.m_off, f.nF, f.r0, f.r1, f.nS, vec, conj, red, m0);
+  C acc = gemv16_finish(Lp + f.m_off, f.ld, f.r0, f.r1, f.nS, vec, conj, red, m0);
   const int i = f.r0 + threadIdx.x;
   if (threadIdx.x < 16 && i < f.r1) {
     if (i < f.nS)
@@ -963,12 +963,12 @@ __global__ void __launch_bounds__(256) k_nd_bwd_big(const NDFrontDev* __restrict
   const NDItem f = items[blockIdx.x];
   const int* id = idx + f.idx_off;
   C m0[16];
-  gemv16_load(Wp + f.m_off, f.nS, f.r0, f.r1, f.nB, m0);
+  gemv16_load(Wp + f.m_off, f.ld, f.r0, f.r1, f.nB, m0);
   const int i = f.r0 + threadIdx.x;
   const int di = threadIdx.x < 16 && i < f.r1 ? id[i] : 0;
   for (int j = threadIdx.x; j < f.nB; j += 256) vec[j] = x[id[f.nS + j]];
   __syncthreads();
-  C acc = gemv16_finish(Wp + f.m_off, f.nS, f.r0, f.r1, f.nB, vec, conj, red, m0);
+  C acc = gemv16_finish(Wp + f.m_off, f.ld, f.r0, f.r1, f.nB, vec, conj, red, m0);
   if (threadIdx.x < 16 && i < f.r1) x[di] = x[di] + acc;
 }
 
@@ -1005,7 +1005,7 @@ __global__ void __launch_bounds__(256) k_nd_tile(const NDFrontDev* __restrict__ 
   P += blockIdx.y * rh.part;
   const NDTile t = tiles[blockIdx.x];
   const NDFrontDev f = fr[t.front];
-  const int ld = FWD ? f.nF : f.nS, rows = FWD ? f.nF : f.nS;
+  const int ld = FWD ? f.ldL : f.ldW, rows = FWD ? f.nF : f.nS;
   const int nk = t.k1 - t.k0;
   if ((int)threadIdx.x < nk) vec[threadIdx.x] = gbuf[t.voff + t.k0 + threadIdx.x];
   __syncthreads();

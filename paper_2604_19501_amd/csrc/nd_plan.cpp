@@ -196,7 +196,9 @@ void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int root_merge, int e
   plan.max_height = 0;
   plan.max_children = 0;
   plan.max_nS = plan.max_nB = plan.max_nF = 0;
-  long long F = 0, L = 0, W = 0, U = 0, P = 0;
+  long long F = 0, L = 0, W = 0, U = 0, P = 0, La = 0, Wa = 0;
+  const long long line = std::max(1, 128 / std::max(1, elem_bytes));   // entries per 128 bytes
+  auto pad_ld = [&](long long n) { return (n + line - 1) / line * line; };
   auto Bof = [&](int t) -> const std::vector<int>& { return bd.B[oid[t]]; };
   auto posF = [&](int t, int v) -> int {   // position of node v in front t's (S, B) list, -1 if absent
     if (owner[v] == t) return pos_in_S[v];
@@ -218,8 +220,12 @@ void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int root_merge, int e
     plan.idx.insert(plan.idx.end(), bd.S[oid[t]].begin(), bd.S[oid[t]].end());
     plan.idx.insert(plan.idx.end(), Bof(t).begin(), Bof(t).end());
     f.F_off = F;  F += (long long)f.nF * f.nF;
-    f.L_off = L;  L += (long long)f.nF * f.nS;
-    f.W_off = W;  W += (long long)f.nS * f.nB;
+    f.ldL = (int)pad_ld(f.nF);
+    f.ldW = (int)pad_ld(f.nS);
+    f.L_off = La; La += (long long)f.ldL * f.nS;
+    f.W_off = Wa; Wa += (long long)f.ldW * f.nB;
+    L += (long long)f.nF * f.nS;
+    W += (long long)f.nS * f.nB;
     f.upd_off = U; U += f.nB;
     f.perm_off = P; P += f.nS;
     plan.max_nS = std::max(plan.max_nS, f.nS);
@@ -297,6 +303,8 @@ void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int root_merge, int e
   plan.F_total = F;
   plan.L_total = L;
   plan.W_total = W;
+  plan.L_alloc = La;
+  plan.W_alloc = Wa;
   plan.upd_total = U;
   plan.perm_total = P;
   plan.by_height.assign(plan.max_height + 1, std::vector<int>());
@@ -562,7 +570,7 @@ void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int root_merge, int e
               for (int p = 0; p < np; ++p) {
                 NDSeg sg;
                 sg.m_off = dir == 0 ? f.L_off : f.W_off;
-                sg.ld = dir == 0 ? f.nF : f.nS;
+                sg.ld = dir == 0 ? f.ldL : f.ldW;
                 sg.r0 = r0;
                 sg.nr = nr;
                 sg.k0 = p * kse;
@@ -690,7 +698,7 @@ void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int root_merge, int e
           fl.gath.push_back(g);
         }
         for (int r = 0; r < f.nF; r += rows_chunk) {
-          fl.items.push_back({t, r, std::min(f.nF, r + rows_chunk), h, f.nS, f.nF, f.nB, g0, f.L_off, f.idx_off,
+          fl.items.push_back({t, r, std::min(f.nF, r + rows_chunk), h, f.nS, f.nF, f.nB, g0, f.ldL, 0, f.L_off, f.idx_off,
                               f.inv_off, f.upd_off});
           fl.task_off.push_back((int)fl.items.size());
         }
@@ -704,7 +712,7 @@ void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int root_merge, int e
         const NDFrontDev& f = plan.fronts[t];
         if (f.nB > 0)          // a front without boundary has nothing to back-substitute
           for (int r = 0; r < f.nS; r += rows_chunk) {
-            bl.items.push_back({t, r, std::min(f.nS, r + rows_chunk), h, f.nS, f.nF, f.nB, 0, f.W_off, f.idx_off,
+            bl.items.push_back({t, r, std::min(f.nS, r + rows_chunk), h, f.nS, f.nF, f.nB, 0, f.ldW, 0, f.W_off, f.idx_off,
                                 f.inv_off, f.upd_off});
             bl.task_off.push_back((int)bl.items.size());
           }
