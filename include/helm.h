@@ -63,10 +63,22 @@ extern "C" {
 #define HELM_ESTAGNATE     2   /* no residual decrease over a full restart cycle */
 
 #define HELM_OP_N 0            /* the operator H */
-#define HELM_OP_C 1            /* its conjugate transpose H^H (= conj(H): H is complex symmetric) */
+#define HELM_OP_C 1            /* its conjugate transpose H^H (= conj(H): the 5/7-point H is
+                                  complex symmetric; not available for the compact stack) */
 
 #define HELM_F64 0
 #define HELM_F32 1
+
+/* discretisation stacks (helm_mg.stack) and transfers of the compact stack (helm_mg.transfer) */
+#define HELM_STACK_P5        0 /* 5-point (2D) / 7-point (3D) operator, full weighting, linear
+                                  interpolation; 9/27-point Galerkin operators */
+#define HELM_STACK_COMPACT   1 /* compact fourth-order 9-point / 19-point operator with its
+                                  mass term (eqs. 3.1, 3.2) */
+#define HELM_TRANSFER_CUBIC  1 /* R = [1 4 6 4 1]/16 per axis on both levels, P = 2^d R^T
+                                  (eq. 3.3): level-2 operator 25 points, level-3 49 (2D only) */
+#define HELM_TRANSFER_LEVDEP 2 /* level-dependent (eq. 3.4): the restriction from level 2 to 3
+                                  is [1 2 1]/4 per axis, the rest cubic: level-2 operator 25 /
+                                  125 points, level-3 25 / 125 (2D / 3D) */
 
 typedef struct helm_ctx helm_ctx;
 
@@ -91,6 +103,11 @@ typedef struct {
   double jacobi[2];    /* damping weight on level 1 and level 2 */
   int cycle_prec;      /* HELM_F32: cycle in complex FP32 (FGMRES stays FP64); HELM_F64 */
   int restart;         /* FGMRES restart length m, 1..64 */
+  int stack;           /* HELM_STACK_P5 (0) or HELM_STACK_COMPACT (Sec. 3.1) */
+  int transfer;        /* HELM_STACK_COMPACT: HELM_TRANSFER_CUBIC (2D) or HELM_TRANSFER_LEVDEP;
+                          ignored for HELM_STACK_P5.  The compact operator is not complex
+                          symmetric: with it every call refuses HELM_OP_C (HELM_EINVAL), and
+                          helm_grad_m refuses the context */
 } helm_mg;
 
 typedef struct {
@@ -262,7 +279,9 @@ int helm_get_timing(helm_ctx* ctx, double* t, int n);
  * [13] leaf box size and [14] root merge limit of the nested dissection, [15] 1 if the
  * schedule came from the autotuner cache (HELM_TUNE_CACHE), [16] number of tree-block
  * launches per direction, [17..20] the heights closing them (-1 beyond), [21] bit mask of
- * the dissection-tree heights whose fronts were merged into their parents.
+ * the dissection-tree heights whose fronts were merged into their parents, [22] and [23]
+ * coefficient planes of the stored level-2 and level-3 operators ((2r+1)^dim for stencil
+ * radius r: 9 / 27 for the 5/7-point stack).
  * Returns the number of entries written (at most n). */
 int helm_get_info(helm_ctx* ctx, long long* out, int n);
 

@@ -127,10 +127,13 @@ def stationary(hier: Hierarchy, b: np.ndarray, tol: float = 1e-6, max_iter: int 
 
 
 def from_problem(prob, conj=False, **kw) -> Hierarchy:
+    compact = getattr(prob, "stack", "p5") == "compact"
     args = dict(alpha=prob.alpha, alpha2=getattr(prob, "alpha2", 1.0), beta=prob.beta, cycle=prob.cycle,
                 nu_pre=prob.nu_pre,
                 nu_post=prob.nu_post,
-                jacobi=tuple(prob.jacobi) if np.ndim(prob.jacobi) else (prob.jacobi, prob.jacobi))
+                jacobi=tuple(prob.jacobi) if np.ndim(prob.jacobi) else (prob.jacobi, prob.jacobi),
+                stack="compact" if compact else "p5fw",
+                transfer=getattr(prob, "transfer", None) if compact else None)
     args.update(kw)
     return Hierarchy(prob.n, prob.h, prob.slowness ** 2, prob.omega, prob.layer, prob.sigma_max,
                      conj=conj, **args)

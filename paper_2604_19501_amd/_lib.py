@@ -32,6 +32,8 @@ HELM_OK, HELM_EINVAL, HELM_EWORKSPACE, HELM_EDEVICE, HELM_ENONFINITE, HELM_ESING
 HELM_ENOCONV, HELM_ESTAGNATE = 1, 2
 HELM_OP_N, HELM_OP_C = 0, 1
 HELM_F64, HELM_F32 = 0, 1
+HELM_STACK_P5, HELM_STACK_COMPACT = 0, 1
+HELM_TRANSFER_CUBIC, HELM_TRANSFER_LEVDEP = 1, 2
 
 
 class Grid(C.Structure):
@@ -45,7 +47,7 @@ class Shift(C.Structure):
 
 class MG(C.Structure):
     _fields_ = [("cycle", C.c_int), ("nu_pre", C.c_int), ("nu_post", C.c_int), ("jacobi", C.c_double * 2),
-                ("cycle_prec", C.c_int), ("restart", C.c_int)]
+                ("cycle_prec", C.c_int), ("restart", C.c_int), ("stack", C.c_int), ("transfer", C.c_int)]
 
 
 class SolveInfo(C.Structure):

@@ -16,7 +16,7 @@ import numpy as np
 import torch
 
 from . import _lib as L
-from .solver import _dev_tensor, _stream_ptr, kernel_times, make_grid, make_mg, parse_info
+from .solver import INFO_LEN, _dev_tensor, _stream_ptr, kernel_times, make_grid, make_mg, parse_info
 
 
 class BatchedSolver:
@@ -62,8 +62,8 @@ class BatchedSolver:
 
     def instance_info(self, inst: int) -> dict:
         """sizes of instance inst (helm_get_info's fields)"""
-        v = (C.c_longlong * 22)()
-        L.check(L.lib.helm_get_instance_info(self.ctx, int(inst), v, 22), "helm_get_instance_info")
+        v = (C.c_longlong * INFO_LEN)()
+        L.check(L.lib.helm_get_instance_info(self.ctx, int(inst), v, INFO_LEN), "helm_get_instance_info")
         return parse_info(v)
 
     def set_timing(self, on: bool = True):

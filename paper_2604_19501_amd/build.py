@@ -18,7 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhelm.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["api.hip", "levels.hip", "galerkin.hip", "nd.hip", "krylov.hip", "grad.hip", "nd_plan.cpp"]
+SOURCES = ["api.hip", "levels.hip", "galerkin.hip", "nd.hip", "krylov.hip", "grad.hip", "wide.hip", "nd_plan.cpp"]
 ARCH = os.environ.get("HELM_OFFLOAD_ARCH", "gfx950")
 
 

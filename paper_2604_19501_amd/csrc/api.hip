@@ -16,6 +16,7 @@
 
 #include "krylov.h"
 #include "levels_api.h"
+#include "wide.h"
 
 namespace helm {
 
@@ -186,6 +187,12 @@ struct helm_ctx {
   size_t lds_panel = 0;         // LDS bytes for a resident factorisation panel (device maximum - 2 KB)
   bool tuned = false;           // schedule parameters came from the autotuner cache
   int nd_leaf = 0, nd_root = 0;  // nested-dissection leaf size and root merge limit in use
+  // the compact fourth-order stack: restriction (tr) and interpolating-restriction (ip, P =
+  // 2^d ip^T) weights between levels 1-2 and 2-3, and the stencil radii and coefficient
+  // planes of the stored level-2 and level-3 operators (radius 1 for the 5/7-point stack)
+  int compact = 0;
+  Transfer1D tr[2], ip[2];
+  int r2 = 1, r3 = 1, K2 = 9, K3 = 9;
   long long nd_merge = 0;        // bit h: fronts of dissection height h merged into their parents
   std::vector<helm_ctx*> sub;   // batched form: one context per instance
   std::vector<hipStream_t> bstreams;   // batched form: streams of the concurrent instances
@@ -219,6 +226,14 @@ int validate(const helm_grid* g, const helm_mg* mg) {
     if (!std::isfinite(mg->jacobi[l])) return fail(HELM_EINVAL, "jacobi weight not finite");
   if (mg->cycle_prec != HELM_F64 && mg->cycle_prec != HELM_F32) return fail(HELM_EINVAL, "cycle_prec must be HELM_F64 or HELM_F32");
   if (mg->restart < 1 || mg->restart > KMAXM) return fail(HELM_EINVAL, "restart must be in 1..%d", KMAXM);
+  if (mg->stack != HELM_STACK_P5 && mg->stack != HELM_STACK_COMPACT)
+    return fail(HELM_EINVAL, "stack must be HELM_STACK_P5 or HELM_STACK_COMPACT");
+  if (mg->stack == HELM_STACK_COMPACT) {
+    if (mg->transfer != HELM_TRANSFER_CUBIC && mg->transfer != HELM_TRANSFER_LEVDEP)
+      return fail(HELM_EINVAL, "the compact stack takes HELM_TRANSFER_CUBIC or HELM_TRANSFER_LEVDEP");
+    if (g->dim == 3 && mg->transfer != HELM_TRANSFER_LEVDEP)
+      return fail(HELM_EINVAL, "3D compact stack: level-dependent transfers only (cubic ones give a 343-point level-3 operator)");
+  }
   long long N1 = 1;
   for (int a = 0; a < g->dim; ++a) N1 *= (g->n[a] + 1);
   if (N1 > (1LL << 31) - 1) return fail(HELM_EINVAL, "grid too large (N1 > 2^31-1)");
@@ -240,6 +255,15 @@ int need_single(const helm_ctx* c, const char* who) {
   return HELM_OK;
 }
 
+// the compact operator is not complex symmetric, so conj(H) is not its adjoint: its
+// contexts take HELM_OP_N only
+int need_op(const helm_ctx* c, int op, const char* who) {
+  if (op != HELM_OP_N && op != HELM_OP_C) return fail(HELM_EINVAL, "op must be HELM_OP_N or HELM_OP_C");
+  if (c->compact && op == HELM_OP_C)
+    return fail(HELM_EINVAL, "%s: the compact stack has no adjoint path (HELM_OP_C)", who);
+  return HELM_OK;
+}
+
 void init_geometry(helm_ctx* c) {
   int n[3] = {c->grid.n[0], c->grid.n[1], c->grid.dim == 3 ? c->grid.n[2] : 0};
   c->g1 = make_geom(c->grid.dim, n);
@@ -253,6 +277,22 @@ void init_geometry(helm_ctx* c) {
   set_layer_profile(c->op);
   c->f32 = c->mg.cycle_prec == HELM_F32;
   c->csz = c->f32 ? sizeof(cf) : sizeof(cd);
+  c->compact = c->mg.stack == HELM_STACK_COMPACT;
+  c->op.compact = c->compact;
+  if (c->compact) {
+    c->tr[0] = c->ip[0] = c->ip[1] = transfer_cubic();
+    c->tr[1] = c->mg.transfer == HELM_TRANSFER_LEVDEP ? transfer_fw() : transfer_cubic();
+    // Galerkin radii: a coarse row reaches (a_R + r_A + a_P) fine nodes, half as many coarse
+    c->r2 = (c->tr[0].a + 1 + c->ip[0].a) / 2;
+    c->r3 = (c->tr[1].a + c->r2 + c->ip[1].a) / 2;
+  } else {
+    c->r2 = c->r3 = 1;
+  }
+  c->K2 = c->K3 = 1;
+  for (int a = 0; a < c->grid.dim; ++a) {
+    c->K2 *= 2 * c->r2 + 1;
+    c->K3 *= 2 * c->r3 + 1;
+  }
 }
 
 // planes of the FP32 level-2 coefficients: 3D keeps the symmetric half (centre onwards;
@@ -370,7 +410,7 @@ void build_plan(helm_ctx* c) {
   // tree-block work-groups of at most HELM_ND_TREE_WAVES wavefronts: 16 in 2D; 8 in 3D, where
   // the many small subtrees run two work-groups per CU (measured 3 % faster at 256^3)
   const int tree_waves = env_int("HELM_ND_TREE_WAVES", c->grid.dim == 3 ? 8 : 16);
-  nd_plan(c->g3, leaf, 16, merge, (int)c->csz, lds, cuts, splitk, c->plan, tree_waves, mh);
+  nd_plan(c->g3, leaf, 16, merge, (int)c->csz, lds, cuts, splitk, c->plan, tree_waves, mh, c->r3);
   NDPlan& P = c->plan;
   c->hlist.clear();
   c->hlist_toff.clear();
@@ -424,21 +464,21 @@ CycleScratch carve_scratch(const helm_ctx* c, Carver& cv, int rc) {
 size_t carve(helm_ctx* c, void* ws) {
   Carver cv(ws);
   const Geom &g1 = c->g1, &g2 = c->g2, &g3 = c->g3;
-  const int K = stencil_points(g1.dim);
   const int m = c->mg.restart;
   const size_t cs = c->csz;
   NDPlan& P = c->plan;
   NDDev& d = c->nd;
   c->m64 = cv.take<double>(g1.tot);
   c->m32 = cv.take<float>(g1.tot);
-  c->dg32 = c->f32 ? cv.take<cf>(g1.tot) : nullptr;
-  c->coef2_64 = cv.take<cd>((size_t)K * g2.tot);
+  c->dg32 = c->f32 && !c->compact ? cv.take<cf>(g1.tot) : nullptr;
+  c->coef2_64 = cv.take<cd>((size_t)c->K2 * g2.tot);
   // the 3D FP32 cycle keeps the complex-symmetric level-2 operator's centre and the 13
   // directions after it (14 of 27 planes); in 2D the mirrored reads cost more than the
   // 4 of 9 planes they save (measured), so all 9 are kept
-  c->coef2_32 = c->f32 ? cv.take<cf>((size_t)sym2_planes(g2.dim) * g2.tot) : nullptr;
-  c->tmp2 = cv.take<cd>((size_t)K * g2.tot);
-  c->coef3_64 = cv.take<cd>((size_t)K * g3.tot);
+  // (the compact stack's level-2 operator is not complex symmetric: all its planes are kept)
+  c->coef2_32 = c->f32 ? cv.take<cf>((size_t)(c->compact ? c->K2 : sym2_planes(g2.dim)) * g2.tot) : nullptr;
+  c->tmp2 = cv.take<cd>((size_t)c->K2 * g2.tot);
+  c->coef3_64 = cv.take<cd>((size_t)c->K3 * g3.tot);
   const size_t rc = (size_t)c->rcap;
   c->r3d = cv.take<cd>(g3.tot);
   c->e3d = cv.take<cd>(g3.tot);
@@ -686,6 +726,18 @@ void numeric_setup(helm_ctx* c, const double* medium, int is_m, hipStream_t s) {
   const double omega = c->omega;
   // a0: m = kappa^2 (FP64 and FP32); the FP32 cycle's level-1 diagonal
   square_slowness(medium, c->m64, c->m32, c->g1.tot, is_m, s);
+  if (c->compact) {
+    // the compact stack: A2 = R1 H_beta^{alpha2} P1, A3 = R2 (R1 H_beta^alpha P1) P2 with
+    // its transfers (eqs. 2.2, 3.3-3.6), then the exact factorisation
+    wgal_fine(c->op, shift_scalar(shift->alpha2, shift->beta, omega), c->m64, c->g2, c->tr[0], c->ip[0], c->r2,
+              c->coef2_64, s);
+    if (c->f32) cast_d2f(c->coef2_64, c->coef2_32, (long long)c->K2 * c->g2.tot, s);
+    wgal_fine(c->op, shift_scalar(shift->alpha, shift->beta, omega), c->m64, c->g2, c->tr[0], c->ip[0], c->r2,
+              c->tmp2, s);
+    wgal_coarse(c->g2, c->tmp2, c->r2, c->g3, c->tr[1], c->ip[1], c->r3, c->coef3_64, s);
+    nd_factor(c, s);
+    return;
+  }
   if (c->f32) {
     L1<float> A;
     A.op = c->op;
@@ -752,8 +804,87 @@ struct Cycle {
   }
   C* other(C* cur, C* a, C* b) { return cur == a ? b : a; }
 
+  // the compact stack's cycle (the two-grid algorithm of Sec. 2 applied recursively, in
+  // the order of the oracle's cycle): plain Jacobi sweeps, residuals and transfers, the
+  // level-2 visits continuing from the current level-2 iterate (x2 + cycle(b2 - A2 x2)
+  // equals the visit from a zero guess on the updated residual).  nullptr iterates are zero.
+  template <typename CO>
+  void run_wide(const cd* b1, CO* out) {
+    const helm_mg& mg = c->mg;
+    const int nr = c->nr;
+    C *x1a = (C*)w.x1a, *x1b = (C*)w.x1b, *x2a = (C*)w.x2a, *x2b = (C*)w.x2b;
+    C *b2 = (C*)w.b2, *b3 = (C*)w.b3, *x3 = (C*)w.x3;
+    const R w1 = (R)mg.jacobi[0], w2 = (R)mg.jacobi[1];
+    WFine<R> F;
+    F.op = c->op;
+    const cd sb = shift_scalar(1.0, c->shift.beta, c->omega);
+    F.s = mk((R)sb.x, (R)sb.y);
+    F.m = (const R*)(sizeof(R) == 4 ? (const void*)c->m32 : (const void*)c->m64);
+    const C* A2c = (const C*)(sizeof(R) == 4 ? (const void*)c->coef2_32 : (const void*)c->coef2_64);
+    auto free1 = [&](const C* x) { return x == x1a ? x1b : x1a; };
+    auto free2 = [&](const C* x) { return x == x2a ? x2b : x2a; };
+    // level 1: pre-relaxation, residual, restriction
+    C* x1 = nullptr;
+    for (int k = 0; k < mg.nu_pre; ++k) {
+      C* o = free1(x1);
+      TIMED(c, KT_L1_SWEEP, s, (w1_step<R, cd, C>(F, WM_JAC, x1 == nullptr, x1, b1, w1, o, nr, s)));
+      x1 = o;
+    }
+    C* r1 = free1(x1);
+    TIMED(c, KT_L1_RESTRICT, s, (w1_step<R, cd, C>(F, WM_RES, x1 == nullptr, x1, b1, (R)0, r1, nr, s)));
+    TIMED(c, KT_L1_RESTRICT, s, (w_restrict<C>(c->g1, r1, c->g2, c->tr[0], b2, nr, s)));
+    // level 2: gamma visits
+    C* x2 = nullptr;
+    for (int v = 0; v < mg.cycle; ++v) {
+      for (int k = 0; k < mg.nu_pre; ++k) {
+        C* o = free2(x2);
+        TIMED(c, KT_L2_SWEEP, s, (w2_step<R>(c->g2, A2c, c->r2, WM_JAC, x2 == nullptr, x2, b2, w2, o, nr, s)));
+        x2 = o;
+      }
+      C* r2 = free2(x2);
+      TIMED(c, KT_L2_RESTRICT, s, (w2_step<R>(c->g2, A2c, c->r2, WM_RES, x2 == nullptr, x2, b2, (R)0, r2, nr, s)));
+      TIMED(c, KT_L2_RESTRICT, s, (w_restrict<C>(c->g2, r2, c->g3, c->tr[1], b3, nr, s)));
+      nd_solve<C>(c, w, b3, x3, 0, s);
+      if (x2 == nullptr) {          // a zero iterate: x2 = P2 x3
+        x2 = r2;
+        w_prolong<C>(c->g3, x3, c->g2, c->ip[1], 0, x2, nr, s);
+      } else {
+        w_prolong<C>(c->g3, x3, c->g2, c->ip[1], 1, x2, nr, s);
+      }
+      for (int k = 0; k < mg.nu_post; ++k) {
+        C* o = free2(x2);
+        TIMED(c, KT_L2_SWEEP, s, (w2_step<R>(c->g2, A2c, c->r2, WM_JAC, 0, x2, b2, w2, o, nr, s)));
+        x2 = o;
+      }
+    }
+    // level 1: correction and post-relaxation; the last sweep writes `out`
+    if (x1 == nullptr) {
+      x1 = x1a;
+      w_prolong<C>(c->g2, x2, c->g1, c->ip[0], 0, x1, nr, s);
+    } else {
+      w_prolong<C>(c->g2, x2, c->g1, c->ip[0], 1, x1, nr, s);
+    }
+    if (mg.nu_post == 0) {
+      w_copy<C, CO>(x1, out, (long long)nr * c->g1.tot, s);
+      return;
+    }
+    for (int k = 0; k < mg.nu_post; ++k) {
+      if (k == mg.nu_post - 1) {
+        TIMED(c, KT_L1_SWEEP, s, (w1_step<R, cd, CO>(F, WM_JAC, 0, x1, b1, w1, out, nr, s)));
+      } else {
+        C* o = free1(x1);
+        TIMED(c, KT_L1_SWEEP, s, (w1_step<R, cd, C>(F, WM_JAC, 0, x1, b1, w1, o, nr, s)));
+        x1 = o;
+      }
+    }
+  }
+
   template <typename CO>
   void run(const cd* b1, CO* out) {
+    if (c->compact) {
+      run_wide<CO>(b1, out);
+      return;
+    }
     const helm_mg& mg = c->mg;
     C *x1a = (C*)w.x1a, *x1b = (C*)w.x1b, *x2a = (C*)w.x2a, *x2b = (C*)w.x2b;
     C *b2 = (C*)w.b2, *b3 = (C*)w.b3, *x3 = (C*)w.x3;
@@ -1317,9 +1448,24 @@ int helm_apply(helm_ctx* c, int op, int prec, const void* x, void* y, void* stre
   if (prec != HELM_F64 && prec != HELM_F32) return fail(HELM_EINVAL, "prec must be HELM_F64 or HELM_F32");
   if (x == y) return fail(HELM_EINVAL, "x and y must differ");
   if (int v = need_single(c, "helm_apply")) return v;
+  if (int v = need_op(c, op, "helm_apply")) return v;
   hipStream_t s = (hipStream_t)stream;
   try {
-    if (prec == HELM_F64) {
+    if (c->compact) {
+      if (prec == HELM_F64) {
+        WFine<double> F;
+        F.op = c->op;
+        F.s = mk(c->omega * c->omega, 0.0);
+        F.m = c->m64;
+        w1_step<double, cd, cd>(F, WM_APPLY, 0, (const cd*)x, (const cd*)nullptr, 0.0, (cd*)y, 1, s);
+      } else {
+        WFine<float> F;
+        F.op = c->op;
+        F.s = mk((float)(c->omega * c->omega), 0.f);
+        F.m = c->m32;
+        w1_step<float, cf, cf>(F, WM_APPLY, 0, (const cf*)x, (const cf*)nullptr, 0.f, (cf*)y, 1, s);
+      }
+    } else if (prec == HELM_F64) {
       L1<double> A;
       A.op = c->op;
       A.s = mk(c->omega * c->omega, 0.0);
@@ -1346,6 +1492,7 @@ int helm_vcycle(helm_ctx* c, int op, const void* r, void* z, void* stream) {
   if (op != HELM_OP_N && op != HELM_OP_C) return fail(HELM_EINVAL, "op must be HELM_OP_N or HELM_OP_C");
   if (r == z) return fail(HELM_EINVAL, "r and z must differ");
   if (int v = need_single(c, "helm_vcycle")) return v;
+  if (int v = need_op(c, op, "helm_vcycle")) return v;
   hipStream_t s = (hipStream_t)stream;
   c->nr = 1;
   try {
@@ -1368,6 +1515,7 @@ int helm_coarse_solve(helm_ctx* c, int op, const void* r, void* e, void* stream)
   if (op != HELM_OP_N && op != HELM_OP_C) return fail(HELM_EINVAL, "op must be HELM_OP_N or HELM_OP_C");
   if (r == e) return fail(HELM_EINVAL, "r and e must differ");
   if (int v = need_single(c, "helm_coarse_solve")) return v;
+  if (int v = need_op(c, op, "helm_coarse_solve")) return v;
   hipStream_t s = (hipStream_t)stream;
   c->nr = 1;
   try {
@@ -1393,6 +1541,7 @@ int helm_solve(helm_ctx* c, int op, const void* rhs, void* x, double tol, int ma
   if (max_iter < 1) return fail(HELM_EINVAL, "max_iter must be >= 1");
   if (rhs == x) return fail(HELM_EINVAL, "rhs and x must differ");
   if (int v = need_single(c, "helm_solve")) return v;
+  if (int v = need_op(c, op, "helm_solve")) return v;
   hipStream_t s = (hipStream_t)stream;
   try {
     int st = c->f32 ? solve_impl<float>(c, op, 1, (const cd*)rhs, (cd*)x, tol, max_iter, info, s)
@@ -1412,6 +1561,7 @@ int helm_iterate(helm_ctx* c, int op, const void* rhs, void* x, double tol, int 
   if (max_iter < 1) return fail(HELM_EINVAL, "max_iter must be >= 1");
   if (rhs == x) return fail(HELM_EINVAL, "rhs and x must differ");
   if (int v = need_single(c, "helm_iterate")) return v;
+  if (int v = need_op(c, op, "helm_iterate")) return v;
   hipStream_t s = (hipStream_t)stream;
   try {
     int st = c->f32 ? stationary_impl<float>(c, op, (const cd*)rhs, (cd*)x, tol, max_iter, info, s)
@@ -1466,13 +1616,13 @@ int helm_get_info(helm_ctx* c, long long* out, int n) {
     sB += f.nB;
     maxF = std::max<long long>(maxF, f.nF);
   }
-  long long v[22] = {c->g1.tot, c->g2.tot, c->g3.tot, (long long)P.fronts.size(), P.L_total, P.W_total, sB,
+  long long v[24] = {c->g1.tot, c->g2.tot, c->g3.tot, (long long)P.fronts.size(), P.L_total, P.W_total, sB,
                      c->g3.tot, (long long)nd_kernels(c->nd.launch[0]), (long long)nd_kernels(c->nd.launch[1]),
                      (long long)c->ws_needed, maxF,
                      (long long)c->csz, c->nd_leaf, c->nd_root, c->tuned ? 1 : 0, (long long)P.cuts.size(),
-                     -1, -1, -1, -1, c->nd_merge};
+                     -1, -1, -1, -1, c->nd_merge, c->K2, c->K3};
   for (size_t i = 0; i < P.cuts.size() && i < 4; ++i) v[17 + i] = P.cuts[i];
-  int m = std::min(n, 22);
+  int m = std::min(n, 24);
   for (int i = 0; i < m; ++i) out[i] = v[i];
   return m;
 }
@@ -1509,7 +1659,7 @@ int helm_get_coefficients(helm_ctx* c, int lev, double* out) {
     const Geom& g = lev == 2 ? c->g2 : c->g3;
     const cd* src = lev == 2 ? c->coef2_64 : c->coef3_64;
     CK(hipDeviceSynchronize());
-    CK(hipMemcpy(out, src, sizeof(cd) * stencil_points(g.dim) * g.tot, hipMemcpyDeviceToHost));
+    CK(hipMemcpy(out, src, sizeof(cd) * (lev == 2 ? c->K2 : c->K3) * g.tot, hipMemcpyDeviceToHost));
   } catch (DevErr& e) {
     return fail(HELM_EDEVICE, "%s", e.what());
   }
@@ -1522,6 +1672,8 @@ int helm_grad_m(helm_ctx* c, int n_src, const void* const* u, const void* const*
   for (int k = 0; k < n_src; ++k)
     if (!u[k] || !lambda[k]) return fail(HELM_EINVAL, "NULL source pointer %d", k);
   if (int v = need_single(c, "helm_grad_m")) return v;
+  if (c->compact)
+    return fail(HELM_EINVAL, "helm_grad_m: the compact stack has no adjoint path (its H is not complex symmetric)");
   hipStream_t s = (hipStream_t)stream;
   try {
     for (int k = 0; k < n_src; ++k)
@@ -1608,6 +1760,7 @@ int helm_solve_batched(helm_ctx* ctx, int op, int n_rhs, const int* inst_of_rhs,
   if (op != HELM_OP_N && op != HELM_OP_C) return fail(HELM_EINVAL, "op must be HELM_OP_N or HELM_OP_C");
   if (!(tol > 0.0) || !std::isfinite(tol)) return fail(HELM_EINVAL, "tol must be positive");
   if (max_iter < 1) return fail(HELM_EINVAL, "max_iter must be >= 1");
+  if (int v = need_op(ctx->sub.empty() ? ctx : ctx->sub[0], op, "helm_solve_batched")) return v;
   const int ninst = ctx->sub.empty() ? 1 : (int)ctx->sub.size();
   std::vector<std::vector<int>> by(ninst);      // right-hand sides of each instance, in order
   for (int k = 0; k < n_rhs; ++k) {
@@ -1770,6 +1923,7 @@ int helm_vcycle_noalloc(helm_ctx* c, int op, const void* r, void* z, void* strea
   if (op != HELM_OP_N && op != HELM_OP_C) return fail(HELM_EINVAL, "op must be HELM_OP_N or HELM_OP_C");
   if (r == z) return fail(HELM_EINVAL, "r and z must differ");
   if (int v = need_single(c, "helm_vcycle_noalloc")) return v;
+  if (int v = need_op(c, op, "helm_vcycle_noalloc")) return v;
   size_t need = 0;
   {
     Carver probe(nullptr);

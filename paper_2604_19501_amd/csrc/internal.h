@@ -120,6 +120,7 @@ inline Geom coarsen(const Geom& f) {
 // fine level operator: -Lap_h - s * m (1 - i sigma) with a complex scalar s
 struct FineOp {
   Geom g;
+  int compact = 0;      // 1: the compact fourth-order operator (eqs. 3.1, 3.2) with its mass term
   double inv_h2;
   int layer[3][2];
   double sigma_max;
@@ -319,9 +320,11 @@ struct NDPlan {
 // tree_waves: the most wavefronts of a tree-block work-group (16 = 1024 threads)
 // merge_heights: heights of the dissection tree (leaves 0, before any merge) whose fronts are
 // merged into their parents (fewer levels, larger fronts)
+// radius: stencil radius of the coarsest operator (its (2 radius + 1)^dim coefficient planes,
+// plane k of offset d = sum_a (d_a + radius) (2 radius + 1)^a)
 void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int root_merge, int elem_bytes, int lds_bytes,
              const std::vector<int>& cuts, long long splitk_bytes, NDPlan& plan, int tree_waves = 16,
-             const std::vector<int>& merge_heights = std::vector<int>());
+             const std::vector<int>& merge_heights = std::vector<int>(), int radius = 1);
 
 
 }  // namespace helm

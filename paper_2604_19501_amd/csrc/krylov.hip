@@ -20,6 +20,7 @@
 #include <cstddef>
 
 #include "krylov.h"
+#include "wide.h"
 
 namespace helm {
 
@@ -63,6 +64,11 @@ __device__ __forceinline__ cd apply_h(const KrylovArgs& a, const CX* __restrict_
   int i0 = (int)(f % g.N[0]);
   long long r = f / g.N[0];
   int i1 = (int)(r % g.N[1]), i2 = (int)(r / g.N[1]);
+  if (a.op.compact) {          // the compact fourth-order operator (no conjugate form)
+    cd dg;
+    return g.dim == 3 ? wide_row<3, double, CX>(a.op, a.s, a.m64, x, f, i0, i1, i2, false, dg)
+                      : wide_row<2, double, CX>(a.op, a.s, a.m64, x, f, i0, i1, i2, false, dg);
+  }
   double sig = layer_sigma(a.op, i0, i1, i2);
   double mm = a.m64[f];
   cd c = a.s * mk(mm, -mm * sig);

@@ -1,13 +1,15 @@
 // Symbolic analysis of the exact coarsest-grid solve.
 //
-// The coarsest operator (eq. 3.6) is a 9-point (2D) / 27-point (3D) stencil on a
-// regular node grid.  It is solved exactly by block Gaussian elimination in a
-// geometric nested-dissection order: a box of nodes is cut by a one-node-thick
-// plane normal to its longest axis (a single plane separates the two halves for
-// any stencil of radius one), recursively, until boxes hold at most leaf_max
-// nodes.  Every tree node ("front") eliminates its separator S; its boundary B
-// is the one-node halo of its box, which lies in ancestor separators.  After
-// its subtree is eliminated, a front couples S and B densely.
+// The coarsest operator (eq. 3.6) is a stencil of radius r on a regular node grid:
+// 9-point (2D) / 27-point (3D) for the 5/7-point fine operator with full weighting
+// (r = 1), 25- or 49-point (2D) and 125-point (3D) for the compact fourth-order stack
+// with high-order or level-dependent transfers (r = 2 or 3).  It is solved exactly by
+// block Gaussian elimination in a geometric nested-dissection order: a box of nodes is
+// cut by a slab of r node planes normal to its longest axis (r planes separate the two
+// halves for a stencil of radius r), recursively, until boxes hold at most leaf_max
+// nodes.  Every tree node ("front") eliminates its separator S; its boundary B is the
+// r-node halo of its box, which lies in ancestor separators.  After its subtree is
+// eliminated, a front couples S and B densely.
 //
 // The separators of the top levels may be merged into one root front (a
 // supernode): elimination stays exact, the tree gets shallower, and the solve
@@ -39,6 +41,7 @@ struct Box {
 struct Builder {
   Geom g;
   int leaf_max;
+  int r = 1;            // stencil radius: separator slab thickness and halo width
   std::vector<Box> box;
   std::vector<std::vector<int>> S, B, kids;
   std::vector<int> parent;
@@ -62,14 +65,15 @@ struct Builder {
       int e = b.hi[a] - b.lo[a] + 1;
       if (e > ext) { ext = e; ax = a; }
     }
-    bool leaf = count(b) <= leaf_max || ext < 3;
+    bool leaf = count(b) <= leaf_max || ext < r + 2;
     Box sep = b;
     if (!leaf) {
-      int mid = (b.lo[ax] + b.hi[ax]) / 2;
-      sep.lo[ax] = sep.hi[ax] = mid;
+      int mid = (b.lo[ax] + b.hi[ax] - (r - 1)) / 2;     // the slab [mid, mid + r)
+      sep.lo[ax] = mid;
+      sep.hi[ax] = mid + r - 1;
       Box c0 = b, c1 = b;
       c0.hi[ax] = mid - 1;
-      c1.lo[ax] = mid + 1;
+      c1.lo[ax] = mid + r;
       int a0 = build(c0, id);
       int a1 = build(c1, id);
       kids[id] = {a0, a1};
@@ -77,11 +81,11 @@ struct Builder {
     for (int i2 = sep.lo[2]; i2 <= sep.hi[2]; ++i2)
       for (int i1 = sep.lo[1]; i1 <= sep.hi[1]; ++i1)
         for (int i0 = sep.lo[0]; i0 <= sep.hi[0]; ++i0) S[id].push_back(flat(i0, i1, i2));
-    // one-node halo of the box inside the domain, increasing flat index
+    // r-node halo of the box inside the domain, increasing flat index
     int lo[3], hi[3];
     for (int a = 0; a < 3; ++a) {
-      lo[a] = std::max(b.lo[a] - 1, 0);
-      hi[a] = std::min(b.hi[a] + 1, g.N[a] - 1);
+      lo[a] = std::max(b.lo[a] - r, 0);
+      hi[a] = std::min(b.hi[a] + r, g.N[a] - 1);
     }
     for (int i2 = lo[2]; i2 <= hi[2]; ++i2)
       for (int i1 = lo[1]; i1 <= hi[1]; ++i1)
@@ -98,11 +102,12 @@ struct Builder {
 
 void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int root_merge, int elem_bytes, int lds_bytes,
              const std::vector<int>& cuts, long long splitk_bytes, NDPlan& plan, int tree_waves,
-             const std::vector<int>& merge_heights) {
+             const std::vector<int>& merge_heights, int radius) {
   tree_waves = std::max(1, std::min(16, tree_waves));
   Builder bd;
   bd.g = g3;
   bd.leaf_max = std::max(leaf_max, 1);
+  bd.r = std::max(1, radius);
   Box rootbox;
   for (int a = 0; a < 3; ++a) {
     rootbox.lo[a] = 0;
@@ -269,6 +274,7 @@ void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int root_merge, int e
   // assembly lists: entry (i, j) of the operator goes to the front where the first
   // eliminated of i, j is a separator node; the other one is then in that front too.
   const int dim = g3.dim;
+  const int rr = bd.r, sw = 2 * bd.r + 1;   // stencil radius and width: plane k of offset d
   for (int t = 0; t < nf; ++t) {
     NDFrontDev& f = plan.fronts[t];
     f.asm_off = (long long)plan.asmv.size();
@@ -277,14 +283,14 @@ void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int root_merge, int e
     for (int ps = 0; ps < f.nS; ++ps) {
       int s = St[ps];
       int s0 = s % g3.N[0], s1 = (s / g3.N[0]) % g3.N[1], s2 = s / (g3.N[0] * g3.N[1]);
-      for (int d2 = (dim == 3 ? -1 : 0); d2 <= (dim == 3 ? 1 : 0); ++d2)
-        for (int d1 = -1; d1 <= 1; ++d1)
-          for (int d0 = -1; d0 <= 1; ++d0) {
+      for (int d2 = (dim == 3 ? -rr : 0); d2 <= (dim == 3 ? rr : 0); ++d2)
+        for (int d1 = -rr; d1 <= rr; ++d1)
+          for (int d0 = -rr; d0 <= rr; ++d0) {
             int q0 = s0 + d0, q1 = s1 + d1, q2 = s2 + d2;
             if (q0 < 0 || q0 >= g3.N[0] || q1 < 0 || q1 >= g3.N[1] || q2 < 0 || q2 >= g3.N[2]) continue;
             int q = bd.flat(q0, q1, q2);
-            int k = (d0 + 1) + 3 * (d1 + 1) + (dim == 3 ? 9 * (d2 + 1) : 0);
-            int kq = (-d0 + 1) + 3 * (-d1 + 1) + (dim == 3 ? 9 * (-d2 + 1) : 0);
+            int k = (d0 + rr) + sw * (d1 + rr) + (dim == 3 ? sw * sw * (d2 + rr) : 0);
+            int kq = (-d0 + rr) + sw * (-d1 + rr) + (dim == 3 ? sw * sw * (-d2 + rr) : 0);
             if (owner[q] == t) {
               plan.asmv.push_back({ps, pos_in_S[q], (long long)k * N3 + s});
             } else {

@@ -1,0 +1,401 @@
+// Kernels of the paper's compact fourth-order stack (eqs. 3.1-3.4): its Galerkin
+// operators (FP64 set-up) and the steps of its cycle (cycle precision).  The layouts and
+// operators are described in wide.h.
+//
+// The cycle steps are plain one-node-per-thread kernels: every neighbour and coefficient
+// load is issued unconditionally (clamped index, zero weight), so a thread waits on one
+// batch of loads.  Right-hand sides solved in lock-step are grid y, N entries apart.
+#include <stdexcept>
+
+#include "wide.h"
+
+namespace helm {
+
+namespace {
+
+// node coordinates of flat index f
+__device__ __forceinline__ void coords(const Geom& g, long long f, int& i0, int& i1, int& i2) {
+  i0 = (int)(f % g.N[0]);
+  const long long r = f / g.N[0];
+  i1 = (int)(r % g.N[1]);
+  i2 = (int)(r / g.N[1]);
+}
+
+// ---------------------------------------------------------------- set-up ----
+// Galerkin product Ac = R A P for one coarse node I per wavefront (four per work-group):
+//   q(j)      = sum_i R(I, i) A(i, j)            over the fine nodes j that R's row I reaches
+//                                                 through A (a box of side 2(a + rin) + 1)
+//   Ac(I, J)  = sum_j q(j) P(j, J)                for every coarse J = I + D, |D_a| <= rc
+// R(I, i) = prod_a Rt.w[i_a - 2 I_a + Rt.a]; P(j, J) = prod_a 2 Pt.w[j_a - 2 J_a + Pt.a]
+// (P = 2^d Pt^T); both truncated at the grid's ends.  SRC 0: A is the fine compact
+// operator with scalar s; SRC 1: A is given as planes of radius rin.
+struct GalArgs {
+  Geom gf, gc;
+  FineOp op;            // SRC 0
+  cd s;
+  const double* m;
+  const cd* A;          // SRC 1
+  int rin;
+  Transfer1D Rt, Pt;
+  int rc;
+  cd* out;
+};
+
+template <int DIM>
+constexpr int gal_qmax() { return DIM == 3 ? 343 : 81; }
+
+template <int DIM, int SRC>
+__global__ void __launch_bounds__(256) k_wgal(GalArgs a) {
+  __shared__ cd q[4][gal_qmax<DIM>()];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const long long I = (long long)blockIdx.x * 4 + wv;
+  const bool live = I < a.gc.tot;
+  const long long Ic = live ? I : 0;
+  int Ia[3];
+  coords(a.gc, Ic, Ia[0], Ia[1], Ia[2]);
+  const int rin = SRC == 0 ? 1 : a.rin;
+  const int ar = a.Rt.a, bp = a.Pt.a;
+  int lo[3] = {0, 0, 0}, sp[3] = {1, 1, 1};
+  for (int d = 0; d < DIM; ++d) {
+    lo[d] = max(2 * Ia[d] - ar - rin, 0);
+    const int hi = min(2 * Ia[d] + ar + rin, a.gf.N[d] - 1);
+    sp[d] = hi - lo[d] + 1;
+  }
+  const int nq = sp[0] * sp[1] * sp[2];
+  const long long sf1 = a.gf.N[0], sf2 = (long long)a.gf.N[0] * a.gf.N[1];
+  const double ih = a.op.inv_h2 / 6.0;
+  for (int e = lane; e < nq; e += 64) {
+    int j[3] = {lo[0] + e % sp[0], lo[1] + (e / sp[0]) % sp[1], lo[2] + e / (sp[0] * sp[1])};
+    const long long jf = j[0] + j[1] * sf1 + j[2] * sf2;
+    int ilo[3] = {0, 0, 0}, ihi[3] = {0, 0, 0};
+    for (int d = 0; d < DIM; ++d) {
+      ilo[d] = max(max(2 * Ia[d] - ar, j[d] - rin), 0);
+      ihi[d] = min(min(2 * Ia[d] + ar, j[d] + rin), a.gf.N[d] - 1);
+    }
+    cd acc = mk(0.0, 0.0);
+    if (SRC == 0) {
+      // sum_i w_i A(i, j) = sum_i w_i L(j - i) - c_j sum_i w_i M(j - i)
+      double sl = 0.0, sm = 0.0;
+      for (int i2 = ilo[2]; i2 <= ihi[2]; ++i2)
+        for (int i1 = ilo[1]; i1 <= ihi[1]; ++i1)
+          for (int i0 = ilo[0]; i0 <= ihi[0]; ++i0) {
+            const int ii[3] = {i0, i1, i2};
+            double w = 1.0;
+            int nz = 0;
+            for (int d = 0; d < DIM; ++d) {
+              w *= a.Rt.w[ii[d] - 2 * Ia[d] + ar];
+              nz += ii[d] != j[d];
+            }
+            const double lw = nz == 0 ? (DIM == 3 ? 24.0 : 20.0)
+                            : nz == 1 ? (DIM == 3 ? -2.0 : -4.0)
+                            : nz == 2 ? -1.0 : 0.0;
+            const double mw = nz == 0 ? (DIM == 3 ? 6.0 / 12.0 : 8.0 / 12.0) : nz == 1 ? 1.0 / 12.0 : 0.0;
+            sl += w * lw;
+            sm += w * mw;
+          }
+      const double mj = a.m[jf];
+      const cd cj = a.s * mk(mj, -mj * layer_sigma(a.op, j[0], j[1], j[2]));
+      acc = mk(sl * ih - sm * cj.x, -sm * cj.y);
+    } else {
+      const int sw = 2 * rin + 1;
+      for (int i2 = ilo[2]; i2 <= ihi[2]; ++i2)
+        for (int i1 = ilo[1]; i1 <= ihi[1]; ++i1)
+          for (int i0 = ilo[0]; i0 <= ihi[0]; ++i0) {
+            const int ii[3] = {i0, i1, i2};
+            double w = 1.0;
+            int k = 0, mul = 1;
+            for (int d = 0; d < DIM; ++d) {
+              w *= a.Rt.w[ii[d] - 2 * Ia[d] + ar];
+              k += (j[d] - ii[d] + rin) * mul;
+              mul *= sw;
+            }
+            const long long iflat = i0 + i1 * sf1 + i2 * sf2;
+            acc += w * a.A[(long long)k * a.gf.tot + iflat];
+          }
+    }
+    q[wv][e] = acc;
+  }
+  __syncthreads();
+  if (!live) return;
+  const int cw = 2 * a.rc + 1;
+  int nout = cw;
+  for (int d = 1; d < DIM; ++d) nout *= cw;
+  for (int o = lane; o < nout; o += 64) {
+    int D[3] = {o % cw - a.rc, DIM > 1 ? (o / cw) % cw - a.rc : 0, DIM > 2 ? o / (cw * cw) - a.rc : 0};
+    int J[3] = {Ia[0] + D[0], Ia[1] + D[1], Ia[2] + D[2]};
+    bool inside = true;
+    int jlo[3] = {0, 0, 0}, jhi[3] = {0, 0, 0};
+    for (int d = 0; d < DIM; ++d) {
+      inside = inside && J[d] >= 0 && J[d] < a.gc.N[d];
+      jlo[d] = max(2 * J[d] - bp, lo[d]);
+      jhi[d] = min(2 * J[d] + bp, lo[d] + sp[d] - 1);
+    }
+    cd acc = mk(0.0, 0.0);
+    if (inside) {
+      for (int j2 = jlo[2]; j2 <= jhi[2]; ++j2)
+        for (int j1 = jlo[1]; j1 <= jhi[1]; ++j1)
+          for (int j0 = jlo[0]; j0 <= jhi[0]; ++j0) {
+            const int jj[3] = {j0, j1, j2};
+            double w = 1.0;
+            for (int d = 0; d < DIM; ++d) w *= 2.0 * a.Pt.w[jj[d] - 2 * J[d] + bp];
+            const int e = (j0 - lo[0]) + sp[0] * ((j1 - lo[1]) + sp[1] * (j2 - lo[2]));
+            acc += w * q[wv][e];
+          }
+    }
+    a.out[(long long)o * a.gc.tot + I] = acc;
+  }
+}
+
+// ----------------------------------------------------------- cycle steps ----
+template <int DIM, typename R, typename CB, typename CO>
+__global__ void __launch_bounds__(256) k_w1(WFine<R> A, int mode, int xz, const typename cplx<R>::type* __restrict__ x,
+                                            const CB* __restrict__ b, R w, CO* __restrict__ out) {
+  typedef typename cplx<R>::type C;
+  const Geom& g = A.op.g;
+  const long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= g.tot) return;
+  const long long off = (long long)blockIdx.y * g.tot;
+  int i0, i1, i2;
+  coords(g, f, i0, i1, i2);
+  C dg;
+  const C ax = wide_row<DIM, R, C>(A.op, A.s, A.m, x + off, f, i0, i1, i2, xz != 0, dg);
+  C v;
+  if (mode == WM_APPLY) {
+    v = ax;
+  } else {
+    const C r = conv<C>::from(b[off + f]) - ax;
+    if (mode == WM_RES) {
+      v = r;
+    } else {
+      const C xo = xz ? mk((R)0, (R)0) : x[off + f];
+      v = xo + w * cdiv(r, dg);
+    }
+  }
+  out[off + f] = conv<CO>::from(v);
+}
+
+// planes of radius RAD: (A x)_i = sum_k coef[k N + i] x[i + d_k]
+template <int DIM, int RAD, typename R>
+__global__ void __launch_bounds__(256) k_w2(Geom g, const typename cplx<R>::type* __restrict__ coef, int mode, int xz,
+                                            const typename cplx<R>::type* __restrict__ x,
+                                            const typename cplx<R>::type* __restrict__ b, R w,
+                                            typename cplx<R>::type* __restrict__ out) {
+  typedef typename cplx<R>::type C;
+  constexpr int SW = 2 * RAD + 1;
+  const long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= g.tot) return;
+  const long long off = (long long)blockIdx.y * g.tot;
+  int i0, i1, i2;
+  coords(g, f, i0, i1, i2);
+  const long long s1 = g.N[0], s2 = (long long)g.N[0] * g.N[1];
+  constexpr int KC = DIM == 3 ? (SW * SW * SW) / 2 : (SW * SW) / 2;    // centre plane
+  const C dg = coef[(long long)KC * g.tot + f];
+  C ax = mk((R)0, (R)0);
+  if (!xz) {
+#pragma unroll
+    for (int d2 = (DIM == 3 ? -RAD : 0); d2 <= (DIM == 3 ? RAD : 0); ++d2)
+#pragma unroll
+      for (int d1 = -RAD; d1 <= RAD; ++d1) {
+        const bool in1 = i1 + d1 >= 0 && i1 + d1 <= g.n[1] && (DIM == 2 || (i2 + d2 >= 0 && i2 + d2 <= g.n[2]));
+#pragma unroll
+        for (int d0 = -RAD; d0 <= RAD; ++d0) {
+          const int k = (d0 + RAD) + SW * (d1 + RAD) + (DIM == 3 ? SW * SW * (d2 + RAD) : 0);
+          const bool in = in1 && i0 + d0 >= 0 && i0 + d0 <= g.n[0];
+          const long long j = in ? f + d0 + d1 * s1 + d2 * s2 : f;
+          const C a = coef[(long long)k * g.tot + f];
+          const C xv = x[off + j];
+          ax += (in ? (R)1 : (R)0) * (a * xv);
+        }
+      }
+  }
+  C v;
+  if (mode == WM_APPLY) {
+    v = ax;
+  } else {
+    const C r = b[off + f] - ax;
+    if (mode == WM_RES) {
+      v = r;
+    } else {
+      const C xo = xz ? mk((R)0, (R)0) : x[off + f];
+      v = xo + w * cdiv(r, dg);
+    }
+  }
+  out[off + f] = v;
+}
+
+template <int DIM, typename C>
+__global__ void __launch_bounds__(256) k_wrestrict(Geom gf, const C* __restrict__ v, Geom gc, Transfer1D Rt,
+                                                   C* __restrict__ out) {
+  typedef decltype(v[0].x) R;
+  const long long I = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (I >= gc.tot) return;
+  v += (long long)blockIdx.y * gf.tot;
+  out += (long long)blockIdx.y * gc.tot;
+  int Ia[3];
+  coords(gc, I, Ia[0], Ia[1], Ia[2]);
+  const int a = Rt.a;
+  int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  for (int d = 0; d < DIM; ++d) {
+    lo[d] = max(2 * Ia[d] - a, 0);
+    hi[d] = min(2 * Ia[d] + a, gf.N[d] - 1);
+  }
+  const long long s1 = gf.N[0], s2 = (long long)gf.N[0] * gf.N[1];
+  C acc = mk((R)0, (R)0);
+  for (int i2 = lo[2]; i2 <= hi[2]; ++i2) {
+    const R w2 = DIM == 3 ? (R)Rt.w[i2 - 2 * Ia[2] + a] : (R)1;
+    for (int i1 = lo[1]; i1 <= hi[1]; ++i1) {
+      const R w1 = w2 * (R)Rt.w[i1 - 2 * Ia[1] + a];
+      for (int i0 = lo[0]; i0 <= hi[0]; ++i0)
+        acc += (w1 * (R)Rt.w[i0 - 2 * Ia[0] + a]) * v[i0 + i1 * s1 + i2 * s2];
+    }
+  }
+  out[I] = acc;
+}
+
+template <int DIM, typename C>
+__global__ void __launch_bounds__(256) k_wprolong(Geom gc, const C* __restrict__ e, Geom gf, Transfer1D Pt, int add,
+                                                  C* __restrict__ x) {
+  typedef decltype(e[0].x) R;
+  const long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= gf.tot) return;
+  e += (long long)blockIdx.y * gc.tot;
+  x += (long long)blockIdx.y * gf.tot;
+  int ia[3];
+  coords(gf, f, ia[0], ia[1], ia[2]);
+  const int a = Pt.a;
+  int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+  for (int d = 0; d < DIM; ++d) {
+    lo[d] = max((ia[d] - a + 1) / 2, 0);           // ceil((i - a) / 2), clamped at 0
+    hi[d] = min((ia[d] + a) / 2, gc.N[d] - 1);
+  }
+  const long long s1 = gc.N[0], s2 = (long long)gc.N[0] * gc.N[1];
+  C acc = mk((R)0, (R)0);
+  for (int J2 = lo[2]; J2 <= hi[2]; ++J2) {
+    const R w2 = DIM == 3 ? (R)(2.0 * Pt.w[ia[2] - 2 * J2 + a]) : (R)1;
+    for (int J1 = lo[1]; J1 <= hi[1]; ++J1) {
+      const R w1 = w2 * (R)(2.0 * Pt.w[ia[1] - 2 * J1 + a]);
+      for (int J0 = lo[0]; J0 <= hi[0]; ++J0)
+        acc += (w1 * (R)(2.0 * Pt.w[ia[0] - 2 * J0 + a])) * e[J0 + J1 * s1 + J2 * s2];
+    }
+  }
+  x[f] = add ? x[f] + acc : acc;
+}
+
+template <typename CI, typename CO>
+__global__ void __launch_bounds__(256) k_wcopy(const CI* __restrict__ in, CO* __restrict__ out, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    out[i] = conv<CO>::from(in[i]);
+}
+
+inline dim3 grid1(long long n, int nr) { return dim3((unsigned)((n + 255) / 256), (unsigned)nr); }
+
+}  // namespace
+
+// ------------------------------------------------------------- launchers ----
+void wgal_fine(const FineOp& op, cd s, const double* m, const Geom& gc, const Transfer1D& Rt, const Transfer1D& Pt,
+               int rc, cd* out, hipStream_t st) {
+  GalArgs a{};
+  a.gf = op.g;
+  a.gc = gc;
+  a.op = op;
+  a.s = s;
+  a.m = m;
+  a.rin = 1;
+  a.Rt = Rt;
+  a.Pt = Pt;
+  a.rc = rc;
+  a.out = out;
+  const dim3 grid((unsigned)((gc.tot + 3) / 4));
+  if (op.g.dim == 3)
+    hipLaunchKernelGGL((k_wgal<3, 0>), grid, dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_wgal<2, 0>), grid, dim3(256), 0, st, a);
+}
+
+void wgal_coarse(const Geom& g, const cd* A, int rin, const Geom& gc, const Transfer1D& Rt, const Transfer1D& Pt,
+                 int rc, cd* out, hipStream_t st) {
+  GalArgs a{};
+  a.gf = g;
+  a.gc = gc;
+  a.A = A;
+  a.rin = rin;
+  a.Rt = Rt;
+  a.Pt = Pt;
+  a.rc = rc;
+  a.out = out;
+  const dim3 grid((unsigned)((gc.tot + 3) / 4));
+  if (g.dim == 3)
+    hipLaunchKernelGGL((k_wgal<3, 1>), grid, dim3(256), 0, st, a);
+  else
+    hipLaunchKernelGGL((k_wgal<2, 1>), grid, dim3(256), 0, st, a);
+}
+
+template <typename R, typename CB, typename CO>
+void w1_step(const WFine<R>& A, int mode, int xz, const typename cplx<R>::type* x, const CB* b, R w, CO* out, int nr,
+             hipStream_t st) {
+  const dim3 grid = grid1(A.op.g.tot, nr);
+  if (xz) x = (const typename cplx<R>::type*)(const void*)out;   // not read; a valid address all the same
+  if (A.op.g.dim == 3)
+    hipLaunchKernelGGL((k_w1<3, R, CB, CO>), grid, dim3(256), 0, st, A, mode, xz, x, b, w, out);
+  else
+    hipLaunchKernelGGL((k_w1<2, R, CB, CO>), grid, dim3(256), 0, st, A, mode, xz, x, b, w, out);
+}
+
+template <typename R>
+void w2_step(const Geom& g, const typename cplx<R>::type* coef, int r, int mode, int xz,
+             const typename cplx<R>::type* x, const typename cplx<R>::type* b, R w, typename cplx<R>::type* out,
+             int nr, hipStream_t st) {
+  const dim3 grid = grid1(g.tot, nr);
+  if (xz) x = out;                                    // not read; a valid address all the same
+  if (g.dim == 3 && r == 2)
+    hipLaunchKernelGGL((k_w2<3, 2, R>), grid, dim3(256), 0, st, g, coef, mode, xz, x, b, w, out);
+  else if (g.dim == 2 && r == 2)
+    hipLaunchKernelGGL((k_w2<2, 2, R>), grid, dim3(256), 0, st, g, coef, mode, xz, x, b, w, out);
+  else if (g.dim == 2 && r == 3)
+    hipLaunchKernelGGL((k_w2<2, 3, R>), grid, dim3(256), 0, st, g, coef, mode, xz, x, b, w, out);
+  else
+    throw std::runtime_error("w2_step: no kernel for this dimension and stencil radius");
+}
+
+template <typename C>
+void w_restrict(const Geom& gf, const C* v, const Geom& gc, const Transfer1D& Rt, C* out, int nr, hipStream_t st) {
+  const dim3 grid = grid1(gc.tot, nr);
+  if (gf.dim == 3)
+    hipLaunchKernelGGL((k_wrestrict<3, C>), grid, dim3(256), 0, st, gf, v, gc, Rt, out);
+  else
+    hipLaunchKernelGGL((k_wrestrict<2, C>), grid, dim3(256), 0, st, gf, v, gc, Rt, out);
+}
+
+template <typename C>
+void w_prolong(const Geom& gc, const C* e, const Geom& gf, const Transfer1D& Pt, int add, C* x, int nr,
+               hipStream_t st) {
+  const dim3 grid = grid1(gf.tot, nr);
+  if (gf.dim == 3)
+    hipLaunchKernelGGL((k_wprolong<3, C>), grid, dim3(256), 0, st, gc, e, gf, Pt, add, x);
+  else
+    hipLaunchKernelGGL((k_wprolong<2, C>), grid, dim3(256), 0, st, gc, e, gf, Pt, add, x);
+}
+
+template <typename CI, typename CO>
+void w_copy(const CI* in, CO* out, long long n, hipStream_t st) {
+  hipLaunchKernelGGL((k_wcopy<CI, CO>), dim3(1024), dim3(256), 0, st, in, out, n);
+}
+
+template void w1_step<float, cd, cf>(const WFine<float>&, int, int, const cf*, const cd*, float, cf*, int, hipStream_t);
+template void w1_step<float, cd, cd>(const WFine<float>&, int, int, const cf*, const cd*, float, cd*, int, hipStream_t);
+template void w1_step<float, cf, cf>(const WFine<float>&, int, int, const cf*, const cf*, float, cf*, int, hipStream_t);
+template void w1_step<double, cd, cd>(const WFine<double>&, int, int, const cd*, const cd*, double, cd*, int,
+                                      hipStream_t);
+template void w2_step<float>(const Geom&, const cf*, int, int, int, const cf*, const cf*, float, cf*, int, hipStream_t);
+template void w2_step<double>(const Geom&, const cd*, int, int, int, const cd*, const cd*, double, cd*, int,
+                              hipStream_t);
+template void w_restrict<cf>(const Geom&, const cf*, const Geom&, const Transfer1D&, cf*, int, hipStream_t);
+template void w_restrict<cd>(const Geom&, const cd*, const Geom&, const Transfer1D&, cd*, int, hipStream_t);
+template void w_prolong<cf>(const Geom&, const cf*, const Geom&, const Transfer1D&, int, cf*, int, hipStream_t);
+template void w_prolong<cd>(const Geom&, const cd*, const Geom&, const Transfer1D&, int, cd*, int, hipStream_t);
+template void w_copy<cf, cf>(const cf*, cf*, long long, hipStream_t);
+template void w_copy<cf, cd>(const cf*, cd*, long long, hipStream_t);
+template void w_copy<cd, cd>(const cd*, cd*, long long, hipStream_t);
+template void w_copy<cd, cf>(const cd*, cf*, long long, hipStream_t);
+
+}  // namespace helm

@@ -23,14 +23,16 @@ from . import _lib as L
 INFO_KEYS = ("N1", "N2", "N3", "fronts", "L_entries", "W_entries", "upd_entries", "sep_entries",
              "fwd_launches", "bwd_launches", "workspace_bytes", "max_front", "cycle_complex_bytes",
              "nd_leaf", "nd_root", "nd_tuned", "nd_tree_launches")
+INFO_LEN = 24
 KERNEL_CLASSES = ("l1_sweep", "l1_restrict", "l2_sweep", "l2_restrict", "nd_fwd", "nd_bwd", "arnoldi")
 
 
 def parse_info(v) -> dict:
-    """the 22 integers of helm_get_info as a dict"""
+    """the INFO_LEN integers of helm_get_info as a dict"""
     out = {k: int(v[i]) for i, k in enumerate(INFO_KEYS)}
     out["nd_cuts"] = [int(v[17 + i]) for i in range(min(4, out["nd_tree_launches"]))]
     out["nd_merge"] = [h for h in range(63) if (int(v[21]) >> h) & 1]
+    out["planes2"], out["planes3"] = int(v[22]), int(v[23])
     return out
 
 
@@ -65,7 +67,15 @@ def make_grid(n: Sequence[int], h: float, layer, sigma_max: float) -> L.Grid:
     return g
 
 
-def make_mg(cycle: int = 2, nu=(1, 1), jacobi=0.8, cycle_prec: str = "f32", restart: int = 20) -> L.MG:
+STACKS = {"p5": L.HELM_STACK_P5, "compact": L.HELM_STACK_COMPACT}
+TRANSFERS = {None: 0, "fw": 0, "cubic": L.HELM_TRANSFER_CUBIC, "levdep": L.HELM_TRANSFER_LEVDEP}
+
+
+def make_mg(cycle: int = 2, nu=(1, 1), jacobi=0.8, cycle_prec: str = "f32", restart: int = 20,
+            stack: str = "p5", transfer=None) -> L.MG:
+    """stack 'p5' (5/7-point operator, full weighting, linear interpolation) or 'compact'
+    (the compact fourth-order operator of eqs. (3.1)/(3.2) with transfer 'cubic', eq. (3.3),
+    or 'levdep', eq. (3.4))"""
     m = L.MG()
     m.cycle = int(cycle)
     m.nu_pre, m.nu_post = int(nu[0]), int(nu[1])
@@ -73,6 +83,8 @@ def make_mg(cycle: int = 2, nu=(1, 1), jacobi=0.8, cycle_prec: str = "f32", rest
     m.jacobi[0], m.jacobi[1] = float(jw[0]), float(jw[1])
     m.cycle_prec = L.HELM_F32 if cycle_prec in ("f32", "fp32", L.HELM_F32) else L.HELM_F64
     m.restart = int(restart)
+    m.stack = STACKS[stack]
+    m.transfer = TRANSFERS[transfer if stack == "compact" else None]
     return m
 
 
@@ -90,13 +102,15 @@ class Solver:
     (solve_many)."""
 
     def __init__(self, n, h, slowness, omega, layer, sigma_max, alpha=1.0, alpha2=1.0, beta=0.0, cycle=2,
-                 nu=(1, 1), jacobi=0.8, cycle_prec="f32", restart=20, device="cuda:0", max_rhs=1):
+                 nu=(1, 1), jacobi=0.8, cycle_prec="f32", restart=20, device="cuda:0", max_rhs=1, stack="p5",
+                 transfer=None):
         self.device = torch.device(device)
         self.n = tuple(int(k) for k in n)
         self.dim = len(self.n)
         self.N = int(np.prod([k + 1 for k in self.n]))
         self.grid = make_grid(n, h, layer, sigma_max)
-        self.mg = make_mg(cycle, nu, jacobi, cycle_prec, restart)
+        self.mg = make_mg(cycle, nu, jacobi, cycle_prec, restart, stack, transfer)
+        self.stack = stack
         self.shift = L.Shift(float(alpha), float(alpha2), float(beta))
         self.omega = float(omega)
         self.max_rhs = int(max_rhs)
@@ -255,8 +269,10 @@ class Solver:
                          true_rel_residual=infos[k].true_rel_residual) for k in range(n)]
 
     def coefficients(self, lev: int) -> np.ndarray:
-        """stored Galerkin coefficients of level 2 or 3: array (3^d, N_lev) complex128."""
-        K = 9 if self.dim == 2 else 27
+        """stored Galerkin coefficients of level 2 or 3: array (planes, N_lev) complex128; plane
+        k holds A(i, i + d) for the offset d with k = sum_a (d_a + r) (2r + 1)^a (r: the
+        level's stencil radius, 1 for the 5/7-point stack)."""
+        K = self.info()["planes2" if lev == 2 else "planes3"]
         Nl = self.level_size(lev)
         out = np.empty(K * Nl, np.complex128)
         L.check(L.lib.helm_get_coefficients(self.ctx, lev, C.c_void_p(out.ctypes.data)), "helm_get_coefficients")
@@ -276,8 +292,8 @@ class Solver:
 
 
     def info(self) -> dict:
-        v = (C.c_longlong * 22)()
-        L.check(L.lib.helm_get_info(self.ctx, v, 22), "helm_get_info")
+        v = (C.c_longlong * INFO_LEN)()
+        L.check(L.lib.helm_get_info(self.ctx, v, INFO_LEN), "helm_get_info")
         return parse_info(v)
 
     def set_timing(self, on: bool = True):
@@ -291,8 +307,10 @@ class Solver:
 
 def from_problem(prob, **kw) -> Solver:
     """Solver for an object with the attributes of a workload description (n, h, slowness,
-    omega, layer, sigma_max, alpha, beta, cycle, nu_pre, nu_post, jacobi, restart)."""
+    omega, layer, sigma_max, alpha, beta, cycle, nu_pre, nu_post, jacobi, restart; stack and
+    transfer if it has them)."""
     args = dict(alpha=prob.alpha, alpha2=getattr(prob, "alpha2", 1.0), beta=prob.beta, cycle=prob.cycle,
-                nu=(prob.nu_pre, prob.nu_post), jacobi=prob.jacobi, restart=prob.restart)
+                nu=(prob.nu_pre, prob.nu_post), jacobi=prob.jacobi, restart=prob.restart,
+                stack=getattr(prob, "stack", "p5"), transfer=getattr(prob, "transfer", None))
     args.update(kw)
     return Solver(prob.n, prob.h, prob.slowness, prob.omega, prob.layer, prob.sigma_max, **args)

@@ -145,6 +145,8 @@ class Problem:
     jacobi: object = 0.8    # damping weight, or (level 1, level 2)
     restart: int = 20
     tol: float = 1e-6
+    stack: str = "p5"       # "p5" (5/7-point, full weighting) or "compact" (the paper's stack)
+    transfer: Optional[str] = None   # compact stack: "cubic" or "levdep"
 
     @property
     def N(self) -> int:
@@ -268,3 +270,43 @@ def random_vector(N: int, seed: int, dtype=np.complex128) -> np.ndarray:
     rng = np.random.default_rng(seed)
     v = rng.standard_normal(N) + 1j * rng.standard_normal(N)
     return v.astype(dtype)
+
+
+# The paper's own discretisation (Sec. 3.1, 5.1, 5.2): compact fourth-order operator, cubic
+# transfers in 2D and level-dependent ones in 3D, the real shift alpha* of Table 1 (2D) /
+# Table 2 (3D) for the stack and G, W(1,1) cycle, damped Jacobi 0.89 on both levels in 2D
+# and 0.6 / 0.4 in 3D, no complex shift, unit-square (cube) domain with a 20-cell absorbing
+# layer (scaled down below 128 cells), point source at the centre.
+PAPER_ALPHA = {
+    (2, "cubic", 10.0): 1.014, (2, "cubic", 11.0): 1.0075, (2, "cubic", 12.0): 1.0045,
+    (2, "levdep", 10.0): 1.029, (2, "levdep", 11.0): 1.019, (2, "levdep", 12.0): 1.0135,
+    (3, "levdep", 10.0): 1.0245, (3, "levdep", 11.0): 1.0165, (3, "levdep", 12.0): 1.012,
+}
+
+
+def paper_stack(n: Sequence[int], transfer: Optional[str] = None, G: float = 12.0, lo: Optional[float] = None,
+                alpha: Optional[float] = None, layer_cells: int = 20) -> Problem:
+    """the paper's stack on a grid of n cells per axis.  Medium: homogeneous (Fig. 4b) or,
+    with lo, Table 3's linear medium, whose slowness grows linearly with depth from lo at the
+    top face to 1 at the bottom (the text's ranges read as slowness); G at the largest
+    slowness."""
+    n = tuple(int(k) for k in n)
+    dim = len(n)
+    transfer = transfer or ("cubic" if dim == 2 else "levdep")
+    h = 1.0 / max(n)
+    shape = node_shape(n)
+    if lo is None:
+        kap = np.ones(shape)
+        name = "paper_homog"
+    else:
+        depth = np.linspace(0.0, 1.0, n[-1] + 1)
+        prof = lo + (1.0 - lo) * depth
+        kap = np.broadcast_to(prof.reshape((-1,) + (1,) * (dim - 1)), shape).copy()
+        name = "paper_linear%g" % lo
+    L = layer_cells if min(n) >= 128 else max(2, (layer_cells * min(n)) // 128)
+    a = PAPER_ALPHA[(dim, transfer, float(G))] if alpha is None else alpha
+    jac = (0.89, 0.89) if dim == 2 else (0.6, 0.4)
+    return Problem("%s_%s_%s" % (name, transfer, "x".join(map(str, n))), dim, n, h, kap,
+                   omega_for_G(G, h, float(kap.max())), tuple((L, L) for _ in range(dim)), SIGMA_MAX, a, 0.0,
+                   [tuple(k // 2 for k in n)], G, nu_pre=1, nu_post=1, jacobi=jac, stack="compact",
+                   transfer=transfer)

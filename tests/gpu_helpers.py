@@ -5,21 +5,25 @@ import synth
 from oracle import multigrid, operators as ops
 
 
-def stencil_arrays(A, n_lev):
-    """(3^d, N) array of a sparse 9/27-point operator: entry k of row i is A[i, i + offset_k],
-    offset k = (d0+1) + 3 (d1+1) [+ 9 (d2+1)], zero where the neighbour is outside the grid."""
+def stencil_arrays(A, n_lev, r=1):
+    """((2r+1)^d, N) array of a sparse operator of stencil radius r: entry k of row i is
+    A[i, i + offset_k], offset k = (d0+r) + (2r+1) (d1+r) [+ (2r+1)^2 (d2+r)], zero where the
+    neighbour is outside the grid."""
     d = len(n_lev)
     Ns = [k + 1 for k in n_lev]
     N = int(np.prod(Ns))
-    K = 3 ** d
+    w = 2 * r + 1
+    K = w ** d
     out = np.zeros((K, N), np.complex128)
     A = A.tocoo()
     i, j = A.row, A.col
     ci = [i % Ns[0], (i // Ns[0]) % Ns[1]] + ([i // (Ns[0] * Ns[1])] if d == 3 else [])
     cj = [j % Ns[0], (j // Ns[0]) % Ns[1]] + ([j // (Ns[0] * Ns[1])] if d == 3 else [])
-    k = (cj[0] - ci[0] + 1) + 3 * (cj[1] - ci[1] + 1)
+    off = [cj[a] - ci[a] for a in range(d)]
+    assert all(np.all(np.abs(o) <= r) for o in off), "operator wider than radius %d" % r
+    k = (off[0] + r) + w * (off[1] + r)
     if d == 3:
-        k = k + 9 * (cj[2] - ci[2] + 1)
+        k = k + w * w * (off[2] + r)
     out[k, i] = A.data
     return out
 

@@ -1,0 +1,172 @@
+"""GPU parity of the paper's own stack (Sec. 3.1: the compact fourth-order operator of
+eqs. (3.1)/(3.2), the high-order transfers of eq. (3.3) and the level-dependent ones of
+eq. (3.4), Galerkin operators of radius 2 and 3, the real shift of eq. (3.6)) against the
+FP64 oracle's compact stack, through the C ABI.
+
+Tolerances as in test_gpu_parity: FP64 set-up and operator to 1e-13, coarsest solve and
+cycle to 1e-10 (FP64) / 1e-4 (FP32), element-wise cycle bounds 1e-10 / 3e-4 of the largest
+entry; whole solves to the oracle's iteration count +-1 and a solution difference of 1e-10
+(FP64 cycle) / 1e-6 (FP32 cycle) relative, below the 1e-6 stopping rule.
+"""
+import ctypes as C
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from tests.gpu_helpers import maxabs_rel, oracle_hierarchy, rel, stencil_arrays
+
+pytestmark = pytest.mark.gpu
+
+L = pytest.importorskip("paper_2604_19501_amd._lib")
+from paper_2604_19501_amd import HELM_OP_C, from_problem  # noqa: E402
+from oracle import fgmres, multigrid  # noqa: E402
+
+TOL_INF = {"f64": 1e-10, "f32": 3e-4}
+CASES = [((32, 32), "cubic"), ((32, 32), "levdep"), ((40, 24), "cubic"), ((16, 16, 16), "levdep")]
+
+
+def _rand(N, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(N) + 1j * rng.standard_normal(N)
+
+
+def _problem(n, transfer, lo=0.4):
+    p = synth.paper_stack(n, transfer, lo=lo)
+    return p
+
+
+@pytest.mark.parametrize("n,transfer", CASES)
+def test_compact_galerkin_coefficients(n, transfer):
+    """A2 = R1 H P1 (radius 2) and A3 = R2 (R1 H^alpha P1) P2 (radius 3 cubic / 2 level-dependent)"""
+    p = _problem(n, transfer)
+    print("compact galerkin", n, transfer, flush=True)
+    H = oracle_hierarchy(p)
+    s = from_problem(p, cycle_prec="f64")
+    r3 = 3 if transfer == "cubic" else 2
+    A2 = stencil_arrays(H.A[1], H.n2, 2)
+    A3 = stencil_arrays(H.A[2], H.n3, r3)
+    assert s.info()["planes2"] == A2.shape[0] and s.info()["planes3"] == A3.shape[0]
+    assert rel(s.coefficients(2), A2) < 1e-13
+    assert rel(s.coefficients(3), A3) < 1e-13
+    s.close()
+
+
+@pytest.mark.parametrize("n,transfer", CASES)
+def test_compact_apply(n, transfer):
+    p = _problem(n, transfer)
+    print("compact apply", n, transfer, flush=True)
+    H = oracle_hierarchy(p)
+    x = _rand(p.N, 1)
+    ref = H.H @ x
+    s = from_problem(p, cycle_prec="f64")
+    y = s.apply(x).cpu().numpy()
+    assert rel(y, ref) < 1e-13 and maxabs_rel(y, ref) < 1e-13
+    y32 = s.apply(x, prec="f32").cpu().numpy()
+    assert rel(y32, ref) < 1e-5
+    s.close()
+
+
+@pytest.mark.parametrize("n,transfer", CASES)
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-4)])
+def test_compact_coarse_solve(n, transfer, prec, tol):
+    p = _problem(n, transfer)
+    print("compact coarse", n, transfer, prec, flush=True)
+    H = oracle_hierarchy(p)
+    s = from_problem(p, cycle_prec=prec)
+    r = _rand(s.level_size(3), 2)
+    e = s.coarse_solve(r).cpu().numpy()
+    assert rel(e, H.lu3.solve(r)) < tol
+    s.close()
+
+
+@pytest.mark.parametrize("n,transfer", CASES)
+@pytest.mark.parametrize("prec,tol", [("f64", 1e-10), ("f32", 1e-4)])
+@pytest.mark.parametrize("cycle,nu", [(2, (1, 1)), (1, (2, 1)), (2, (0, 1)), (2, (1, 0))])
+def test_compact_cycle(n, transfer, prec, tol, cycle, nu):
+    p = _problem(n, transfer)
+    p.cycle, p.nu_pre, p.nu_post = cycle, nu[0], nu[1]
+    print("compact cycle", n, transfer, prec, cycle, nu, flush=True)
+    H = oracle_hierarchy(p)
+    r = _rand(p.N, 3)
+    ref = H.precond(r)
+    s = from_problem(p, cycle_prec=prec)
+    z = s.vcycle(r).cpu().numpy()
+    assert rel(z, ref) < tol, rel(z, ref)
+    assert maxabs_rel(z, ref) < TOL_INF[prec], maxabs_rel(z, ref)
+    s.close()
+
+
+@pytest.mark.parametrize("n,transfer,restart", [((64, 64), "cubic", 20), ((64, 64), "levdep", 3),
+                                                ((24, 24, 24), "levdep", 20)])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_compact_solve_matches_oracle(n, transfer, restart, prec):
+    """FGMRES with the compact stack's cycle: iterations equal the oracle's +-1 (restart 3 runs
+    several restart cycles), and the solution agrees with the oracle's"""
+    p = _problem(n, transfer)
+    p.restart = restart
+    print("compact solve", n, transfer, restart, prec, flush=True)
+    H = oracle_hierarchy(p)
+    q = p.rhs()
+    ro = fgmres.solve(H, q, tol=1e-6, restart=restart, max_iter=300)
+    s = from_problem(p, cycle_prec=prec)
+    x, info = s.solve(q, tol=1e-6, max_iter=300)
+    x = x.cpu().numpy()
+    print("  gpu %d iterations, oracle %d" % (info["iterations"], ro.iterations), flush=True)
+    assert abs(info["iterations"] - ro.iterations) <= 1
+    assert info["true_rel_residual"] <= 1e-6
+    assert rel(x, ro.x) < (1e-10 if prec == "f64" else 1e-6)
+    s.close()
+
+
+@pytest.mark.parametrize("lo,paper_fgmres,paper_solver", [(0.5, 6, 9), (0.1, 6, 8)])
+def test_table_3_linear_media_counts_on_the_gpu(lo, paper_fgmres, paper_solver):
+    """Table 3 at 128^2 (linear media, G = 12, cubic transfers, alpha* = 1.0045): FGMRES
+    (non-restarted) and the cycle as a stand-alone solver, each within one iteration of the
+    paper's count, with the FP32 cycle"""
+    p = synth.paper_stack((128, 128), "cubic", lo=lo)
+    p.restart = 64
+    print("table 3", lo, flush=True)
+    s = from_problem(p, cycle_prec="f32")
+    q = p.rhs()
+    _, info = s.solve(q, tol=1e-6, max_iter=100)
+    _, it2 = s.iterate(q, tol=1e-6, max_iter=100)
+    print("  fgmres %d (paper %d), solver %d (paper %d)" % (info["iterations"], paper_fgmres, it2["iterations"],
+                                                           paper_solver), flush=True)
+    assert abs(info["iterations"] - paper_fgmres) <= 1
+    assert abs(it2["iterations"] - paper_solver) <= 1
+    s.close()
+
+
+def test_fig_4b_count_at_1024():
+    """Fig. 4b: 6-8 FGMRES(20) iterations for the homogeneous G = 12 problem at 1024^2 with
+    the real shift alpha* = 1.0045, and more without it (the oracle pins the same at 1024^2)"""
+    its = {}
+    for a in (1.0045, 1.0):
+        p = synth.paper_stack((1024, 1024), "cubic", alpha=a)
+        print("fig 4b 1024 alpha", a, flush=True)
+        s = from_problem(p, cycle_prec="f32")
+        _, info = s.solve(p.rhs(), tol=1e-6, max_iter=200)
+        its[a] = info["iterations"]
+        assert info["true_rel_residual"] <= 1e-6
+        s.close()
+    print("  iterations", its, flush=True)
+    assert 6 <= its[1.0045] <= 8 and its[1.0] >= its[1.0045] + 2, its
+
+
+def test_compact_refuses_the_adjoint():
+    p = _problem((32, 32), "cubic")
+    s = from_problem(p, cycle_prec="f64")
+    x = torch.zeros(p.N, dtype=torch.complex128, device="cuda")
+    y = torch.zeros_like(x)
+    st = torch.cuda.current_stream().cuda_stream
+    assert L.lib.helm_apply(s.ctx, HELM_OP_C, L.HELM_F64, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                            C.c_void_p(st)) == L.HELM_EINVAL
+    assert b"adjoint" in L.lib.helm_last_error()
+    assert L.lib.helm_vcycle(s.ctx, HELM_OP_C, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr()),
+                             C.c_void_p(st)) == L.HELM_EINVAL
+    g = torch.zeros(p.N, dtype=torch.float64, device="cuda")
+    ptrs = (C.c_void_p * 1)(x.data_ptr())
+    assert L.lib.helm_grad_m(s.ctx, 1, ptrs, ptrs, C.c_void_p(g.data_ptr()), 0, C.c_void_p(st)) == L.HELM_EINVAL
+    s.close()
