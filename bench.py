@@ -123,6 +123,21 @@ def bytes_model(cls, p, info, iters, restart, nr=1):
     cb = info["cycle_complex_bytes"]
     K = 3 ** d
     U = info["upd_entries"]
+    if getattr(p, "stack", "p5") == "compact" and cls in ("l1_restrict", "l1_sweep", "l2_restrict", "l2_sweep"):
+        # the compact stack's plain kernels (one node per thread, neighbours from cache):
+        # Jacobi sweeps read x, b, m and write x; a restriction class launch is either the
+        # residual (x, b, m in, r out) or the transfer (r in, the coarse right-hand side
+        # out): the class's bytes per launch are the two launches' mean
+        K2 = info["planes2"]
+        mb = cb // 2                            # m in the cycle's real precision
+        if cls == "l1_sweep":
+            return N1 * ((cb + 16 + cb) * nr + mb)
+        if cls == "l1_restrict":
+            return (N1 * ((cb + 16 + cb) * nr + mb) + (N1 * cb + N2 * cb) * nr) / 2
+        if cls == "l2_sweep":
+            return N2 * cb * (K2 + 3 * nr)
+        if cls == "l2_restrict":
+            return (N2 * cb * (K2 + 3 * nr) + (N2 + N3) * cb * nr) / 2
     # the level-1 diagonal: precomputed complex FP32 (the FP32 cycle) or m in FP64 (8 B either way)
     if cls == "l1_restrict":      # b (c128) per fine node and r2 per level-2 node per rhs; the diagonal
         return N1 * (16 * nr + 8) + N2 * cb * nr
@@ -496,9 +511,38 @@ def workload_cfg5(args):
     return out
 
 
+def workload_paper(args):
+    """the paper's own stack (compact fourth-order 9-point operator, cubic transfers, alpha*
+    of Table 1) on Fig. 4b's homogeneous G = 12 problem at 1024^2, with the oracle's complete
+    solve of the same system"""
+    import synth
+    p = synth.paper_stack((1024, 1024), "cubic")
+    label = ("2D 1024x1024 homogeneous, G=12, 20-cell absorbing layer, centre point source, the paper's compact "
+             "fourth-order 9-point operator with cubic transfers (25- and 49-point Galerkin levels), alpha=%.4f "
+             "(Table 1), FGMRES(20) tol 1e-6, W(1,1) cycle, Jacobi 0.89" % p.alpha)
+    out, xs = run_single(args, p, label, not args.no_fp64)
+    if not args.no_cpu_baseline:
+        print("[bench] %s GPU part done, oracle solve" % p.name, file=sys.stderr, flush=True)
+        setup, solve, r = oracle_full_solve(p)
+        out["cpu_baseline"] = dict(
+            value=1.0 / (setup + solve), unit="solves/s", kind="oracle",
+            sample="the oracle's complete solve of the same system (set-up %.1f s: Galerkin products and a "
+                   "sparse LU of the 49-point coarsest operator; FGMRES %.1f s for %d iterations)"
+                   % (setup, solve, r.iterations),
+            iterations=r.iterations, setup_s=setup, solve_s=solve, **host_fields())
+        out["oracle_parity"] = {
+            "iterations_oracle": r.iterations, "iterations_gpu_mixed": out["config"]["iterations"],
+            "rel_diff_to_oracle_solution_mixed": rel(xs["f32"], r.x),
+            "paper_iterations_fig_4b": "6-8"}
+        if "f64" in xs:
+            out["oracle_parity"]["iterations_gpu_fp64"] = out["fp64"]["iterations"]
+            out["oracle_parity"]["rel_diff_to_oracle_solution_fp64"] = rel(xs["f64"], r.x)
+    return out
+
+
 def workload_suite(args):
-    """the headline (1024^2 layered, mixed vs FP64, oracle full solve) with the 256^3 and the
-    batched workloads as sub-records"""
+    """the headline (1024^2 layered, mixed vs FP64, oracle full solve) with the 256^3, the
+    batched and the paper-stack workloads as sub-records"""
     out = workload_cfg2(args)
     print("[bench] cfg2 done: %.3f solves/s" % out["value"], file=sys.stderr, flush=True)
     sub = {}
@@ -506,7 +550,7 @@ def workload_suite(args):
     # solves), so that the whole run stays within a few minutes
     sargs = argparse.Namespace(**vars(args))
     sargs.steps, sargs.warmup = min(args.steps, 3), min(args.warmup, 1)
-    for name, fn in (("cfg3", workload_cfg3), ("cfg4", workload_cfg4)):
+    for name, fn in (("cfg3", workload_cfg3), ("cfg4", workload_cfg4), ("paper", workload_paper)):
         free_gpu()
         t0 = time.perf_counter()
         sub[name] = fn(sargs)
@@ -522,7 +566,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=("suite", "cfg1", "cfg2", "cfg3", "cfg4", "cfg5"), default="suite")
+    ap.add_argument("--workload", choices=("suite", "cfg1", "cfg2", "cfg3", "cfg4", "cfg5", "paper"),
+                    default="suite")
     ap.add_argument("--n", type=int, default=1024, help="cells per axis of the cfg2 workload")
     ap.add_argument("--batch-per-size", type=int, default=32, help="cfg4: instances per grid size")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -553,7 +598,7 @@ def main():
         print(json.dumps({"pmc_pass": True, "iterations": info["iterations"], "copy_bytes": 2 * a.numel() * 8}))
         return
     out = {"suite": workload_suite, "cfg1": workload_cfg1, "cfg2": workload_cfg2, "cfg3": workload_cfg3,
-           "cfg4": workload_cfg4, "cfg5": workload_cfg5}[args.workload](args)
+           "cfg4": workload_cfg4, "cfg5": workload_cfg5, "paper": workload_paper}[args.workload](args)
     print(json.dumps(out))
 
 

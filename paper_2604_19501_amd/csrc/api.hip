@@ -307,7 +307,8 @@ int env_int(const char* name, int dflt) {
 }
 
 // schedule parameters of the coarsest solve picked by the autotuner: the JSON file named
-// by HELM_TUNE_CACHE maps "nd:<dim>:<n0>x<n1>x<n2>:<f32|f64>" to an object with integers
+// by HELM_TUNE_CACHE maps "nd:<dim>:<n0>x<n1>x<n2>:<f32|f64>" (with ":r<radius>" appended
+// when the coarsest stencil radius is not 1) to an object with integers
 // "leaf", "root" and "splitk_kb" and strings "cuts" and "merge"; returns false when the file
 // or the key is absent
 struct TunedND {
@@ -325,9 +326,10 @@ bool tuned_nd(const helm_ctx* c, TunedND& t) {
   size_t n;
   while ((n = fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, n);
   fclose(f);
-  char key[128];
-  snprintf(key, sizeof key, "\"nd:%d:%dx%dx%d:%s\"", c->grid.dim, c->grid.n[0], c->grid.n[1],
-           c->grid.dim == 3 ? c->grid.n[2] : 0, c->f32 ? "f32" : "f64");
+  char key[128], rad[16] = "";
+  if (c->r3 != 1) snprintf(rad, sizeof rad, ":r%d", c->r3);
+  snprintf(key, sizeof key, "\"nd:%d:%dx%dx%d:%s%s\"", c->grid.dim, c->grid.n[0], c->grid.n[1],
+           c->grid.dim == 3 ? c->grid.n[2] : 0, c->f32 ? "f32" : "f64", rad);
   size_t k = txt.find(key);
   if (k == std::string::npos) return false;
   size_t ob = txt.find('{', k), oe = txt.find('}', k);

@@ -12,6 +12,7 @@ context of that shape (file named by HELM_TUNE_CACHE; the package sets it to
 tune_cache.json next to the library unless the caller set it).
 
     python -m paper_2604_19501_amd.tune --n 1024 1024 --prec f32 [--its 150] [--out FILE]
+        [--stack compact --transfer cubic]
 
 Each candidate is scored by its numerical set-up time (coefficients, Galerkin operators,
 factorisation) plus --its times its per-iteration time: a larger root front shortens the
@@ -91,7 +92,23 @@ def _problem(n, G=10.0, layer=8):
     return dim, h, kappa, omega, tuple((layer, layer) for _ in range(dim))
 
 
-def time_schedule(n, prec, leaf, root, cuts, iters=30, repeats=2, merge="none", splitk_kb=SPLITK_DEFAULT_KB):
+def coarsest_radius(stack="p5", transfer=None):
+    """stencil radius of the coarsest operator: 1 for the 5/7-point stack; the compact
+    stack's 49-point (cubic) or 25/125-point (level-dependent) operator: 3 or 2"""
+    if stack != "compact":
+        return 1
+    return 3 if transfer == "cubic" else 2
+
+
+def cache_key(n, prec, stack="p5", transfer=None):
+    dim = len(n)
+    r = coarsest_radius(stack, transfer)
+    return "nd:%d:%s:%s%s" % (dim, "x".join(str(k) for k in (tuple(n) + (0,) * (3 - dim))), prec,
+                              ":r%d" % r if r != 1 else "")
+
+
+def time_schedule(n, prec, leaf, root, cuts, iters=30, repeats=2, merge="none", splitk_kb=SPLITK_DEFAULT_KB,
+                  stack="p5", transfer=None):
     """(seconds per FGMRES iteration, seconds per numerical set-up, plan info)"""
     env = {"HELM_ND_LEAF": str(leaf), "HELM_ND_ROOT": str(root), "HELM_ND_CUTS": cuts,
            "HELM_ND_MERGE": merge, "HELM_ND_SPLITK_KB": str(splitk_kb)}
@@ -100,7 +117,7 @@ def time_schedule(n, prec, leaf, root, cuts, iters=30, repeats=2, merge="none", 
     try:
         dim, h, kappa, omega, layer = _problem(n)
         s = Solver(n, h, kappa, omega, layer=layer, sigma_max=2.0, alpha=1.1, alpha2=1.0, beta=0.1,
-                   nu=(1, 1), cycle_prec=prec)
+                   nu=(1, 1), cycle_prec=prec, stack=stack, transfer=transfer)
         info = s.info()
         q = np.zeros(int(np.prod([k + 1 for k in n])), np.complex128)
         q[q.size // 2] = 1.0
@@ -127,16 +144,17 @@ def time_schedule(n, prec, leaf, root, cuts, iters=30, repeats=2, merge="none", 
         torch.cuda.empty_cache()
 
 
-def tune(n, prec="f32", out=None, its=150, verbose=True):
+def tune(n, prec="f32", out=None, its=150, verbose=True, stack="p5", transfer=None):
     n = tuple(int(k) for k in n)
     dim = len(n)
-    key = "nd:%d:%s:%s" % (dim, "x".join(str(k) for k in (n + (0,) * (3 - dim))), prec)
+    key = cache_key(n, prec, stack, transfer)
     results, seen = [], set()
 
     def run(cands):
         for leaf, root, cuts, merge, sk in cands:
             try:
-                t, ts, info = time_schedule(n, prec, leaf, root, cuts, merge=merge, splitk_kb=sk)
+                t, ts, info = time_schedule(n, prec, leaf, root, cuts, merge=merge, splitk_kb=sk, stack=stack,
+                                            transfer=transfer)
             except L.HelmError as e:
                 if verbose:
                     print("  leaf %d root %d cuts %r merge %r: %s" % (leaf, root, cuts, merge, e), flush=True)
@@ -183,8 +201,10 @@ def main():
     ap.add_argument("--prec", choices=("f32", "f64"), default="f32")
     ap.add_argument("--out", default=None)
     ap.add_argument("--its", type=int, default=150, help="iterations per set-up in the score")
+    ap.add_argument("--stack", choices=("p5", "compact"), default="p5")
+    ap.add_argument("--transfer", choices=("cubic", "levdep"), default=None)
     a = ap.parse_args()
-    tune(a.n, a.prec, a.out, a.its)
+    tune(a.n, a.prec, a.out, a.its, stack=a.stack, transfer=a.transfer)
 
 
 if __name__ == "__main__":
