@@ -540,6 +540,42 @@ def workload_paper(args):
     return out
 
 
+def workload_paper3d(args):
+    """the paper's 3D stack on a stand-in of its largest 3D grid (Table 5: 192x192x72 cells,
+    G = 12): GPU timing, the true residual of the GPU solution under the oracle's operator,
+    and the oracle's complete solve of the same recipe at 96x96x40 scaled to this grid"""
+    import synth
+    from oracle import operators as ops
+    p = synth.paper_3d((192, 192, 72), 12.0)
+    label = ("3D 192x192x72 layered stand-in (8 sharp layers, noise smoothed over 4 cells), G=12, 12-cell "
+             "absorbing layer on five faces, source at the centre of the top face, the paper's compact 19-point "
+             "operator with level-dependent transfers (125-point Galerkin levels), alpha=%.4f (Table 2), "
+             "FGMRES(20) tol 1e-6, W(1,1) cycle, Jacobi 0.6/0.4" % p.alpha)
+    out, xs = run_single(args, p, label, not args.no_fp64)
+    sigma = ops.layer_sigma(p.n, p.layer, p.sigma_max)
+    Hc = ops.helmholtz_compact(p.n, p.h, p.slowness.ravel() ** 2, p.omega, sigma)
+    b = p.rhs()
+    out["oracle_parity"] = {"true_rel_residual_oracle_operator_mixed":
+                            float(np.linalg.norm(b - Hc @ xs["f32"]) / np.linalg.norm(b)),
+                            "paper_iterations_table_5": 10}
+    if "f64" in xs:
+        out["oracle_parity"]["true_rel_residual_oracle_operator_fp64"] = float(
+            np.linalg.norm(b - Hc @ xs["f64"]) / np.linalg.norm(b))
+    if not args.no_cpu_baseline:
+        print("[bench] %s GPU part done, oracle sample" % p.name, file=sys.stderr, flush=True)
+        ps = synth.paper_3d((96, 96, 40), 12.0)
+        setup, solve, r = oracle_full_solve(ps)
+        scale = p.N / ps.N
+        its = out["config"]["iterations"]
+        est = scale * (setup + solve * its / max(1, r.iterations))
+        out["cpu_baseline"] = dict(
+            value=1.0 / est, unit="solves/s", kind="oracle",
+            sample="the oracle's complete solve of the same recipe at 96x96x40 (%d unknowns: set-up %.1f s, "
+                   "%d iterations in %.1f s), scaled to the GPU's %d iterations and by the unknown count to "
+                   "192x192x72 (x%.1f)" % (ps.N, setup, r.iterations, solve, its, scale), **host_fields())
+    return out
+
+
 def workload_suite(args):
     """the headline (1024^2 layered, mixed vs FP64, oracle full solve) with the 256^3, the
     batched and the paper-stack workloads as sub-records"""
@@ -550,7 +586,8 @@ def workload_suite(args):
     # solves), so that the whole run stays within a few minutes
     sargs = argparse.Namespace(**vars(args))
     sargs.steps, sargs.warmup = min(args.steps, 3), min(args.warmup, 1)
-    for name, fn in (("cfg3", workload_cfg3), ("cfg4", workload_cfg4), ("paper", workload_paper)):
+    for name, fn in (("cfg3", workload_cfg3), ("cfg4", workload_cfg4), ("paper", workload_paper),
+                     ("paper3d", workload_paper3d)):
         free_gpu()
         t0 = time.perf_counter()
         sub[name] = fn(sargs)
@@ -566,7 +603,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=("suite", "cfg1", "cfg2", "cfg3", "cfg4", "cfg5", "paper"),
+    ap.add_argument("--workload", choices=("suite", "cfg1", "cfg2", "cfg3", "cfg4", "cfg5", "paper", "paper3d"),
                     default="suite")
     ap.add_argument("--n", type=int, default=1024, help="cells per axis of the cfg2 workload")
     ap.add_argument("--batch-per-size", type=int, default=32, help="cfg4: instances per grid size")
@@ -598,7 +635,8 @@ def main():
         print(json.dumps({"pmc_pass": True, "iterations": info["iterations"], "copy_bytes": 2 * a.numel() * 8}))
         return
     out = {"suite": workload_suite, "cfg1": workload_cfg1, "cfg2": workload_cfg2, "cfg3": workload_cfg3,
-           "cfg4": workload_cfg4, "cfg5": workload_cfg5, "paper": workload_paper}[args.workload](args)
+           "cfg4": workload_cfg4, "cfg5": workload_cfg5, "paper": workload_paper,
+           "paper3d": workload_paper3d}[args.workload](args)
     print(json.dumps(out))
 
 

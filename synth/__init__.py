@@ -310,3 +310,21 @@ def paper_stack(n: Sequence[int], transfer: Optional[str] = None, G: float = 12.
                    omega_for_G(G, h, float(kap.max())), tuple((L, L) for _ in range(dim)), SIGMA_MAX, a, 0.0,
                    [tuple(k // 2 for k in n)], G, nu_pre=1, nu_post=1, jacobi=jac, stack="compact",
                    transfer=transfer)
+
+
+def paper_3d(n: Sequence[int] = (192, 192, 72), G: float = 12.0, seed: int = 6000) -> Problem:
+    """stand-in for the paper's 3D layered-media experiment (Sec. 5.2, Table 5: grids of
+    64x64x32 up to 192x192x72 cells, G = 12 and 10, no complex shift): a layered medium with
+    sharp interfaces (8 layers, noise smoothed over 4 cells) on a shallow box, h from the
+    horizontal extent, a 12-cell absorbing layer on the five faces other than the top one
+    (none there), the source at the centre of the top face; the paper's 3D stack: compact
+    19-point operator, level-dependent transfers, alpha* of Table 2, W(1,1) with Jacobi
+    damping 0.6 / 0.4."""
+    n = tuple(int(k) for k in n)
+    h = 1.0 / max(n)
+    kap = layered_slowness(n, 8, 4.0, seed)
+    L = 12 if min(n) >= 64 else max(2, min(n) // 6)
+    return Problem("paper3d_%s" % "x".join(map(str, n)), 3, n, h, kap, omega_for_G(G, h, float(kap.max())),
+                   ((L, L), (L, L), (0, L)), SIGMA_MAX, PAPER_ALPHA[(3, "levdep", float(G))], 0.0,
+                   [(n[0] // 2, n[1] // 2, 0)], G, nu_pre=1, nu_post=1, jacobi=(0.6, 0.4), stack="compact",
+                   transfer="levdep")

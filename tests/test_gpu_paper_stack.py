@@ -155,6 +155,27 @@ def test_fig_4b_count_at_1024():
     assert 6 <= its[1.0045] <= 8 and its[1.0] >= its[1.0045] + 2, its
 
 
+@pytest.mark.parametrize("G", [12.0, 10.0])
+def test_3d_layered_stand_in_of_table_5(G):
+    """the paper's 3D stack (19-point operator, level-dependent transfers, alpha* of Table 2,
+    Jacobi 0.6 / 0.4) on Table 5's smallest grid (64x64x32 cells, G = 12 and 10) with a
+    layered stand-in medium: non-restarted FGMRES iterations equal the oracle's +-1 and the
+    solutions agree (the paper reports 10 iterations for its overthrust medium)"""
+    p = synth.paper_3d((64, 64, 32), G)
+    p.restart = 64
+    print("3d table 5 stand-in G", G, flush=True)
+    H = oracle_hierarchy(p)
+    q = p.rhs()
+    ro = fgmres.solve(H, q, tol=1e-6, restart=64, max_iter=100)
+    s = from_problem(p, cycle_prec="f32")
+    x, info = s.solve(q, tol=1e-6, max_iter=100)
+    print("  gpu %d iterations, oracle %d (paper, overthrust: 10)" % (info["iterations"], ro.iterations), flush=True)
+    assert abs(info["iterations"] - ro.iterations) <= 1
+    assert info["true_rel_residual"] <= 1e-6
+    assert rel(x.cpu().numpy(), ro.x) < 1e-6
+    s.close()
+
+
 def test_compact_refuses_the_adjoint():
     p = _problem((32, 32), "cubic")
     s = from_problem(p, cycle_prec="f64")
