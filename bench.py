@@ -150,11 +150,12 @@ def bytes_model(cls, p, info, iters, restart, nr=1):
         return N2 * cb * (S + 3 * nr)
     if cls == "l2_restrict":      # coefficients + b2, x per level-2 node
         return N2 * cb * (S + 2 * nr)
+    nb = info.get("coarse_complex_bytes", cb)     # the coarsest solve's precision
     if cls == "nd_fwd":           # [A^-1; C A^-1] once, right-hand side gather, updates written and read
-        per_solve = info["L_entries"] * cb + 4 * (N3 + U) + nr * (2 * N3 * cb + 2 * U * cb)
+        per_solve = info["L_entries"] * nb + 4 * (N3 + U) + nr * (2 * N3 * nb + 2 * U * nb)
         return per_solve / info["fwd_launches"]
     if cls == "nd_bwd":           # -A^-1 B once, boundary gather, g read and x written
-        per_solve = info["W_entries"] * cb + 4 * U + nr * (U * cb + 2 * N3 * cb)
+        per_solve = info["W_entries"] * nb + 4 * U + nr * (U * nb + 2 * N3 * nb)
         return per_solve / max(1, info["bwd_launches"])
     if cls == "arnoldi":          # two passes, each reading z, m and V_0..V_j; V_{j+1} written
         js = [k % restart for k in range(iters)]

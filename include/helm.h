@@ -281,7 +281,8 @@ int helm_get_timing(helm_ctx* ctx, double* t, int n);
  * launches per direction, [17..20] the heights closing them (-1 beyond), [21] bit mask of
  * the dissection-tree heights whose fronts were merged into their parents, [22] and [23]
  * coefficient planes of the stored level-2 and level-3 operators ((2r+1)^dim for stencil
- * radius r: 9 / 27 for the 5/7-point stack).
+ * radius r: 9 / 27 for the 5/7-point stack), [24] bytes per complex of the coarsest solve's
+ * factors and vectors (the cycle's precision; 16 for the compact stack).
  * Returns the number of entries written (at most n). */
 int helm_get_info(helm_ctx* ctx, long long* out, int n);
 

@@ -149,6 +149,10 @@ struct helm_ctx {
   FineOp op;
   int f32;              // cycle precision is FP32
   size_t csz;           // bytes of one complex in cycle precision
+  // the coarsest solve's factors, vectors and substitution kernels in FP64 (nd64) or in the
+  // cycle's precision, and their bytes per complex
+  int nd64 = 0;
+  size_t ndsz = 16;
   // device state
   double *m64 = nullptr;
   float* m32 = nullptr;
@@ -288,6 +292,12 @@ void init_geometry(helm_ctx* c) {
   } else {
     c->r2 = c->r3 = 1;
   }
+  // The compact stack's coarsest operator, shifted by its alpha* (1.0045 at G = 12), is close
+  // to singular: at 1024^2 (257^2 coarsest nodes) its FP64 factors leave a relative residual
+  // near 1e-8, so FP32 factors would give errors of order one.  Its coarsest solve keeps
+  // FP64 factors with either cycle precision.
+  c->nd64 = !c->f32 || c->compact;
+  c->ndsz = c->nd64 ? sizeof(cd) : sizeof(cf);
   c->K2 = c->K3 = 1;
   for (int a = 0; a < c->grid.dim; ++a) {
     c->K2 *= 2 * c->r2 + 1;
@@ -307,8 +317,9 @@ int env_int(const char* name, int dflt) {
 }
 
 // schedule parameters of the coarsest solve picked by the autotuner: the JSON file named
-// by HELM_TUNE_CACHE maps "nd:<dim>:<n0>x<n1>x<n2>:<f32|f64>" (with ":r<radius>" appended
-// when the coarsest stencil radius is not 1) to an object with integers
+// by HELM_TUNE_CACHE maps "nd:<dim>:<n0>x<n1>x<n2>:<f32|f64>" (the coarsest solve's
+// precision; ":r<radius>" appended when the coarsest stencil radius is not 1) to an object
+// with integers
 // "leaf", "root" and "splitk_kb" and strings "cuts" and "merge"; returns false when the file
 // or the key is absent
 struct TunedND {
@@ -329,7 +340,7 @@ bool tuned_nd(const helm_ctx* c, TunedND& t) {
   char key[128], rad[16] = "";
   if (c->r3 != 1) snprintf(rad, sizeof rad, ":r%d", c->r3);
   snprintf(key, sizeof key, "\"nd:%d:%dx%dx%d:%s%s\"", c->grid.dim, c->grid.n[0], c->grid.n[1],
-           c->grid.dim == 3 ? c->grid.n[2] : 0, c->f32 ? "f32" : "f64", rad);
+           c->grid.dim == 3 ? c->grid.n[2] : 0, c->nd64 ? "f64" : "f32", rad);
   size_t k = txt.find(key);
   if (k == std::string::npos) return false;
   size_t ob = txt.find('{', k), oe = txt.find('}', k);
@@ -412,7 +423,7 @@ void build_plan(helm_ctx* c) {
   // tree-block work-groups of at most HELM_ND_TREE_WAVES wavefronts: 16 in 2D; 8 in 3D, where
   // the many small subtrees run two work-groups per CU (measured 3 % faster at 256^3)
   const int tree_waves = env_int("HELM_ND_TREE_WAVES", c->grid.dim == 3 ? 8 : 16);
-  nd_plan(c->g3, leaf, 16, merge, (int)c->csz, lds, cuts, splitk, c->plan, tree_waves, mh, c->r3);
+  nd_plan(c->g3, leaf, 16, merge, (int)c->ndsz, lds, cuts, splitk, c->plan, tree_waves, mh, c->r3);
   NDPlan& P = c->plan;
   c->hlist.clear();
   c->hlist_toff.clear();
@@ -445,7 +456,7 @@ void build_plan(helm_ctx* c) {
 // the cycle's per-call scratch for rc right-hand sides, taken from cv (the sizes of the
 // coarsest solve's buffers, d.*_n, must have been set)
 CycleScratch carve_scratch(const helm_ctx* c, Carver& cv, int rc) {
-  const size_t cs = c->csz, r = (size_t)rc;
+  const size_t cs = c->csz, ns = c->ndsz, r = (size_t)rc;
   const NDDev& d = c->nd;
   CycleScratch w;
   w.x1a = cv.take<char>(r * cs * c->g1.tot);
@@ -453,12 +464,12 @@ CycleScratch carve_scratch(const helm_ctx* c, Carver& cv, int rc) {
   w.b2 = cv.take<char>(r * cs * c->g2.tot);
   w.x2a = cv.take<char>(r * cs * c->g2.tot);
   w.x2b = cv.take<char>(r * cs * c->g2.tot);
-  w.b3 = cv.take<char>(r * cs * c->g3.tot);
-  w.x3 = cv.take<char>(r * cs * c->g3.tot);
-  w.upd = cv.take<char>(r * cs * std::max<long long>(1, c->plan.upd_total));
-  w.gvec = d.gvec_n ? cv.take<char>(r * cs * d.gvec_n) : nullptr;
-  w.gbuf = cv.take<char>(r * cs * d.gbuf_n);
-  w.part = cv.take<char>(r * cs * d.part_n);
+  w.b3 = cv.take<char>(r * ns * c->g3.tot);       // the coarsest solve's vectors: its precision
+  w.x3 = cv.take<char>(r * ns * c->g3.tot);
+  w.upd = cv.take<char>(r * ns * std::max<long long>(1, c->plan.upd_total));
+  w.gvec = d.gvec_n ? cv.take<char>(r * ns * d.gvec_n) : nullptr;
+  w.gbuf = cv.take<char>(r * ns * d.gbuf_n);
+  w.part = cv.take<char>(r * ns * d.part_n);
   return w;
 }
 
@@ -513,8 +524,8 @@ size_t carve(helm_ctx* c, void* ws) {
   d.err = cv.take<int>(1);
   d.F = cv.take<cd>(P.F_total);
   d.T = cv.take<cd>(std::max<long long>(1, P.T_scratch));
-  d.L = cv.take<char>(cs * P.L_alloc);
-  d.W = cv.take<char>(cs * std::max<long long>(1, P.W_alloc));
+  d.L = cv.take<char>(c->ndsz * P.L_alloc);
+  d.W = cv.take<char>(c->ndsz * std::max<long long>(1, P.W_alloc));
   long long gbuf_max = 1, part_max = 1;      // split-K buffers (entries)
   for (int fb = 0; fb < 2; ++fb) {
     std::vector<NDLaunch>& Ls = fb == 0 ? P.fwd : P.bwd;
@@ -557,7 +568,7 @@ size_t carve(helm_ctx* c, void* ws) {
     for (size_t l = 0; l < (fb == 0 ? P.fwd : P.bwd).size(); ++l) {
       const NDLaunch& L = (fb == 0 ? P.fwd : P.bwd)[l];
       if (L.kind != 1) continue;
-      const size_t need = (size_t)L.max_rows_vec * cs;
+      const size_t need = (size_t)L.max_rows_vec * c->ndsz;
       d.launch[fb][l].shm = need <= c->lds_limit ? std::max<size_t>(need, 16) : 0;
       if (need > c->lds_limit) {
         gcap = std::max<long long>(gcap, L.max_rows_vec);
@@ -640,7 +651,7 @@ void nd_factor(helm_ctx* c, hipStream_t s) {
       nd_save_t(hf, nullptr, hi.count, toff, hi.max_T, d.F, d.T, k0, kout, 0, -1, s);
       nd_gemm(hf, nullptr, hi.count, toff, hi.max_nF, hi.max_nF, d.F, d.T, k0, kout, 0, -1, s);
     }
-    if (c->f32)
+    if (!c->nd64)
       nd_finalize<cf>(hf, nullptr, hi.count, hi.max_fin, d.F, d.perm, (cf*)d.L, (cf*)d.W, s);
     else
       nd_finalize<cd>(hf, nullptr, hi.count, hi.max_fin, d.F, d.perm, (cd*)d.L, (cd*)d.W, s);
@@ -815,7 +826,7 @@ struct Cycle {
     const helm_mg& mg = c->mg;
     const int nr = c->nr;
     C *x1a = (C*)w.x1a, *x1b = (C*)w.x1b, *x2a = (C*)w.x2a, *x2b = (C*)w.x2b;
-    C *b2 = (C*)w.b2, *b3 = (C*)w.b3, *x3 = (C*)w.x3;
+    C* b2 = (C*)w.b2;
     const R w1 = (R)mg.jacobi[0], w2 = (R)mg.jacobi[1];
     WFine<R> F;
     F.op = c->op;
@@ -834,7 +845,7 @@ struct Cycle {
     }
     C* r1 = free1(x1);
     TIMED(c, KT_L1_RESTRICT, s, (w1_step<R, cd, C>(F, WM_RES, x1 == nullptr, x1, b1, (R)0, r1, nr, s)));
-    TIMED(c, KT_L1_RESTRICT, s, (w_restrict<C>(c->g1, r1, c->g2, c->tr[0], b2, nr, s)));
+    TIMED(c, KT_L1_RESTRICT, s, (w_restrict<C, C>(c->g1, r1, c->g2, c->tr[0], b2, nr, s)));
     // level 2: gamma visits
     C* x2 = nullptr;
     for (int v = 0; v < mg.cycle; ++v) {
@@ -845,14 +856,20 @@ struct Cycle {
       }
       C* r2 = free2(x2);
       TIMED(c, KT_L2_RESTRICT, s, (w2_step<R>(c->g2, A2c, c->r2, WM_RES, x2 == nullptr, x2, b2, (R)0, r2, nr, s)));
-      TIMED(c, KT_L2_RESTRICT, s, (w_restrict<C>(c->g2, r2, c->g3, c->tr[1], b3, nr, s)));
-      nd_solve<C>(c, w, b3, x3, 0, s);
-      if (x2 == nullptr) {          // a zero iterate: x2 = P2 x3
-        x2 = r2;
-        w_prolong<C>(c->g3, x3, c->g2, c->ip[1], 0, x2, nr, s);
+      // the coarsest solve in its own precision (FP64 for this stack)
+      if (c->nd64) {
+        TIMED(c, KT_L2_RESTRICT, s, (w_restrict<C, cd>(c->g2, r2, c->g3, c->tr[1], (cd*)w.b3, nr, s)));
+        nd_solve<cd>(c, w, (const cd*)w.b3, (cd*)w.x3, 0, s);
       } else {
-        w_prolong<C>(c->g3, x3, c->g2, c->ip[1], 1, x2, nr, s);
+        TIMED(c, KT_L2_RESTRICT, s, (w_restrict<C, cf>(c->g2, r2, c->g3, c->tr[1], (cf*)w.b3, nr, s)));
+        nd_solve<cf>(c, w, (const cf*)w.b3, (cf*)w.x3, 0, s);
       }
+      const int add = x2 != nullptr;
+      if (x2 == nullptr) x2 = r2;   // a zero iterate: x2 = P2 x3
+      if (c->nd64)
+        w_prolong<cd, C>(c->g3, (const cd*)w.x3, c->g2, c->ip[1], add, x2, nr, s);
+      else
+        w_prolong<cf, C>(c->g3, (const cf*)w.x3, c->g2, c->ip[1], add, x2, nr, s);
       for (int k = 0; k < mg.nu_post; ++k) {
         C* o = free2(x2);
         TIMED(c, KT_L2_SWEEP, s, (w2_step<R>(c->g2, A2c, c->r2, WM_JAC, 0, x2, b2, w2, o, nr, s)));
@@ -862,9 +879,9 @@ struct Cycle {
     // level 1: correction and post-relaxation; the last sweep writes `out`
     if (x1 == nullptr) {
       x1 = x1a;
-      w_prolong<C>(c->g2, x2, c->g1, c->ip[0], 0, x1, nr, s);
+      w_prolong<C, C>(c->g2, x2, c->g1, c->ip[0], 0, x1, nr, s);
     } else {
-      w_prolong<C>(c->g2, x2, c->g1, c->ip[0], 1, x1, nr, s);
+      w_prolong<C, C>(c->g2, x2, c->g1, c->ip[0], 1, x1, nr, s);
     }
     if (mg.nu_post == 0) {
       w_copy<C, CO>(x1, out, (long long)nr * c->g1.tot, s);
@@ -1521,7 +1538,7 @@ int helm_coarse_solve(helm_ctx* c, int op, const void* r, void* e, void* stream)
   hipStream_t s = (hipStream_t)stream;
   c->nr = 1;
   try {
-    if (c->f32) {
+    if (!c->nd64) {
       cast_d2f((const cd*)r, (cf*)c->scr.b3, c->g3.tot, s);
       nd_solve<cf>(c, c->scr, (const cf*)c->scr.b3, (cf*)c->scr.x3, op, s);
       cast_f2d((const cf*)c->scr.x3, (cd*)e, c->g3.tot, s);
@@ -1618,13 +1635,13 @@ int helm_get_info(helm_ctx* c, long long* out, int n) {
     sB += f.nB;
     maxF = std::max<long long>(maxF, f.nF);
   }
-  long long v[24] = {c->g1.tot, c->g2.tot, c->g3.tot, (long long)P.fronts.size(), P.L_total, P.W_total, sB,
+  long long v[25] = {c->g1.tot, c->g2.tot, c->g3.tot, (long long)P.fronts.size(), P.L_total, P.W_total, sB,
                      c->g3.tot, (long long)nd_kernels(c->nd.launch[0]), (long long)nd_kernels(c->nd.launch[1]),
                      (long long)c->ws_needed, maxF,
                      (long long)c->csz, c->nd_leaf, c->nd_root, c->tuned ? 1 : 0, (long long)P.cuts.size(),
-                     -1, -1, -1, -1, c->nd_merge, c->K2, c->K3};
+                     -1, -1, -1, -1, c->nd_merge, c->K2, c->K3, (long long)c->ndsz};
   for (size_t i = 0; i < P.cuts.size() && i < 4; ++i) v[17 + i] = P.cuts[i];
-  int m = std::min(n, 24);
+  int m = std::min(n, 25);
   for (int i = 0; i < m; ++i) out[i] = v[i];
   return m;
 }

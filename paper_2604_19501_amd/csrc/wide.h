@@ -58,12 +58,13 @@ template <typename R>
 void w2_step(const Geom& g, const typename cplx<R>::type* coef, int r, int mode, int xz,
              const typename cplx<R>::type* x, const typename cplx<R>::type* b, R w, typename cplx<R>::type* out,
              int nr, hipStream_t st);
-// out(I) = sum_i R(I, i) v(i) from grid gf onto gc
-template <typename C>
-void w_restrict(const Geom& gf, const C* v, const Geom& gc, const Transfer1D& Rt, C* out, int nr, hipStream_t st);
-// x(i) = [x(i)] + sum_J P(i, J) e(J), P = 2^d Pt^T, from gc onto gf (add: keep x)
-template <typename C>
-void w_prolong(const Geom& gc, const C* e, const Geom& gf, const Transfer1D& Pt, int add, C* x, int nr,
+// out(I) = sum_i R(I, i) v(i) from grid gf onto gc (summed in v's precision, stored in out's)
+template <typename CI, typename CO>
+void w_restrict(const Geom& gf, const CI* v, const Geom& gc, const Transfer1D& Rt, CO* out, int nr, hipStream_t st);
+// x(i) = [x(i)] + sum_J P(i, J) e(J), P = 2^d Pt^T, from gc onto gf (add: keep x); summed in
+// x's precision
+template <typename CE, typename C>
+void w_prolong(const Geom& gc, const CE* e, const Geom& gf, const Transfer1D& Pt, int add, C* x, int nr,
                hipStream_t st);
 // out = in, converted to out's precision (n entries)
 template <typename CI, typename CO>

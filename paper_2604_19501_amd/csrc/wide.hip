@@ -223,9 +223,9 @@ __global__ void __launch_bounds__(256) k_w2(Geom g, const typename cplx<R>::type
   out[off + f] = v;
 }
 
-template <int DIM, typename C>
+template <int DIM, typename C, typename CO>
 __global__ void __launch_bounds__(256) k_wrestrict(Geom gf, const C* __restrict__ v, Geom gc, Transfer1D Rt,
-                                                   C* __restrict__ out) {
+                                                   CO* __restrict__ out) {
   typedef decltype(v[0].x) R;
   const long long I = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (I >= gc.tot) return;
@@ -249,13 +249,13 @@ __global__ void __launch_bounds__(256) k_wrestrict(Geom gf, const C* __restrict_
         acc += (w1 * (R)Rt.w[i0 - 2 * Ia[0] + a]) * v[i0 + i1 * s1 + i2 * s2];
     }
   }
-  out[I] = acc;
+  out[I] = conv<CO>::from(acc);
 }
 
-template <int DIM, typename C>
-__global__ void __launch_bounds__(256) k_wprolong(Geom gc, const C* __restrict__ e, Geom gf, Transfer1D Pt, int add,
+template <int DIM, typename CE, typename C>
+__global__ void __launch_bounds__(256) k_wprolong(Geom gc, const CE* __restrict__ e, Geom gf, Transfer1D Pt, int add,
                                                   C* __restrict__ x) {
-  typedef decltype(e[0].x) R;
+  typedef decltype(x[0].x) R;
   const long long f = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= gf.tot) return;
   e += (long long)blockIdx.y * gc.tot;
@@ -275,7 +275,7 @@ __global__ void __launch_bounds__(256) k_wprolong(Geom gc, const C* __restrict__
     for (int J1 = lo[1]; J1 <= hi[1]; ++J1) {
       const R w1 = w2 * (R)(2.0 * Pt.w[ia[1] - 2 * J1 + a]);
       for (int J0 = lo[0]; J0 <= hi[0]; ++J0)
-        acc += (w1 * (R)(2.0 * Pt.w[ia[0] - 2 * J0 + a])) * e[J0 + J1 * s1 + J2 * s2];
+        acc += (w1 * (R)(2.0 * Pt.w[ia[0] - 2 * J0 + a])) * conv<C>::from(e[J0 + J1 * s1 + J2 * s2]);
     }
   }
   x[f] = add ? x[f] + acc : acc;
@@ -357,23 +357,23 @@ void w2_step(const Geom& g, const typename cplx<R>::type* coef, int r, int mode,
     throw std::runtime_error("w2_step: no kernel for this dimension and stencil radius");
 }
 
-template <typename C>
-void w_restrict(const Geom& gf, const C* v, const Geom& gc, const Transfer1D& Rt, C* out, int nr, hipStream_t st) {
+template <typename CI, typename CO>
+void w_restrict(const Geom& gf, const CI* v, const Geom& gc, const Transfer1D& Rt, CO* out, int nr, hipStream_t st) {
   const dim3 grid = grid1(gc.tot, nr);
   if (gf.dim == 3)
-    hipLaunchKernelGGL((k_wrestrict<3, C>), grid, dim3(256), 0, st, gf, v, gc, Rt, out);
+    hipLaunchKernelGGL((k_wrestrict<3, CI, CO>), grid, dim3(256), 0, st, gf, v, gc, Rt, out);
   else
-    hipLaunchKernelGGL((k_wrestrict<2, C>), grid, dim3(256), 0, st, gf, v, gc, Rt, out);
+    hipLaunchKernelGGL((k_wrestrict<2, CI, CO>), grid, dim3(256), 0, st, gf, v, gc, Rt, out);
 }
 
-template <typename C>
-void w_prolong(const Geom& gc, const C* e, const Geom& gf, const Transfer1D& Pt, int add, C* x, int nr,
+template <typename CE, typename C>
+void w_prolong(const Geom& gc, const CE* e, const Geom& gf, const Transfer1D& Pt, int add, C* x, int nr,
                hipStream_t st) {
   const dim3 grid = grid1(gf.tot, nr);
   if (gf.dim == 3)
-    hipLaunchKernelGGL((k_wprolong<3, C>), grid, dim3(256), 0, st, gc, e, gf, Pt, add, x);
+    hipLaunchKernelGGL((k_wprolong<3, CE, C>), grid, dim3(256), 0, st, gc, e, gf, Pt, add, x);
   else
-    hipLaunchKernelGGL((k_wprolong<2, C>), grid, dim3(256), 0, st, gc, e, gf, Pt, add, x);
+    hipLaunchKernelGGL((k_wprolong<2, CE, C>), grid, dim3(256), 0, st, gc, e, gf, Pt, add, x);
 }
 
 template <typename CI, typename CO>
@@ -389,10 +389,14 @@ template void w1_step<double, cd, cd>(const WFine<double>&, int, int, const cd*,
 template void w2_step<float>(const Geom&, const cf*, int, int, int, const cf*, const cf*, float, cf*, int, hipStream_t);
 template void w2_step<double>(const Geom&, const cd*, int, int, int, const cd*, const cd*, double, cd*, int,
                               hipStream_t);
-template void w_restrict<cf>(const Geom&, const cf*, const Geom&, const Transfer1D&, cf*, int, hipStream_t);
-template void w_restrict<cd>(const Geom&, const cd*, const Geom&, const Transfer1D&, cd*, int, hipStream_t);
-template void w_prolong<cf>(const Geom&, const cf*, const Geom&, const Transfer1D&, int, cf*, int, hipStream_t);
-template void w_prolong<cd>(const Geom&, const cd*, const Geom&, const Transfer1D&, int, cd*, int, hipStream_t);
+template void w_restrict<cf, cf>(const Geom&, const cf*, const Geom&, const Transfer1D&, cf*, int, hipStream_t);
+template void w_restrict<cf, cd>(const Geom&, const cf*, const Geom&, const Transfer1D&, cd*, int, hipStream_t);
+template void w_restrict<cd, cd>(const Geom&, const cd*, const Geom&, const Transfer1D&, cd*, int, hipStream_t);
+template void w_restrict<cd, cf>(const Geom&, const cd*, const Geom&, const Transfer1D&, cf*, int, hipStream_t);
+template void w_prolong<cf, cf>(const Geom&, const cf*, const Geom&, const Transfer1D&, int, cf*, int, hipStream_t);
+template void w_prolong<cd, cf>(const Geom&, const cd*, const Geom&, const Transfer1D&, int, cf*, int, hipStream_t);
+template void w_prolong<cd, cd>(const Geom&, const cd*, const Geom&, const Transfer1D&, int, cd*, int, hipStream_t);
+template void w_prolong<cf, cd>(const Geom&, const cf*, const Geom&, const Transfer1D&, int, cd*, int, hipStream_t);
 template void w_copy<cf, cf>(const cf*, cf*, long long, hipStream_t);
 template void w_copy<cf, cd>(const cf*, cd*, long long, hipStream_t);
 template void w_copy<cd, cd>(const cd*, cd*, long long, hipStream_t);

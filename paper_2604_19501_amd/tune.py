@@ -101,9 +101,12 @@ def coarsest_radius(stack="p5", transfer=None):
 
 
 def cache_key(n, prec, stack="p5", transfer=None):
+    """the library's key: grid, the coarsest solve's precision (the cycle's for the 5/7-point
+    stack; FP64 for the compact stack, whose coarsest factors are always FP64) and radius"""
     dim = len(n)
     r = coarsest_radius(stack, transfer)
-    return "nd:%d:%s:%s%s" % (dim, "x".join(str(k) for k in (tuple(n) + (0,) * (3 - dim))), prec,
+    nd_prec = "f64" if stack == "compact" else prec
+    return "nd:%d:%s:%s%s" % (dim, "x".join(str(k) for k in (tuple(n) + (0,) * (3 - dim))), nd_prec,
                               ":r%d" % r if r != 1 else "")
 
 

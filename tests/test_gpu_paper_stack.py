@@ -176,6 +176,41 @@ def test_3d_layered_stand_in_of_table_5(G):
     s.close()
 
 
+def _apply_planes(A, nl, r, x):
+    """y = A x for an operator stored as planes of radius r on a 2D grid of nl cells"""
+    Ns = [k + 1 for k in nl]
+    X = x.reshape(Ns[1], Ns[0])
+    y = np.zeros_like(X)
+    k = 0
+    for d1 in range(-r, r + 1):
+        for d0 in range(-r, r + 1):
+            sh = np.zeros_like(X)
+            sh[max(0, -d1):Ns[1] - max(0, d1), max(0, -d0):Ns[0] - max(0, d0)] = \
+                X[max(0, d1):Ns[1] + min(0, d1), max(0, d0):Ns[0] + min(0, d0)]
+            y += A[k].reshape(X.shape) * sh
+            k += 1
+    return y.ravel()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_compact_coarse_solve_full_size(prec):
+    """the 49-point coarsest operator of the 1024^2 problem (257^2 nodes; alpha* = 1.0045
+    leaves it close to singular): the exact solve's relative residual, under the stored
+    coefficients (pinned against the oracle at small sizes), with either cycle precision
+    (the coarsest factors are FP64 for this stack)"""
+    p = synth.paper_stack((1024, 1024), "cubic")
+    print("compact coarse full size", prec, flush=True)
+    s = from_problem(p, cycle_prec=prec)
+    assert s.info()["coarse_complex_bytes"] == 16
+    A3 = s.coefficients(3)
+    r = _rand(s.level_size(3), 9)
+    e = s.coarse_solve(r).cpu().numpy()
+    res = np.linalg.norm(_apply_planes(A3, (256, 256), 3, e) - r) / np.linalg.norm(r)
+    print("  relative residual %.3e" % res, flush=True)
+    assert res < 1e-6
+    s.close()
+
+
 def test_compact_refuses_the_adjoint():
     p = _problem((32, 32), "cubic")
     s = from_problem(p, cycle_prec="f64")
