@@ -58,13 +58,16 @@ __device__ __forceinline__ long long node_of(int q) {
   return ((long long)blockIdx.x * KNPT + q) * 256 + threadIdx.x;
 }
 
-template <typename CX>
+// CMP: the compact fourth-order operator (no conjugate form), a separate instantiation of
+// every kernel that applies H: inlined into the 5/7-point kernels as a run-time branch it
+// raised their register count from 116 to 152 and added a stack frame
+template <int CMP, typename CX>
 __device__ __forceinline__ cd apply_h(const KrylovArgs& a, const CX* __restrict__ x, long long f) {
   const Geom& g = a.op.g;
   int i0 = (int)(f % g.N[0]);
   long long r = f / g.N[0];
   int i1 = (int)(r % g.N[1]), i2 = (int)(r / g.N[1]);
-  if (a.op.compact) {          // the compact fourth-order operator (no conjugate form)
+  if constexpr (CMP) {
     cd dg;
     return g.dim == 3 ? wide_row<3, double, CX>(a.op, a.s, a.m64, x, f, i0, i1, i2, false, dg)
                       : wide_row<2, double, CX>(a.op, a.s, a.m64, x, f, i0, i1, i2, false, dg);
@@ -100,7 +103,7 @@ __device__ __forceinline__ void store_partials(cd (*red)[2 * KMAXM + 3], int nv,
 // w = H z_j (FP64); partials of <V_i, w> (values 0..j), <V_i, V_j> (values j+1..2j+1) and
 // ||w||^2 (value 2j+2, real part).  Nodes past the end are clamped to the last node and
 // weighted 0; basis vector i + 1 is loaded while vector i is reduced.
-template <typename CZ>
+template <typename CZ, int CMP>
 __global__ void __launch_bounds__(256) k_arnoldi_dots(KrylovArgs a, const CZ* __restrict__ z, int j) {
   __shared__ cd red[4][2 * KMAXM + 3];
   const RhsPtr p = at_rhs(a);
@@ -122,7 +125,7 @@ __global__ void __launch_bounds__(256) k_arnoldi_dots(KrylovArgs a, const CZ* __
   }
   double nw = 0.0;
   for (int q = 0; q < KNPT; ++q) {
-    w[q] = on[q] * apply_h(a, z, f[q]);
+    w[q] = on[q] * apply_h<CMP>(a, z, f[q]);
     nw += abs2(w[q]);
   }
   for (int i = 0; i <= j; ++i) {
@@ -148,6 +151,7 @@ __global__ void __launch_bounds__(256) k_arnoldi_dots(KrylovArgs a, const CZ* __
 }
 
 // r = b - H x (FP64) into V_0; partials of (||r||^2, ||b||^2) in slot 0
+template <int CMP>
 __global__ void __launch_bounds__(256) k_residual(KrylovArgs a, const cd* __restrict__ x,
                                                   const cd* __restrict__ b) {
   __shared__ cd lds[4];
@@ -159,7 +163,7 @@ __global__ void __launch_bounds__(256) k_residual(KrylovArgs a, const cd* __rest
   for (int q = 0; q < KNPT; ++q) {
     long long f = node_of(q);
     if (f < N) {
-      cd res = b[f] - apply_h(a, x, f);
+      cd res = b[f] - apply_h<CMP>(a, x, f);
       p.V[f] = res;
       v += mk(abs2(res), abs2(b[f]));
     }
@@ -309,7 +313,7 @@ __global__ void __launch_bounds__(64) k_givens(KrylovArgs a, int j, double tol) 
 // the most likely to still be in the memory-side cache.  This pass is the basis's last
 // reader in the iteration: its loads are non-temporal, so that they do not displace the
 // data the next iteration's cycle reuses (the coarsest factors, the level-2 coefficients).
-template <typename CZ>
+template <typename CZ, int CMP>
 __global__ void __launch_bounds__(256) k_arnoldi_update(KrylovArgs a, const CZ* __restrict__ z, int j) {
   __shared__ cd sc[KMAXM + 1];
   __shared__ double sinv;
@@ -329,7 +333,7 @@ __global__ void __launch_bounds__(256) k_arnoldi_update(KrylovArgs a, const CZ* 
   }
   cd w[KNPT], nx[KNPT];
   for (int q = 0; q < KNPT; ++q) nx[q] = ld_nt(p.V + f[q]);
-  for (int q = 0; q < KNPT; ++q) w[q] = apply_h(a, z, f[q]);
+  for (int q = 0; q < KNPT; ++q) w[q] = apply_h<CMP>(a, z, f[q]);
   __syncthreads();
   for (int i = 0; i <= j; ++i) {
     cd vi[KNPT];
@@ -473,7 +477,10 @@ void kr_init(const KrylovArgs& a, int max_iter, hipStream_t s) {
   hipLaunchKernelGGL(k_init_state, dim3(1, a.nrhs), dim3(1), 0, s, a.st, max_iter);
 }
 void kr_residual(const KrylovArgs& a, const cd* x, const cd* b, int with_b, hipStream_t s) {
-  hipLaunchKernelGGL(k_residual, dim3(a.nblk, a.nrhs), dim3(256), 0, s, a, x, b);
+  if (a.op.compact)
+    hipLaunchKernelGGL((k_residual<1>), dim3(a.nblk, a.nrhs), dim3(256), 0, s, a, x, b);
+  else
+    hipLaunchKernelGGL((k_residual<0>), dim3(a.nblk, a.nrhs), dim3(256), 0, s, a, x, b);
   hipLaunchKernelGGL(k_fin_sum, dim3(1, a.nrhs), dim3(256), 0, s, a, offsetof(KrylovState, tmp));
   hipLaunchKernelGGL(k_fin_residual, dim3(1, a.nrhs), dim3(1), 0, s, a, with_b);
 }
@@ -482,16 +489,25 @@ void kr_scale_v0(const KrylovArgs& a, hipStream_t s) {
 }
 void kr_arnoldi(const KrylovArgs& a, const void* z, int z_f32, int j, double tol, hipStream_t s) {
   dim3 g(a.nblk, a.nrhs);
-  if (z_f32)
-    hipLaunchKernelGGL((k_arnoldi_dots<cf>), g, dim3(256), 0, s, a, (const cf*)z, j);
+  const int cmp = a.op.compact;
+  if (z_f32 && !cmp)
+    hipLaunchKernelGGL((k_arnoldi_dots<cf, 0>), g, dim3(256), 0, s, a, (const cf*)z, j);
+  else if (!cmp)
+    hipLaunchKernelGGL((k_arnoldi_dots<cd, 0>), g, dim3(256), 0, s, a, (const cd*)z, j);
+  else if (z_f32)
+    hipLaunchKernelGGL((k_arnoldi_dots<cf, 1>), g, dim3(256), 0, s, a, (const cf*)z, j);
   else
-    hipLaunchKernelGGL((k_arnoldi_dots<cd>), g, dim3(256), 0, s, a, (const cd*)z, j);
+    hipLaunchKernelGGL((k_arnoldi_dots<cd, 1>), g, dim3(256), 0, s, a, (const cd*)z, j);
   hipLaunchKernelGGL(k_fin_sum, dim3(2 * j + 3, a.nrhs), dim3(256), 0, s, a, offsetof(KrylovState, h1));
   hipLaunchKernelGGL(k_givens, dim3(1, a.nrhs), dim3(64), 0, s, a, j, tol);
-  if (z_f32)
-    hipLaunchKernelGGL((k_arnoldi_update<cf>), g, dim3(256), 0, s, a, (const cf*)z, j);
+  if (z_f32 && !cmp)
+    hipLaunchKernelGGL((k_arnoldi_update<cf, 0>), g, dim3(256), 0, s, a, (const cf*)z, j);
+  else if (!cmp)
+    hipLaunchKernelGGL((k_arnoldi_update<cd, 0>), g, dim3(256), 0, s, a, (const cd*)z, j);
+  else if (z_f32)
+    hipLaunchKernelGGL((k_arnoldi_update<cf, 1>), g, dim3(256), 0, s, a, (const cf*)z, j);
   else
-    hipLaunchKernelGGL((k_arnoldi_update<cd>), g, dim3(256), 0, s, a, (const cd*)z, j);
+    hipLaunchKernelGGL((k_arnoldi_update<cd, 1>), g, dim3(256), 0, s, a, (const cd*)z, j);
 }
 void kr_update_x(const KrylovArgs& a, const void* Z, int z_f32, long long ldz, cd* x, hipStream_t s) {
   hipLaunchKernelGGL(k_solve_y, dim3(1, a.nrhs), dim3(1), 0, s, a);

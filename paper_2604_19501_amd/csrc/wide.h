@@ -70,6 +70,17 @@ void w_prolong(const Geom& gc, const CE* e, const Geom& gf, const Transfer1D& Pt
 template <typename CI, typename CO>
 void w_copy(const CI* in, CO* out, long long n, hipStream_t st);
 
+// the absorbing layer's squared depth term on axis A at index i (the summand of
+// layer_sigma for that axis), in the arithmetic of R
+template <typename R, int A>
+__device__ __forceinline__ R layer_t2(const FineOp& op, int i) {
+  const R wl = sizeof(R) == 4 ? (R)op.inv_wf[A][0] : (R)op.inv_w[A][0];
+  const R wh = sizeof(R) == 4 ? (R)op.inv_wf[A][1] : (R)op.inv_w[A][1];
+  const R tl = (R)max(op.layer[A][0] - i, 0) * wl;
+  const R th = (R)max(i - op.inner_hi[A], 0) * wh;
+  return tl * tl + th * th;
+}
+
 // Row f (node i0, i1, i2) of the fine compact operator with coefficient scalar s, applied
 // to x (any precision) in the arithmetic of R; dg receives the diagonal L_ff - M_ff c_f.
 // xz: x is zero (only dg is computed).  Neighbours outside the grid are read at f and
@@ -87,8 +98,30 @@ __device__ __forceinline__ typename cplx<R>::type wide_row(const FineOp& op, typ
   const R lf = DIM == 3 ? (R)-2 : (R)-4;                       // L: faces
   const R mc = DIM == 3 ? (R)(6.0 / 12.0) : (R)(8.0 / 12.0);   // M: centre
   const R mf = (R)(1.0 / 12.0);                                // M: faces
+  // sigma at the node and its face neighbours from per-axis terms (a face neighbour differs
+  // in one axis), summed in axis order as layer_sigma does
+  const R smax = (R)op.sigma_max;
+  R tc[3], tm[3], tp[3];
+  tc[0] = layer_t2<R, 0>(op, i0);
+  tm[0] = layer_t2<R, 0>(op, i0 - 1);
+  tp[0] = layer_t2<R, 0>(op, i0 + 1);
+  tc[1] = layer_t2<R, 1>(op, i1);
+  tm[1] = layer_t2<R, 1>(op, i1 - 1);
+  tp[1] = layer_t2<R, 1>(op, i1 + 1);
+  tc[2] = tm[2] = tp[2] = (R)0;
+  if (DIM == 3) {
+    tc[2] = layer_t2<R, 2>(op, i2);
+    tm[2] = layer_t2<R, 2>(op, i2 - 1);
+    tp[2] = layer_t2<R, 2>(op, i2 + 1);
+  }
+  auto sig = [&](int ax, int dir) -> R {     // ax < 0: the node itself
+    R t = (R)0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) t += a != ax ? tc[a] : (dir < 0 ? tm[a] : tp[a]);
+    return smax * t;
+  };
   const R mm0 = m[f];
-  const C c0 = s * mk(mm0, -mm0 * layer_sigma_r<R>(op, i0, i1, i2));
+  const C c0 = s * mk(mm0, -mm0 * sig(-1, 0));
   dg = mk(lc * ih - mc * c0.x, -mc * c0.y);
   C acc = mk((R)0, (R)0);
   if (xz) return acc;
@@ -109,7 +142,8 @@ __device__ __forceinline__ typename cplx<R>::type wide_row(const FineOp& op, typ
         const R on = in ? (R)1 : (R)0;
         if (nz == 1) {                              // face: L and M entries
           const R mj = m[j];
-          const C cj = s * mk(mj, -mj * layer_sigma_r<R>(op, a0, a1, a2));
+          const int ax = d0 != 0 ? 0 : d1 != 0 ? 1 : 2, dir = d0 + d1 + d2;
+          const C cj = s * mk(mj, -mj * sig(ax, dir));
           const C a = mk(lf * ih - mf * cj.x, -mf * cj.y);
           acc += on * (a * xv);
         } else {                                    // 2D corner / 3D edge: L only (-1)

@@ -192,7 +192,9 @@ __global__ void __launch_bounds__(256) k_w2(Geom g, const typename cplx<R>::type
   const C dg = coef[(long long)KC * g.tot + f];
   C ax = mk((R)0, (R)0);
   if (!xz) {
-#pragma unroll
+    // one plane of (2 RAD + 1)^2 taps in flight at a time: the fully unrolled 125-tap 3D
+    // loop needed 512 registers and spilled
+#pragma unroll 1
     for (int d2 = (DIM == 3 ? -RAD : 0); d2 <= (DIM == 3 ? RAD : 0); ++d2)
 #pragma unroll
       for (int d1 = -RAD; d1 <= RAD; ++d1) {
