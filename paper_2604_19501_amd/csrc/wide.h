@@ -53,7 +53,8 @@ enum : int { WM_RES = 0, WM_JAC = 1, WM_APPLY = 2 };
 template <typename R, typename CB, typename CO>
 void w1_step(const WFine<R>& A, int mode, int xz, const typename cplx<R>::type* x, const CB* b, R w, CO* out,
              int nr, hipStream_t st);
-// levels 2 and 3 (planes of radius r in precision R): the same three modes
+// level 2 (planes of radius r = 2, the compact stack's level-2 operator, in precision R): the
+// same three modes
 template <typename R>
 void w2_step(const Geom& g, const typename cplx<R>::type* coef, int r, int mode, int xz,
              const typename cplx<R>::type* x, const typename cplx<R>::type* b, R w, typename cplx<R>::type* out,

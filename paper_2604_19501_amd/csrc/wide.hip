@@ -353,8 +353,6 @@ void w2_step(const Geom& g, const typename cplx<R>::type* coef, int r, int mode,
     hipLaunchKernelGGL((k_w2<3, 2, R>), grid, dim3(256), 0, st, g, coef, mode, xz, x, b, w, out);
   else if (g.dim == 2 && r == 2)
     hipLaunchKernelGGL((k_w2<2, 2, R>), grid, dim3(256), 0, st, g, coef, mode, xz, x, b, w, out);
-  else if (g.dim == 2 && r == 3)
-    hipLaunchKernelGGL((k_w2<2, 3, R>), grid, dim3(256), 0, st, g, coef, mode, xz, x, b, w, out);
   else
     throw std::runtime_error("w2_step: no kernel for this dimension and stencil radius");
 }
