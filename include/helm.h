@@ -282,7 +282,9 @@ int helm_get_timing(helm_ctx* ctx, double* t, int n);
  * the dissection-tree heights whose fronts were merged into their parents, [22] and [23]
  * coefficient planes of the stored level-2 and level-3 operators ((2r+1)^dim for stencil
  * radius r: 9 / 27 for the 5/7-point stack), [24] bytes per complex of the coarsest solve's
- * factors and vectors (the cycle's precision; 16 for the compact stack).
+ * factors and vectors (the cycle's precision; 16 for the compact stack), [25..28] box-shape
+ * variants of the tiled level-1 sweep, level-1 restriction, level-2 sweep and level-2
+ * restriction kernels (5/7-point stack; HELM_BOXES or the autotuner's cache).
  * Returns the number of entries written (at most n). */
 int helm_get_info(helm_ctx* ctx, long long* out, int n);
 

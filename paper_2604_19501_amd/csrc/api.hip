@@ -198,6 +198,9 @@ struct helm_ctx {
   Transfer1D tr[2], ip[2];
   int r2 = 1, r3 = 1, K2 = 9, K3 = 9;
   long long nd_merge = 0;        // bit h: fronts of dissection height h merged into their parents
+  // box-shape variants of the tiled cycle kernels: level-1 sweep, level-1 restriction,
+  // level-2 sweep, level-2 restriction (levels.hip lists the shapes)
+  int box[4] = {0, 0, 0, 0};
   std::vector<helm_ctx*> sub;   // batched form: one context per instance
   std::vector<hipStream_t> bstreams;   // batched form: streams of the concurrent instances
   // one captured graph per (operator, Arnoldi index j): cycle on V_j + Arnoldi step
@@ -324,8 +327,8 @@ int env_int(const char* name, int dflt) {
 // or the key is absent
 struct TunedND {
   int leaf = -1, root = -1, splitk_kb = -1;
-  std::string cuts, merge;
-  bool has_cuts = false, has_merge = false;
+  std::string cuts, merge, boxes;
+  bool has_cuts = false, has_merge = false, has_boxes = false;
 };
 bool tuned_nd(const helm_ctx* c, TunedND& t) {
   const char* path = getenv("HELM_TUNE_CACHE");
@@ -367,6 +370,7 @@ bool tuned_nd(const helm_ctx* c, TunedND& t) {
   };
   str("\"cuts\"", t.cuts, t.has_cuts);
   str("\"merge\"", t.merge, t.has_merge);
+  str("\"boxes\"", t.boxes, t.has_boxes);
   return true;
 }
 
@@ -408,6 +412,17 @@ void build_plan(helm_ctx* c) {
     const char* v = getenv("HELM_ND_MERGE");
     std::string mv = v ? std::string(v) : (tuned && tn.has_merge ? tn.merge : std::string());
     if (!mv.empty() && mv != "none") mh = parse_cuts(mv.c_str());
+  }
+  // box variants of the cycle kernels: "a,b,c,d" (HELM_BOXES, else the cache; default 0)
+  {
+    const char* v = getenv("HELM_BOXES");
+    std::string bv = v ? std::string(v) : (tuned && tn.has_boxes ? tn.boxes : std::string());
+    std::vector<int> bx = bv.empty() ? std::vector<int>() : parse_cuts(bv.c_str());
+    for (int q = 0; q < 4; ++q) {
+      c->box[q] = q < (int)bx.size() ? bx[q] : 0;
+      const int nmax = (q % 2 == 0) ? 4 : 3;     // sweeps: 4 variants, restrictions: 3
+      if (c->box[q] < 0 || c->box[q] >= nmax) throw std::runtime_error("HELM_BOXES: variant out of range");
+    }
   }
   c->nd_merge = 0;
   for (int h : mh) {
@@ -798,9 +813,13 @@ struct Cycle {
     A1.m = (const R*)(sizeof(R) == 4 ? (const void*)c->m32 : (const void*)c->m64);
     A1.conj = op;
     A1.dg = (const C*)(sizeof(R) == 4 ? (const void*)c->dg32 : nullptr);
+    A1.box_sweep = c->box[0];
+    A1.box_restrict = c->box[1];
     A2.g = c->g2;
     A2.coef = (const C*)(sizeof(R) == 4 ? (const void*)c->coef2_32 : (const void*)c->coef2_64);
     A2.conj = op;
+    A2.box_sweep = c->box[2];
+    A2.box_restrict = c->box[3];
   }
 
   // level 1: one more sweep (or the virtual first sweep) on state st
@@ -1635,13 +1654,14 @@ int helm_get_info(helm_ctx* c, long long* out, int n) {
     sB += f.nB;
     maxF = std::max<long long>(maxF, f.nF);
   }
-  long long v[25] = {c->g1.tot, c->g2.tot, c->g3.tot, (long long)P.fronts.size(), P.L_total, P.W_total, sB,
+  long long v[29] = {c->g1.tot, c->g2.tot, c->g3.tot, (long long)P.fronts.size(), P.L_total, P.W_total, sB,
                      c->g3.tot, (long long)nd_kernels(c->nd.launch[0]), (long long)nd_kernels(c->nd.launch[1]),
                      (long long)c->ws_needed, maxF,
                      (long long)c->csz, c->nd_leaf, c->nd_root, c->tuned ? 1 : 0, (long long)P.cuts.size(),
-                     -1, -1, -1, -1, c->nd_merge, c->K2, c->K3, (long long)c->ndsz};
+                     -1, -1, -1, -1, c->nd_merge, c->K2, c->K3, (long long)c->ndsz,
+                     c->box[0], c->box[1], c->box[2], c->box[3]};
   for (size_t i = 0; i < P.cuts.size() && i < 4; ++i) v[17 + i] = P.cuts[i];
-  int m = std::min(n, 25);
+  int m = std::min(n, 29);
   for (int i = 0; i < m; ++i) out[i] = v[i];
   return m;
 }

@@ -67,15 +67,24 @@ __device__ __forceinline__ int flat(const Geom& g, int i0, int i1, int i2) {
 // values one node outside); the stored coarse coefficients that point outside
 // are zero as well.
 //
-// Box shapes (threads = 256):
-//   sweeps       2D 32 x 16            3D 32 x 8 x 4
-//   restrictions 2D 16 x 8 coarse      3D 8 x 4 x 4 coarse
-template <int DIM> struct SBox {
-  static constexpr int x = 32, y = DIM == 2 ? 16 : 8, z = DIM == 2 ? 1 : 4;
+// Box shapes (threads = 256), chosen per context (L1/L2::box_sweep, box_restrict; the
+// autotuner picks them), variant 0 the default:
+//   sweeps       2D 32 x 16, 64 x 8, 64 x 16, 32 x 32
+//                3D 32 x 8 x 4, 32 x 8 x 8, 64 x 8 x 4, 32 x 16 x 4
+//   restrictions 2D 16 x 8, 32 x 8, 16 x 16 coarse
+//                3D 8 x 4 x 4, 16 x 4 x 4, 8 x 8 x 4 coarse
+// The FP64 cycle keeps variant 0 in 3D (the others exceed the block's LDS).
+template <int DIM, int V> struct SBox {
+  static constexpr int x = DIM == 2 ? (V == 0 || V == 3 ? 32 : 64) : (V == 2 ? 64 : 32);
+  static constexpr int y = DIM == 2 ? (V == 0 ? 16 : V == 1 ? 8 : V == 2 ? 16 : 32) : (V == 3 ? 16 : 8);
+  static constexpr int z = DIM == 2 ? 1 : (V == 1 ? 8 : 4);
 };
-template <int DIM, int CSZ> struct RBox {
-  static constexpr int x = DIM == 2 ? 16 : 8, y = DIM == 2 ? 8 : 4, z = DIM == 2 ? 1 : 4;
+template <int DIM, int V> struct RBox {
+  static constexpr int x = DIM == 2 ? (V == 1 ? 32 : 16) : (V == 1 ? 16 : 8);
+  static constexpr int y = DIM == 2 ? (V == 2 ? 16 : 8) : (V == 2 ? 8 : 4);
+  static constexpr int z = DIM == 2 ? 1 : 4;
 };
+constexpr int N_SBOX = 4, N_RBOX = 3;
 
 // level-1 operator H_s with x from LDS (centre index k, strides sy, sz).  The FP32 cycle
 // reads its diagonal from the array precomputed at set-up (one 8-byte load per node instead
@@ -261,14 +270,14 @@ __device__ __forceinline__ void stage_xin(const Op& op, const C* __restrict__ x,
 
 // x_out = x_in + w D^{-1}(b - A x_in) on one box (w = 0: materialise x_in).  The output
 // nodes' b and D are loaded before the staging barriers, so their latency overlaps it.
-template <int DIM, class Op, typename CB, typename CO, int XIN>
+template <int DIM, class Op, typename CB, typename CO, int XIN, int BV>
 __global__ void __launch_bounds__(256) k_sweep(Op op, const typename Op::C* __restrict__ x,
                                                const CB* __restrict__ b, typename Op::Real w_in, Geom gc,
                                                const typename Op::C* __restrict__ e,
                                                typename Op::Real w, CO* __restrict__ out, TileGrid tg) {
   typedef typename Op::C C;
   typedef typename Op::Real R;
-  constexpr int TX = SBox<DIM>::x, TY = SBox<DIM>::y, TZ = SBox<DIM>::z;
+  constexpr int TX = SBox<DIM, BV>::x, TY = SBox<DIM, BV>::y, TZ = SBox<DIM, BV>::z;
   constexpr int SX = TX + 2, SY = TY + 2, SZ = DIM == 3 ? TZ + 2 : 1;
   constexpr int EX = TX / 2 + 3, EY = TY / 2 + 3, EZ = DIM == 3 ? TZ / 2 + 3 : 1;
   constexpr int NOUT = TX * TY * TZ / 256;
@@ -363,13 +372,13 @@ __global__ void __launch_bounds__(256) k_sweep(Op op, const typename Op::C* __re
 }
 
 // b_c(I) = sum_f R(I, f) (b - A x_in)(f), full weighting [1 2 1]/4 per axis, one coarse box
-template <int DIM, class Op, typename CB, int XIN>
+template <int DIM, class Op, typename CB, int XIN, int BV>
 __global__ void __launch_bounds__(256) k_restrict(Op op, const typename Op::C* __restrict__ x,
                                                   const CB* __restrict__ b, typename Op::Real w_in,
                                                   Geom g2, typename Op::C* __restrict__ b2, TileGrid tg) {
   typedef typename Op::C C;
   typedef typename Op::Real R;
-  constexpr int CX = RBox<DIM, sizeof(C)>::x, CY = RBox<DIM, sizeof(C)>::y, CZ = RBox<DIM, sizeof(C)>::z;
+  constexpr int CX = RBox<DIM, BV>::x, CY = RBox<DIM, BV>::y, CZ = RBox<DIM, BV>::z;
   constexpr int RX = 2 * CX + 1, RY = 2 * CY + 1, RZ = DIM == 3 ? 2 * CZ + 1 : 1;
   constexpr int SX = RX + 2, SY = RY + 2, SZ = DIM == 3 ? RZ + 2 : 1;
   constexpr int RT = RX * RY * RZ, NR = (RT + 255) / 256;
@@ -531,12 +540,13 @@ static inline TileGrid tiles(const Geom& g, int bx, int by, int bz) {
 }
 static inline unsigned grid_tiles(const TileGrid& t) { return (unsigned)((t.ntiles + 7) / 8 * 8); }
 
-template <int DIM, class Op, typename CB, typename CO>
-void sweep_dim(const Op& op, int xin, const typename Op::C* x, const CB* b, typename Op::Real w_in,
+template <int DIM, class Op, typename CB, typename CO, int BV>
+void sweep_box(const Op& op, int xin, const typename Op::C* x, const CB* b, typename Op::Real w_in,
                const Geom& gc, const typename Op::C* e, typename Op::Real w, CO* out, int nrhs, hipStream_t s) {
-  TileGrid tg = tiles(op.geom(), SBox<DIM>::x, SBox<DIM>::y, SBox<DIM>::z);
+  TileGrid tg = tiles(op.geom(), SBox<DIM, BV>::x, SBox<DIM, BV>::y, SBox<DIM, BV>::z);
   dim3 grid(grid_tiles(tg), nrhs), blk(256);
-#define SW(F) hipLaunchKernelGGL((k_sweep<DIM, Op, CB, CO, F>), grid, blk, 0, s, op, x, b, w_in, gc, e, w, out, tg)
+#define SW(F) \
+  hipLaunchKernelGGL((k_sweep<DIM, Op, CB, CO, F, BV>), grid, blk, 0, s, op, x, b, w_in, gc, e, w, out, tg)
   switch (xin) {
     case 0: SW(0); break;
     case XIN_X: SW(XIN_X); break;
@@ -549,13 +559,29 @@ void sweep_dim(const Op& op, int xin, const typename Op::C* x, const CB* b, type
 #undef SW
 }
 
-template <int DIM, class Op, typename CB>
-void restrict_dim(const Op& op, int xin, const typename Op::C* x, const CB* b, typename Op::Real w_in,
+template <int DIM, class Op, typename CB, typename CO>
+void sweep_dim(const Op& op, int xin, const typename Op::C* x, const CB* b, typename Op::Real w_in,
+               const Geom& gc, const typename Op::C* e, typename Op::Real w, CO* out, int nrhs, hipStream_t s) {
+  // the FP64 cycle's 3D boxes stay at variant 0 (the larger ones exceed the block's LDS)
+  const int v = (DIM == 3 && sizeof(typename Op::C) == 16) ? 0 : op.A.box_sweep;
+  if constexpr (DIM == 3 && sizeof(typename Op::C) == 16) {
+    sweep_box<DIM, Op, CB, CO, 0>(op, xin, x, b, w_in, gc, e, w, out, nrhs, s);
+  } else {
+    switch (v) {
+      case 1: sweep_box<DIM, Op, CB, CO, 1>(op, xin, x, b, w_in, gc, e, w, out, nrhs, s); break;
+      case 2: sweep_box<DIM, Op, CB, CO, 2>(op, xin, x, b, w_in, gc, e, w, out, nrhs, s); break;
+      case 3: sweep_box<DIM, Op, CB, CO, 3>(op, xin, x, b, w_in, gc, e, w, out, nrhs, s); break;
+      default: sweep_box<DIM, Op, CB, CO, 0>(op, xin, x, b, w_in, gc, e, w, out, nrhs, s); break;
+    }
+  }
+}
+
+template <int DIM, class Op, typename CB, int BV>
+void restrict_box(const Op& op, int xin, const typename Op::C* x, const CB* b, typename Op::Real w_in,
                   const Geom& g2, typename Op::C* b2, int nrhs, hipStream_t s) {
-  typedef typename Op::C C;
-  TileGrid tg = tiles(g2, RBox<DIM, sizeof(C)>::x, RBox<DIM, sizeof(C)>::y, RBox<DIM, sizeof(C)>::z);
+  TileGrid tg = tiles(g2, RBox<DIM, BV>::x, RBox<DIM, BV>::y, RBox<DIM, BV>::z);
   dim3 grid(grid_tiles(tg), nrhs), blk(256);
-#define RS(F) hipLaunchKernelGGL((k_restrict<DIM, Op, CB, F>), grid, blk, 0, s, op, x, b, w_in, g2, b2, tg)
+#define RS(F) hipLaunchKernelGGL((k_restrict<DIM, Op, CB, F, BV>), grid, blk, 0, s, op, x, b, w_in, g2, b2, tg)
   switch (xin) {
     case 0: RS(0); break;
     case XIN_X: RS(XIN_X); break;
@@ -563,6 +589,20 @@ void restrict_dim(const Op& op, int xin, const typename Op::C* x, const CB* b, t
     default: break;
   }
 #undef RS
+}
+
+template <int DIM, class Op, typename CB>
+void restrict_dim(const Op& op, int xin, const typename Op::C* x, const CB* b, typename Op::Real w_in,
+                  const Geom& g2, typename Op::C* b2, int nrhs, hipStream_t s) {
+  if constexpr (DIM == 3 && sizeof(typename Op::C) == 16) {
+    restrict_box<DIM, Op, CB, 0>(op, xin, x, b, w_in, g2, b2, nrhs, s);
+  } else {
+    switch (op.A.box_restrict) {
+      case 1: restrict_box<DIM, Op, CB, 1>(op, xin, x, b, w_in, g2, b2, nrhs, s); break;
+      case 2: restrict_box<DIM, Op, CB, 2>(op, xin, x, b, w_in, g2, b2, nrhs, s); break;
+      default: restrict_box<DIM, Op, CB, 0>(op, xin, x, b, w_in, g2, b2, nrhs, s); break;
+    }
+  }
 }
 
 template <typename R, typename CB, typename CO>

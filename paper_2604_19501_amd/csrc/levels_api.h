@@ -34,6 +34,7 @@ struct L1 {
   int conj;            // 1: coefficients of conj(H) (the adjoint, H being complex symmetric)
   const C* dg = nullptr;   // the FP32 cycle: its diagonal precomputed at set-up (of the
                            // operator, not of its conjugate), read instead of m
+  int box_sweep = 0, box_restrict = 0;   // box-shape variants of the tiled kernels
   // the coefficient and the diagonal from the node's squared slowness mm = m[f]
   __device__ __forceinline__ C coef_m(R mm, int i0, int i1, int i2) const {
     R sig = layer_sigma_r<R>(op, i0, i1, i2);
@@ -58,6 +59,7 @@ struct L2 {
   const C* coef;     // SoA, plane k at coef[k * N]: 3^d planes, or (SYM2) the centre and the
                      // 13 directions after it
   int conj;          // use conj(coef) (adjoint)
+  int box_sweep = 0, box_restrict = 0;   // box-shape variants of the tiled kernels
   __device__ __forceinline__ C get(int k, long long i) const {
     C c = coef[(long long)k * g.tot + i];
     if (conj) c.y = -c.y;

@@ -23,7 +23,7 @@ from . import _lib as L
 INFO_KEYS = ("N1", "N2", "N3", "fronts", "L_entries", "W_entries", "upd_entries", "sep_entries",
              "fwd_launches", "bwd_launches", "workspace_bytes", "max_front", "cycle_complex_bytes",
              "nd_leaf", "nd_root", "nd_tuned", "nd_tree_launches")
-INFO_LEN = 25
+INFO_LEN = 29
 KERNEL_CLASSES = ("l1_sweep", "l1_restrict", "l2_sweep", "l2_restrict", "nd_fwd", "nd_bwd", "arnoldi")
 
 
@@ -34,6 +34,7 @@ def parse_info(v) -> dict:
     out["nd_merge"] = [h for h in range(63) if (int(v[21]) >> h) & 1]
     out["planes2"], out["planes3"] = int(v[22]), int(v[23])
     out["coarse_complex_bytes"] = int(v[24])
+    out["boxes"] = [int(v[25 + i]) for i in range(4)]
     return out
 
 

@@ -111,10 +111,10 @@ def cache_key(n, prec, stack="p5", transfer=None):
 
 
 def time_schedule(n, prec, leaf, root, cuts, iters=30, repeats=2, merge="none", splitk_kb=SPLITK_DEFAULT_KB,
-                  stack="p5", transfer=None):
+                  stack="p5", transfer=None, boxes="0,0,0,0"):
     """(seconds per FGMRES iteration, seconds per numerical set-up, plan info)"""
     env = {"HELM_ND_LEAF": str(leaf), "HELM_ND_ROOT": str(root), "HELM_ND_CUTS": cuts,
-           "HELM_ND_MERGE": merge, "HELM_ND_SPLITK_KB": str(splitk_kb)}
+           "HELM_ND_MERGE": merge, "HELM_ND_SPLITK_KB": str(splitk_kb), "HELM_BOXES": boxes}
     saved = {k: os.environ.get(k) for k in env}
     os.environ.update(env)
     try:
@@ -146,6 +146,61 @@ def time_schedule(n, prec, leaf, root, cuts, iters=30, repeats=2, merge="none", 
                 os.environ[k] = v
         torch.cuda.empty_cache()
 
+
+def class_times(n, prec, sched, boxes, iters=30):
+    """per-class kernel times (ms, HIP events on the solver's stream) of one solve of
+    `iters` iterations under the schedule and the box variants"""
+    env = {"HELM_ND_LEAF": str(sched["leaf"]), "HELM_ND_ROOT": str(sched["root"]), "HELM_ND_CUTS": sched["cuts"],
+           "HELM_ND_MERGE": sched.get("merge", "none"),
+           "HELM_ND_SPLITK_KB": str(sched.get("splitk_kb", SPLITK_DEFAULT_KB)), "HELM_BOXES": boxes}
+    saved = {k: os.environ.get(k) for k in env}
+    os.environ.update(env)
+    try:
+        dim, h, kappa, omega, layer = _problem(n)
+        s = Solver(n, h, kappa, omega, layer=layer, sigma_max=2.0, alpha=1.1, alpha2=1.0, beta=0.1,
+                   nu=(1, 1), cycle_prec=prec)
+        q = np.zeros(int(np.prod([k + 1 for k in n])), np.complex128)
+        q[q.size // 2] = 1.0
+        s.solve(q, tol=1e-300, max_iter=iters)
+        s.set_timing(True)
+        s.solve(q, tol=1e-300, max_iter=iters)
+        torch.cuda.synchronize()
+        kt = {k: v[0] for k, v in s.kernel_times().items()}
+        s.set_timing(False)
+        s.close()
+        return kt
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+        torch.cuda.empty_cache()
+
+
+def tune_boxes(n, prec, sched, verbose=True):
+    """stage three: the box shapes of the tiled cycle kernels (level-1 sweep, level-1
+    restriction, level-2 sweep, level-2 restriction) under the given schedule.  Each class
+    is timed by its own HIP events (whole iterations vary by about as much as one class's
+    gain); a variant replaces the default when its class time is 2 % lower.  Returns (boxes
+    string, {class: ms} of the choice)."""
+    classes = ("l1_sweep", "l1_restrict", "l2_sweep", "l2_restrict")
+    nvar = (4, 3, 4, 3)
+    base = class_times(n, prec, sched, "0,0,0,0")
+    boxes = [0, 0, 0, 0]
+    best_ms = {c: base[c] for c in classes}
+    for v in range(1, 4):
+        trial = [v if v < nvar[q] else 0 for q in range(4)]
+        bx = ",".join(map(str, trial))
+        kt = class_times(n, prec, sched, bx)
+        for q, c in enumerate(classes):
+            if trial[q] and kt[c] < 0.98 * best_ms[c]:
+                boxes[q], best_ms[c] = trial[q], kt[c]
+        if verbose:
+            print("  boxes %s -> %s" % (bx, " ".join("%s %.3f" % (c, kt[c]) for c in classes)), flush=True)
+    if verbose:
+        print("  default -> %s" % " ".join("%s %.3f" % (c, base[c]) for c in classes), flush=True)
+    return ",".join(map(str, boxes)), {c: round(best_ms[c], 4) for c in classes}
 
 def tune(n, prec="f32", out=None, its=150, verbose=True, stack="p5", transfer=None):
     n = tuple(int(k) for k in n)
@@ -180,6 +235,9 @@ def tune(n, prec="f32", out=None, its=150, verbose=True, stack="p5", transfer=No
     run(list(_stage_two(results, top=3 if dim == 2 else 1)))
     results.sort(key=lambda r: r["score_ms"])
     best = dict(results[0])
+    best["boxes"] = "0,0,0,0"
+    if stack == "p5":
+        best["boxes"], best["box_class_ms"] = tune_boxes(n, prec, best, verbose)
     best["device"] = torch.cuda.get_device_name(0)
     best["score"] = "setup + %d iterations" % its
     best["runners_up"] = results[1:6]
@@ -206,7 +264,20 @@ def main():
     ap.add_argument("--its", type=int, default=150, help="iterations per set-up in the score")
     ap.add_argument("--stack", choices=("p5", "compact"), default="p5")
     ap.add_argument("--transfer", choices=("cubic", "levdep"), default=None)
+    ap.add_argument("--boxes-only", action="store_true",
+                    help="only stage three (cycle-kernel boxes) under the cache entry's schedule")
     a = ap.parse_args()
+    if a.boxes_only:
+        n = tuple(a.n)
+        key = cache_key(n, a.prec)
+        path = a.out or os.environ.get("HELM_TUNE_CACHE") or L.TUNE_CACHE
+        cache = json.load(open(path))
+        cache[key].pop("us_per_it_boxes", None)
+        cache[key]["boxes"], cache[key]["box_class_ms"] = tune_boxes(n, a.prec, cache[key])
+        with open(path, "w") as f:
+            json.dump(cache, f, indent=1, sort_keys=True)
+        print("%s -> boxes %s %s" % (key, cache[key]["boxes"], cache[key]["box_class_ms"]))
+        return
     tune(a.n, a.prec, a.out, a.its, stack=a.stack, transfer=a.transfer)
 
 

@@ -174,6 +174,26 @@ def test_cycle_rectangular_multi_tile(n, nu):
         s.close()
 
 
+@pytest.mark.parametrize("n", [(136, 72), (40, 24, 32), (200, 136)])
+@pytest.mark.parametrize("boxes", ["1,1,1,1", "2,2,2,2", "3,0,3,0"])
+def test_cycle_box_variants(monkeypatch, n, boxes):
+    """every box-shape variant of the tiled cycle kernels (level-1/level-2 sweeps and
+    restrictions), on grids with several tiles per axis and ragged last tiles, against the
+    oracle element by element (the FP64 3D kernels keep the default boxes)"""
+    monkeypatch.setenv("HELM_BOXES", boxes)
+    p = rect_problem(n)
+    print("cycle boxes", n, boxes, flush=True)
+    H = oracle_hierarchy(p, cycle=2, nu_pre=1, nu_post=1)
+    r = _rand(p.N, 7)
+    ref = H.precond(r)
+    for prec, tol in (("f64", 1e-10), ("f32", 1e-4)):
+        s = from_problem(p, cycle=2, nu=(1, 1), cycle_prec=prec)
+        z = s.vcycle(r).cpu().numpy()
+        assert rel(z, ref) < tol, (prec, rel(z, ref))
+        assert maxabs_rel(z, ref) < TOL_INF[prec], (prec, maxabs_rel(z, ref))
+        s.close()
+
+
 @pytest.mark.parametrize("restart", [20, 4])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_solve_small(case, prec, restart):
