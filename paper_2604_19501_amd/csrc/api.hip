@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdlib>
 #include <cstddef>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <stdexcept>
@@ -322,14 +323,62 @@ int env_int(const char* name, int dflt) {
 // schedule parameters of the coarsest solve picked by the autotuner: the JSON file named
 // by HELM_TUNE_CACHE maps "nd:<dim>:<n0>x<n1>x<n2>:<f32|f64>" (the coarsest solve's
 // precision; ":r<radius>" appended when the coarsest stencil radius is not 1) to an object
-// with integers
-// "leaf", "root" and "splitk_kb" and strings "cuts" and "merge"; returns false when the file
-// or the key is absent
+// with the integers "leaf", "root" and "splitk_kb" and the strings "cuts", "merge" and
+// "boxes" among its members (others, nested objects and arrays included, are skipped);
+// returns false when the file or the key is absent
 struct TunedND {
   int leaf = -1, root = -1, splitk_kb = -1;
   std::string cuts, merge, boxes;
   bool has_cuts = false, has_merge = false, has_boxes = false;
 };
+
+// the members of the JSON object starting at txt[ob] == '{' that sit directly in it:
+// name -> the raw text of the value (strings without their quotes)
+std::map<std::string, std::string> json_members(const std::string& txt, size_t ob) {
+  std::map<std::string, std::string> out;
+  int depth = 0;
+  size_t i = ob;
+  std::string key;
+  auto read_string = [&](size_t& p) {      // p at the opening quote; returns the content
+    std::string v;
+    for (++p; p < txt.size() && txt[p] != '"'; ++p) {
+      if (txt[p] == '\\' && p + 1 < txt.size()) ++p;
+      v += txt[p];
+    }
+    return v;                              // p at the closing quote
+  };
+  for (; i < txt.size(); ++i) {
+    const char ch = txt[i];
+    if (ch == '"') {
+      std::string sv = read_string(i);
+      if (depth == 1) {
+        size_t k = i + 1;
+        while (k < txt.size() && isspace((unsigned char)txt[k])) ++k;
+        if (k < txt.size() && txt[k] == ':') {
+          key = sv;                        // a member name; its value follows
+          i = k;
+          size_t v = k + 1;
+          while (v < txt.size() && isspace((unsigned char)txt[v])) ++v;
+          if (v < txt.size() && txt[v] == '"') {
+            out[key] = read_string(v);
+            i = v;
+          } else if (v < txt.size() && txt[v] != '{' && txt[v] != '[') {
+            size_t e = v;
+            while (e < txt.size() && txt[e] != ',' && txt[e] != '}' && !isspace((unsigned char)txt[e])) ++e;
+            out[key] = txt.substr(v, e - v);
+            i = e - 1;
+          }
+        }
+      }
+    } else if (ch == '{' || ch == '[') {
+      ++depth;
+    } else if (ch == '}' || ch == ']') {
+      if (--depth == 0) break;
+    }
+  }
+  return out;
+}
+
 bool tuned_nd(const helm_ctx* c, TunedND& t) {
   const char* path = getenv("HELM_TUNE_CACHE");
   if (!path || !*path) return false;
@@ -346,31 +395,26 @@ bool tuned_nd(const helm_ctx* c, TunedND& t) {
            c->grid.dim == 3 ? c->grid.n[2] : 0, c->nd64 ? "f64" : "f32", rad);
   size_t k = txt.find(key);
   if (k == std::string::npos) return false;
-  size_t ob = txt.find('{', k), oe = txt.find('}', k);
-  if (ob == std::string::npos || oe == std::string::npos || oe < ob) return false;
-  const std::string obj = txt.substr(ob, oe - ob + 1);
+  size_t ob = txt.find('{', k);
+  if (ob == std::string::npos) return false;
+  const std::map<std::string, std::string> m = json_members(txt, ob);
   auto num = [&](const char* name, int& out) {
-    size_t p = obj.find(name);
-    if (p == std::string::npos) return;
-    p = obj.find(':', p);
-    if (p != std::string::npos) out = atoi(obj.c_str() + p + 1);
+    auto it = m.find(name);
+    if (it != m.end()) out = atoi(it->second.c_str());
   };
-  num("\"leaf\"", t.leaf);
-  num("\"root\"", t.root);
-  num("\"splitk_kb\"", t.splitk_kb);
   auto str = [&](const char* name, std::string& out, bool& has) {
-    size_t p = obj.find(name);
-    if (p == std::string::npos) return;
-    size_t q0 = obj.find('"', obj.find(':', p));
-    size_t q1 = q0 == std::string::npos ? q0 : obj.find('"', q0 + 1);
-    if (q0 != std::string::npos && q1 != std::string::npos) {
-      out = obj.substr(q0 + 1, q1 - q0 - 1);
+    auto it = m.find(name);
+    if (it != m.end()) {
+      out = it->second;
       has = true;
     }
   };
-  str("\"cuts\"", t.cuts, t.has_cuts);
-  str("\"merge\"", t.merge, t.has_merge);
-  str("\"boxes\"", t.boxes, t.has_boxes);
+  num("leaf", t.leaf);
+  num("root", t.root);
+  num("splitk_kb", t.splitk_kb);
+  str("cuts", t.cuts, t.has_cuts);
+  str("merge", t.merge, t.has_merge);
+  str("boxes", t.boxes, t.has_boxes);
   return true;
 }
 
@@ -1045,6 +1089,9 @@ void iter_graphs(helm_ctx* c, int op, double tol) {
     CK(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
     cyc.template run<C>(c->V + j * NJ, (C*)c->Z + j * NJ);
     kr_arnoldi(a, (const char*)c->Z + j * NJ * c->csz, c->f32, j, tol, c->cap);
+    // the state read-back of this position into its slot of the pinned buffer, inside the
+    // graph: a separate launch between graphs cost a dispatch and about 8 us of idle device
+    read_states_async(c, 1 + (j & 1), c->cap);
     CK(hipStreamEndCapture(c->cap, &g));
     hipGraphExec_t e = nullptr;
     CK(hipGraphInstantiate(&e, g, nullptr, nullptr, 0));
@@ -1119,7 +1166,7 @@ int solve_impl(helm_ctx* c, int op, int nr, const cd* b, cd* x, double tol, int 
       // once and leave its basis, Hessenberg column and counters as they are.
       auto queue = [&](int j) {
         CK(hipGraphLaunch(c->gexec[op][j], s));
-        read_states_async(c, 1 + (j & 1), s);
+        // (the graph ends with the read-back of its states into slot 1 + (j & 1))
         CK(hipEventRecord(c->itev[j & 1], s));
       };
       for (hipEvent_t& e : c->itev)

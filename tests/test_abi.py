@@ -118,3 +118,32 @@ def test_tuning_cache_changes_the_plan(tmp_path, monkeypatch):
     path.write_text("{ not json")
     monkeypatch.setenv("HELM_TUNE_CACHE", str(path))
     assert ws() == base
+
+
+def test_tune_cache_members_are_read_at_the_top_level(monkeypatch, tmp_path):
+    """the planner reads the cached schedule's own members: nested objects and arrays
+    (per-class timings, runners-up) before and after them, holding members of the same
+    names, are skipped.  Checked through helm_workspace_bytes, which plans on the host."""
+    import json
+    n = (256, 256)
+    key = "nd:2:256x256x0:f32"
+    monkeypatch.setenv("HELM_TUNE_CACHE", str(tmp_path / "none.json"))
+    monkeypatch.setenv("HELM_ND_ROOT", "100")
+    monkeypatch.setenv("HELM_ND_LEAF", "8")
+    st8, b8 = _bytes(n)
+    monkeypatch.setenv("HELM_ND_LEAF", "64")
+    st64, b64 = _bytes(n)
+    monkeypatch.delenv("HELM_ND_LEAF")
+    monkeypatch.delenv("HELM_ND_ROOT")
+    assert st8 == st64 == 0 and b8 != b64
+    entry = {"a_nested": {"leaf": 8, "root": 1}, "leaf": 64, "merge": "none", "root": 100,
+             "runners_up": [{"leaf": 8, "splitk_kb": 1}], "splitk_kb": 4096, "cuts": ""}
+    path = tmp_path / "cache.json"
+    path.write_text(json.dumps({key: entry}, indent=1, sort_keys=True))
+    monkeypatch.setenv("HELM_TUNE_CACHE", str(path))
+    st, b = _bytes(n)
+    assert st == 0 and b == b64
+    entry["leaf"] = 8
+    path.write_text(json.dumps({key: entry}, indent=1, sort_keys=True))
+    st, b = _bytes(n)
+    assert st == 0 and b == b8
