@@ -44,14 +44,13 @@ void nd_finalize(const NDFrontDev* fr, const int* ids, int nids, long long max_n
                  C* Lp, C* Wp, hipStream_t s);
 template <typename C>
 void nd_fwd(const NDLaunchDev& L, const NDFrontDev* fr, const int* idx, const int* cptr, const int* cidx,
-            const C* Lp, C* upd, const C* r, C* x, C* gvec, int cap, int conj, C* gbuf, C* P, const NDRhs& rh,
-            hipStream_t s);
+            const C* Lp, C* upd, const C* r, C* x, C* gvec, int cap, int conj, C* P, const NDRhs& rh, hipStream_t s);
 int panel_reg_kb(int nF);
 void nd_panel_reg(const NDFrontDev* fr, const int* ids, int nids, int max_nF, cd* Fp, int* perm, int* swp, int k0,
                   int kb, int* err, hipStream_t s);
 template <typename C>
 void nd_bwd(const NDLaunchDev& L, const NDFrontDev* fr, const int* idx, const int* cidx, const C* Wp, C* upd, C* x,
-            C* gvec, int cap, int conj, C* gbuf, C* P, const NDRhs& rh, hipStream_t s);
+            C* gvec, int cap, int conj, C* P, const NDRhs& rh, hipStream_t s);
 void grad_accumulate(const FineOp& op, double omega, const cd* u, const cd* lam, double* g, int first,
                      hipStream_t s);
 
@@ -110,18 +109,18 @@ struct NDDev {        // device-side ND tables (pointers into the workspace)
   void *L = nullptr, *W = nullptr;
   std::vector<NDLaunchDev> launch[2];   // forward, backward
   int gvec_cap = 0;
-  long long gbuf_n = 1, part_n = 1, gvec_n = 0;   // entries per right-hand side of gbuf, part, gvec
+  long long part_n = 1, gvec_n = 0;   // entries per right-hand side of part, gvec
 };
 
 // Per-call scratch of one cycle: the iterates and right-hand sides of levels 1-3 and the
 // coarsest solve's update pool, global gather vectors (launches whose vectors do not fit
-// in LDS) and split-K gathered vectors and partial products.  Nothing in it needs to
+// in LDS) and split-K partial products.  Nothing in it needs to
 // start at zero: every entry is written before it is read within the call.  Sized for
 // rc right-hand sides in lock-step.
 struct CycleScratch {
   void *x1a = nullptr, *x1b = nullptr, *b2 = nullptr, *x2a = nullptr, *x2b = nullptr, *b3 = nullptr,
        *x3 = nullptr;
-  void *upd = nullptr, *gvec = nullptr, *gbuf = nullptr, *part = nullptr;
+  void *upd = nullptr, *gvec = nullptr, *part = nullptr;
 };
 
 // kernel classes timed with HIP events when timing is on
@@ -248,8 +247,8 @@ int validate(const helm_grid* g, const helm_mg* mg) {
   return HELM_OK;
 }
 
-// kernels one substitution step launches (a split-K step: gather, tiles, row sums)
-int nd_step_kernels(int kind) { return kind == 3 ? 3 : 1; }
+// kernels one substitution step launches (a split-K step: tiles, row sums)
+int nd_step_kernels(int kind) { return kind == 3 ? 2 : 1; }
 int nd_kernels(const std::vector<NDLaunchDev>& Ls) {
   int k = 0;
   for (const NDLaunchDev& L : Ls) k += nd_step_kernels(L.kind);
@@ -527,7 +526,6 @@ CycleScratch carve_scratch(const helm_ctx* c, Carver& cv, int rc) {
   w.x3 = cv.take<char>(r * ns * c->g3.tot);
   w.upd = cv.take<char>(r * ns * std::max<long long>(1, c->plan.upd_total));
   w.gvec = d.gvec_n ? cv.take<char>(r * ns * d.gvec_n) : nullptr;
-  w.gbuf = cv.take<char>(r * ns * d.gbuf_n);
   w.part = cv.take<char>(r * ns * d.part_n);
   return w;
 }
@@ -585,7 +583,7 @@ size_t carve(helm_ctx* c, void* ws) {
   d.T = cv.take<cd>(std::max<long long>(1, P.T_scratch));
   d.L = cv.take<char>(c->ndsz * P.L_alloc);
   d.W = cv.take<char>(c->ndsz * std::max<long long>(1, P.W_alloc));
-  long long gbuf_max = 1, part_max = 1;      // split-K buffers (entries)
+  long long part_max = 1;      // split-K partial products (entries)
   for (int fb = 0; fb < 2; ++fb) {
     std::vector<NDLaunch>& Ls = fb == 0 ? P.fwd : P.bwd;
     d.launch[fb].assign(Ls.size(), NDLaunchDev());
@@ -610,7 +608,6 @@ size_t carve(helm_ctx* c, void* ws) {
         D.gath = cv.take<NDGather>(std::max<size_t>(1, L.gath.size()));
         D.tiles = cv.take<NDTile>(std::max<size_t>(1, L.tiles.size()));
         D.rtiles = cv.take<NDRowTile>(std::max<size_t>(1, L.rtiles.size()));
-        gbuf_max = std::max(gbuf_max, L.gbuf_elems);
         part_max = std::max(part_max, L.p_elems);
       } else {
         D.ntasks = (int)L.task_off.size() - 1;
@@ -636,7 +633,6 @@ size_t carve(helm_ctx* c, void* ws) {
     }
   d.gvec_cap = (int)gcap;
   d.gvec_n = gcap * gneed;
-  d.gbuf_n = gbuf_max;
   d.part_n = part_max;
   c->scr = carve_scratch(c, cv, (int)rc);
   // Krylov
@@ -761,7 +757,6 @@ void nd_solve(helm_ctx* c, const CycleScratch& w, const C* r, C* x, int conj, hi
   rh.n = c->nr;
   rh.vec = c->g3.tot;
   rh.upd = std::max<long long>(1, c->plan.upd_total);
-  rh.gbuf = d.gbuf_n;
   rh.part = d.part_n;
   rh.gvec = d.gvec_n;
   // timing: one event pair around each direction's launches (they run back to back), so
@@ -771,7 +766,7 @@ void nd_solve(helm_ctx* c, const CycleScratch& w, const C* r, C* x, int conj, hi
   for (const NDLaunchDev& L : d.launch[0]) {
     C* gv = L.kind == 1 && L.shm == 0 ? (C*)w.gvec : nullptr;
     nd_fwd<C>(L, d.fronts, d.idx, d.cptr, d.cidx, (const C*)d.L, (C*)w.upd, r, x, gv, d.gvec_cap, conj,
-              (C*)w.gbuf, (C*)w.part, rh, s);
+              (C*)w.part, rh, s);
   }
   hipEvent_t e1 = nullptr;
   if (c->timing) {
@@ -780,8 +775,8 @@ void nd_solve(helm_ctx* c, const CycleScratch& w, const C* r, C* x, int conj, hi
   }
   for (const NDLaunchDev& L : d.launch[1]) {
     C* gv = L.kind == 1 && L.shm == 0 ? (C*)w.gvec : nullptr;
-    nd_bwd<C>(L, d.fronts, d.idx, d.cidx, (const C*)d.W, (C*)w.upd, x, gv, d.gvec_cap, conj, (C*)w.gbuf,
-              (C*)w.part, rh, s);
+    nd_bwd<C>(L, d.fronts, d.idx, d.cidx, (const C*)d.W, (C*)w.upd, x, gv, d.gvec_cap, conj, (C*)w.part,
+              rh, s);
   }
   if (c->timing && !d.launch[1].empty()) {
     hipEvent_t e2 = ev_get(c);

@@ -242,7 +242,7 @@ struct NDOut {          // rows [r0, r0 + nr): y = sum of nparts partial blocks 
 struct NDTile {
   int front, r0, k0, k1;
   int pslot;            // partial sums P[pslot + t], t < 256
-  int voff;             // the front's vector in the gather buffer
+  int voff;             // the front's first entry in the flat gather list
 };
 struct NDRowTile {
   int front, r0, nkt, pslot, voff, pad;
@@ -262,7 +262,7 @@ struct NDLaunch {       // one kernel launch of a substitution
   std::vector<int> dst;
   std::vector<NDTile> tiles;        // kind 3 (with gath: the flat gather list)
   std::vector<NDRowTile> rtiles;
-  long long gbuf_elems = 0, p_elems = 0;
+  long long p_elems = 0;
   int lds_bytes = 0;    // kind 2: schedule + vectors + partials per work-group
   int threads = 256;
 };
@@ -274,7 +274,6 @@ struct NDRhs {
   int pad = 0;
   long long vec = 0;     // r and x (N3)
   long long upd = 0;     // update pool
-  long long gbuf = 0;    // split-K gathered vectors
   long long part = 0;    // split-K partial products
   long long gvec = 0;    // row-chunk launches' global vectors
 };

@@ -973,46 +973,38 @@ __global__ void __launch_bounds__(256) k_nd_bwd_big(const NDFrontDev* __restrict
 }
 
 // ---- split-K launches (kind 3) -------------------------------------------
-// flat gather of the fronts' input vectors into gbuf
-template <typename C>
-__global__ void __launch_bounds__(256) k_nd_gather(const NDGather* __restrict__ gath, int n,
-                                                   const int* __restrict__ cidx, const C* __restrict__ upd,
-                                                   const C* __restrict__ src, C* __restrict__ gbuf, NDRhs rh) {
-  typedef decltype(src[0].x) R;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n) return;
-  upd += blockIdx.y * rh.upd;
-  src += blockIdx.y * rh.vec;
-  gbuf += blockIdx.y * rh.gbuf;
-  const NDGather g = gath[e];
-  const C v0 = src[max(g.rid, 0)], u0 = upd[max(g.u0, 0)], u1 = upd[max(g.u1, 0)];
-  C v = mk((R)0, (R)0);
-  if (g.rid >= 0) v += v0;
-  if (g.u0 >= 0) v += u0;
-  if (g.u1 >= 0) v += u1;
-  for (int q = g.ca; q < g.cb; ++q) v += upd[cidx[q]];
-  gbuf[g.slot] = v;
-}
-
-// P[pslot + t] = sum_{k0 <= k < k1} M[k ld + r0 + t] vec[k]: one row per thread, 16 loads in flight
+// P[pslot + t] = sum_{k0 <= k < k1} M[k ld + r0 + t] vec[k]: one row per thread, 16 loads in
+// flight.  The tile gathers its own k-slice of the front's input vector from the gather list
+// (entry voff + k is the front's entry k), so no separate gather launch and buffer pass is
+// needed; tiles of the same k-slice repeat its 128 gathers, which are small beside the
+// 256 x 128 matrix block each of them streams.
 template <typename C, int FWD>
 __global__ void __launch_bounds__(256) k_nd_tile(const NDFrontDev* __restrict__ fr, const C* __restrict__ Mp,
-                                                 const NDTile* __restrict__ tiles, const C* __restrict__ gbuf,
-                                                 C* __restrict__ P, int conj, NDRhs rh) {
-  typedef decltype(gbuf[0].x) R;
+                                                 const NDTile* __restrict__ tiles, const NDGather* __restrict__ gath,
+                                                 const int* __restrict__ cidx, const C* __restrict__ upd,
+                                                 const C* __restrict__ src, C* __restrict__ P, int conj, NDRhs rh) {
+  typedef decltype(src[0].x) R;
   __shared__ C vec[128];
-  gbuf += blockIdx.y * rh.gbuf;
+  upd += blockIdx.y * rh.upd;
+  src += blockIdx.y * rh.vec;
   P += blockIdx.y * rh.part;
   const NDTile t = tiles[blockIdx.x];
   const NDFrontDev f = fr[t.front];
   const int ld = FWD ? f.ldL : f.ldW, rows = FWD ? f.nF : f.nS;
   const int nk = t.k1 - t.k0;
-  if ((int)threadIdx.x < nk) vec[threadIdx.x] = gbuf[t.voff + t.k0 + threadIdx.x];
-  __syncthreads();
   const int i = min(t.r0 + (int)threadIdx.x, rows - 1);
   const C* col = Mp + (FWD ? f.L_off : f.W_off) + (long long)t.k0 * ld + i;
+  // the first 16 matrix entries do not depend on the gathered slice: request them first
+  C m0[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) m0[q] = col[(long long)min(q, nk - 1) * ld];
+  if ((int)threadIdx.x < nk) vec[threadIdx.x] = gather_list(gath[t.voff + t.k0 + threadIdx.x], cidx, upd, src);
+  __syncthreads();
   C acc = mk((R)0, (R)0);
-  for (int k = 0; k < nk; k += 16) {
+#pragma unroll
+  for (int q = 0; q < 16; ++q)
+    if (q < nk) acc += cmul_conj(m0[q], vec[q], conj);
+  for (int k = 16; k < nk; k += 16) {
     C m[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) m[q] = col[(long long)min(k + q, nk - 1) * ld];
@@ -1023,16 +1015,18 @@ __global__ void __launch_bounds__(256) k_nd_tile(const NDFrontDev* __restrict__ 
   P[t.pslot + threadIdx.x] = acc;
 }
 
-// rows of a row tile: the partials summed in k order, then x (or the update) written
+// rows of a row tile: the partials summed in k order, then x (or the update) written; the
+// forward update rows gather their own input entry
 template <typename C, int FWD>
 __global__ void __launch_bounds__(256) k_nd_rowsum(const NDFrontDev* __restrict__ fr, const int* __restrict__ idx,
                                                    const NDRowTile* __restrict__ rt, const C* __restrict__ P,
-                                                   const C* __restrict__ gbuf, C* __restrict__ upd,
+                                                   const NDGather* __restrict__ gath, const int* __restrict__ cidx,
+                                                   const C* __restrict__ src, C* __restrict__ upd,
                                                    C* __restrict__ x, NDRhs rh) {
-  typedef decltype(gbuf[0].x) R;
+  typedef decltype(src[0].x) R;
   P += blockIdx.y * rh.part;
-  gbuf += blockIdx.y * rh.gbuf;
   upd += blockIdx.y * rh.upd;
+  src += blockIdx.y * rh.vec;
   x += blockIdx.y * rh.vec;
   const NDRowTile t = rt[blockIdx.x];
   const NDFrontDev f = fr[t.front];
@@ -1044,7 +1038,7 @@ __global__ void __launch_bounds__(256) k_nd_rowsum(const NDFrontDev* __restrict_
     if (i < f.nS)
       x[idx[f.idx_off + i]] = acc;
     else
-      upd[f.upd_off + i - f.nS] = gbuf[t.voff + i] - acc;
+      upd[f.upd_off + i - f.nS] = gather_list(gath[t.voff + i], cidx, (const C*)upd, src) - acc;
   } else {
     const int id = idx[f.idx_off + i];
     x[id] = x[id] + acc;
@@ -1053,13 +1047,11 @@ __global__ void __launch_bounds__(256) k_nd_rowsum(const NDFrontDev* __restrict_
 
 template <typename C, int FWD>
 static void splitk(const NDLaunchDev& L, const NDFrontDev* fr, const int* idx, const int* cidx, const C* M, C* upd,
-                   const C* src, C* x, C* gbuf, C* P, int conj, const NDRhs& rh, hipStream_t s) {
-  hipLaunchKernelGGL((k_nd_gather<C>), dim3((L.ngath + 255) / 256, rh.n), dim3(256), 0, s, L.gath, L.ngath, cidx,
-                     (const C*)upd, src, gbuf, rh);
-  hipLaunchKernelGGL((k_nd_tile<C, FWD>), dim3(L.ntiles, rh.n), dim3(256), 0, s, fr, M, L.tiles, (const C*)gbuf, P,
-                     conj, rh);
+                   const C* src, C* x, C* P, int conj, const NDRhs& rh, hipStream_t s) {
+  hipLaunchKernelGGL((k_nd_tile<C, FWD>), dim3(L.ntiles, rh.n), dim3(256), 0, s, fr, M, L.tiles, L.gath, cidx,
+                     (const C*)upd, src, P, conj, rh);
   hipLaunchKernelGGL((k_nd_rowsum<C, FWD>), dim3(L.nrt, rh.n), dim3(256), 0, s, fr, idx, L.rtiles, (const C*)P,
-                     (const C*)gbuf, upd, x, rh);
+                     L.gath, cidx, src, upd, x, rh);
 }
 
 // ------------------------------------------------------------- launchers ----
@@ -1140,10 +1132,10 @@ static void tree_attr(size_t lds) {
 
 template <typename C>
 void nd_fwd(const NDLaunchDev& L, const NDFrontDev* fr, const int* idx, const int* cptr, const int* cidx,
-            const C* Lp, C* upd, const C* r, C* x, C* gvec, int cap, int conj, C* gbuf, C* P, const NDRhs& rh,
+            const C* Lp, C* upd, const C* r, C* x, C* gvec, int cap, int conj, C* P, const NDRhs& rh,
             hipStream_t s) {
   if (L.kind == 3) {
-    splitk<C, 1>(L, fr, idx, cidx, Lp, upd, r, x, gbuf, P, conj, rh, s);
+    splitk<C, 1>(L, fr, idx, cidx, Lp, upd, r, x, P, conj, rh, s);
   } else if (L.kind == 2) {
     size_t lds = (size_t)L.lds_bytes;
     tree_attr<C, 1>(lds);
@@ -1156,9 +1148,9 @@ void nd_fwd(const NDLaunchDev& L, const NDFrontDev* fr, const int* idx, const in
 }
 template <typename C>
 void nd_bwd(const NDLaunchDev& L, const NDFrontDev* fr, const int* idx, const int* cidx, const C* Wp, C* upd, C* x,
-            C* gvec, int cap, int conj, C* gbuf, C* P, const NDRhs& rh, hipStream_t s) {
+            C* gvec, int cap, int conj, C* P, const NDRhs& rh, hipStream_t s) {
   if (L.kind == 3) {
-    splitk<C, 0>(L, fr, idx, cidx, Wp, upd, (const C*)x, x, gbuf, P, conj, rh, s);
+    splitk<C, 0>(L, fr, idx, cidx, Wp, upd, (const C*)x, x, P, conj, rh, s);
   } else if (L.kind == 2) {
     size_t lds = (size_t)L.lds_bytes;
     tree_attr<C, 0>(lds);
@@ -1175,13 +1167,13 @@ template void nd_finalize<cf>(const NDFrontDev*, const int*, int, long long, con
 template void nd_finalize<cd>(const NDFrontDev*, const int*, int, long long, const cd*, const int*,
                                    cd*, cd*, hipStream_t);
 template void nd_fwd<cf>(const NDLaunchDev&, const NDFrontDev*, const int*, const int*, const int*, const cf*, cf*,
-                         const cf*, cf*, cf*, int, int, cf*, cf*, const NDRhs&, hipStream_t);
+                         const cf*, cf*, cf*, int, int, cf*, const NDRhs&, hipStream_t);
 template void nd_fwd<cd>(const NDLaunchDev&, const NDFrontDev*, const int*, const int*, const int*, const cd*, cd*,
-                         const cd*, cd*, cd*, int, int, cd*, cd*, const NDRhs&, hipStream_t);
+                         const cd*, cd*, cd*, int, int, cd*, const NDRhs&, hipStream_t);
 template void nd_bwd<cf>(const NDLaunchDev&, const NDFrontDev*, const int*, const int*, const cf*, cf*, cf*, cf*, int,
-                         int, cf*, cf*, const NDRhs&, hipStream_t);
+                         int, cf*, const NDRhs&, hipStream_t);
 template void nd_bwd<cd>(const NDLaunchDev&, const NDFrontDev*, const int*, const int*, const cd*, cd*, cd*, cd*, int,
-                         int, cd*, cd*, const NDRhs&, hipStream_t);
+                         int, cd*, const NDRhs&, hipStream_t);
 
 
 }  // namespace helm

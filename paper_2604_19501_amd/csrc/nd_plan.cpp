@@ -648,7 +648,7 @@ void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int root_merge, int e
       const int R = dir == 0 ? f.nF : f.nS, K = dir == 0 ? f.nS : f.nB;
       if (R == 0 || K == 0) continue;
       const int* ids = plan.idx.data() + f.idx_off;
-      const int voff = (int)L.gbuf_elems;
+      const int voff = (int)L.gath.size();
       if (dir == 0) {
         for (int i = 0; i < f.nF; ++i) {
           int ca = plan.cptr[f.inv_off + i], cb = plan.cptr[f.inv_off + i + 1];
@@ -662,7 +662,6 @@ void nd_plan(const Geom& g3, int leaf_max, int rows_chunk, int root_merge, int e
       } else {
         for (int j = 0; j < f.nB; ++j) L.gath.push_back({voff + j, ids[f.nS + j], -1, -1, 0, 0});
       }
-      L.gbuf_elems += dir == 0 ? f.nF : f.nB;
       const int nkt = (K + KT - 1) / KT;
       for (int r0 = 0; r0 < R; r0 += 256) {
         const int ps0 = (int)L.p_elems;
