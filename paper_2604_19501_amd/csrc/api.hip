@@ -463,7 +463,7 @@ void build_plan(helm_ctx* c) {
     std::vector<int> bx = bv.empty() ? std::vector<int>() : parse_cuts(bv.c_str());
     for (int q = 0; q < 4; ++q) {
       c->box[q] = q < (int)bx.size() ? bx[q] : 0;
-      const int nmax = (q % 2 == 0) ? 4 : 3;     // sweeps: 4 variants, restrictions: 3
+      const int nmax = (q % 2 == 0) ? 6 : 5;     // sweeps: 6 variants, restrictions: 5
       if (c->box[q] < 0 || c->box[q] >= nmax) throw std::runtime_error("HELM_BOXES: variant out of range");
     }
   }
@@ -1083,10 +1083,11 @@ void iter_graphs(helm_ctx* c, int op, double tol) {
     hipGraph_t g = nullptr;
     CK(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
     cyc.template run<C>(c->V + j * NJ, (C*)c->Z + j * NJ);
-    kr_arnoldi(a, (const char*)c->Z + j * NJ * c->csz, c->f32, j, tol, c->cap);
-    // the state read-back of this position into its slot of the pinned buffer, inside the
-    // graph: a separate launch between graphs cost a dispatch and about 8 us of idle device
-    read_states_async(c, 1 + (j & 1), c->cap);
+    // the state read-back of this position into its slot of the pinned buffer is made by
+    // the Givens step inside the graph: a separate launch between graphs cost a dispatch
+    // and about 8 us of idle device, one inside it about 4 us
+    kr_arnoldi(a, (const char*)c->Z + j * NJ * c->csz, c->f32, j, tol, c->hstate_dev + HSLOT * (1 + (j & 1)),
+               c->cap);
     CK(hipStreamEndCapture(c->cap, &g));
     hipGraphExec_t e = nullptr;
     CK(hipGraphInstantiate(&e, g, nullptr, nullptr, 0));
@@ -1179,8 +1180,9 @@ int solve_impl(helm_ctx* c, int op, int nr, const cd* b, cd* x, double tol, int 
       for (int j = 0; j < m; ++j) {
         if (c->timing) kr_hold(150, s);     // the iteration's launches are queued before they run
         cyc.template run<C>(c->V + j * NJ, (C*)c->Z + j * NJ);
-        TIMED(c, KT_APPLY_DOT, s, kr_arnoldi(a, (const char*)c->Z + j * NJ * c->csz, c->f32, j, tol, s));
-        read_states(c, s);
+        TIMED(c, KT_APPLY_DOT, s, kr_arnoldi(a, (const char*)c->Z + j * NJ * c->csz, c->f32, j, tol,
+                                             c->hstate_dev, s));
+        CK(hipStreamSynchronize(s));
         if (all_done(hs(c))) break;
       }
     }

@@ -26,6 +26,7 @@ struct KrylovState {
   int maxit;          // iteration limit (the column that reaches it ends the solve)
   double hist[KMAXIT];
   cd G[(KMAXM + 1) * (KMAXM + 1)];   // Gram matrix of the stored basis, leading dimension KMAXM + 1
+  int ticket;         // blocks of the current final-sum launch that have stored their sum
 };
 
 // nrhs right-hand sides are iterated in lock-step (grid y): right-hand side r has state
@@ -50,7 +51,9 @@ struct KrylovArgs {
 void kr_init(const KrylovArgs& a, int max_iter, hipStream_t s);
 void kr_residual(const KrylovArgs& a, const cd* x, const cd* b, int with_b, hipStream_t s);
 void kr_scale_v0(const KrylovArgs& a, hipStream_t s);
-void kr_arnoldi(const KrylovArgs& a, const void* z, int z_f32, int j, double tol, hipStream_t s);
+// pack_dst: host-mapped slot that receives the scalar blocks of the states after the
+// column's Givens update (as kr_pack_states); null: none
+void kr_arnoldi(const KrylovArgs& a, const void* z, int z_f32, int j, double tol, void* pack_dst, hipStream_t s);
 // x += Z y over each right-hand side's columns of the current cycle (Z: ldz between columns)
 void kr_update_x(const KrylovArgs& a, const void* Z, int z_f32, long long ldz, cd* x, hipStream_t s);
 // x += z (the stationary iteration's update; z in cycle precision)

@@ -4,9 +4,10 @@
 // the basis:
 //   k_arnoldi_dots    w = H z_j (FP64) and, reading every V_i once, partial sums of
 //                     h1_i = <V_i, w>, the Gram column G_ij = <V_i, V_j> and ||w||^2
-//   k_fin_sum         the sums, in a fixed order
-//   k_givens          classical Gram-Schmidt with one re-orthogonalisation, the second
-//                     projection taken from the Gram matrix instead of a second pass:
+//   k_fin_givens      the sums, in a fixed order, one block per value; the block that
+//                     stores the last of them then runs classical Gram-Schmidt with one
+//                     re-orthogonalisation, the second projection taken from the Gram
+//                     matrix instead of a second pass:
 //                       h2 = V^H (w - V h1) = h1 - G h1,   c = h1 + h2 = H(:, j),
 //                       h_{j+1,j}^2 = ||w - V c||^2 = ||w||^2 - 2 Re(c^H h1) + c^H G c;
 //                     then the Givens rotation of the Hessenberg column, the residual
@@ -199,17 +200,22 @@ __device__ inline void givens(cd a, cd b, double& c, cd& s, cd& r) {
   r = t * ph;
 }
 
-// finish the Arnoldi column j and the Givens update (one wavefront); st->h1 holds the
-// sums of k_arnoldi_dots.  Lane i owns row i of the Gram products; the serial part
-// (rotations of the column) runs on lane 0 out of LDS.
-__global__ void __launch_bounds__(64) k_givens(KrylovArgs a, int j, double tol) {
-  const RhsPtr p = at_rhs(a);
+// the scalar block (bnorm .. hist) of state r into slot r of the host-mapped dst
+__device__ __forceinline__ void pack_state(const KrylovState* st, char* dst, int r) {
+  constexpr int W = (int)((offsetof(KrylovState, hist) - offsetof(KrylovState, bnorm)) / 4);
+  const int* src = (const int*)((const char*)st + offsetof(KrylovState, bnorm));
+  for (int q = threadIdx.x; q < W; q += blockDim.x) ((int*)dst)[r * W + q] = src[q];
+}
+
+// finish the Arnoldi column j and the Givens update in one block of 256 threads, of which
+// the first wavefront works (the others only meet the barriers); st->h1 holds the sums of
+// k_arnoldi_dots.  Lane i owns row i of the Gram products; the serial part (rotations of
+// the column) runs on lane 0 out of LDS.
+__device__ void givens_column(const KrylovArgs& a, KrylovState* st, int j, double tol) {
   __shared__ cd sh1[KMAXM + 1], sg[KMAXM + 1], sc[KMAXM + 1], col[KMAXM + 2], ssn[KMAXM];
   __shared__ double scs[KMAXM], r1[64], r2[64];
   __shared__ cd sG[(KMAXM + 1) * (KMAXM + 1)];
-  KrylovState* st = p.st;
-  if (st->done) return;            // converged in an earlier column: the state stays as it is
-  const int t = threadIdx.x, ld = KMAXM + 1;
+  const int t = threadIdx.x < 64 ? (int)threadIdx.x : 1 << 20, ld = KMAXM + 1;
   // the scalars the serial part needs, loaded now so that their latency overlaps the
   // products below (the stores into the state would otherwise keep them in order)
   double nw2 = 0.0, bnorm = 1.0;
@@ -255,8 +261,10 @@ __global__ void __launch_bounds__(64) k_givens(KrylovArgs a, int j, double tol) 
     p1 += sc[i].x * sh1[i].x + sc[i].y * sh1[i].y;
     p2 += sc[i].x * gc.x + sc[i].y * gc.y;
   }
-  r1[t] = p1;
-  r2[t] = p2;
+  if (t < 64) {
+    r1[t] = p1;
+    r2[t] = p2;
+  }
   for (int i = t; i <= j; i += 64) {          // store column / row j of G for later columns
     st->G[i + ld * j] = sg[i];
     st->G[j + ld * i] = conjc(sg[i]);
@@ -307,6 +315,40 @@ __global__ void __launch_bounds__(64) k_givens(KrylovArgs a, int j, double tol) 
   for (int i = t; i <= j + 1; i += 64) st->H[i + ld * j] = col[i];
   for (int i = t; i <= j; i += 64) st->c[i] = sc[i];
 }
+
+// one block per value: st->h1[i] = sum over the dot pass's blocks of part[i]; the block
+// that stores the last of the 2 j + 3 sums of its right-hand side (a device-scope ticket,
+// returned to zero by that block) then finishes the column (givens_column) and, with
+// pack_dst, packs the state for the host.  The sums are formed in a fixed order whichever
+// block finishes last.
+__global__ void __launch_bounds__(256) k_fin_givens(KrylovArgs a, int j, double tol, char* pack_dst) {
+  __shared__ cd lds[4];
+  __shared__ int last;
+  const RhsPtr p = at_rhs(a);
+  KrylovState* st = p.st;
+  const int i = blockIdx.x;
+  cd v = mk(0.0, 0.0);
+  for (int b = threadIdx.x; b < a.nblk; b += 256) v += p.part[(long long)i * a.pcap + b];
+  block_sum(v, lds, st->h1 + i);
+  if (threadIdx.x == 0) {
+    __threadfence();                     // this block's sum before its ticket
+    last = atomicAdd(&st->ticket, 1) == (int)gridDim.x - 1;
+    if (last) {
+      __threadfence();                   // every other block's sum after their tickets
+      st->ticket = 0;
+    }
+  }
+  __syncthreads();
+  if (!last) return;
+  // converged in an earlier column: the state stays as it is
+  if (!st->done) givens_column(a, st, j, tol);
+  if (pack_dst) {
+    __syncthreads();
+    pack_state(st, pack_dst, blockIdx.y);
+    __threadfence_system();
+  }
+}
+
 
 // V_{j+1} = (H z_j - sum_i c_i V_i) / h_{j+1,j}.  The blocks take the nodes in reverse
 // order: the dots pass just streamed the same basis front to back, so its last part is
@@ -436,17 +478,14 @@ __global__ void k_init_state(KrylovState* st, int maxit) {
     st->final = 0;
     st->kcols = 0;
     st->maxit = maxit;
+    st->ticket = 0;
   }
 }
 
 // the scalar blocks (bnorm .. hist) of the nrhs states, packed one after the other into
 // host-visible memory (pinned, written through), for the host to read after an event
 __global__ void k_pack_states(const KrylovState* st, char* dst, int nrhs) {
-  constexpr int W = (int)((offsetof(KrylovState, hist) - offsetof(KrylovState, bnorm)) / 4);
-  for (int e = threadIdx.x; e < nrhs * W; e += blockDim.x) {
-    const int r = e / W, q = e % W;
-    ((int*)dst)[e] = ((const int*)((const char*)(st + r) + offsetof(KrylovState, bnorm)))[q];
-  }
+  for (int r = 0; r < nrhs; ++r) pack_state(st + r, dst, r);
   __threadfence_system();
 }
 
@@ -487,7 +526,7 @@ void kr_residual(const KrylovArgs& a, const cd* x, const cd* b, int with_b, hipS
 void kr_scale_v0(const KrylovArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_scale_v0, dim3(a.nblk, a.nrhs), dim3(256), 0, s, a);
 }
-void kr_arnoldi(const KrylovArgs& a, const void* z, int z_f32, int j, double tol, hipStream_t s) {
+void kr_arnoldi(const KrylovArgs& a, const void* z, int z_f32, int j, double tol, void* pack_dst, hipStream_t s) {
   dim3 g(a.nblk, a.nrhs);
   const int cmp = a.op.compact;
   if (z_f32 && !cmp)
@@ -498,8 +537,7 @@ void kr_arnoldi(const KrylovArgs& a, const void* z, int z_f32, int j, double tol
     hipLaunchKernelGGL((k_arnoldi_dots<cf, 1>), g, dim3(256), 0, s, a, (const cf*)z, j);
   else
     hipLaunchKernelGGL((k_arnoldi_dots<cd, 1>), g, dim3(256), 0, s, a, (const cd*)z, j);
-  hipLaunchKernelGGL(k_fin_sum, dim3(2 * j + 3, a.nrhs), dim3(256), 0, s, a, offsetof(KrylovState, h1));
-  hipLaunchKernelGGL(k_givens, dim3(1, a.nrhs), dim3(64), 0, s, a, j, tol);
+  hipLaunchKernelGGL(k_fin_givens, dim3(2 * j + 3, a.nrhs), dim3(256), 0, s, a, j, tol, (char*)pack_dst);
   if (z_f32 && !cmp)
     hipLaunchKernelGGL((k_arnoldi_update<cf, 0>), g, dim3(256), 0, s, a, (const cf*)z, j);
   else if (!cmp)

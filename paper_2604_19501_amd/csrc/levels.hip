@@ -73,6 +73,8 @@ __device__ __forceinline__ int flat(const Geom& g, int i0, int i1, int i2) {
 //                3D 32 x 8 x 4, 32 x 8 x 8, 64 x 8 x 4, 32 x 16 x 4
 //   restrictions 2D 16 x 8, 32 x 8, 16 x 16 coarse
 //                3D 8 x 4 x 4, 16 x 4 x 4, 8 x 8 x 4 coarse
+//   and, 3D FP32 only, z-marching tiles (below): sweeps 4 and 5, restrictions 3 and 4
+//   (in 2D these variants run variant 0).
 // The FP64 cycle keeps variant 0 in 3D (the others exceed the block's LDS).
 template <int DIM, int V> struct SBox {
   static constexpr int x = DIM == 2 ? (V == 0 || V == 3 ? 32 : 64) : (V == 2 ? 64 : 32);
@@ -84,7 +86,17 @@ template <int DIM, int V> struct RBox {
   static constexpr int y = DIM == 2 ? (V == 2 ? 16 : 8) : (V == 2 ? 8 : 4);
   static constexpr int z = DIM == 2 ? 1 : 4;
 };
-constexpr int N_SBOX = 4, N_RBOX = 3;
+constexpr int N_SBOX = 6, N_RBOX = 5;
+// z-marching tiles: an xy tile of output nodes over z consecutive planes
+//   sweeps       30 x 14 nodes, 16 (variant 4) or 4 (variant 5) planes
+//   restrictions 14 x 6 coarse nodes, 8 (variant 3) or 4 (variant 4) coarse planes
+// (the staged planes, 32 x 16 and 31 x 15 nodes, take two wavefront passes of 256 threads)
+template <int V> struct ZSBox {
+  static constexpr int x = 30, y = 14, z = V == 4 ? 16 : 4;
+};
+template <int V> struct ZRBox {
+  static constexpr int x = 14, y = 6, z = V == 3 ? 8 : 4;
+};
 
 // level-1 operator H_s with x from LDS (centre index k, strides sy, sz).  The FP32 cycle
 // reads its diagonal from the array precomputed at set-up (one 8-byte load per node instead
@@ -121,6 +133,13 @@ struct Op1 {
     if (DIM == 3) nb += xs[k - sz] + xs[k + sz];
     return D * xs[k] - (R)A.op.inv_h2 * nb;
   }
+  // 3D, the planes below / at / above the node staged apart (z-marching tiles); the same
+  // sums in the same order as ax
+  __device__ __forceinline__ C ax3(const C* xm, const C* x0, const C* xp, int k, int sy, long long, C D) const {
+    C nb = (x0[k - 1] + x0[k + 1]) + (x0[k - sy] + x0[k + sy]);
+    nb += xm[k] + xp[k];
+    return D * x0[k] - (R)A.op.inv_h2 * nb;
+  }
 };
 
 // level-2 Galerkin operator (3^d coefficients per node; the 3D FP32 cycle stores the
@@ -148,6 +167,21 @@ struct Op2 {
           if (d0 == 0 && d1 == 0 && d2 == 0) continue;
           const int kk = (d0 + 1) + 3 * (d1 + 1) + (DIM == 3 ? 9 * (d2 + 1) : 0);
           acc += coef_at(kk, f) * xs[k + d0 + sy * d1 + sz * d2];
+        }
+    return acc;
+  }
+  __device__ __forceinline__ C ax3(const C* xm, const C* x0, const C* xp, int k, int sy, long long f, C D) const {
+    C acc = D * x0[k];
+#pragma unroll
+    for (int d2 = -1; d2 <= 1; ++d2)
+#pragma unroll
+      for (int d1 = -1; d1 <= 1; ++d1)
+#pragma unroll
+        for (int d0 = -1; d0 <= 1; ++d0) {
+          if (d0 == 0 && d1 == 0 && d2 == 0) continue;
+          const int kk = (d0 + 1) + 3 * (d1 + 1) + 9 * (d2 + 1);
+          const C* pl = d2 < 0 ? xm : d2 > 0 ? xp : x0;
+          acc += coef_at(kk, f) * pl[k + d0 + sy * d1];
         }
     return acc;
   }
@@ -476,6 +510,289 @@ __global__ void __launch_bounds__(256) k_restrict(Op op, const typename Op::C* _
   }
 }
 
+// ---- z-marching tiles (3D) --------------------------------------------------
+// A block owns an xy tile and walks consecutive planes.  The staged iterate x_in lives in
+// a ring of 4 planes (tile plus a one-node halo) in LDS; the inputs of the plane after
+// next are requested into registers while the current plane is computed; the thread that
+// stages a node keeps the b and D it loaded, and computes that node's output (sweep) or
+// residual (restriction) from them.  Against the box tiles this stages about 1.2-1.4
+// nodes per output instead of 2, loads b and D once instead of twice, and forms each
+// slot's indices once per block.  The sums are those of the box kernels, in their order.
+struct ZSlots {
+  int k, fxy, j0, j1;    // staged position, flat xy offset and clamped coordinates
+  bool in, own;          // xy inside the grid (and a real position); an output / residual node
+};
+
+template <class Op, typename CB, typename CO, int XIN, int BV>
+__global__ void __launch_bounds__(256) k_sweep_z(Op op, const typename Op::C* __restrict__ x,
+                                                 const CB* __restrict__ b, typename Op::Real w_in, Geom gc,
+                                                 const typename Op::C* __restrict__ e, typename Op::Real w,
+                                                 CO* __restrict__ out, TileGrid tg) {
+  typedef typename Op::C C;
+  typedef typename Op::Real R;
+  typedef typename Op::Aux A;
+  constexpr int TX = ZSBox<BV>::x, TY = ZSBox<BV>::y, ZC = ZSBox<BV>::z;
+  constexpr int SX = TX + 2, SY = TY + 2, PL = SX * SY, NS = (PL + 255) / 256;
+  constexpr int EX = TX / 2 + 3, EY = TY / 2 + 3, EZ = ZC / 2 + 3;
+  __shared__ C ring[4 * PL];
+  __shared__ C es[(XIN & XIN_E) ? EX * EY * EZ : 1];
+  const Geom& g = op.geom();
+  const long long ry = blockIdx.y;
+  if (XIN & XIN_X) x += ry * g.tot;
+  b += ry * g.tot;
+  if (XIN & XIN_E) e += ry * gc.tot;
+  out += ry * g.tot;
+  int o0, o1, o2;
+  if (!tile_origin(tg, TX, TY, ZC, o0, o1, o2)) return;
+  const int s0 = o0 - 1, s1 = o1 - 1;
+  const int c0 = s0 >> 1, c1 = s1 >> 1, c2 = (o2 - 1) >> 1;
+  if (XIN & XIN_E) {
+    constexpr int tot = EX * EY * EZ, NIT = (tot + 255) / 256;
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+      const int k = min((int)threadIdx.x + 256 * it, tot - 1);
+      const int a = k % EX, q = k / EX;
+      const int j0 = c0 + a, j1 = c1 + q % EY, j2 = c2 + q / EY;
+      int l0 = j0, l1 = j1, l2 = j2;
+      clamp_node(gc, l0, l1, l2);
+      C v = e[flat(gc, l0, l1, l2)];
+      if (!inside(gc, j0, j1, j2)) v = mk((R)0, (R)0);
+      if ((int)threadIdx.x + 256 * it < tot) es[k] = v;
+    }
+    __syncthreads();
+  }
+  ZSlots sl[NS];
+#pragma unroll
+  for (int u = 0; u < NS; ++u) {
+    const int k = min((int)threadIdx.x + 256 * u, PL - 1);
+    const int a = k % SX, q = k / SX;
+    const int i0 = s0 + a, i1 = s1 + q;
+    sl[u].k = k;
+    sl[u].j0 = min(max(i0, 0), g.n[0]);
+    sl[u].j1 = min(max(i1, 0), g.n[1]);
+    sl[u].fxy = sl[u].j0 + g.N[0] * sl[u].j1;
+    sl[u].in = (int)threadIdx.x + 256 * u < PL && i0 >= 0 && i0 <= g.n[0] && i1 >= 0 && i1 <= g.n[1];
+    sl[u].own = sl[u].in && a >= 1 && a <= TX && q >= 1 && q <= TY;
+  }
+  const int NP = g.N[0] * g.N[1];
+  // two register sets of plane inputs: plane q in set q & 1, requested two planes ahead
+  C rx[2][NS];
+  CB rb[2][NS];
+  A ra[2][NS];
+  auto load = [&](auto S, int z) {
+    constexpr int s = decltype(S)::value;
+    const int base = NP * min(max(z, 0), g.n[2]);
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      const int f = base + sl[u].fxy;
+      if (XIN & XIN_X) rx[s][u] = x[f];
+      rb[s][u] = b[f];
+      ra[s][u] = op.aux(f);
+    }
+  };
+  // x_in of plane z (inputs in set S) into its ring slot; bo, Do receive its b and D
+  auto stage = [&](auto S, int z, C* bo, C* Do) {
+    constexpr int s = decltype(S)::value;
+    const int jz = min(max(z, 0), g.n[2]);
+    const bool inz = z >= 0 && z <= g.n[2];
+    C* dst = ring + (z & 3) * PL;
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      const C D = op.diag_aux(ra[s][u], sl[u].j0, sl[u].j1, jz);
+      const C bb = conv<C>::from(rb[s][u]);
+      C v = mk((R)0, (R)0);
+      if (XIN & XIN_X) v += rx[s][u];
+      if (XIN & XIN_Z) v += w_in * jdiv(bb, D);
+      if (XIN & XIN_E) v += prolong_lds<3>(es, EX, EY, c0, c1, c2, sl[u].j0, sl[u].j1, jz);
+      if (!(sl[u].in && inz)) v = mk((R)0, (R)0);
+      if ((int)threadIdx.x + 256 * u < PL) dst[sl[u].k] = v;
+      bo[u] = bb;
+      Do[u] = D;
+    }
+  };
+  const std::integral_constant<int, 0> S0;
+  const std::integral_constant<int, 1> S1;
+  const int zend = min(o2 + ZC, g.n[2] + 1);        // output planes o2 .. zend - 1 (o2 even)
+  C bA[NS], DA[NS], bB[NS], DB[NS];
+  load(S1, o2 - 1);
+  stage(S1, o2 - 1, bA, DA);
+  load(S0, o2);
+  load(S1, o2 + 1);
+  stage(S0, o2, bA, DA);
+  load(S0, o2 + 2);
+  // plane p: stage p + 1 (set S, = (p + 1) & 1), refill S with p + 3, output p
+  auto plane = [&](auto S, int p) {
+    stage(S, p + 1, bB, DB);
+    if (p + 3 <= zend) load(S, p + 3);
+    __syncthreads();
+    const C* xm = ring + ((p - 1) & 3) * PL;
+    const C* x0 = ring + (p & 3) * PL;
+    const C* xp = ring + ((p + 1) & 3) * PL;
+    const int base = NP * p;
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      if (sl[u].own) {
+        const int f = base + sl[u].fxy;
+        const C r = bA[u] - op.ax3(xm, x0, xp, sl[u].k, SX, f, DA[u]);
+        out[f] = conv<CO>::from(x0[sl[u].k] + w * jdiv(r, DA[u]));
+      }
+      bA[u] = bB[u];
+      DA[u] = DB[u];
+    }
+  };
+  for (int p = o2; p < zend; p += 2) {
+    plane(S1, p);
+    if (p + 1 < zend) plane(S0, p + 1);
+  }
+}
+
+// b_c(I) = sum_f R(I, f) (b - A x_in)(f) over a coarse xy tile and CZ coarse planes: the
+// fine residual planes 2 Z - 1, 2 Z, 2 Z + 1 of coarse plane Z arrive in that order, and
+// each coarse node's sum takes their terms in the box kernel's order (one accumulator for
+// plane Z, one started for Z + 1 by the odd plane they share)
+template <class Op, typename CB, int XIN, int BV>
+__global__ void __launch_bounds__(256) k_restrict_z(Op op, const typename Op::C* __restrict__ x,
+                                                    const CB* __restrict__ b, typename Op::Real w_in, Geom g2,
+                                                    typename Op::C* __restrict__ b2, TileGrid tg) {
+  typedef typename Op::C C;
+  typedef typename Op::Real R;
+  typedef typename Op::Aux A;
+  constexpr int CX = ZRBox<BV>::x, CY = ZRBox<BV>::y, CZ = ZRBox<BV>::z;
+  constexpr int RX = 2 * CX + 1, RY = 2 * CY + 1;
+  constexpr int SX = RX + 2, SY = RY + 2, PL = SX * SY, NS = (PL + 255) / 256;
+  static_assert(CX * CY <= 256, "one coarse node per thread");
+  __shared__ C ring[4 * PL];
+  __shared__ C rbuf[2 * PL];
+  const Geom& g = op.geom();
+  const long long ry = blockIdx.y;
+  if (XIN & XIN_X) x += ry * g.tot;
+  b += ry * g.tot;
+  b2 += ry * g2.tot;
+  int O0, O1, O2;
+  if (!tile_origin(tg, CX, CY, CZ, O0, O1, O2)) return;
+  const int s0 = 2 * O0 - 2, s1 = 2 * O1 - 2;       // staged region: residual region - 1
+  ZSlots sl[NS];
+#pragma unroll
+  for (int u = 0; u < NS; ++u) {
+    const int k = min((int)threadIdx.x + 256 * u, PL - 1);
+    const int a = k % SX, q = k / SX;
+    const int i0 = s0 + a, i1 = s1 + q;
+    sl[u].k = k;
+    sl[u].j0 = min(max(i0, 0), g.n[0]);
+    sl[u].j1 = min(max(i1, 0), g.n[1]);
+    sl[u].fxy = sl[u].j0 + g.N[0] * sl[u].j1;
+    sl[u].in = (int)threadIdx.x + 256 * u < PL && i0 >= 0 && i0 <= g.n[0] && i1 >= 0 && i1 <= g.n[1];
+    sl[u].own = (int)threadIdx.x + 256 * u < PL && a >= 1 && a <= RX && q >= 1 && q <= RY;
+  }
+  const int NP = g.N[0] * g.N[1];
+  // two register sets of plane inputs: plane q in set q & 1, requested two planes ahead
+  C rx[2][NS];
+  CB rb[2][NS];
+  A ra[2][NS];
+  auto load = [&](auto S, int z) {
+    constexpr int s = decltype(S)::value;
+    const int base = NP * min(max(z, 0), g.n[2]);
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      const int f = base + sl[u].fxy;
+      if (XIN & XIN_X) rx[s][u] = x[f];
+      rb[s][u] = b[f];
+      ra[s][u] = op.aux(f);
+    }
+  };
+  auto stage = [&](auto S, int z, C* bo, C* Do) {
+    constexpr int s = decltype(S)::value;
+    const int jz = min(max(z, 0), g.n[2]);
+    const bool inz = z >= 0 && z <= g.n[2];
+    C* dst = ring + (z & 3) * PL;
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      const C D = op.diag_aux(ra[s][u], sl[u].j0, sl[u].j1, jz);
+      const C bb = conv<C>::from(rb[s][u]);
+      C v = mk((R)0, (R)0);
+      if (XIN & XIN_X) v += rx[s][u];
+      if (XIN & XIN_Z) v += w_in * jdiv(bb, D);
+      if (!(sl[u].in && inz)) v = mk((R)0, (R)0);
+      if ((int)threadIdx.x + 256 * u < PL) dst[sl[u].k] = v;
+      bo[u] = bb;
+      Do[u] = D;
+    }
+  };
+  const std::integral_constant<int, 0> S0;
+  const std::integral_constant<int, 1> S1;
+  // this thread's coarse node
+  const int t = threadIdx.x;
+  const bool cown = t < CX * CY;
+  const int ca = t % CX, cb = t / CX;
+  const bool cin = cown && O0 + ca <= g2.n[0] && O1 + cb <= g2.n[1];
+  const int zc_end = min(O2 + CZ, g2.n[2] + 1);      // coarse planes O2 .. zc_end - 1
+  const int p0 = 2 * O2 - 1, p1 = 2 * zc_end - 1;    // fine residual planes p0 .. p1 (p0 odd)
+  C accA = mk((R)0, (R)0), accB = mk((R)0, (R)0);
+  C bA[NS], DA[NS], bB[NS], DB[NS];
+  load(S0, p0 - 1);
+  stage(S0, p0 - 1, bA, DA);
+  load(S1, p0);
+  load(S0, p0 + 1);
+  stage(S1, p0, bA, DA);
+  load(S1, p0 + 2);
+  // residual plane p: stage p + 1 (set S, = (p + 1) & 1), refill S with p + 3
+  auto plane = [&](auto S, int p) {
+    stage(S, p + 1, bB, DB);
+    if (p + 3 <= p1 + 1) load(S, p + 3);
+    __syncthreads();
+    const C* xm = ring + ((p - 1) & 3) * PL;
+    const C* x0 = ring + (p & 3) * PL;
+    const C* xp = ring + ((p + 1) & 3) * PL;
+    C* rs = rbuf + (p & 1) * PL;
+    const bool inz = p >= 0 && p <= g.n[2];
+    const int base = NP * p;
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      if (sl[u].own) {
+        C v = mk((R)0, (R)0);
+        if (sl[u].in && inz) {
+          v = bA[u];
+          if (XIN) v -= op.ax3(xm, x0, xp, sl[u].k, SX, base + sl[u].fxy, DA[u]);
+        }
+        rs[sl[u].k] = v;
+      }
+      bA[u] = bB[u];
+      DA[u] = DB[u];
+    }
+    __syncthreads();
+    if (cown) {
+      // the 3 x 3 in-plane terms of this residual plane, weights w0 w1 w2 as in k_restrict
+      auto terms = [&](C acc, R w2) {
+#pragma unroll
+        for (int d1 = -1; d1 <= 1; ++d1) {
+          const R w1 = d1 == 0 ? (R)0.5 : (R)0.25;
+#pragma unroll
+          for (int d0 = -1; d0 <= 1; ++d0) {
+            const R w0 = d0 == 0 ? (R)0.5 : (R)0.25;
+            acc += (w0 * w1 * w2) * rs[(2 * ca + 2 + d0) + SX * (2 * cb + 2 + d1)];
+          }
+        }
+        return acc;
+      };
+      if ((p & 1) == 0) {
+        accA = terms(accA, (R)0.5);                  // d2 = 0 of plane p / 2
+      } else {
+        const int Z = (p - 1) >> 1;                  // d2 = +1 of Z, then d2 = -1 of Z + 1
+        if (Z >= O2) {
+          accA = terms(accA, (R)0.25);
+          if (cin) b2[flat(g2, O0 + ca, O1 + cb, Z)] = accA;
+        }
+        if (Z + 1 < zc_end) accB = terms(mk((R)0, (R)0), (R)0.25);
+        accA = accB;
+      }
+    }
+  };
+  for (int p = p0; p <= p1; p += 2) {
+    plane(S0, p);
+    if (p + 1 <= p1) plane(S1, p + 1);
+  }
+}
+
 // y = A x for the outer operator (FP64 arithmetic), x in c64 or c128
 template <typename CX>
 __global__ void __launch_bounds__(256) k_l1_apply64(L1<double> A, const CX* __restrict__ x,
@@ -559,13 +876,41 @@ void sweep_box(const Op& op, int xin, const typename Op::C* x, const CB* b, type
 #undef SW
 }
 
+template <class Op, typename CB, typename CO, int BV>
+void sweep_z(const Op& op, int xin, const typename Op::C* x, const CB* b, typename Op::Real w_in, const Geom& gc,
+             const typename Op::C* e, typename Op::Real w, CO* out, int nrhs, hipStream_t s) {
+  TileGrid tg = tiles(op.geom(), ZSBox<BV>::x, ZSBox<BV>::y, ZSBox<BV>::z);
+  dim3 grid(grid_tiles(tg), nrhs), blk(256);
+#define SW(F) hipLaunchKernelGGL((k_sweep_z<Op, CB, CO, F, BV>), grid, blk, 0, s, op, x, b, w_in, gc, e, w, out, tg)
+  switch (xin) {
+    case XIN_X: SW(XIN_X); break;
+    case XIN_Z: SW(XIN_Z); break;
+    case XIN_E: SW(XIN_E); break;
+    case XIN_X | XIN_E: SW(XIN_X | XIN_E); break;
+    case XIN_Z | XIN_E: SW(XIN_Z | XIN_E); break;
+    default: break;
+  }
+#undef SW
+}
+
 template <int DIM, class Op, typename CB, typename CO>
 void sweep_dim(const Op& op, int xin, const typename Op::C* x, const CB* b, typename Op::Real w_in,
                const Geom& gc, const typename Op::C* e, typename Op::Real w, CO* out, int nrhs, hipStream_t s) {
-  // the FP64 cycle's 3D boxes stay at variant 0 (the larger ones exceed the block's LDS)
+  // the FP64 cycle's 3D boxes stay at variant 0 (the larger ones exceed the block's LDS);
+  // the z-marching variants are 3D (variant 0 in 2D), and a sweep from nothing (xin 0,
+  // which materialises zero) keeps the box kernel
   const int v = (DIM == 3 && sizeof(typename Op::C) == 16) ? 0 : op.A.box_sweep;
   if constexpr (DIM == 3 && sizeof(typename Op::C) == 16) {
     sweep_box<DIM, Op, CB, CO, 0>(op, xin, x, b, w_in, gc, e, w, out, nrhs, s);
+  } else if constexpr (DIM == 3) {
+    switch (xin == 0 ? 0 : v) {
+      case 1: sweep_box<DIM, Op, CB, CO, 1>(op, xin, x, b, w_in, gc, e, w, out, nrhs, s); break;
+      case 2: sweep_box<DIM, Op, CB, CO, 2>(op, xin, x, b, w_in, gc, e, w, out, nrhs, s); break;
+      case 3: sweep_box<DIM, Op, CB, CO, 3>(op, xin, x, b, w_in, gc, e, w, out, nrhs, s); break;
+      case 4: sweep_z<Op, CB, CO, 4>(op, xin, x, b, w_in, gc, e, w, out, nrhs, s); break;
+      case 5: sweep_z<Op, CB, CO, 5>(op, xin, x, b, w_in, gc, e, w, out, nrhs, s); break;
+      default: sweep_box<DIM, Op, CB, CO, 0>(op, xin, x, b, w_in, gc, e, w, out, nrhs, s); break;
+    }
   } else {
     switch (v) {
       case 1: sweep_box<DIM, Op, CB, CO, 1>(op, xin, x, b, w_in, gc, e, w, out, nrhs, s); break;
@@ -591,11 +936,32 @@ void restrict_box(const Op& op, int xin, const typename Op::C* x, const CB* b, t
 #undef RS
 }
 
+template <class Op, typename CB, int BV>
+void restrict_z(const Op& op, int xin, const typename Op::C* x, const CB* b, typename Op::Real w_in,
+                const Geom& g2, typename Op::C* b2, int nrhs, hipStream_t s) {
+  TileGrid tg = tiles(g2, ZRBox<BV>::x, ZRBox<BV>::y, ZRBox<BV>::z);
+  dim3 grid(grid_tiles(tg), nrhs), blk(256);
+  if (xin == XIN_X)
+    hipLaunchKernelGGL((k_restrict_z<Op, CB, XIN_X, BV>), grid, blk, 0, s, op, x, b, w_in, g2, b2, tg);
+  else if (xin == XIN_Z)
+    hipLaunchKernelGGL((k_restrict_z<Op, CB, XIN_Z, BV>), grid, blk, 0, s, op, x, b, w_in, g2, b2, tg);
+}
+
 template <int DIM, class Op, typename CB>
 void restrict_dim(const Op& op, int xin, const typename Op::C* x, const CB* b, typename Op::Real w_in,
                   const Geom& g2, typename Op::C* b2, int nrhs, hipStream_t s) {
   if constexpr (DIM == 3 && sizeof(typename Op::C) == 16) {
     restrict_box<DIM, Op, CB, 0>(op, xin, x, b, w_in, g2, b2, nrhs, s);
+  } else if constexpr (DIM == 3) {
+    // the z-marching variants take an iterate (xin X or Z); restricting b alone keeps the
+    // box kernel
+    switch (xin == 0 ? 0 : op.A.box_restrict) {
+      case 1: restrict_box<DIM, Op, CB, 1>(op, xin, x, b, w_in, g2, b2, nrhs, s); break;
+      case 2: restrict_box<DIM, Op, CB, 2>(op, xin, x, b, w_in, g2, b2, nrhs, s); break;
+      case 3: restrict_z<Op, CB, 3>(op, xin, x, b, w_in, g2, b2, nrhs, s); break;
+      case 4: restrict_z<Op, CB, 4>(op, xin, x, b, w_in, g2, b2, nrhs, s); break;
+      default: restrict_box<DIM, Op, CB, 0>(op, xin, x, b, w_in, g2, b2, nrhs, s); break;
+    }
   } else {
     switch (op.A.box_restrict) {
       case 1: restrict_box<DIM, Op, CB, 1>(op, xin, x, b, w_in, g2, b2, nrhs, s); break;

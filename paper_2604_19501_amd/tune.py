@@ -185,11 +185,12 @@ def tune_boxes(n, prec, sched, verbose=True):
     gain); a variant replaces the default when its class time is 2 % lower.  Returns (boxes
     string, {class: ms} of the choice)."""
     classes = ("l1_sweep", "l1_restrict", "l2_sweep", "l2_restrict")
-    nvar = (4, 3, 4, 3)
+    # 3D adds the z-marching tiles (sweeps 4 and 5, restrictions 3 and 4)
+    nvar = (6, 5, 6, 5) if len(n) == 3 else (4, 3, 4, 3)
     base = class_times(n, prec, sched, "0,0,0,0")
     boxes = [0, 0, 0, 0]
     best_ms = {c: base[c] for c in classes}
-    for v in range(1, 4):
+    for v in range(1, max(nvar)):
         trial = [v if v < nvar[q] else 0 for q in range(4)]
         bx = ",".join(map(str, trial))
         kt = class_times(n, prec, sched, bx)

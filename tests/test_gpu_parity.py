@@ -175,11 +175,12 @@ def test_cycle_rectangular_multi_tile(n, nu):
 
 
 @pytest.mark.parametrize("n", [(136, 72), (40, 24, 32), (200, 136)])
-@pytest.mark.parametrize("boxes", ["1,1,1,1", "2,2,2,2", "3,0,3,0"])
+@pytest.mark.parametrize("boxes", ["1,1,1,1", "2,2,2,2", "3,0,3,0", "4,3,4,3", "5,4,5,4"])
 def test_cycle_box_variants(monkeypatch, n, boxes):
     """every box-shape variant of the tiled cycle kernels (level-1/level-2 sweeps and
-    restrictions), on grids with several tiles per axis and ragged last tiles, against the
-    oracle element by element (the FP64 3D kernels keep the default boxes)"""
+    restrictions; 4/5 and 3/4 the 3D z-marching tiles, several z-chunks with a ragged last
+    one), on grids with several tiles per axis and ragged last tiles, against the oracle
+    element by element (the FP64 3D kernels keep the default boxes)"""
     monkeypatch.setenv("HELM_BOXES", boxes)
     p = rect_problem(n)
     print("cycle boxes", n, boxes, flush=True)
@@ -192,6 +193,27 @@ def test_cycle_box_variants(monkeypatch, n, boxes):
         assert rel(z, ref) < tol, (prec, rel(z, ref))
         assert maxabs_rel(z, ref) < TOL_INF[prec], (prec, maxabs_rel(z, ref))
         s.close()
+
+
+@pytest.mark.parametrize("n", [(40, 24, 32), (64, 64, 64)])
+def test_z_marching_tiles_match_box_tiles(monkeypatch, n):
+    """the 3D z-marching sweep and restriction tiles take the box kernels' sums in the same
+    order: the FP32 cycle through them equals the default boxes' to rounding (printed: the
+    largest difference relative to the largest entry)"""
+    p = rect_problem(n)
+    r = _rand(p.N, 8)
+    out = {}
+    for boxes in ("0,0,0,0", "4,3,4,3", "5,4,5,4"):
+        monkeypatch.setenv("HELM_BOXES", boxes)
+        print("z tiles", n, boxes, flush=True)
+        s = from_problem(p, cycle=2, nu=(1, 1), cycle_prec="f32")
+        out[boxes] = s.vcycle(r).cpu().numpy()
+        s.close()
+    ref = out["0,0,0,0"]
+    for boxes in ("4,3,4,3", "5,4,5,4"):
+        d = np.abs(out[boxes] - ref).max() / np.abs(ref).max()
+        print("  %s: max difference %.3e of the largest entry" % (boxes, d), flush=True)
+        assert d < 1e-6, (boxes, d)
 
 
 @pytest.mark.parametrize("restart", [20, 4])
