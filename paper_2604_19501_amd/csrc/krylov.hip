@@ -316,6 +316,13 @@ __device__ void givens_column(const KrylovArgs& a, KrylovState* st, int j, doubl
   for (int i = t; i <= j; i += 64) st->c[i] = sc[i];
 }
 
+// the column's finish as a launch of its own (one wavefront), after k_fin_sum
+__global__ void __launch_bounds__(64) k_givens(KrylovArgs a, int j, double tol) {
+  KrylovState* st = at_rhs(a).st;
+  if (st->done) return;            // converged in an earlier column: the state stays as it is
+  givens_column(a, st, j, tol);
+}
+
 // one block per value: st->h1[i] = sum over the dot pass's blocks of part[i]; the block
 // that stores the last of the 2 j + 3 sums of its right-hand side (a device-scope ticket,
 // returned to zero by that block) then finishes the column (givens_column) and, with
@@ -526,7 +533,8 @@ void kr_residual(const KrylovArgs& a, const cd* x, const cd* b, int with_b, hipS
 void kr_scale_v0(const KrylovArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_scale_v0, dim3(a.nblk, a.nrhs), dim3(256), 0, s, a);
 }
-void kr_arnoldi(const KrylovArgs& a, const void* z, int z_f32, int j, double tol, void* pack_dst, hipStream_t s) {
+void kr_arnoldi(const KrylovArgs& a, const void* z, int z_f32, int j, double tol, void* pack_dst, int fused,
+                hipStream_t s) {
   dim3 g(a.nblk, a.nrhs);
   const int cmp = a.op.compact;
   if (z_f32 && !cmp)
@@ -537,7 +545,13 @@ void kr_arnoldi(const KrylovArgs& a, const void* z, int z_f32, int j, double tol
     hipLaunchKernelGGL((k_arnoldi_dots<cf, 1>), g, dim3(256), 0, s, a, (const cf*)z, j);
   else
     hipLaunchKernelGGL((k_arnoldi_dots<cd, 1>), g, dim3(256), 0, s, a, (const cd*)z, j);
-  hipLaunchKernelGGL(k_fin_givens, dim3(2 * j + 3, a.nrhs), dim3(256), 0, s, a, j, tol, (char*)pack_dst);
+  if (fused) {
+    hipLaunchKernelGGL(k_fin_givens, dim3(2 * j + 3, a.nrhs), dim3(256), 0, s, a, j, tol, (char*)pack_dst);
+  } else {
+    hipLaunchKernelGGL(k_fin_sum, dim3(2 * j + 3, a.nrhs), dim3(256), 0, s, a, offsetof(KrylovState, h1));
+    hipLaunchKernelGGL(k_givens, dim3(1, a.nrhs), dim3(64), 0, s, a, j, tol);
+    if (pack_dst) hipLaunchKernelGGL(k_pack_states, dim3(1), dim3(256), 0, s, a.st, (char*)pack_dst, a.nrhs);
+  }
   if (z_f32 && !cmp)
     hipLaunchKernelGGL((k_arnoldi_update<cf, 0>), g, dim3(256), 0, s, a, (const cf*)z, j);
   else if (!cmp)
