@@ -33,8 +33,10 @@ void nd_assemble(const NDFrontDev* fr, const int* ids, int nids, int max_asm, co
                  cd* Fp, hipStream_t s);
 void nd_extend(const NDFrontDev* fr, const int* ids, int nids, long long max_nb2, const int* children,
                const long long* child_map_off, const int* maps, cd* Fp, int slot, hipStream_t s);
-void nd_panel_multi(const NDFrontDev* fr, const int* ids, int nids, int max_nF, cd* Fp, int* perm, int* swp,
-                    PivCand* cand, cd* rkb, int k0, int kb, int max_nS, int* err, hipStream_t s);
+// Fp: the fronts; Pb: a panel buffer of max_nF (rounded to 32) x kb entries per front;
+// cand: two candidate sets of nids x ceil(max_nF / 32)
+void nd_panel_multi(const NDFrontDev* fr, int nids, int max_nF, cd* Fp, cd* Pb, int* perm, int* swp,
+                    PivCand* cand, int k0, int kb, int max_nS, int* err, hipStream_t s);
 void nd_save_t(const NDFrontDev* fr, const int* ids, int nids, const long long* toff, long long max_n, cd* Fp,
                cd* T, int k0, int kb, int u0, int un, hipStream_t s);
 void nd_gemm(const NDFrontDev* fr, const int* ids, int nids, const long long* toff, int max_rows, int max_cols,
@@ -104,7 +106,7 @@ struct NDDev {        // device-side ND tables (pointers into the workspace)
   long long* child_map_off = nullptr;
   NDAsm* asmv = nullptr;
   long long* toff = nullptr;
-  cd *F = nullptr, *T = nullptr, *rkb = nullptr;
+  cd *F = nullptr, *T = nullptr, *pb = nullptr;   // pb: multi-work-group panel buffer
   PivCand* cand = nullptr;
   void *L = nullptr, *W = nullptr;
   std::vector<NDLaunchDev> launch[2];   // forward, backward
@@ -564,15 +566,21 @@ size_t carve(helm_ctx* c, void* ws) {
   {
     size_t mx = 1;
     size_t nc = 1;     // pivot candidates of the multi-work-group panels: fronts x row blocks of 32
+    size_t pbr = 1;    // panel-buffer rows: fronts x rows rounded to 32, over the multi-panel heights
+    // every height takes the multi-work-group panel when HELM_ND_LDS_PANEL is 0, else those
+    // whose fronts are too large for the register panel (as nd_factor decides)
+    const bool all_multi = getenv("HELM_ND_LDS_PANEL") && env_int("HELM_ND_LDS_PANEL", 0) <= 0;
     for (auto& h : P.by_height) {
       mx = std::max(mx, h.size());
       int mf = 0;
       for (int t : h) mf = std::max(mf, P.fronts[t].nF);
-      nc = std::max(nc, h.size() * (size_t)((mf + 31) / 32));
+      const size_t rows = h.size() * (size_t)((mf + 31) / 32) * 32;
+      nc = std::max(nc, rows / 32);
+      if (all_multi || panel_reg_kb(mf) == 0) pbr = std::max(pbr, rows);
     }
     d.swp = cv.take<int>((size_t)ND_KBMAX * mx);
-    d.cand = cv.take<PivCand>(nc);
-    d.rkb = cv.take<cd>((size_t)(ND_KBMAX + 1) * mx);
+    d.cand = cv.take<PivCand>(2 * nc);
+    d.pb = cv.take<cd>(pbr * ND_KBMAX);
   }
   d.asmv = cv.take<NDAsm>(P.asmv.size());
   d.perm = cv.take<int>(P.perm_total);
@@ -697,8 +705,7 @@ void nd_factor(helm_ctx* c, hipStream_t s) {
         if (reg_panel)
           nd_panel_reg(hf, nullptr, hi.count, hi.max_nF, d.F, d.perm, d.swp, k1, kb, d.err, s);
         else
-          nd_panel_multi(hf, nullptr, hi.count, hi.max_nF, d.F, d.perm, d.swp, d.cand, d.rkb, k1, kb, hi.max_nS,
-                         d.err, s);
+          nd_panel_multi(hf, hi.count, hi.max_nF, d.F, d.pb, d.perm, d.swp, d.cand, k1, kb, hi.max_nS, d.err, s);
         if (kout > kb) {        // the block's other panels, earlier ones included
           nd_save_t(hf, nullptr, hi.count, toff, (long long)kb * kout, d.F, d.T, k1, kb, k0, kout, s);
           nd_gemm(hf, nullptr, hi.count, toff, hi.max_nF, kout, d.F, d.T, k1, kb, k0, kout, s);

@@ -230,11 +230,11 @@ __global__ void __launch_bounds__(NT) k_nd_panel_reg(const NDFrontDev* __restric
 // Panel [k0, k0 + kbb) of fronts too large for an LDS-resident panel: every pivot step
 // is spread over work-groups of PROWS rows.
 //   k_piv_search   argmax of |F[i][k0]| over the S rows i >= k0 of each row block
-//   k_piv_select   one work-group per front: reduce the block candidates (ties: lower
-//                  row), swap the two rows' panel entries, stage the pivot row and its
-//                  inverse; the swap of the other columns is recorded (k_nd_swap_rest)
-//   k_piv_update   the exchange of pivot k on the panel columns of a row block, and the
-//                  block's candidate for the next pivot column
+//   k_piv_step     one launch per pivot: the pivot from the block candidates, the exchange
+//                  of its row block from one panel copy into the other, and the block's
+//                  candidate for the next column; the swap of the other columns is
+//                  recorded (k_nd_swap_rest)
+//   k_piv_back     the panel copied back into the front where its column count is odd
 // Arithmetic and pivot choice are those of the single-work-group exchange, so the
 // factors do not depend on which path a front takes.
 #define PROWS 32
@@ -274,103 +274,92 @@ __global__ void __launch_bounds__(256) k_piv_search(const NDFrontDev* __restrict
   if (threadIdx.x == 0) cand[(long long)blockIdx.y * nblk + blockIdx.x] = PivCand{sv[0], si[0], 0};
 }
 
-__global__ void __launch_bounds__(64) k_piv_select(const NDFrontDev* __restrict__ fr, const int* __restrict__ ids,
-                                                   cd* __restrict__ Fp, int* __restrict__ perm, int* __restrict__ swp,
-                                                   int k0, int kb, int kk, const PivCand* __restrict__ cand, int nblk,
-                                                   cd* __restrict__ rkb, int* __restrict__ err) {
-  const NDFrontDev f = front_at(fr, ids, blockIdx.x);
-  const int k = k0 + kk;
-  if (f.nS <= k) return;
-  const int kbb = min(kb, f.nS - k0);
-  const int nb = (f.nF + PROWS - 1) / PROWS;
-  __shared__ double sv[1];
-  __shared__ int si[1];
-  cd* F = Fp + f.F_off;
-  const int t = threadIdx.x;
-  // row k's panel entries do not depend on the pivot: their load overlaps the reduction
-  cd a = mk(0.0, 0.0);
-  if (t < kbb) a = F[(long long)k * f.nF + k0 + t];
-  // candidates of the blocks that hold S rows >= k
-  double best = -1.0;
-  int bi = 0x7fffffff;
-  for (int b = (int)threadIdx.x + k / PROWS; b < nb && b * PROWS < f.nS; b += 64) {
-    PivCand c = cand[(long long)blockIdx.x * nblk + b];
-    if (c.v > best || (c.v == best && c.i < bi)) { best = c.v; bi = c.i; }
-  }
-  for (int o = 32; o > 0; o >>= 1) {
-    double ov = __shfl_xor(best, o, 64);
-    int oi = __shfl_xor(bi, o, 64);
-    if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
-  }
-  if (threadIdx.x == 0) { sv[0] = best; si[0] = bi; }
-  __syncthreads();
-  const double pv = sv[0];
-  const int p = pv >= 0.0 && si[0] < f.nS ? si[0] : k;
-  cd* rk = rkb + (long long)blockIdx.x * (ND_KBMAX + 1);
-  if (t < kbb) {
-    if (p != k) {
-      cd b = F[(long long)p * f.nF + k0 + t];
-      F[(long long)k * f.nF + k0 + t] = b;
-      F[(long long)p * f.nF + k0 + t] = a;
-      a = b;
-    }
-    rk[t] = a;
-  }
-  __syncthreads();
-  if (t == 0) {
-    swp[(long long)blockIdx.x * ND_KBMAX + kk] = p;
-    if (p != k) {
-      int q = perm[f.perm_off + k];
-      perm[f.perm_off + k] = perm[f.perm_off + p];
-      perm[f.perm_off + p] = q;
-    }
-    cd piv = rk[kk];
-    if (!(pv > 0.0)) {
-      atomicOr(err, 1);
-      piv = mk(1.0, 0.0);
-    }
-    rk[ND_KBMAX] = cdiv(mk(1.0, 0.0), piv);
-  }
-}
-
-// CW lanes per row (the panel's width rounded up to 32 or 64), 256 / CW rows per pass.  All
-// loads of the block's rows are issued before the first store, so one memory round trip
-// serves the whole block; lane kk's store of row[kk] follows every read of it in the wave.
+// One pivot step of a multi-work-group panel in one launch.  Every work-group reduces the
+// row blocks' candidates to the pivot p exactly as a single reduction would (the larger
+// value, the lower row on ties), reads the pivot row, and writes the exchange update of its
+// rows from the panel copy S into the other copy D: the front itself and a panel buffer
+// alternate by column, so no work-group reads what another writes in the same launch, and
+// rows k and p are read exchanged instead of being swapped in place.  The front's first
+// work-group records the swap and the permutation.  The arithmetic is that of the
+// single-work-group exchange, so the factors do not depend on the path a front takes.
 template <int CW>
-__global__ void __launch_bounds__(256) k_piv_update(const NDFrontDev* __restrict__ fr, const int* __restrict__ ids,
-                                                    cd* __restrict__ Fp, int k0, int kb, int kk,
-                                                    const cd* __restrict__ rkb, PivCand* __restrict__ cand,
-                                                    int nblk) {
+__global__ void __launch_bounds__(256) k_piv_step(const NDFrontDev* __restrict__ fr, cd* __restrict__ Fp,
+                                                  cd* __restrict__ Pb, long long pstride, int s_is_pb, int k0, int kb,
+                                                  int kk, const PivCand* __restrict__ cin, PivCand* __restrict__ cout,
+                                                  int nblk, int* __restrict__ perm, int* __restrict__ swp,
+                                                  int* __restrict__ err) {
   constexpr int RPP = 256 / CW, NP = PROWS / RPP;
-  __shared__ cd srk[ND_KBMAX + 1];
+  __shared__ cd srk[ND_KBMAX];
   __shared__ double sv[4];
   __shared__ int si[4];
-  const NDFrontDev f = front_at(fr, ids, blockIdx.y);
+  const NDFrontDev f = fr[blockIdx.y];
   const int k = k0 + kk;
   if (f.nS <= k || (int)blockIdx.x * PROWS >= f.nF) return;
   const int kbb = min(kb, f.nS - k0);
-  if (threadIdx.x < ND_KBMAX + 1) srk[threadIdx.x] = rkb[(long long)blockIdx.y * (ND_KBMAX + 1) + threadIdx.x];
-  cd* F = Fp + f.F_off;
-  const int jj = threadIdx.x & (CW - 1), rsub = threadIdx.x / CW;
+  // row i of the panel: F + F_off + i nF + k0 in the front, Pb + y pstride + i kb in the buffer
+  cd* const Fr = Fp + f.F_off + k0;
+  cd* const Pr = Pb + (long long)blockIdx.y * pstride;
+  const cd* const S = s_is_pb ? Pr : Fr;
+  cd* const D = s_is_pb ? Fr : Pr;
+  const long long lS = s_is_pb ? kb : f.nF, lD = s_is_pb ? f.nF : kb;
+  const int t = threadIdx.x;
+  const int jj = t & (CW - 1), rsub = t / CW;
   const int r0 = (int)blockIdx.x * PROWS + rsub;
   const int jl = min(jj, kbb - 1);
+  // the block's rows as they stand (rows k and p are read again below, exchanged): these
+  // loads do not depend on the pivot and overlap its reduction
   cd ckv[NP], rv[NP];
 #pragma unroll
   for (int q = 0; q < NP; ++q) {
     const long long i = min(r0 + RPP * q, f.nF - 1);
-    ckv[q] = F[i * f.nF + k0 + kk];
-    rv[q] = F[i * f.nF + k0 + jl];
+    ckv[q] = S[i * lS + kk];
+    rv[q] = S[i * lS + jl];
   }
-  __syncthreads();
-  const cd inv = srk[ND_KBMAX];
-  const bool next = kk + 1 < kbb;
   double best = -1.0;
   int bi = 0x7fffffff;
+  const int nb = (f.nF + PROWS - 1) / PROWS;
+  for (int b = t + k / PROWS; b < nb && b * PROWS < f.nS; b += 256) {
+    const PivCand c = cin[(long long)blockIdx.y * nblk + b];
+    if (c.v > best || (c.v == best && c.i < bi)) {
+      best = c.v;
+      bi = c.i;
+    }
+  }
+  cand_argmax(best, bi, sv, si, blockDim.x);
+  const double pv = sv[0];
+  const int p = pv >= 0.0 && si[0] < f.nS ? si[0] : k;
+  if (t < kbb) srk[t] = S[(long long)p * lS + t];      // the pivot row: old row p
+  if (blockIdx.x == 0 && t == 0) {
+    swp[(long long)blockIdx.y * ND_KBMAX + kk] = p;
+    if (p != k) {
+      const int q = perm[f.perm_off + k];
+      perm[f.perm_off + k] = perm[f.perm_off + p];
+      perm[f.perm_off + p] = q;
+    }
+    if (!(pv > 0.0)) atomicOr(err, 1);
+  }
+  // rows k and p of this block take each other's content
+#pragma unroll
+  for (int q = 0; q < NP; ++q) {
+    const int i = r0 + RPP * q;
+    if (p != k && i < f.nF && (i == k || i == p)) {
+      const long long src = i == k ? p : k;
+      ckv[q] = S[src * lS + kk];
+      rv[q] = S[src * lS + jl];
+    }
+  }
+  __syncthreads();
+  cd piv = srk[kk];
+  if (!(pv > 0.0)) piv = mk(1.0, 0.0);
+  const cd inv = cdiv(mk(1.0, 0.0), piv);
+  const bool next = kk + 1 < kbb;
+  best = -1.0;
+  bi = 0x7fffffff;
 #pragma unroll
   for (int q = 0; q < NP; ++q) {
     const int i = r0 + RPP * q;
     if (i >= f.nF) continue;
-    cd* row = F + (long long)i * f.nF + k0;
+    cd* row = D + (long long)i * lD;
     if (i == k) {
       if (jj < kbb) row[jj] = jj == kk ? inv : -(srk[jj] * inv);
       continue;
@@ -383,13 +372,30 @@ __global__ void __launch_bounds__(256) k_piv_update(const NDFrontDev* __restrict
     }
     if (next && jj == kk + 1 && i > k && i < f.nS) {
       double v = abs2(nv);
-      if (v > best) { best = v; bi = i; }
+      if (v > best) {
+        best = v;
+        bi = i;
+      }
     }
   }
   if (next) {
     cand_argmax(best, bi, sv, si, blockDim.x);
-    if (threadIdx.x == 0) cand[(long long)blockIdx.y * nblk + blockIdx.x] = PivCand{sv[0], si[0], 0};
+    if (t == 0) cout[(long long)blockIdx.y * nblk + blockIdx.x] = PivCand{sv[0], si[0], 0};
   }
+}
+
+// fronts whose panel has an odd column count end in the buffer: copy it back
+__global__ void __launch_bounds__(256) k_piv_back(const NDFrontDev* __restrict__ fr, cd* __restrict__ Fp,
+                                                  const cd* __restrict__ Pb, long long pstride, int k0, int kb) {
+  const NDFrontDev f = fr[blockIdx.y];
+  if (f.nS <= k0) return;
+  const int kbb = min(kb, f.nS - k0);
+  if ((kbb & 1) == 0) return;
+  const int r = (int)blockIdx.x * PROWS + (int)threadIdx.x / 8;
+  if (r >= f.nF) return;
+  const cd* src = Pb + (long long)blockIdx.y * pstride + (long long)r * kb;
+  cd* dst = Fp + f.F_off + (long long)r * f.nF + k0;
+  for (int j = threadIdx.x % 8; j < kbb; j += 8) dst[j] = src[j];
 }
 
 // apply the panel's recorded row swaps to the columns outside the panel
@@ -1071,23 +1077,24 @@ void nd_extend(const NDFrontDev* fr, const int* ids, int nids, long long max_nb2
   unsigned gx = (unsigned)std::min<long long>(2048, std::max<long long>(1, (max_nb2 + 255) / 256));
   hipLaunchKernelGGL(k_nd_extend, dim3(gx, nids), dim3(256), 0, s, fr, ids, children, child_map_off, maps, Fp, slot);
 }
-void nd_panel_multi(const NDFrontDev* fr, const int* ids, int nids, int max_nF, cd* Fp, int* perm, int* swp,
-                    PivCand* cand, cd* rkb, int k0, int kb, int max_nS, int* err, hipStream_t s) {
+void nd_panel_multi(const NDFrontDev* fr, int nids, int max_nF, cd* Fp, cd* Pb, int* perm, int* swp,
+                    PivCand* cand, int k0, int kb, int max_nS, int* err, hipStream_t s) {
   const int nblk = (max_nF + PROWS - 1) / PROWS;
   const int kbb = std::min(kb, max_nS - k0);
-  hipLaunchKernelGGL(k_piv_search, dim3(nblk, nids), dim3(256), 0, s, fr, ids, Fp, k0, cand, nblk);
+  const long long pstride = (long long)nblk * PROWS * kb;     // panel-buffer entries per front
+  PivCand* cbuf[2] = {cand, cand + (size_t)nids * nblk};
+  hipLaunchKernelGGL(k_piv_search, dim3(nblk, nids), dim3(256), 0, s, fr, nullptr, Fp, k0, cbuf[0], nblk);
   for (int kk = 0; kk < kbb; ++kk) {
-    hipLaunchKernelGGL(k_piv_select, dim3(nids), dim3(64), 0, s, fr, ids, Fp, perm, swp, k0, kb, kk, cand, nblk, rkb,
-                       err);
     if (kb > 32)
-      hipLaunchKernelGGL(k_piv_update<64>, dim3(nblk, nids), dim3(256), 0, s, fr, ids, Fp, k0, kb, kk, rkb, cand,
-                         nblk);
+      hipLaunchKernelGGL(k_piv_step<64>, dim3(nblk, nids), dim3(256), 0, s, fr, Fp, Pb, pstride, kk & 1, k0, kb, kk,
+                         cbuf[kk & 1], cbuf[(kk + 1) & 1], nblk, perm, swp, err);
     else
-      hipLaunchKernelGGL(k_piv_update<32>, dim3(nblk, nids), dim3(256), 0, s, fr, ids, Fp, k0, kb, kk, rkb, cand,
-                         nblk);
+      hipLaunchKernelGGL(k_piv_step<32>, dim3(nblk, nids), dim3(256), 0, s, fr, Fp, Pb, pstride, kk & 1, k0, kb, kk,
+                         cbuf[kk & 1], cbuf[(kk + 1) & 1], nblk, perm, swp, err);
   }
+  hipLaunchKernelGGL(k_piv_back, dim3(nblk, nids), dim3(256), 0, s, fr, Fp, Pb, pstride, k0, kb);
   unsigned gx = (unsigned)std::min(64, std::max(1, (max_nF + 255) / 256));
-  hipLaunchKernelGGL(k_nd_swap_rest, dim3(gx, nids), dim3(256), 0, s, fr, ids, Fp, swp, k0, kb);
+  hipLaunchKernelGGL(k_nd_swap_rest, dim3(gx, nids), dim3(256), 0, s, fr, nullptr, Fp, swp, k0, kb);
 }
 void nd_panel_reg(const NDFrontDev* fr, const int* ids, int nids, int max_nF, cd* Fp, int* perm, int* swp, int k0,
                   int kb, int* err, hipStream_t s) {
