@@ -172,6 +172,23 @@ __global__ void __launch_bounds__(256) k_residual(KrylovArgs a, const cd* __rest
   block_sum(v, lds, p.part + blockIdx.x);
 }
 
+// this thread's share of a block-wide sum of src[0 .. n): entries threadIdx.x + 256 m in
+// increasing m; groups of 8 loads are issued before their sums, so they are in flight
+// together (the order of the sums is that of the plain loop)
+__device__ __forceinline__ cd sum_strided(const cd* __restrict__ src, int n) {
+  cd v = mk(0.0, 0.0);
+  int b = threadIdx.x;
+  for (; b + 256 * 7 < n; b += 256 * 8) {
+    cd w[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) w[u] = src[b + 256 * u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v += w[u];
+  }
+  for (; b < n; b += 256) v += src[b];
+  return v;
+}
+
 // one block per value: dst[i] = sum over blocks of part[i] (dst: the state member at off)
 __global__ void __launch_bounds__(256) k_fin_sum(KrylovArgs a, size_t off) {
   __shared__ cd lds[4];
@@ -179,7 +196,7 @@ __global__ void __launch_bounds__(256) k_fin_sum(KrylovArgs a, size_t off) {
   cd* dst = (cd*)((char*)p.st + off);
   const int i = blockIdx.x;
   cd v = mk(0.0, 0.0);
-  for (int b = threadIdx.x; b < a.nblk; b += 256) v += p.part[(long long)i * a.pcap + b];
+  v = sum_strided(p.part + (long long)i * a.pcap, a.nblk);
   block_sum(v, lds, dst + i);
 }
 
@@ -335,7 +352,7 @@ __global__ void __launch_bounds__(256) k_fin_givens(KrylovArgs a, int j, double 
   KrylovState* st = p.st;
   const int i = blockIdx.x;
   cd v = mk(0.0, 0.0);
-  for (int b = threadIdx.x; b < a.nblk; b += 256) v += p.part[(long long)i * a.pcap + b];
+  v = sum_strided(p.part + (long long)i * a.pcap, a.nblk);
   block_sum(v, lds, st->h1 + i);
   if (threadIdx.x == 0) {
     __threadfence();                     // this block's sum before its ticket

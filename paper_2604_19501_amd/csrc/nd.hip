@@ -1039,7 +1039,17 @@ __global__ void __launch_bounds__(256) k_nd_rowsum(const NDFrontDev* __restrict_
   const int i = t.r0 + threadIdx.x;
   if (i >= (FWD ? f.nF : f.nS)) return;
   C acc = mk((R)0, (R)0);
-  for (int q = 0; q < t.nkt; ++q) acc += P[t.pslot + 256 * q + threadIdx.x];
+  // in k order; groups of 8 loads are issued before their sums, so they are in flight together
+  const C* pp = P + t.pslot + threadIdx.x;
+  int q = 0;
+  for (; q + 8 <= t.nkt; q += 8) {
+    C v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = pp[256 * (q + u)];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += v[u];
+  }
+  for (; q < t.nkt; ++q) acc += pp[256 * q];
   if (FWD) {
     if (i < f.nS)
       x[idx[f.idx_off + i]] = acc;

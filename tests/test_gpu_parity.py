@@ -198,8 +198,9 @@ def test_cycle_box_variants(monkeypatch, n, boxes):
 @pytest.mark.parametrize("n", [(40, 24, 32), (64, 64, 64)])
 def test_z_marching_tiles_match_box_tiles(monkeypatch, n):
     """the 3D z-marching sweep and restriction tiles take the box kernels' sums in the same
-    order: the FP32 cycle through them equals the default boxes' to rounding (printed: the
-    largest difference relative to the largest entry)"""
+    order: the FP32 cycle through them equals the default boxes' to rounding, for the
+    operator and its conjugate (the adjoint solves' cycle; printed: the largest difference
+    relative to the largest entry)"""
     p = rect_problem(n)
     r = _rand(p.N, 8)
     out = {}
@@ -207,13 +208,14 @@ def test_z_marching_tiles_match_box_tiles(monkeypatch, n):
         monkeypatch.setenv("HELM_BOXES", boxes)
         print("z tiles", n, boxes, flush=True)
         s = from_problem(p, cycle=2, nu=(1, 1), cycle_prec="f32")
-        out[boxes] = s.vcycle(r).cpu().numpy()
+        out[boxes] = (s.vcycle(r).cpu().numpy(), s.vcycle(r, op=HELM_OP_C).cpu().numpy())
         s.close()
-    ref = out["0,0,0,0"]
-    for boxes in ("4,3,4,3", "5,4,5,4"):
-        d = np.abs(out[boxes] - ref).max() / np.abs(ref).max()
-        print("  %s: max difference %.3e of the largest entry" % (boxes, d), flush=True)
-        assert d < 1e-6, (boxes, d)
+    for o, name in ((0, "H"), (1, "conj(H)")):
+        ref = out["0,0,0,0"][o]
+        for boxes in ("4,3,4,3", "5,4,5,4"):
+            d = np.abs(out[boxes][o] - ref).max() / np.abs(ref).max()
+            print("  %s %s: max difference %.3e of the largest entry" % (name, boxes, d), flush=True)
+            assert d < 1e-6, (name, boxes, d)
 
 
 @pytest.mark.parametrize("restart", [20, 4])
