@@ -103,7 +103,8 @@ __device__ __forceinline__ void store_partials(cd (*red)[2 * KMAXM + 3], int nv,
 
 // w = H z_j (FP64); partials of <V_i, w> (values 0..j), <V_i, V_j> (values j+1..2j+1) and
 // ||w||^2 (value 2j+2, real part).  Nodes past the end are clamped to the last node and
-// weighted 0; basis vector i + 1 is loaded while vector i is reduced.
+// weighted 0; basis vector i + 1 is loaded while vector i is reduced, and V_j, loaded
+// first for the Gram column, serves as the last vector (read from memory once).
 template <typename CZ, int CMP>
 __global__ void __launch_bounds__(256) k_arnoldi_dots(KrylovArgs a, const CZ* __restrict__ z, int j) {
   __shared__ cd red[4][2 * KMAXM + 3];
@@ -122,7 +123,7 @@ __global__ void __launch_bounds__(256) k_arnoldi_dots(KrylovArgs a, const CZ* __
   cd w[KNPT], vj[KNPT], nx[KNPT];
   for (int q = 0; q < KNPT; ++q) {
     vj[q] = on[q] * p.V[(long long)j * a.ldv + f[q]];
-    nx[q] = p.V[f[q]];
+    if (j > 0) nx[q] = p.V[f[q]];
   }
   double nw = 0.0;
   for (int q = 0; q < KNPT; ++q) {
@@ -130,10 +131,12 @@ __global__ void __launch_bounds__(256) k_arnoldi_dots(KrylovArgs a, const CZ* __
     nw += abs2(w[q]);
   }
   for (int i = 0; i <= j; ++i) {
+    // V_i: the prefetched vector, or V_j itself (the weights of clamped nodes are 0 in w
+    // and vj, so their partial terms vanish either way)
     cd vi[KNPT];
-    for (int q = 0; q < KNPT; ++q) vi[q] = nx[q];
-    const long long in = (long long)(i < j ? i + 1 : j) * a.ldv;   // the last pass reloads V_j
-    for (int q = 0; q < KNPT; ++q) nx[q] = p.V[in + f[q]];
+    for (int q = 0; q < KNPT; ++q) vi[q] = i < j ? nx[q] : vj[q];
+    if (i + 1 < j)                                                // uniform over the block
+      for (int q = 0; q < KNPT; ++q) nx[q] = p.V[(long long)(i + 1) * a.ldv + f[q]];
     cd s1 = mk(0.0, 0.0), s2 = mk(0.0, 0.0);
     for (int q = 0; q < KNPT; ++q) {
       s1 += cmulc(vi[q], w[q]);
