@@ -43,10 +43,15 @@ struct GalArgs {
 
 template <int DIM>
 constexpr int gal_qmax() { return DIM == 3 ? 343 : 81; }
+// the partial sums of the output passes: (j2, j1, D0) after the first, (j2, D1, D0) after
+// the second (the second overwrites q); 3D: 7 x 7 x 5, 2D: 9 x 7
+template <int DIM>
+constexpr int gal_tmax() { return DIM == 3 ? 245 : 63; }
 
 template <int DIM, int SRC>
 __global__ void __launch_bounds__(256) k_wgal(GalArgs a) {
   __shared__ cd q[4][gal_qmax<DIM>()];
+  __shared__ cd t1[4][gal_tmax<DIM>()];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const long long I = (long long)blockIdx.x * 4 + wv;
   const bool live = I < a.gc.tot;
@@ -74,25 +79,32 @@ __global__ void __launch_bounds__(256) k_wgal(GalArgs a) {
     }
     cd acc = mk(0.0, 0.0);
     if (SRC == 0) {
-      // sum_i w_i A(i, j) = sum_i w_i L(j - i) - c_j sum_i w_i M(j - i)
-      double sl = 0.0, sm = 0.0;
-      for (int i2 = ilo[2]; i2 <= ihi[2]; ++i2)
-        for (int i1 = ilo[1]; i1 <= ihi[1]; ++i1)
-          for (int i0 = ilo[0]; i0 <= ihi[0]; ++i0) {
-            const int ii[3] = {i0, i1, i2};
-            double w = 1.0;
-            int nz = 0;
-            for (int d = 0; d < DIM; ++d) {
-              w *= a.Rt.w[ii[d] - 2 * Ia[d] + ar];
-              nz += ii[d] != j[d];
-            }
-            const double lw = nz == 0 ? (DIM == 3 ? 24.0 : 20.0)
-                            : nz == 1 ? (DIM == 3 ? -2.0 : -4.0)
-                            : nz == 2 ? -1.0 : 0.0;
-            const double mw = nz == 0 ? (DIM == 3 ? 6.0 / 12.0 : 8.0 / 12.0) : nz == 1 ? 1.0 / 12.0 : 0.0;
-            sl += w * lw;
-            sm += w * mw;
-          }
+      // sum_i w_i A(i, j) = sum_i w_i L(j - i) - c_j sum_i w_i M(j - i), w_i = prod_a r_a(i_a)
+      // the row of R (zero off its support and off the grid).  L and M weigh an offset by
+      // the number of axes it moves along, so with c_a = r_a(j_a) and s_a = r_a(j_a - 1) +
+      // r_a(j_a + 1) the sums over i are those over the subsets of moved axes:
+      //   centre prod c, faces sum_a s_a prod_{b != a} c_b, edges (3D) sum_a c_a prod_{b != a} s_b
+      double cv[3] = {1.0, 1.0, 1.0}, sv[3] = {0.0, 0.0, 0.0};
+      for (int d = 0; d < DIM; ++d) {
+        auto rw = [&](int i) -> double {
+          const int o = i - 2 * Ia[d] + ar;
+          return o >= 0 && o <= 2 * ar && i >= 0 && i < a.gf.N[d] ? a.Rt.w[o] : 0.0;
+        };
+        cv[d] = rw(j[d]);
+        sv[d] = rw(j[d] - 1) + rw(j[d] + 1);
+      }
+      double sl, sm;
+      if (DIM == 3) {
+        const double cc = cv[0] * cv[1] * cv[2];
+        const double ff = sv[0] * cv[1] * cv[2] + cv[0] * sv[1] * cv[2] + cv[0] * cv[1] * sv[2];
+        const double ee = cv[0] * sv[1] * sv[2] + sv[0] * cv[1] * sv[2] + sv[0] * sv[1] * cv[2];
+        sl = 24.0 * cc - 2.0 * ff - ee;
+        sm = (6.0 / 12.0) * cc + (1.0 / 12.0) * ff;
+      } else {
+        const double cc = cv[0] * cv[1], ff = sv[0] * cv[1] + cv[0] * sv[1], ee = sv[0] * sv[1];
+        sl = 20.0 * cc - 4.0 * ff - ee;
+        sm = (8.0 / 12.0) * cc + (1.0 / 12.0) * ff;
+      }
       const double mj = a.m[jf];
       const cd cj = a.s * mk(mj, -mj * layer_sigma(a.op, j[0], j[1], j[2]));
       acc = mk(sl * ih - sm * cj.x, -sm * cj.y);
@@ -116,31 +128,54 @@ __global__ void __launch_bounds__(256) k_wgal(GalArgs a) {
     q[wv][e] = acc;
   }
   __syncthreads();
-  if (!live) return;
+  // Ac(I, I + D) = sum_j q(j) P(j, I + D), P a tensor product: three one-axis passes over
+  // the box (axis 0, then 1, then 2), each term 2 Pt.w[j_a - 2 J_a + bp] for the j_a that
+  // lie in the box and within bp of 2 J_a; the same terms as the triple sum, taken per axis
   const int cw = 2 * a.rc + 1;
+  int Jlo[3];
+  for (int d = 0; d < 3; ++d) Jlo[d] = Ia[d] - (d < DIM ? a.rc : 0);
+  auto wgt = [&](int j, int J) -> double {            // j, J absolute
+    const int o = j - 2 * J + bp;
+    return o >= 0 && o <= 2 * bp ? 2.0 * a.Pt.w[o] : 0.0;
+  };
+  const int c0 = cw, c1 = cw;
+  // pass 1: t1(j2, j1, D0) = sum_j0 W0(D0, j0) q(j0, j1, j2)
+  for (int e = lane; e < sp[2] * sp[1] * c0; e += 64) {
+    const int D0 = e % c0, r = e / c0;             // r = j1 + sp1 j2 (box-relative)
+    const int J0 = Jlo[0] + D0;
+    const int jl = max(2 * J0 - bp, lo[0]), jh = min(2 * J0 + bp, lo[0] + sp[0] - 1);
+    cd acc = mk(0.0, 0.0);
+    for (int j0 = jl; j0 <= jh; ++j0) acc += wgt(j0, J0) * q[wv][(j0 - lo[0]) + sp[0] * r];
+    t1[wv][e] = acc;
+  }
+  __syncthreads();
+  // pass 2: t2(j2, D1, D0) = sum_j1 W1(D1, j1) t1(j2, j1, D0), into q
+  for (int e = lane; e < sp[2] * c1 * c0; e += 64) {
+    const int D0 = e % c0, D1 = (e / c0) % c1, j2r = e / (c0 * c1);
+    const int J1 = Jlo[1] + D1;
+    const int jl = max(2 * J1 - bp, lo[1]), jh = min(2 * J1 + bp, lo[1] + sp[1] - 1);
+    cd acc = mk(0.0, 0.0);
+    for (int j1 = jl; j1 <= jh; ++j1) acc += wgt(j1, J1) * t1[wv][D0 + c0 * ((j1 - lo[1]) + sp[1] * j2r)];
+    q[wv][e] = acc;
+  }
+  __syncthreads();
+  if (!live) return;
+  // pass 3: Ac(I, I + D) = sum_j2 W2(D2, j2) t2(j2, D1, D0); 0 for J outside the grid
   int nout = cw;
   for (int d = 1; d < DIM; ++d) nout *= cw;
   for (int o = lane; o < nout; o += 64) {
-    int D[3] = {o % cw - a.rc, DIM > 1 ? (o / cw) % cw - a.rc : 0, DIM > 2 ? o / (cw * cw) - a.rc : 0};
-    int J[3] = {Ia[0] + D[0], Ia[1] + D[1], Ia[2] + D[2]};
+    const int D0 = o % cw, D1 = DIM > 1 ? (o / cw) % cw : 0, D2 = DIM > 2 ? o / (cw * cw) : 0;
+    const int J[3] = {Jlo[0] + D0, Jlo[1] + D1, Jlo[2] + D2};
     bool inside = true;
-    int jlo[3] = {0, 0, 0}, jhi[3] = {0, 0, 0};
-    for (int d = 0; d < DIM; ++d) {
-      inside = inside && J[d] >= 0 && J[d] < a.gc.N[d];
-      jlo[d] = max(2 * J[d] - bp, lo[d]);
-      jhi[d] = min(2 * J[d] + bp, lo[d] + sp[d] - 1);
-    }
+    for (int d = 0; d < DIM; ++d) inside = inside && J[d] >= 0 && J[d] < a.gc.N[d];
     cd acc = mk(0.0, 0.0);
     if (inside) {
-      for (int j2 = jlo[2]; j2 <= jhi[2]; ++j2)
-        for (int j1 = jlo[1]; j1 <= jhi[1]; ++j1)
-          for (int j0 = jlo[0]; j0 <= jhi[0]; ++j0) {
-            const int jj[3] = {j0, j1, j2};
-            double w = 1.0;
-            for (int d = 0; d < DIM; ++d) w *= 2.0 * a.Pt.w[jj[d] - 2 * J[d] + bp];
-            const int e = (j0 - lo[0]) + sp[0] * ((j1 - lo[1]) + sp[1] * (j2 - lo[2]));
-            acc += w * q[wv][e];
-          }
+      if (DIM < 3) {
+        acc = q[wv][D0 + c0 * D1];
+      } else {
+        const int jl = max(2 * J[2] - bp, lo[2]), jh = min(2 * J[2] + bp, lo[2] + sp[2] - 1);
+        for (int j2 = jl; j2 <= jh; ++j2) acc += wgt(j2, J[2]) * q[wv][D0 + c0 * (D1 + c1 * (j2 - lo[2]))];
+      }
     }
     a.out[(long long)o * a.gc.tot + I] = acc;
   }
