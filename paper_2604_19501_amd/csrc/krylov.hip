@@ -227,9 +227,9 @@ __device__ __forceinline__ void pack_state(const KrylovState* st, char* dst, int
   for (int q = threadIdx.x; q < W; q += blockDim.x) ((int*)dst)[r * W + q] = src[q];
 }
 
-// finish the Arnoldi column j and the Givens update in one block of 256 threads, of which
-// the first wavefront works (the others only meet the barriers); st->h1 holds the sums of
-// k_arnoldi_dots.  Lane i owns row i of the Gram products; the serial part (rotations of
+// finish the Arnoldi column j and the Givens update in one block (256 threads in
+// k_fin_givens, 64 in k_givens), of which the first wavefront works (the others only meet
+// the barriers); st->h1 holds the sums of k_arnoldi_dots.  Lane i owns row i of the Gram products; the serial part (rotations of
 // the column) runs on lane 0 out of LDS.
 __device__ void givens_column(const KrylovArgs& a, KrylovState* st, int j, double tol) {
   __shared__ cd sh1[KMAXM + 1], sg[KMAXM + 1], sc[KMAXM + 1], col[KMAXM + 2], ssn[KMAXM];
