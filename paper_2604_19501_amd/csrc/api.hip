@@ -127,7 +127,7 @@ struct CycleScratch {
 
 // kernel classes timed with HIP events when timing is on
 enum KClass { KT_L1_SWEEP, KT_L1_RESTRICT, KT_L2_SWEEP, KT_L2_RESTRICT, KT_ND_FWD, KT_ND_BWD, KT_APPLY_DOT,
-              KT_UPDATE_DOT, KT_NORMALIZE, KT_KRYLOV_OTHER, KT_N };
+              KT_UPDATE_DOT, KT_NORMALIZE, KT_KRYLOV_OTHER, KT_L2_CHAIN, KT_N };
 struct Pending {
   int cls;
   hipEvent_t a, b;
@@ -177,6 +177,7 @@ struct helm_ctx {
   // right-hand sides and solutions
   int rcap = 1, nr = 1;
   int tail_fused = 1;   // the FGMRES tail as one launch (kr_arnoldi)
+  int l2_chain = 1;     // 2D: level-2 post-sweep, next pre-sweep and restriction fused (HELM_L2_CHAIN)
   cd *Bm = nullptr, *Xm = nullptr;
   KrylovArgs ka;
   size_t ws_needed = 0;
@@ -982,17 +983,29 @@ struct Cycle {
     }
     TIMED(c, KT_L1_RESTRICT, s,
           (l1_restrict<R, cd>(A1, s1.xin, s1.x, b1, w1, c->g2, nullptr, c->g2, b2, c->nr, s)));
-    // ---- level 2 visits
+    // ---- level 2 visits.  In 2D with one pre- and one post-sweep, the post-sweep of a
+    // visit, the pre-sweep of the next and its restriction run as one kernel (l2_chain)
     St<C> s2{0, nullptr};
+    const bool chain = c->l2_chain && c->g2.dim == 2 && mg.nu_pre == 1 && mg.nu_post == 1;
+    bool chained = false;       // this visit's pre-sweep and restriction are done
     for (int v = 0; v < mg.cycle; ++v) {
-      for (int k = 0; k < mg.nu_pre; ++k) {
-        if (s2.xin == 0) s2 = St<C>{XIN_Z, nullptr};
-        else s2 = adv2(s2, b2, nullptr, other(s2.x, x2a, x2b));
+      if (!chained) {
+        for (int k = 0; k < mg.nu_pre; ++k) {
+          if (s2.xin == 0) s2 = St<C>{XIN_Z, nullptr};
+          else s2 = adv2(s2, b2, nullptr, other(s2.x, x2a, x2b));
+        }
+        TIMED(c, KT_L2_RESTRICT, s,
+              (l2_restrict<R>(A2, s2.xin, s2.x, b2, w2, c->g3, nullptr, c->g3, b3, c->nr, s)));
       }
-      TIMED(c, KT_L2_RESTRICT, s,
-            (l2_restrict<R>(A2, s2.xin, s2.x, b2, w2, c->g3, nullptr, c->g3, b3, c->nr, s)));
       nd_solve<C>(c, w, b3, x3, conj, s);
       s2.xin |= XIN_E;
+      chained = chain && v + 1 < mg.cycle && s2.xin == (XIN_Z | XIN_E);
+      if (chained) {
+        C* xb = other(s2.x, x2a, x2b);
+        TIMED(c, KT_L2_CHAIN, s, (l2_chain<R>(A2, s2.xin, s2.x, b2, w2, c->g3, x3, w2, xb, b3, c->nr, s)));
+        s2 = St<C>{XIN_X, xb};
+        continue;
+      }
       for (int k = 0; k < mg.nu_post; ++k) s2 = adv2(s2, b2, x3, other(s2.x, x2a, x2b));
       if (s2.xin != XIN_X) {   // materialise (no post-relaxation)
         R w0 = 0;
@@ -1388,6 +1401,7 @@ static int setup_rcap(const helm_grid* grid, const double* slowness, double omeg
     c->omega = omega;
     c->rcap = rcap;
     c->graphs = env_int("HELM_GRAPHS", 1);
+    c->l2_chain = env_int("HELM_L2_CHAIN", 1);
     // HELM_ARNOLDI_GUARD (tests): the cancellation threshold of the Arnoldi norm formula
     if (const char* g = getenv("HELM_ARNOLDI_GUARD")) c->arnoldi_guard = atof(g);
     init_geometry(c.get());

@@ -793,6 +793,118 @@ __global__ void __launch_bounds__(256) k_restrict_z(Op op, const typename Op::C*
   }
 }
 
+// ---- level-2 chain (2D) ------------------------------------------------------
+// Between two level-2 visits with one pre- and one post-sweep, three kernels run back to
+// back on level 2 with no coarse work between them: the post-sweep of the visit just ended
+// (x_in = x or the virtual first sweep, plus the coarse correction e), the pre-sweep of the
+// next visit, and that visit's residual and restriction.  One coarse box of this kernel
+// does all three on its fine footprint: the virtual iterate x0 on the footprint plus a
+// halo of 3, xa = one Jacobi sweep of x0 on halo 2, xb = one sweep of xa on halo 1 (written
+// for the box's own fine nodes [2 O, 2 O + 2 C)), r = b - A xb on the footprint and
+// b3 = R r.  The sums are those of k_sweep and k_restrict, in their order.
+template <class Op, int XIN>
+__global__ void __launch_bounds__(256) k_l2_chain(Op op, const typename Op::C* __restrict__ x,
+                                                  const typename Op::C* __restrict__ b, typename Op::Real w_in,
+                                                  Geom gc, const typename Op::C* __restrict__ e, typename Op::Real w,
+                                                  typename Op::C* __restrict__ xb_out, typename Op::C* __restrict__ b3,
+                                                  TileGrid tg) {
+  typedef typename Op::C C;
+  typedef typename Op::Real R;
+  constexpr int CX = RBox<2, 0>::x, CY = RBox<2, 0>::y;
+  constexpr int RX = 2 * CX + 1, RY = 2 * CY + 1;           // residual footprint
+  constexpr int AX = RX + 6, AY = RY + 6;                   // x0: halo 3
+  constexpr int BX = RX + 4, BY = RY + 4;                   // xa: halo 2
+  constexpr int DX = RX + 2, DY = RY + 2;                   // xb: halo 1
+  constexpr int EX = AX / 2 + 2, EY = AY / 2 + 2;           // e on x0's coarse footprint
+  __shared__ C es[EX * EY];
+  __shared__ C x0[AX * AY];
+  __shared__ C xa[BX * BY];
+  __shared__ C xb[DX * DY];
+  __shared__ C rs[RX * RY];
+  const Geom& g = op.geom();
+  const long long ry = blockIdx.y;
+  if (XIN & XIN_X) x += ry * g.tot;
+  b += ry * g.tot;
+  e += ry * gc.tot;
+  xb_out += ry * g.tot;
+  b3 += ry * gc.tot;
+  int O0, O1, O2;
+  if (!tile_origin(tg, CX, CY, 1, O0, O1, O2)) return;
+  const int f0 = 2 * O0 - 1, f1 = 2 * O1 - 1;               // the footprint's origin
+  const int c0 = (f0 - 3) >> 1, c1 = (f1 - 3) >> 1;         // floor: may be negative
+  for (int k = threadIdx.x; k < EX * EY; k += 256) {
+    const int j0 = c0 + k % EX, j1 = c1 + k / EX;
+    int l0 = j0, l1 = j1, l2 = 0;
+    clamp_node(gc, l0, l1, l2);
+    C v = e[flat(gc, l0, l1, 0)];
+    if (!inside(gc, j0, j1, 0)) v = mk((R)0, (R)0);
+    es[k] = v;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < AX * AY; k += 256) {
+    const int i0 = f0 - 3 + k % AX, i1 = f1 - 3 + k / AX;
+    int j0 = i0, j1 = i1, j2 = 0;
+    clamp_node(g, j0, j1, j2);
+    const int f = flat(g, j0, j1, 0);
+    C v = prolong_lds<2>(es, EX, EY, c0, c1, 0, j0, j1, 0);
+    if (XIN & XIN_X) v += x[f];
+    if (XIN & XIN_Z) v += w_in * jdiv(b[f], op.diag(f, j0, j1, 0));
+    if (!inside(g, i0, i1, 0)) v = mk((R)0, (R)0);
+    x0[k] = v;
+  }
+  __syncthreads();
+  // one Jacobi sweep from src (stride sx, the node's centre at (a + 1, q + 1)) into dst
+  auto sweep = [&](const C* src, int sx, C* dst, int nx, int ny, int o0, int o1, bool write_out) {
+    for (int k = threadIdx.x; k < nx * ny; k += 256) {
+      const int a = k % nx, q = k / nx;
+      const int i0 = o0 + a, i1 = o1 + q;
+      C v = mk((R)0, (R)0);
+      if (inside(g, i0, i1, 0)) {
+        const int f = flat(g, i0, i1, 0);
+        const C D = op.diag(f, i0, i1, 0);
+        const int kk = (a + 1) + sx * (q + 1);
+        const C r = b[f] - op.ax(src, kk, sx, 0, f, D);
+        v = src[kk] + w * jdiv(r, D);
+        if (write_out && i0 >= 2 * O0 && i0 < 2 * (O0 + CX) && i1 >= 2 * O1 && i1 < 2 * (O1 + CY)) xb_out[f] = v;
+      }
+      dst[k] = v;
+    }
+  };
+  sweep(x0, AX, xa, BX, BY, f0 - 2, f1 - 2, false);
+  __syncthreads();
+  sweep(xa, BX, xb, DX, DY, f0 - 1, f1 - 1, true);
+  __syncthreads();
+  for (int k = threadIdx.x; k < RX * RY; k += 256) {
+    const int a = k % RX, q = k / RX;
+    const int i0 = f0 + a, i1 = f1 + q;
+    C v = mk((R)0, (R)0);
+    if (inside(g, i0, i1, 0)) {
+      const int f = flat(g, i0, i1, 0);
+      const C D = op.diag(f, i0, i1, 0);
+      v = b[f];
+      v -= op.ax(xb, (a + 1) + DX * (q + 1), DX, 0, f, D);
+    }
+    rs[k] = v;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < CX * CY; k += 256) {
+    const int a = k % CX, q = k / CX;
+    const int I0 = O0 + a, I1 = O1 + q;
+    if (!inside(gc, I0, I1, 0)) continue;
+    C acc = mk((R)0, (R)0);
+#pragma unroll
+    for (int d1 = -1; d1 <= 1; ++d1) {
+      const R w1 = d1 == 0 ? (R)0.5 : (R)0.25;
+#pragma unroll
+      for (int d0 = -1; d0 <= 1; ++d0) {
+        const R w0 = d0 == 0 ? (R)0.5 : (R)0.25;
+        acc += (w0 * w1 * (R)1) * rs[(2 * a + 1 + d0) + RX * (2 * q + 1 + d1)];
+      }
+    }
+    b3[flat(gc, I0, I1, 0)] = acc;
+  }
+}
+
 // y = A x for the outer operator (FP64 arithmetic), x in c64 or c128
 template <typename CX>
 __global__ void __launch_bounds__(256) k_l1_apply64(L1<double> A, const CX* __restrict__ x,
@@ -1016,6 +1128,19 @@ void l2_restrict(const L2<R>& A, int xin, const typename cplx<R>::type* x, const
     restrict_dim<3, Op2<3, R>, C>(Op2<3, R>{A}, xin, x, b, w_in, g3, b3, nrhs, s);
 }
 
+template <typename R>
+void l2_chain(const L2<R>& A, int xin, const typename cplx<R>::type* x, const typename cplx<R>::type* b, R w_in,
+              const Geom& gc, const typename cplx<R>::type* e, R w, typename cplx<R>::type* xb,
+              typename cplx<R>::type* b3, int nrhs, hipStream_t s) {
+  TileGrid tg = tiles(gc, RBox<2, 0>::x, RBox<2, 0>::y, 1);
+  dim3 grid(grid_tiles(tg), nrhs), blk(256);
+  if (xin == (XIN_Z | XIN_E))
+    hipLaunchKernelGGL((k_l2_chain<Op2<2, R>, XIN_Z | XIN_E>), grid, blk, 0, s, Op2<2, R>{A}, x, b, w_in, gc, e, w,
+                       xb, b3, tg);
+  else
+    throw std::runtime_error("l2_chain: the chain starts from the virtual first sweep (xin Z | E)");
+}
+
 void l1_apply64(const L1<double>& A, const void* x, int x_is_f32, cd* y, hipStream_t s) {
   dim3 grid(grid_xcd(A.op.g.tot)), blk(256);
   if (x_is_f32)
@@ -1058,6 +1183,10 @@ template void l2_sweep<float>(const L2<float>&, int, const cf*, const cf*, float
                               const cf*, float, cf*, int, hipStream_t);
 template void l2_sweep<double>(const L2<double>&, int, const cd*, const cd*, double, const Geom&,
                                const cd*, double, cd*, int, hipStream_t);
+template void l2_chain<float>(const L2<float>&, int, const cf*, const cf*, float, const Geom&, const cf*, float,
+                              cf*, cf*, int, hipStream_t);
+template void l2_chain<double>(const L2<double>&, int, const cd*, const cd*, double, const Geom&, const cd*, double,
+                               cd*, cd*, int, hipStream_t);
 template void l2_restrict<float>(const L2<float>&, int, const cf*, const cf*, float, const Geom&,
                                  const cf*, const Geom&, cf*, int, hipStream_t);
 template void l2_restrict<double>(const L2<double>&, int, const cd*, const cd*, double, const Geom&,

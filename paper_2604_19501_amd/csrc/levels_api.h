@@ -102,6 +102,14 @@ template <typename R>
 void l2_restrict(const L2<R>& A, int xin, const typename cplx<R>::type* x, const typename cplx<R>::type* b,
                  R w_in, const Geom& gc, const typename cplx<R>::type* e, const Geom& g3,
                  typename cplx<R>::type* b3, int nrhs, hipStream_t s);
+// 2D, between the two level-2 visits of a W-cycle with one pre- and one post-sweep: the
+// post-sweep of the first visit (xin = XIN_Z | XIN_E, e the coarse correction on gc), the
+// pre-sweep of the next (xb receives its iterate) and that visit's residual, restricted into
+// b3 on gc, in one launch
+template <typename R>
+void l2_chain(const L2<R>& A, int xin, const typename cplx<R>::type* x, const typename cplx<R>::type* b, R w_in,
+              const Geom& gc, const typename cplx<R>::type* e, R w, typename cplx<R>::type* xb,
+              typename cplx<R>::type* b3, int nrhs, hipStream_t s);
 void l1_apply64(const L1<double>& A, const void* x, int x_is_f32, cd* y, hipStream_t s);
 // dg[f] = the diagonal of A at every node (set-up of the FP32 cycle's level-1 operator)
 void l1_diag32(const L1<float>& A, cf* dg, hipStream_t s);

@@ -195,6 +195,32 @@ def test_cycle_box_variants(monkeypatch, n, boxes):
         s.close()
 
 
+@pytest.mark.parametrize("n", [(136, 72), (200, 136)])
+def test_level2_chain_matches_separate_kernels(monkeypatch, n):
+    """2D W-cycle with one pre- and one post-sweep: the fused level-2 chain (the first
+    visit's post-sweep, the second visit's pre-sweep and restriction in one kernel) takes
+    the separate kernels' sums in their order: the cycle equals theirs to rounding in both
+    precisions, for the operator and its conjugate, and the oracle's"""
+    cycle = 2
+    p = rect_problem(n)
+    r = _rand(p.N, 9)
+    H = oracle_hierarchy(p, cycle=cycle, nu_pre=1, nu_post=1)
+    ref = H.precond(r)
+    for prec, tol in (("f64", 1e-14), ("f32", 1e-6)):
+        out = {}
+        for on in ("0", "1"):
+            monkeypatch.setenv("HELM_L2_CHAIN", on)
+            print("l2 chain", n, cycle, prec, on, flush=True)
+            s = from_problem(p, cycle=cycle, nu=(1, 1), cycle_prec=prec)
+            out[on] = (s.vcycle(r).cpu().numpy(), s.vcycle(r, op=HELM_OP_C).cpu().numpy())
+            s.close()
+        for o in (0, 1):
+            d = np.abs(out["1"][o] - out["0"][o]).max() / np.abs(out["0"][o]).max()
+            print("  %s op %d: max difference %.3e of the largest entry" % (prec, o, d), flush=True)
+            assert d < tol, (prec, o, d)
+        assert maxabs_rel(out["1"][0], ref) < TOL_INF[prec]
+
+
 @pytest.mark.parametrize("n", [(40, 24, 32), (64, 64, 64)])
 def test_z_marching_tiles_match_box_tiles(monkeypatch, n):
     """the 3D z-marching sweep and restriction tiles take the box kernels' sums in the same
