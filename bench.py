@@ -152,6 +152,8 @@ def bytes_model(cls, p, info, iters, restart, nr=1):
         return N2 * cb * (S + 2 * nr)
     if cls == "l2_chain":         # two sweeps and a residual in one pass: coefficients + b2, x in,
         return N2 * cb * (S + 3 * nr) + 2 * N3 * cb * nr      # x out; e in and b3 out per level-3 node
+    if cls == "cycle_tail":       # the level-1 sweep's bytes; level-2 coefficients, x2 and b2; e3
+        return N1 * ((16 + cb) * nr + 8) + N2 * cb * (S + 2 * nr) + N3 * cb * nr
     nb = info.get("coarse_complex_bytes", cb)     # the coarsest solve's precision
     if cls == "nd_fwd":           # [A^-1; C A^-1] once, right-hand side gather, updates written and read
         per_solve = info["L_entries"] * nb + 4 * (N3 + U) + nr * (2 * N3 * nb + 2 * U * nb)

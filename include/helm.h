@@ -262,13 +262,14 @@ const char* helm_last_error(void);
 /* Device timing (HIP events), recorded while enabled by helm_set_timing(ctx, 1), which also
  * clears the accumulators (on every instance of a batched context; its class sums are then
  * summed over the instances).  helm_get_timing fills host array t[0..n): [0] last solve total ms,
- * [1..3] reserved (0), [4] last setup ms, then for kernel class k = 0..10 (level-1 sweep,
+ * [1..3] reserved (0), [4] last setup ms, then for kernel class k = 0..11 (level-1 sweep,
  * level-1 residual+restriction, level-2 sweep, level-2 residual+restriction, coarsest
  * forward substitution, coarsest backward substitution, Arnoldi step (apply, two
  * orthogonalisation passes, Givens, normalisation), -, -, -, level-2 chain (2D, one pre-
  * and one post-sweep: the post-sweep of a level-2 visit, the pre-sweep of the next and its
- * residual+restriction in one launch)) the pair t[5+2k] = accumulated ms, t[6+2k] =
- * launches.  Returns the number of entries written. */
+ * residual+restriction in one launch), cycle tail (2D, one post-sweep per level: the last
+ * level-2 post-sweep and the level-1 post-sweep in one launch)) the pair t[5+2k] =
+ * accumulated ms, t[6+2k] = launches.  Returns the number of entries written. */
 int helm_set_timing(helm_ctx* ctx, int on);
 int helm_get_timing(helm_ctx* ctx, double* t, int n);
 

@@ -127,7 +127,7 @@ struct CycleScratch {
 
 // kernel classes timed with HIP events when timing is on
 enum KClass { KT_L1_SWEEP, KT_L1_RESTRICT, KT_L2_SWEEP, KT_L2_RESTRICT, KT_ND_FWD, KT_ND_BWD, KT_APPLY_DOT,
-              KT_UPDATE_DOT, KT_NORMALIZE, KT_KRYLOV_OTHER, KT_L2_CHAIN, KT_N };
+              KT_UPDATE_DOT, KT_NORMALIZE, KT_KRYLOV_OTHER, KT_L2_CHAIN, KT_TAIL, KT_N };
 struct Pending {
   int cls;
   hipEvent_t a, b;
@@ -987,6 +987,9 @@ struct Cycle {
     // visit, the pre-sweep of the next and its restriction run as one kernel (l2_chain)
     St<C> s2{0, nullptr};
     const bool chain = c->l2_chain && c->g2.dim == 2 && mg.nu_pre == 1 && mg.nu_post == 1;
+    // in 2D with one pre- and one post-sweep, the last level-2 post-sweep and the level-1
+    // post-sweep run as one kernel (cycle_tail)
+    const bool tail = chain && s1.xin == XIN_Z;
     bool chained = false;       // this visit's pre-sweep and restriction are done
     for (int v = 0; v < mg.cycle; ++v) {
       if (!chained) {
@@ -999,6 +1002,8 @@ struct Cycle {
       }
       nd_solve<C>(c, w, b3, x3, conj, s);
       s2.xin |= XIN_E;
+      // the last visit's post-sweep, left to the cycle's tail (below)
+      if (tail && v + 1 == mg.cycle && s2.xin == (XIN_X | XIN_E)) break;
       chained = chain && v + 1 < mg.cycle && s2.xin == (XIN_Z | XIN_E);
       if (chained) {
         C* xb = other(s2.x, x2a, x2b);
@@ -1014,6 +1019,10 @@ struct Cycle {
       }
     }
     // ---- level 1 correction and post-relaxation; the last sweep writes `out`
+    if (tail && s2.xin == (XIN_X | XIN_E)) {
+      TIMED(c, KT_TAIL, s, (cycle_tail<R, CO>(A1, b1, w1, A2, s2.x, b2, w2, c->g3, x3, out, c->nr, s)));
+      return;
+    }
     s1.xin |= XIN_E;
     const C* e2 = s2.x;
     if (mg.nu_post == 0) {

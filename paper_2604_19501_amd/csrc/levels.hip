@@ -905,6 +905,99 @@ __global__ void __launch_bounds__(256) k_l2_chain(Op op, const typename Op::C* _
   }
 }
 
+// ---- cycle tail (2D) -------------------------------------------------------------
+// The last level-2 post-sweep (from x2 + P e3) feeds only the level-1 post-sweep (from
+// w D1^-1 b1 + P e2): one level-1 box of this kernel computes the level-2 sweep on the
+// coarse footprint its staging reads (plus a halo of 1 for the sweep's neighbours) and then
+// the level-1 sweep, so the level-2 iterate is never written.  The sums are those of
+// k_sweep on each level, in its order.
+template <typename R, typename CO>
+__global__ void __launch_bounds__(256) k_cycle_tail(Op1<2, R> o1, Op2<2, R> o2, const cd* __restrict__ b1, R w1,
+                                                    const typename cplx<R>::type* __restrict__ x2,
+                                                    const typename cplx<R>::type* __restrict__ b2, R w2, Geom g3,
+                                                    const typename cplx<R>::type* __restrict__ e3,
+                                                    CO* __restrict__ out, TileGrid tg) {
+  typedef typename cplx<R>::type C;
+  constexpr int TX = SBox<2, 0>::x, TY = SBox<2, 0>::y;
+  constexpr int SX = TX + 2, SY = TY + 2;                   // level-1 staging
+  constexpr int EX = TX / 2 + 3, EY = TY / 2 + 3;           // e2 on its coarse footprint
+  constexpr int YX = EX + 2, YY = EY + 2;                   // x2 + P e3 on that plus a halo of 1
+  constexpr int FX = YX / 2 + 2, FY = YY / 2 + 2;           // e3 on the level-3 footprint
+  __shared__ C e3s[FX * FY];
+  __shared__ C y2[YX * YY];
+  __shared__ C e2s[EX * EY];
+  __shared__ C xs[SX * SY];
+  const Geom& g1 = o1.geom();
+  const Geom& g2 = o2.geom();
+  const long long ry = blockIdx.y;
+  b1 += ry * g1.tot;
+  out += ry * g1.tot;
+  x2 += ry * g2.tot;
+  b2 += ry * g2.tot;
+  e3 += ry * g3.tot;
+  int o0, o1_, o2_;
+  if (!tile_origin(tg, TX, TY, 1, o0, o1_, o2_)) return;
+  const int s0 = o0 - 1, s1 = o1_ - 1;
+  const int c0 = s0 >> 1, c1 = s1 >> 1;                     // floor: may be negative
+  const int q0 = c0 - 1, q1 = c1 - 1;
+  const int d0 = q0 >> 1, d1 = q1 >> 1;
+  for (int k = threadIdx.x; k < FX * FY; k += 256) {
+    const int j0 = d0 + k % FX, j1 = d1 + k / FX;
+    int l0 = j0, l1 = j1, l2 = 0;
+    clamp_node(g3, l0, l1, l2);
+    C v = e3[flat(g3, l0, l1, 0)];
+    if (!inside(g3, j0, j1, 0)) v = mk((R)0, (R)0);
+    e3s[k] = v;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < YX * YY; k += 256) {
+    const int i0 = q0 + k % YX, i1 = q1 + k / YX;
+    int j0 = i0, j1 = i1, j2 = 0;
+    clamp_node(g2, j0, j1, j2);
+    C v = prolong_lds<2>(e3s, FX, FY, d0, d1, 0, j0, j1, 0);
+    v += x2[flat(g2, j0, j1, 0)];
+    if (!inside(g2, i0, i1, 0)) v = mk((R)0, (R)0);
+    y2[k] = v;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < EX * EY; k += 256) {
+    const int a = k % EX, q = k / EX;
+    const int i0 = c0 + a, i1 = c1 + q;
+    C v = mk((R)0, (R)0);
+    if (inside(g2, i0, i1, 0)) {
+      const int f = flat(g2, i0, i1, 0);
+      const C D = o2.diag(f, i0, i1, 0);
+      const int kk = (a + 1) + YX * (q + 1);
+      const C r = b2[f] - o2.ax(y2, kk, YX, 0, f, D);
+      v = y2[kk] + w2 * jdiv(r, D);
+    }
+    e2s[k] = v;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < SX * SY; k += 256) {
+    const int i0 = s0 + k % SX, i1 = s1 + k / SX;
+    int j0 = i0, j1 = i1, j2 = 0;
+    clamp_node(g1, j0, j1, j2);
+    const int f = flat(g1, j0, j1, 0);
+    C v = prolong_lds<2>(e2s, EX, EY, c0, c1, 0, j0, j1, 0);
+    v += w1 * jdiv(conv<C>::from(b1[f]), o1.diag(f, j0, j1, 0));
+    if (!inside(g1, i0, i1, 0)) v = mk((R)0, (R)0);
+    xs[k] = v;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < TX * TY; k += 256) {
+    const int a = k % TX, q = k / TX;
+    const int i0 = o0 + a, i1 = o1_ + q;
+    if (!inside(g1, i0, i1, 0)) continue;
+    const int f = flat(g1, i0, i1, 0);
+    const C bo = conv<C>::from(b1[f]);
+    const C D = o1.diag(f, i0, i1, 0);
+    const int kk = (a + 1) + SX * (q + 1);
+    const C r = bo - o1.ax(xs, kk, SX, 0, f, D);
+    out[f] = conv<CO>::from(xs[kk] + w1 * jdiv(r, D));
+  }
+}
+
 // y = A x for the outer operator (FP64 arithmetic), x in c64 or c128
 template <typename CX>
 __global__ void __launch_bounds__(256) k_l1_apply64(L1<double> A, const CX* __restrict__ x,
@@ -1128,6 +1221,16 @@ void l2_restrict(const L2<R>& A, int xin, const typename cplx<R>::type* x, const
     restrict_dim<3, Op2<3, R>, C>(Op2<3, R>{A}, xin, x, b, w_in, g3, b3, nrhs, s);
 }
 
+template <typename R, typename CO>
+void cycle_tail(const L1<R>& A1, const cd* b1, R w1, const L2<R>& A2, const typename cplx<R>::type* x2,
+                const typename cplx<R>::type* b2, R w2, const Geom& g3, const typename cplx<R>::type* e3, CO* out,
+                int nrhs, hipStream_t s) {
+  TileGrid tg = tiles(A1.op.g, SBox<2, 0>::x, SBox<2, 0>::y, 1);
+  dim3 grid(grid_tiles(tg), nrhs), blk(256);
+  hipLaunchKernelGGL((k_cycle_tail<R, CO>), grid, blk, 0, s, Op1<2, R>{A1}, Op2<2, R>{A2}, b1, w1, x2, b2, w2, g3, e3,
+                     out, tg);
+}
+
 template <typename R>
 void l2_chain(const L2<R>& A, int xin, const typename cplx<R>::type* x, const typename cplx<R>::type* b, R w_in,
               const Geom& gc, const typename cplx<R>::type* e, R w, typename cplx<R>::type* xb,
@@ -1183,6 +1286,12 @@ template void l2_sweep<float>(const L2<float>&, int, const cf*, const cf*, float
                               const cf*, float, cf*, int, hipStream_t);
 template void l2_sweep<double>(const L2<double>&, int, const cd*, const cd*, double, const Geom&,
                                const cd*, double, cd*, int, hipStream_t);
+template void cycle_tail<float, cf>(const L1<float>&, const cd*, float, const L2<float>&, const cf*, const cf*,
+                                    float, const Geom&, const cf*, cf*, int, hipStream_t);
+template void cycle_tail<float, cd>(const L1<float>&, const cd*, float, const L2<float>&, const cf*, const cf*,
+                                    float, const Geom&, const cf*, cd*, int, hipStream_t);
+template void cycle_tail<double, cd>(const L1<double>&, const cd*, double, const L2<double>&, const cd*, const cd*,
+                                     double, const Geom&, const cd*, cd*, int, hipStream_t);
 template void l2_chain<float>(const L2<float>&, int, const cf*, const cf*, float, const Geom&, const cf*, float,
                               cf*, cf*, int, hipStream_t);
 template void l2_chain<double>(const L2<double>&, int, const cd*, const cd*, double, const Geom&, const cd*, double,

@@ -110,6 +110,14 @@ template <typename R>
 void l2_chain(const L2<R>& A, int xin, const typename cplx<R>::type* x, const typename cplx<R>::type* b, R w_in,
               const Geom& gc, const typename cplx<R>::type* e, R w, typename cplx<R>::type* xb,
               typename cplx<R>::type* b3, int nrhs, hipStream_t s);
+// 2D, the end of a cycle with one post-sweep on each level: the last level-2 post-sweep
+// (from x2 + P e3, e3 on g3) and the level-1 post-sweep (from the virtual first sweep
+// w1 D1^-1 b1 plus the prolongated level-2 result) into out, in one launch; the level-2
+// iterate is not written
+template <typename R, typename CO>
+void cycle_tail(const L1<R>& A1, const cd* b1, R w1, const L2<R>& A2, const typename cplx<R>::type* x2,
+                const typename cplx<R>::type* b2, R w2, const Geom& g3, const typename cplx<R>::type* e3, CO* out,
+                int nrhs, hipStream_t s);
 void l1_apply64(const L1<double>& A, const void* x, int x_is_f32, cd* y, hipStream_t s);
 // dg[f] = the diagonal of A at every node (set-up of the FP32 cycle's level-1 operator)
 void l1_diag32(const L1<float>& A, cf* dg, hipStream_t s);

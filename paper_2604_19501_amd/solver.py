@@ -24,10 +24,11 @@ INFO_KEYS = ("N1", "N2", "N3", "fronts", "L_entries", "W_entries", "upd_entries"
              "fwd_launches", "bwd_launches", "workspace_bytes", "max_front", "cycle_complex_bytes",
              "nd_leaf", "nd_root", "nd_tuned", "nd_tree_launches")
 INFO_LEN = 29
-KERNEL_CLASSES = ("l1_sweep", "l1_restrict", "l2_sweep", "l2_restrict", "nd_fwd", "nd_bwd", "arnoldi", "l2_chain")
+KERNEL_CLASSES = ("l1_sweep", "l1_restrict", "l2_sweep", "l2_restrict", "nd_fwd", "nd_bwd", "arnoldi", "l2_chain",
+                  "cycle_tail")
 # their indices among the library's timing classes (helm_get_timing)
 _CLASS_INDEX = {"l1_sweep": 0, "l1_restrict": 1, "l2_sweep": 2, "l2_restrict": 3, "nd_fwd": 4, "nd_bwd": 5,
-                "arnoldi": 6, "l2_chain": 10}
+                "arnoldi": 6, "l2_chain": 10, "cycle_tail": 11}
 
 
 def parse_info(v) -> dict:
@@ -43,8 +44,8 @@ def parse_info(v) -> dict:
 
 def kernel_times(ctx) -> dict:
     """{class: (ms, launches)} accumulated since helm_set_timing(ctx, 1)"""
-    t = (C.c_double * 27)()
-    L.lib.helm_get_timing(ctx, t, 27)
+    t = (C.c_double * 29)()
+    L.lib.helm_get_timing(ctx, t, 29)
     return {k: (t[5 + 2 * _CLASS_INDEX[k]], int(t[6 + 2 * _CLASS_INDEX[k]])) for k in KERNEL_CLASSES}
 
 
