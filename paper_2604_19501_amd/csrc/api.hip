@@ -1863,8 +1863,11 @@ int helm_setup_batched(int n_inst, const helm_grid* grids, const double* const* 
     }
     // instances are solved concurrently on several streams: there the fences of the fused
     // FGMRES tail write back L2 lines that the other streams' kernels use (2.4 % fewer
-    // solves per second on the 96-instance workload), so their tail takes three launches
+    // solves per second on the 96-instance workload), so their tail takes three launches;
+    // and the device is busy, so the fused level-2 chain and cycle tail, which save
+    // launches at the cost of halo work, measured 2 % fewer solves per second there
     c->tail_fused = n_inst == 1;
+    if (n_inst > 1) c->l2_chain = 0;
     b->sub.push_back(c);
     p += al(bi);
   }
