@@ -101,6 +101,17 @@ struct Geom {
   long long tot;  // total nodes
 };
 
+// coordinates of flat node index f = i0 + N0 (i1 + N1 i2); a grid has fewer than 2^31 nodes,
+// so 32-bit division serves (64-bit division has no instruction and costs some 40)
+__device__ __forceinline__ void node_coords(const Geom& g, long long f, int& i0, int& i1, int& i2) {
+  const unsigned u = (unsigned)f, N0 = (unsigned)g.N[0], N1 = (unsigned)g.N[1];
+  const unsigned r = u / N0;
+  i0 = (int)(u - r * N0);
+  const unsigned q = r / N1;
+  i1 = (int)(r - q * N1);
+  i2 = (int)q;
+}
+
 inline Geom make_geom(int dim, const int* n) {
   Geom g;
   g.dim = dim;

@@ -25,13 +25,31 @@
 
 namespace helm {
 
-__device__ __forceinline__ cd wsum(cd v) {
-  for (int o = 32; o > 0; o >>= 1) {
-    v.x += __shfl_xor(v.x, o, 64);
-    v.y += __shfl_xor(v.y, o, 64);
-  }
-  return v;
+// v + (v of the lane that DPP control ctrl selects), the moved value 0 in the rows outside
+// rmask; a double moves as its two 32-bit halves
+template <int CTRL, int RMASK>
+__device__ __forceinline__ double dpp_add(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, RMASK, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, RMASK, 0xf, false);
+  return v + __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
+
+// sum of v over the 64-lane wavefront in a fixed order, returned to every lane.  DPP lane
+// moves (pair swap, quad swap, half-row mirror, row mirror, then the broadcasts of lanes 15
+// and 31 into the rows above) leave the sum in lane 63; no LDS traffic.
+__device__ __forceinline__ double wsum1(double v) {
+  v = dpp_add<0xB1, 0xf>(v);        // quad_perm [1,0,3,2]
+  v = dpp_add<0x4E, 0xf>(v);        // quad_perm [2,3,0,1]
+  v = dpp_add<0x141, 0xf>(v);       // row_half_mirror
+  v = dpp_add<0x140, 0xf>(v);       // row_mirror: every lane of a row holds the row's sum
+  v = dpp_add<0x142, 0xa>(v);       // row_bcast15 into rows 1 and 3
+  v = dpp_add<0x143, 0xc>(v);       // row_bcast31 into rows 2 and 3
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63), hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ cd wsum(cd v) { return mk(wsum1(v.x), wsum1(v.y)); }
 
 // sum v over the 256-thread block; thread 0 writes it to *out
 __device__ __forceinline__ void block_sum(cd v, cd* lds, cd* out) {
@@ -65,9 +83,8 @@ __device__ __forceinline__ long long node_of(int q) {
 template <int CMP, typename CX>
 __device__ __forceinline__ cd apply_h(const KrylovArgs& a, const CX* __restrict__ x, long long f) {
   const Geom& g = a.op.g;
-  int i0 = (int)(f % g.N[0]);
-  long long r = f / g.N[0];
-  int i1 = (int)(r % g.N[1]), i2 = (int)(r / g.N[1]);
+  int i0, i1, i2;
+  node_coords(g, f, i0, i1, i2);
   if constexpr (CMP) {
     cd dg;
     return g.dim == 3 ? wide_row<3, double, CX>(a.op, a.s, a.m64, x, f, i0, i1, i2, false, dg)
@@ -104,7 +121,10 @@ __device__ __forceinline__ void store_partials(cd (*red)[2 * KMAXM + 3], int nv,
 // w = H z_j (FP64); partials of <V_i, w> (values 0..j), <V_i, V_j> (values j+1..2j+1) and
 // ||w||^2 (value 2j+2, real part).  Nodes past the end are clamped to the last node and
 // weighted 0; basis vector i + 1 is loaded while vector i is reduced, and V_j, loaded
-// first for the Gram column, serves as the last vector (read from memory once).
+// first for the Gram column, serves as the last vector (read from memory once).  The
+// V_0..V_{j-1} loads are non-temporal: the basis (about 17 MB per vector at 1025^2) is
+// larger than the caches, and streaming it through them would displace what the cycle
+// reuses (measured: 1 % more solves per second at 1025^2 with these loads non-temporal).
 template <typename CZ, int CMP>
 __global__ void __launch_bounds__(256) k_arnoldi_dots(KrylovArgs a, const CZ* __restrict__ z, int j) {
   __shared__ cd red[4][2 * KMAXM + 3];
@@ -123,7 +143,7 @@ __global__ void __launch_bounds__(256) k_arnoldi_dots(KrylovArgs a, const CZ* __
   cd w[KNPT], vj[KNPT], nx[KNPT];
   for (int q = 0; q < KNPT; ++q) {
     vj[q] = on[q] * p.V[(long long)j * a.ldv + f[q]];
-    if (j > 0) nx[q] = p.V[f[q]];
+    if (j > 0) nx[q] = ld_nt(p.V + f[q]);
   }
   double nw = 0.0;
   for (int q = 0; q < KNPT; ++q) {
@@ -136,7 +156,7 @@ __global__ void __launch_bounds__(256) k_arnoldi_dots(KrylovArgs a, const CZ* __
     cd vi[KNPT];
     for (int q = 0; q < KNPT; ++q) vi[q] = i < j ? nx[q] : vj[q];
     if (i + 1 < j)                                                // uniform over the block
-      for (int q = 0; q < KNPT; ++q) nx[q] = p.V[(long long)(i + 1) * a.ldv + f[q]];
+      for (int q = 0; q < KNPT; ++q) nx[q] = ld_nt(p.V + (long long)(i + 1) * a.ldv + f[q]);
     cd s1 = mk(0.0, 0.0), s2 = mk(0.0, 0.0);
     for (int q = 0; q < KNPT; ++q) {
       s1 += cmulc(vi[q], w[q]);
@@ -176,19 +196,19 @@ __global__ void __launch_bounds__(256) k_residual(KrylovArgs a, const cd* __rest
 }
 
 // this thread's share of a block-wide sum of src[0 .. n): entries threadIdx.x + 256 m in
-// increasing m; groups of 8 loads are issued before their sums, so they are in flight
-// together (the order of the sums is that of the plain loop)
+// increasing m; up to 8 of them are loaded before any is summed, so that they are in
+// flight together (the order of the sums is that of the plain loop)
 __device__ __forceinline__ cd sum_strided(const cd* __restrict__ src, int n) {
   cd v = mk(0.0, 0.0);
-  int b = threadIdx.x;
-  for (; b + 256 * 7 < n; b += 256 * 8) {
+  for (int b = threadIdx.x; b < n; b += 256 * 8) {
     cd w[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) w[u] = src[b + 256 * u];
+    for (int u = 0; u < 8; ++u)
+      if (b + 256 * u < n) w[u] = src[b + 256 * u];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v += w[u];
+    for (int u = 0; u < 8; ++u)
+      if (b + 256 * u < n) v += w[u];
   }
-  for (; b < n; b += 256) v += src[b];
   return v;
 }
 
@@ -227,74 +247,107 @@ __device__ __forceinline__ void pack_state(const KrylovState* st, char* dst, int
   for (int q = threadIdx.x; q < W; q += blockDim.x) ((int*)dst)[r * W + q] = src[q];
 }
 
-// finish the Arnoldi column j and the Givens update in one block (256 threads in
-// k_fin_givens, 64 in k_givens), of which the first wavefront works (the others only meet
-// the barriers); st->h1 holds the sums of k_arnoldi_dots.  Lane i owns row i of the Gram products; the serial part (rotations of
-// the column) runs on lane 0 out of LDS.
-__device__ void givens_column(const KrylovArgs& a, KrylovState* st, int j, double tol) {
-  __shared__ cd sh1[KMAXM + 1], sg[KMAXM + 1], sc[KMAXM + 1], col[KMAXM + 2], ssn[KMAXM];
-  __shared__ double scs[KMAXM], r1[64], r2[64];
-  __shared__ cd sG[(KMAXM + 1) * (KMAXM + 1)];
-  const int t = threadIdx.x < 64 ? (int)threadIdx.x : 1 << 20, ld = KMAXM + 1;
-  // the scalars the serial part needs, loaded now so that their latency overlaps the
-  // products below (the stores into the state would otherwise keep them in order)
-  double nw2 = 0.0, bnorm = 1.0;
-  cd gj = mk(0.0, 0.0);
-  int its = 0, maxit = 0;
+static_assert(KMAXM <= 64, "one lane per row of the Arnoldi column");
+
+// LDS of a column's finish: the column's sums, the Gram matrix, the rotations
+struct GivensLds {
+  cd sh1[KMAXM + 1], sg[KMAXM + 1], sc[KMAXM + 1], col[KMAXM + 2], ssn[KMAXM];
+  double scs[KMAXM], r1[64], r2[64];
+  cd sG[(KMAXM + 1) * (KMAXM + 1) + 1];     // the last entry: a sink for stores past the end
+};
+// the scalars of the serial part, held by lane 0
+struct GivensScal {
+  cd gj;
+  double bnorm;
+  int its, maxit;
+};
+
+// first part of the finish of Arnoldi column j: what earlier launches wrote (G(i, k) for
+// i, k < j, the rotations of columns < j, the scalars of the serial part) into LDS and lane
+// 0's registers.  The first wavefront issues every load of a batch before it stores any, so
+// that their latencies overlap; a barrier of the caller precedes their use.
+__device__ __forceinline__ void givens_stage(GivensLds& L, const KrylovState* st, int j, GivensScal& sc) {
+  const int t = threadIdx.x, ld = KMAXM + 1;
+  if (t >= 64) return;
   if (t == 0) {
-    nw2 = st->h1[2 * j + 2].x;
-    gj = st->g[j];
-    bnorm = st->bnorm;
-    its = st->its;
-    maxit = st->maxit;
+    sc.gj = st->g[j];
+    sc.bnorm = st->bnorm;
+    sc.its = st->its;
+    sc.maxit = st->maxit;
   }
-  for (int i = t; i <= j; i += 64) {
-    sh1[i] = st->h1[i];
-    sg[i] = st->h1[j + 1 + i];                 // G(i, j) = <V_i, V_j>
+  // rotations: lane t < KMAXM loads entry t whether or not t < j (the rest are unused),
+  // stored after the Gram loads so that all of them are in flight together
+  const double cs_t = st->cs[t];
+  const cd sn_t = st->sn[t];
+  const int nG = j * j;
+  for (int e0 = t; e0 < nG; e0 += 64 * 8) {
+    // loads and stores unconditional (past the end: entry e0 into the sink), so that the
+    // loads are not sunk into the stores' branches
+    cd v[8];
+    int at[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = e0 + 64 * u < nG ? e0 + 64 * u : e0;
+      at[u] = (e % j) + ld * (e / j);
+      v[u] = st->G[at[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (e0 + 64 * u >= nG) at[u] = (KMAXM + 1) * (KMAXM + 1);
+      L.sG[at[u]] = v[u];
+    }
   }
-  for (int i = t; i < j; i += 64) {
-    scs[i] = st->cs[i];
-    ssn[i] = st->sn[i];
+  L.scs[t] = cs_t;
+  L.ssn[t] = sn_t;
+}
+
+// second part: the sums of k_arnoldi_dots (st->h1), then the column and its Givens update
+// in one block (256 threads in k_fin_givens, 64 in k_givens), of which the first wavefront
+// works (the others only meet the barriers).  Lane i owns row i of the Gram products; the
+// serial part (rotations of the column) runs on lane 0 out of LDS.
+__device__ __forceinline__ void givens_finish(GivensLds& L, const KrylovArgs& a, KrylovState* st, int j, double tol,
+                                              const GivensScal& sc) {
+  const int t = threadIdx.x < 64 ? (int)threadIdx.x : 1 << 20, ld = KMAXM + 1;
+  double nw2 = 0.0;
+  if (t == 0) nw2 = st->h1[2 * j + 2].x;
+  if (t <= j) {                                // j < KMAXM <= 64: one row per lane
+    const cd h = st->h1[t], g = st->h1[j + 1 + t];   // g = G(t, j) = <V_t, V_j>
+    L.sh1[t] = h;
+    L.sg[t] = g;
+    L.sG[j + ld * t] = conjc(g);
+    L.sG[t + ld * j] = g;                      // the diagonal entry as summed
   }
-  // G(i, k): k < j from earlier columns, column / row j from this pass; staged in LDS so
-  // that the products below do not wait on global loads one by one
-  for (int e = t; e < j * j; e += 64) sG[(e % j) + ld * (e / j)] = st->G[(e % j) + ld * (e / j)];
   __syncthreads();
-  for (int i = t; i <= j; i += 64) {
-    sG[j + ld * i] = conjc(sg[i]);
-    sG[i + ld * j] = sg[i];                    // the diagonal entry as summed
-  }
-  __syncthreads();
-  auto gik = [&](int i, int k) -> cd { return sG[i + ld * k]; };
+  auto gik = [&](int i, int k) -> cd { return L.sG[i + ld * k]; };
   // c = h1 + (h1 - G h1)
-  for (int i = t; i <= j; i += 64) {
+  if (t <= j) {
     cd gh = mk(0.0, 0.0);
-    for (int k = 0; k <= j; ++k) gh += gik(i, k) * sh1[k];
-    sc[i] = (sh1[i] + sh1[i]) - gh;
+    for (int k = 0; k <= j; ++k) gh += gik(t, k) * L.sh1[k];
+    L.sc[t] = (L.sh1[t] + L.sh1[t]) - gh;
   }
   __syncthreads();
   // Re(c^H h1) and c^H G c, per lane then summed in lane order
   double p1 = 0.0, p2 = 0.0;
-  for (int i = t; i <= j; i += 64) {
+  if (t <= j) {
     cd gc = mk(0.0, 0.0);
-    for (int k = 0; k <= j; ++k) gc += gik(i, k) * sc[k];
-    p1 += sc[i].x * sh1[i].x + sc[i].y * sh1[i].y;
-    p2 += sc[i].x * gc.x + sc[i].y * gc.y;
+    for (int k = 0; k <= j; ++k) gc += gik(t, k) * L.sc[k];
+    p1 = L.sc[t].x * L.sh1[t].x + L.sc[t].y * L.sh1[t].y;
+    p2 = L.sc[t].x * gc.x + L.sc[t].y * gc.y;
   }
   if (t < 64) {
-    r1[t] = p1;
-    r2[t] = p2;
+    L.r1[t] = p1;
+    L.r2[t] = p2;
   }
-  for (int i = t; i <= j; i += 64) {          // store column / row j of G for later columns
-    st->G[i + ld * j] = sg[i];
-    st->G[j + ld * i] = conjc(sg[i]);
+  if (t <= j) {                                // column / row j of G for later columns
+    st->G[t + ld * j] = L.sg[t];
+    st->G[j + ld * t] = conjc(L.sg[t]);
   }
   __syncthreads();
   if (t == 0) {
     double ch = 0.0, cgc = 0.0;
-    for (int i = 0; i < 64; ++i) {
-      ch += r1[i];
-      cgc += r2[i];
+    for (int i = 0; i <= j; ++i) {
+      ch += L.r1[i];
+      cgc += L.r2[i];
     }
     const double n2 = nw2 - 2.0 * ch + cgc;     // ||w - V c||^2
     const double hn = n2 > 0.0 ? sqrt(n2) : 0.0;
@@ -304,13 +357,14 @@ __device__ void givens_column(const KrylovArgs& a, KrylovState* st, int j, doubl
     // rotation uses hn, which only enters through c^2 + hn^2 there) and the cycle ends:
     // the solution is updated and the restart recomputes the true residual in FP64.
     const bool cancel = n2 < a.guard * nw2;
-    for (int i = 0; i <= j; ++i) col[i] = sc[i];
+    cd* col = L.col;
+    for (int i = 0; i <= j; ++i) col[i] = L.sc[i];
     col[j + 1] = mk(hn, 0.0);
     st->hnext = hn;
     for (int i = 0; i < j; ++i) {             // previous rotations on column j
       cd hi = col[i], hi1 = col[i + 1];
-      col[i] = scs[i] * hi + ssn[i] * hi1;
-      col[i + 1] = scs[i] * hi1 - conjc(ssn[i]) * hi;
+      col[i] = L.scs[i] * hi + L.ssn[i] * hi1;
+      col[i + 1] = L.scs[i] * hi1 - conjc(L.ssn[i]) * hi;
     }
     double c;
     cd s, r;
@@ -319,44 +373,52 @@ __device__ void givens_column(const KrylovArgs& a, KrylovState* st, int j, doubl
     st->sn[j] = s;
     col[j] = r;
     col[j + 1] = mk(0.0, 0.0);
-    const cd gnext = -(conjc(s) * gj);
+    const cd gnext = -(conjc(s) * sc.gj);
     st->g[j + 1] = gnext;
-    st->g[j] = c * gj;
-    double est = sqrt(abs2(gnext)) / bnorm;
+    st->g[j] = c * sc.gj;
+    double est = sqrt(abs2(gnext)) / sc.bnorm;
     st->est = est;
-    if (its < KMAXIT) st->hist[its] = est;
-    st->its = its + 1;
+    if (sc.its < KMAXIT) st->hist[sc.its] = est;
+    st->its = sc.its + 1;
     st->kcols = j + 1;
     bool fin = isfinite(est) && isfinite(hn);
     if (!fin) st->nonfinite = 1;
-    st->done = (est <= tol || !fin || hn == 0.0 || cancel || its + 1 >= maxit) ? 1 : 0;
+    st->done = (est <= tol || !fin || hn == 0.0 || cancel || sc.its + 1 >= sc.maxit) ? 1 : 0;
   }
   __syncthreads();
-  for (int i = t; i <= j + 1; i += 64) st->H[i + ld * j] = col[i];
-  for (int i = t; i <= j; i += 64) st->c[i] = sc[i];
+  for (int i = t; i <= j + 1; i += 64) st->H[i + ld * j] = L.col[i];
+  if (t <= j) st->c[t] = L.sc[t];
 }
 
 // the column's finish as a launch of its own (one wavefront), after k_fin_sum
 __global__ void __launch_bounds__(64) k_givens(KrylovArgs a, int j, double tol) {
+  __shared__ GivensLds L;
   KrylovState* st = at_rhs(a).st;
   if (st->done) return;            // converged in an earlier column: the state stays as it is
-  givens_column(a, st, j, tol);
+  GivensScal sc;
+  givens_stage(L, st, j, sc);
+  givens_finish(L, a, st, j, tol, sc);
 }
 
 // one block per value: st->h1[i] = sum over the dot pass's blocks of part[i]; the block
 // that stores the last of the 2 j + 3 sums of its right-hand side (a device-scope ticket,
-// returned to zero by that block) then finishes the column (givens_column) and, with
+// returned to zero by that block) then finishes the column (givens_finish) and, with
 // pack_dst, packs the state for the host.  The sums are formed in a fixed order whichever
-// block finishes last.
+// block finishes last.  Every block stages the column's inputs from earlier launches
+// before its ticket, so that their loads overlap the fences.
 __global__ void __launch_bounds__(256) k_fin_givens(KrylovArgs a, int j, double tol, char* pack_dst) {
   __shared__ cd lds[4];
   __shared__ int last;
+  __shared__ GivensLds L;
   const RhsPtr p = at_rhs(a);
   KrylovState* st = p.st;
   const int i = blockIdx.x;
+  const bool live = !st->done;         // converged in an earlier column: the state stays as it is
   cd v = mk(0.0, 0.0);
   v = sum_strided(p.part + (long long)i * a.pcap, a.nblk);
   block_sum(v, lds, st->h1 + i);
+  GivensScal sc;
+  if (live) givens_stage(L, st, j, sc);
   if (threadIdx.x == 0) {
     __threadfence();                     // this block's sum before its ticket
     last = atomicAdd(&st->ticket, 1) == (int)gridDim.x - 1;
@@ -367,8 +429,7 @@ __global__ void __launch_bounds__(256) k_fin_givens(KrylovArgs a, int j, double 
   }
   __syncthreads();
   if (!last) return;
-  // converged in an earlier column: the state stays as it is
-  if (!st->done) givens_column(a, st, j, tol);
+  if (live) givens_finish(L, a, st, j, tol, sc);
   if (pack_dst) {
     __syncthreads();
     pack_state(st, pack_dst, blockIdx.y);
@@ -378,10 +439,10 @@ __global__ void __launch_bounds__(256) k_fin_givens(KrylovArgs a, int j, double 
 
 
 // V_{j+1} = (H z_j - sum_i c_i V_i) / h_{j+1,j}.  The blocks take the nodes in reverse
-// order: the dots pass just streamed the same basis front to back, so its last part is
-// the most likely to still be in the memory-side cache.  This pass is the basis's last
-// reader in the iteration: its loads are non-temporal, so that they do not displace the
-// data the next iteration's cycle reuses (the coarsest factors, the level-2 coefficients).
+// order, so that the first nodes they read are the last the dots pass read.  This pass is
+// the basis's last reader in the iteration: its loads are non-temporal, so that they do
+// not displace the data the next iteration's cycle reuses (the coarsest factors, the
+// level-2 coefficients).
 template <typename CZ, int CMP>
 __global__ void __launch_bounds__(256) k_arnoldi_update(KrylovArgs a, const CZ* __restrict__ z, int j) {
   __shared__ cd sc[KMAXM + 1];

@@ -41,10 +41,7 @@ __device__ __forceinline__ long long xcd_block(long long nblocks) {
 }
 
 __device__ __forceinline__ void decode(const Geom& g, long long f, int& i0, int& i1, int& i2) {
-  i0 = (int)(f % g.N[0]);
-  long long r = f / g.N[0];
-  i1 = (int)(r % g.N[1]);
-  i2 = (int)(r / g.N[1]);
+  node_coords(g, f, i0, i1, i2);
 }
 
 __device__ __forceinline__ bool inside(const Geom& g, int i0, int i1, int i2) {

@@ -15,10 +15,7 @@ namespace {
 
 // node coordinates of flat index f
 __device__ __forceinline__ void coords(const Geom& g, long long f, int& i0, int& i1, int& i2) {
-  i0 = (int)(f % g.N[0]);
-  const long long r = f / g.N[0];
-  i1 = (int)(r % g.N[1]);
-  i2 = (int)(r / g.N[1]);
+  node_coords(g, f, i0, i1, i2);
 }
 
 // ---------------------------------------------------------------- set-up ----
