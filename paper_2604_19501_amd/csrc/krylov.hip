@@ -431,9 +431,10 @@ __global__ void __launch_bounds__(256) k_fin_givens(KrylovArgs a, int j, double 
   if (!last) return;
   if (live) givens_finish(L, a, st, j, tol, sc);
   if (pack_dst) {
+    // the host reads the slot after an event recorded behind this launch, whose completion
+    // makes the stores visible; no fence of system scope is needed here
     __syncthreads();
     pack_state(st, pack_dst, blockIdx.y);
-    __threadfence_system();
   }
 }
 

@@ -883,25 +883,25 @@ __global__ void __launch_bounds__(1024) k_nd_tree(const NDTask* __restrict__ tas
   }
 }
 
-// rows [r0, r1) (at most 16) of a big front: 16 row lanes x 16 k-splits per work-group,
+// rows [r0, r1) (at most 16) of a big front: 16 row lanes x KS (16 or 64) k-splits per work-group,
 // partial sums reduced through LDS; consecutive threads read consecutive rows of one column.
 // gemv16_load issues the thread's first 16 matrix entries, which do not depend on v, so
 // callers start it before gathering v; gemv16_finish does the rest.
-template <typename C>
+template <typename C, int KS = 16>
 __device__ __forceinline__ void gemv16_load(const C* __restrict__ M, long long ld, int r0, int r1, int K, C* m) {
   const int row = threadIdx.x & 15, ks = threadIdx.x >> 4;
-  const int kq = (K + 15) / 16, kb = ks * kq, ke = min(K, kb + kq);
+  const int kq = (K + KS - 1) / KS, kb = ks * kq, ke = min(K, kb + kq);
   const C* col = M + min(r0 + row, r1 - 1);
 #pragma unroll
   for (int q = 0; q < 16; ++q) m[q] = col[(long long)max(0, min(kb + q, ke - 1)) * ld];
 }
-template <typename C>
+template <typename C, int KS = 16>
 __device__ __forceinline__ C gemv16_finish(const C* __restrict__ M, long long ld, int r0, int r1, int K,
                                            const C* __restrict__ v, int conj, C* red, const C* m0) {
   typedef decltype(v[0].x) R;
   const int row = threadIdx.x & 15, ks = threadIdx.x >> 4;
   const int i = r0 + row;
-  const int kq = (K + 15) / 16, kb = ks * kq, ke = min(K, kb + kq);
+  const int kq = (K + KS - 1) / KS, kb = ks * kq, ke = min(K, kb + kq);
   C acc = mk((R)0, (R)0);
   if (i < r1 && kb < ke) {
 #pragma unroll
@@ -920,6 +920,17 @@ __device__ __forceinline__ C gemv16_finish(const C* __restrict__ M, long long ld
   }
   red[threadIdx.x] = acc;
   __syncthreads();
+  if (KS > 16) {                       // fold the k-splits 16 apart onto the first 256 threads
+    C t = mk((R)0, (R)0);
+    if (threadIdx.x < 256) {
+      t = red[threadIdx.x];
+#pragma unroll
+      for (int g = 1; g < KS / 16; ++g) t += red[threadIdx.x + 256 * g];
+    }
+    __syncthreads();
+    if (threadIdx.x < 256) red[threadIdx.x] = t;
+    __syncthreads();
+  }
   C tot = mk((R)0, (R)0);
   if (threadIdx.x < 16)
     for (int q = 0; q < 16; ++q) tot += red[q * 16 + threadIdx.x];
@@ -957,24 +968,27 @@ __global__ void __launch_bounds__(256) k_nd_fwd_big(const NDGather* __restrict__
   }
 }
 
-template <typename C>
-__global__ void __launch_bounds__(256) k_nd_bwd_big(const NDFrontDev* __restrict__ fr, const int* __restrict__ idx,
-                                                    const C* __restrict__ Wp, const NDItem* __restrict__ items,
-                                                    C* __restrict__ x, C* __restrict__ gvec, int cap, int conj,
-                                                    NDRhs rh) {
+// backward substitution, big fronts: one work-group per chunk of at most 16 rows; KS = 64
+// (1024 threads) for launches whose vectors exceed 256 entries, so that the gather of x_B
+// takes one pass and a thread's k-slice one batch of loads
+template <typename C, int KS>
+__global__ void __launch_bounds__(16 * KS) k_nd_bwd_big(const NDFrontDev* __restrict__ fr, const int* __restrict__ idx,
+                                                         const C* __restrict__ Wp, const NDItem* __restrict__ items,
+                                                         C* __restrict__ x, C* __restrict__ gvec, int cap, int conj,
+                                                         NDRhs rh) {
   extern __shared__ char smem[];
-  __shared__ C red[256];
+  __shared__ C red[16 * KS];
   x += blockIdx.y * rh.vec;
   C* vec = gvec ? gvec + blockIdx.y * rh.gvec + (long long)blockIdx.x * cap : (C*)smem;
   const NDItem f = items[blockIdx.x];
   const int* id = idx + f.idx_off;
   C m0[16];
-  gemv16_load(Wp + f.m_off, f.ld, f.r0, f.r1, f.nB, m0);
+  gemv16_load<C, KS>(Wp + f.m_off, f.ld, f.r0, f.r1, f.nB, m0);
   const int i = f.r0 + threadIdx.x;
   const int di = threadIdx.x < 16 && i < f.r1 ? id[i] : 0;
-  for (int j = threadIdx.x; j < f.nB; j += 256) vec[j] = x[id[f.nS + j]];
+  for (int j = threadIdx.x; j < f.nB; j += 16 * KS) vec[j] = x[id[f.nS + j]];
   __syncthreads();
-  C acc = gemv16_finish(Wp + f.m_off, f.ld, f.r0, f.r1, f.nB, vec, conj, red, m0);
+  C acc = gemv16_finish<C, KS>(Wp + f.m_off, f.ld, f.r0, f.r1, f.nB, vec, conj, red, m0);
   if (threadIdx.x < 16 && i < f.r1) x[di] = x[di] + acc;
 }
 
@@ -1174,8 +1188,12 @@ void nd_bwd(const NDLaunchDev& L, const NDFrontDev* fr, const int* idx, const in
     hipLaunchKernelGGL((k_nd_tree<C, 0>), dim3(L.ntasks, rh.n), dim3(L.threads), lds, s, L.tasks, L.stages, L.gath,
                        L.segs, L.outs, L.dst, cidx, Wp, upd, (const C*)x, x, conj, rh);
   } else {
-    hipLaunchKernelGGL((k_nd_bwd_big<C>), dim3(L.ntasks, rh.n), dim3(256), L.shm, s, fr, idx, Wp, L.items, x, gvec,
-                       cap, conj, rh);
+    if (L.threads == 1024)
+      hipLaunchKernelGGL((k_nd_bwd_big<C, 64>), dim3(L.ntasks, rh.n), dim3(1024), L.shm, s, fr, idx, Wp, L.items, x,
+                         gvec, cap, conj, rh);
+    else
+      hipLaunchKernelGGL((k_nd_bwd_big<C, 16>), dim3(L.ntasks, rh.n), dim3(256), L.shm, s, fr, idx, Wp, L.items, x,
+                         gvec, cap, conj, rh);
   }
 }
 
