@@ -573,9 +573,10 @@ __global__ void k_init_state(KrylovState* st, int maxit) {
 
 // the scalar blocks (bnorm .. hist) of the nrhs states, packed one after the other into
 // host-visible memory (pinned, written through), for the host to read after an event
+// (the host reads dst after synchronising with the stream or an event behind this launch,
+// which makes the stores visible: no fence of system scope)
 __global__ void k_pack_states(const KrylovState* st, char* dst, int nrhs) {
   for (int r = 0; r < nrhs; ++r) pack_state(st + r, dst, r);
-  __threadfence_system();
 }
 
 // right-hand sides in mask: finished, done from now on
