@@ -636,9 +636,9 @@ size_t carve(helm_ctx* c, void* ws) {
       if (L.kind != 1) continue;
       const size_t need = (size_t)L.max_rows_vec * c->ndsz;
       d.launch[fb][l].shm = need <= c->lds_limit ? std::max<size_t>(need, 16) : 0;
-      // backward: 1024-thread work-groups (64 k-splits) where a vector exceeds 256 entries
-      // (forward, the same measured slower: 15.07 against 14.19 ms per 1024^2 solve)
-      d.launch[fb][l].threads = fb == 1 && L.max_rows_vec > 256 ? 1024 : 256;
+      // 1024-thread work-groups (64 k-splits) where a vector exceeds 256 entries, if the
+      // launch fits the chip at once (decided at launch time with the right-hand sides)
+      d.launch[fb][l].threads = L.max_rows_vec > 256 ? 1024 : 256;
       if (need > c->lds_limit) {
         gcap = std::max<long long>(gcap, L.max_rows_vec);
         gneed = std::max<long long>(gneed, (long long)(L.task_off.size() - 1));

@@ -937,15 +937,16 @@ __device__ __forceinline__ C gemv16_finish(const C* __restrict__ M, long long ld
   return tot;
 }
 
-// forward substitution, big fronts: one work-group per chunk of at most 64 rows
-template <typename C>
-__global__ void __launch_bounds__(256) k_nd_fwd_big(const NDGather* __restrict__ gath, const int* __restrict__ idx,
-                                                    const int* __restrict__ cidx, const C* __restrict__ Lp,
-                                                    C* __restrict__ upd, const NDItem* __restrict__ items,
-                                                    const C* __restrict__ r, C* __restrict__ x,
-                                                    C* __restrict__ gvec, int cap, int conj, NDRhs rh) {
+// forward substitution, big fronts: one work-group per chunk of at most 16 rows; KS = 64
+// (1024 threads) as for the backward substitution
+template <typename C, int KS>
+__global__ void __launch_bounds__(16 * KS) k_nd_fwd_big(const NDGather* __restrict__ gath, const int* __restrict__ idx,
+                                                         const int* __restrict__ cidx, const C* __restrict__ Lp,
+                                                         C* __restrict__ upd, const NDItem* __restrict__ items,
+                                                         const C* __restrict__ r, C* __restrict__ x,
+                                                         C* __restrict__ gvec, int cap, int conj, NDRhs rh) {
   extern __shared__ char smem[];
-  __shared__ C red[256];
+  __shared__ C red[16 * KS];
   upd += blockIdx.y * rh.upd;
   r += blockIdx.y * rh.vec;
   x += blockIdx.y * rh.vec;
@@ -953,12 +954,12 @@ __global__ void __launch_bounds__(256) k_nd_fwd_big(const NDGather* __restrict__
   const NDItem f = items[blockIdx.x];
   const int* id = idx + f.idx_off;
   C m0[16];
-  gemv16_load(Lp + f.m_off, f.ld, f.r0, f.r1, f.nS, m0);
+  gemv16_load<C, KS>(Lp + f.m_off, f.ld, f.r0, f.r1, f.nS, m0);
   const NDGather* gl = gath + f.g0;
-  for (int i = threadIdx.x; i < f.nS; i += 256) vec[i] = gather_list(gl[i], cidx, upd, r);
-  for (int i = max(f.r0, f.nS) + threadIdx.x; i < f.r1; i += 256) vec[i] = gather_list(gl[i], cidx, upd, r);
+  for (int i = threadIdx.x; i < f.nS; i += 16 * KS) vec[i] = gather_list(gl[i], cidx, upd, r);
+  for (int i = max(f.r0, f.nS) + threadIdx.x; i < f.r1; i += 16 * KS) vec[i] = gather_list(gl[i], cidx, upd, r);
   __syncthreads();
-  C acc = gemv16_finish(Lp + f.m_off, f.ld, f.r0, f.r1, f.nS, vec, conj, red, m0);
+  C acc = gemv16_finish<C, KS>(Lp + f.m_off, f.ld, f.r0, f.r1, f.nS, vec, conj, red, m0);
   const int i = f.r0 + threadIdx.x;
   if (threadIdx.x < 16 && i < f.r1) {
     if (i < f.nS)
@@ -969,8 +970,9 @@ __global__ void __launch_bounds__(256) k_nd_fwd_big(const NDGather* __restrict__
 }
 
 // backward substitution, big fronts: one work-group per chunk of at most 16 rows; KS = 64
-// (1024 threads) for launches whose vectors exceed 256 entries, so that the gather of x_B
-// takes one pass and a thread's k-slice one batch of loads
+// (1024 threads) for launches whose vectors exceed 256 entries and whose work-groups fit
+// the chip at once (see big_threads), so that the gather of x_B takes one pass and a
+// thread's k-slice one batch of loads
 template <typename C, int KS>
 __global__ void __launch_bounds__(16 * KS) k_nd_bwd_big(const NDFrontDev* __restrict__ fr, const int* __restrict__ idx,
                                                          const C* __restrict__ Wp, const NDItem* __restrict__ items,
@@ -1161,6 +1163,14 @@ static void tree_attr(size_t lds) {
     (void)hipFuncSetAttribute((const void*)k_nd_tree<C, FWD>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
+// threads of a row-chunk launch: 1024 (64 k-splits) where the plan marks its vectors as
+// longer than 256 entries and at most 512 work-groups run (two 16-wavefront work-groups
+// per CU: one generation); otherwise 256.  A second generation doubles the launch's
+// latency, which cost more than the shorter gather and k-slices save.
+static int big_threads(const NDLaunchDev& L, const NDRhs& rh) {
+  return L.threads == 1024 && (long long)L.ntasks * rh.n <= 512 ? 1024 : 256;
+}
+
 template <typename C>
 void nd_fwd(const NDLaunchDev& L, const NDFrontDev* fr, const int* idx, const int* cptr, const int* cidx,
             const C* Lp, C* upd, const C* r, C* x, C* gvec, int cap, int conj, C* P, const NDRhs& rh,
@@ -1173,8 +1183,12 @@ void nd_fwd(const NDLaunchDev& L, const NDFrontDev* fr, const int* idx, const in
     hipLaunchKernelGGL((k_nd_tree<C, 1>), dim3(L.ntasks, rh.n), dim3(L.threads), lds, s, L.tasks, L.stages, L.gath,
                        L.segs, L.outs, L.dst, cidx, Lp, upd, r, x, conj, rh);
   } else {
-    hipLaunchKernelGGL((k_nd_fwd_big<C>), dim3(L.ntasks, rh.n), dim3(256), L.shm, s, L.gath, idx, cidx, Lp, upd,
-                       L.items, r, x, gvec, cap, conj, rh);
+    if (big_threads(L, rh) == 1024)
+      hipLaunchKernelGGL((k_nd_fwd_big<C, 64>), dim3(L.ntasks, rh.n), dim3(1024), L.shm, s, L.gath, idx, cidx, Lp,
+                         upd, L.items, r, x, gvec, cap, conj, rh);
+    else
+      hipLaunchKernelGGL((k_nd_fwd_big<C, 16>), dim3(L.ntasks, rh.n), dim3(256), L.shm, s, L.gath, idx, cidx, Lp,
+                         upd, L.items, r, x, gvec, cap, conj, rh);
   }
 }
 template <typename C>
@@ -1188,7 +1202,7 @@ void nd_bwd(const NDLaunchDev& L, const NDFrontDev* fr, const int* idx, const in
     hipLaunchKernelGGL((k_nd_tree<C, 0>), dim3(L.ntasks, rh.n), dim3(L.threads), lds, s, L.tasks, L.stages, L.gath,
                        L.segs, L.outs, L.dst, cidx, Wp, upd, (const C*)x, x, conj, rh);
   } else {
-    if (L.threads == 1024)
+    if (big_threads(L, rh) == 1024)
       hipLaunchKernelGGL((k_nd_bwd_big<C, 64>), dim3(L.ntasks, rh.n), dim3(1024), L.shm, s, fr, idx, Wp, L.items, x,
                          gvec, cap, conj, rh);
     else
