@@ -1117,7 +1117,7 @@ void iter_graphs(helm_ctx* c, int op, double tol) {
     CK(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
     cyc.template run<C>(c->V + j * NJ, (C*)c->Z + j * NJ);
     // the state read-back of this position into its slot of the pinned buffer is made by
-    // the Givens step inside the graph: a separate launch between graphs cost a dispatch
+    // the update pass inside the graph: a separate launch between graphs cost a dispatch
     // and about 8 us of idle device, one inside it about 4 us
     kr_arnoldi(a, (const char*)c->Z + j * NJ * c->csz, c->f32, j, tol, c->hstate_dev + HSLOT * (1 + (j & 1)),
                c->tail_fused, c->cap);

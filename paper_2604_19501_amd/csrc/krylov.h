@@ -52,9 +52,9 @@ void kr_init(const KrylovArgs& a, int max_iter, hipStream_t s);
 void kr_residual(const KrylovArgs& a, const cd* x, const cd* b, int with_b, hipStream_t s);
 void kr_scale_v0(const KrylovArgs& a, hipStream_t s);
 // pack_dst: host-mapped slot that receives the scalar blocks of the states after the
-// column's Givens update (as kr_pack_states); null: none.  fused: the final sums, the
-// Givens update and the pack in one launch (the last block of each right-hand side's sums
-// finishing the column behind device-scope fences); else three launches
+// column's Givens update (as kr_pack_states; written by the update pass); null: none.
+// fused: the final sums and the Givens update in one launch (the last block of each
+// right-hand side's sums finishing the column behind device-scope fences); else two
 void kr_arnoldi(const KrylovArgs& a, const void* z, int z_f32, int j, double tol, void* pack_dst, int fused,
                 hipStream_t s);
 // x += Z y over each right-hand side's columns of the current cycle (Z: ldz between columns)

@@ -13,7 +13,8 @@
 //                     then the Givens rotation of the Hessenberg column, the residual
 //                     estimate |g_{j+1}| / ||b|| and the convergence flag
 //   k_arnoldi_update  V_{j+1} = (H z_j - V c) / h_{j+1,j}, recomputing H z_j (16 B per
-//                     node) instead of storing and reloading w (32 B per node)
+//                     node) instead of storing and reloading w (32 B per node); its first
+//                     block also packs the state for the host
 // Because G holds the inner products of the stored vectors, any loss of orthogonality
 // of V is corrected in the next column rather than accumulated.  Reductions are
 // two-stage (per-block partials, then a fixed-order sum), so the results are bitwise
@@ -402,11 +403,10 @@ __global__ void __launch_bounds__(64) k_givens(KrylovArgs a, int j, double tol) 
 
 // one block per value: st->h1[i] = sum over the dot pass's blocks of part[i]; the block
 // that stores the last of the 2 j + 3 sums of its right-hand side (a device-scope ticket,
-// returned to zero by that block) then finishes the column (givens_finish) and, with
-// pack_dst, packs the state for the host.  The sums are formed in a fixed order whichever
-// block finishes last.  Every block stages the column's inputs from earlier launches
-// before its ticket, so that their loads overlap the fences.
-__global__ void __launch_bounds__(256) k_fin_givens(KrylovArgs a, int j, double tol, char* pack_dst) {
+// returned to zero by that block) then finishes the column (givens_finish).  The sums are
+// formed in a fixed order whichever block finishes last.  Every block stages the column's
+// inputs from earlier launches before its ticket, so that their loads overlap the fences.
+__global__ void __launch_bounds__(256) k_fin_givens(KrylovArgs a, int j, double tol) {
   __shared__ cd lds[4];
   __shared__ int last;
   __shared__ GivensLds L;
@@ -430,12 +430,6 @@ __global__ void __launch_bounds__(256) k_fin_givens(KrylovArgs a, int j, double 
   __syncthreads();
   if (!last) return;
   if (live) givens_finish(L, a, st, j, tol, sc);
-  if (pack_dst) {
-    // the host reads the slot after an event recorded behind this launch, whose completion
-    // makes the stores visible; no fence of system scope is needed here
-    __syncthreads();
-    pack_state(st, pack_dst, blockIdx.y);
-  }
 }
 
 
@@ -444,11 +438,17 @@ __global__ void __launch_bounds__(256) k_fin_givens(KrylovArgs a, int j, double 
 // the basis's last reader in the iteration: its loads are non-temporal, so that they do
 // not displace the data the next iteration's cycle reuses (the coarsest factors, the
 // level-2 coefficients).
+// With pack_dst, the first block of each right-hand side also packs its state (final after
+// the column's finish) into the host-mapped slot, so that the stores to host memory drain
+// while this pass streams instead of delaying it; the host reads the slot after an event
+// recorded behind the launch, whose completion makes them visible (no fence of system scope).
 template <typename CZ, int CMP>
-__global__ void __launch_bounds__(256) k_arnoldi_update(KrylovArgs a, const CZ* __restrict__ z, int j) {
+__global__ void __launch_bounds__(256) k_arnoldi_update(KrylovArgs a, const CZ* __restrict__ z, int j,
+                                                        char* pack_dst) {
   __shared__ cd sc[KMAXM + 1];
   __shared__ double sinv;
   const RhsPtr p = at_rhs(a);
+  if (pack_dst && blockIdx.x == 0) pack_state(p.st, pack_dst, blockIdx.y);
   z += blockIdx.y * a.op.g.tot;
   if (p.st->done) return;
   if (threadIdx.x <= j) sc[threadIdx.x] = p.st->c[threadIdx.x];
@@ -629,20 +629,20 @@ void kr_arnoldi(const KrylovArgs& a, const void* z, int z_f32, int j, double tol
   else
     hipLaunchKernelGGL((k_arnoldi_dots<cd, 1>), g, dim3(256), 0, s, a, (const cd*)z, j);
   if (fused) {
-    hipLaunchKernelGGL(k_fin_givens, dim3(2 * j + 3, a.nrhs), dim3(256), 0, s, a, j, tol, (char*)pack_dst);
+    hipLaunchKernelGGL(k_fin_givens, dim3(2 * j + 3, a.nrhs), dim3(256), 0, s, a, j, tol);
   } else {
     hipLaunchKernelGGL(k_fin_sum, dim3(2 * j + 3, a.nrhs), dim3(256), 0, s, a, offsetof(KrylovState, h1));
     hipLaunchKernelGGL(k_givens, dim3(1, a.nrhs), dim3(64), 0, s, a, j, tol);
-    if (pack_dst) hipLaunchKernelGGL(k_pack_states, dim3(1), dim3(256), 0, s, a.st, (char*)pack_dst, a.nrhs);
   }
+  char* pk = (char*)pack_dst;
   if (z_f32 && !cmp)
-    hipLaunchKernelGGL((k_arnoldi_update<cf, 0>), g, dim3(256), 0, s, a, (const cf*)z, j);
+    hipLaunchKernelGGL((k_arnoldi_update<cf, 0>), g, dim3(256), 0, s, a, (const cf*)z, j, pk);
   else if (!cmp)
-    hipLaunchKernelGGL((k_arnoldi_update<cd, 0>), g, dim3(256), 0, s, a, (const cd*)z, j);
+    hipLaunchKernelGGL((k_arnoldi_update<cd, 0>), g, dim3(256), 0, s, a, (const cd*)z, j, pk);
   else if (z_f32)
-    hipLaunchKernelGGL((k_arnoldi_update<cf, 1>), g, dim3(256), 0, s, a, (const cf*)z, j);
+    hipLaunchKernelGGL((k_arnoldi_update<cf, 1>), g, dim3(256), 0, s, a, (const cf*)z, j, pk);
   else
-    hipLaunchKernelGGL((k_arnoldi_update<cd, 1>), g, dim3(256), 0, s, a, (const cd*)z, j);
+    hipLaunchKernelGGL((k_arnoldi_update<cd, 1>), g, dim3(256), 0, s, a, (const cd*)z, j, pk);
 }
 void kr_update_x(const KrylovArgs& a, const void* Z, int z_f32, long long ldz, cd* x, hipStream_t s) {
   hipLaunchKernelGGL(k_solve_y, dim3(1, a.nrhs), dim3(1), 0, s, a);
