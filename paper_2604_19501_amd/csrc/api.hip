@@ -1866,7 +1866,8 @@ int helm_setup_batched(int n_inst, const helm_grid* grids, const double* const* 
     }
     // instances are solved concurrently on several streams: there the fences of the fused
     // FGMRES tail write back L2 lines that the other streams' kernels use (2.4 % fewer
-    // solves per second on the 96-instance workload), so their tail takes three launches;
+    // solves per second on the 96-instance workload), so their final sums and Givens step
+    // are separate launches;
     // and the device is busy, so the fused level-2 chain and cycle tail, which save
     // launches at the cost of halo work, measured 2 % fewer solves per second there
     c->tail_fused = n_inst == 1;

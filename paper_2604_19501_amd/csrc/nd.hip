@@ -883,10 +883,10 @@ __global__ void __launch_bounds__(1024) k_nd_tree(const NDTask* __restrict__ tas
   }
 }
 
-// rows [r0, r1) (at most 16) of a big front: 16 row lanes x KS (16 or 64) k-splits per work-group,
-// partial sums reduced through LDS; consecutive threads read consecutive rows of one column.
-// gemv16_load issues the thread's first 16 matrix entries, which do not depend on v, so
-// callers start it before gathering v; gemv16_finish does the rest.
+// rows [r0, r1) (at most 16) of a big front: 16 row lanes x KS (16 or 64) k-splits per
+// work-group, partial sums reduced through LDS; consecutive threads read consecutive rows
+// of one column.  gemv16_load issues the thread's first 16 matrix entries, which do not
+// depend on v, so callers start it before gathering v; gemv16_finish does the rest.
 template <typename C, int KS = 16>
 __device__ __forceinline__ void gemv16_load(const C* __restrict__ M, long long ld, int r0, int r1, int K, C* m) {
   const int row = threadIdx.x & 15, ks = threadIdx.x >> 4;
