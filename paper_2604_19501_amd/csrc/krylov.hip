@@ -359,14 +359,18 @@ __device__ __forceinline__ void givens_finish(GivensLds& L, const KrylovArgs& a,
     // the solution is updated and the restart recomputes the true residual in FP64.
     const bool cancel = n2 < a.guard * nw2;
     cd* col = L.col;
-    for (int i = 0; i <= j; ++i) col[i] = L.sc[i];
-    col[j + 1] = mk(hn, 0.0);
     st->hnext = hn;
-    for (int i = 0; i < j; ++i) {             // previous rotations on column j
-      cd hi = col[i], hi1 = col[i + 1];
+    // previous rotations on column (c_0 .. c_j, hn): rotation i mixes entry i, already
+    // rotated by rotation i - 1 and carried in registers, with the untouched c_{i+1}; the
+    // rotated entry i is stored and not read again here
+    cd hi = L.sc[0];
+    for (int i = 0; i < j; ++i) {
+      const cd hi1 = L.sc[i + 1];
       col[i] = L.scs[i] * hi + L.ssn[i] * hi1;
-      col[i + 1] = L.scs[i] * hi1 - conjc(L.ssn[i]) * hi;
+      hi = L.scs[i] * hi1 - conjc(L.ssn[i]) * hi;
     }
+    col[j] = hi;
+    col[j + 1] = mk(hn, 0.0);
     double c;
     cd s, r;
     givens(col[j], col[j + 1], c, s, r);
